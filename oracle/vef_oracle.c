@@ -1,0 +1,835 @@
+/*
+ * vef_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, serial, double-precision reference implementation of
+ *   (1) the discrete-ordinates, upwind discontinuous-Galerkin transport sweep
+ *       on curved quadrilateral meshes (Sec. 5 with Eq. eq:transport and the
+ *       inflow condition eq:trans_bc; mesh maps and reference-space
+ *       integration of Sec. 3.1-3.2; the DG space Y_p of Sec. 4.1), and
+ *   (2) the angular-moment reduction and the VEF closures E and E_b
+ *       (Eq. eq:vef_disc), the inflow partial current J_in and the source
+ *       moments Q_0, Q_1 (Sec. 2), and the source iteration with the max-norm
+ *       stopping rule of Sec. 8 (successive iterates).
+ *
+ * Only the test-suite, the smoke entry point and the CPU-baseline leg of the
+ * benchmark may call this code.  The product path (the HIP library) shares no
+ * code with it.  Nothing here is tuned: every quantity is evaluated from its
+ * definition at the point where it is needed.
+ *
+ * Readings of the paper that this oracle fixes (the paper defers the transport
+ * discretisation to external references):
+ *   - weak form per element K and direction d, tested with every u in Q_p(K):
+ *       -int_K psi (Omega . grad u) + int_K sigma_t psi u
+ *       + int_{dK} (Omega . n) psihat u = int_K (sigma_s/(4 pi) phi + q) u,
+ *     psihat = own trace on outflow faces, upwind neighbour trace (or the
+ *     inflow data) on inflow faces;
+ *   - the upwind side of a face is chosen for the whole face from the sign of
+ *     Omega . N_F, N_F the rotated chord of the face (= integral of n ds);
+ *     a zero product makes the lower element id upwind; a boundary face is
+ *     inflow when Omega . N_F < 0;
+ *   - tensor Gauss-Lobatto nodal basis of degree p on [0,1]^2, tensor
+ *     Gauss-Legendre quadrature with nq points per direction (default p+m);
+ *   - dense Gaussian elimination with partial pivoting (first maximal entry).
+ *   Parity of the curved-face upwind rule is unpinned beyond its definition.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_ERR_INVALID (-1)
+#define ORACLE_ERR_CYCLE (-2)
+#define ORACLE_ERR_JACOBIAN (-3)
+#define ORACLE_ERR_OOM (-5)
+
+#define MAXP 4
+#define MAXM 3
+#define MAXNQ 12
+#define MAXN ((MAXP + 1) * (MAXP + 1))
+
+typedef struct {
+  int p, m, nq;
+  int n_elem, n_cp;
+  const double *cp_xy;  /* [n_cp][2] */
+  const int *elem_cp;   /* [n_elem][(m+1)^2], xi fastest */
+  int n_dir;
+  const double *omega;  /* [n_dir][2] */
+  const double *weight; /* [n_dir] */
+  const double *sigma_t;
+  const double *sigma_s;
+} oracle_problem;
+
+/* ------------------------------------------------------------------------ */
+/* one-dimensional tables                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Gauss-Lobatto points of degree k on [0,1] (endpoints and the roots of the
+ * derivative of the Legendre polynomial P_k), closed forms for k <= 4. */
+int oracle_gl_nodes(int k, double *z) {
+  switch (k) {
+    case 1: z[0] = 0.0; z[1] = 1.0; return ORACLE_OK;
+    case 2: z[0] = 0.0; z[1] = 0.5; z[2] = 1.0; return ORACLE_OK;
+    case 3: {
+      double r = 1.0 / sqrt(5.0);
+      z[0] = 0.0; z[1] = 0.5 * (1.0 - r); z[2] = 0.5 * (1.0 + r); z[3] = 1.0;
+      return ORACLE_OK;
+    }
+    case 4: {
+      double r = sqrt(3.0 / 7.0);
+      z[0] = 0.0; z[1] = 0.5 * (1.0 - r); z[2] = 0.5; z[3] = 0.5 * (1.0 + r); z[4] = 1.0;
+      return ORACLE_OK;
+    }
+    default: return ORACLE_ERR_INVALID;
+  }
+}
+
+/* Legendre polynomial P_n(x) and its derivative on [-1,1] by the three-term
+ * recurrence. */
+static void legendre(int n, double x, double *pn, double *dpn) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) { *pn = 1.0; *dpn = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *pn = p1;
+  *dpn = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+/* n-point Gauss-Legendre rule mapped to [0,1] (weights sum to 1), nodes
+ * ascending: Newton iteration on P_n from the Chebyshev-like initial guess. */
+int oracle_gauss_rule(int n, double *x, double *w) {
+  if (n < 1 || n > MAXNQ) return ORACLE_ERR_INVALID;
+  for (int i = 0; i < n; ++i) {
+    double t = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pn, dpn;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, t, &pn, &dpn);
+      double dt = pn / dpn;
+      t -= dt;
+      if (fabs(dt) < 1e-16) break;
+    }
+    legendre(n, t, &pn, &dpn);
+    /* t runs from near +1 downwards; store ascending */
+    x[n - 1 - i] = 0.5 * (1.0 + t);
+    w[n - 1 - i] = 1.0 / ((1.0 - t * t) * dpn * dpn);
+  }
+  return ORACLE_OK;
+}
+
+/* Lagrange polynomial a through nodes z[0..k] and its derivative at x. */
+static double lagrange(const double *z, int k, int a, double x) {
+  double v = 1.0;
+  for (int b = 0; b <= k; ++b)
+    if (b != a) v *= (x - z[b]) / (z[a] - z[b]);
+  return v;
+}
+
+static double lagrange_deriv(const double *z, int k, int a, double x) {
+  double s = 0.0;
+  for (int c = 0; c <= k; ++c) {
+    if (c == a) continue;
+    double t = 1.0 / (z[a] - z[c]);
+    for (int b = 0; b <= k; ++b)
+      if (b != a && b != c) t *= (x - z[b]) / (z[a] - z[b]);
+    s += t;
+  }
+  return s;
+}
+
+/* Tensor nodal basis of Q_k on [0,1]^2: l_i(xi,eta) = L_a(xi) L_b(eta) with
+ * i = a + (k+1) b; values and reference gradient. */
+static void basis2d(const double *z, int k, double xi, double eta, double *v,
+                    double *dxi, double *deta) {
+  double lx[MAXP + 1], ly[MAXP + 1], dx[MAXP + 1], dy[MAXP + 1];
+  for (int a = 0; a <= k; ++a) {
+    lx[a] = lagrange(z, k, a, xi);
+    ly[a] = lagrange(z, k, a, eta);
+    dx[a] = lagrange_deriv(z, k, a, xi);
+    dy[a] = lagrange_deriv(z, k, a, eta);
+  }
+  for (int b = 0; b <= k; ++b)
+    for (int a = 0; a <= k; ++a) {
+      int i = a + (k + 1) * b;
+      v[i] = lx[a] * ly[b];
+      if (dxi) dxi[i] = dx[a] * ly[b];
+      if (deta) deta[i] = lx[a] * dy[b];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* geometry (Sec. 3.1-3.2)                                                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  const oracle_problem *pr;
+  int n, nq, Q, ncp_e;
+  double zp[MAXP + 1];   /* basis nodes */
+  double zm[MAXM + 1];   /* geometry nodes */
+  double gx[MAXNQ], gw[MAXNQ];
+} ctx_t;
+
+static int ctx_init(ctx_t *c, const oracle_problem *pr) {
+  if (!pr || pr->p < 1 || pr->p > MAXP || pr->m < 1 || pr->m > MAXM) return ORACLE_ERR_INVALID;
+  if (pr->n_elem < 1 || pr->n_cp < 1 || pr->n_dir < 1) return ORACLE_ERR_INVALID;
+  c->pr = pr;
+  c->n = (pr->p + 1) * (pr->p + 1);
+  c->nq = pr->nq > 0 ? pr->nq : pr->p + pr->m;
+  if (c->nq > MAXNQ) return ORACLE_ERR_INVALID;
+  c->Q = c->nq * c->nq;
+  c->ncp_e = (pr->m + 1) * (pr->m + 1);
+  if (oracle_gl_nodes(pr->p, c->zp) || oracle_gl_nodes(pr->m, c->zm)) return ORACLE_ERR_INVALID;
+  if (oracle_gauss_rule(c->nq, c->gx, c->gw)) return ORACLE_ERR_INVALID;
+  for (int e = 0; e < pr->n_elem * c->ncp_e; ++e)
+    if (pr->elem_cp[e] < 0 || pr->elem_cp[e] >= pr->n_cp) return ORACLE_ERR_INVALID;
+  return ORACLE_OK;
+}
+
+/* x(xi) = sum_i x_{e,i} l_i(xi) and F = dx/dxi = [[x_xi, x_eta],[y_xi, y_eta]]. */
+static void map_point(const ctx_t *c, int e, double xi, double eta, double *x, double F[2][2]) {
+  const oracle_problem *pr = c->pr;
+  double v[(MAXM + 1) * (MAXM + 1)], dxi[(MAXM + 1) * (MAXM + 1)], deta[(MAXM + 1) * (MAXM + 1)];
+  basis2d(c->zm, pr->m, xi, eta, v, dxi, deta);
+  double X = 0, Y = 0, F00 = 0, F01 = 0, F10 = 0, F11 = 0;
+  for (int i = 0; i < c->ncp_e; ++i) {
+    const double *cp = pr->cp_xy + 2 * (size_t)pr->elem_cp[(size_t)e * c->ncp_e + i];
+    X += cp[0] * v[i];
+    Y += cp[1] * v[i];
+    F00 += cp[0] * dxi[i];
+    F01 += cp[0] * deta[i];
+    F10 += cp[1] * dxi[i];
+    F11 += cp[1] * deta[i];
+  }
+  if (x) { x[0] = X; x[1] = Y; }
+  if (F) { F[0][0] = F00; F[0][1] = F01; F[1][0] = F10; F[1][1] = F11; }
+}
+
+/* Faces in counter-clockwise order: 0: eta=0, 1: xi=1, 2: eta=1, 3: xi=0,
+ * each parameterised by s in [0,1] in the counter-clockwise sense. */
+static void face_point(int f, double s, double *xi, double *eta) {
+  switch (f) {
+    case 0: *xi = s; *eta = 0.0; break;
+    case 1: *xi = 1.0; *eta = s; break;
+    case 2: *xi = 1.0 - s; *eta = 1.0; break;
+    default: *xi = 0.0; *eta = 1.0 - s; break;
+  }
+}
+
+/* Outward n ds per unit s: the tangent t = dx/ds rotated clockwise. */
+static void face_nds(const double F[2][2], int f, double *nx, double *ny) {
+  double tx, ty;
+  switch (f) {
+    case 0: tx = F[0][0]; ty = F[1][0]; break;
+    case 1: tx = F[0][1]; ty = F[1][1]; break;
+    case 2: tx = -F[0][0]; ty = -F[1][0]; break;
+    default: tx = -F[0][1]; ty = -F[1][1]; break;
+  }
+  *nx = ty;
+  *ny = -tx;
+}
+
+/* local control-point index of the start and end corner of face f */
+static void face_corners(int m, int f, int *s, int *t) {
+  int c00 = 0, c10 = m, c01 = m * (m + 1), c11 = (m + 1) * (m + 1) - 1;
+  switch (f) {
+    case 0: *s = c00; *t = c10; break;
+    case 1: *s = c10; *t = c11; break;
+    case 2: *s = c11; *t = c01; break;
+    default: *s = c01; *t = c00; break;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* connectivity                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int *nbr;      /* [n_elem][4] neighbour element or -1 */
+  int *nbr_face; /* [n_elem][4] neighbour's local face */
+  int *nbr_rev;  /* [n_elem][4] 1 if the neighbour runs the face the other way */
+  int *bf_id;    /* [n_elem][4] boundary face index or -1 */
+  double *chord; /* [n_elem][4][2] N_F = rotated chord */
+  int n_bf;
+} conn_t;
+
+typedef struct { int lo, hi, e, f; } fkey_t;
+
+static int fkey_cmp(const void *a, const void *b) {
+  const fkey_t *x = (const fkey_t *)a, *y = (const fkey_t *)b;
+  if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
+  if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+  if (x->e != y->e) return x->e < y->e ? -1 : 1;
+  return x->f - y->f;
+}
+
+static void conn_free(conn_t *c) {
+  free(c->nbr); free(c->nbr_face); free(c->nbr_rev); free(c->bf_id); free(c->chord);
+  memset(c, 0, sizeof(*c));
+}
+
+/* Faces are matched by their two corner control points; an unmatched face lies
+ * on the domain boundary (Sec. 3.1, Gamma_0 and Gamma_b). */
+static int build_conn(const ctx_t *c, conn_t *cn) {
+  const oracle_problem *pr = c->pr;
+  int ne = pr->n_elem, m = pr->m;
+  memset(cn, 0, sizeof(*cn));
+  cn->nbr = (int *)malloc(sizeof(int) * 4 * (size_t)ne);
+  cn->nbr_face = (int *)malloc(sizeof(int) * 4 * (size_t)ne);
+  cn->nbr_rev = (int *)malloc(sizeof(int) * 4 * (size_t)ne);
+  cn->bf_id = (int *)malloc(sizeof(int) * 4 * (size_t)ne);
+  cn->chord = (double *)malloc(sizeof(double) * 8 * (size_t)ne);
+  fkey_t *keys = (fkey_t *)malloc(sizeof(fkey_t) * 4 * (size_t)ne);
+  if (!cn->nbr || !cn->nbr_face || !cn->nbr_rev || !cn->bf_id || !cn->chord || !keys) {
+    free(keys);
+    conn_free(cn);
+    return ORACLE_ERR_OOM;
+  }
+  for (int e = 0; e < ne; ++e)
+    for (int f = 0; f < 4; ++f) {
+      int ls, lt;
+      face_corners(m, f, &ls, &lt);
+      int gs = pr->elem_cp[(size_t)e * c->ncp_e + ls], gt = pr->elem_cp[(size_t)e * c->ncp_e + lt];
+      fkey_t *k = &keys[4 * e + f];
+      k->lo = gs < gt ? gs : gt;
+      k->hi = gs < gt ? gt : gs;
+      k->e = e;
+      k->f = f;
+      const double *xs = pr->cp_xy + 2 * (size_t)gs, *xt = pr->cp_xy + 2 * (size_t)gt;
+      double dx = xt[0] - xs[0], dy = xt[1] - xs[1];
+      cn->chord[8 * e + 2 * f + 0] = dy;
+      cn->chord[8 * e + 2 * f + 1] = -dx;
+      cn->nbr[4 * e + f] = -1;
+      cn->nbr_face[4 * e + f] = -1;
+      cn->nbr_rev[4 * e + f] = 0;
+      cn->bf_id[4 * e + f] = -1;
+    }
+  qsort(keys, 4 * (size_t)ne, sizeof(fkey_t), fkey_cmp);
+  int err = ORACLE_OK;
+  for (size_t i = 0; i < 4 * (size_t)ne;) {
+    size_t j = i + 1;
+    while (j < 4 * (size_t)ne && keys[j].lo == keys[i].lo && keys[j].hi == keys[i].hi) ++j;
+    if (j - i > 2) { err = ORACLE_ERR_INVALID; break; }
+    if (j - i == 2) {
+      fkey_t a = keys[i], b = keys[i + 1];
+      int as, at, bs, bt;
+      face_corners(m, a.f, &as, &at);
+      face_corners(m, b.f, &bs, &bt);
+      int gas = pr->elem_cp[(size_t)a.e * c->ncp_e + as];
+      int gbs = pr->elem_cp[(size_t)b.e * c->ncp_e + bs];
+      int rev = (gas != gbs); /* starts differ: the faces run in opposite senses */
+      cn->nbr[4 * a.e + a.f] = b.e; cn->nbr_face[4 * a.e + a.f] = b.f; cn->nbr_rev[4 * a.e + a.f] = rev;
+      cn->nbr[4 * b.e + b.f] = a.e; cn->nbr_face[4 * b.e + b.f] = a.f; cn->nbr_rev[4 * b.e + b.f] = rev;
+    }
+    i = j;
+  }
+  free(keys);
+  if (err) { conn_free(cn); return err; }
+  /* boundary faces numbered by (element, local face) ascending */
+  int nb = 0;
+  for (int e = 0; e < ne; ++e)
+    for (int f = 0; f < 4; ++f)
+      if (cn->nbr[4 * e + f] < 0) cn->bf_id[4 * e + f] = nb++;
+  cn->n_bf = nb;
+  return ORACLE_OK;
+}
+
+/* Jacobian determinant must be positive at every volume quadrature point. */
+static int check_jacobian(const ctx_t *c) {
+  for (int e = 0; e < c->pr->n_elem; ++e)
+    for (int qy = 0; qy < c->nq; ++qy)
+      for (int qx = 0; qx < c->nq; ++qx) {
+        double F[2][2];
+        map_point(c, e, c->gx[qx], c->gx[qy], NULL, F);
+        double J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+        if (!(J > 0.0)) return ORACLE_ERR_JACOBIAN;
+      }
+  return ORACLE_OK;
+}
+
+/* Is element e upwind of its face f for direction (ox, oy)? Interior faces
+ * only. */
+static int is_upwind(const conn_t *cn, int e, int f, double ox, double oy) {
+  double s = ox * cn->chord[8 * e + 2 * f] + oy * cn->chord[8 * e + 2 * f + 1];
+  if (s > 0.0) return 1;
+  if (s < 0.0) return 0;
+  return e < cn->nbr[4 * e + f];
+}
+
+/* Kahn topological order of the per-direction upwind graph, FIFO seeded with
+ * the sources in increasing element id; level = 1 + max upwind level. */
+static int topo_order(const ctx_t *c, const conn_t *cn, double ox, double oy, int *order,
+                      int *indeg, int *level, int *max_level) {
+  int ne = c->pr->n_elem;
+  for (int e = 0; e < ne; ++e) {
+    indeg[e] = 0;
+    level[e] = 0;
+    for (int f = 0; f < 4; ++f)
+      if (cn->nbr[4 * e + f] >= 0 && !is_upwind(cn, e, f, ox, oy)) indeg[e]++;
+  }
+  int head = 0, tail = 0;
+  for (int e = 0; e < ne; ++e)
+    if (indeg[e] == 0) order[tail++] = e;
+  int ml = 0;
+  while (head < tail) {
+    int e = order[head++];
+    if (level[e] > ml) ml = level[e];
+    for (int f = 0; f < 4; ++f) {
+      int nb = cn->nbr[4 * e + f];
+      if (nb >= 0 && is_upwind(cn, e, f, ox, oy)) {
+        if (level[e] + 1 > level[nb]) level[nb] = level[e] + 1;
+        if (--indeg[nb] == 0) order[tail++] = nb;
+      }
+    }
+  }
+  if (max_level) *max_level = ml;
+  return tail == ne ? ORACLE_OK : ORACLE_ERR_CYCLE;
+}
+
+/* Gaussian elimination with partial pivoting (first maximal |a| wins). */
+static int dense_solve(int n, double *A, double *b, double *x) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    double best = fabs(A[k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(A[i * n + k]) > best) { best = fabs(A[i * n + k]); piv = i; }
+    if (best == 0.0) return ORACLE_ERR_INVALID;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
+      double t = b[k]; b[k] = b[piv]; b[piv] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      double l = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+      b[i] -= l * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+    x[i] = s / A[i * n + i];
+  }
+  return ORACLE_OK;
+}
+
+/* Value of the degree-p DG function with nodal coefficients u at (xi, eta). */
+static double dg_eval(const ctx_t *c, const double *u, double xi, double eta) {
+  double v[MAXN];
+  basis2d(c->zp, c->pr->p, xi, eta, v, NULL, NULL);
+  double s = 0.0;
+  for (int j = 0; j < c->n; ++j) s += u[j] * v[j];
+  return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the sweep                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Assemble and solve the local system of element e for direction d.
+ * psi_d holds the already computed angular flux of direction d ([n_elem][n]). */
+static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const double *phi_in,
+                       const double *q_iso, const double *q_dir, const double *psi_bc,
+                       double *psi_d) {
+  const oracle_problem *pr = c->pr;
+  int n = c->n, nq = c->nq;
+  double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1];
+  double st = pr->sigma_t[e], ss = pr->sigma_s[e];
+  double A[MAXN * MAXN], b[MAXN], x[MAXN];
+  double v[MAXN], dxi[MAXN], deta[MAXN];
+  memset(A, 0, sizeof(double) * n * n);
+  memset(b, 0, sizeof(double) * n);
+  /* volume terms */
+  for (int qy = 0; qy < nq; ++qy)
+    for (int qx = 0; qx < nq; ++qx) {
+      double xi = c->gx[qx], eta = c->gx[qy], w = c->gw[qx] * c->gw[qy];
+      double F[2][2];
+      map_point(c, e, xi, eta, NULL, F);
+      double J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+      /* adj(F) = J F^{-1}: grad u = F^{-T} grad_ref u, so
+       * Omega . grad u J = (adj(F) Omega) . grad_ref u */
+      double gxi = F[1][1] * ox - F[0][1] * oy;
+      double geta = -F[1][0] * ox + F[0][0] * oy;
+      basis2d(c->zp, pr->p, xi, eta, v, dxi, deta);
+      double src = 0.0;
+      if (phi_in) {
+        double ph = 0.0;
+        for (int j = 0; j < n; ++j) ph += phi_in[(size_t)e * n + j] * v[j];
+        src += ss / (4.0 * M_PI) * ph;
+      }
+      if (q_iso) {
+        double qq = 0.0;
+        for (int j = 0; j < n; ++j) qq += q_iso[(size_t)e * n + j] * v[j];
+        src += qq;
+      }
+      if (q_dir) src += q_dir[((size_t)d * pr->n_elem + e) * c->Q + qx + nq * qy];
+      for (int i = 0; i < n; ++i) {
+        double stream = gxi * dxi[i] + geta * deta[i];
+        for (int j = 0; j < n; ++j)
+          A[i * n + j] += w * (st * J * v[i] * v[j] - stream * v[j]);
+        b[i] += w * J * v[i] * src;
+      }
+    }
+  /* face terms */
+  for (int f = 0; f < 4; ++f) {
+    int nb = cn->nbr[4 * e + f];
+    int outflow;
+    if (nb >= 0) {
+      outflow = is_upwind(cn, e, f, ox, oy);
+    } else {
+      double s = ox * cn->chord[8 * e + 2 * f] + oy * cn->chord[8 * e + 2 * f + 1];
+      outflow = !(s < 0.0);
+    }
+    for (int qs = 0; qs < nq; ++qs) {
+      double s = c->gx[qs], ws = c->gw[qs];
+      double xi, eta, F[2][2], nx, ny;
+      face_point(f, s, &xi, &eta);
+      map_point(c, e, xi, eta, NULL, F);
+      face_nds(F, f, &nx, &ny);
+      double on = ox * nx + oy * ny;
+      basis2d(c->zp, pr->p, xi, eta, v, NULL, NULL);
+      if (outflow) {
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) A[i * n + j] += ws * on * v[i] * v[j];
+      } else {
+        double up;
+        if (nb >= 0) {
+          double s2 = cn->nbr_rev[4 * e + f] ? 1.0 - s : s, xi2, eta2;
+          face_point(cn->nbr_face[4 * e + f], s2, &xi2, &eta2);
+          up = dg_eval(c, psi_d + (size_t)nb * n, xi2, eta2);
+        } else {
+          int bf = cn->bf_id[4 * e + f];
+          up = psi_bc ? psi_bc[((size_t)d * cn->n_bf + bf) * nq + qs] : 0.0;
+        }
+        for (int i = 0; i < n; ++i) b[i] -= ws * on * v[i] * up;
+      }
+    }
+  }
+  int rc = dense_solve(n, A, b, x);
+  if (rc) return rc;
+  memcpy(psi_d + (size_t)e * n, x, sizeof(double) * n);
+  return ORACLE_OK;
+}
+
+/* One transport sweep for every direction in dir_list (all when NULL):
+ *   phi_in  [n_elem][n]    scalar flux for the scattering source (NULL = 0)
+ *   q_iso   [n_elem][n]    isotropic source, nodal (NULL = 0)
+ *   q_dir   [n_dir][n_elem][Q] source at volume quadrature points (NULL = 0)
+ *   psi_bc  [n_dir][n_bf][nq] inflow data at boundary-face points (NULL = 0)
+ * outputs (each may be NULL):
+ *   psi_out [n_sel][n_elem][n], mom [6][n_elem][n] (phi, Jx, Jy, Pxx, Pxy,
+ *   Pyy summed over the selected directions in list order),
+ *   bnd_acc [n_bf][nq][2] (sum w |Omega.n| psi, sum w psi at boundary points,
+ *   interior trace), levels [n_sel] (1 + deepest level). */
+int oracle_sweep(const oracle_problem *pr, const double *phi_in, const double *q_iso,
+                 const double *q_dir, const double *psi_bc, const int *dir_list, int n_sel,
+                 double *psi_out, double *mom, double *bnd_acc, int *levels) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  if ((rc = check_jacobian(&c))) return rc;
+  conn_t cn;
+  if ((rc = build_conn(&c, &cn))) return rc;
+  int ne = pr->n_elem, n = c.n, nq = c.nq;
+  if (!dir_list) n_sel = pr->n_dir;
+  double *psi_d = (double *)calloc((size_t)ne * n, sizeof(double));
+  int *order = (int *)malloc(sizeof(int) * ne), *indeg = (int *)malloc(sizeof(int) * ne),
+      *lev = (int *)malloc(sizeof(int) * ne);
+  if (!psi_d || !order || !indeg || !lev) { rc = ORACLE_ERR_OOM; goto done; }
+  if (mom) memset(mom, 0, sizeof(double) * 6 * (size_t)ne * n);
+  if (bnd_acc) memset(bnd_acc, 0, sizeof(double) * 2 * (size_t)cn.n_bf * nq);
+  for (int k = 0; k < n_sel; ++k) {
+    int d = dir_list ? dir_list[k] : k;
+    if (d < 0 || d >= pr->n_dir) { rc = ORACLE_ERR_INVALID; goto done; }
+    double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1], w = pr->weight[d];
+    int ml;
+    if ((rc = topo_order(&c, &cn, ox, oy, order, indeg, lev, &ml))) goto done;
+    if (levels) levels[k] = ml + 1;
+    for (int t = 0; t < ne; ++t)
+      if ((rc = local_solve(&c, &cn, order[t], d, phi_in, q_iso, q_dir, psi_bc, psi_d))) goto done;
+    if (psi_out) memcpy(psi_out + (size_t)k * ne * n, psi_d, sizeof(double) * (size_t)ne * n);
+    if (mom) {
+      double fac[6] = {1.0, ox, oy, ox * ox, ox * oy, oy * oy};
+      for (int f = 0; f < 6; ++f)
+        for (size_t i = 0; i < (size_t)ne * n; ++i) mom[f * (size_t)ne * n + i] += w * fac[f] * psi_d[i];
+    }
+    if (bnd_acc) {
+      for (int e = 0; e < ne; ++e)
+        for (int f = 0; f < 4; ++f) {
+          int bf = cn.bf_id[4 * e + f];
+          if (bf < 0) continue;
+          for (int qs = 0; qs < nq; ++qs) {
+            double xi, eta, F[2][2], nx, ny;
+            face_point(f, c.gx[qs], &xi, &eta);
+            map_point(&c, e, xi, eta, NULL, F);
+            face_nds(F, f, &nx, &ny);
+            double len = sqrt(nx * nx + ny * ny);
+            double on = fabs(ox * nx / len + oy * ny / len);
+            double val = dg_eval(&c, psi_d + (size_t)e * n, xi, eta);
+            bnd_acc[((size_t)bf * nq + qs) * 2 + 0] += w * on * val;
+            bnd_acc[((size_t)bf * nq + qs) * 2 + 1] += w * val;
+          }
+        }
+    }
+  }
+done:
+  free(psi_d); free(order); free(indeg); free(lev);
+  conn_free(&cn);
+  return rc;
+}
+
+/* Number of boundary faces; fills bf[n_bf][2] = (element, local face) when
+ * given. */
+int oracle_boundary_faces(const oracle_problem *pr, int *bf) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  conn_t cn;
+  if ((rc = build_conn(&c, &cn))) return rc;
+  if (bf)
+    for (int e = 0; e < pr->n_elem; ++e)
+      for (int f = 0; f < 4; ++f)
+        if (cn.bf_id[4 * e + f] >= 0) {
+          bf[2 * cn.bf_id[4 * e + f]] = e;
+          bf[2 * cn.bf_id[4 * e + f] + 1] = f;
+        }
+  int nb = cn.n_bf;
+  conn_free(&cn);
+  return nb;
+}
+
+/* Physical coordinates of the quadrature points: vol_xy [n_elem][Q][2] (qx
+ * fastest), bnd_xy and unit outward normals bnd_n [n_bf][nq][2]. */
+int oracle_qp_coords(const oracle_problem *pr, double *vol_xy, double *bnd_xy, double *bnd_n) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  conn_t cn;
+  if ((rc = build_conn(&c, &cn))) return rc;
+  int nq = c.nq;
+  for (int e = 0; e < pr->n_elem; ++e) {
+    if (vol_xy)
+      for (int qy = 0; qy < nq; ++qy)
+        for (int qx = 0; qx < nq; ++qx)
+          map_point(&c, e, c.gx[qx], c.gx[qy], vol_xy + ((size_t)e * c.Q + qx + nq * qy) * 2, NULL);
+    for (int f = 0; f < 4; ++f) {
+      int bf = cn.bf_id[4 * e + f];
+      if (bf < 0) continue;
+      for (int qs = 0; qs < nq; ++qs) {
+        double xi, eta, F[2][2], x[2], nx, ny;
+        face_point(f, c.gx[qs], &xi, &eta);
+        map_point(&c, e, xi, eta, x, F);
+        face_nds(F, f, &nx, &ny);
+        double len = sqrt(nx * nx + ny * ny);
+        if (bnd_xy) { bnd_xy[((size_t)bf * nq + qs) * 2] = x[0]; bnd_xy[((size_t)bf * nq + qs) * 2 + 1] = x[1]; }
+        if (bnd_n) { bnd_n[((size_t)bf * nq + qs) * 2] = nx / len; bnd_n[((size_t)bf * nq + qs) * 2 + 1] = ny / len; }
+      }
+    }
+  }
+  conn_free(&cn);
+  return ORACLE_OK;
+}
+
+/* Geometry checks: total area sum_e sum_q w J, the largest |closed-contour
+ * integral of n ds| over elements, and the largest distance between the
+ * physical positions of a shared face quadrature point seen from its two
+ * elements. */
+int oracle_geometry_report(const oracle_problem *pr, double *area, double *max_closure,
+                           double *max_mismatch) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  conn_t cn;
+  if ((rc = build_conn(&c, &cn))) return rc;
+  int nq = c.nq;
+  double A = 0.0, mc = 0.0, mm = 0.0;
+  for (int e = 0; e < pr->n_elem; ++e) {
+    for (int qy = 0; qy < nq; ++qy)
+      for (int qx = 0; qx < nq; ++qx) {
+        double F[2][2];
+        map_point(&c, e, c.gx[qx], c.gx[qy], NULL, F);
+        A += c.gw[qx] * c.gw[qy] * (F[0][0] * F[1][1] - F[0][1] * F[1][0]);
+      }
+    double cx = 0.0, cy = 0.0;
+    for (int f = 0; f < 4; ++f)
+      for (int qs = 0; qs < nq; ++qs) {
+        double xi, eta, F[2][2], x[2], nx, ny;
+        face_point(f, c.gx[qs], &xi, &eta);
+        map_point(&c, e, xi, eta, x, F);
+        face_nds(F, f, &nx, &ny);
+        cx += c.gw[qs] * nx;
+        cy += c.gw[qs] * ny;
+        int nb = cn.nbr[4 * e + f];
+        if (nb >= 0) {
+          double s2 = cn.nbr_rev[4 * e + f] ? 1.0 - c.gx[qs] : c.gx[qs], xi2, eta2, x2[2];
+          face_point(cn.nbr_face[4 * e + f], s2, &xi2, &eta2);
+          map_point(&c, nb, xi2, eta2, x2, NULL);
+          double dd = hypot(x2[0] - x[0], x2[1] - x[1]);
+          if (dd > mm) mm = dd;
+        }
+      }
+    double cl = hypot(cx, cy);
+    if (cl > mc) mc = cl;
+  }
+  conn_free(&cn);
+  if (area) *area = A;
+  if (max_closure) *max_closure = mc;
+  if (max_mismatch) *max_mismatch = mm;
+  return ORACLE_OK;
+}
+
+/* Upwind-graph depth per direction (number of levels). */
+int oracle_levels(const oracle_problem *pr, int *levels) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  conn_t cn;
+  if ((rc = build_conn(&c, &cn))) return rc;
+  int ne = pr->n_elem;
+  int *order = (int *)malloc(sizeof(int) * ne), *indeg = (int *)malloc(sizeof(int) * ne),
+      *lev = (int *)malloc(sizeof(int) * ne);
+  if (!order || !indeg || !lev) rc = ORACLE_ERR_OOM;
+  for (int d = 0; !rc && d < pr->n_dir; ++d) {
+    int ml;
+    rc = topo_order(&c, &cn, pr->omega[2 * d], pr->omega[2 * d + 1], order, indeg, lev, &ml);
+    if (!rc) levels[d] = ml + 1;
+  }
+  free(order); free(indeg); free(lev);
+  conn_free(&cn);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* moments and closures (Eq. eq:vef_disc; Sec. 2)                           */
+/* ------------------------------------------------------------------------ */
+
+/* mom [6][n_elem][n] from psi [n_dir][n_elem][n], summed in direction order. */
+int oracle_moments_from_psi(const oracle_problem *pr, const double *psi, double *mom) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  size_t N = (size_t)pr->n_elem * c.n;
+  memset(mom, 0, sizeof(double) * 6 * N);
+  for (int d = 0; d < pr->n_dir; ++d) {
+    double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1], w = pr->weight[d];
+    double fac[6] = {1.0, ox, oy, ox * ox, ox * oy, oy * oy};
+    for (int f = 0; f < 6; ++f)
+      for (size_t i = 0; i < N; ++i) mom[f * N + i] += w * fac[f] * psi[d * N + i];
+  }
+  return ORACLE_OK;
+}
+
+/* Closures at quadrature points:
+ *   E  [3][n_elem][Q]  (xx, xy, yy) = P(x)/phi(x), ratios of DG functions;
+ *   Eb [n_bf][nq]      = bnd_acc num / den;
+ *   Jin [n_bf][nq]     = sum over directions with Omega.n < 0 of w (Omega.n) psibar;
+ *   Q0 [n_elem][Q], Q1 [2][n_elem][Q]: angular moments of the fixed source.
+ * Points where phi <= 0 (or the boundary denominator <= 0) get 0 and are
+ * counted in n_nonpos. Any output may be NULL. */
+int oracle_closures(const oracle_problem *pr, const double *mom, const double *bnd_acc,
+                    const double *q_iso, const double *q_dir, const double *psi_bc, double *E,
+                    double *Eb, double *Jin, double *Q0, double *Q1, int *n_nonpos) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  conn_t cn;
+  if ((rc = build_conn(&c, &cn))) return rc;
+  int ne = pr->n_elem, n = c.n, nq = c.nq, Q = c.Q;
+  size_t N = (size_t)ne * n;
+  int bad = 0;
+  for (int e = 0; e < ne; ++e)
+    for (int qy = 0; qy < nq; ++qy)
+      for (int qx = 0; qx < nq; ++qx) {
+        int q = qx + nq * qy;
+        double xi = c.gx[qx], eta = c.gx[qy];
+        if (E && mom) {
+          double ph = dg_eval(&c, mom + (size_t)e * n, xi, eta);
+          double pxx = dg_eval(&c, mom + 3 * N + (size_t)e * n, xi, eta);
+          double pxy = dg_eval(&c, mom + 4 * N + (size_t)e * n, xi, eta);
+          double pyy = dg_eval(&c, mom + 5 * N + (size_t)e * n, xi, eta);
+          size_t o = (size_t)e * Q + q;
+          if (ph > 0.0) {
+            E[o] = pxx / ph;
+            E[(size_t)ne * Q + o] = pxy / ph;
+            E[2 * (size_t)ne * Q + o] = pyy / ph;
+          } else {
+            E[o] = E[(size_t)ne * Q + o] = E[2 * (size_t)ne * Q + o] = 0.0;
+            bad++;
+          }
+        }
+        if (Q0 || Q1) {
+          double qi = q_iso ? dg_eval(&c, q_iso + (size_t)e * n, xi, eta) : 0.0;
+          double s0 = 0.0, s1x = 0.0, s1y = 0.0;
+          for (int d = 0; d < pr->n_dir; ++d) {
+            double qd = qi + (q_dir ? q_dir[((size_t)d * ne + e) * Q + q] : 0.0);
+            s0 += pr->weight[d] * qd;
+            s1x += pr->weight[d] * pr->omega[2 * d] * qd;
+            s1y += pr->weight[d] * pr->omega[2 * d + 1] * qd;
+          }
+          size_t o = (size_t)e * Q + q;
+          if (Q0) Q0[o] = s0;
+          if (Q1) { Q1[o] = s1x; Q1[(size_t)ne * Q + o] = s1y; }
+        }
+      }
+  for (int e = 0; e < ne; ++e)
+    for (int f = 0; f < 4; ++f) {
+      int bf = cn.bf_id[4 * e + f];
+      if (bf < 0) continue;
+      for (int qs = 0; qs < nq; ++qs) {
+        size_t o = (size_t)bf * nq + qs;
+        if (Eb && bnd_acc) {
+          double num = bnd_acc[2 * o], den = bnd_acc[2 * o + 1];
+          if (den > 0.0) Eb[o] = num / den;
+          else { Eb[o] = 0.0; bad++; }
+        }
+        if (Jin) {
+          double xi, eta, F[2][2], nx, ny;
+          face_point(f, c.gx[qs], &xi, &eta);
+          map_point(&c, e, xi, eta, NULL, F);
+          face_nds(F, f, &nx, &ny);
+          double len = sqrt(nx * nx + ny * ny);
+          double s = 0.0;
+          for (int d = 0; d < pr->n_dir; ++d) {
+            double on = pr->omega[2 * d] * nx / len + pr->omega[2 * d + 1] * ny / len;
+            if (on < 0.0 && psi_bc) s += pr->weight[d] * on * psi_bc[((size_t)d * cn.n_bf + bf) * nq + qs];
+          }
+          Jin[o] = s;
+        }
+      }
+    }
+  conn_free(&cn);
+  if (n_nonpos) *n_nonpos = bad;
+  return ORACLE_OK;
+}
+
+/* Source iteration: phi^0 = phi0 (NULL = 0); phi^{k+1} = phi of the sweep
+ * driven by phi^k; r_k = max_j |phi^{k+1}_j - phi^k_j| (max norm of successive
+ * iterates); stops after n_iter sweeps or when r_k < tol (tol > 0).
+ * mom receives the moments of the last sweep, resid [n_iter] the history. */
+int oracle_source_iteration(const oracle_problem *pr, const double *phi0, const double *q_iso,
+                            const double *q_dir, const double *psi_bc, int n_iter, double tol,
+                            double *mom, double *bnd_acc, double *resid, int *iters_done) {
+  ctx_t c;
+  int rc = ctx_init(&c, pr);
+  if (rc) return rc;
+  size_t N = (size_t)pr->n_elem * c.n;
+  double *phi = (double *)calloc(N, sizeof(double));
+  if (!phi) return ORACLE_ERR_OOM;
+  if (phi0) memcpy(phi, phi0, sizeof(double) * N);
+  int k = 0;
+  for (; k < n_iter; ++k) {
+    rc = oracle_sweep(pr, phi, q_iso, q_dir, psi_bc, NULL, 0, NULL, mom, bnd_acc, NULL);
+    if (rc) break;
+    double r = 0.0;
+    for (size_t i = 0; i < N; ++i) {
+      double dlt = fabs(mom[i] - phi[i]);
+      if (dlt > r) r = dlt;
+      phi[i] = mom[i];
+    }
+    if (resid) resid[k] = r;
+    if (tol > 0.0 && r < tol) { ++k; break; }
+  }
+  if (iters_done) *iters_done = k;
+  free(phi);
+  return rc;
+}
