@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the DG S_N sweep + VEF-moment path on one MI355X.
+
+One step = one full pass of the hot path over the synthetic workload with all
+inputs already in HBM: for the default workload (64x64 quadrilaterals, p = 2,
+level-symmetric S8 = 40 directions, sigma_t log-uniform in [0.1, 100] per 8x8
+block, scattering ratio 0.9, isotropic source 1, vacuum boundaries) that is 50
+source iterations -- each a full transport sweep (assembly + local solve of
+every element-direction pair in upwind order), the angular moments, the
+boundary sums and the max-norm residual -- followed by the VEF closures.
+The handle (host plan + upload) is created outside the timed region.
+
+Prints one JSON line.  Metric: element-direction solves per second
+(elements x directions x sweeps / time).  The roofline object refers to the
+dominant kernel (the sweep kernel), timed with HIP events on its own stream.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "element-direction solves/sec and HBM GB/s; FP32 batched vs FP64 sweep at 1e-5"
+FP64_PEAK_TFLOPS = 78.6    # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32
+HBM_PEAK_GBS = 8000.0
+
+
+def sweep_flops_per_solve(p):
+    """Algorithmic flops of one element-direction solve in the sweep kernel:
+    LU with pivoting (2/3 n^3) + two triangular solves (2 n^2) + A = sigma_t M +
+    Omega_x G^x + Omega_y G^y (6 n^2) + b = M s (2 n^2) + four face terms (12 (p+1)^2)."""
+    n = (p + 1) ** 2
+    return (2.0 / 3.0) * n ** 3 + 2 * n * n + 6 * n * n + 2 * n * n + 12 * (p + 1) ** 2
+
+
+def sweep_bytes_per_solve(p, m, n_dir, s):
+    """Algorithmic HBM bytes of one solve in the sweep kernel: psi write (n s),
+    upwind trace read (2 (p+1) s), and the element data (control points,
+    cross sections, scalar-flux coefficients) amortised over the n_dir/4
+    directions of a quadrant that visit the element together."""
+    n = (p + 1) ** 2
+    return n * s + 2 * (p + 1) * s + ((m + 1) ** 2 * 16 + 16 + 8 * n) / (n_dir / 4.0)
+
+
+def workload(name):
+    from paper_2301_04758_amd import problems as P
+    probs, run = P.make_config(name)
+    return probs, run
+
+
+def describe(name, probs, run):
+    pr = probs[0]
+    if name == "c2":
+        return ("64x64 quads, p=2, S8 (40 dirs), sigma_t log-uniform [0.1,100] per 8x8 block, c=0.9, "
+                "isotropic source 1, vacuum; 50 source iterations + closures")
+    return "%s: %d problems, first %dx%d p=%d n_dir=%d" % (name, len(probs), pr.nx, pr.ny, pr.p, pr.n_dir)
+
+
+def run_gpu(probs, n_iter, precision, steps, warmup, timing=True):
+    import torch
+    from paper_2301_04758_amd import vef
+    sw = vef.Sweep(probs, precision=precision, timing=timing)
+    io = sw.buffers(n_iter=n_iter, store_psi=True)
+    mio = sw.moment_buffers(io)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        sw.run(io, n_iter=n_iter, stream=stream)
+        sw.moments(mio, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    sweep_ms = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        if timing:
+            ms, nl = sw.timing()  # synchronises the stream after this step
+            sweep_ms += ms
+            launches += nl
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sw.check()
+    out = dict(seconds=t1 - t0, sweep_ms=sweep_ms, launches=launches,
+               phi=[b["mom"][0].double().cpu().numpy() for b in io],
+               resid=[b["resid"].cpu().numpy() for b in io])
+    sw.close()
+    return out
+
+
+def cpu_baseline(probs, iters):
+    """The oracle (serial double-precision C, gcc -O2) on the host, on the first
+    `iters` source iterations of the same workload."""
+    from oracle import oracle as O
+    pr = probs[0]
+    t0 = time.perf_counter()
+    r = O.source_iteration(pr, iters)
+    dt = time.perf_counter() - t0
+    solves = pr.n_elem * pr.n_dir * r["iters"]
+    return dict(value=solves / dt, unit="element-direction solves/s", cores=1, kind="oracle",
+                sample="first %d of the 50 source iterations of the same workload (%d solves, %.1f s)"
+                % (r["iters"], solves, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the sweep library has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    probs, run = workload(args.workload)
+    n_iter = run["n_iter"]
+    pr = probs[0]
+    solves_per_step = sum(p.n_elem * p.n_dir for p in probs) * n_iter
+
+    g64 = run_gpu(probs, n_iter, "fp64", args.steps, args.warmup)
+    ms_step = 1e3 * g64["seconds"] / args.steps
+    value = solves_per_step * args.steps / g64["seconds"]
+
+    # dominant kernel: the sweep kernel, timed by events on the run's stream
+    F = sweep_flops_per_solve(pr.p)
+    B = sweep_bytes_per_solve(pr.p, pr.m, pr.n_dir, 8)
+    launches = max(g64["launches"], 1)
+    avg_launch_s = g64["sweep_ms"] * 1e-3 / launches
+    solves_per_launch = solves_per_step * args.steps / launches
+    achieved_tf = F * solves_per_launch / avg_launch_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_sweep_level<2,3,double>", "avg_launch_us": avg_launch_s * 1e6,
+                "launches_per_step": launches / args.steps,
+                "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
+                "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
+    hbm_gbs = B * solves_per_step / (ms_step * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "element-direction solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": describe(args.workload, probs, run), "n_elem": pr.n_elem, "p": pr.p,
+                   "n_dir": pr.n_dir, "sweeps_per_step": n_iter, "schedule": "level_sync",
+                   "precision": "fp64"},
+        "hbm_gbs_algorithmic": hbm_gbs,
+        "roofline": roofline,
+    }
+    if not args.no_fp32:
+        g32 = run_gpu(probs, n_iter, "fp32", args.steps, args.warmup)
+        ms32 = 1e3 * g32["seconds"] / args.steps
+        err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(g32["phi"], g64["phi"]))
+        result["fp32_local"] = {"ms_per_step": ms32, "value": solves_per_step / (ms32 * 1e-3),
+                                "speedup_vs_fp64": ms_step / ms32,
+                                "rel_inf_phi_vs_fp64_path": err, "within_1e-5": err <= 1e-5}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(probs, args.cpu_iters)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

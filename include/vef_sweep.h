@@ -1,0 +1,201 @@
+/*
+ * vef_sweep.h -- C ABI of the MI355X (gfx950) discrete-ordinates DG transport
+ * sweep and VEF-moment library.
+ *
+ * What it computes.  For the steady, mono-energetic transport equation with
+ * isotropic scattering (Olivier & Haut, "High-Order Mixed Finite Element
+ * Variable Eddington Factor Methods", Sec. 2, Eq. eq:transport with inflow
+ * condition eq:trans_bc), discretised in angle by discrete ordinates and in
+ * space by an upwind discontinuous Galerkin method of degree p on curved
+ * quadrilateral meshes (Sec. 5; meshes and reference-space integration of
+ * Sec. 3.1-3.2; DG space Y_p of Sec. 4.1):
+ *   - vef_sweep_run: for every direction and every element, in upwind order,
+ *     assemble the (p+1)^2-unknown local system by quadrature and solve it
+ *     (a transport sweep), then reduce the angular flux to its angular moments
+ *     phi, J, P (the numerator and denominator sums of Eq. eq:vef_disc);
+ *     optionally repeat as a source iteration with the max-norm residual of
+ *     successive scalar-flux iterates (stopping rule of Sec. 8);
+ *   - vef_moments: the VEF closures at quadrature points: the Eddington
+ *     tensor E = P/phi (ratio of DG functions, Sec. 5), the boundary factor
+ *     E_b (Eq. eq:vef_disc), the inflow partial current J_in and the source
+ *     moments Q_0, Q_1 (Sec. 2).
+ *
+ * Discretisation conventions (fixed by this library, and identical in its
+ * test oracle):
+ *   - reference element [0,1]^2, coordinates (xi, eta); element map of order
+ *     m from (m+1)^2 control points at Gauss-Lobatto points, xi fastest;
+ *   - angular flux basis: tensor Lagrange polynomials through the p+1
+ *     Gauss-Lobatto points, node index a + (p+1) b (a along xi);
+ *   - quadrature: tensor Gauss-Legendre, nq points per direction
+ *     (default p + m), volume point index qx + nq*qy, ascending;
+ *   - faces 0: eta=0, 1: xi=1, 2: eta=1, 3: xi=0, each parameterised
+ *     counter-clockwise by s in [0,1]; face points ascending in s;
+ *   - the upwind side of a face is chosen for the whole face from the sign
+ *     of Omega . N_F, N_F the clockwise-rotated chord from the face's first
+ *     to its last corner (equal to the integral of n ds); a zero product makes
+ *     the lower element id upwind; a boundary face is inflow when
+ *     Omega . N_F < 0;
+ *   - boundary faces are numbered in ascending (element, local face) order.
+ *
+ * Errors: every call returns a status (VEF_OK or a negative VEF_ERR_*).
+ * vef_last_error(h) returns a message for the last failure on h, or for the
+ * last failed create when h is NULL.  Handles are not thread-safe; calls on
+ * one handle must not overlap.
+ */
+#ifndef VEF_SWEEP_H
+#define VEF_SWEEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vef_sweep vef_sweep_t;
+
+enum {
+  VEF_OK = 0,
+  VEF_ERR_INVALID = -1,  /* bad argument, size or mesh */
+  VEF_ERR_CYCLE = -2,    /* upwind graph of some direction is cyclic */
+  VEF_ERR_JACOBIAN = -3, /* element map with J <= 0 at a quadrature point */
+  VEF_ERR_HIP = -4,      /* HIP runtime failure (no device, launch error) */
+  VEF_ERR_OOM = -5,      /* device or host allocation failed */
+  VEF_ERR_TIMEOUT = -6   /* reserved: bounded device wait expired */
+};
+
+enum { VEF_FP64 = 0, VEF_FP32_LOCAL = 1 };
+enum { VEF_LEVEL_SYNC = 0, VEF_PERSISTENT = 1 };
+
+/* One transport problem (host pointers, copied by vef_sweep_create and not
+ * retained).  Mirrors the problem statement of Sec. 2 (sigma_t, sigma_s),
+ * the mesh description of Sec. 3.1 (control points + local nodal map), the
+ * degree p of Y_p (Sec. 4.1) and the discrete-ordinates set of Sec. 5. */
+typedef struct {
+  int p;                  /* DG degree, 1..4 */
+  int m;                  /* geometry order, 1..3 */
+  int nq;                 /* Gauss points per direction; 0 = p + m; else p+1..p+4 */
+  int n_elem;             /* elements, >= 1 */
+  int n_cp;               /* control points, >= 4 */
+  const double *cp_xy;    /* [n_cp][2] */
+  const int32_t *elem_cp; /* [n_elem][(m+1)^2] control point ids, xi fastest */
+  int n_dir;              /* directions, 1..1024 */
+  const double *omega;    /* [n_dir][2] in-plane components, |Omega| <= 1 */
+  const double *weight;   /* [n_dir] positive, sum 4 pi (checked to 1e-12 rel) */
+  const double *sigma_t;  /* [n_elem] total cross section, >= 0 */
+  const double *sigma_s;  /* [n_elem] scattering cross section, >= 0 */
+} vef_problem_desc;
+
+typedef struct {
+  int precision; /* VEF_FP64: every step in double.  VEF_FP32_LOCAL: local
+                    assembly and solves in float with float accumulation,
+                    angular flux stored as float; moments, residual and
+                    closures in double. */
+  int schedule;  /* VEF_LEVEL_SYNC: one launch per upwind level.
+                    VEF_PERSISTENT: one launch per sweep with device-side
+                    dependency counters. */
+  int block;     /* work-group size for the sweep kernels; 0 = default 256 */
+  int timing;    /* nonzero: runs record HIP events around the sweep kernels
+                    of every source iteration (read with vef_sweep_timing) */
+  int reserved[4];
+} vef_options;
+
+/* Per-problem device buffers of one run (device pointers owned by the caller).
+ * n = (p+1)^2, Q = nq^2, n_bf = boundary faces (vef_problem_info). */
+typedef struct {
+  const double *phi_in; /* [n_elem][n] scalar flux for the scattering source of
+                           the first sweep; NULL = 0.  Later source iterations
+                           use the previous sweep's phi. */
+  const double *q_iso;  /* [n_elem][n] isotropic source per steradian, nodal; NULL = 0 */
+  const double *q_dir;  /* [n_dir][n_elem][Q] source at volume points; NULL = 0 */
+  const double *psi_bc; /* [n_dir][n_bf][nq] inflow data at boundary points; NULL = vacuum */
+  double *mom;          /* [6][n_elem][n] out: phi, Jx, Jy, Pxx, Pxy, Pyy (nodal) */
+  void *psi_out;        /* [n_dir][n_elem][n] out: angular flux, double (VEF_FP64)
+                           or float (VEF_FP32_LOCAL); NULL = kept internally */
+  double *resid;        /* [n_iter] out: max_j |phi_new_j - phi_in_j| per sweep; may be NULL */
+} vef_problem_io;
+
+typedef struct {
+  const vef_problem_io *io; /* host array [n_probs] */
+  int n_iter;               /* sweeps of source iteration, >= 1 */
+  double tol;               /* > 0: stop (device-side test) once every problem's
+                               residual is < tol; later sweeps are skipped */
+  int *iters_done;          /* device int out: sweeps performed; may be NULL */
+} vef_run_args;
+
+/* Per-problem device buffers of vef_moments (device pointers, caller-owned). */
+typedef struct {
+  const double *mom;    /* [6][n_elem][n] from vef_sweep_run */
+  const double *q_iso;  /* as in the run (for Q0, Q1); may be NULL */
+  const double *q_dir;  /* as in the run; may be NULL */
+  const double *psi_bc; /* as in the run (for J_in); may be NULL */
+  double *E;            /* [3][n_elem][Q] out: Exx, Exy, Eyy at volume points; may be NULL */
+  double *Eb;           /* [n_bf][nq] out; may be NULL */
+  double *Jin;          /* [n_bf][nq] out; may be NULL */
+  double *Q0;           /* [n_elem][Q] out; may be NULL */
+  double *Q1;           /* [2][n_elem][Q] out; may be NULL */
+  int *n_nonpos;        /* device int out: points where phi <= 0 (E left 0) plus
+                           boundary points with a non-positive denominator (E_b
+                           left 0); may be NULL */
+} vef_moment_io;
+
+typedef struct {
+  int n;         /* unknowns per element, (p+1)^2 */
+  int nq;        /* Gauss points per direction */
+  int Q;         /* volume points per element */
+  int n_bf;      /* boundary faces */
+  int n_levels;  /* deepest upwind level over directions, plus one */
+  int n_groups;  /* classes of directions sharing one upwind graph */
+  long long n_solves; /* n_elem * n_dir */
+} vef_info;
+
+/* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
+ * upwind graphs), build the sweep plan on the host and upload it to the
+ * current HIP device.  Synchronous.  n_probs > 1 gives one batched handle
+ * whose runs sweep all problems together.  opt may be NULL (defaults). */
+int vef_sweep_create(const vef_problem_desc *probs, int n_probs, const vef_options *opt,
+                     vef_sweep_t **out);
+
+/* Enqueue n_iter sweeps (+ moments, residual, boundary sums) on stream
+ * (a hipStream_t; NULL = default stream).  Asynchronous: outputs are valid
+ * after the stream is synchronised.  The library keeps the boundary sums of
+ * the last sweep for vef_moments. */
+int vef_sweep_run(vef_sweep_t *h, const vef_run_args *args, void *stream);
+
+/* Enqueue the closure kernels for every problem (io: host array [n_probs]),
+ * reading the boundary sums of the last run on h. */
+int vef_moments(vef_sweep_t *h, const vef_moment_io *io, void *stream);
+
+/* Free all device and host memory of h.  NULL is a no-op. */
+int vef_sweep_destroy(vef_sweep_t *h);
+
+/* Host-only: validate one problem and build its plan without touching the
+ * GPU; fills *info.  Returns the status vef_sweep_create would return for the
+ * problem (except HIP and device-memory errors). */
+int vef_plan_query(const vef_problem_desc *prob, vef_info *info);
+
+/* Sizes of problem k of a handle. */
+int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info);
+
+/* Boundary faces of problem k as (element, local face) pairs, host array
+ * [n_bf][2]. */
+int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out);
+
+/* Synchronise the handle's last stream and return the device status word:
+ * VEF_OK, or VEF_ERR_INVALID when a local system had a zero pivot. */
+int vef_sweep_check(vef_sweep_t *h);
+
+/* Timing of the last run on a handle created with opt->timing != 0:
+ * synchronises, then returns in *sweep_ms the summed device time from the
+ * first to the last sweep kernel of each source iteration (HIP events on the
+ * run's stream) and in *n_launches the number of sweep-kernel launches that
+ * time covers.  Either pointer may be NULL. */
+int vef_sweep_timing(vef_sweep_t *h, double *sweep_ms, int *n_launches);
+
+const char *vef_last_error(const vef_sweep_t *h);
+const char *vef_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VEF_SWEEP_H */

@@ -1,0 +1,523 @@
+// C ABI of the sweep library (declared in include/vef_sweep.h): handle
+// creation (host plan + upload), runs (enqueue of the level-synchronous sweep,
+// moment/residual/boundary kernels per source iteration), closures, queries.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+#include "vef_sweep.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct TableSet {
+  void *dev_T = nullptr;       // float or double tables for the sweep kernel
+  double *dev_d = nullptr;     // double tables for reductions / closures
+};
+
+struct LevelLaunch {
+  int p, nq;
+  int off, cnt;
+  const void *tab;
+};
+
+}  // namespace
+
+struct vef_sweep {
+  std::string err;
+  int precision = VEF_FP64;
+  int schedule = VEF_LEVEL_SYNC;
+  int block = 256;
+  int device = 0;
+  std::vector<vefplan::ProblemPlan> plans;
+  std::vector<void *> allocs;
+  std::map<std::pair<int, int>, TableSet> tables;
+  std::vector<vefk::KProb> h_probs;
+  vefk::KProb *d_probs = nullptr;
+  vefk::KIO *d_io = nullptr;
+  vefk::KMomIO *d_mio = nullptr;
+  vefk::KIO *h_io_pinned = nullptr;       // staging for d_io uploads
+  vefk::KMomIO *h_mio_pinned = nullptr;   // staging for d_mio uploads
+  hipEvent_t io_uploaded = nullptr;
+  hipEvent_t mio_uploaded = nullptr;
+  std::vector<vefk::KIO> io_last;
+  bool io_valid = false;
+  int2 *d_solves = nullptr;
+  std::vector<std::vector<LevelLaunch>> levels;
+  std::vector<void *> psi_internal;   // per problem, allocated on first need
+  std::vector<double *> resid_scratch;
+  std::vector<int> resid_cap;
+  int *d_flags = nullptr;  // [0] stop, [1] iterations done, [2] status
+  hipStream_t last_stream = nullptr;
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // [2 * iterations] of the last run
+  int timed_iters = 0;
+  int timed_launches = 0;
+};
+
+namespace {
+
+int set_err(vef_sweep *h, int code, const std::string &msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_error = msg;
+  return code;
+}
+
+int hip_fail(vef_sweep *h, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_err(h, e == hipErrorOutOfMemory ? VEF_ERR_OOM : VEF_ERR_HIP, m);
+}
+
+template <typename X>
+hipError_t dev_alloc(vef_sweep *h, X **p, size_t count) {
+  void *v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(count * sizeof(X), 16));
+  if (e != hipSuccess) return e;
+  h->allocs.push_back(v);
+  *p = static_cast<X *>(v);
+  return hipSuccess;
+}
+
+template <typename X>
+hipError_t upload(vef_sweep *h, X **p, const X *src, size_t count) {
+  hipError_t e = dev_alloc(h, p, count);
+  if (e != hipSuccess) return e;
+  if (count == 0) return hipSuccess;
+  return hipMemcpy(*p, src, count * sizeof(X), hipMemcpyHostToDevice);
+}
+
+template <typename X>
+hipError_t upload_as(vef_sweep *h, void **p, const std::vector<double> &src) {
+  std::vector<X> tmp(src.begin(), src.end());
+  X *q = nullptr;
+  hipError_t e = upload(h, &q, tmp.data(), tmp.size());
+  *p = q;
+  return e;
+}
+
+void free_all(vef_sweep *h) {
+  if (!h) return;
+  for (void *p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  for (void *p : h->psi_internal)
+    if (p) (void)hipFree(p);
+  h->psi_internal.clear();
+  for (double *p : h->resid_scratch)
+    if (p) (void)hipFree(p);
+  h->resid_scratch.clear();
+  if (h->h_io_pinned) (void)hipHostFree(h->h_io_pinned);
+  if (h->h_mio_pinned) (void)hipHostFree(h->h_mio_pinned);
+  h->h_io_pinned = nullptr;
+  h->h_mio_pinned = nullptr;
+  for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+  h->events.clear();
+  if (h->io_uploaded) (void)hipEventDestroy(h->io_uploaded);
+  if (h->mio_uploaded) (void)hipEventDestroy(h->mio_uploaded);
+  h->io_uploaded = h->mio_uploaded = nullptr;
+}
+
+std::vector<double> table_blob(const vefplan::Tables &t) {
+  std::vector<double> b;
+  b.insert(b.end(), t.V.begin(), t.V.end());
+  b.insert(b.end(), t.Dx.begin(), t.Dx.end());
+  b.insert(b.end(), t.Dy.begin(), t.Dy.end());
+  b.insert(b.end(), t.F.begin(), t.F.end());
+  return b;
+}
+
+int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *opt, vef_sweep *h) {
+  if (opt) {
+    if (opt->precision != VEF_FP64 && opt->precision != VEF_FP32_LOCAL)
+      return set_err(h, VEF_ERR_INVALID, "unknown precision");
+    if (opt->schedule != VEF_LEVEL_SYNC)
+      return set_err(h, VEF_ERR_INVALID, "schedule not available (use VEF_LEVEL_SYNC)");
+    if (opt->block != 0 && (opt->block < 64 || opt->block > 1024 || opt->block % 64))
+      return set_err(h, VEF_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
+    h->precision = opt->precision;
+    h->schedule = opt->schedule;
+    h->timing = opt->timing != 0;
+    h->block = opt->block ? opt->block : 256;
+    if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
+  }
+  if (n_probs > 1024) return set_err(h, VEF_ERR_INVALID, "at most 1024 problems per handle");
+  h->plans.resize(n_probs);
+  for (int k = 0; k < n_probs; ++k) {
+    std::string e;
+    int rc = vefplan::build_problem_plan(probs[k], h->plans[k], e);
+    if (rc) return set_err(h, rc, "problem " + std::to_string(k) + ": " + e);
+  }
+  hipError_t he = hipGetDevice(&h->device);
+  if (he != hipSuccess) return hip_fail(h, he, "hipGetDevice");
+  const bool fp32 = h->precision == VEF_FP32_LOCAL;
+
+  // tables per (p, nq)
+  for (auto &pl : h->plans) {
+    auto key = std::make_pair(pl.p, pl.nq);
+    if (h->tables.count(key)) continue;
+    TableSet ts;
+    std::vector<double> blob = table_blob(pl.tab);
+    he = fp32 ? upload_as<float>(h, &ts.dev_T, blob) : upload_as<double>(h, &ts.dev_T, blob);
+    if (he != hipSuccess) return hip_fail(h, he, "upload tables");
+    he = upload(h, &ts.dev_d, blob.data(), blob.size());
+    if (he != hipSuccess) return hip_fail(h, he, "upload tables");
+    h->tables[key] = ts;
+  }
+
+  // per-problem constant data
+  h->h_probs.resize(n_probs);
+  for (int k = 0; k < n_probs; ++k) {
+    const auto &pl = h->plans[k];
+    vefk::KProb kp{};
+    kp.ne = pl.ne;
+    kp.nd = pl.nd;
+    kp.nbf = pl.nbf;
+    kp.n = pl.n;
+    kp.Q = pl.Q;
+    kp.nq = pl.nq;
+    kp.p = pl.p;
+    void *gv = nullptr, *gf = nullptr;
+    he = fp32 ? upload_as<float>(h, &gv, pl.geo_v) : upload_as<double>(h, &gv, pl.geo_v);
+    if (he == hipSuccess) he = fp32 ? upload_as<float>(h, &gf, pl.geo_f) : upload_as<double>(h, &gf, pl.geo_f);
+    kp.geo_v = gv;
+    kp.geo_f = gf;
+    double *gfd = nullptr, *om = nullptr, *wt = nullptr, *sig = nullptr, *bnd = nullptr;
+    int32_t *nbr = nullptr, *bfe = nullptr;
+    int8_t *nbf = nullptr;
+    uint8_t *mask = nullptr;
+    std::vector<double> sg(2 * (size_t)pl.ne);
+    for (int e = 0; e < pl.ne; ++e) {
+      sg[2 * e] = pl.sigma_t[e];
+      sg[2 * e + 1] = pl.sigma_s[e];
+    }
+    if (he == hipSuccess) he = upload(h, &gfd, pl.geo_f.data(), pl.geo_f.size());
+    if (he == hipSuccess) he = upload(h, &nbr, pl.nbr.data(), pl.nbr.size());
+    if (he == hipSuccess) he = upload(h, &nbf, pl.nbr_face.data(), pl.nbr_face.size());
+    if (he == hipSuccess) he = upload(h, &mask, pl.mask.data(), pl.mask.size());
+    if (he == hipSuccess) he = upload(h, &om, pl.omega.data(), pl.omega.size());
+    if (he == hipSuccess) he = upload(h, &wt, pl.weight.data(), pl.weight.size());
+    if (he == hipSuccess) he = upload(h, &sig, sg.data(), sg.size());
+    if (he == hipSuccess) he = upload(h, &bfe, pl.bf_ef.data(), pl.bf_ef.size());
+    if (he == hipSuccess) he = dev_alloc(h, &bnd, (size_t)pl.nbf * pl.nq * 2);
+    if (he != hipSuccess) return hip_fail(h, he, "upload problem data");
+    kp.geo_fd = gfd;
+    kp.nbr = nbr;
+    kp.nbr_face = nbf;
+    kp.mask = mask;
+    kp.omega = om;
+    kp.weight = wt;
+    kp.sig = sig;
+    kp.bf_ef = bfe;
+    kp.bnd = bnd;
+    kp.tab_d = h->tables[std::make_pair(pl.p, pl.nq)].dev_d;
+    h->h_probs[k] = kp;
+  }
+  he = upload(h, &h->d_probs, h->h_probs.data(), h->h_probs.size());
+  if (he == hipSuccess) he = dev_alloc(h, &h->d_io, n_probs);
+  if (he == hipSuccess) he = dev_alloc(h, &h->d_mio, n_probs);
+  if (he == hipSuccess) he = dev_alloc(h, &h->d_flags, 4);
+  if (he == hipSuccess) he = hipMemset(h->d_flags, 0, 4 * sizeof(int));
+  if (he == hipSuccess) he = hipHostMalloc((void **)&h->h_io_pinned, sizeof(vefk::KIO) * n_probs, 0);
+  if (he == hipSuccess) he = hipHostMalloc((void **)&h->h_mio_pinned, sizeof(vefk::KMomIO) * n_probs, 0);
+  if (he == hipSuccess) he = hipEventCreateWithFlags(&h->io_uploaded, hipEventDisableTiming);
+  if (he == hipSuccess) he = hipEventCreateWithFlags(&h->mio_uploaded, hipEventDisableTiming);
+  if (he != hipSuccess) return hip_fail(h, he, "allocate handle buffers");
+
+  // level lists: level -> variant (p, nq) -> problem -> class -> element -> direction
+  int max_levels = 0;
+  for (auto &pl : h->plans) max_levels = std::max(max_levels, pl.n_levels);
+  std::vector<std::pair<int, int>> variants;
+  for (auto &kv : h->tables) variants.push_back(kv.first);
+  std::vector<std::vector<std::vector<int>>> dirs_of(n_probs);
+  for (int k = 0; k < n_probs; ++k) {
+    const auto &pl = h->plans[k];
+    dirs_of[k].resize(pl.n_groups);
+    for (int d = 0; d < pl.nd; ++d) dirs_of[k][pl.dir_group[d]].push_back(d);
+  }
+  size_t total = 0;
+  for (auto &pl : h->plans) total += (size_t)pl.ne * pl.nd;
+  std::vector<int2> solves;
+  solves.reserve(total);
+  h->levels.assign(max_levels, {});
+  for (int L = 0; L < max_levels; ++L)
+    for (auto &var : variants) {
+      const int off = (int)solves.size();
+      for (int k = 0; k < n_probs; ++k) {
+        const auto &pl = h->plans[k];
+        if (pl.p != var.first || pl.nq != var.second || L >= pl.n_levels) continue;
+        for (int g = 0; g < pl.n_groups; ++g) {
+          const int *lo = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
+          const int32_t *ord = &pl.order[(size_t)g * pl.ne];
+          for (int t = lo[L]; t < lo[L + 1]; ++t)
+            for (int d : dirs_of[k][g]) solves.push_back(make_int2(ord[t], d | (k << 16)));
+        }
+      }
+      const int cnt = (int)solves.size() - off;
+      if (cnt > 0) h->levels[L].push_back({var.first, var.second, off, cnt, h->tables[var].dev_T});
+    }
+  if (solves.size() != total) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
+  if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
+  he = upload(h, &h->d_solves, solves.data(), solves.size());
+  if (he != hipSuccess) return hip_fail(h, he, "upload solve lists");
+  h->psi_internal.assign(n_probs, nullptr);
+  h->resid_scratch.assign(n_probs, nullptr);
+  h->resid_cap.assign(n_probs, 0);
+  return VEF_OK;
+}
+
+bool same_io(const vefk::KIO &a, const vefk::KIO &b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int vef_sweep_create(const vef_problem_desc *probs, int n_probs, const vef_options *opt,
+                     vef_sweep_t **out) {
+  if (!out) return set_err(nullptr, VEF_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!probs || n_probs < 1) return set_err(nullptr, VEF_ERR_INVALID, "no problems");
+  vef_sweep *h = new (std::nothrow) vef_sweep();
+  if (!h) return set_err(nullptr, VEF_ERR_OOM, "host allocation failed");
+  int rc;
+  try {
+    rc = create_impl(probs, n_probs, opt, h);
+  } catch (const std::bad_alloc &) {
+    rc = set_err(h, VEF_ERR_OOM, "host allocation failed");
+  }
+  if (rc) {
+    g_create_error = h->err;
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return VEF_OK;
+}
+
+int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
+  if (!h) return VEF_ERR_INVALID;
+  if (!a || !a->io || a->n_iter < 1) return set_err(h, VEF_ERR_INVALID, "bad run arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int np = (int)h->plans.size();
+  const bool fp32 = h->precision == VEF_FP32_LOCAL;
+  const size_t esz = fp32 ? sizeof(float) : sizeof(double);
+  hipError_t he;
+  std::vector<vefk::KIO> io(np);
+  for (int k = 0; k < np; ++k) {
+    const vef_problem_io &u = a->io[k];
+    const auto &pl = h->plans[k];
+    if (!u.mom) return set_err(h, VEF_ERR_INVALID, "mom is NULL for problem " + std::to_string(k));
+    void *psi = u.psi_out;
+    if (!psi) {
+      if (!h->psi_internal[k]) {
+        he = hipMalloc(&h->psi_internal[k], std::max<size_t>((size_t)pl.nd * pl.ne * pl.n * esz, 16));
+        if (he != hipSuccess) {
+          h->psi_internal[k] = nullptr;
+          return hip_fail(h, he, "allocate angular flux");
+        }
+      }
+      psi = h->psi_internal[k];
+    }
+    double *resid = u.resid;
+    if (!resid) {
+      if (h->resid_cap[k] < a->n_iter) {
+        if (h->resid_scratch[k]) {
+          (void)hipDeviceSynchronize();
+          (void)hipFree(h->resid_scratch[k]);
+          h->resid_scratch[k] = nullptr;
+        }
+        he = hipMalloc((void **)&h->resid_scratch[k], sizeof(double) * a->n_iter);
+        if (he != hipSuccess) return hip_fail(h, he, "allocate residual scratch");
+        h->resid_cap[k] = a->n_iter;
+      }
+      resid = h->resid_scratch[k];
+    }
+    io[k] = vefk::KIO{u.phi_in, u.q_iso, u.q_dir, u.psi_bc, u.mom, psi, resid};
+  }
+  bool changed = !h->io_valid;
+  for (int k = 0; k < np && !changed; ++k) changed = !same_io(io[k], h->io_last[k]);
+  if (changed) {
+    // the pinned staging buffer may still feed a previous upload
+    he = hipEventSynchronize(h->io_uploaded);
+    if (he != hipSuccess) return hip_fail(h, he, "wait for previous upload");
+    std::memcpy(h->h_io_pinned, io.data(), sizeof(vefk::KIO) * np);
+    he = hipMemcpyAsync(h->d_io, h->h_io_pinned, sizeof(vefk::KIO) * np, hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipEventRecord(h->io_uploaded, s);
+    if (he != hipSuccess) return hip_fail(h, he, "upload run pointers");
+    h->io_last = io;
+    h->io_valid = true;
+  }
+  int *stop = h->d_flags, *iters = h->d_flags + 1, *status = h->d_flags + 2;
+  if (h->timing) {
+    while ((int)h->events.size() < 2 * a->n_iter) {
+      hipEvent_t ev;
+      he = hipEventCreate(&ev);
+      if (he != hipSuccess) return hip_fail(h, he, "create timing event");
+      h->events.push_back(ev);
+    }
+    h->timed_iters = a->n_iter;
+    h->timed_launches = 0;
+  }
+  he = vefk::launch_run_init(h->d_io, np, a->n_iter, stop, iters, s);
+  if (he != hipSuccess) return hip_fail(h, he, "launch init");
+  for (int it = 0; it < a->n_iter; ++it) {
+    if (h->timing && (he = hipEventRecord(h->events[2 * it], s)) != hipSuccess)
+      return hip_fail(h, he, "record timing event");
+    for (auto &lv : h->levels)
+      for (auto &L : lv) {
+        he = vefk::launch_sweep_level(L.p, L.nq, fp32, h->d_solves + L.off, L.cnt, h->d_probs, h->d_io,
+                                      L.tab, it, stop, status, h->block, s);
+        if (he != hipSuccess) return hip_fail(h, he, "launch sweep");
+        if (h->timing) h->timed_launches++;
+      }
+    if (h->timing && (he = hipEventRecord(h->events[2 * it + 1], s)) != hipSuccess)
+      return hip_fail(h, he, "record timing event");
+    for (int k = 0; k < np; ++k) {
+      const auto &pl = h->plans[k];
+      he = vefk::launch_moments(fp32, h->d_probs, h->d_io, k, pl.ne * pl.n, it, stop, s);
+      if (he == hipSuccess) he = vefk::launch_boundary(fp32, h->d_probs, h->d_io, k, pl.nbf, pl.nq, pl.p, stop, s);
+      if (he != hipSuccess) return hip_fail(h, he, "launch moments");
+    }
+    he = vefk::launch_finalize(h->d_io, np, it, a->tol, stop, iters, a->iters_done, s);
+    if (he != hipSuccess) return hip_fail(h, he, "launch finalize");
+  }
+  h->last_stream = s;
+  return VEF_OK;
+}
+
+int vef_moments(vef_sweep_t *h, const vef_moment_io *io, void *stream) {
+  if (!h) return VEF_ERR_INVALID;
+  if (!io) return set_err(h, VEF_ERR_INVALID, "io is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int np = (int)h->plans.size();
+  std::vector<vefk::KMomIO> m(np);
+  for (int k = 0; k < np; ++k) {
+    const vef_moment_io &u = io[k];
+    if (u.E && !u.mom) return set_err(h, VEF_ERR_INVALID, "E requested without mom");
+    m[k] = vefk::KMomIO{u.mom, u.q_iso, u.q_dir, u.psi_bc, u.E, u.Eb, u.Jin, u.Q0, u.Q1, u.n_nonpos};
+  }
+  hipError_t he = hipEventSynchronize(h->mio_uploaded);
+  if (he != hipSuccess) return hip_fail(h, he, "wait for previous upload");
+  std::memcpy(h->h_mio_pinned, m.data(), sizeof(vefk::KMomIO) * np);
+  he = hipMemcpyAsync(h->d_mio, h->h_mio_pinned, sizeof(vefk::KMomIO) * np, hipMemcpyHostToDevice, s);
+  if (he == hipSuccess) he = hipEventRecord(h->mio_uploaded, s);
+  if (he == hipSuccess) he = vefk::launch_zero_nonpos(h->d_mio, np, s);
+  if (he != hipSuccess) return hip_fail(h, he, "upload closure pointers");
+  for (int k = 0; k < np; ++k) {
+    const auto &pl = h->plans[k];
+    he = vefk::launch_closures(h->d_probs, h->d_mio, k, pl.ne, pl.Q, pl.nbf, pl.nq, s);
+    if (he != hipSuccess) return hip_fail(h, he, "launch closures");
+  }
+  h->last_stream = s;
+  return VEF_OK;
+}
+
+int vef_sweep_destroy(vef_sweep_t *h) {
+  if (!h) return VEF_OK;
+  (void)hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+  return VEF_OK;
+}
+
+int vef_plan_query(const vef_problem_desc *prob, vef_info *info) {
+  if (!prob) return set_err(nullptr, VEF_ERR_INVALID, "prob is NULL");
+  vefplan::ProblemPlan pl;
+  std::string e;
+  int rc;
+  try {
+    rc = vefplan::build_problem_plan(*prob, pl, e);
+  } catch (const std::bad_alloc &) {
+    return set_err(nullptr, VEF_ERR_OOM, "host allocation failed");
+  }
+  if (rc) return set_err(nullptr, rc, e);
+  if (info) {
+    info->n = pl.n;
+    info->nq = pl.nq;
+    info->Q = pl.Q;
+    info->n_bf = pl.nbf;
+    info->n_levels = pl.n_levels;
+    info->n_groups = pl.n_groups;
+    info->n_solves = (long long)pl.ne * pl.nd;
+  }
+  return VEF_OK;
+}
+
+int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
+  if (!h || !info || k < 0 || k >= (int)h->plans.size()) return VEF_ERR_INVALID;
+  const auto &pl = h->plans[k];
+  info->n = pl.n;
+  info->nq = pl.nq;
+  info->Q = pl.Q;
+  info->n_bf = pl.nbf;
+  info->n_levels = pl.n_levels;
+  info->n_groups = pl.n_groups;
+  info->n_solves = (long long)pl.ne * pl.nd;
+  return VEF_OK;
+}
+
+int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out) {
+  if (!h || !out || k < 0 || k >= (int)h->plans.size()) return VEF_ERR_INVALID;
+  const auto &pl = h->plans[k];
+  for (int b = 0; b < pl.nbf; ++b) {
+    out[2 * b] = pl.bf_ef[b] >> 2;
+    out[2 * b + 1] = pl.bf_ef[b] & 3;
+  }
+  return VEF_OK;
+}
+
+int vef_sweep_check(vef_sweep_t *h) {
+  if (!h) return VEF_ERR_INVALID;
+  hipError_t he = hipStreamSynchronize(h->last_stream);
+  if (he != hipSuccess) return hip_fail(h, he, "stream synchronize");
+  int flags[4];
+  he = hipMemcpy(flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return hip_fail(h, he, "read status");
+  if (flags[2]) return set_err(h, VEF_ERR_INVALID, "zero pivot in a local system");
+  return VEF_OK;
+}
+
+int vef_sweep_timing(vef_sweep_t *h, double *sweep_ms, int *n_launches) {
+  if (!h) return VEF_ERR_INVALID;
+  if (!h->timing) return set_err(h, VEF_ERR_INVALID, "handle was created without timing");
+  hipError_t he = hipStreamSynchronize(h->last_stream);
+  if (he != hipSuccess) return hip_fail(h, he, "stream synchronize");
+  double tot = 0.0;
+  for (int it = 0; it < h->timed_iters; ++it) {
+    float ms = 0.0f;
+    he = hipEventElapsedTime(&ms, h->events[2 * it], h->events[2 * it + 1]);
+    if (he != hipSuccess) return hip_fail(h, he, "event elapsed time");
+    tot += ms;
+  }
+  if (sweep_ms) *sweep_ms = tot;
+  if (n_launches) *n_launches = h->timed_launches;
+  return VEF_OK;
+}
+
+const char *vef_last_error(const vef_sweep_t *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+const char *vef_status_string(int status) {
+  switch (status) {
+    case VEF_OK: return "ok";
+    case VEF_ERR_INVALID: return "invalid argument";
+    case VEF_ERR_CYCLE: return "cyclic upwind graph";
+    case VEF_ERR_JACOBIAN: return "non-positive Jacobian";
+    case VEF_ERR_HIP: return "HIP runtime error";
+    case VEF_ERR_OOM: return "out of memory";
+    case VEF_ERR_TIMEOUT: return "device wait timed out";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Device-side data structures and kernel entry points of the sweep library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vefk {
+
+// Per-problem constant data (device pointers), one entry per problem of a handle.
+struct KProb {
+  int ne, nd, nbf, n, Q, nq, p, pad;
+  const void *geo_v;       // T [ne][Q][5]: w J, w adj(F) (row major)
+  const void *geo_f;       // T [ne][4][nq][2]: w_s n ds
+  const double *geo_fd;    // double copy of geo_f
+  const int32_t *nbr;      // [ne][4] neighbour or -(bf+1)
+  const int8_t *nbr_face;  // [ne][4]
+  const uint8_t *mask;     // [nd][ne] inflow-face bits
+  const double *omega;     // [nd][2]
+  const double *weight;    // [nd]
+  const double *sig;       // [ne][2] sigma_t, sigma_s
+  const int32_t *bf_ef;    // [nbf] 4*e + f
+  double *bnd;             // [nbf][nq][2] boundary sums of the last sweep
+  const double *tab_d;     // double tables of (p, nq): V, Dx, Dy [Q][n] then F [nq][p+1]
+};
+
+// Per-problem buffers of one run.
+struct KIO {
+  const double *phi_in;
+  const double *q_iso;
+  const double *q_dir;
+  const double *psi_bc;
+  double *mom;
+  void *psi;      // T [nd][ne][n]
+  double *resid;  // [n_iter] (library scratch when the caller passes NULL)
+};
+
+struct KMomIO {
+  const double *mom, *q_iso, *q_dir, *psi_bc;
+  double *E, *Eb, *Jin, *Q0, *Q1;
+  int *n_nonpos;
+};
+
+// Launch helpers (defined in kernels.hip).  All return the launch's hipError_t.
+hipError_t launch_sweep_level(int p, int nq, bool fp32, const int2 *solves, int n_solves,
+                              const KProb *probs, const KIO *io, const void *tables, int it,
+                              const int *stop, int *status, int block, hipStream_t s);
+hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob, int ne_n, int it,
+                          const int *stop, hipStream_t s);
+hipError_t launch_boundary(bool fp32, const KProb *probs, const KIO *io, int prob, int nbf, int nq,
+                           int p, const int *stop, hipStream_t s);
+hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, int *iters,
+                           hipStream_t s);
+hipError_t launch_finalize(const KIO *io, int n_probs, int it, double tol, int *stop, int *iters,
+                           int *iters_user, hipStream_t s);
+hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int nbf,
+                           int nq, hipStream_t s);
+hipError_t launch_zero_nonpos(const KMomIO *io, int n_probs, hipStream_t s);
+
+}  // namespace vefk

@@ -1,0 +1,58 @@
+// Host-side sweep plan: reference tables, geometry at quadrature points, face
+// connectivity, per-direction upwind masks, direction classes and upwind
+// levels.  Pure C++ (no HIP): everything here runs once at handle creation.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vef_sweep.h"
+
+namespace vefplan {
+
+constexpr int kMaxP = 4;
+constexpr int kMaxM = 3;
+constexpr int kMaxDirs = 1024;
+
+// Basis and quadrature tables of one (p, nq) pair, all in double.
+struct Tables {
+  int p = 0, nq = 0;
+  std::vector<double> gl;   // [p+1] Gauss-Lobatto nodes on [0,1], exactly symmetric
+  std::vector<double> gx;   // [nq] Gauss-Legendre points on [0,1], exactly symmetric
+  std::vector<double> gw;   // [nq] weights, sum 1
+  std::vector<double> V;    // [Q][n] basis values at volume points
+  std::vector<double> Dx;   // [Q][n] d/dxi
+  std::vector<double> Dy;   // [Q][n] d/deta
+  std::vector<double> F;    // [nq][p+1] 1D basis at face points
+};
+
+struct ProblemPlan {
+  int p = 0, m = 0, nq = 0, n = 0, Q = 0;
+  int ne = 0, nd = 0, nbf = 0;
+  // geometry, double precision
+  std::vector<double> geo_v;     // [ne][Q][5]: w J, w adjF00, w adjF01, w adjF10, w adjF11
+  std::vector<double> geo_f;     // [ne][4][nq][2]: w_s * (n ds) at face points
+  std::vector<int32_t> nbr;      // [ne][4]: neighbour element, or -(bf+1) on the boundary
+  std::vector<int8_t> nbr_face;  // [ne][4]: neighbour's local face (or -1)
+  std::vector<int32_t> bf_ef;    // [nbf]: 4*element + face
+  std::vector<uint8_t> mask;     // [nd][ne]: bit f set when face f is inflow
+  std::vector<int32_t> dir_group;   // [nd] direction class (identical masks)
+  std::vector<int32_t> group_rep;   // [n_groups] first direction of each class
+  std::vector<int32_t> level;       // [n_groups][ne] upwind level
+  std::vector<int32_t> order;       // [n_groups][ne] elements in (level, id) order
+  std::vector<int32_t> level_off;   // [n_groups][n_levels+1] offsets into order
+  int n_groups = 0;
+  int n_levels = 0;                 // max over classes
+  std::vector<int32_t> n_levels_g;  // [n_groups]
+  std::vector<double> omega, weight, sigma_t, sigma_s;
+  Tables tab;
+};
+
+int build_tables(int p, int nq, Tables &t);
+
+// Validates and plans one problem.  Returns VEF_OK or a VEF_ERR_* status and
+// a message in err.
+int build_problem_plan(const vef_problem_desc &d, ProblemPlan &out, std::string &err);
+
+}  // namespace vefplan

@@ -1,0 +1,295 @@
+"""Thin ctypes binding of the C ABI in include/vef_sweep.h (argument marshalling only).
+
+The functions vef_sweep_create / vef_sweep_run / vef_moments / vef_sweep_destroy
+and the queries keep the C names and argument order.  Device buffers are
+PyTorch tensors on the current HIP device (only their data pointers cross the
+boundary); streams are torch streams (their hipStream_t handle crosses).
+Every step of the sweep runs in the HIP library: if libvefsweep.so is missing
+the import of this module fails.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvefsweep.so")
+
+VEF_OK = 0
+VEF_ERR_INVALID = -1
+VEF_ERR_CYCLE = -2
+VEF_ERR_JACOBIAN = -3
+VEF_ERR_HIP = -4
+VEF_ERR_OOM = -5
+VEF_ERR_TIMEOUT = -6
+VEF_FP64 = 0
+VEF_FP32_LOCAL = 1
+VEF_LEVEL_SYNC = 0
+VEF_PERSISTENT = 1
+
+EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
+            "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
+            "vef_last_error", "vef_status_string")
+
+
+class vef_problem_desc(C.Structure):
+    _fields_ = [("p", C.c_int), ("m", C.c_int), ("nq", C.c_int), ("n_elem", C.c_int), ("n_cp", C.c_int),
+                ("cp_xy", C.c_void_p), ("elem_cp", C.c_void_p), ("n_dir", C.c_int),
+                ("omega", C.c_void_p), ("weight", C.c_void_p), ("sigma_t", C.c_void_p),
+                ("sigma_s", C.c_void_p)]
+
+
+class vef_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("schedule", C.c_int), ("block", C.c_int), ("timing", C.c_int),
+                ("reserved", C.c_int * 4)]
+
+
+class vef_problem_io(C.Structure):
+    _fields_ = [("phi_in", C.c_void_p), ("q_iso", C.c_void_p), ("q_dir", C.c_void_p),
+                ("psi_bc", C.c_void_p), ("mom", C.c_void_p), ("psi_out", C.c_void_p),
+                ("resid", C.c_void_p)]
+
+
+class vef_run_args(C.Structure):
+    _fields_ = [("io", C.POINTER(vef_problem_io)), ("n_iter", C.c_int), ("tol", C.c_double),
+                ("iters_done", C.c_void_p)]
+
+
+class vef_moment_io(C.Structure):
+    _fields_ = [("mom", C.c_void_p), ("q_iso", C.c_void_p), ("q_dir", C.c_void_p), ("psi_bc", C.c_void_p),
+                ("E", C.c_void_p), ("Eb", C.c_void_p), ("Jin", C.c_void_p), ("Q0", C.c_void_p),
+                ("Q1", C.c_void_p), ("n_nonpos", C.c_void_p)]
+
+
+class vef_info(C.Structure):
+    _fields_ = [("n", C.c_int), ("nq", C.c_int), ("Q", C.c_int), ("n_bf", C.c_int), ("n_levels", C.c_int),
+                ("n_groups", C.c_int), ("n_solves", C.c_longlong)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libvefsweep.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2301_04758_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    H = C.c_void_p
+    L.vef_sweep_create.argtypes = [C.POINTER(vef_problem_desc), C.c_int, C.POINTER(vef_options), C.POINTER(H)]
+    L.vef_sweep_run.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p]
+    L.vef_moments.argtypes = [H, C.POINTER(vef_moment_io), C.c_void_p]
+    L.vef_sweep_destroy.argtypes = [H]
+    L.vef_plan_query.argtypes = [C.POINTER(vef_problem_desc), C.POINTER(vef_info)]
+    L.vef_problem_info.argtypes = [H, C.c_int, C.POINTER(vef_info)]
+    L.vef_boundary_faces.argtypes = [H, C.c_int, C.c_void_p]
+    L.vef_sweep_check.argtypes = [H]
+    L.vef_sweep_timing.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.vef_last_error.argtypes = [H]
+    L.vef_last_error.restype = C.c_char_p
+    L.vef_status_string.argtypes = [C.c_int]
+    L.vef_status_string.restype = C.c_char_p
+    for f in ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
+              "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing"):
+        getattr(L, f).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+class VefError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (status %d: %s)" % (msg, code, lib.vef_status_string(code).decode()))
+        self.code = code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class _Desc:
+    """A vef_problem_desc plus the numpy arrays its pointers refer to."""
+
+    def __init__(self, pr):
+        self.cp = np.ascontiguousarray(pr.cp_xy, dtype=np.float64)
+        self.ec = np.ascontiguousarray(pr.elem_cp, dtype=np.int32)
+        self.om = np.ascontiguousarray(pr.omega, dtype=np.float64)
+        self.wt = np.ascontiguousarray(pr.weight, dtype=np.float64)
+        self.st = np.ascontiguousarray(pr.sigma_t, dtype=np.float64)
+        self.ss = np.ascontiguousarray(pr.sigma_s, dtype=np.float64)
+        self.s = vef_problem_desc(pr.p, pr.m, int(pr.nq), self.ec.shape[0], self.cp.shape[0], self.cp.ctypes.data,
+                                  self.ec.ctypes.data, self.om.shape[0], self.om.ctypes.data, self.wt.ctypes.data,
+                                  self.st.ctypes.data, self.ss.ctypes.data)
+
+
+# ------------------------------------------------------------------ C names
+
+
+def vef_plan_query(problem) -> dict:
+    d = _Desc(problem)
+    info = vef_info()
+    rc = lib.vef_plan_query(C.byref(d.s), C.byref(info))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(None).decode())
+    return {f: getattr(info, f) for f, _ in vef_info._fields_}
+
+
+def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_LEVEL_SYNC,
+                     block: int = 0, timing: bool = False) -> int:
+    descs = [_Desc(p) for p in problems]
+    arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
+    opt = vef_options(precision, schedule, block, 1 if timing else 0)
+    h = C.c_void_p()
+    rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(None).decode())
+    return h.value
+
+
+def vef_sweep_run(h: int, io: Sequence[dict], n_iter: int = 1, tol: float = 0.0, iters_done=None, stream=None):
+    arr = (vef_problem_io * len(io))()
+    for k, b in enumerate(io):
+        arr[k] = vef_problem_io(_ptr(b.get("phi_in")), _ptr(b.get("q_iso")), _ptr(b.get("q_dir")),
+                                _ptr(b.get("psi_bc")), _ptr(b["mom"]), _ptr(b.get("psi_out")), _ptr(b.get("resid")))
+    args = vef_run_args(arr, int(n_iter), float(tol), _ptr(iters_done))
+    rc = lib.vef_sweep_run(C.c_void_p(h), C.byref(args), C.c_void_p(_stream_handle(stream)))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+
+
+def vef_moments(h: int, io: Sequence[dict], stream=None):
+    arr = (vef_moment_io * len(io))()
+    for k, b in enumerate(io):
+        arr[k] = vef_moment_io(*[_ptr(b.get(f)) for f, _ in vef_moment_io._fields_])
+    rc = lib.vef_moments(C.c_void_p(h), arr, C.c_void_p(_stream_handle(stream)))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+
+
+def vef_sweep_destroy(h: Optional[int]):
+    lib.vef_sweep_destroy(C.c_void_p(h) if h else None)
+
+
+def vef_problem_info(h: int, k: int) -> dict:
+    info = vef_info()
+    rc = lib.vef_problem_info(C.c_void_p(h), int(k), C.byref(info))
+    if rc != VEF_OK:
+        raise VefError(rc, "vef_problem_info")
+    return {f: getattr(info, f) for f, _ in vef_info._fields_}
+
+
+def vef_boundary_faces(h: int, k: int) -> np.ndarray:
+    nbf = vef_problem_info(h, k)["n_bf"]
+    out = np.zeros((nbf, 2), dtype=np.int32)
+    rc = lib.vef_boundary_faces(C.c_void_p(h), int(k), out.ctypes.data)
+    if rc != VEF_OK:
+        raise VefError(rc, "vef_boundary_faces")
+    return out
+
+
+def vef_sweep_timing(h: int):
+    """(summed sweep-kernel device time in ms of the last run, number of sweep launches)."""
+    ms = C.c_double()
+    n = C.c_int()
+    rc = lib.vef_sweep_timing(C.c_void_p(h), C.byref(ms), C.byref(n))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+    return ms.value, n.value
+
+
+def vef_sweep_check(h: int):
+    rc = lib.vef_sweep_check(C.c_void_p(h))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+
+
+# ------------------------------------------------------------------ convenience
+
+
+class Sweep:
+    """Owns one handle; allocates device buffers with torch for convenience."""
+
+    def __init__(self, problems, precision="fp64", block=0, device=None, timing=False):
+        import torch
+        self.torch = torch
+        self.problems = list(problems)
+        self.fp32 = precision == "fp32"
+        self.device = torch.device("cuda" if device is None else device)
+        with torch.cuda.device(self.device):
+            self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64, VEF_LEVEL_SYNC, block,
+                                      timing)
+        self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
+
+    def close(self):
+        if self.h:
+            vef_sweep_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _t(self, a, dtype=None):
+        if a is None:
+            return None
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(self.device).contiguous()
+        return t.as_tensor(np.ascontiguousarray(a), dtype=dtype or t.float64, device=self.device)
+
+    def buffers(self, n_iter=1, store_psi=True, phi_in=None):
+        """Device buffers for every problem: inputs from the Problem arrays, zeroed outputs."""
+        t = self.torch
+        out = []
+        for pr, inf in zip(self.problems, self.info):
+            n = inf["n"]
+            b = dict(q_iso=self._t(pr.q_iso), q_dir=self._t(pr.q_dir), psi_bc=self._t(pr.psi_bc),
+                     phi_in=self._t(phi_in) if phi_in is not None else None,
+                     mom=t.zeros((6, pr.n_elem, n), dtype=t.float64, device=self.device),
+                     resid=t.zeros(n_iter, dtype=t.float64, device=self.device))
+            if store_psi:
+                b["psi_out"] = t.zeros((pr.n_dir, pr.n_elem, n), dtype=t.float32 if self.fp32 else t.float64,
+                                       device=self.device)
+            out.append(b)
+        return out
+
+    def run(self, io, n_iter=1, tol=0.0, iters_done=None, stream=None):
+        vef_sweep_run(self.h, io, n_iter, tol, iters_done, stream)
+
+    def moment_buffers(self, io):
+        t = self.torch
+        out = []
+        for b, pr, inf in zip(io, self.problems, self.info):
+            Q, nbf, nq = inf["Q"], inf["n_bf"], inf["nq"]
+            out.append(dict(mom=b["mom"], q_iso=b.get("q_iso"), q_dir=b.get("q_dir"), psi_bc=b.get("psi_bc"),
+                            E=t.zeros((3, pr.n_elem, Q), dtype=t.float64, device=self.device),
+                            Eb=t.zeros((nbf, nq), dtype=t.float64, device=self.device),
+                            Jin=t.zeros((nbf, nq), dtype=t.float64, device=self.device),
+                            Q0=t.zeros((pr.n_elem, Q), dtype=t.float64, device=self.device),
+                            Q1=t.zeros((2, pr.n_elem, Q), dtype=t.float64, device=self.device),
+                            n_nonpos=t.zeros(1, dtype=t.int32, device=self.device)))
+        return out
+
+    def moments(self, mio, stream=None):
+        vef_moments(self.h, mio, stream)
+
+    def check(self):
+        vef_sweep_check(self.h)
+
+    def timing(self):
+        return vef_sweep_timing(self.h)

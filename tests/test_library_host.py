@@ -1,0 +1,108 @@
+"""CPU-side checks of the HIP library: it loads, exports every declared entry
+point, and its host planner (validation, face matching, upwind levels) agrees
+with the oracle.  No kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2301_04758_amd import problems as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vef_sweep.h")
+
+
+def _vef():
+    from paper_2301_04758_amd import vef
+    return vef
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vef_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    vef = _vef()
+    names = declared_functions()
+    assert {"vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy"} <= set(names)
+    lib = C.CDLL(vef.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(vef.EXPORTED)
+
+
+def test_status_strings():
+    vef = _vef()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert vef.lib.vef_status_string(code)
+    vef.vef_sweep_destroy(None)  # NULL is a no-op
+
+
+@pytest.mark.parametrize("cfg,scale", [("c1", None), ("c2", 16), ("c3", 12), ("c5", 8)])
+def test_plan_matches_oracle_levels_and_faces(cfg, scale):
+    vef = _vef()
+    (pr,), _ = P.make_config(cfg, scale=scale)
+    info = vef.vef_plan_query(pr)
+    assert info["n"] == (pr.p + 1) ** 2
+    assert info["nq"] == pr.p + pr.m
+    assert info["n_bf"] == O.n_boundary_faces(pr)
+    assert info["n_levels"] == int(O.levels(pr).max())
+    assert info["n_solves"] == pr.n_elem * pr.n_dir
+    if pr.m == 1:
+        assert info["n_groups"] == 4  # straight Cartesian mesh: one upwind graph per quadrant
+
+
+def _bad(pr, code):
+    vef = _vef()
+    with pytest.raises(vef.VefError) as ei:
+        vef.vef_plan_query(pr)
+    assert ei.value.code == code
+    return str(ei.value)
+
+
+def test_plan_rejects_bad_inputs():
+    vef = _vef()
+    base, _ = P.make_config("c1")
+    pr = base[0]
+    import copy
+    q = copy.deepcopy(pr)
+    q.p = 5
+    _bad(q, vef.VEF_ERR_INVALID)
+    q = copy.deepcopy(pr)
+    q.weight = q.weight * 1.001
+    assert "4 pi" in _bad(q, vef.VEF_ERR_INVALID)
+    q = copy.deepcopy(pr)
+    q.sigma_t = q.sigma_t.copy()
+    q.sigma_t[3] = np.nan
+    _bad(q, vef.VEF_ERR_INVALID)
+    q = copy.deepcopy(pr)
+    q.elem_cp = q.elem_cp.copy()
+    q.elem_cp[0, 0] = 10 ** 6
+    _bad(q, vef.VEF_ERR_INVALID)
+    q = copy.deepcopy(pr)
+    q.nq = pr.p + 5
+    _bad(q, vef.VEF_ERR_INVALID)
+    # mirrored element: negative Jacobian
+    q = copy.deepcopy(pr)
+    ec = q.elem_cp.copy()
+    ec[0] = ec[0][[1, 0, 3, 2]]
+    q.elem_cp = ec
+    _bad(q, vef.VEF_ERR_JACOBIAN)
+
+
+def test_plan_detects_cycle():
+    """A mesh whose upwind graph has a cycle for some direction is rejected
+    before any launch (the fixture is a 3x3 curved mesh with non-convex chord quadrilaterals)."""
+    vef = _vef()
+    from cyclic_mesh import reentrant_problem
+    pr = reentrant_problem()
+    with pytest.raises(O.OracleError) as oe:
+        O.levels(pr)
+    assert oe.value.code == O.ERR_CYCLE
+    msg = _bad(pr, vef.VEF_ERR_CYCLE)
+    assert "cycle" in msg
