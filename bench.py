@@ -61,10 +61,10 @@ def describe(name, probs, run):
     return "%s: %d problems, first %dx%d p=%d n_dir=%d" % (name, len(probs), pr.nx, pr.ny, pr.p, pr.n_dir)
 
 
-def run_gpu(probs, n_iter, precision, steps, warmup, timing=True):
+def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto"):
     import torch
     from paper_2301_04758_amd import vef
-    sw = vef.Sweep(probs, precision=precision, timing=timing)
+    sw = vef.Sweep(probs, precision=precision, timing=timing, schedule=schedule)
     io = sw.buffers(n_iter=n_iter, store_psi=True)
     mio = sw.moment_buffers(io)
     stream = torch.cuda.current_stream()
@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir"])
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -133,7 +134,7 @@ def main():
     pr = probs[0]
     solves_per_step = sum(p.n_elem * p.n_dir for p in probs) * n_iter
 
-    g64 = run_gpu(probs, n_iter, "fp64", args.steps, args.warmup)
+    g64 = run_gpu(probs, n_iter, "fp64", args.steps, args.warmup, schedule=args.schedule)
     ms_step = 1e3 * g64["seconds"] / args.steps
     value = solves_per_step * args.steps / g64["seconds"]
 
@@ -146,7 +147,8 @@ def main():
     achieved_tf = F * solves_per_launch / avg_launch_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_sweep_level<2,3,double>", "avg_launch_us": avg_launch_s * 1e6,
+                "kernel": "k_sweep_%s<%d,%d,double>" % ("level" if args.schedule == "level" else "dir",
+                                                         pr.p, pr.p + pr.m), "avg_launch_us": avg_launch_s * 1e6,
                 "launches_per_step": launches / args.steps,
                 "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
                 "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
@@ -157,13 +159,14 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": describe(args.workload, probs, run), "n_elem": pr.n_elem, "p": pr.p,
-                   "n_dir": pr.n_dir, "sweeps_per_step": n_iter, "schedule": "level_sync",
+                   "n_dir": pr.n_dir, "sweeps_per_step": n_iter,
+                   "schedule": {"auto": "dir_resident", "dir": "dir_resident", "level": "level_sync"}[args.schedule],
                    "precision": "fp64"},
         "hbm_gbs_algorithmic": hbm_gbs,
         "roofline": roofline,
     }
     if not args.no_fp32:
-        g32 = run_gpu(probs, n_iter, "fp32", args.steps, args.warmup)
+        g32 = run_gpu(probs, n_iter, "fp32", args.steps, args.warmup, schedule=args.schedule)
         ms32 = 1e3 * g32["seconds"] / args.steps
         err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(g32["phi"], g64["phi"]))
         result["fp32_local"] = {"ms_per_step": ms32, "value": solves_per_step / (ms32 * 1e-3),

@@ -64,7 +64,13 @@ enum {
 };
 
 enum { VEF_FP64 = 0, VEF_FP32_LOCAL = 1 };
-enum { VEF_LEVEL_SYNC = 0, VEF_PERSISTENT = 1 };
+enum {
+  VEF_SCHEDULE_AUTO = 0, /* library choice (currently VEF_DIR_RESIDENT) */
+  VEF_LEVEL_SYNC = 1,    /* one launch per upwind level over all directions */
+  VEF_DIR_RESIDENT = 2   /* one launch per sweep; one work-group per (problem,
+                            direction) walks all upwind levels with work-group
+                            barriers between levels */
+};
 
 /* One transport problem (host pointers, copied by vef_sweep_create and not
  * retained).  Mirrors the problem statement of Sec. 2 (sigma_t, sigma_s),
@@ -73,7 +79,7 @@ enum { VEF_LEVEL_SYNC = 0, VEF_PERSISTENT = 1 };
 typedef struct {
   int p;                  /* DG degree, 1..4 */
   int m;                  /* geometry order, 1..3 */
-  int nq;                 /* Gauss points per direction; 0 = p + m; else p+1..p+4 */
+  int nq;                 /* Gauss points per direction; 0 = p + m; else p+1..p+3 */
   int n_elem;             /* elements, >= 1 */
   int n_cp;               /* control points, >= 4 */
   const double *cp_xy;    /* [n_cp][2] */
@@ -90,9 +96,7 @@ typedef struct {
                     assembly and solves in float with float accumulation,
                     angular flux stored as float; moments, residual and
                     closures in double. */
-  int schedule;  /* VEF_LEVEL_SYNC: one launch per upwind level.
-                    VEF_PERSISTENT: one launch per sweep with device-side
-                    dependency counters. */
+  int schedule;  /* VEF_SCHEDULE_AUTO, VEF_LEVEL_SYNC or VEF_DIR_RESIDENT */
   int block;     /* work-group size for the sweep kernels; 0 = default 256 */
   int timing;    /* nonzero: runs record HIP events around the sweep kernels
                     of every source iteration (read with vef_sweep_timing) */
@@ -145,6 +149,10 @@ typedef struct {
   int n_bf;      /* boundary faces */
   int n_levels;  /* deepest upwind level over directions, plus one */
   int n_groups;  /* classes of directions sharing one upwind graph */
+  int pivoting;  /* 1: local solves use partial pivoting; 0: every face is
+                    straight and sigma_t > 0, so the local matrices have a
+                    positive definite symmetric part and are eliminated in
+                    natural order */
   long long n_solves; /* n_elem * n_dir */
 } vef_info;
 

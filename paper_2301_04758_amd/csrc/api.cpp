@@ -25,9 +25,25 @@ struct TableSet {
   double *dev_d = nullptr;     // double tables for reductions / closures
 };
 
+// Kernel variant of a problem: degree, quadrature, pivoting.
+struct Variant {
+  int p, nq, pivot;
+  bool operator<(const Variant &o) const {
+    return p != o.p ? p < o.p : (nq != o.nq ? nq < o.nq : pivot < o.pivot);
+  }
+};
+
 struct LevelLaunch {
-  int p, nq;
+  Variant v;
   int off, cnt;
+  const void *tab;
+};
+
+struct DirLaunch {  // one direction-resident launch: all (problem, direction) pairs of a variant
+  Variant v;
+  int off, cnt;    // into d_dir_tasks
+  int width;       // widest upwind level among the variant's problems
+  int max_levels;  // deepest level count among them
   const void *tab;
 };
 
@@ -36,9 +52,10 @@ struct LevelLaunch {
 struct vef_sweep {
   std::string err;
   int precision = VEF_FP64;
-  int schedule = VEF_LEVEL_SYNC;
+  int schedule = VEF_DIR_RESIDENT;
   int block = 256;
   int device = 0;
+  size_t lds_max = 65536;  // shared memory per work-group of the device
   std::vector<vefplan::ProblemPlan> plans;
   std::vector<void *> allocs;
   std::map<std::pair<int, int>, TableSet> tables;
@@ -54,6 +71,8 @@ struct vef_sweep {
   bool io_valid = false;
   int2 *d_solves = nullptr;
   std::vector<std::vector<LevelLaunch>> levels;
+  int2 *d_dir_tasks = nullptr;
+  std::vector<DirLaunch> dir_launches;
   std::vector<void *> psi_internal;   // per problem, allocated on first need
   std::vector<double *> resid_scratch;
   std::vector<int> resid_cap;
@@ -141,12 +160,13 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   if (opt) {
     if (opt->precision != VEF_FP64 && opt->precision != VEF_FP32_LOCAL)
       return set_err(h, VEF_ERR_INVALID, "unknown precision");
-    if (opt->schedule != VEF_LEVEL_SYNC)
-      return set_err(h, VEF_ERR_INVALID, "schedule not available (use VEF_LEVEL_SYNC)");
+    if (opt->schedule != VEF_SCHEDULE_AUTO && opt->schedule != VEF_LEVEL_SYNC &&
+        opt->schedule != VEF_DIR_RESIDENT)
+      return set_err(h, VEF_ERR_INVALID, "unknown schedule");
     if (opt->block != 0 && (opt->block < 64 || opt->block > 1024 || opt->block % 64))
       return set_err(h, VEF_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
     h->precision = opt->precision;
-    h->schedule = opt->schedule;
+    h->schedule = opt->schedule == VEF_SCHEDULE_AUTO ? VEF_DIR_RESIDENT : opt->schedule;
     h->timing = opt->timing != 0;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
@@ -160,6 +180,10 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   }
   hipError_t he = hipGetDevice(&h->device);
   if (he != hipSuccess) return hip_fail(h, he, "hipGetDevice");
+  int lds = 0;
+  he = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+  if (he != hipSuccess) return hip_fail(h, he, "hipDeviceGetAttribute");
+  h->lds_max = (size_t)lds;
   const bool fp32 = h->precision == VEF_FP32_LOCAL;
 
   // tables per (p, nq)
@@ -210,7 +234,22 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (he == hipSuccess) he = upload(h, &sig, sg.data(), sg.size());
     if (he == hipSuccess) he = upload(h, &bfe, pl.bf_ef.data(), pl.bf_ef.size());
     if (he == hipSuccess) he = dev_alloc(h, &bnd, (size_t)pl.nbf * pl.nq * 2);
+    int32_t *dg = nullptr, *nlg = nullptr, *lof = nullptr, *ord = nullptr, *def = nullptr, *dnb = nullptr;
+    if (he == hipSuccess) he = upload(h, &def, pl.desc_ef.data(), pl.desc_ef.size());
+    if (he == hipSuccess) he = upload(h, &dnb, pl.desc_nb.data(), pl.desc_nb.size());
+    if (he == hipSuccess) he = upload(h, &dg, pl.dir_group.data(), pl.dir_group.size());
+    if (he == hipSuccess) he = upload(h, &nlg, pl.n_levels_g.data(), pl.n_levels_g.size());
+    if (he == hipSuccess) he = upload(h, &lof, pl.level_off.data(), pl.level_off.size());
+    if (he == hipSuccess) he = upload(h, &ord, pl.order.data(), pl.order.size());
     if (he != hipSuccess) return hip_fail(h, he, "upload problem data");
+    kp.dir_group = dg;
+    kp.n_levels_g = nlg;
+    kp.level_off = lof;
+    kp.order = ord;
+    kp.desc_ef = reinterpret_cast<const int2 *>(def);
+    kp.desc_nb = reinterpret_cast<const int4 *>(dnb);
+    kp.n_levels = pl.n_levels;
+    kp.n_groups = pl.n_groups;
     kp.geo_fd = gfd;
     kp.nbr = nbr;
     kp.nbr_face = nbf;
@@ -237,8 +276,15 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   // level lists: level -> variant (p, nq) -> problem -> class -> element -> direction
   int max_levels = 0;
   for (auto &pl : h->plans) max_levels = std::max(max_levels, pl.n_levels);
-  std::vector<std::pair<int, int>> variants;
-  for (auto &kv : h->tables) variants.push_back(kv.first);
+  std::vector<Variant> variants;
+  {
+    std::map<Variant, int> vs;
+    for (auto &pl : h->plans) vs[Variant{pl.p, pl.nq, pl.nopivot ? 0 : 1}] = 1;
+    for (auto &kv : vs) variants.push_back(kv.first);
+  }
+  auto in_variant = [](const vefplan::ProblemPlan &pl, const Variant &v) {
+    return pl.p == v.p && pl.nq == v.nq && (pl.nopivot ? 0 : 1) == v.pivot;
+  };
   std::vector<std::vector<std::vector<int>>> dirs_of(n_probs);
   for (int k = 0; k < n_probs; ++k) {
     const auto &pl = h->plans[k];
@@ -255,7 +301,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       const int off = (int)solves.size();
       for (int k = 0; k < n_probs; ++k) {
         const auto &pl = h->plans[k];
-        if (pl.p != var.first || pl.nq != var.second || L >= pl.n_levels) continue;
+        if (!in_variant(pl, var) || L >= pl.n_levels) continue;
         for (int g = 0; g < pl.n_groups; ++g) {
           const int *lo = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
           const int32_t *ord = &pl.order[(size_t)g * pl.ne];
@@ -264,12 +310,30 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         }
       }
       const int cnt = (int)solves.size() - off;
-      if (cnt > 0) h->levels[L].push_back({var.first, var.second, off, cnt, h->tables[var].dev_T});
+      if (cnt > 0) h->levels[L].push_back({var, off, cnt, h->tables[std::make_pair(var.p, var.nq)].dev_T});
     }
   if (solves.size() != total) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
   if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
   he = upload(h, &h->d_solves, solves.data(), solves.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload solve lists");
+  // direction-resident tasks: (problem, direction) per variant
+  std::vector<int2> tasks;
+  for (auto &var : variants) {
+    const int off = (int)tasks.size();
+    int width = 1, maxl = 1;
+    for (int k = 0; k < n_probs; ++k) {
+      const auto &pl = h->plans[k];
+      if (!in_variant(pl, var)) continue;
+      for (int d = 0; d < pl.nd; ++d) tasks.push_back(make_int2(k, d));
+      width = std::max(width, pl.max_width);
+      maxl = std::max(maxl, pl.n_levels);
+    }
+    const int cnt = (int)tasks.size() - off;
+    if (cnt > 0)
+      h->dir_launches.push_back({var, off, cnt, width, maxl, h->tables[std::make_pair(var.p, var.nq)].dev_T});
+  }
+  he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
+  if (he != hipSuccess) return hip_fail(h, he, "upload direction tasks");
   h->psi_internal.assign(n_probs, nullptr);
   h->resid_scratch.assign(n_probs, nullptr);
   h->resid_cap.assign(n_probs, 0);
@@ -374,13 +438,44 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
   for (int it = 0; it < a->n_iter; ++it) {
     if (h->timing && (he = hipEventRecord(h->events[2 * it], s)) != hipSuccess)
       return hip_fail(h, he, "record timing event");
-    for (auto &lv : h->levels)
-      for (auto &L : lv) {
-        he = vefk::launch_sweep_level(L.p, L.nq, fp32, h->d_solves + L.off, L.cnt, h->d_probs, h->d_io,
-                                      L.tab, it, stop, status, h->block, s);
+    vefk::SweepLaunch SL{};
+    SL.fp32 = fp32;
+    SL.probs = h->d_probs;
+    SL.io = h->d_io;
+    SL.it = it;
+    SL.stop = stop;
+    SL.status = status;
+    SL.block = h->block;
+    SL.lds_max = h->lds_max;
+    SL.stream = s;
+    if (h->schedule == VEF_LEVEL_SYNC) {
+      for (auto &lv : h->levels)
+        for (auto &L : lv) {
+          SL.p = L.v.p;
+          SL.nq = L.v.nq;
+          SL.pivot = L.v.pivot != 0;
+          SL.list = h->d_solves + L.off;
+          SL.count = L.cnt;
+          SL.tables = L.tab;
+          he = vefk::launch_sweep_level(SL);
+          if (he != hipSuccess) return hip_fail(h, he, "launch sweep");
+          if (h->timing) h->timed_launches++;
+        }
+    } else {
+      for (auto &D : h->dir_launches) {
+        SL.p = D.v.p;
+        SL.nq = D.v.nq;
+        SL.pivot = D.v.pivot != 0;
+        SL.list = h->d_dir_tasks + D.off;
+        SL.count = D.cnt;
+        SL.width = D.width;
+        SL.max_levels = D.max_levels;
+        SL.tables = D.tab;
+        he = vefk::launch_sweep_dir(SL);
         if (he != hipSuccess) return hip_fail(h, he, "launch sweep");
         if (h->timing) h->timed_launches++;
       }
+    }
     if (h->timing && (he = hipEventRecord(h->events[2 * it + 1], s)) != hipSuccess)
       return hip_fail(h, he, "record timing event");
     for (int k = 0; k < np; ++k) {
@@ -449,6 +544,7 @@ int vef_plan_query(const vef_problem_desc *prob, vef_info *info) {
     info->n_bf = pl.nbf;
     info->n_levels = pl.n_levels;
     info->n_groups = pl.n_groups;
+    info->pivoting = pl.nopivot ? 0 : 1;
     info->n_solves = (long long)pl.ne * pl.nd;
   }
   return VEF_OK;
@@ -463,6 +559,7 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->n_bf = pl.nbf;
   info->n_levels = pl.n_levels;
   info->n_groups = pl.n_groups;
+  info->pivoting = pl.nopivot ? 0 : 1;
   info->n_solves = (long long)pl.ne * pl.nd;
   return VEF_OK;
 }

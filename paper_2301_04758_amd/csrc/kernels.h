@@ -22,6 +22,13 @@ struct KProb {
   const int32_t *bf_ef;    // [nbf] 4*e + f
   double *bnd;             // [nbf][nq][2] boundary sums of the last sweep
   const double *tab_d;     // double tables of (p, nq): V, Dx, Dy [Q][n] then F [nq][p+1]
+  const int32_t *dir_group;   // [nd] direction class
+  const int32_t *n_levels_g;  // [n_groups] levels per class
+  const int32_t *level_off;   // [n_groups][n_levels + 1] offsets into order
+  const int32_t *order;       // [n_groups][ne] elements by (level, id)
+  const int2 *desc_ef;        // [n_groups][ne] in order: (element, inflow mask | neighbour faces << 4)
+  const int4 *desc_nb;        // [n_groups][ne] in order: neighbours (or -(boundary face + 1))
+  int n_levels, n_groups;
 };
 
 // Per-problem buffers of one run.
@@ -42,9 +49,28 @@ struct KMomIO {
 };
 
 // Launch helpers (defined in kernels.hip).  All return the launch's hipError_t.
-hipError_t launch_sweep_level(int p, int nq, bool fp32, const int2 *solves, int n_solves,
-                              const KProb *probs, const KIO *io, const void *tables, int it,
-                              const int *stop, int *status, int block, hipStream_t s);
+// One sweep launch (both schedules).
+struct SweepLaunch {
+  int p, nq;
+  bool fp32, pivot;
+  const int2 *list;  // level schedule: (element, direction | problem << 16) pairs of one level;
+                     // direction-resident schedule: (problem, direction) tasks
+  int count;
+  int width;       // direction-resident: widest upwind level
+  int max_levels;  // direction-resident: deepest level count (offsets staged in LDS)
+  const KProb *probs;
+  const KIO *io;
+  const void *tables;
+  int it;
+  const int *stop;
+  int *status;
+  int block;
+  size_t lds_max;
+  hipStream_t stream;
+};
+
+hipError_t launch_sweep_level(const SweepLaunch &L);
+hipError_t launch_sweep_dir(const SweepLaunch &L);
 hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob, int ne_n, int it,
                           const int *stop, hipStream_t s);
 hipError_t launch_boundary(bool fp32, const KProb *probs, const KIO *io, int prob, int nbf, int nq,

@@ -221,8 +221,8 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   if (d.p < 1 || d.p > kMaxP) return fail(err, VEF_ERR_INVALID, "p=%lld out of range 1..4", d.p);
   if (d.m < 1 || d.m > kMaxM) return fail(err, VEF_ERR_INVALID, "m=%lld out of range 1..3", d.m);
   const int nq = d.nq > 0 ? d.nq : d.p + d.m;
-  if (nq < d.p + 1 || nq > d.p + 4)
-    return fail(err, VEF_ERR_INVALID, "nq=%lld outside p+1..p+4 (p=%lld)", nq, d.p);
+  if (nq < d.p + 1 || nq > d.p + 3)
+    return fail(err, VEF_ERR_INVALID, "nq=%lld outside p+1..p+3 (p=%lld)", nq, d.p);
   if (d.n_elem < 1 || d.n_cp < 4) return fail(err, VEF_ERR_INVALID, "n_elem=%lld n_cp=%lld", d.n_elem, d.n_cp);
   if (d.n_elem > (1 << 26)) return fail(err, VEF_ERR_INVALID, "n_elem=%lld too large", d.n_elem);
   if (d.n_dir < 1 || d.n_dir > kMaxDirs) return fail(err, VEF_ERR_INVALID, "n_dir=%lld out of range 1..1024", d.n_dir);
@@ -453,6 +453,55 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   for (int g = 0; g < o.n_groups; ++g)
     for (int l = 0; l <= o.n_levels; ++l)
       o.level_off[(size_t)g * (o.n_levels + 1) + l] = offs[g][std::min(l, (int)offs[g].size() - 1)];
+
+  // packed element descriptors in (level, id) order per class
+  o.desc_ef.assign((size_t)o.n_groups * ne * 2, 0);
+  o.desc_nb.assign((size_t)o.n_groups * ne * 4, 0);
+  o.max_width = 1;
+  for (int g = 0; g < o.n_groups; ++g) {
+    const uint8_t *mk = &o.mask[(size_t)o.group_rep[g] * ne];
+    const int32_t *ord = &o.order[(size_t)g * ne];
+    for (int t = 0; t < ne; ++t) {
+      const int e = ord[t];
+      int flags = mk[e];
+      for (int f = 0; f < 4; ++f) {
+        flags |= (std::max<int>(o.nbr_face[4 * e + f], 0) & 3) << (4 + 2 * f);
+        o.desc_nb[((size_t)g * ne + t) * 4 + f] = o.nbr[4 * e + f];
+      }
+      o.desc_ef[((size_t)g * ne + t) * 2] = e;
+      o.desc_ef[((size_t)g * ne + t) * 2 + 1] = flags;
+    }
+    for (int L = 0; L < o.n_levels; ++L) {
+      const int *lo = &o.level_off[(size_t)g * (o.n_levels + 1)];
+      o.max_width = std::max(o.max_width, lo[L + 1] - lo[L]);
+    }
+  }
+
+  // straight faces: every control point of a face on the chord of its corners
+  o.straight = true;
+  for (int e = 0; e < ne && o.straight && m > 1; ++e)
+    for (int f = 0; f < 4 && o.straight; ++f) {
+      int la, lb;
+      corner_pair(m, f, la, lb);
+      const double *xa = d.cp_xy + 2 * (size_t)d.elem_cp[(size_t)e * ncp_e + la];
+      const double *xb = d.cp_xy + 2 * (size_t)d.elem_cp[(size_t)e * ncp_e + lb];
+      const double cx = xb[0] - xa[0], cy = xb[1] - xa[1];
+      for (int k = 1; k < m; ++k) {
+        int li;
+        switch (f) {
+          case 0: li = k; break;
+          case 1: li = m + (m + 1) * k; break;
+          case 2: li = k + (m + 1) * m; break;
+          default: li = (m + 1) * k; break;
+        }
+        const double *xi = d.cp_xy + 2 * (size_t)d.elem_cp[(size_t)e * ncp_e + li];
+        const double cr = (xi[0] - xa[0]) * cy - (xi[1] - xa[1]) * cx;
+        if (std::fabs(cr) > 1e-13 * (cx * cx + cy * cy)) o.straight = false;
+      }
+    }
+  double smin = d.sigma_t[0];
+  for (int e = 1; e < ne; ++e) smin = std::min(smin, d.sigma_t[e]);
+  o.nopivot = o.straight && smin > 0.0;
 
   o.omega.assign(d.omega, d.omega + 2 * nd);
   o.weight.assign(d.weight, d.weight + nd);

@@ -45,6 +45,11 @@ struct ProblemPlan {
   int n_groups = 0;
   int n_levels = 0;                 // max over classes
   std::vector<int32_t> n_levels_g;  // [n_groups]
+  std::vector<int32_t> desc_ef;     // [n_groups][ne][2] in order: element, inflow mask | nbr faces << 4
+  std::vector<int32_t> desc_nb;     // [n_groups][ne][4] in order: neighbours
+  int max_width = 1;                // widest level over classes
+  bool straight = true;             // every face of the mesh is a straight segment
+  bool nopivot = false;             // straight faces and sigma_t > 0 everywhere
   std::vector<double> omega, weight, sigma_t, sigma_s;
   Tables tab;
 };

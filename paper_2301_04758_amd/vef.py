@@ -27,8 +27,10 @@ VEF_ERR_OOM = -5
 VEF_ERR_TIMEOUT = -6
 VEF_FP64 = 0
 VEF_FP32_LOCAL = 1
-VEF_LEVEL_SYNC = 0
-VEF_PERSISTENT = 1
+VEF_SCHEDULE_AUTO = 0
+VEF_LEVEL_SYNC = 1
+VEF_DIR_RESIDENT = 2
+SCHEDULES = {"auto": VEF_SCHEDULE_AUTO, "level": VEF_LEVEL_SYNC, "dir": VEF_DIR_RESIDENT}
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
@@ -66,7 +68,7 @@ class vef_moment_io(C.Structure):
 
 class vef_info(C.Structure):
     _fields_ = [("n", C.c_int), ("nq", C.c_int), ("Q", C.c_int), ("n_bf", C.c_int), ("n_levels", C.c_int),
-                ("n_groups", C.c_int), ("n_solves", C.c_longlong)]
+                ("n_groups", C.c_int), ("pivoting", C.c_int), ("n_solves", C.c_longlong)]
 
 
 def _load():
@@ -147,7 +149,7 @@ def vef_plan_query(problem) -> dict:
     return {f: getattr(info, f) for f, _ in vef_info._fields_}
 
 
-def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_LEVEL_SYNC,
+def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
                      block: int = 0, timing: bool = False) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
@@ -222,15 +224,15 @@ def vef_sweep_check(h: int):
 class Sweep:
     """Owns one handle; allocates device buffers with torch for convenience."""
 
-    def __init__(self, problems, precision="fp64", block=0, device=None, timing=False):
+    def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto"):
         import torch
         self.torch = torch
         self.problems = list(problems)
         self.fp32 = precision == "fp32"
         self.device = torch.device("cuda" if device is None else device)
         with torch.cuda.device(self.device):
-            self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64, VEF_LEVEL_SYNC, block,
-                                      timing)
+            self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64,
+                                      SCHEDULES[schedule], block, timing)
         self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
 
     def close(self):

@@ -38,10 +38,11 @@ def torch():
     return T
 
 
-def gpu_run(torch, problems, precision, n_iter=1, phi_in=None, tol=0.0, store_psi=True, closures=False):
+def gpu_run(torch, problems, precision, n_iter=1, phi_in=None, tol=0.0, store_psi=True, closures=False,
+            schedule="auto"):
     from paper_2301_04758_amd import vef
-    print("gpu_run", [p.name for p in problems][:3], precision, "n_iter", n_iter, flush=True)
-    sw = vef.Sweep(problems, precision=precision)
+    print("gpu_run", [p.name for p in problems][:3], precision, schedule, "n_iter", n_iter, flush=True)
+    sw = vef.Sweep(problems, precision=precision, schedule=schedule)
     io = sw.buffers(n_iter=n_iter, store_psi=store_psi, phi_in=phi_in)
     iters = torch.zeros(1, dtype=torch.int32, device="cuda")
     sw.run(io, n_iter=n_iter, tol=tol, iters_done=iters)
@@ -78,10 +79,14 @@ def _small(nx, ny, p, m, N, st=1.0, ss=0.0, warp=0.0, q=1.0, seed=0):
     return pr
 
 
+SCHEDULES = ["level", "dir"]
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_c1_single_sweep(torch, precision):
+def test_c1_single_sweep(torch, precision, schedule):
     (pr,), _ = P.make_config("c1")
-    (g,), _ = gpu_run(torch, [pr], precision, closures=True)
+    (g,), _ = gpu_run(torch, [pr], precision, closures=True, schedule=schedule)
     ref = O.sweep(pr)
     tol = TOL[precision]
     assert rel_inf(g["psi_out"], ref["psi"]) <= tol
@@ -97,11 +102,12 @@ def test_c1_single_sweep(torch, precision):
     assert abs(g["resid"][0] - np.abs(ref["mom"][0]).max()) <= tol * np.abs(ref["mom"][0]).max()
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_c2_scaled_source_iteration(torch, precision):
+def test_c2_scaled_source_iteration(torch, precision, schedule):
     (pr,), _ = P.make_config("c2", scale=16)
     n_iter = 12
-    (g,), out = gpu_run(torch, [pr], precision, n_iter=n_iter)
+    (g,), out = gpu_run(torch, [pr], precision, n_iter=n_iter, schedule=schedule)
     ref = O.source_iteration(pr, n_iter)
     tol = TOL[precision]
     assert out["iters"] == n_iter
@@ -110,14 +116,15 @@ def test_c2_scaled_source_iteration(torch, precision):
     assert np.abs(g["resid"] - ref["resid"]).max() <= tol * ref["resid"].max()
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [(12, 12, 3, 2, 12), (7, 5, 2, 2, 8), (9, 4, 1, 3, 6), (6, 6, 4, 2, 4)])
-def test_curved_meshes(torch, precision, shape):
+def test_curved_meshes(torch, precision, shape, schedule):
     nx, ny, p, m, N = shape
     pr = _small(nx, ny, p, m, N, st=lambda r, n: r.uniform(1, 10, n), warp=0.1 if m == 2 else 0.05)
     pr.sigma_s = 0.5 * pr.sigma_t
     phi = np.random.default_rng(1).uniform(0, 3, (pr.n_elem, (p + 1) ** 2))
-    (g,), _ = gpu_run(torch, [pr], precision, phi_in=phi, closures=True)
+    (g,), _ = gpu_run(torch, [pr], precision, phi_in=phi, closures=True, schedule=schedule)
     ref = O.sweep(pr, phi_in=phi)
     tol = TOL[precision]
     assert rel_inf(g["psi_out"], ref["psi"]) <= tol
@@ -147,12 +154,13 @@ def test_mms_inputs(torch, precision, p, m, warp):
         assert rel_inf(g["cl_" + key], cl[key], sc[key]) <= 10 * tol, key
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_thick_p4_scaled(torch, precision):
+def test_thick_p4_scaled(torch, precision, schedule):
     """C5-like thick diffusive cells (sigma_t = 1000, c = 0.9999), p = 4, S16."""
     (pr,), _ = P.make_config("c5", scale=10)
     n_iter = 3
-    (g,), _ = gpu_run(torch, [pr], precision, n_iter=n_iter)
+    (g,), _ = gpu_run(torch, [pr], precision, n_iter=n_iter, schedule=schedule)
     ref = O.source_iteration(pr, n_iter)
     tol = TOL[precision]
     assert rel_inf(g["mom"][0], ref["mom"][0]) <= tol
@@ -218,3 +226,16 @@ def test_invalid_problem_rejected_before_launch(torch):
     pr.weight = pr.weight * 2
     with pytest.raises(vef.VefError):
         vef.Sweep([pr])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg,scale", [("c2", 24), ("c3", 10), ("c5", 12)])
+def test_schedules_bitwise_equal(torch, precision, cfg, scale):
+    """Both schedules run the same per-solve arithmetic in a different order:
+    their outputs must agree bit for bit (any race or stale read would show)."""
+    (pr,), _ = P.make_config(cfg, scale=scale)
+    (a,), _ = gpu_run(torch, [pr], precision, n_iter=2, schedule="level")
+    (b,), _ = gpu_run(torch, [pr], precision, n_iter=2, schedule="dir")
+    assert np.array_equal(a["psi_out"], b["psi_out"])
+    assert np.array_equal(a["mom"], b["mom"])
+    assert np.array_equal(a["resid"], b["resid"])

@@ -55,6 +55,24 @@ def test_plan_matches_oracle_levels_and_faces(cfg, scale):
     assert info["n_solves"] == pr.n_elem * pr.n_dir
     if pr.m == 1:
         assert info["n_groups"] == 4  # straight Cartesian mesh: one upwind graph per quadrant
+        assert info["pivoting"] == 0  # straight faces, sigma_t > 0: natural-order elimination
+    else:
+        assert info["pivoting"] == 1  # curved faces keep partial pivoting
+
+
+def test_pivoting_choice():
+    vef = _vef()
+    import copy
+    (pr,), _ = P.make_config("c1")
+    assert vef.vef_plan_query(pr)["pivoting"] == 0
+    q = copy.deepcopy(pr)
+    q.sigma_t = q.sigma_t.copy()
+    q.sigma_t[5] = 0.0  # a purely streaming element: symmetric part only semidefinite
+    assert vef.vef_plan_query(q)["pivoting"] == 1
+    # straight but m = 2 (midpoint control points on the chords): still natural order
+    cp, ec = P.quad_mesh(4, 4, 2)
+    q = P.Problem("m2", 2, 2, cp, ec, pr.omega, pr.weight, np.ones(16), np.zeros(16))
+    assert vef.vef_plan_query(q)["pivoting"] == 0
 
 
 def _bad(pr, code):
