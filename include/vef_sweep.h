@@ -153,6 +153,9 @@ typedef struct {
                     straight and sigma_t > 0, so the local matrices have a
                     positive definite symmetric part and are eliminated in
                     natural order */
+  int affine;    /* 1: every element map is affine (constant J and adj(F)),
+                    so the local matrices are assembled from reference
+                    matrices scaled by the element's J and adj(F) */
   long long n_solves; /* n_elem * n_dir */
 } vef_info;
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvefsweep.so")
-SOURCES = ["plan.cpp", "kernels.hip", "api.cpp"]
+SOURCES = ["plan.cpp", "kernels.hip", "sweep_p1.hip", "sweep_p2.hip", "sweep_p3.hip", "sweep_p4.hip", "api.cpp"]
 ARCH = os.environ.get("VEF_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU forms.
@@ -24,21 +24,26 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False, out: str = LIB) -> str:
-    objs = []
+def _compile(src, verbose):
+    obj = os.path.join(HERE, "_build", os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-c",
+           "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-command-line-argument"]
+    cmd += DEVICE_FLAGS
+    if src.endswith(".cpp"):
+        cmd += ["-x", "hip"]
+    cmd += [os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
+def build(verbose: bool = False, out: str = LIB, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(HERE, "_build", os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-c",
-               "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-command-line-argument"]
-        cmd += DEVICE_FLAGS
-        if src.endswith(".cpp"):
-            cmd += ["-x", "hip"]
-        cmd += [os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+    jobs = jobs or min(len(SOURCES), max(1, min(os.cpu_count() or 1, 8)))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = out + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -21,17 +21,24 @@ namespace {
 thread_local std::string g_create_error;
 
 struct TableSet {
-  void *dev_T = nullptr;       // float or double tables for the sweep kernel
+  void *dev_T = nullptr;       // float or double tables for the general sweep kernels
+  void *dev_A = nullptr;       // float or double tables for the affine sweep kernels
   double *dev_d = nullptr;     // double tables for reductions / closures
 };
 
-// Kernel variant of a problem: degree, quadrature, pivoting.
+// Kernel variant of a problem: degree, quadrature, assembly/solve mode
+// (0: general elements with pivoting, 1: general pivot-free, 2: affine pivot-free).
 struct Variant {
-  int p, nq, pivot;
+  int p, nq, mode;
   bool operator<(const Variant &o) const {
-    return p != o.p ? p < o.p : (nq != o.nq ? nq < o.nq : pivot < o.pivot);
+    return p != o.p ? p < o.p : (nq != o.nq ? nq < o.nq : mode < o.mode);
   }
 };
+
+int mode_of(const vefplan::ProblemPlan &pl) {
+  if (!pl.nopivot) return 0;
+  return pl.affine ? 2 : 1;
+}
 
 struct LevelLaunch {
   Variant v;
@@ -193,6 +200,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     TableSet ts;
     std::vector<double> blob = table_blob(pl.tab);
     he = fp32 ? upload_as<float>(h, &ts.dev_T, blob) : upload_as<double>(h, &ts.dev_T, blob);
+    if (he == hipSuccess)
+      he = fp32 ? upload_as<float>(h, &ts.dev_A, pl.tab.affine) : upload_as<double>(h, &ts.dev_A, pl.tab.affine);
     if (he != hipSuccess) return hip_fail(h, he, "upload tables");
     he = upload(h, &ts.dev_d, blob.data(), blob.size());
     if (he != hipSuccess) return hip_fail(h, he, "upload tables");
@@ -216,6 +225,10 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (he == hipSuccess) he = fp32 ? upload_as<float>(h, &gf, pl.geo_f) : upload_as<double>(h, &gf, pl.geo_f);
     kp.geo_v = gv;
     kp.geo_f = gf;
+    void *ga = nullptr;
+    if (he == hipSuccess && pl.affine)
+      he = fp32 ? upload_as<float>(h, &ga, pl.geo_a) : upload_as<double>(h, &ga, pl.geo_a);
+    kp.geo_a = ga;
     double *gfd = nullptr, *om = nullptr, *wt = nullptr, *sig = nullptr, *bnd = nullptr;
     int32_t *nbr = nullptr, *bfe = nullptr;
     int8_t *nbf = nullptr;
@@ -279,11 +292,11 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   std::vector<Variant> variants;
   {
     std::map<Variant, int> vs;
-    for (auto &pl : h->plans) vs[Variant{pl.p, pl.nq, pl.nopivot ? 0 : 1}] = 1;
+    for (auto &pl : h->plans) vs[Variant{pl.p, pl.nq, mode_of(pl)}] = 1;
     for (auto &kv : vs) variants.push_back(kv.first);
   }
   auto in_variant = [](const vefplan::ProblemPlan &pl, const Variant &v) {
-    return pl.p == v.p && pl.nq == v.nq && (pl.nopivot ? 0 : 1) == v.pivot;
+    return pl.p == v.p && pl.nq == v.nq && mode_of(pl) == v.mode;
   };
   std::vector<std::vector<std::vector<int>>> dirs_of(n_probs);
   for (int k = 0; k < n_probs; ++k) {
@@ -310,7 +323,10 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         }
       }
       const int cnt = (int)solves.size() - off;
-      if (cnt > 0) h->levels[L].push_back({var, off, cnt, h->tables[std::make_pair(var.p, var.nq)].dev_T});
+      if (cnt > 0) {
+        const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
+        h->levels[L].push_back({var, off, cnt, var.mode == 2 ? ts.dev_A : ts.dev_T});
+      }
     }
   if (solves.size() != total) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
   if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
@@ -329,8 +345,10 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       maxl = std::max(maxl, pl.n_levels);
     }
     const int cnt = (int)tasks.size() - off;
-    if (cnt > 0)
-      h->dir_launches.push_back({var, off, cnt, width, maxl, h->tables[std::make_pair(var.p, var.nq)].dev_T});
+    if (cnt > 0) {
+      const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
+      h->dir_launches.push_back({var, off, cnt, width, maxl, var.mode == 2 ? ts.dev_A : ts.dev_T});
+    }
   }
   he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload direction tasks");
@@ -453,7 +471,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
         for (auto &L : lv) {
           SL.p = L.v.p;
           SL.nq = L.v.nq;
-          SL.pivot = L.v.pivot != 0;
+          SL.mode = L.v.mode;
           SL.list = h->d_solves + L.off;
           SL.count = L.cnt;
           SL.tables = L.tab;
@@ -465,7 +483,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
       for (auto &D : h->dir_launches) {
         SL.p = D.v.p;
         SL.nq = D.v.nq;
-        SL.pivot = D.v.pivot != 0;
+        SL.mode = D.v.mode;
         SL.list = h->d_dir_tasks + D.off;
         SL.count = D.cnt;
         SL.width = D.width;
@@ -545,6 +563,7 @@ int vef_plan_query(const vef_problem_desc *prob, vef_info *info) {
     info->n_levels = pl.n_levels;
     info->n_groups = pl.n_groups;
     info->pivoting = pl.nopivot ? 0 : 1;
+    info->affine = pl.affine ? 1 : 0;
     info->n_solves = (long long)pl.ne * pl.nd;
   }
   return VEF_OK;
@@ -560,6 +579,7 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->n_levels = pl.n_levels;
   info->n_groups = pl.n_groups;
   info->pivoting = pl.nopivot ? 0 : 1;
+  info->affine = pl.affine ? 1 : 0;
   info->n_solves = (long long)pl.ne * pl.nd;
   return VEF_OK;
 }

@@ -12,6 +12,7 @@ struct KProb {
   int ne, nd, nbf, n, Q, nq, p, pad;
   const void *geo_v;       // T [ne][Q][5]: w J, w adj(F) (row major)
   const void *geo_f;       // T [ne][4][nq][2]: w_s n ds
+  const void *geo_a;       // T [ne][16]: J, adj(F) (row major), face chords N_0..N_3 (affine meshes)
   const double *geo_fd;    // double copy of geo_f
   const int32_t *nbr;      // [ne][4] neighbour or -(bf+1)
   const int8_t *nbr_face;  // [ne][4]
@@ -52,7 +53,8 @@ struct KMomIO {
 // One sweep launch (both schedules).
 struct SweepLaunch {
   int p, nq;
-  bool fp32, pivot;
+  bool fp32;
+  int mode;          // 0: general elements, pivoting; 1: general, pivot-free; 2: affine, pivot-free
   const int2 *list;  // level schedule: (element, direction | problem << 16) pairs of one level;
                      // direction-resident schedule: (problem, direction) tasks
   int count;

@@ -214,6 +214,26 @@ int build_tables(int p, int nq, Tables &t) {
         }
     }
   t.F = v1;
+  // affine-element tables (quadrature sums with the same rule)
+  t.affine.assign(3 * n * n + P1 * P1 + Q * n + nq * P1, 0.0);
+  double *Mt = t.affine.data(), *Gx = Mt + n * n, *Gy = Gx + n * n, *M1 = Gy + n * n;
+  double *WV = M1 + P1 * P1, *WL = WV + Q * n;
+  for (int q = 0; q < Q; ++q) {
+    const double w = t.gw[q % nq] * t.gw[q / nq];
+    for (int i = 0; i < n; ++i) {
+      WV[q * n + i] = w * t.V[q * n + i];
+      for (int j = 0; j < n; ++j) {
+        Mt[j * n + i] += w * t.V[q * n + i] * t.V[q * n + j];
+        Gx[j * n + i] += w * t.Dx[q * n + i] * t.V[q * n + j];
+        Gy[j * n + i] += w * t.Dy[q * n + i] * t.V[q * n + j];
+      }
+    }
+  }
+  for (int q = 0; q < nq; ++q)
+    for (int a = 0; a < P1; ++a) {
+      WL[q * P1 + a] = t.gw[q] * v1[q * P1 + a];
+      for (int c = 0; c < P1; ++c) M1[a * P1 + c] += t.gw[q] * v1[q * P1 + a] * v1[q * P1 + c];
+    }
   return VEF_OK;
 }
 
@@ -502,6 +522,36 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   double smin = d.sigma_t[0];
   for (int e = 1; e < ne; ++e) smin = std::min(smin, d.sigma_t[e]);
   o.nopivot = o.straight && smin > 0.0;
+
+  // affine maps: J and adj(F) equal at every volume point (to rounding), and
+  // n ds along each face equal to the face chord
+  o.affine = o.straight;
+  for (int e = 0; e < ne && o.affine; ++e) {
+    const double *g0 = &o.geo_v[(size_t)e * o.Q * 5];
+    const double w0 = T.gw[0] * T.gw[0];
+    double scale = 0.0;
+    for (int k = 1; k < 5; ++k) scale = std::max(scale, std::fabs(g0[k] / w0));
+    for (int q = 1; q < o.Q && o.affine; ++q) {
+      const double *gq = &o.geo_v[((size_t)e * o.Q + q) * 5];
+      const double wq = T.gw[q % nq] * T.gw[q / nq];
+      if (std::fabs(gq[0] / wq - g0[0] / w0) > 1e-13 * std::fabs(g0[0] / w0)) o.affine = false;
+      for (int k = 1; k < 5; ++k)
+        if (std::fabs(gq[k] / wq - g0[k] / w0) > 1e-13 * scale) o.affine = false;
+    }
+  }
+  if (o.affine) {
+    o.geo_a.assign((size_t)ne * 16, 0.0);
+    const double w0 = T.gw[0] * T.gw[0];
+    for (int e = 0; e < ne; ++e) {
+      const double *g0 = &o.geo_v[(size_t)e * o.Q * 5];
+      double *ga = &o.geo_a[(size_t)e * 16];
+      for (int k = 0; k < 5; ++k) ga[k] = g0[k] / w0;
+      for (int f = 0; f < 4; ++f) {
+        ga[5 + 2 * f] = chord[8 * e + 2 * f];
+        ga[6 + 2 * f] = chord[8 * e + 2 * f + 1];
+      }
+    }
+  }
 
   o.omega.assign(d.omega, d.omega + 2 * nd);
   o.weight.assign(d.weight, d.weight + nd);

@@ -25,6 +25,9 @@ struct Tables {
   std::vector<double> Dx;   // [Q][n] d/dxi
   std::vector<double> Dy;   // [Q][n] d/deta
   std::vector<double> F;    // [nq][p+1] 1D basis at face points
+  // affine-element tables: Mhat^T, Ghat_xi^T, Ghat_eta^T [n][n] (entry [j][i]),
+  // face mass [p+1][p+1], w V [Q][n], w L [nq][p+1]
+  std::vector<double> affine;
 };
 
 struct ProblemPlan {
@@ -50,6 +53,8 @@ struct ProblemPlan {
   int max_width = 1;                // widest level over classes
   bool straight = true;             // every face of the mesh is a straight segment
   bool nopivot = false;             // straight faces and sigma_t > 0 everywhere
+  bool affine = false;              // every element map is affine (constant J and adj(F))
+  std::vector<double> geo_a;        // [ne][16] J, adj(F), chords (when affine)
   std::vector<double> omega, weight, sigma_t, sigma_s;
   Tables tab;
 };

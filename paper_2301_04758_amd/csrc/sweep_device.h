@@ -1,0 +1,769 @@
+// Device code of the DG S_N sweep kernels (templates shared by the per-degree
+// translation units).
+//
+// Work mapping: a "slot" of SLOT lanes (the power of two >= n = (p+1)^2,
+// aligned inside one 64-wide wavefront) owns one element-direction solve;
+// lane r owns row r (test function r) of the local system.  One solve:
+//   1. inputs: the lanes of the slot load the element's data, a few values
+//      per lane, all loads independent (the direction-resident schedule
+//      issues them one solve ahead);
+//   2. staging: those values go to the slot's private LDS area (wave-local,
+//      no work-group barrier);
+//   3. assembly of row r, by one of two exact evaluations of the same
+//      quadrature:
+//      - general elements: the sum over volume points of the geometry
+//        factors (w J and w adj(F)) times the basis tables, and over face
+//        points of w n ds;
+//      - affine elements (constant J and adj(F), straight faces): J and
+//        adj(F) leave the quadrature, so the row is sigma_t J Mhat -
+//        (adj(F) Omega)_xi Ghat_xi - (adj(F) Omega)_eta Ghat_eta with
+//        reference matrices shared by all elements, and each face term is
+//        (Omega . N_F) times the 1D face mass matrix;
+//      inflow traces come from the upwind element's face nodes
+//      (Gauss-Lobatto nodes include the element boundary, so a face trace is
+//      the p+1 face-node values, read in reversed order because the two
+//      sides run the shared face in opposite senses);
+//   4. solve: Gauss-Jordan elimination with normalised pivot rows across the
+//      slot's lanes, so that each lane ends with one unknown.  With partial
+//      pivoting the pivot lane is one unsigned max of packed (magnitude,
+//      lane) keys by DPP lane moves and the pivot row goes through the slot's
+//      LDS area; without pivoting (used only when every face of the mesh is
+//      straight and sigma_t > 0, so that the local matrix has a positive
+//      definite symmetric part) lane k broadcasts row k by a DPP row
+//      broadcast or an LDS swizzle, with no LDS round trip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace vefk {
+
+namespace {
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
+
+// Assembly/solve modes of a kernel variant.
+enum : int { MODE_GENERAL_PIVOT = 0, MODE_GENERAL_NOPIVOT = 1, MODE_AFFINE_NOPIVOT = 2 };
+
+template <int P, int NQ>
+struct Shape {
+  static constexpr int P1 = P + 1;
+  static constexpr int N = P1 * P1;
+  static constexpr int Q = NQ * NQ;
+  static constexpr int SLOT = N <= 4 ? 4 : (N <= 8 ? 8 : (N <= 16 ? 16 : 32));
+  static constexpr int SPW = 64 / SLOT;
+  // general path: per-lane shares of the element inputs
+  static constexpr int GV = (5 * Q + SLOT - 1) / SLOT;
+  static constexpr int GF = (8 * NQ + SLOT - 1) / SLOT;
+  static constexpr int QD = (Q + SLOT - 1) / SLOT;
+  // general path LDS: tables V, Dx, Dy [Q][n] and F [nq][p+1], then one area per slot
+  static constexpr int TAB = 3 * Q * N + NQ * P1;
+  static constexpr int OFF_GEO = 0;                 // [Q][5]
+  static constexpr int OFF_GF = OFF_GEO + 5 * Q;    // [4][NQ][2]
+  static constexpr int OFF_SRC = OFF_GF + 8 * NQ;   // [Q] source at volume points
+  static constexpr int OFF_S = OFF_SRC + Q;         // [N] nodal source coefficients
+  static constexpr int OFF_PIV = ((OFF_S + N + 1) / 2) * 2;  // [N + 1] pivot row + rhs
+  static constexpr int SLOT_AREA = ((OFF_PIV + N + 1 + 1) / 2) * 2;
+  static constexpr int QU = P <= 2 ? Q : 1;  // volume loop fully unrolled for small elements
+  // affine path: 16 values per element (J, adj(F), four face chords)
+  static constexpr int GA = (16 + SLOT - 1) / SLOT;
+  // tables Mhat^T, Ghat_xi^T, Ghat_eta^T [n][n], face mass [p+1][p+1],
+  // w V [Q][n] (direction-dependent source), w L [nq][p+1] (boundary data)
+  static constexpr int A_MT = 0, A_GX = N * N, A_GY = 2 * N * N, A_M1 = 3 * N * N;
+  static constexpr int A_WV = A_M1 + P1 * P1, A_WL = A_WV + Q * N;
+  static constexpr int TAB_A = A_WL + NQ * P1;
+  static constexpr int AOFF_G = 0, AOFF_S = 16, AOFF_QD = 16 + N;
+  static constexpr int AOFF_PIV = ((AOFF_QD + Q + 1) / 2) * 2;
+  static constexpr int SLOT_AREA_A = ((AOFF_PIV + N + 1 + 1) / 2) * 2;
+};
+
+template <int P, int NQ, int MODE>
+struct Lds {
+  using S = Shape<P, NQ>;
+  static constexpr int TAB = MODE == MODE_AFFINE_NOPIVOT ? S::TAB_A : S::TAB;
+  static constexpr int AREA = MODE == MODE_AFFINE_NOPIVOT ? S::SLOT_AREA_A : S::SLOT_AREA;
+};
+
+template <typename T>
+__host__ __device__ constexpr size_t lds_bytes(int tab, int slot_area, int slots, int extra_ints) {
+  return sizeof(T) * ((size_t)tab + (size_t)slot_area * slots) + sizeof(int) * (size_t)extra_ints;
+}
+
+// node index of position c (counter-clockwise) along face f
+template <int P>
+__device__ __forceinline__ int face_node(int f, int c) {
+  constexpr int P1 = P + 1;
+  switch (f) {
+    case 0: return c;
+    case 1: return P + P1 * c;
+    case 2: return (P - c) + P1 * P;
+    default: return P1 * (P - c);
+  }
+}
+
+// DPP lane moves (whole-wave, all lanes active)
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(dpp_mov<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = dpp_mov<CTRL>(__double2loint(v));
+  const int hi = dpp_mov<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// LDS-crossbar swizzle with an immediate bit-mask pattern (32-lane groups)
+template <int PAT>
+__device__ __forceinline__ int swz(int v) {
+  return __builtin_amdgcn_ds_swizzle(v, PAT);
+}
+template <int PAT>
+__device__ __forceinline__ float swz(float v) {
+  return __int_as_float(swz<PAT>(__float_as_int(v)));
+}
+template <int PAT>
+__device__ __forceinline__ double swz(double v) {
+  const int lo = swz<PAT>(__double2loint(v));
+  const int hi = swz<PAT>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Value of lane K of the caller's slot.  16-lane slots are DPP rows
+// (row_newbcast:K); other sizes use the swizzle "and/or" mode, which keeps
+// the slot bits of the lane id and forces the low bits to K.
+template <int SLOT, int K, typename T>
+__device__ __forceinline__ T slot_bcast(T v) {
+  if constexpr (SLOT == 16) {
+    return dpp_mov<0x150 + K>(v);
+  } else {
+    constexpr int AND = (~(SLOT - 1)) & 0x1F;
+    return swz<AND | (K << 5)>(v);
+  }
+}
+
+// Pivot lane of a slot: each lane offers a key made of its |a_k| rounded
+// down to float with the low five mantissa bits replaced by (31 - lane in
+// slot); lanes that may not pivot offer 0.  For non-negative floats the bit
+// pattern orders like an unsigned integer, so one unsigned max over the slot
+// picks the largest magnitude and, among equal keys, the lowest lane.
+// quad_perm [1,0,3,2] and [2,3,0,1] pair lanes inside quads, row_half_mirror
+// pairs the two quads of an 8-lane group, row_mirror the two halves of a
+// 16-lane row; 32-lane slots finish with one cross-row exchange.
+template <int SLOT>
+__device__ __forceinline__ int slot_pivot(float mag, bool cand, int r) {
+  unsigned key = cand ? ((__float_as_uint(mag) & ~31u) | (31u - (unsigned)r)) : 0u;
+  key = max(key, (unsigned)dpp_mov<0xB1>((int)key));
+  key = max(key, (unsigned)dpp_mov<0x4E>((int)key));
+  if constexpr (SLOT >= 8) key = max(key, (unsigned)dpp_mov<0x141>((int)key));
+  if constexpr (SLOT >= 16) key = max(key, (unsigned)dpp_mov<0x140>((int)key));
+  if constexpr (SLOT >= 32) key = max(key, (unsigned)__shfl_xor((int)key, 16, 32));
+  return 31 - (int)(key & 31u);
+}
+
+// 1/x from the hardware reciprocal refined by Newton steps (two in double,
+// one in float: each step squares the relative error).
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float x) {
+  float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Step K of the pivot-free Gauss-Jordan elimination: lane K's row is the
+// pivot row; every lane subtracts l times it, where the pivot lane's own l
+// turns its row into the row divided by its pivot.
+template <int SLOT, int N, int K, typename T>
+__device__ __forceinline__ void gj_nopivot(T (&A)[N], T &rhs, int r) {
+  if constexpr (K < N) {
+    const T pk = slot_bcast<SLOT, K>(A[K]);
+    const T inv = recip(pk);
+    const T l = (r == K) ? (A[K] - T(1)) * inv : A[K] * inv;
+#pragma unroll
+    for (int j = K + 1; j < N; ++j) A[j] -= l * slot_bcast<SLOT, K>(A[j]);
+    rhs -= l * slot_bcast<SLOT, K>(rhs);
+    gj_nopivot<SLOT, N, K + 1, T>(A, rhs, r);
+  }
+}
+
+// Step K with partial pivoting; the pivot row travels through LDS.
+template <int SLOT, int N, int K, typename T>
+__device__ __forceinline__ void gj_pivot(T (&A)[N], T &rhs, int r, bool &active, int &my_k, T *pv) {
+  if constexpr (K < N) {
+    const int pl = slot_pivot<SLOT>(static_cast<float>(fabs(A[K])), active, r);
+    if (r == pl) {
+#pragma unroll
+      for (int j = K; j < N; ++j) pv[j] = A[j];
+      pv[N] = rhs;
+      active = false;
+      my_k = K;
+    }
+    wave_sync_lds();
+    const T inv = recip(pv[K]);
+    const T l = (r == pl) ? (A[K] - T(1)) * inv : A[K] * inv;
+#pragma unroll
+    for (int j = K + 1; j < N; ++j) A[j] -= l * pv[j];
+    rhs -= l * pv[N];
+    __builtin_amdgcn_wave_barrier();
+    gj_pivot<SLOT, N, K + 1, T>(A, rhs, r, active, my_k, pv);
+  }
+}
+
+// Per-lane inputs of one solve (loaded ahead of the solve).
+template <int P, int NQ, typename T>
+struct SolveIn {
+  using S = Shape<P, NQ>;
+  int e, flags;  // flags: bits 0-3 inflow faces, bits 4+2f.. neighbour's local face
+  int nb[4];     // neighbour element, or -(boundary face + 1)
+  bool valid;
+  T g[S::GV];
+  T f[S::GF];
+  T s;
+  T qd[S::QD];
+};
+
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void load_one(SolveIn<P, NQ, T> &in, int d, const KProb &pb,
+                                            const KIO &pio, int it, int r) {
+  using S = Shape<P, NQ>;
+  constexpr int N = S::N, Q = S::Q, SLOT = S::SLOT;
+  const int e = in.e;
+  if (!in.valid) return;
+  const T *gv = static_cast<const T *>(pb.geo_v) + (size_t)e * Q * 5;
+#pragma unroll
+  for (int k = 0; k < S::GV; ++k) {
+    const int i = r + k * SLOT;
+    in.g[k] = i < 5 * Q ? gv[i] : T(0);
+  }
+  const T *gf = static_cast<const T *>(pb.geo_f) + (size_t)e * 8 * NQ;
+#pragma unroll
+  for (int k = 0; k < S::GF; ++k) {
+    const int i = r + k * SLOT;
+    in.f[k] = i < 8 * NQ ? gf[i] : T(0);
+  }
+  const double *phi = it == 0 ? pio.phi_in : pio.mom;
+  T sv = T(0);
+  if (r < N) {
+    if (phi) sv = static_cast<T>(pb.sig[2 * e + 1] * kInv4Pi) * static_cast<T>(phi[(size_t)e * N + r]);
+    if (pio.q_iso) sv += static_cast<T>(pio.q_iso[(size_t)e * N + r]);
+  }
+  in.s = sv;
+#pragma unroll
+  for (int k = 0; k < S::QD; ++k) {
+    const int q = r + k * SLOT;
+    in.qd[k] = (pio.q_dir && q < Q) ? static_cast<T>(pio.q_dir[((size_t)d * pb.ne + e) * Q + q]) : T(0);
+  }
+}
+
+// Assemble and solve one element-direction system from prefetched inputs.
+// All lanes of the slot must call it; slots with in.valid == false store
+// nothing.  Uses only the slot's LDS area (no work-group barrier inside).
+template <int P, int NQ, typename T, bool PIVOT>
+__device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, const KProb &pb,
+                                           const KIO &pio, T *lds, int r, int slot, int *status) {
+  using S = Shape<P, NQ>;
+  constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
+  const T *sV = lds;
+  const T *sDx = lds + Q * N;
+  const T *sDy = lds + 2 * Q * N;
+  const T *sF = lds + 3 * Q * N;
+  T *area = lds + S::TAB + (size_t)slot * S::SLOT_AREA;
+  const int ne = pb.ne;
+  const int e = in.e;
+  const bool valid = in.valid;
+  const bool row_ok = valid && r < N;
+  const int rr = r < N ? r : N - 1;  // table index for padding lanes
+  const int a = rr % P1, b = rr / P1;
+  const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
+  const T *psi = static_cast<const T *>(pio.psi);
+
+  // upwind traces: the only loads on the critical path
+  T tr[4][P1];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+#pragma unroll
+    for (int c = 0; c < P1; ++c) tr[f][c] = T(0);
+    if (row_ok && on_face && ((mask >> f) & 1u) && in.nb[f] >= 0) {
+      const int f2 = (in.flags >> (4 + 2 * f)) & 3;
+      const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
+#pragma unroll
+      for (int c = 0; c < P1; ++c) tr[f][c] = up[face_node<P>(f2, P - c)];
+    }
+  }
+
+  // staging (wave-local)
+#pragma unroll
+  for (int k = 0; k < S::GV; ++k) {
+    const int i = r + k * SLOT;
+    if (i < 5 * Q) area[S::OFF_GEO + i] = in.g[k];
+  }
+#pragma unroll
+  for (int k = 0; k < S::GF; ++k) {
+    const int i = r + k * SLOT;
+    if (i < 8 * NQ) area[S::OFF_GF + i] = in.f[k];
+  }
+  if (r < N) area[S::OFF_S + r] = in.s;
+  wave_sync_lds();
+#pragma unroll
+  for (int k = 0; k < S::QD; ++k) {
+    const int q = r + k * SLOT;
+    if (q < Q) {
+      T src = in.qd[k];
+#pragma unroll
+      for (int j = 0; j < N; ++j) src += area[S::OFF_S + j] * sV[q * N + j];
+      area[S::OFF_SRC + q] = src;
+    }
+  }
+  wave_sync_lds();
+
+  // assembly of row r
+  const T ox = static_cast<T>(pb.omega[2 * d]);
+  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
+  const T st = static_cast<T>(pb.sig[2 * (valid ? e : 0)]);
+  T A[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) A[j] = T(0);
+  T rhs = T(0);
+  const T *g5 = area + S::OFF_GEO;
+  const T *srcq = area + S::OFF_SRC;
+#pragma unroll S::QU
+  for (int q = 0; q < Q; ++q) {
+    const T wJ = g5[5 * q], a00 = g5[5 * q + 1], a01 = g5[5 * q + 2], a10 = g5[5 * q + 3], a11 = g5[5 * q + 4];
+    const T gx = a00 * ox + a01 * oy;
+    const T gy = a10 * ox + a11 * oy;
+    const T li = sV[q * N + rr];
+    const T c = st * wJ * li - (gx * sDx[q * N + rr] + gy * sDy[q * N + rr]);
+    rhs += wJ * li * srcq[q];
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[j] += c * sV[q * N + j];
+  }
+
+  // face terms
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+    const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+    const T *gf = area + S::OFF_GF + f * NQ * 2;
+    if (!(row_ok && on_face)) continue;
+    if (!((mask >> f) & 1u)) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T on = ox * gf[2 * q] + oy * gf[2 * q + 1];
+        const T t = on * sF[q * P1 + pos];
+#pragma unroll
+        for (int c = 0; c < P1; ++c) A[face_node<P>(f, c)] += t * sF[q * P1 + c];
+      }
+    } else if (in.nb[f] >= 0) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        T ph = T(0);
+#pragma unroll
+        for (int c = 0; c < P1; ++c) ph += tr[f][c] * sF[q * P1 + c];
+        const T on = ox * gf[2 * q] + oy * gf[2 * q + 1];
+        rhs -= on * sF[q * P1 + pos] * ph;
+      }
+    } else if (pio.psi_bc) {
+      const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T on = ox * gf[2 * q] + oy * gf[2 * q + 1];
+        rhs -= on * sF[q * P1 + pos] * static_cast<T>(bc[q]);
+      }
+    }
+  }
+
+  // Gauss-Jordan elimination; lane r ends with unknown my_k in rhs
+  int my_k = r;
+  if constexpr (PIVOT) {
+    bool active = row_ok;
+    gj_pivot<SLOT, N, 0, T>(A, rhs, r, active, my_k, area + S::OFF_PIV);
+  } else {
+    gj_nopivot<SLOT, N, 0, T>(A, rhs, r);
+  }
+  if (row_ok) {
+    T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
+    out[my_k] = rhs;
+    if (!(rhs == rhs) || rhs - rhs != T(0)) atomicOr(status, 1);  // non-finite unknown
+  }
+}
+
+// Per-lane inputs of one solve on an affine element.
+template <int P, int NQ, typename T>
+struct SolveInA {
+  using S = Shape<P, NQ>;
+  int e, flags;
+  int nb[4];
+  bool valid;
+  T g[S::GA];
+  T s;
+  T qd[S::QD];
+};
+
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void load_one(SolveInA<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio,
+                                         int it, int r) {
+  using S = Shape<P, NQ>;
+  constexpr int N = S::N, Q = S::Q, SLOT = S::SLOT;
+  const int e = in.e;
+  if (!in.valid) return;
+  const T *ga = static_cast<const T *>(pb.geo_a) + (size_t)e * 16;
+#pragma unroll
+  for (int k = 0; k < S::GA; ++k) {
+    const int i = r + k * SLOT;
+    in.g[k] = i < 16 ? ga[i] : T(0);
+  }
+  const double *phi = it == 0 ? pio.phi_in : pio.mom;
+  T sv = T(0);
+  if (r < N) {
+    if (phi) sv = static_cast<T>(pb.sig[2 * e + 1] * kInv4Pi) * static_cast<T>(phi[(size_t)e * N + r]);
+    if (pio.q_iso) sv += static_cast<T>(pio.q_iso[(size_t)e * N + r]);
+  }
+  in.s = sv;
+#pragma unroll
+  for (int k = 0; k < S::QD; ++k) {
+    const int q = r + k * SLOT;
+    in.qd[k] = (pio.q_dir && q < Q) ? static_cast<T>(pio.q_dir[((size_t)d * pb.ne + e) * Q + q]) : T(0);
+  }
+}
+
+// Solve on an affine element (see the file comment); pivot-free.
+template <int P, int NQ, typename T, bool PIVOT>
+__device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, const KProb &pb,
+                                          const KIO &pio, T *lds, int r, int slot, int *status) {
+  using S = Shape<P, NQ>;
+  constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
+  static_assert(!PIVOT, "the affine path is pivot-free");
+  const T *Mt = lds + S::A_MT;
+  const T *Gxt = lds + S::A_GX;
+  const T *Gyt = lds + S::A_GY;
+  const T *M1 = lds + S::A_M1;
+  const T *WV = lds + S::A_WV;
+  const T *WL = lds + S::A_WL;
+  T *area = lds + S::TAB_A + (size_t)slot * S::SLOT_AREA_A;
+  const int ne = pb.ne;
+  const int e = in.e;
+  const bool valid = in.valid;
+  const bool row_ok = valid && r < N;
+  const int rr = r < N ? r : N - 1;
+  const int a = rr % P1, b = rr / P1;
+  const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
+  const T *psi = static_cast<const T *>(pio.psi);
+
+  // upwind traces: the only loads on the critical path
+  T tr[4][P1];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+#pragma unroll
+    for (int c = 0; c < P1; ++c) tr[f][c] = T(0);
+    if (row_ok && on_face && ((mask >> f) & 1u) && in.nb[f] >= 0) {
+      const int f2 = (in.flags >> (4 + 2 * f)) & 3;
+      const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
+#pragma unroll
+      for (int c = 0; c < P1; ++c) tr[f][c] = up[face_node<P>(f2, P - c)];
+    }
+  }
+
+  // staging (wave-local)
+#pragma unroll
+  for (int k = 0; k < S::GA; ++k) {
+    const int i = r + k * SLOT;
+    if (i < 16) area[S::AOFF_G + i] = in.g[k];
+  }
+  if (r < N) area[S::AOFF_S + r] = in.s;
+  if (pio.q_dir) {
+#pragma unroll
+    for (int k = 0; k < S::QD; ++k) {
+      const int q = r + k * SLOT;
+      if (q < Q) area[S::AOFF_QD + q] = in.qd[k];
+    }
+  }
+  wave_sync_lds();
+
+  // assembly of row r
+  const T ox = static_cast<T>(pb.omega[2 * d]);
+  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
+  const T st = static_cast<T>(pb.sig[2 * (valid ? e : 0)]);
+  const T *g = area + S::AOFF_G;
+  const T J = g[0];
+  const T stJ = st * J;
+  const T gx = g[1] * ox + g[2] * oy;
+  const T gy = g[3] * ox + g[4] * oy;
+  T A[N];
+  T rhs = T(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    A[j] = stJ * Mt[j * N + rr] - gx * Gxt[j * N + rr] - gy * Gyt[j * N + rr];
+    rhs += Mt[j * N + rr] * area[S::AOFF_S + j];
+  }
+  rhs *= J;
+  if (pio.q_dir) {
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc += WV[q * N + rr] * area[S::AOFF_QD + q];
+    rhs += J * acc;
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+    const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+    if (!(row_ok && on_face)) continue;
+    const T on = ox * g[5 + 2 * f] + oy * g[6 + 2 * f];
+    if (!((mask >> f) & 1u)) {
+#pragma unroll
+      for (int c = 0; c < P1; ++c) A[face_node<P>(f, c)] += on * M1[pos * P1 + c];
+    } else if (in.nb[f] >= 0) {
+      T acc = T(0);
+#pragma unroll
+      for (int c = 0; c < P1; ++c) acc += M1[pos * P1 + c] * tr[f][c];
+      rhs -= on * acc;
+    } else if (pio.psi_bc) {
+      const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
+      T acc = T(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc += WL[q * P1 + pos] * static_cast<T>(bc[q]);
+      rhs -= on * acc;
+    }
+  }
+
+  gj_nopivot<SLOT, N, 0, T>(A, rhs, r);
+  if (row_ok) {
+    T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
+    out[r] = rhs;
+    if (!(rhs == rhs) || rhs - rhs != T(0)) atomicOr(status, 1);  // non-finite unknown
+  }
+}
+
+template <int P, int NQ, typename T, int MODE>
+using InputsOf = std::conditional_t<MODE == MODE_AFFINE_NOPIVOT, SolveInA<P, NQ, T>, SolveIn<P, NQ, T>>;
+
+// Stage the tables of a variant into LDS.
+template <int P, int NQ, typename T, int MODE>
+__device__ __forceinline__ void stage_tables(const T *__restrict__ tables, T *lds) {
+  constexpr int TAB = Lds<P, NQ, MODE>::TAB;
+  for (int i = threadIdx.x; i < TAB; i += blockDim.x) lds[i] = tables[i];
+}
+
+// Level-synchronous schedule: one launch per upwind level over the list of
+// (element, direction | problem << 16) pairs of that level.
+template <int P, int NQ, typename T, int MODE>
+__global__ void __launch_bounds__(256)
+k_sweep_level(const int2 *__restrict__ solves, int n_solves, const KProb *__restrict__ probs,
+              const KIO *__restrict__ io, const T *__restrict__ tables, int it,
+              const int *__restrict__ stop, int *__restrict__ status) {
+  using S = Shape<P, NQ>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  if (*stop) return;
+  stage_tables<P, NQ, T, MODE>(tables, lds);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (S::SLOT - 1);
+  const int slot = (threadIdx.x >> 6) * S::SPW + lane / S::SLOT;
+  const int sid = blockIdx.x * ((blockDim.x >> 6) * S::SPW) + slot;
+  InputsOf<P, NQ, T, MODE> in;
+  in.valid = sid < n_solves;
+  int d = 0, prob = 0;
+  in.e = 0;
+  in.flags = 0;
+  if (in.valid) {
+    const int2 sv = solves[sid];
+    in.e = sv.x;
+    d = sv.y & 0xffff;
+    prob = sv.y >> 16;
+  }
+  const KProb &pb = probs[prob];
+  const KIO &pio = io[prob];
+  if (in.valid) {
+    in.flags = pb.mask[(size_t)d * pb.ne + in.e];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      in.nb[f] = pb.nbr[4 * in.e + f];
+      in.flags |= ((int)pb.nbr_face[4 * in.e + f] & 3) << (4 + 2 * f);
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) in.nb[f] = -1;
+  }
+  load_one<P, NQ, T>(in, d, pb, pio, it, r);
+  solve_one<P, NQ, T, MODE == MODE_GENERAL_PIVOT>(in, d, pb, pio, lds, r, slot, status);
+}
+
+// Largest work-group of the direction-resident schedule for a variant, chosen
+// so that the kernel's registers fit without spilling (a 1024-thread group
+// leaves 128 VGPRs per lane, 512 leaves 256).
+template <int P, int NQ, typename T, int MODE>
+constexpr int dir_block_max() {
+  if (MODE == MODE_AFFINE_NOPIVOT) {
+    if (sizeof(T) == 8) return P <= 3 ? 512 : 256;
+    return P <= 2 ? 1024 : 512;
+  }
+  if (sizeof(T) == 8) return 512;
+  return (P == 4 && NQ >= 6) ? 512 : 1024;
+}
+
+// Direction-resident schedule: work-group b sweeps one (problem, direction)
+// pair through all upwind levels of its direction class.  The elements of a
+// level are solved in rounds of (blockDim / SLOT) slots; each slot loads the
+// inputs of its next solve before computing the current one, and a
+// work-group barrier separates consecutive levels (upwind values were
+// written by this work-group, so work-group scope visibility suffices).
+// Element descriptors (id, inflow mask, neighbours) come packed in level
+// order per direction class; the level offsets sit in LDS.
+template <int P, int NQ, typename T, int MODE>
+__global__ void __launch_bounds__((dir_block_max<P, NQ, T, MODE>()))
+k_sweep_dir(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
+            const KIO *__restrict__ io, const T *__restrict__ tables, int it,
+            const int *__restrict__ stop, int *__restrict__ status) {
+  using S = Shape<P, NQ>;
+  using LD = Lds<P, NQ, MODE>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  if (*stop) return;
+  const int2 tk = tasks[blockIdx.x];
+  const int prob = tk.x, d = tk.y;
+  const KProb &pb = probs[prob];
+  const KIO &pio = io[prob];
+  const int g = pb.dir_group[d];
+  const int nl = pb.n_levels_g[g];
+  const int slots = (blockDim.x >> 6) * S::SPW;
+  int *lo = reinterpret_cast<int *>(lds + LD::TAB + (size_t)slots * LD::AREA);
+  stage_tables<P, NQ, T, MODE>(tables, lds);
+  const int32_t *lo_g = pb.level_off + (size_t)g * (pb.n_levels + 1);
+  for (int i = threadIdx.x; i <= nl; i += blockDim.x) lo[i] = lo_g[i];
+  __syncthreads();
+  const int2 *dsc = pb.desc_ef + (size_t)g * pb.ne;
+  const int4 *dnb = pb.desc_nb + (size_t)g * pb.ne;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (S::SLOT - 1);
+  const int slot = (threadIdx.x >> 6) * S::SPW + lane / S::SLOT;
+
+  auto fetch = [&](InputsOf<P, NQ, T, MODE> &in, int L, int t) {
+    in.valid = L < nl && t < lo[L + 1];
+    in.e = 0;
+    in.flags = 0;
+    in.nb[0] = in.nb[1] = in.nb[2] = in.nb[3] = -1;
+    if (in.valid) {
+      const int2 ef = dsc[t];
+      const int4 nb = dnb[t];
+      in.e = ef.x;
+      in.flags = ef.y;
+      in.nb[0] = nb.x;
+      in.nb[1] = nb.y;
+      in.nb[2] = nb.z;
+      in.nb[3] = nb.w;
+    }
+    load_one<P, NQ, T>(in, d, pb, pio, it, r);
+  };
+
+  InputsOf<P, NQ, T, MODE> cur, nxt;
+  int L = 0, base = 0;
+  fetch(cur, 0, slot);
+  while (L < nl) {
+    // the round after (L, base)
+    int L2 = L, base2 = base + slots;
+    if (base2 >= lo[L + 1]) {
+      L2 = L + 1;
+      base2 = L2 < nl ? lo[L2] : 0;
+    }
+    fetch(nxt, L2, base2 + slot);
+    solve_one<P, NQ, T, MODE == MODE_GENERAL_PIVOT>(cur, d, pb, pio, lds, r, slot, status);
+    if (L2 != L) __syncthreads();  // the level's fluxes are upwind values of the next
+    cur = nxt;
+    L = L2;
+    base = base2;
+  }
+}
+
+// Largest multiple of 64 threads <= want whose LDS fits in lds_max bytes.
+template <int P, int NQ, int MODE>
+int fit_block(bool fp32, int want, size_t lds_max, int extra_ints, size_t *bytes) {
+  using S = Shape<P, NQ>;
+  using LD = Lds<P, NQ, MODE>;
+  for (int block = want; block >= 64; block -= 64) {
+    const int slots = (block / 64) * S::SPW;
+    const size_t b = fp32 ? lds_bytes<float>(LD::TAB, LD::AREA, slots, extra_ints)
+                          : lds_bytes<double>(LD::TAB, LD::AREA, slots, extra_ints);
+    if (b <= lds_max) {
+      *bytes = b;
+      return block;
+    }
+  }
+  return 0;
+}
+
+template <int P, int NQ, typename T, int MODE>
+hipError_t launch_level_t(const SweepLaunch &L) {
+  size_t bytes = 0;
+  const int block = fit_block<P, NQ, MODE>(L.fp32, L.block > 256 ? 256 : L.block, L.lds_max, 0, &bytes);
+  if (block == 0) return hipErrorInvalidValue;
+  const int per_block = (block / 64) * Shape<P, NQ>::SPW;
+  const int grid = (L.count + per_block - 1) / per_block;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sweep_level<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.list,
+                     L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
+  return hipGetLastError();
+}
+
+template <int P, int NQ, typename T, int MODE>
+hipError_t launch_dir_t(const SweepLaunch &L) {
+  if (L.count == 0) return hipSuccess;
+  constexpr int SLOT = Shape<P, NQ>::SLOT;
+  const int maxb = dir_block_max<P, NQ, T, MODE>();
+  int block = ((L.width * SLOT + 63) / 64) * 64;
+  block = block < 64 ? 64 : (block > maxb ? maxb : block);
+  size_t bytes = 0;
+  block = fit_block<P, NQ, MODE>(L.fp32, block, L.lds_max, L.max_levels + 1, &bytes);
+  if (block == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep_dir<P, NQ, T, MODE>), dim3(L.count), dim3(block), bytes, L.stream, L.list,
+                     L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
+  return hipGetLastError();
+}
+
+template <int P, int NQ, typename T, bool DIR>
+hipError_t launch_mode(const SweepLaunch &L) {
+  switch (L.mode) {
+    case MODE_GENERAL_PIVOT:
+      return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_PIVOT>(L) : launch_level_t<P, NQ, T, MODE_GENERAL_PIVOT>(L);
+    case MODE_GENERAL_NOPIVOT:
+      return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_NOPIVOT>(L)
+                 : launch_level_t<P, NQ, T, MODE_GENERAL_NOPIVOT>(L);
+    case MODE_AFFINE_NOPIVOT:
+      return DIR ? launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L) : launch_level_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P, bool DIR>
+hipError_t launch_p(const SweepLaunch &L) {
+  switch (L.nq - P) {
+    case 1: return L.fp32 ? launch_mode<P, P + 1, float, DIR>(L) : launch_mode<P, P + 1, double, DIR>(L);
+    case 2: return L.fp32 ? launch_mode<P, P + 2, float, DIR>(L) : launch_mode<P, P + 2, double, DIR>(L);
+    case 3: return L.fp32 ? launch_mode<P, P + 3, float, DIR>(L) : launch_mode<P, P + 3, double, DIR>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+}  // namespace vefk

@@ -68,7 +68,7 @@ class vef_moment_io(C.Structure):
 
 class vef_info(C.Structure):
     _fields_ = [("n", C.c_int), ("nq", C.c_int), ("Q", C.c_int), ("n_bf", C.c_int), ("n_levels", C.c_int),
-                ("n_groups", C.c_int), ("pivoting", C.c_int), ("n_solves", C.c_longlong)]
+                ("n_groups", C.c_int), ("pivoting", C.c_int), ("affine", C.c_int), ("n_solves", C.c_longlong)]
 
 
 def _load():

@@ -134,8 +134,29 @@ def test_curved_meshes(torch, precision, shape, schedule):
     assert rel_inf(g["cl_Eb"], cl["Eb"]) <= 10 * tol
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("p,m,warp", [(2, 2, 0.08), (3, 1, 0.0), (1, 2, 0.05)])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_straight_non_affine_mesh(torch, precision, p, schedule):
+    """Trapezoids (straight faces, varying J): the general pivot-free path."""
+    from test_library_host import _trapezoids
+    cp, ec = _trapezoids(7, 0.2, seed=p)
+    om, wt = P.level_symmetric_2d(6)
+    ne = ec.shape[0]
+    rng = np.random.default_rng(p)
+    st = rng.uniform(0.5, 20, ne)
+    pr = P.Problem("trap", p, 1, cp, ec, om, wt, st, 0.7 * st, q_iso=rng.uniform(0, 1, (ne, (p + 1) ** 2)))
+    nb = O.n_boundary_faces(pr)
+    pr.psi_bc = rng.uniform(0, 1, (pr.n_dir, nb, p + 1))
+    phi = rng.uniform(0, 2, (ne, (p + 1) ** 2))
+    (g,), _ = gpu_run(torch, [pr], precision, phi_in=phi, schedule=schedule)
+    ref = O.sweep(pr, phi_in=phi)
+    assert rel_inf(g["psi_out"], ref["psi"]) <= TOL[precision]
+    assert rel_inf(g["mom"][0], ref["mom"][0]) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p,m,warp", [(2, 2, 0.08), (3, 1, 0.0), (1, 2, 0.05), (4, 1, 0.0), (2, 2, 0.0)])
 def test_mms_inputs(torch, precision, p, m, warp):
     """Direction-dependent source at volume points and non-isotropic inflow data."""
     pr = _small(8, 8, p, m, 4, warp=warp, q=0.0)

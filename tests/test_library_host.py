@@ -124,3 +124,30 @@ def test_plan_detects_cycle():
     assert oe.value.code == O.ERR_CYCLE
     msg = _bad(pr, vef.VEF_ERR_CYCLE)
     assert "cycle" in msg
+
+
+def _trapezoids(n=6, amp=0.15, seed=3):
+    """Straight-sided, non-affine mesh: interior vertices of an m = 1 grid moved at random."""
+    cp, ec = P.quad_mesh(n, n, 1)
+    cp = cp.copy()
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    inner = (cp[:, 0] > 1e-12) & (cp[:, 0] < 1 - 1e-12) & (cp[:, 1] > 1e-12) & (cp[:, 1] < 1 - 1e-12)
+    cp[inner] += rng.uniform(-amp * h, amp * h, (inner.sum(), 2))
+    return cp, ec
+
+
+def test_affine_classification():
+    vef = _vef()
+    (c1,), _ = P.make_config("c1")
+    assert vef.vef_plan_query(c1)["affine"] == 1
+    (c3,), _ = P.make_config("c3", scale=6)
+    i3 = vef.vef_plan_query(c3)
+    assert i3["affine"] == 0 and i3["pivoting"] == 1
+    cp, ec = P.quad_mesh(4, 4, 2)  # straight, uniformly placed midpoints: affine
+    q = P.Problem("m2", 2, 2, cp, ec, c1.omega, c1.weight, np.ones(16), np.zeros(16))
+    assert vef.vef_plan_query(q)["affine"] == 1
+    cp, ec = _trapezoids()
+    q = P.Problem("trap", 2, 1, cp, ec, c1.omega, c1.weight, np.ones(36), np.zeros(36))
+    i = vef.vef_plan_query(q)
+    assert i["affine"] == 0 and i["pivoting"] == 0
