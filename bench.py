@@ -160,7 +160,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": describe(args.workload, probs, run), "n_elem": pr.n_elem, "p": pr.p,
                    "n_dir": pr.n_dir, "sweeps_per_step": n_iter,
-                   "schedule": {"auto": "dir_resident", "dir": "dir_resident", "level": "level_sync"}[args.schedule],
+                   "schedule": {"auto": "auto (dir_resident for this workload)", "dir": "dir_resident",
+                                "level": "level_sync"}[args.schedule],
                    "precision": "fp64"},
         "hbm_gbs_algorithmic": hbm_gbs,
         "roofline": roofline,

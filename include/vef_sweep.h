@@ -65,7 +65,9 @@ enum {
 
 enum { VEF_FP64 = 0, VEF_FP32_LOCAL = 1 };
 enum {
-  VEF_SCHEDULE_AUTO = 0, /* library choice (currently VEF_DIR_RESIDENT) */
+  VEF_SCHEDULE_AUTO = 0, /* VEF_DIR_RESIDENT when every problem's mean level
+                            width fits one round of a work-group, else
+                            VEF_LEVEL_SYNC */
   VEF_LEVEL_SYNC = 1,    /* one launch per upwind level over all directions */
   VEF_DIR_RESIDENT = 2   /* one launch per sweep; one work-group per (problem,
                             direction) walks all upwind levels with work-group

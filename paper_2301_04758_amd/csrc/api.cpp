@@ -59,7 +59,7 @@ struct DirLaunch {  // one direction-resident launch: all (problem, direction) p
 struct vef_sweep {
   std::string err;
   int precision = VEF_FP64;
-  int schedule = VEF_DIR_RESIDENT;
+  int schedule = VEF_SCHEDULE_AUTO;
   int block = 256;
   int device = 0;
   size_t lds_max = 65536;  // shared memory per work-group of the device
@@ -173,7 +173,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (opt->block != 0 && (opt->block < 64 || opt->block > 1024 || opt->block % 64))
       return set_err(h, VEF_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
     h->precision = opt->precision;
-    h->schedule = opt->schedule == VEF_SCHEDULE_AUTO ? VEF_DIR_RESIDENT : opt->schedule;
+    h->schedule = opt->schedule;
     h->timing = opt->timing != 0;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
@@ -352,6 +352,18 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   }
   he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload direction tasks");
+  if (h->schedule == VEF_SCHEDULE_AUTO) {
+    // direction-resident when every problem's mean level width fits in one
+    // round of a work-group (the sweep then costs one barrier per level and
+    // no launches); level-synchronous otherwise (wide levels keep all CUs busy)
+    bool narrow = true;
+    for (auto &pl : h->plans) {
+      const int slot = pl.n <= 4 ? 4 : (pl.n <= 8 ? 8 : (pl.n <= 16 ? 16 : 32));
+      const int slots = (fp32 ? 1024 : 512) / slot;
+      if ((double)pl.ne / pl.n_levels > slots) narrow = false;
+    }
+    h->schedule = narrow ? VEF_DIR_RESIDENT : VEF_LEVEL_SYNC;
+  }
   h->psi_internal.assign(n_probs, nullptr);
   h->resid_scratch.assign(n_probs, nullptr);
   h->resid_cap.assign(n_probs, 0);
