@@ -187,20 +187,26 @@ static int ctx_init(ctx_t *c, const oracle_problem *pr) {
   return ORACLE_OK;
 }
 
-/* x(xi) = sum_i x_{e,i} l_i(xi) and F = dx/dxi = [[x_xi, x_eta],[y_xi, y_eta]]. */
+/* x(xi) = sum_i x_{e,i} l_i(xi) and F = dx/dxi = [[x_xi, x_eta],[y_xi, y_eta]].
+ * The basis functions sum to one, so their derivatives sum to zero and
+ * F = sum_i (x_{e,i} - x_{e,0}) grad l_i: the same quantity, evaluated from
+ * coordinate differences of element size instead of coordinates of domain
+ * size (whose cancellation would cost log2(domain / element) bits). */
 static void map_point(const ctx_t *c, int e, double xi, double eta, double *x, double F[2][2]) {
   const oracle_problem *pr = c->pr;
   double v[(MAXM + 1) * (MAXM + 1)], dxi[(MAXM + 1) * (MAXM + 1)], deta[(MAXM + 1) * (MAXM + 1)];
   basis2d(c->zm, pr->m, xi, eta, v, dxi, deta);
+  const double *c0 = pr->cp_xy + 2 * (size_t)pr->elem_cp[(size_t)e * c->ncp_e];
   double X = 0, Y = 0, F00 = 0, F01 = 0, F10 = 0, F11 = 0;
   for (int i = 0; i < c->ncp_e; ++i) {
     const double *cp = pr->cp_xy + 2 * (size_t)pr->elem_cp[(size_t)e * c->ncp_e + i];
+    const double rx = cp[0] - c0[0], ry = cp[1] - c0[1];
     X += cp[0] * v[i];
     Y += cp[1] * v[i];
-    F00 += cp[0] * dxi[i];
-    F01 += cp[0] * deta[i];
-    F10 += cp[1] * dxi[i];
-    F11 += cp[1] * deta[i];
+    F00 += rx * dxi[i];
+    F01 += rx * deta[i];
+    F10 += ry * dxi[i];
+    F11 += ry * deta[i];
   }
   if (x) { x[0] = X; x[1] = Y; }
   if (F) { F[0][0] = F00; F[0][1] = F01; F[1][0] = F10; F[1][1] = F11; }

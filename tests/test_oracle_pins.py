@@ -88,6 +88,32 @@ def test_boundary_face_numbering_is_element_face_order():
 # ---------------------------------------------------------------- invariants
 
 
+
+def _random_st(ne):
+    return np.random.default_rng(7).uniform(0.5, 5.0, ne)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_translation_invariance(m):
+    """Geometry: the discrete problem is invariant under a translation of the
+    mesh.  Control points on a 2^-30 grid stay exact when shifted by 2^10, so
+    the translated problem is the same problem; only an evaluation of the map
+    derivatives from absolute coordinates (cancellation of domain-size
+    numbers down to element size) could tell them apart, by about
+    eps * 2^10 / h = 5e-12 here."""
+    pr = _problem(24, 24, 3, m, 4, st=_random_st(24 * 24), ss=0.0, warp=0.08 if m > 1 else 0.0, q=1.0)
+    if m == 1:  # straight but non-affine: move interior vertices
+        cp = pr.cp_xy.copy()
+        inner = (cp > 1e-12).all(1) & (cp < 1 - 1e-12).all(1)
+        cp[inner] += RNG.uniform(-0.01, 0.01, (inner.sum(), 2))
+        pr.cp_xy = cp
+    pr.cp_xy = np.round(pr.cp_xy * 2.0 ** 30) / 2.0 ** 30
+    a = O.sweep(pr)
+    pr.cp_xy = pr.cp_xy + 2.0 ** 10
+    b = O.sweep(pr)
+    assert np.abs(b["psi"] - a["psi"]).max() <= 4e-16 * np.abs(a["psi"]).max()
+
+
 @pytest.mark.parametrize("p,m,warp", [(1, 1, 0.0), (3, 1, 0.0), (2, 2, 0.1), (3, 2, 0.1), (4, 1, 0.0)])
 def test_constant_preservation(p, m, warp):
     """sigma_s = 0, q const, inflow q/sigma_t: psi == q/sigma_t (Piola identity keeps
