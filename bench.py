@@ -89,10 +89,20 @@ def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto
     t1 = time.perf_counter()
     sw.check()
     out = dict(seconds=t1 - t0, sweep_ms=sweep_ms, launches=launches,
+               schedule=vef.SCHEDULE_NAMES[sw.info[0]["schedule"]], kernel=sw.info[0]["kernel"],
                phi=[b["mom"][0].double().cpu().numpy() for b in io],
                resid=[b["resid"].cpu().numpy() for b in io])
     sw.close()
     return out
+
+
+def kernel_name(g, pr):
+    """Name of the sweep kernel that ran (as the profiler lists it)."""
+    nq = pr.nq or pr.p + pr.m
+    if g["schedule"] == "dir_resident" and g["kernel"] == 3:
+        return "k_sweep_pipe<%d, %d, double>" % (pr.p, nq)
+    kind = "dir" if g["schedule"] == "dir_resident" else "level"
+    return "k_sweep_%s<%d, %d, double, %d>" % (kind, pr.p, nq, g["kernel"])
 
 
 def cpu_baseline(probs, iters):
@@ -119,6 +129,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 256 MiB (three times), the reference kernel "
+                         "for scaling HBM byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -147,8 +160,7 @@ def main():
     achieved_tf = F * solves_per_launch / avg_launch_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_sweep_%s<%d,%d,double>" % ("level" if args.schedule == "level" else "dir",
-                                                         pr.p, pr.p + pr.m), "avg_launch_us": avg_launch_s * 1e6,
+                "kernel": kernel_name(g64, pr), "avg_launch_us": avg_launch_s * 1e6,
                 "launches_per_step": launches / args.steps,
                 "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
                 "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
@@ -160,8 +172,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": describe(args.workload, probs, run), "n_elem": pr.n_elem, "p": pr.p,
                    "n_dir": pr.n_dir, "sweeps_per_step": n_iter,
-                   "schedule": {"auto": "auto (dir_resident for this workload)", "dir": "dir_resident",
-                                "level": "level_sync"}[args.schedule],
+                   "schedule": ("auto: " if args.schedule == "auto" else "") + g64["schedule"],
                    "precision": "fp64"},
         "hbm_gbs_algorithmic": hbm_gbs,
         "roofline": roofline,
@@ -173,6 +184,18 @@ def main():
         result["fp32_local"] = {"ms_per_step": ms32, "value": solves_per_step / (ms32 * 1e-3),
                                 "speedup_vs_fp64": ms_step / ms32,
                                 "rel_inf_phi_vs_fp64_path": err, "within_1e-5": err <= 1e-5}
+    if args.copy_calibration:
+        n = 256 << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration"] = {"bytes_read": n, "bytes_written": n, "launches": 3,
+                                      "gbs": 2 * n * 3 / (time.perf_counter() - t0) / 1e9}
+        del src, dst
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(probs, args.cpu_iters)
     print(json.dumps(result), flush=True)

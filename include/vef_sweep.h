@@ -82,7 +82,7 @@ typedef struct {
   int p;                  /* DG degree, 1..4 */
   int m;                  /* geometry order, 1..3 */
   int nq;                 /* Gauss points per direction; 0 = p + m; else p+1..p+3 */
-  int n_elem;             /* elements, >= 1 */
+  int n_elem;             /* elements, 1..4194304 */
   int n_cp;               /* control points, >= 4 */
   const double *cp_xy;    /* [n_cp][2] */
   const int32_t *elem_cp; /* [n_elem][(m+1)^2] control point ids, xi fastest */
@@ -102,7 +102,15 @@ typedef struct {
   int block;     /* work-group size for the sweep kernels; 0 = default 256 */
   int timing;    /* nonzero: runs record HIP events around the sweep kernels
                     of every source iteration (read with vef_sweep_timing) */
-  int reserved[4];
+  int pipeline_waves; /* waves per work-group of the pipelined
+                    direction-resident kernel (affine elements, p <= 2):
+                    0 = default 8, 1..8; -1 = use the row-per-lane
+                    kernel instead) */
+  int pipeline_ring;  /* levels of face traces the pipelined kernel keeps in
+                    LDS (0 = default 4, 1..4; fewer when LDS is short);
+                    upwind elements further back are read from the angular
+                    flux in global memory */
+  int reserved[2];
 } vef_options;
 
 /* Per-problem device buffers of one run (device pointers owned by the caller).
@@ -159,7 +167,20 @@ typedef struct {
                     so the local matrices are assembled from reference
                     matrices scaled by the element's J and adj(F) */
   long long n_solves; /* n_elem * n_dir */
+  int schedule;  /* vef_problem_info: the handle's schedule as resolved at
+                    create (VEF_LEVEL_SYNC or VEF_DIR_RESIDENT);
+                    vef_plan_query: VEF_SCHEDULE_AUTO */
+  int kernel;    /* vef_problem_info: sweep kernel of this problem,
+                    VEF_KERNEL_*; vef_plan_query: -1 */
 } vef_info;
+
+/* Sweep kernels (vef_info.kernel). */
+#define VEF_KERNEL_PIVOT 0          /* row per lane, partial pivoting */
+#define VEF_KERNEL_NOPIVOT 1        /* row per lane, natural order */
+#define VEF_KERNEL_AFFINE 2         /* row per lane, reference-matrix assembly */
+#define VEF_KERNEL_AFFINE_PIPELINE 3 /* element per lane, LU ahead of the
+                                       upwind data (direction-resident,
+                                       affine, p <= 2) */
 
 /* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
  * upwind graphs), build the sweep plan on the host and upload it to the
@@ -194,7 +215,10 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info);
 int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out);
 
 /* Synchronise the handle's last stream and return the device status word:
- * VEF_OK, or VEF_ERR_INVALID when a local system had a zero pivot. */
+ * VEF_OK; VEF_ERR_INVALID when a local solve produced a non-finite unknown
+ * (singular or overflowing local system); VEF_ERR_TIMEOUT when a bounded
+ * device-side wait of the pipelined kernel expired (the kernel then exits
+ * without finishing the sweep). */
 int vef_sweep_check(vef_sweep_t *h);
 
 /* Timing of the last run on a handle created with opt->timing != 0:

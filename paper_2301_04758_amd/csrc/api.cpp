@@ -35,9 +35,10 @@ struct Variant {
   }
 };
 
-int mode_of(const vefplan::ProblemPlan &pl) {
+int mode_of(const vefplan::ProblemPlan &pl, int schedule, bool pipeline = true) {
   if (!pl.nopivot) return 0;
-  return pl.affine ? 2 : 1;
+  if (!pl.affine) return 1;
+  return (pipeline && schedule == VEF_DIR_RESIDENT && pl.p <= 2) ? 3 : 2;
 }
 
 struct LevelLaunch {
@@ -51,6 +52,7 @@ struct DirLaunch {  // one direction-resident launch: all (problem, direction) p
   int off, cnt;    // into d_dir_tasks
   int width;       // widest upwind level among the variant's problems
   int max_levels;  // deepest level count among them
+  int max_gap;     // largest upwind level gap among them
   const void *tab;
 };
 
@@ -86,6 +88,8 @@ struct vef_sweep {
   int *d_flags = nullptr;  // [0] stop, [1] iterations done, [2] status
   hipStream_t last_stream = nullptr;
   bool timing = false;
+  int pipeline_waves = 0;
+  int pipeline_ring = 0;
   std::vector<hipEvent_t> events;  // [2 * iterations] of the last run
   int timed_iters = 0;
   int timed_launches = 0;
@@ -175,6 +179,12 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     h->precision = opt->precision;
     h->schedule = opt->schedule;
     h->timing = opt->timing != 0;
+    if (opt->pipeline_waves < -1 || opt->pipeline_waves > 8)
+      return set_err(h, VEF_ERR_INVALID, "pipeline_waves must be -1..8");
+    h->pipeline_waves = opt->pipeline_waves;
+    if (opt->pipeline_ring < 0 || opt->pipeline_ring > 4)
+      return set_err(h, VEF_ERR_INVALID, "pipeline_ring must be 0..4");
+    h->pipeline_ring = opt->pipeline_ring;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
   }
@@ -248,6 +258,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (he == hipSuccess) he = upload(h, &bfe, pl.bf_ef.data(), pl.bf_ef.size());
     if (he == hipSuccess) he = dev_alloc(h, &bnd, (size_t)pl.nbf * pl.nq * 2);
     int32_t *dg = nullptr, *nlg = nullptr, *lof = nullptr, *ord = nullptr, *def = nullptr, *dnb = nullptr;
+    uint32_t *dup = nullptr;
+    if (he == hipSuccess) he = upload(h, &dup, pl.desc_up.data(), pl.desc_up.size());
     if (he == hipSuccess) he = upload(h, &def, pl.desc_ef.data(), pl.desc_ef.size());
     if (he == hipSuccess) he = upload(h, &dnb, pl.desc_nb.data(), pl.desc_nb.size());
     if (he == hipSuccess) he = upload(h, &dg, pl.dir_group.data(), pl.dir_group.size());
@@ -261,6 +273,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     kp.order = ord;
     kp.desc_ef = reinterpret_cast<const int2 *>(def);
     kp.desc_nb = reinterpret_cast<const int4 *>(dnb);
+    kp.desc_up = dup;
     kp.n_levels = pl.n_levels;
     kp.n_groups = pl.n_groups;
     kp.geo_fd = gfd;
@@ -286,17 +299,47 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   if (he == hipSuccess) he = hipEventCreateWithFlags(&h->mio_uploaded, hipEventDisableTiming);
   if (he != hipSuccess) return hip_fail(h, he, "allocate handle buffers");
 
+  if (h->schedule == VEF_SCHEDULE_AUTO) {
+    // Direction-resident when every problem is narrow enough, level-synchronous
+    // otherwise.  A level-synchronous level costs a launch (several us) however
+    // narrow it is; a direction-resident level costs the work of the level on
+    // one CU.  Measured crossovers: the row-per-lane kernel wins while the mean
+    // level width fits in one round of slots of a work-group; the pipelined
+    // kernel (about 1 us + 0.03 us per element of a level, p <= 2) up to a
+    // mean width of about 256.
+    bool narrow = true;
+    for (auto &pl : h->plans) {
+      const double width = (double)pl.ne / pl.n_levels;
+      if (mode_of(pl, VEF_DIR_RESIDENT, h->pipeline_waves >= 0) == 3) {
+        if (width > 256.0) narrow = false;
+        continue;
+      }
+      const int slot = pl.n <= 4 ? 4 : (pl.n <= 8 ? 8 : (pl.n <= 16 ? 16 : 32));
+      const int slots = (fp32 ? 1024 : 512) / slot;
+      if (width > slots) narrow = false;
+    }
+    h->schedule = narrow ? VEF_DIR_RESIDENT : VEF_LEVEL_SYNC;
+  }
   // level lists: level -> variant (p, nq) -> problem -> class -> element -> direction
   int max_levels = 0;
   for (auto &pl : h->plans) max_levels = std::max(max_levels, pl.n_levels);
   std::vector<Variant> variants;
   {
     std::map<Variant, int> vs;
-    for (auto &pl : h->plans) vs[Variant{pl.p, pl.nq, mode_of(pl)}] = 1;
+    for (auto &pl : h->plans) {
+      const int m = mode_of(pl, h->schedule, h->pipeline_waves >= 0);
+      vs[Variant{pl.p, pl.nq, m}] = 1;
+      if (m == 3) vs[Variant{pl.p, pl.nq, 2}] = 1;  // level lists keep mode 2
+    }
     for (auto &kv : vs) variants.push_back(kv.first);
   }
-  auto in_variant = [](const vefplan::ProblemPlan &pl, const Variant &v) {
-    return pl.p == v.p && pl.nq == v.nq && mode_of(pl) == v.mode;
+  auto in_variant = [&](const vefplan::ProblemPlan &pl, const Variant &v) {
+    return pl.p == v.p && pl.nq == v.nq && mode_of(pl, h->schedule, h->pipeline_waves >= 0) == v.mode;
+  };
+  // the level-synchronous lists use the row-per-lane variant of every problem
+  auto in_level_variant = [&](const vefplan::ProblemPlan &pl, const Variant &v) {
+    const int m = mode_of(pl, VEF_LEVEL_SYNC);
+    return pl.p == v.p && pl.nq == v.nq && m == v.mode;
   };
   std::vector<std::vector<std::vector<int>>> dirs_of(n_probs);
   for (int k = 0; k < n_probs; ++k) {
@@ -314,7 +357,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       const int off = (int)solves.size();
       for (int k = 0; k < n_probs; ++k) {
         const auto &pl = h->plans[k];
-        if (!in_variant(pl, var) || L >= pl.n_levels) continue;
+        if (!in_level_variant(pl, var) || L >= pl.n_levels) continue;
         for (int g = 0; g < pl.n_groups; ++g) {
           const int *lo = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
           const int32_t *ord = &pl.order[(size_t)g * pl.ne];
@@ -325,7 +368,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       const int cnt = (int)solves.size() - off;
       if (cnt > 0) {
         const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
-        h->levels[L].push_back({var, off, cnt, var.mode == 2 ? ts.dev_A : ts.dev_T});
+        h->levels[L].push_back({var, off, cnt, var.mode >= 2 ? ts.dev_A : ts.dev_T});
       }
     }
   if (solves.size() != total) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
@@ -336,34 +379,23 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   std::vector<int2> tasks;
   for (auto &var : variants) {
     const int off = (int)tasks.size();
-    int width = 1, maxl = 1;
+    int width = 1, maxl = 1, gap = 0;
     for (int k = 0; k < n_probs; ++k) {
       const auto &pl = h->plans[k];
       if (!in_variant(pl, var)) continue;
       for (int d = 0; d < pl.nd; ++d) tasks.push_back(make_int2(k, d));
       width = std::max(width, pl.max_width);
       maxl = std::max(maxl, pl.n_levels);
+      gap = std::max(gap, pl.max_gap);
     }
     const int cnt = (int)tasks.size() - off;
     if (cnt > 0) {
       const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
-      h->dir_launches.push_back({var, off, cnt, width, maxl, var.mode == 2 ? ts.dev_A : ts.dev_T});
+      h->dir_launches.push_back({var, off, cnt, width, maxl, gap, var.mode >= 2 ? ts.dev_A : ts.dev_T});
     }
   }
   he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload direction tasks");
-  if (h->schedule == VEF_SCHEDULE_AUTO) {
-    // direction-resident when every problem's mean level width fits in one
-    // round of a work-group (the sweep then costs one barrier per level and
-    // no launches); level-synchronous otherwise (wide levels keep all CUs busy)
-    bool narrow = true;
-    for (auto &pl : h->plans) {
-      const int slot = pl.n <= 4 ? 4 : (pl.n <= 8 ? 8 : (pl.n <= 16 ? 16 : 32));
-      const int slots = (fp32 ? 1024 : 512) / slot;
-      if ((double)pl.ne / pl.n_levels > slots) narrow = false;
-    }
-    h->schedule = narrow ? VEF_DIR_RESIDENT : VEF_LEVEL_SYNC;
-  }
   h->psi_internal.assign(n_probs, nullptr);
   h->resid_scratch.assign(n_probs, nullptr);
   h->resid_cap.assign(n_probs, 0);
@@ -478,6 +510,9 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
     SL.block = h->block;
     SL.lds_max = h->lds_max;
     SL.stream = s;
+    SL.waves = h->pipeline_waves > 0 ? h->pipeline_waves : 0;
+    SL.ring = h->pipeline_ring;
+    SL.wait_spins = 1LL << 26;  // seconds of polling: a healthy wait takes microseconds
     if (h->schedule == VEF_LEVEL_SYNC) {
       for (auto &lv : h->levels)
         for (auto &L : lv) {
@@ -500,6 +535,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
         SL.count = D.cnt;
         SL.width = D.width;
         SL.max_levels = D.max_levels;
+        SL.max_gap = D.max_gap;
         SL.tables = D.tab;
         he = vefk::launch_sweep_dir(SL);
         if (he != hipSuccess) return hip_fail(h, he, "launch sweep");
@@ -511,11 +547,17 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
     for (int k = 0; k < np; ++k) {
       const auto &pl = h->plans[k];
       he = vefk::launch_moments(fp32, h->d_probs, h->d_io, k, pl.ne * pl.n, it, stop, s);
-      if (he == hipSuccess) he = vefk::launch_boundary(fp32, h->d_probs, h->d_io, k, pl.nbf, pl.nq, pl.p, stop, s);
       if (he != hipSuccess) return hip_fail(h, he, "launch moments");
     }
     he = vefk::launch_finalize(h->d_io, np, it, a->tol, stop, iters, a->iters_done, s);
     if (he != hipSuccess) return hip_fail(h, he, "launch finalize");
+  }
+  // Boundary sums for E_b and J_in, once, from the angular flux of the last
+  // sweep performed (later sweeps skipped by the tolerance test leave it).
+  for (int k = 0; k < np; ++k) {
+    const auto &pl = h->plans[k];
+    he = vefk::launch_boundary(fp32, h->d_probs, h->d_io, k, pl.nbf, pl.nq, pl.p, nullptr, s);
+    if (he != hipSuccess) return hip_fail(h, he, "launch boundary sums");
   }
   h->last_stream = s;
   return VEF_OK;
@@ -577,6 +619,8 @@ int vef_plan_query(const vef_problem_desc *prob, vef_info *info) {
     info->pivoting = pl.nopivot ? 0 : 1;
     info->affine = pl.affine ? 1 : 0;
     info->n_solves = (long long)pl.ne * pl.nd;
+    info->schedule = VEF_SCHEDULE_AUTO;
+    info->kernel = -1;
   }
   return VEF_OK;
 }
@@ -593,6 +637,8 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->pivoting = pl.nopivot ? 0 : 1;
   info->affine = pl.affine ? 1 : 0;
   info->n_solves = (long long)pl.ne * pl.nd;
+  info->schedule = h->schedule;
+  info->kernel = mode_of(pl, h->schedule, h->pipeline_waves >= 0);
   return VEF_OK;
 }
 
@@ -613,7 +659,8 @@ int vef_sweep_check(vef_sweep_t *h) {
   int flags[4];
   he = hipMemcpy(flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost);
   if (he != hipSuccess) return hip_fail(h, he, "read status");
-  if (flags[2]) return set_err(h, VEF_ERR_INVALID, "zero pivot in a local system");
+  if (flags[2] & 2) return set_err(h, VEF_ERR_TIMEOUT, "a pipelined sweep wait exceeded its bound");
+  if (flags[2]) return set_err(h, VEF_ERR_INVALID, "non-finite unknown (singular local system)");
   return VEF_OK;
 }
 

@@ -29,6 +29,7 @@ struct KProb {
   const int32_t *order;       // [n_groups][ne] elements by (level, id)
   const int2 *desc_ef;        // [n_groups][ne] in order: (element, inflow mask | neighbour faces << 4)
   const int4 *desc_nb;        // [n_groups][ne] in order: neighbours (or -(boundary face + 1))
+  const uint32_t *desc_up;    // [n_groups][ne][4] in order: upwind level gap | position << 8 | face << 30
   int n_levels, n_groups;
 };
 
@@ -60,6 +61,10 @@ struct SweepLaunch {
   int count;
   int width;       // direction-resident: widest upwind level
   int max_levels;  // direction-resident: deepest level count (offsets staged in LDS)
+  int max_gap;     // pipelined: largest level gap of an upwind edge
+  int waves;       // pipelined: waves per work-group (0 = default)
+  int ring;        // pipelined: trace ring depth in levels (0 = default)
+  long long wait_spins;   // pipelined: bound of a wait, in polls of about 64 clocks each
   const KProb *probs;
   const KIO *io;
   const void *tables;

@@ -69,7 +69,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_boundary(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob, int nbf, int nq,
            int p, const int *__restrict__ stop) {
-  if (*stop) return;
+  if (stop && *stop) return;
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

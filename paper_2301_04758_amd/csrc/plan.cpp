@@ -244,7 +244,7 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   if (nq < d.p + 1 || nq > d.p + 3)
     return fail(err, VEF_ERR_INVALID, "nq=%lld outside p+1..p+3 (p=%lld)", nq, d.p);
   if (d.n_elem < 1 || d.n_cp < 4) return fail(err, VEF_ERR_INVALID, "n_elem=%lld n_cp=%lld", d.n_elem, d.n_cp);
-  if (d.n_elem > (1 << 26)) return fail(err, VEF_ERR_INVALID, "n_elem=%lld too large", d.n_elem);
+  if (d.n_elem > (1 << 22)) return fail(err, VEF_ERR_INVALID, "n_elem=%lld too large (max 4194304)", d.n_elem);
   if (d.n_dir < 1 || d.n_dir > kMaxDirs) return fail(err, VEF_ERR_INVALID, "n_dir=%lld out of range 1..1024", d.n_dir);
   if (!d.cp_xy || !d.elem_cp || !d.omega || !d.weight || !d.sigma_t || !d.sigma_s)
     return fail(err, VEF_ERR_INVALID, "NULL array in problem description");
@@ -289,10 +289,14 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   o.geo_f.assign((size_t)ne * 4 * nq * 2, 0.0);
   std::vector<double> X(2 * ncp_e);
   for (int e = 0; e < ne; ++e) {
+    // control points relative to the element's first one: the map derivatives
+    // (all that is evaluated here) are unchanged, and the sums no longer
+    // cancel coordinates of domain size down to element size
+    const double *c0 = d.cp_xy + 2 * (size_t)d.elem_cp[(size_t)e * ncp_e];
     for (int i = 0; i < ncp_e; ++i) {
       const int c = d.elem_cp[(size_t)e * ncp_e + i];
-      X[2 * i] = d.cp_xy[2 * c];
-      X[2 * i + 1] = d.cp_xy[2 * c + 1];
+      X[2 * i] = d.cp_xy[2 * c] - c0[0];
+      X[2 * i + 1] = d.cp_xy[2 * c + 1] - c0[1];
     }
     for (int qy = 0; qy < nq; ++qy)
       for (int qx = 0; qx < nq; ++qx) {
@@ -477,16 +481,30 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   // packed element descriptors in (level, id) order per class
   o.desc_ef.assign((size_t)o.n_groups * ne * 2, 0);
   o.desc_nb.assign((size_t)o.n_groups * ne * 4, 0);
+  o.desc_up.assign((size_t)o.n_groups * ne * 4, 0u);
   o.max_width = 1;
+  o.max_gap = 0;
+  std::vector<int> pos_in_level(ne);
   for (int g = 0; g < o.n_groups; ++g) {
     const uint8_t *mk = &o.mask[(size_t)o.group_rep[g] * ne];
     const int32_t *ord = &o.order[(size_t)g * ne];
+    const int32_t *lev = &o.level[(size_t)g * ne];
+    const int *lo = &o.level_off[(size_t)g * (o.n_levels + 1)];
+    for (int t = 0; t < ne; ++t) pos_in_level[ord[t]] = t - lo[lev[ord[t]]];
     for (int t = 0; t < ne; ++t) {
       const int e = ord[t];
       int flags = mk[e];
       for (int f = 0; f < 4; ++f) {
         flags |= (std::max<int>(o.nbr_face[4 * e + f], 0) & 3) << (4 + 2 * f);
-        o.desc_nb[((size_t)g * ne + t) * 4 + f] = o.nbr[4 * e + f];
+        const int nb = o.nbr[4 * e + f];
+        o.desc_nb[((size_t)g * ne + t) * 4 + f] = nb;
+        if (nb >= 0 && ((mk[e] >> f) & 1)) {
+          const int gap = lev[e] - lev[nb];
+          o.max_gap = std::max(o.max_gap, gap);
+          const uint32_t code = (uint32_t)std::min(gap, 255) | ((uint32_t)pos_in_level[nb] << 8) |
+                                ((uint32_t)(o.nbr_face[4 * e + f] & 3) << 30);
+          o.desc_up[((size_t)g * ne + t) * 4 + f] = code;
+        }
       }
       o.desc_ef[((size_t)g * ne + t) * 2] = e;
       o.desc_ef[((size_t)g * ne + t) * 2 + 1] = flags;
@@ -498,7 +516,10 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   }
 
   // straight faces: every control point of a face on the chord of its corners
+  // (to the rounding of the coordinates, whose size R bounds the error of
+  // the cross product together with the chord length)
   o.straight = true;
+  const double eps_geo = 256.0 * 2.220446049250313e-16;
   for (int e = 0; e < ne && o.straight && m > 1; ++e)
     for (int f = 0; f < 4 && o.straight; ++f) {
       int la, lb;
@@ -516,27 +537,40 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
         }
         const double *xi = d.cp_xy + 2 * (size_t)d.elem_cp[(size_t)e * ncp_e + li];
         const double cr = (xi[0] - xa[0]) * cy - (xi[1] - xa[1]) * cx;
-        if (std::fabs(cr) > 1e-13 * (cx * cx + cy * cy)) o.straight = false;
+        const double R = std::max(std::max(std::fabs(xa[0]), std::fabs(xa[1])),
+                                  std::max(std::fabs(xi[0]), std::fabs(xi[1])));
+        const double c2 = cx * cx + cy * cy;
+        if (std::fabs(cr) > 1e-13 * c2 + eps_geo * R * std::sqrt(c2)) o.straight = false;
       }
     }
   double smin = d.sigma_t[0];
   for (int e = 1; e < ne; ++e) smin = std::min(smin, d.sigma_t[e]);
   o.nopivot = o.straight && smin > 0.0;
 
-  // affine maps: J and adj(F) equal at every volume point (to rounding), and
-  // n ds along each face equal to the face chord
+  // affine maps: J and adj(F) equal at every volume point to rounding, and
+  // n ds along each face equal to the face chord.  The map derivatives are
+  // sums of control-point coordinates times O(1) basis derivatives, so their
+  // rounding error scales with the size of the coordinates (R), not with the
+  // element: on fine meshes far from the origin it is many times 1e-13 of
+  // the derivatives themselves.
   o.affine = o.straight;
   for (int e = 0; e < ne && o.affine; ++e) {
     const double *g0 = &o.geo_v[(size_t)e * o.Q * 5];
     const double w0 = T.gw[0] * T.gw[0];
-    double scale = 0.0;
+    double scale = 0.0, R = 0.0;
     for (int k = 1; k < 5; ++k) scale = std::max(scale, std::fabs(g0[k] / w0));
+    for (int li = 0; li < ncp_e; ++li) {
+      const double *x = d.cp_xy + 2 * (size_t)d.elem_cp[(size_t)e * ncp_e + li];
+      R = std::max(R, std::max(std::fabs(x[0]), std::fabs(x[1])));
+    }
+    const double tol_adj = 1e-13 * scale + eps_geo * R;
+    const double tol_J = 1e-13 * std::fabs(g0[0] / w0) + 2.0 * scale * eps_geo * R;
     for (int q = 1; q < o.Q && o.affine; ++q) {
       const double *gq = &o.geo_v[((size_t)e * o.Q + q) * 5];
       const double wq = T.gw[q % nq] * T.gw[q / nq];
-      if (std::fabs(gq[0] / wq - g0[0] / w0) > 1e-13 * std::fabs(g0[0] / w0)) o.affine = false;
+      if (std::fabs(gq[0] / wq - g0[0] / w0) > tol_J) o.affine = false;
       for (int k = 1; k < 5; ++k)
-        if (std::fabs(gq[k] / wq - g0[k] / w0) > 1e-13 * scale) o.affine = false;
+        if (std::fabs(gq[k] / wq - g0[k] / w0) > tol_adj) o.affine = false;
     }
   }
   if (o.affine) {

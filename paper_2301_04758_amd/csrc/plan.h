@@ -50,6 +50,10 @@ struct ProblemPlan {
   std::vector<int32_t> n_levels_g;  // [n_groups]
   std::vector<int32_t> desc_ef;     // [n_groups][ne][2] in order: element, inflow mask | nbr faces << 4
   std::vector<int32_t> desc_nb;     // [n_groups][ne][4] in order: neighbours
+  std::vector<uint32_t> desc_up;    // [n_groups][ne][4] in order, per inflow interior face: level gap
+                                    // (bits 0-7, 255 = far), upwind position in its level (8-29),
+                                    // upwind local face (30-31); 0 for other faces
+  int max_gap = 0;                  // largest level gap of an upwind edge
   int max_width = 1;                // widest level over classes
   bool straight = true;             // every face of the mesh is a straight segment
   bool nopivot = false;             // straight faces and sigma_t > 0 everywhere

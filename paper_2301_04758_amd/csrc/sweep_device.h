@@ -47,7 +47,12 @@ namespace {
 constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
 
 // Assembly/solve modes of a kernel variant.
-enum : int { MODE_GENERAL_PIVOT = 0, MODE_GENERAL_NOPIVOT = 1, MODE_AFFINE_NOPIVOT = 2 };
+enum : int {
+  MODE_GENERAL_PIVOT = 0,
+  MODE_GENERAL_NOPIVOT = 1,
+  MODE_AFFINE_NOPIVOT = 2,
+  MODE_AFFINE_PIPELINE = 3  // direction-resident schedule only, p <= 2
+};
 
 template <int P, int NQ>
 struct Shape {
@@ -403,7 +408,7 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
   if (row_ok) {
     T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
     out[my_k] = rhs;
-    if (!(rhs == rhs) || rhs - rhs != T(0)) atomicOr(status, 1);  // non-finite unknown
+    if (!__builtin_isfinite(rhs)) atomicOr(status, 1);  // non-finite unknown
   }
 }
 
@@ -550,7 +555,7 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
   if (row_ok) {
     T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
     out[r] = rhs;
-    if (!(rhs == rhs) || rhs - rhs != T(0)) atomicOr(status, 1);  // non-finite unknown
+    if (!__builtin_isfinite(rhs)) atomicOr(status, 1);  // non-finite unknown
   }
 }
 
@@ -695,6 +700,332 @@ k_sweep_dir(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-pipelined thread-per-solve schedule (affine elements, p <= 2,
+// pivot-free).  One work-group per (problem, direction) with W waves.  The
+// 64-element chunks of the upwind levels, in level order, are dealt
+// round-robin to the waves; lane l of a chunk solves one element.  The local
+// matrix and its LU factors do not depend on upwind data, so a wave assembles
+// and factors its next chunk while earlier levels are still being solved;
+// only "read the upwind traces, finish the right-hand side, two triangular
+// solves, write" waits for the levels below.  Chunks hand off through an LDS
+// counter of completed chunks; face traces go through an LDS ring of R levels
+// indexed by (level mod R, position in level, face).  An upwind element more
+// than R - 1 levels back is read from the angular flux in global memory,
+// written before its chunk's counter update.  Waits are bounded by a spin
+// count: on expiry the wave sets the status word and every wave leaves the
+// kernel.
+// ---------------------------------------------------------------------------
+
+constexpr int kPipeMaxWaves = 8;
+constexpr int kPipeRing = 4;  // default ring depth (levels)
+
+// Waves per work-group of a pipelined variant (every variant fits in 256
+// registers per lane, two waves per SIMD).
+template <int P, typename T>
+constexpr int pipe_max_waves() {
+  return kPipeMaxWaves;
+}
+
+template <int P, int NQ, typename T>
+__global__ void __launch_bounds__((pipe_max_waves<P, T>() * 64))
+k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
+             const KIO *__restrict__ io, const T *__restrict__ tables, int it,
+             const int *__restrict__ stop, int *__restrict__ status, int ring_levels, int ring_width,
+             int global_sync, long long wait_spins) {
+  using S = Shape<P, NQ>;
+  constexpr int P1 = S::P1, N = S::N, Q = S::Q;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  if (*stop) return;
+  const int W = blockDim.x >> 6;
+  const int2 tk = tasks[blockIdx.x];
+  const int prob = tk.x, d = tk.y;
+  const KProb &pb = probs[prob];
+  const KIO &pio = io[prob];
+  const int g = pb.dir_group[d];
+  const int nl = pb.n_levels_g[g];
+  const int ne = pb.ne;
+  T *ring = lds + S::TAB_A;  // [R][ring_width][4][P1]
+  int *lo = reinterpret_cast<int *>(ring + (size_t)ring_levels * ring_width * 4 * P1);
+  int *done = lo + nl + 1;   // chunks completed
+  int *abort_flag = done + 1;
+  for (int i = threadIdx.x; i < S::TAB_A; i += blockDim.x) lds[i] = tables[i];
+  const int32_t *lo_g = pb.level_off + (size_t)g * (pb.n_levels + 1);
+  for (int i = threadIdx.x; i <= nl; i += blockDim.x) lo[i] = lo_g[i];
+  if (threadIdx.x == 0) {
+    *done = 0;
+    *abort_flag = 0;
+  }
+  __syncthreads();  // the only work-group barrier
+
+  const int2 *dsc = pb.desc_ef + (size_t)g * ne;
+  const int4 *dnb = pb.desc_nb + (size_t)g * ne;
+  const uint4 *dup = reinterpret_cast<const uint4 *>(pb.desc_up) + (size_t)g * ne;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const T ox = static_cast<T>(pb.omega[2 * d]);
+  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
+  const double *phi = it == 0 ? pio.phi_in : pio.mom;
+  T *psi = static_cast<T *>(pio.psi);
+
+  // Tasks are the 64-element chunks of the levels in level order; wave w
+  // takes tasks w, w + W, ...  `before` counts the tasks of the levels below
+  // L: the task may start its critical part once that many have completed.
+  int L = 0, base = lo[0], before = 0;
+  auto advance = [&](int k) {
+    for (int i = 0; i < k && L < nl; ++i) {
+      base += 64;
+      if (base >= lo[L + 1]) {
+        before += (lo[L + 1] - lo[L] + 63) >> 6;
+        ++L;
+        base = L < nl ? lo[L] : 0;
+      }
+    }
+  };
+  advance(wave);
+  for (; L < nl; advance(W)) {
+    const int beg = lo[L], end = lo[L + 1];
+    {
+      const int t = base + lane;
+      const bool valid = t < end;
+      // The table reads are loop invariant; an opaque offset keeps the
+      // compiler from hoisting all of them (hundreds of values) out of the
+      // loop, which would not fit in registers.
+      int toff = 0;
+      asm volatile("" : "+v"(toff));
+      const T *Mt = lds + S::A_MT + toff;
+      const T *Gxt = lds + S::A_GX + toff;
+      const T *Gyt = lds + S::A_GY + toff;
+      const T *M1 = lds + S::A_M1 + toff;
+      const T *WV = lds + S::A_WV + toff;
+      const T *WL = lds + S::A_WL + toff;
+      // ---- prep: everything that does not depend on upwind values
+      int e = 0, flags = 0;
+      int nb[4] = {-1, -1, -1, -1};
+      uint32_t up[4] = {0u, 0u, 0u, 0u};
+      if (valid) {
+        const int2 ef = dsc[t];
+        const int4 n4 = dnb[t];
+        const uint4 u4 = dup[t];
+        e = ef.x;
+        flags = ef.y;
+        nb[0] = n4.x; nb[1] = n4.y; nb[2] = n4.z; nb[3] = n4.w;
+        up[0] = u4.x; up[1] = u4.y; up[2] = u4.z; up[3] = u4.w;
+      }
+      const T *ga = static_cast<const T *>(pb.geo_a) + (size_t)e * 16;
+      T gv[13];
+#pragma unroll
+      for (int k = 0; k < 13; ++k) gv[k] = ga[k];
+      const T st = static_cast<T>(pb.sig[2 * e]);
+      const T ss = static_cast<T>(pb.sig[2 * e + 1] * kInv4Pi);
+      T sj[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        T v = phi ? ss * static_cast<T>(phi[(size_t)e * N + j]) : T(0);
+        if (pio.q_iso) v += static_cast<T>(pio.q_iso[(size_t)e * N + j]);
+        sj[j] = v;
+      }
+      const T J = gv[0];
+      const T stJ = st * J;
+      const T gx = gv[1] * ox + gv[2] * oy;
+      const T gy = gv[3] * ox + gv[4] * oy;
+      T on[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) on[f] = ox * gv[5 + 2 * f] + oy * gv[6 + 2 * f];
+      // Right-hand side first: every branch of the prep happens while only
+      // these N values are live, the matrix below is straight-line code.
+      T b[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc += Mt[j * N + i] * sj[j];
+        b[i] = J * acc;
+      }
+      if (pio.q_dir) {
+        const double *qd = pio.q_dir + ((size_t)d * ne + e) * Q;
+        T qv[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) qv[q] = static_cast<T>(qd[q]);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          T acc = T(0);
+#pragma unroll
+          for (int q = 0; q < Q; ++q) acc += WV[q * N + i] * qv[q];
+          b[i] += J * acc;
+        }
+      }
+      if (pio.psi_bc) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          if (!(valid && ((flags >> f) & 1) && nb[f] < 0)) continue;
+          const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-nb[f] - 1)) * NQ;
+          T bq[NQ];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) bq[q] = static_cast<T>(bc[q]);
+#pragma unroll
+          for (int a = 0; a < P1; ++a) {
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc += WL[q * P1 + a] * bq[q];
+            b[face_node<P>(f, a)] -= on[f] * acc;
+          }
+        }
+      }
+      // Matrix: reference matrices scaled by the element's constants, plus
+      // on * M1 on the outflow faces (a select, not a branch: a divergent
+      // branch around the update would copy the whole matrix).
+      T cf[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) cf[f] = ((flags >> f) & 1) ? T(0) : on[f];
+      T A[N][N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+          A[i][j] = stJ * Mt[j * N + i] - gx * Gxt[j * N + i] - gy * Gyt[j * N + i];
+        __builtin_amdgcn_sched_barrier(0);  // keep table reads row by row (register pressure)
+      }
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int a = 0; a < P1; ++a)
+#pragma unroll
+          for (int c = 0; c < P1; ++c) A[face_node<P>(f, a)][face_node<P>(f, c)] += cf[f] * M1[a * P1 + c];
+      // LU factors in place (natural order), reciprocal pivots kept
+      T inv[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        inv[k] = recip(A[k][k]);
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+          A[i][k] *= inv[k];
+#pragma unroll
+          for (int j = k + 1; j < N; ++j) A[i][j] -= A[i][k] * A[k][j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // Keep the factorisation ahead of the wait: without these register
+      // dependencies the compiler may sink the arithmetic past the wait loop
+      // (it has no memory effects), which would put it on the critical path.
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) asm volatile("" : "+v"(A[i][j]));
+        asm volatile("" : "+v"(inv[i]));
+        asm volatile("" : "+v"(b[i]));
+      }
+
+      // ---- wait for every task of the levels below L
+      if (L > 0) {
+        long long spins = 0;
+        while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < before) {
+          if ((++spins & 63) == 0) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
+            if (spins > wait_spins) {
+              __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              if (lane == 0) atomicOr(status, 2);
+              return;
+            }
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+
+      // ---- critical: upwind traces, substitution, outputs
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if (!valid || !((flags >> f) & 1) || nb[f] < 0) continue;
+        const uint32_t u = up[f];
+        const int gap = (int)(u & 255u);
+        const int pos_up = (int)((u >> 8) & 0x3FFFFFu);
+        const int f_up = (int)(u >> 30);
+        T tr[P1];
+        if (gap < ring_levels) {
+          const T *src = ring + ((size_t)(((L - gap) % ring_levels) * ring_width + pos_up) * 4 + f_up) * P1;
+#pragma unroll
+          for (int c = 0; c < P1; ++c) tr[c] = src[P - c];
+        } else {
+          const T *src = psi + ((size_t)d * ne + nb[f]) * N;
+#pragma unroll
+          for (int c = 0; c < P1; ++c) tr[c] = src[face_node<P>(f_up, P - c)];
+        }
+#pragma unroll
+        for (int a = 0; a < P1; ++a) {
+          T acc = T(0);
+#pragma unroll
+          for (int c = 0; c < P1; ++c) acc += M1[a * P1 + c] * tr[c];
+          b[face_node<P>(f, a)] -= on[f] * acc;
+        }
+      }
+      // forward (unit lower) and backward substitution
+#pragma unroll
+      for (int i = 1; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < i; ++k) b[i] -= A[i][k] * b[k];
+#pragma unroll
+      for (int i = N - 1; i >= 0; --i) {
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) b[i] -= A[i][j] * b[j];
+        b[i] *= inv[i];
+      }
+      if (valid) {
+        T *out = psi + ((size_t)d * ne + e) * N;
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          out[i] = b[i];
+          bad |= !__builtin_isfinite(b[i]);  // a class test: "x - x != 0" may be contracted
+        }
+        if (bad) atomicOr(status, 1);
+        // outflow traces for the levels below
+        T *dst = ring + ((size_t)((L % ring_levels) * ring_width + (t - beg)) * 4) * P1;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          if (!((flags >> f) & 1))
+#pragma unroll
+            for (int c = 0; c < P1; ++c) dst[f * P1 + c] = b[face_node<P>(f, c)];
+      }
+    }
+    // ---- task complete: publish (ring writes by this wave, and the global
+    // stores when some consumer reads them).  Tasks of level L + 1 cannot
+    // finish before every task of level L, so the count of completed tasks
+    // reaches `before` exactly when the levels below L are complete.
+    if (global_sync) __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt, lgkmcnt all zero
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+template <int P, int NQ, typename T, int MODE>
+hipError_t launch_dir_t(const SweepLaunch &L);
+
+template <int P, int NQ, typename T>
+hipError_t launch_pipe_t(const SweepLaunch &L) {
+  if constexpr (P > 2) {
+    return hipErrorInvalidValue;
+  } else {
+    if (L.count == 0) return hipSuccess;
+    using S = Shape<P, NQ>;
+    constexpr int maxw = pipe_max_waves<P, T>();
+    const int waves = L.waves > 0 ? (L.waves > maxw ? maxw : L.waves) : maxw;
+    const size_t ring_bytes_per_level = (size_t)L.width * 4 * S::P1 * sizeof(T);
+    const size_t fixed = sizeof(T) * S::TAB_A + sizeof(int) * ((size_t)L.max_levels + 3);
+    int R = L.ring > 0 ? L.ring : kPipeRing;
+    while (R > 1 && fixed + R * ring_bytes_per_level > L.lds_max) --R;
+    // a level too wide for even one ring slot: the row-per-lane kernel
+    if (fixed + R * ring_bytes_per_level > L.lds_max) return launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L);
+    const int global_sync = (L.max_gap >= R) ? 1 : 0;
+    const size_t bytes = fixed + R * ring_bytes_per_level;
+    hipLaunchKernelGGL((k_sweep_pipe<P, NQ, T>), dim3(L.count), dim3(waves * 64), bytes, L.stream, L.list, L.probs,
+                       L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status, R, L.width, global_sync,
+                       L.wait_spins);
+    return hipGetLastError();
+  }
+}
+
 // Largest multiple of 64 threads <= want whose LDS fits in lds_max bytes.
 template <int P, int NQ, int MODE>
 int fit_block(bool fp32, int want, size_t lds_max, int extra_ints, size_t *bytes) {
@@ -750,6 +1081,8 @@ hipError_t launch_mode(const SweepLaunch &L) {
                  : launch_level_t<P, NQ, T, MODE_GENERAL_NOPIVOT>(L);
     case MODE_AFFINE_NOPIVOT:
       return DIR ? launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L) : launch_level_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L);
+    case MODE_AFFINE_PIPELINE:
+      return DIR ? launch_pipe_t<P, NQ, T>(L) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

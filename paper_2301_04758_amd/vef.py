@@ -31,6 +31,10 @@ VEF_SCHEDULE_AUTO = 0
 VEF_LEVEL_SYNC = 1
 VEF_DIR_RESIDENT = 2
 SCHEDULES = {"auto": VEF_SCHEDULE_AUTO, "level": VEF_LEVEL_SYNC, "dir": VEF_DIR_RESIDENT}
+SCHEDULE_NAMES = {VEF_LEVEL_SYNC: "level_sync", VEF_DIR_RESIDENT: "dir_resident"}
+VEF_KERNEL_PIVOT, VEF_KERNEL_NOPIVOT, VEF_KERNEL_AFFINE, VEF_KERNEL_AFFINE_PIPELINE = 0, 1, 2, 3
+KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KERNEL_AFFINE: "affine",
+                VEF_KERNEL_AFFINE_PIPELINE: "affine_pipeline"}
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
@@ -46,7 +50,7 @@ class vef_problem_desc(C.Structure):
 
 class vef_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("schedule", C.c_int), ("block", C.c_int), ("timing", C.c_int),
-                ("reserved", C.c_int * 4)]
+                ("pipeline_waves", C.c_int), ("pipeline_ring", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class vef_problem_io(C.Structure):
@@ -68,7 +72,8 @@ class vef_moment_io(C.Structure):
 
 class vef_info(C.Structure):
     _fields_ = [("n", C.c_int), ("nq", C.c_int), ("Q", C.c_int), ("n_bf", C.c_int), ("n_levels", C.c_int),
-                ("n_groups", C.c_int), ("pivoting", C.c_int), ("affine", C.c_int), ("n_solves", C.c_longlong)]
+                ("n_groups", C.c_int), ("pivoting", C.c_int), ("affine", C.c_int), ("n_solves", C.c_longlong),
+                ("schedule", C.c_int), ("kernel", C.c_int)]
 
 
 def _load():
@@ -150,10 +155,11 @@ def vef_plan_query(problem) -> dict:
 
 
 def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
-                     block: int = 0, timing: bool = False) -> int:
+                     block: int = 0, timing: bool = False, pipeline_waves: int = 0,
+                     pipeline_ring: int = 0) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
-    opt = vef_options(precision, schedule, block, 1 if timing else 0)
+    opt = vef_options(precision, schedule, block, 1 if timing else 0, pipeline_waves, pipeline_ring)
     h = C.c_void_p()
     rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))
     if rc != VEF_OK:
@@ -224,7 +230,8 @@ def vef_sweep_check(h: int):
 class Sweep:
     """Owns one handle; allocates device buffers with torch for convenience."""
 
-    def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto"):
+    def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto",
+                 pipeline_waves=0, pipeline_ring=0):
         import torch
         self.torch = torch
         self.problems = list(problems)
@@ -232,7 +239,7 @@ class Sweep:
         self.device = torch.device("cuda" if device is None else device)
         with torch.cuda.device(self.device):
             self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64,
-                                      SCHEDULES[schedule], block, timing)
+                                      SCHEDULES[schedule], block, timing, pipeline_waves, pipeline_ring)
         self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
 
     def close(self):

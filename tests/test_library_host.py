@@ -151,3 +151,25 @@ def test_affine_classification():
     q = P.Problem("trap", 2, 1, cp, ec, c1.omega, c1.weight, np.ones(36), np.zeros(36))
     i = vef.vef_plan_query(q)
     assert i["affine"] == 0 and i["pivoting"] == 0
+
+
+@pytest.mark.parametrize("n,m,shift", [(1024, 1, 0.0), (512, 2, 0.0), (300, 1, 1000.0)])
+def test_affine_classification_fine_meshes(n, m, shift):
+    """Rounding of the geometry grows with coordinate size / element size:
+    fine uniform meshes, also far from the origin, stay affine; a corner
+    moved by 1e-9 of the element size (1e-7 far from the origin, where
+    1e-9 is within a few ulps of the coordinates) makes it non-affine."""
+    vef = _vef()
+    cp, ec = P.quad_mesh(n, n, m)
+    cp = cp + shift
+    om, wt = P.level_symmetric_2d(4)
+    ne = n * n
+    q = P.Problem("fine", 1, m, cp, ec, om, wt, np.ones(ne), np.zeros(ne))
+    i = vef.vef_plan_query(q)
+    assert i["affine"] == 1 and i["pivoting"] == 0
+    if m == 1:
+        cp2 = cp.copy()
+        k = (n + 1) * (n // 2) + n // 2  # an interior vertex
+        cp2[k, 0] += (1e-9 if shift == 0 else 1e-7) / n
+        i2 = vef.vef_plan_query(P.Problem("fine", 1, m, cp2, ec, om, wt, np.ones(ne), np.zeros(ne)))
+        assert i2["affine"] == 0
