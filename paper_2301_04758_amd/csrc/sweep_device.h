@@ -99,6 +99,15 @@ __host__ __device__ constexpr size_t lds_bytes(int tab, int slot_area, int slots
 }
 
 // node index of position c (counter-clockwise) along face f
+// Global-memory view of a generic pointer.  Accesses through it compile to
+// global_* instructions, which count only on vmcnt; flat accesses also count
+// on lgkmcnt, so every wait for LDS results would wait for them too.
+#define VEF_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ VEF_GLOBAL T *gmem(T *p) {
+  return (VEF_GLOBAL T *)p;
+}
+
 template <int P>
 __device__ __forceinline__ int face_node(int f, int c) {
   constexpr int P1 = P + 1;
@@ -759,15 +768,17 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
   }
   __syncthreads();  // the only work-group barrier
 
-  const int2 *dsc = pb.desc_ef + (size_t)g * ne;
-  const int4 *dnb = pb.desc_nb + (size_t)g * ne;
-  const uint4 *dup = reinterpret_cast<const uint4 *>(pb.desc_up) + (size_t)g * ne;
+  const VEF_GLOBAL int *dsc = gmem(reinterpret_cast<const int *>(pb.desc_ef + (size_t)g * ne));
+  const VEF_GLOBAL int *dnb = gmem(reinterpret_cast<const int *>(pb.desc_nb + (size_t)g * ne));
+  const VEF_GLOBAL uint32_t *dup = gmem(pb.desc_up + (size_t)g * ne * 4);
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const T ox = static_cast<T>(pb.omega[2 * d]);
   const T oy = static_cast<T>(pb.omega[2 * d + 1]);
-  const double *phi = it == 0 ? pio.phi_in : pio.mom;
-  T *psi = static_cast<T *>(pio.psi);
+  const VEF_GLOBAL double *phi = gmem(it == 0 ? pio.phi_in : pio.mom);
+  const VEF_GLOBAL double *q_iso = gmem(pio.q_iso);
+  VEF_GLOBAL T *psi = gmem(static_cast<T *>(pio.psi));
+  const VEF_GLOBAL double *sig = gmem(pb.sig);
 
   // Tasks are the 64-element chunks of the levels in level order; wave w
   // takes tasks w, w + W, ...  `before` counts the tasks of the levels below
@@ -805,27 +816,41 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       int nb[4] = {-1, -1, -1, -1};
       uint32_t up[4] = {0u, 0u, 0u, 0u};
       if (valid) {
-        const int2 ef = dsc[t];
-        const int4 n4 = dnb[t];
-        const uint4 u4 = dup[t];
-        e = ef.x;
-        flags = ef.y;
-        nb[0] = n4.x; nb[1] = n4.y; nb[2] = n4.z; nb[3] = n4.w;
-        up[0] = u4.x; up[1] = u4.y; up[2] = u4.z; up[3] = u4.w;
+        e = dsc[2 * t];
+        flags = dsc[2 * t + 1];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          nb[f] = dnb[4 * t + f];
+          up[f] = dup[4 * t + f];
+        }
       }
-      const T *ga = static_cast<const T *>(pb.geo_a) + (size_t)e * 16;
+      const VEF_GLOBAL T *ga = gmem(static_cast<const T *>(pb.geo_a) + (size_t)e * 16);
       T gv[13];
 #pragma unroll
       for (int k = 0; k < 13; ++k) gv[k] = ga[k];
-      const T st = static_cast<T>(pb.sig[2 * e]);
-      const T ss = static_cast<T>(pb.sig[2 * e + 1] * kInv4Pi);
+      const T st = static_cast<T>(sig[2 * e]);
+      const T ss = static_cast<T>(sig[2 * e + 1] * kInv4Pi);
+      // nodal source s_j = sigma_s / (4 pi) phi_j + q_j.  One branch per
+      // array and all N loads of an array issued together (a branch inside
+      // the node loop would make every load a separate round trip).
+      double pv[N], qv[N];
+      if (phi) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) pv[j] = phi[(size_t)e * N + j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) pv[j] = 0.0;
+      }
+      if (q_iso) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) qv[j] = q_iso[(size_t)e * N + j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) qv[j] = 0.0;
+      }
       T sj[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        T v = phi ? ss * static_cast<T>(phi[(size_t)e * N + j]) : T(0);
-        if (pio.q_iso) v += static_cast<T>(pio.q_iso[(size_t)e * N + j]);
-        sj[j] = v;
-      }
+      for (int j = 0; j < N; ++j) sj[j] = ss * static_cast<T>(pv[j]) + static_cast<T>(qv[j]);
       const T J = gv[0];
       const T stJ = st * J;
       const T gx = gv[1] * ox + gv[2] * oy;
@@ -844,7 +869,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
         b[i] = J * acc;
       }
       if (pio.q_dir) {
-        const double *qd = pio.q_dir + ((size_t)d * ne + e) * Q;
+        const VEF_GLOBAL double *qd = gmem(pio.q_dir + ((size_t)d * ne + e) * Q);
         T qv[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) qv[q] = static_cast<T>(qd[q]);
@@ -860,7 +885,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           if (!(valid && ((flags >> f) & 1) && nb[f] < 0)) continue;
-          const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-nb[f] - 1)) * NQ;
+          const VEF_GLOBAL double *bc = gmem(pio.psi_bc + ((size_t)d * pb.nbf + (-nb[f] - 1)) * NQ);
           T bq[NQ];
 #pragma unroll
           for (int q = 0; q < NQ; ++q) bq[q] = static_cast<T>(bc[q]);
@@ -933,7 +958,11 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
         }
       }
 
-      // ---- critical: upwind traces, substitution, outputs
+      // ---- critical: upwind traces, substitution, outputs.  The wave runs
+      // it at raised issue priority: the other waves of its SIMD are doing
+      // their (long, independent) prep, which would otherwise take every
+      // second issue slot of this dependent chain.
+      __builtin_amdgcn_s_setprio(3);
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         if (!valid || !((flags >> f) & 1) || nb[f] < 0) continue;
@@ -947,7 +976,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
 #pragma unroll
           for (int c = 0; c < P1; ++c) tr[c] = src[P - c];
         } else {
-          const T *src = psi + ((size_t)d * ne + nb[f]) * N;
+          const VEF_GLOBAL T *src = psi + ((size_t)d * ne + nb[f]) * N;
 #pragma unroll
           for (int c = 0; c < P1; ++c) tr[c] = src[face_node<P>(f_up, P - c)];
         }
@@ -971,7 +1000,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
         b[i] *= inv[i];
       }
       if (valid) {
-        T *out = psi + ((size_t)d * ne + e) * N;
+        VEF_GLOBAL T *out = psi + ((size_t)d * ne + e) * N;
         bool bad = false;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -996,6 +1025,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __builtin_amdgcn_s_setprio(0);
   }
 }
 
