@@ -107,7 +107,8 @@ typedef struct {
                     0 = default 8, 1..8; -1 = use the row-per-lane
                     kernel instead) */
   int pipeline_ring;  /* levels of face traces the pipelined kernel keeps in
-                    LDS (0 = default 4, 1..4; fewer when LDS is short);
+                    LDS (0 = default 4; 1..4, rounded down to a power of
+                    two; fewer when LDS is short);
                     upwind elements further back are read from the angular
                     flux in global memory */
   int reserved[2];

@@ -755,7 +755,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
   const int g = pb.dir_group[d];
   const int nl = pb.n_levels_g[g];
   const int ne = pb.ne;
-  T *ring = lds + S::TAB_A;  // [R][ring_width][4][P1]
+  T *ring = lds + S::TAB_A;  // [R][4][P1][ring_width]: position fastest (no bank conflicts)
   int *lo = reinterpret_cast<int *>(ring + (size_t)ring_levels * ring_width * 4 * P1);
   int *done = lo + nl + 1;   // chunks completed
   int *abort_flag = done + 1;
@@ -972,9 +972,9 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
         const int f_up = (int)(u >> 30);
         T tr[P1];
         if (gap < ring_levels) {
-          const T *src = ring + ((size_t)(((L - gap) % ring_levels) * ring_width + pos_up) * 4 + f_up) * P1;
+          const T *src = ring + (size_t)((L - gap) & (ring_levels - 1)) * 4 * P1 * ring_width + pos_up;
 #pragma unroll
-          for (int c = 0; c < P1; ++c) tr[c] = src[P - c];
+          for (int c = 0; c < P1; ++c) tr[c] = src[(size_t)(f_up * P1 + P - c) * ring_width];
         } else {
           const VEF_GLOBAL T *src = psi + ((size_t)d * ne + nb[f]) * N;
 #pragma unroll
@@ -999,33 +999,41 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
         for (int j = i + 1; j < N; ++j) b[i] -= A[i][j] * b[j];
         b[i] *= inv[i];
       }
+      // outflow traces for the levels below
       if (valid) {
-        VEF_GLOBAL T *out = psi + ((size_t)d * ne + e) * N;
-        bool bad = false;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          out[i] = b[i];
-          bad |= !__builtin_isfinite(b[i]);  // a class test: "x - x != 0" may be contracted
-        }
-        if (bad) atomicOr(status, 1);
-        // outflow traces for the levels below
-        T *dst = ring + ((size_t)((L % ring_levels) * ring_width + (t - beg)) * 4) * P1;
+        T *dst = ring + (size_t)(L & (ring_levels - 1)) * 4 * P1 * ring_width + (t - beg);
 #pragma unroll
         for (int f = 0; f < 4; ++f)
           if (!((flags >> f) & 1))
 #pragma unroll
-            for (int c = 0; c < P1; ++c) dst[f * P1 + c] = b[face_node<P>(f, c)];
+            for (int c = 0; c < P1; ++c) dst[(size_t)(f * P1 + c) * ring_width] = b[face_node<P>(f, c)];
+      }
+      VEF_GLOBAL T *out = psi + ((size_t)d * ne + e) * N;
+      if (global_sync) {  // some consumer reads fluxes from global memory: store before publishing
+        if (valid) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) out[i] = b[i];
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt, lgkmcnt all zero
+      }
+      // ---- chunk complete: publish.  Chunks of level L + 1 cannot finish
+      // before every chunk of level L, so the count of completed chunks
+      // reaches `before` exactly when the levels below L are complete.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __builtin_amdgcn_s_setprio(0);
+      // the angular flux, off the critical path when only LDS hands off
+      if (valid) {
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          if (!global_sync) out[i] = b[i];
+          bad |= !__builtin_isfinite(b[i]);  // a class test: "x - x != 0" may be contracted
+        }
+        if (bad) atomicOr(status, 1);
       }
     }
-    // ---- task complete: publish (ring writes by this wave, and the global
-    // stores when some consumer reads them).  Tasks of level L + 1 cannot
-    // finish before every task of level L, so the count of completed tasks
-    // reaches `before` exactly when the levels below L are complete.
-    if (global_sync) __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt, lgkmcnt all zero
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __builtin_amdgcn_s_setprio(0);
   }
 }
 
@@ -1044,7 +1052,8 @@ hipError_t launch_pipe_t(const SweepLaunch &L) {
     const size_t ring_bytes_per_level = (size_t)L.width * 4 * S::P1 * sizeof(T);
     const size_t fixed = sizeof(T) * S::TAB_A + sizeof(int) * ((size_t)L.max_levels + 3);
     int R = L.ring > 0 ? L.ring : kPipeRing;
-    while (R > 1 && fixed + R * ring_bytes_per_level > L.lds_max) --R;
+    R = R >= 4 ? 4 : (R >= 2 ? 2 : 1);  // a power of two: the slot of a level is a mask
+    while (R > 1 && fixed + R * ring_bytes_per_level > L.lds_max) R >>= 1;
     // a level too wide for even one ring slot: the row-per-lane kernel
     if (fixed + R * ring_bytes_per_level > L.lds_max) return launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L);
     const int global_sync = (L.max_gap >= R) ? 1 : 0;
