@@ -90,10 +90,36 @@ def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto
     sw.check()
     out = dict(seconds=t1 - t0, sweep_ms=sweep_ms, launches=launches,
                schedule=vef.SCHEDULE_NAMES[sw.info[0]["schedule"]], kernel=sw.info[0]["kernel"],
+               n_levels=sw.info[0]["n_levels"],
                phi=[b["mom"][0].double().cpu().numpy() for b in io],
                resid=[b["resid"].cpu().numpy() for b in io])
     sw.close()
     return out
+
+
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                       "k_sweep_pipe_c2_64x64_p2_S8_fp64.md")
+KERNEL_SOURCES = ["paper_2301_04758_amd/csrc/sweep_device.h", "paper_2301_04758_amd/csrc/sweep_p2.hip",
+                  "paper_2301_04758_amd/csrc/kernels.h"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the C2 pipelined kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy kernel),
+    or None when the kernel differs or its sources changed since then."""
+    import hashlib
+    import re
+    if kernel != "k_sweep_pipe<2, 3, double>" or not os.path.exists(PROFILE):
+        return None
+    text = open(PROFILE).read()
+    m = re.search(r"traffic_bytes_per_launch=([0-9.e+]+) kernel_sources_sha256_16=([0-9a-f]+)", text)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(root, f), "rb").read())
+    return float(m.group(1)) if h.hexdigest()[:16] == m.group(2) else None
 
 
 def kernel_name(g, pr):
@@ -103,6 +129,63 @@ def kernel_name(g, pr):
         return "k_sweep_pipe<%d, %d, double>" % (pr.p, nq)
     kind = "dir" if g["schedule"] == "dir_resident" else "level"
     return "k_sweep_%s<%d, %d, double, %d>" % (kind, pr.p, nq, g["kernel"])
+
+
+def c4_batched(reps=3):
+    """The 64-problem batch: plain FP64 level-synchronous sweeps one problem at
+    a time, against all 64 in one FP32-local handle whose run is captured in a
+    HIP graph and replayed.  Error: rel_inf of phi against the FP64 runs."""
+    import numpy as np
+    import torch
+    from paper_2301_04758_amd import problems as P
+    from paper_2301_04758_amd import vef
+    probs, _ = P.make_config("c4")
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    t_plain, phi64 = 0.0, []
+    for pr in probs:
+        sw = vef.Sweep([pr], precision="fp64", schedule="level")
+        io = sw.buffers(n_iter=1, store_psi=False)
+        sw.run(io, n_iter=1)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            sw.run(io, n_iter=1)
+        b.record()
+        torch.cuda.synchronize()
+        sw.check()
+        t_plain += a.elapsed_time(b) / reps
+        phi64.append(io[0]["mom"][0].cpu().numpy())
+        sw.close()
+        del io
+    sw = vef.Sweep(probs, precision="fp32")
+    io = sw.buffers(n_iter=1, store_psi=False)
+    sw.run(io, n_iter=1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sw.run(io, n_iter=1)
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    sw.check()
+    t_batch = a.elapsed_time(b) / reps
+    err = max(float(np.abs(io[k]["mom"][0].cpu().numpy() - phi64[k]).max() / np.abs(phi64[k]).max())
+              for k in range(len(probs)))
+    solves = sum(p.n_elem * p.n_dir for p in probs)
+    out = {"problems": len(probs), "solves_per_sweep": solves, "plain_fp64_one_by_one_ms": t_plain,
+           "batched_fp32_graph_ms": t_batch, "schedule": vef.SCHEDULE_NAMES[sw.info[0]["schedule"]],
+           "rel_inf_phi_vs_fp64": err, "within_1e-5": err <= 1e-5,
+           "speedup": (t_plain / t_batch) if err <= 1e-5 else None,
+           "batched_solves_per_s": solves / (t_batch * 1e-3)}
+    del g
+    sw.close()
+    return out
 
 
 def cpu_baseline(probs, iters):
@@ -127,8 +210,9 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir"])
+    ap.add_argument("--no-c4", action="store_true", help="skip the 64-problem batched FP32 vs one-by-one FP64 block")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (three times), the reference kernel "
                          "for scaling HBM byte counters")
@@ -158,9 +242,17 @@ def main():
     avg_launch_s = g64["sweep_ms"] * 1e-3 / launches
     solves_per_launch = solves_per_step * args.steps / launches
     achieved_tf = F * solves_per_launch / avg_launch_s / 1e12
+    kname = kernel_name(g64, pr)
+    sweeps_per_launch = solves_per_launch / sum(p.n_elem * p.n_dir for p in probs)
+    t_bw = B * solves_per_launch / (HBM_PEAK_GBS * 1e9)
+    t_flop = F * solves_per_launch / (FP64_PEAK_TFLOPS * 1e12)
     roofline = {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
-                "kernel": kernel_name(g64, pr), "avg_launch_us": avg_launch_s * 1e6,
+                "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": measured_traffic(kname),
+                "kernel": kname, "avg_launch_us": avg_launch_s * 1e6,
+                "levels_per_sweep": g64["n_levels"],
+                "us_per_level": avg_launch_s * 1e6 / (g64["n_levels"] * sweeps_per_launch),
+                "lower_bounds_us": {"hbm": t_bw * 1e6, "fp64_alu": t_flop * 1e6},
+                "binding": "critical path: %d dependent upwind levels per sweep" % g64["n_levels"],
                 "launches_per_step": launches / args.steps,
                 "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
                 "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
@@ -184,6 +276,8 @@ def main():
         result["fp32_local"] = {"ms_per_step": ms32, "value": solves_per_step / (ms32 * 1e-3),
                                 "speedup_vs_fp64": ms_step / ms32,
                                 "rel_inf_phi_vs_fp64_path": err, "within_1e-5": err <= 1e-5}
+    if not args.no_c4:
+        result["c4_batched_fp32_vs_plain_fp64"] = c4_batched()
     if args.copy_calibration:
         n = 256 << 20
         src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
