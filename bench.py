@@ -61,13 +61,14 @@ def describe(name, probs, run):
     return "%s: %d problems, first %dx%d p=%d n_dir=%d" % (name, len(probs), pr.nx, pr.ny, pr.p, pr.n_dir)
 
 
-def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto"):
+def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto", tune=True):
     import torch
     from paper_2301_04758_amd import vef
     sw = vef.Sweep(probs, precision=precision, timing=timing, schedule=schedule)
     io = sw.buffers(n_iter=n_iter, store_psi=True)
     mio = sw.moment_buffers(io)
     stream = torch.cuda.current_stream()
+    tuned = sw.autotune(io, n_iter=n_iter, reps=1, stream=stream) if tune and schedule == "auto" else None
 
     def step():
         sw.run(io, n_iter=n_iter, stream=stream)
@@ -90,7 +91,7 @@ def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto
     sw.check()
     out = dict(seconds=t1 - t0, sweep_ms=sweep_ms, launches=launches,
                schedule=vef.SCHEDULE_NAMES[sw.info[0]["schedule"]], kernel=sw.info[0]["kernel"],
-               n_levels=sw.info[0]["n_levels"],
+               n_levels=sw.info[0]["n_levels"], tuned=tuned,
                phi=[b["mom"][0].double().cpu().numpy() for b in io],
                resid=[b["resid"].cpu().numpy() for b in io])
     sw.close()
@@ -160,6 +161,7 @@ def c4_batched(reps=3):
         del io
     sw = vef.Sweep(probs, precision="fp32")
     io = sw.buffers(n_iter=1, store_psi=False)
+    tuned = sw.autotune(io, n_iter=1, reps=2)
     sw.run(io, n_iter=1)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -180,6 +182,7 @@ def c4_batched(reps=3):
     solves = sum(p.n_elem * p.n_dir for p in probs)
     out = {"problems": len(probs), "solves_per_sweep": solves, "plain_fp64_one_by_one_ms": t_plain,
            "batched_fp32_graph_ms": t_batch, "schedule": vef.SCHEDULE_NAMES[sw.info[0]["schedule"]],
+           "tuning": tuned,
            "rel_inf_phi_vs_fp64": err, "within_1e-5": err <= 1e-5,
            "speedup": (t_plain / t_batch) if err <= 1e-5 else None,
            "batched_solves_per_s": solves / (t_batch * 1e-3)}
@@ -211,7 +214,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=30)
-    ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir"],
+                    help="auto: the library's autotuner picks schedule and kernel before the timed steps")
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-problem batched FP32 vs one-by-one FP64 block")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (three times), the reference kernel "
@@ -264,7 +268,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": describe(args.workload, probs, run), "n_elem": pr.n_elem, "p": pr.p,
                    "n_dir": pr.n_dir, "sweeps_per_step": n_iter,
-                   "schedule": ("auto: " if args.schedule == "auto" else "") + g64["schedule"],
+                   "schedule": ("autotuned: " if g64["tuned"] else "") + g64["schedule"],
+                   "tuning": g64["tuned"],
                    "precision": "fp64"},
         "hbm_gbs_algorithmic": hbm_gbs,
         "roofline": roofline,

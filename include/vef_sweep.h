@@ -215,6 +215,29 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info);
  * [n_bf][2]. */
 int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out);
 
+/* Result of vef_sweep_autotune. */
+typedef struct {
+  int schedule;       /* chosen: VEF_LEVEL_SYNC or VEF_DIR_RESIDENT */
+  int pipeline_waves; /* chosen waves of the pipelined kernel; -1 = row-per-lane kernel */
+  int block;          /* chosen work-group size of the level-synchronous kernels */
+  int n_candidates;   /* configurations timed */
+  double best_ms;     /* one run of the given arguments with the choice (mean of reps) */
+  double before_ms;   /* the same with the configuration the handle had before */
+} vef_tune_result;
+
+/* Same operation as vef_sweep_run (the sweep of Sec. 5 with the moments of
+ * Eq. eq:vef_disc), run repeatedly to choose how it is scheduled: the
+ * level-synchronous kernels with 128 or 256 threads per work-group, the
+ * direction-resident row-per-lane kernel, and (when some problem has affine
+ * elements of degree <= 2) the pipelined kernel with 8, 6 or 4 waves.  Each
+ * candidate runs once untimed and then reps (1..1000) times between HIP
+ * events on stream; the fastest is kept by the handle for later runs
+ * (results differ between kernels only by rounding).  Blocking.  The output
+ * buffers of a hold the last candidate's results.  out may be NULL.  Errors:
+ * as vef_sweep_run and vef_sweep_check; the handle then keeps its previous
+ * configuration. */
+int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int reps, vef_tune_result *out);
+
 /* Synchronise the handle's last stream and return the device status word:
  * VEF_OK; VEF_ERR_INVALID when a local solve produced a non-finite unknown
  * (singular or overflowing local system); VEF_ERR_TIMEOUT when a bounded

@@ -81,7 +81,8 @@ struct vef_sweep {
   int2 *d_solves = nullptr;
   std::vector<std::vector<LevelLaunch>> levels;
   int2 *d_dir_tasks = nullptr;
-  std::vector<DirLaunch> dir_launches;
+  std::vector<DirLaunch> dir_rows;  // direction-resident, row-per-lane kernels only
+  std::vector<DirLaunch> dir_pipe;  // direction-resident, pipelined kernel where it applies
   std::vector<void *> psi_internal;   // per problem, allocated on first need
   std::vector<double *> resid_scratch;
   std::vector<int> resid_cap;
@@ -323,19 +324,17 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   // level lists: level -> variant (p, nq) -> problem -> class -> element -> direction
   int max_levels = 0;
   for (auto &pl : h->plans) max_levels = std::max(max_levels, pl.n_levels);
+  // Launch lists for every schedule are built here, so that the schedule and
+  // the kernel can change after create (vef_sweep_autotune).
   std::vector<Variant> variants;
   {
     std::map<Variant, int> vs;
     for (auto &pl : h->plans) {
-      const int m = mode_of(pl, h->schedule, h->pipeline_waves >= 0);
-      vs[Variant{pl.p, pl.nq, m}] = 1;
-      if (m == 3) vs[Variant{pl.p, pl.nq, 2}] = 1;  // level lists keep mode 2
+      vs[Variant{pl.p, pl.nq, mode_of(pl, VEF_DIR_RESIDENT, false)}] = 1;
+      vs[Variant{pl.p, pl.nq, mode_of(pl, VEF_DIR_RESIDENT, true)}] = 1;
     }
     for (auto &kv : vs) variants.push_back(kv.first);
   }
-  auto in_variant = [&](const vefplan::ProblemPlan &pl, const Variant &v) {
-    return pl.p == v.p && pl.nq == v.nq && mode_of(pl, h->schedule, h->pipeline_waves >= 0) == v.mode;
-  };
   // the level-synchronous lists use the row-per-lane variant of every problem
   auto in_level_variant = [&](const vefplan::ProblemPlan &pl, const Variant &v) {
     const int m = mode_of(pl, VEF_LEVEL_SYNC);
@@ -375,25 +374,27 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
   he = upload(h, &h->d_solves, solves.data(), solves.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload solve lists");
-  // direction-resident tasks: (problem, direction) per variant
+  // direction-resident tasks: (problem, direction) per variant, one list per kernel choice
   std::vector<int2> tasks;
-  for (auto &var : variants) {
-    const int off = (int)tasks.size();
-    int width = 1, maxl = 1, gap = 0;
-    for (int k = 0; k < n_probs; ++k) {
-      const auto &pl = h->plans[k];
-      if (!in_variant(pl, var)) continue;
-      for (int d = 0; d < pl.nd; ++d) tasks.push_back(make_int2(k, d));
-      width = std::max(width, pl.max_width);
-      maxl = std::max(maxl, pl.n_levels);
-      gap = std::max(gap, pl.max_gap);
+  for (int pipe = 0; pipe < 2; ++pipe)
+    for (auto &var : variants) {
+      const int off = (int)tasks.size();
+      int width = 1, maxl = 1, gap = 0;
+      for (int k = 0; k < n_probs; ++k) {
+        const auto &pl = h->plans[k];
+        if (!(pl.p == var.p && pl.nq == var.nq && mode_of(pl, VEF_DIR_RESIDENT, pipe != 0) == var.mode)) continue;
+        for (int d = 0; d < pl.nd; ++d) tasks.push_back(make_int2(k, d));
+        width = std::max(width, pl.max_width);
+        maxl = std::max(maxl, pl.n_levels);
+        gap = std::max(gap, pl.max_gap);
+      }
+      const int cnt = (int)tasks.size() - off;
+      if (cnt > 0) {
+        const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
+        (pipe ? h->dir_pipe : h->dir_rows)
+            .push_back({var, off, cnt, width, maxl, gap, var.mode >= 2 ? ts.dev_A : ts.dev_T});
+      }
     }
-    const int cnt = (int)tasks.size() - off;
-    if (cnt > 0) {
-      const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
-      h->dir_launches.push_back({var, off, cnt, width, maxl, gap, var.mode >= 2 ? ts.dev_A : ts.dev_T});
-    }
-  }
   he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload direction tasks");
   h->psi_internal.assign(n_probs, nullptr);
@@ -527,7 +528,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
           if (h->timing) h->timed_launches++;
         }
     } else {
-      for (auto &D : h->dir_launches) {
+      for (auto &D : (h->pipeline_waves >= 0 ? h->dir_pipe : h->dir_rows)) {
         SL.p = D.v.p;
         SL.nq = D.v.nq;
         SL.mode = D.v.mode;
@@ -650,6 +651,76 @@ int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out) {
     out[2 * b + 1] = pl.bf_ef[b] & 3;
   }
   return VEF_OK;
+}
+
+int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int reps, vef_tune_result *out) {
+  if (!h) return VEF_ERR_INVALID;
+  if (!a || reps < 1 || reps > 1000) return set_err(h, VEF_ERR_INVALID, "bad autotune arguments (reps 1..1000)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  struct Cand {
+    int schedule, waves, block;
+    bool operator==(const Cand &o) const { return schedule == o.schedule && waves == o.waves && block == o.block; }
+  };
+  const Cand before{h->schedule, h->pipeline_waves, h->block};
+  bool any_pipe = false;
+  for (auto &pl : h->plans) any_pipe |= mode_of(pl, VEF_DIR_RESIDENT, true) == 3;
+  std::vector<Cand> cands{before};
+  auto add = [&](Cand c) {
+    for (auto &x : cands)
+      if (x == c) return;
+    cands.push_back(c);
+  };
+  add({VEF_LEVEL_SYNC, before.waves, 256});
+  add({VEF_LEVEL_SYNC, before.waves, 128});
+  add({VEF_DIR_RESIDENT, -1, before.block});
+  if (any_pipe)
+    for (int w : {8, 6, 4}) add({VEF_DIR_RESIDENT, w, before.block});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(h, he, "create tuning events");
+  }
+  auto finish = [&](int rc, const Cand &c) {
+    h->schedule = c.schedule;
+    h->pipeline_waves = c.waves;
+    h->block = c.block;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+  };
+  double best = 1e300, before_ms = -1.0;
+  Cand bestc = before;
+  for (const Cand &c : cands) {
+    h->schedule = c.schedule;
+    h->pipeline_waves = c.waves;
+    h->block = c.block;
+    int rc = vef_sweep_run(h, a, stream);  // warm-up (uploads, first-touch)
+    if (rc == VEF_OK && (he = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(h, he, "record tuning event");
+    for (int r = 0; r < reps && rc == VEF_OK; ++r) rc = vef_sweep_run(h, a, stream);
+    if (rc == VEF_OK && (he = hipEventRecord(e1, s)) != hipSuccess) rc = hip_fail(h, he, "record tuning event");
+    if (rc == VEF_OK && (he = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(h, he, "wait for tuning run");
+    if (rc == VEF_OK) rc = vef_sweep_check(h);
+    if (rc != VEF_OK) return finish(rc, before);
+    float ms = 0.f;
+    if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return finish(hip_fail(h, he, "read tuning events"), before);
+    const double per = (double)ms / reps;
+    if (c == before) before_ms = per;
+    if (per < best) {
+      best = per;
+      bestc = c;
+    }
+  }
+  if (out) {
+    out->schedule = bestc.schedule;
+    out->pipeline_waves = bestc.waves;
+    out->block = bestc.block;
+    out->n_candidates = (int)cands.size();
+    out->best_ms = best;
+    out->before_ms = before_ms;
+  }
+  return finish(VEF_OK, bestc);
 }
 
 int vef_sweep_check(vef_sweep_t *h) {

@@ -38,7 +38,7 @@ KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KE
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
-            "vef_last_error", "vef_status_string")
+            "vef_sweep_autotune", "vef_last_error", "vef_status_string")
 
 
 class vef_problem_desc(C.Structure):
@@ -91,6 +91,7 @@ def _load():
     L.vef_boundary_faces.argtypes = [H, C.c_int, C.c_void_p]
     L.vef_sweep_check.argtypes = [H]
     L.vef_sweep_timing.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.vef_sweep_autotune.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p, C.c_int, C.c_void_p]
     L.vef_last_error.argtypes = [H]
     L.vef_last_error.restype = C.c_char_p
     L.vef_status_string.argtypes = [C.c_int]
@@ -218,6 +219,25 @@ def vef_sweep_timing(h: int):
     return ms.value, n.value
 
 
+class vef_tune_result(C.Structure):
+    _fields_ = [("schedule", C.c_int), ("pipeline_waves", C.c_int), ("block", C.c_int), ("n_candidates", C.c_int),
+                ("best_ms", C.c_double), ("before_ms", C.c_double)]
+
+
+def vef_sweep_autotune(h: int, io: Sequence[dict], n_iter: int = 1, reps: int = 3, stream=None) -> dict:
+    arr = (vef_problem_io * len(io))()
+    for k, b in enumerate(io):
+        arr[k] = vef_problem_io(_ptr(b.get("phi_in")), _ptr(b.get("q_iso")), _ptr(b.get("q_dir")),
+                                _ptr(b.get("psi_bc")), _ptr(b.get("mom")), _ptr(b.get("psi_out")), _ptr(b.get("resid")))
+    args = vef_run_args(arr, n_iter, 0.0, None)
+    res = vef_tune_result()
+    rc = lib.vef_sweep_autotune(C.c_void_p(h), C.byref(args), C.c_void_p(_stream_handle(stream)), int(reps),
+                                C.cast(C.byref(res), C.c_void_p))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+    return {f: getattr(res, f) for f, _ in vef_tune_result._fields_}
+
+
 def vef_sweep_check(h: int):
     rc = lib.vef_sweep_check(C.c_void_p(h))
     if rc != VEF_OK:
@@ -299,6 +319,13 @@ class Sweep:
 
     def check(self):
         vef_sweep_check(self.h)
+
+    def autotune(self, io, n_iter=1, reps=3, stream=None):
+        """Time every schedule/kernel candidate on these buffers and keep the
+        fastest (vef_sweep_autotune); refreshes self.info."""
+        res = vef_sweep_autotune(self.h, io, n_iter, reps, stream)
+        self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
+        return res
 
     def timing(self):
         return vef_sweep_timing(self.h)

@@ -355,3 +355,34 @@ def test_graph_capture_replays(torch, precision, schedule):
                 assert torch.equal(b[key], ref[k][key]), (rep, k, key)
     del g
     sw.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_choice_keeps_parity(torch, precision):
+    """vef_sweep_autotune times every schedule/kernel candidate and keeps the
+    fastest; the handle then reports it and still matches the oracle."""
+    from paper_2301_04758_amd import vef
+    (pr,), _ = P.make_config("c2", scale=20)
+    small = _small(11, 6, 3, 1, 6, st=lambda r, n: r.uniform(0.5, 5, n))
+    small.sigma_s = 0.5 * small.sigma_t
+    probs = [pr, small]
+    print("autotune", precision, flush=True)
+    sw = vef.Sweep(probs, precision=precision)
+    io = sw.buffers(n_iter=2)
+    res = sw.autotune(io, n_iter=2, reps=2)
+    assert res["n_candidates"] >= 4
+    assert 0 < res["best_ms"] <= res["before_ms"]
+    assert sw.info[0]["schedule"] == res["schedule"]
+    if res["schedule"] == vef.VEF_DIR_RESIDENT and res["pipeline_waves"] >= 0:
+        assert sw.info[0]["kernel"] == vef.VEF_KERNEL_AFFINE_PIPELINE
+    else:
+        assert sw.info[0]["kernel"] == vef.VEF_KERNEL_AFFINE
+    sw.run(io, n_iter=2)
+    torch.cuda.synchronize()
+    sw.check()
+    for k, p in enumerate(probs):
+        ref = O.source_iteration(p, 2)
+        assert rel_inf(io[k]["mom"][0].cpu().numpy(), ref["mom"][0]) <= TOL[precision]
+    with pytest.raises(vef.VefError):
+        sw.autotune(io, n_iter=1, reps=0)
+    sw.close()
