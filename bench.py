@@ -235,6 +235,8 @@ def main():
     pr = probs[0]
     solves_per_step = sum(p.n_elem * p.n_dir for p in probs) * n_iter
 
+    from paper_2301_04758_amd import vef
+    machine = vef.vef_probe_machine()
     g64 = run_gpu(probs, n_iter, "fp64", args.steps, args.warmup, schedule=args.schedule)
     ms_step = 1e3 * g64["seconds"] / args.steps
     value = solves_per_step * args.steps / g64["seconds"]
@@ -257,6 +259,8 @@ def main():
                 "us_per_level": avg_launch_s * 1e6 / (g64["n_levels"] * sweeps_per_launch),
                 "lower_bounds_us": {"hbm": t_bw * 1e6, "fp64_alu": t_flop * 1e6},
                 "binding": "critical path: %d dependent upwind levels per sweep" % g64["n_levels"],
+                "measured_peak": machine["fp64_fma_tflops"],
+                "frac_of_measured_peak": achieved_tf / machine["fp64_fma_tflops"],
                 "launches_per_step": launches / args.steps,
                 "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
                 "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
@@ -273,6 +277,7 @@ def main():
                    "precision": "fp64"},
         "hbm_gbs_algorithmic": hbm_gbs,
         "roofline": roofline,
+        "machine": machine,
     }
     if not args.no_fp32:
         g32 = run_gpu(probs, n_iter, "fp32", args.steps, args.warmup, schedule=args.schedule)

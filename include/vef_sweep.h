@@ -215,6 +215,24 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info);
  * [n_bf][2]. */
 int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out);
 
+/* Measured machine figures (vef_probe_machine). */
+typedef struct {
+  int compute_units;      /* of the current device */
+  double hbm_copy_gbs;    /* device-to-device copy of 512 MiB, bytes read + written per second / 1e9 */
+  double fp64_fma_tflops; /* FP64 vector FMA rate over all compute units */
+  double fp32_fma_tflops; /* FP32 vector FMA rate, non-packed forms (as the library is built) */
+  double lds_handoff_ns;  /* one hand-off between two waves of a work-group through an LDS counter */
+} vef_machine;
+
+/* Roofline denominators of the sweep measured on the current device, which
+ * the paper does not give (a property of the machine, not of the method):
+ * HBM copy rate, FP64 and FP32 vector FMA rates, and the latency of the
+ * LDS-counter hand-off the pipelined sweep uses between levels.  Allocates
+ * and frees about 1 GiB of device memory; blocking (runs on stream).
+ * Errors: VEF_ERR_INVALID (out NULL), VEF_ERR_OOM, VEF_ERR_HIP, VEF_ERR_TIMEOUT
+ * (a bounded hand-off wait expired). */
+int vef_probe_machine(vef_machine *out, void *stream);
+
 /* Result of vef_sweep_autotune. */
 typedef struct {
   int schedule;       /* chosen: VEF_LEVEL_SYNC or VEF_DIR_RESIDENT */

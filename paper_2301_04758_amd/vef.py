@@ -38,7 +38,7 @@ KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KE
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
-            "vef_sweep_autotune", "vef_last_error", "vef_status_string")
+            "vef_sweep_autotune", "vef_probe_machine", "vef_last_error", "vef_status_string")
 
 
 class vef_problem_desc(C.Structure):
@@ -92,6 +92,7 @@ def _load():
     L.vef_sweep_check.argtypes = [H]
     L.vef_sweep_timing.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.vef_sweep_autotune.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p, C.c_int, C.c_void_p]
+    L.vef_probe_machine.argtypes = [C.c_void_p, C.c_void_p]
     L.vef_last_error.argtypes = [H]
     L.vef_last_error.restype = C.c_char_p
     L.vef_status_string.argtypes = [C.c_int]
@@ -236,6 +237,19 @@ def vef_sweep_autotune(h: int, io: Sequence[dict], n_iter: int = 1, reps: int = 
     if rc != VEF_OK:
         raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
     return {f: getattr(res, f) for f, _ in vef_tune_result._fields_}
+
+
+class vef_machine(C.Structure):
+    _fields_ = [("compute_units", C.c_int), ("hbm_copy_gbs", C.c_double), ("fp64_fma_tflops", C.c_double),
+                ("fp32_fma_tflops", C.c_double), ("lds_handoff_ns", C.c_double)]
+
+
+def vef_probe_machine(stream=None) -> dict:
+    m = vef_machine()
+    rc = lib.vef_probe_machine(C.cast(C.byref(m), C.c_void_p), C.c_void_p(_stream_handle(stream)))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(None).decode())
+    return {f: getattr(m, f) for f, _ in vef_machine._fields_}
 
 
 def vef_sweep_check(h: int):

@@ -386,3 +386,16 @@ def test_autotune_choice_keeps_parity(torch, precision):
     with pytest.raises(vef.VefError):
         sw.autotune(io, n_iter=1, reps=0)
     sw.close()
+
+
+def test_probe_machine(torch):
+    """Measured roofline denominators are in a plausible range for MI355X
+    (published: 8 TB/s HBM, 78.6 TFLOP/s FP64 vector)."""
+    from paper_2301_04758_amd import vef
+    m = vef.vef_probe_machine()
+    print("machine", m, flush=True)
+    assert m["compute_units"] >= 1
+    assert 500 < m["hbm_copy_gbs"] < 9000
+    assert 1 < m["fp64_fma_tflops"] < 90
+    assert 1 < m["fp32_fma_tflops"] < 180
+    assert 1 < m["lds_handoff_ns"] < 100000
