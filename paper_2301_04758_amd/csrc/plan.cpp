@@ -215,9 +215,9 @@ int build_tables(int p, int nq, Tables &t) {
     }
   t.F = v1;
   // affine-element tables (quadrature sums with the same rule)
-  t.affine.assign(3 * n * n + P1 * P1 + Q * n + nq * P1, 0.0);
+  t.affine.assign(3 * n * n + P1 * P1 + Q * n + nq * P1 + P1 * P1, 0.0);
   double *Mt = t.affine.data(), *Gx = Mt + n * n, *Gy = Gx + n * n, *M1 = Gy + n * n;
-  double *WV = M1 + P1 * P1, *WL = WV + Q * n;
+  double *WV = M1 + P1 * P1, *WL = WV + Q * n, *GD1 = WL + nq * P1;
   for (int q = 0; q < Q; ++q) {
     const double w = t.gw[q % nq] * t.gw[q / nq];
     for (int i = 0; i < n; ++i) {
@@ -232,7 +232,12 @@ int build_tables(int p, int nq, Tables &t) {
   for (int q = 0; q < nq; ++q)
     for (int a = 0; a < P1; ++a) {
       WL[q * P1 + a] = t.gw[q] * v1[q * P1 + a];
-      for (int c = 0; c < P1; ++c) M1[a * P1 + c] += t.gw[q] * v1[q * P1 + a] * v1[q * P1 + c];
+      for (int c = 0; c < P1; ++c) {
+        M1[a * P1 + c] += t.gw[q] * v1[q * P1 + a] * v1[q * P1 + c];
+        // 1D factors of the tensor-product matrices: Mt = M1 (x) M1,
+        // Gx = GD1 (x) M1, Gy = M1 (x) GD1 (test index first)
+        GD1[a * P1 + c] += t.gw[q] * d1[q * P1 + a] * v1[q * P1 + c];
+      }
     }
   return VEF_OK;
 }

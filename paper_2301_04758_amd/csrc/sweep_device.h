@@ -79,8 +79,8 @@ struct Shape {
   // tables Mhat^T, Ghat_xi^T, Ghat_eta^T [n][n], face mass [p+1][p+1],
   // w V [Q][n] (direction-dependent source), w L [nq][p+1] (boundary data)
   static constexpr int A_MT = 0, A_GX = N * N, A_GY = 2 * N * N, A_M1 = 3 * N * N;
-  static constexpr int A_WV = A_M1 + P1 * P1, A_WL = A_WV + Q * N;
-  static constexpr int TAB_A = A_WL + NQ * P1;
+  static constexpr int A_WV = A_M1 + P1 * P1, A_WL = A_WV + Q * N, A_GD1 = A_WL + NQ * P1;
+  static constexpr int TAB_A = A_GD1 + P1 * P1;
   static constexpr int AOFF_G = 0, AOFF_S = 16, AOFF_QD = 16 + N;
   static constexpr int AOFF_PIV = ((AOFF_QD + Q + 1) / 2) * 2;
   static constexpr int SLOT_AREA_A = ((AOFF_PIV + N + 1 + 1) / 2) * 2;
@@ -103,6 +103,8 @@ __host__ __device__ constexpr size_t lds_bytes(int tab, int slot_area, int slots
 // global_* instructions, which count only on vmcnt; flat accesses also count
 // on lgkmcnt, so every wait for LDS results would wait for them too.
 #define VEF_GLOBAL __attribute__((address_space(1)))
+// Constant-memory view (uniform reads compile to scalar loads).
+#define VEF_CONST __attribute__((address_space(4)))
 template <typename T>
 __device__ __forceinline__ VEF_GLOBAL T *gmem(T *p) {
   return (VEF_GLOBAL T *)p;
@@ -467,9 +469,6 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
   using S = Shape<P, NQ>;
   constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
   static_assert(!PIVOT, "the affine path is pivot-free");
-  const T *Mt = lds + S::A_MT;
-  const T *Gxt = lds + S::A_GX;
-  const T *Gyt = lds + S::A_GY;
   const T *M1 = lds + S::A_M1;
   const T *WV = lds + S::A_WV;
   const T *WL = lds + S::A_WL;
@@ -523,12 +522,31 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
   const T stJ = st * J;
   const T gx = g[1] * ox + g[2] * oy;
   const T gy = g[3] * ox + g[4] * oy;
+  // Row rr = (a, b) of A = stJ M - gx Gx - gy Gy from the 1D factors:
+  // M = m (x) m, Gx = gd (x) m, Gy = m (x) gd (test index first), so
+  // A[(a,b)][(c,d)] = m_bd (stJ m_ac - gx gd_ac) - gd_bd (gy m_ac).
+  const T *m1 = lds + S::A_M1;
+  const T *gdt = lds + S::A_GD1;
+  T mb[P1], gb[P1], Xa[P1], Ya[P1];
+#pragma unroll
+  for (int c = 0; c < P1; ++c) {
+    const T mac = m1[a * P1 + c];
+    Xa[c] = stJ * mac - gx * gdt[a * P1 + c];
+    Ya[c] = gy * mac;
+    mb[c] = m1[b * P1 + c];
+    gb[c] = gdt[b * P1 + c];
+  }
   T A[N];
   T rhs = T(0);
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    A[j] = stJ * Mt[j * N + rr] - gx * Gxt[j * N + rr] - gy * Gyt[j * N + rr];
-    rhs += Mt[j * N + rr] * area[S::AOFF_S + j];
+  for (int dd = 0; dd < P1; ++dd) {
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < P1; ++c) {
+      A[c + P1 * dd] = mb[dd] * Xa[c] - gb[dd] * Ya[c];
+      acc += m1[a * P1 + c] * area[S::AOFF_S + c + P1 * dd];
+    }
+    rhs += mb[dd] * acc;  // (m (x) m) s, summed over (c, d)
   }
   rhs *= J;
   if (pio.q_dir) {
@@ -794,6 +812,17 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       }
     }
   };
+  // 1D factors of the reference matrices (uniform: scalar loads, held in
+  // scalar registers): m = 1D mass, gd = 1D derivative-times-value table.
+  // M = m (x) m, Gx = gd (x) m, Gy = m (x) gd with the test index first, and
+  // M1 (the face mass) = m.
+  const VEF_CONST T *tabc = (const VEF_CONST T *)tables;
+  T m1[P1 * P1], gd[P1 * P1];
+#pragma unroll
+  for (int k = 0; k < P1 * P1; ++k) {
+    m1[k] = tabc[S::A_M1 + k];
+    gd[k] = tabc[S::A_GD1 + k];
+  }
   advance(wave);
   for (; L < nl; advance(W)) {
     const int beg = lo[L], end = lo[L + 1];
@@ -803,12 +832,10 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       // The table reads are loop invariant; an opaque offset keeps the
       // compiler from hoisting all of them (hundreds of values) out of the
       // loop, which would not fit in registers.
+      // q_dir and inflow-data tables stay in LDS (paths taken only with
+      // those inputs); the opaque offset keeps their reads in the loop.
       int toff = 0;
       asm volatile("" : "+v"(toff));
-      const T *Mt = lds + S::A_MT + toff;
-      const T *Gxt = lds + S::A_GX + toff;
-      const T *Gyt = lds + S::A_GY + toff;
-      const T *M1 = lds + S::A_M1 + toff;
       const T *WV = lds + S::A_WV + toff;
       const T *WL = lds + S::A_WL + toff;
       // ---- prep: everything that does not depend on upwind values
@@ -860,13 +887,28 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       for (int f = 0; f < 4; ++f) on[f] = ox * gv[5 + 2 * f] + oy * gv[6 + 2 * f];
       // Right-hand side first: every branch of the prep happens while only
       // these N values are live, the matrix below is straight-line code.
+      // b = J (m (x) m) s by sum factorisation: node (a, b) = a + P1 * b.
       T b[N];
+      {
+        T h[P1][P1];  // h[a][d] = sum_c m[a][c] s[c][d]
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = T(0);
+        for (int a = 0; a < P1; ++a)
 #pragma unroll
-        for (int j = 0; j < N; ++j) acc += Mt[j * N + i] * sj[j];
-        b[i] = J * acc;
+          for (int dd = 0; dd < P1; ++dd) {
+            T acc = T(0);
+#pragma unroll
+            for (int c = 0; c < P1; ++c) acc += m1[a * P1 + c] * sj[c + P1 * dd];
+            h[a][dd] = acc;
+          }
+#pragma unroll
+        for (int a = 0; a < P1; ++a)
+#pragma unroll
+          for (int bb = 0; bb < P1; ++bb) {
+            T acc = T(0);
+#pragma unroll
+            for (int dd = 0; dd < P1; ++dd) acc += m1[bb * P1 + dd] * h[a][dd];
+            b[a + P1 * bb] = J * acc;
+          }
       }
       if (pio.q_dir) {
         const VEF_GLOBAL double *qd = gmem(pio.q_dir + ((size_t)d * ne + e) * Q);
@@ -904,20 +946,30 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       T cf[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) cf[f] = ((flags >> f) & 1) ? T(0) : on[f];
+      // A[(a,b)][(c,d)] = stJ m_ac m_bd - gx gd_ac m_bd - gy m_ac gd_bd
+      //                  = m_bd X_ac - gd_bd Y_ac
+      T X[P1 * P1], Y[P1 * P1];
+#pragma unroll
+      for (int k = 0; k < P1 * P1; ++k) {
+        X[k] = stJ * m1[k] - gx * gd[k];
+        Y[k] = gy * m1[k];
+      }
       T A[N][N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
+      for (int bb = 0; bb < P1; ++bb)
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-          A[i][j] = stJ * Mt[j * N + i] - gx * Gxt[j * N + i] - gy * Gyt[j * N + i];
-        __builtin_amdgcn_sched_barrier(0);  // keep table reads row by row (register pressure)
-      }
+        for (int a = 0; a < P1; ++a)
+#pragma unroll
+          for (int dd = 0; dd < P1; ++dd)
+#pragma unroll
+            for (int c = 0; c < P1; ++c)
+              A[a + P1 * bb][c + P1 * dd] = m1[bb * P1 + dd] * X[a * P1 + c] - gd[bb * P1 + dd] * Y[a * P1 + c];
 #pragma unroll
       for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int a = 0; a < P1; ++a)
 #pragma unroll
-          for (int c = 0; c < P1; ++c) A[face_node<P>(f, a)][face_node<P>(f, c)] += cf[f] * M1[a * P1 + c];
+          for (int c = 0; c < P1; ++c) A[face_node<P>(f, a)][face_node<P>(f, c)] += cf[f] * m1[a * P1 + c];
       // LU factors in place (natural order), reciprocal pivots kept
       T inv[N];
 #pragma unroll
@@ -984,7 +1036,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
         for (int a = 0; a < P1; ++a) {
           T acc = T(0);
 #pragma unroll
-          for (int c = 0; c < P1; ++c) acc += M1[a * P1 + c] * tr[c];
+          for (int c = 0; c < P1; ++c) acc += m1[a * P1 + c] * tr[c];
           b[face_node<P>(f, a)] -= on[f] * acc;
         }
       }
