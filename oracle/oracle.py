@@ -54,7 +54,7 @@ class _Prob(C.Structure):
                 ("n_elem", C.c_int), ("n_cp", C.c_int),
                 ("cp_xy", C.c_void_p), ("elem_cp", C.c_void_p),
                 ("n_dir", C.c_int), ("omega", C.c_void_p), ("weight", C.c_void_p),
-                ("sigma_t", C.c_void_p), ("sigma_s", C.c_void_p)]
+                ("sigma_t", C.c_void_p), ("sigma_s", C.c_void_p), ("fixup", C.c_int)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -99,7 +99,7 @@ def _f64(a):
 class _Bound:
     """Keeps the numpy arrays behind an oracle_problem struct alive."""
 
-    def __init__(self, pr, nq=None):
+    def __init__(self, pr, nq=None, fixup=False):
         self.cp = np.ascontiguousarray(pr.cp_xy, dtype=np.float64)
         self.ec = np.ascontiguousarray(pr.elem_cp, dtype=np.int32)
         self.om = np.ascontiguousarray(pr.omega, dtype=np.float64)
@@ -108,7 +108,7 @@ class _Bound:
         self.ss = np.ascontiguousarray(pr.sigma_s, dtype=np.float64)
         self.s = _Prob(pr.p, pr.m, int(pr.nq if nq is None else nq), self.ec.shape[0], self.cp.shape[0],
                        self.cp.ctypes.data, self.ec.ctypes.data, self.om.shape[0], self.om.ctypes.data,
-                       self.wt.ctypes.data, self.st.ctypes.data, self.ss.ctypes.data)
+                       self.wt.ctypes.data, self.st.ctypes.data, self.ss.ctypes.data, 1 if fixup else 0)
         self.nq = self.s.nq if self.s.nq > 0 else pr.p + pr.m
         self.n = (pr.p + 1) ** 2
         self.Q = self.nq * self.nq
@@ -178,10 +178,11 @@ def levels(pr, nq=None):
 
 
 def sweep(pr, phi_in=None, dirs=None, want_psi=True, nq=None, q_iso="problem", q_dir="problem",
-          psi_bc="problem"):
+          psi_bc="problem", fixup=False):
     """One sweep.  Returns dict(psi [n_sel,n_elem,n] or None, mom [6,n_elem,n],
-    bnd [n_bf,nq,2], levels [n_sel])."""
-    b = _Bound(pr, nq)
+    bnd [n_bf,nq,2], levels [n_sel]).  fixup: set-to-zero-and-scale
+    negative-flux fixup after each local solve."""
+    b = _Bound(pr, nq, fixup)
     q_iso = _f64(pr.q_iso if isinstance(q_iso, str) else q_iso)
     q_dir = _f64(pr.q_dir if isinstance(q_dir, str) else q_dir)
     psi_bc = _f64(pr.psi_bc if isinstance(psi_bc, str) else psi_bc)
@@ -227,9 +228,9 @@ def closures(pr, mom, bnd, nq=None, q_iso="problem", q_dir="problem", psi_bc="pr
     return dict(E=E, Eb=Eb, Jin=Jin, Q0=Q0, Q1=Q1, n_nonpos=nn.value)
 
 
-def source_iteration(pr, n_iter, tol=0.0, phi0=None, nq=None):
+def source_iteration(pr, n_iter, tol=0.0, phi0=None, nq=None, fixup=False):
     """dict(mom [6,n_elem,n] of the last sweep, bnd, resid [iters], iters)."""
-    b = _Bound(pr, nq)
+    b = _Bound(pr, nq, fixup)
     nb = n_boundary_faces(pr, nq)
     mom = np.zeros((6, pr.n_elem, b.n))
     bnd = np.zeros((nb, b.nq, 2))

@@ -29,7 +29,10 @@
  *     inflow when Omega . N_F < 0;
  *   - tensor Gauss-Lobatto nodal basis of degree p on [0,1]^2, tensor
  *     Gauss-Legendre quadrature with nq points per direction (default p+m);
- *   - dense Gaussian elimination with partial pivoting (first maximal entry).
+ *   - dense Gaussian elimination with partial pivoting (first maximal entry);
+ *   - optional negative-flux fixup (set to zero and scale, keeping the
+ *     element's particle balance), in place of the paper's QP fixup
+ *     (Sec. 8.4), which is not reproduced.
  *   Parity of the curved-face upwind rule is unpinned beyond its definition.
  */
 #include <math.h>
@@ -58,6 +61,7 @@ typedef struct {
   const double *weight; /* [n_dir] */
   const double *sigma_t;
   const double *sigma_s;
+  int fixup; /* 1: set-to-zero-and-scale negative-flux fixup after each local solve */
 } oracle_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -434,6 +438,27 @@ static double dg_eval(const ctx_t *c, const double *u, double xi, double eta) {
 
 /* Assemble and solve the local system of element e for direction d.
  * psi_d holds the already computed angular flux of direction d ([n_elem][n]). */
+/* Negative-flux fixup, "set to zero and scale": when some nodal value of the
+ * element's solution is negative, the negative values are set to zero and the
+ * others multiplied by alpha = (c . x) / (c . x+), so that the element's
+ * particle balance c . x (outflow plus absorption, c the balance weights) is
+ * unchanged.  A solution without negative values is left as it is; when
+ * c . x <= 0 no non-negative solution has that balance and the element is set
+ * to zero.  (Applied before the element's outflow is used downstream: the
+ * fixup is part of the sweep.) */
+static void zero_and_scale(int n, const double *c, double *x) {
+  int neg = 0;
+  for (int j = 0; j < n; ++j) neg |= x[j] < 0.0;
+  if (!neg) return;
+  double bal = 0.0, pos = 0.0;
+  for (int j = 0; j < n; ++j) {
+    bal += c[j] * x[j];
+    if (x[j] > 0.0) pos += c[j] * x[j];
+  }
+  const double alpha = (bal > 0.0 && pos > 0.0) ? bal / pos : 0.0;
+  for (int j = 0; j < n; ++j) x[j] = x[j] > 0.0 ? alpha * x[j] : 0.0;
+}
+
 static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const double *phi_in,
                        const double *q_iso, const double *q_dir, const double *psi_bc,
                        double *psi_d) {
@@ -511,8 +536,18 @@ static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const dou
       }
     }
   }
+  /* balance weights: testing with u = 1 gives sum_j c_j psi_j = sum_i b_i,
+   * c_j = sum_i A_ij (outflow plus absorption; the streaming columns sum to
+   * zero because the basis sums to one) */
+  double cbal[MAXN];
+  if (pr->fixup)
+    for (int j = 0; j < n; ++j) {
+      cbal[j] = 0.0;
+      for (int i = 0; i < n; ++i) cbal[j] += A[i * n + j];
+    }
   int rc = dense_solve(n, A, b, x);
   if (rc) return rc;
+  if (pr->fixup) zero_and_scale(n, cbal, x);
   memcpy(psi_d + (size_t)e * n, x, sizeof(double) * n);
   return ORACLE_OK;
 }
