@@ -111,7 +111,14 @@ typedef struct {
                     two; fewer when LDS is short);
                     upwind elements further back are read from the angular
                     flux in global memory */
-  int reserved[2];
+  int fixup;         /* 1: negative-flux fixup after each local solve: when an
+                    element's solution has a negative nodal value, negatives
+                    become zero and the rest is scaled so that the element's
+                    particle balance (outflow + absorption, testing with
+                    u = 1) is unchanged; non-negative solutions are untouched.
+                    A simpler stand-in for the paper's QP fixup (Sec. 8.4).
+                    0 = off (default) */
+  int reserved[1];
 } vef_options;
 
 /* Per-problem device buffers of one run (device pointers owned by the caller).

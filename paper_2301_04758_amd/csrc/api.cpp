@@ -91,6 +91,7 @@ struct vef_sweep {
   bool timing = false;
   int pipeline_waves = 0;
   int pipeline_ring = 0;
+  int fixup = 0;
   std::vector<hipEvent_t> events;  // [2 * iterations] of the last run
   int timed_iters = 0;
   int timed_launches = 0;
@@ -186,6 +187,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (opt->pipeline_ring < 0 || opt->pipeline_ring > 4)
       return set_err(h, VEF_ERR_INVALID, "pipeline_ring must be 0..4");
     h->pipeline_ring = opt->pipeline_ring;
+    if (opt->fixup < 0 || opt->fixup > 1) return set_err(h, VEF_ERR_INVALID, "fixup must be 0 or 1");
+    h->fixup = opt->fixup;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
   }
@@ -513,6 +516,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
     SL.stream = s;
     SL.waves = h->pipeline_waves > 0 ? h->pipeline_waves : 0;
     SL.ring = h->pipeline_ring;
+    SL.fixup = h->fixup;
     SL.wait_spins = 1LL << 26;  // seconds of polling: a healthy wait takes microseconds
     if (h->schedule == VEF_LEVEL_SYNC) {
       for (auto &lv : h->levels)

@@ -64,6 +64,7 @@ struct SweepLaunch {
   int max_gap;     // pipelined: largest level gap of an upwind edge
   int waves;       // pipelined: waves per work-group (0 = default)
   int ring;        // pipelined: trace ring depth in levels (0 = default)
+  int fixup;       // 1: negative-flux fixup after each local solve (kernel variant)
   long long wait_spins;   // pipelined: bound of a wait, in polls of about 64 clocks each
   const KProb *probs;
   const KIO *io;

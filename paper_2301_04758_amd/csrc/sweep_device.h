@@ -51,7 +51,9 @@ enum : int {
   MODE_GENERAL_PIVOT = 0,
   MODE_GENERAL_NOPIVOT = 1,
   MODE_AFFINE_NOPIVOT = 2,
-  MODE_AFFINE_PIPELINE = 3  // direction-resident schedule only, p <= 2
+  MODE_AFFINE_PIPELINE = 3,  // direction-resident schedule only, p <= 2
+  MODE_KIND = 7,             // mask of the kernel kind above
+  MODE_FIX = 8               // flag: negative-flux fixup after each local solve
 };
 
 template <int P, int NQ>
@@ -89,8 +91,8 @@ struct Shape {
 template <int P, int NQ, int MODE>
 struct Lds {
   using S = Shape<P, NQ>;
-  static constexpr int TAB = MODE == MODE_AFFINE_NOPIVOT ? S::TAB_A : S::TAB;
-  static constexpr int AREA = MODE == MODE_AFFINE_NOPIVOT ? S::SLOT_AREA_A : S::SLOT_AREA;
+  static constexpr int TAB = (MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT ? S::TAB_A : S::TAB;
+  static constexpr int AREA = (MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT ? S::SLOT_AREA_A : S::SLOT_AREA;
 };
 
 template <typename T>
@@ -244,6 +246,32 @@ __device__ __forceinline__ void gj_pivot(T (&A)[N], T &rhs, int r, bool &active,
   }
 }
 
+// Negative-flux fixup of one solve held one unknown per lane (x, with its
+// balance weight c): when some unknown of the slot is negative, negatives
+// become zero and the rest is scaled by (c . x) / (c . x+), which keeps the
+// element's particle balance c . x; a slot without negative unknowns is left
+// alone.  c_j = sigma_t int phi_j + outflow int (Omega . n) phi_j, the column
+// sums of the local matrix (the streaming columns sum to zero).  Wave-uniform
+// early exit: the reductions run only when some lane has a negative value.
+template <int SLOT, typename T>
+__device__ __forceinline__ void zero_and_scale_slot(T &x, T c, bool row_ok) {
+  const bool neg = row_ok && x < T(0);
+  if (__builtin_amdgcn_ballot_w64(neg) == 0) return;
+  T cx = row_ok ? c * x : T(0);
+  T cp = (row_ok && x > T(0)) ? c * x : T(0);
+  int nneg = neg ? 1 : 0;
+#pragma unroll
+  for (int m = 1; m < SLOT; m <<= 1) {
+    cx += __shfl_xor(cx, m);
+    cp += __shfl_xor(cp, m);
+    nneg += __shfl_xor(nneg, m);
+  }
+  if (nneg > 0 && row_ok) {
+    const T alpha = (cx > T(0) && cp > T(0)) ? cx / cp : T(0);
+    x = x > T(0) ? alpha * x : T(0);
+  }
+}
+
 // Per-lane inputs of one solve (loaded ahead of the solve).
 template <int P, int NQ, typename T>
 struct SolveIn {
@@ -293,7 +321,7 @@ __device__ __forceinline__ void load_one(SolveIn<P, NQ, T> &in, int d, const KPr
 // Assemble and solve one element-direction system from prefetched inputs.
 // All lanes of the slot must call it; slots with in.valid == false store
 // nothing.  Uses only the slot's LDS area (no work-group barrier inside).
-template <int P, int NQ, typename T, bool PIVOT>
+template <int P, int NQ, typename T, bool PIVOT, bool FIX>
 __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, const KProb &pb,
                                            const KIO &pio, T *lds, int r, int slot, int *status) {
   using S = Shape<P, NQ>;
@@ -416,6 +444,31 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
   } else {
     gj_nopivot<SLOT, N, 0, T>(A, rhs, r);
   }
+  if constexpr (FIX) {
+    // balance weight of unknown rr, recomputed here (rare path) from the
+    // geometry still in LDS: sigma_t int phi_rr + outflow int (Omega.n) phi_rr
+    T cr = T(0);
+    if (row_ok) {
+      T cv = T(0);
+      for (int q = 0; q < Q; ++q) cv += g5[5 * q] * sV[q * N + rr];
+      cr = static_cast<T>(pb.sig[2 * e]) * cv;
+      for (int f = 0; f < 4; ++f) {
+        const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+        const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+        if (!on_face || ((mask >> f) & 1u)) continue;
+        const T *gf = area + S::OFF_GF + f * NQ * 2;
+        for (int q = 0; q < NQ; ++q) cr += (ox * gf[2 * q] + oy * gf[2 * q + 1]) * sF[q * P1 + pos];
+      }
+    }
+    if constexpr (PIVOT) {  // lane r holds unknown my_k: fetch its weight
+      T *cw = area + S::OFF_PIV;
+      if (row_ok) cw[r] = cr;
+      wave_sync_lds();
+      cr = cw[my_k];
+      __builtin_amdgcn_wave_barrier();
+    }
+    zero_and_scale_slot<SLOT, T>(rhs, cr, row_ok);
+  }
   if (row_ok) {
     T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
     out[my_k] = rhs;
@@ -463,7 +516,7 @@ __device__ __forceinline__ void load_one(SolveInA<P, NQ, T> &in, int d, const KP
 }
 
 // Solve on an affine element (see the file comment); pivot-free.
-template <int P, int NQ, typename T, bool PIVOT>
+template <int P, int NQ, typename T, bool PIVOT, bool FIX>
 __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, const KProb &pb,
                                           const KIO &pio, T *lds, int r, int slot, int *status) {
   using S = Shape<P, NQ>;
@@ -579,6 +632,27 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
   }
 
   gj_nopivot<SLOT, N, 0, T>(A, rhs, r);
+  if constexpr (FIX) {
+    // balance weight of unknown rr (rare path): stJ (sum_c m_ac)(sum_d m_bd)
+    // + outflow faces through rr: (Omega . N_f) sum_c M1[pos][c]
+    T cr = T(0);
+    if (row_ok) {
+      T sma = T(0), smb = T(0);
+      for (int c = 0; c < P1; ++c) {
+        sma += m1[a * P1 + c];
+        smb += m1[b * P1 + c];
+      }
+      cr = static_cast<T>(pb.sig[2 * e]) * area[S::AOFF_G] * sma * smb;
+      for (int f = 0; f < 4; ++f) {
+        const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+        const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+        if (!on_face || ((mask >> f) & 1u)) continue;
+        const T on = ox * area[S::AOFF_G + 5 + 2 * f] + oy * area[S::AOFF_G + 6 + 2 * f];
+        for (int c = 0; c < P1; ++c) cr += on * M1[pos * P1 + c];
+      }
+    }
+    zero_and_scale_slot<SLOT, T>(rhs, cr, row_ok);
+  }
   if (row_ok) {
     T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
     out[r] = rhs;
@@ -587,7 +661,7 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
 }
 
 template <int P, int NQ, typename T, int MODE>
-using InputsOf = std::conditional_t<MODE == MODE_AFFINE_NOPIVOT, SolveInA<P, NQ, T>, SolveIn<P, NQ, T>>;
+using InputsOf = std::conditional_t<(MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT, SolveInA<P, NQ, T>, SolveIn<P, NQ, T>>;
 
 // Stage the tables of a variant into LDS.
 template <int P, int NQ, typename T, int MODE>
@@ -638,7 +712,8 @@ k_sweep_level(const int2 *__restrict__ solves, int n_solves, const KProb *__rest
     for (int f = 0; f < 4; ++f) in.nb[f] = -1;
   }
   load_one<P, NQ, T>(in, d, pb, pio, it, r);
-  solve_one<P, NQ, T, MODE == MODE_GENERAL_PIVOT>(in, d, pb, pio, lds, r, slot, status);
+  solve_one<P, NQ, T, (MODE & MODE_KIND) == MODE_GENERAL_PIVOT, (MODE & MODE_FIX) != 0>(in, d, pb, pio, lds, r, slot,
+                                                                                     status);
 }
 
 // Largest work-group of the direction-resident schedule for a variant, chosen
@@ -646,11 +721,12 @@ k_sweep_level(const int2 *__restrict__ solves, int n_solves, const KProb *__rest
 // leaves 128 VGPRs per lane, 512 leaves 256).
 template <int P, int NQ, typename T, int MODE>
 constexpr int dir_block_max() {
-  if (MODE == MODE_AFFINE_NOPIVOT) {
+  if ((MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT) {
     if (sizeof(T) == 8) return P <= 3 ? 512 : 256;
     return P <= 2 ? 1024 : 512;
   }
   if (sizeof(T) == 8) return 512;
+  if (MODE & MODE_FIX) return 512;  // the fixup variant needs more than 128 registers
   return (P == 4 && NQ >= 6) ? 512 : 1024;
 }
 
@@ -719,7 +795,8 @@ k_sweep_dir(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       base2 = L2 < nl ? lo[L2] : 0;
     }
     fetch(nxt, L2, base2 + slot);
-    solve_one<P, NQ, T, MODE == MODE_GENERAL_PIVOT>(cur, d, pb, pio, lds, r, slot, status);
+    solve_one<P, NQ, T, (MODE & MODE_KIND) == MODE_GENERAL_PIVOT, (MODE & MODE_FIX) != 0>(cur, d, pb, pio, lds, r,
+                                                                                       slot, status);
     if (L2 != L) __syncthreads();  // the level's fluxes are upwind values of the next
     cur = nxt;
     L = L2;
@@ -754,7 +831,7 @@ constexpr int pipe_max_waves() {
   return kPipeMaxWaves;
 }
 
-template <int P, int NQ, typename T>
+template <int P, int NQ, typename T, bool FIX>
 __global__ void __launch_bounds__((pipe_max_waves<P, T>() * 64))
 k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
              const KIO *__restrict__ io, const T *__restrict__ tables, int it,
@@ -1051,6 +1128,39 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
         for (int j = i + 1; j < N; ++j) b[i] -= A[i][j] * b[j];
         b[i] *= inv[i];
       }
+      if constexpr (FIX) {  // negative-flux fixup (see zero_and_scale_slot), one element per lane
+        bool neg = false;
+#pragma unroll
+        for (int i = 0; i < N; ++i) neg |= b[i] < T(0);
+        if (neg) {
+          const T stJ = static_cast<T>(sig[2 * e]) * gmem(static_cast<const T *>(pb.geo_a))[(size_t)e * 16];
+          // balance weight of node (a, b): stJ sm_a sm_b plus (Omega . N_f) sm_pos
+          // for each outflow face f through it (sm = row sums of m)
+          T cx = T(0), cp = T(0);
+          for (int i = 0; i < N; ++i) {
+            const int a = i % P1, bb = i / P1;
+            T sa = T(0), sb = T(0);
+            for (int c = 0; c < P1; ++c) {
+              sa += m1[a * P1 + c];
+              sb += m1[bb * P1 + c];
+            }
+            T cw = stJ * sa * sb;
+            for (int f = 0; f < 4; ++f) {
+              const bool on_face = (f == 0) ? (bb == 0) : (f == 1) ? (a == P) : (f == 2) ? (bb == P) : (a == 0);
+              if (!on_face || ((flags >> f) & 1)) continue;
+              const int pos = (f == 0) ? a : (f == 1) ? bb : (f == 2) ? (P - a) : (P - bb);
+              T sp = T(0);
+              for (int c = 0; c < P1; ++c) sp += m1[pos * P1 + c];
+              cw += on[f] * sp;
+            }
+            cx += cw * b[i];
+            if (b[i] > T(0)) cp += cw * b[i];
+          }
+          const T alpha = (cx > T(0) && cp > T(0)) ? cx / cp : T(0);
+#pragma unroll
+          for (int i = 0; i < N; ++i) b[i] = b[i] > T(0) ? alpha * b[i] : T(0);
+        }
+      }
       // outflow traces for the levels below
       if (valid) {
         T *dst = ring + (size_t)(L & (ring_levels - 1)) * 4 * P1 * ring_width + (t - beg);
@@ -1092,7 +1202,7 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
 template <int P, int NQ, typename T, int MODE>
 hipError_t launch_dir_t(const SweepLaunch &L);
 
-template <int P, int NQ, typename T>
+template <int P, int NQ, typename T, bool FIX>
 hipError_t launch_pipe_t(const SweepLaunch &L) {
   if constexpr (P > 2) {
     return hipErrorInvalidValue;
@@ -1107,10 +1217,11 @@ hipError_t launch_pipe_t(const SweepLaunch &L) {
     R = R >= 4 ? 4 : (R >= 2 ? 2 : 1);  // a power of two: the slot of a level is a mask
     while (R > 1 && fixed + R * ring_bytes_per_level > L.lds_max) R >>= 1;
     // a level too wide for even one ring slot: the row-per-lane kernel
-    if (fixed + R * ring_bytes_per_level > L.lds_max) return launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L);
+    if (fixed + R * ring_bytes_per_level > L.lds_max)
+      return launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT | (FIX ? MODE_FIX : 0)>(L);
     const int global_sync = (L.max_gap >= R) ? 1 : 0;
     const size_t bytes = fixed + R * ring_bytes_per_level;
-    hipLaunchKernelGGL((k_sweep_pipe<P, NQ, T>), dim3(L.count), dim3(waves * 64), bytes, L.stream, L.list, L.probs,
+    hipLaunchKernelGGL((k_sweep_pipe<P, NQ, T, FIX>), dim3(L.count), dim3(waves * 64), bytes, L.stream, L.list, L.probs,
                        L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status, R, L.width, global_sync,
                        L.wait_spins);
     return hipGetLastError();
@@ -1162,20 +1273,28 @@ hipError_t launch_dir_t(const SweepLaunch &L) {
   return hipGetLastError();
 }
 
-template <int P, int NQ, typename T, bool DIR>
-hipError_t launch_mode(const SweepLaunch &L) {
+template <int P, int NQ, typename T, bool DIR, int FX>
+hipError_t launch_mode_fx(const SweepLaunch &L) {
   switch (L.mode) {
     case MODE_GENERAL_PIVOT:
-      return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_PIVOT>(L) : launch_level_t<P, NQ, T, MODE_GENERAL_PIVOT>(L);
+      return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_PIVOT | FX>(L)
+                 : launch_level_t<P, NQ, T, MODE_GENERAL_PIVOT | FX>(L);
     case MODE_GENERAL_NOPIVOT:
-      return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_NOPIVOT>(L)
-                 : launch_level_t<P, NQ, T, MODE_GENERAL_NOPIVOT>(L);
+      return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_NOPIVOT | FX>(L)
+                 : launch_level_t<P, NQ, T, MODE_GENERAL_NOPIVOT | FX>(L);
     case MODE_AFFINE_NOPIVOT:
-      return DIR ? launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L) : launch_level_t<P, NQ, T, MODE_AFFINE_NOPIVOT>(L);
+      return DIR ? launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT | FX>(L)
+                 : launch_level_t<P, NQ, T, MODE_AFFINE_NOPIVOT | FX>(L);
     case MODE_AFFINE_PIPELINE:
-      return DIR ? launch_pipe_t<P, NQ, T>(L) : hipErrorInvalidValue;
+      return DIR ? launch_pipe_t<P, NQ, T, FX != 0>(L) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
+}
+
+// The fixup is a compile-time variant: kernels without it carry none of its code.
+template <int P, int NQ, typename T, bool DIR>
+hipError_t launch_mode(const SweepLaunch &L) {
+  return L.fixup ? launch_mode_fx<P, NQ, T, DIR, MODE_FIX>(L) : launch_mode_fx<P, NQ, T, DIR, 0>(L);
 }
 
 template <int P, bool DIR>

@@ -50,7 +50,8 @@ class vef_problem_desc(C.Structure):
 
 class vef_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("schedule", C.c_int), ("block", C.c_int), ("timing", C.c_int),
-                ("pipeline_waves", C.c_int), ("pipeline_ring", C.c_int), ("reserved", C.c_int * 2)]
+                ("pipeline_waves", C.c_int), ("pipeline_ring", C.c_int), ("fixup", C.c_int),
+                ("reserved", C.c_int * 1)]
 
 
 class vef_problem_io(C.Structure):
@@ -158,10 +159,11 @@ def vef_plan_query(problem) -> dict:
 
 def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
                      block: int = 0, timing: bool = False, pipeline_waves: int = 0,
-                     pipeline_ring: int = 0) -> int:
+                     pipeline_ring: int = 0, fixup: bool = False) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
-    opt = vef_options(precision, schedule, block, 1 if timing else 0, pipeline_waves, pipeline_ring)
+    opt = vef_options(precision, schedule, block, 1 if timing else 0, pipeline_waves, pipeline_ring,
+                      1 if fixup else 0)
     h = C.c_void_p()
     rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))
     if rc != VEF_OK:
@@ -265,7 +267,7 @@ class Sweep:
     """Owns one handle; allocates device buffers with torch for convenience."""
 
     def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto",
-                 pipeline_waves=0, pipeline_ring=0):
+                 pipeline_waves=0, pipeline_ring=0, fixup=False):
         import torch
         self.torch = torch
         self.problems = list(problems)
@@ -273,7 +275,8 @@ class Sweep:
         self.device = torch.device("cuda" if device is None else device)
         with torch.cuda.device(self.device):
             self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64,
-                                      SCHEDULES[schedule], block, timing, pipeline_waves, pipeline_ring)
+                                      SCHEDULES[schedule], block, timing, pipeline_waves, pipeline_ring,
+                                      fixup)
         self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
 
     def close(self):
