@@ -54,7 +54,7 @@ class _Prob(C.Structure):
                 ("n_elem", C.c_int), ("n_cp", C.c_int),
                 ("cp_xy", C.c_void_p), ("elem_cp", C.c_void_p),
                 ("n_dir", C.c_int), ("omega", C.c_void_p), ("weight", C.c_void_p),
-                ("sigma_t", C.c_void_p), ("sigma_s", C.c_void_p), ("fixup", C.c_int)]
+                ("sigma_t", C.c_void_p), ("sigma_s", C.c_void_p), ("fixup", C.c_int), ("lag", C.c_int)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -65,15 +65,15 @@ def _setup(L):
     P = C.POINTER(_Prob)
     L.oracle_gl_nodes.argtypes = [C.c_int, _DP]
     L.oracle_gauss_rule.argtypes = [C.c_int, _DP, _DP]
-    L.oracle_sweep.argtypes = [P, _DP, _DP, _DP, _DP, _IP, C.c_int, _DP, _DP, _DP, _IP]
+    L.oracle_sweep.argtypes = [P, _DP, _DP, _DP, _DP, _IP, C.c_int, _DP, _DP, _DP, _DP, _IP]
     L.oracle_boundary_faces.argtypes = [P, _IP]
     L.oracle_qp_coords.argtypes = [P, _DP, _DP, _DP]
     L.oracle_geometry_report.argtypes = [P, _DP, _DP, _DP]
-    L.oracle_levels.argtypes = [P, _IP]
+    L.oracle_levels.argtypes = [P, _IP, _IP]
     L.oracle_moments_from_psi.argtypes = [P, _DP, _DP]
     L.oracle_closures.argtypes = [P, _DP, _DP, _DP, _DP, _DP, _DP, _DP, _DP, _DP, _DP, _IP]
     L.oracle_source_iteration.argtypes = [P, _DP, _DP, _DP, _DP, C.c_int, C.c_double, _DP, _DP,
-                                          _DP, _IP]
+                                          _DP, _IP, _DP]
     for f in ("oracle_gl_nodes", "oracle_gauss_rule", "oracle_sweep", "oracle_boundary_faces",
               "oracle_qp_coords", "oracle_geometry_report", "oracle_levels",
               "oracle_moments_from_psi", "oracle_closures", "oracle_source_iteration"):
@@ -99,7 +99,7 @@ def _f64(a):
 class _Bound:
     """Keeps the numpy arrays behind an oracle_problem struct alive."""
 
-    def __init__(self, pr, nq=None, fixup=False):
+    def __init__(self, pr, nq=None, fixup=False, lag=False):
         self.cp = np.ascontiguousarray(pr.cp_xy, dtype=np.float64)
         self.ec = np.ascontiguousarray(pr.elem_cp, dtype=np.int32)
         self.om = np.ascontiguousarray(pr.omega, dtype=np.float64)
@@ -108,7 +108,8 @@ class _Bound:
         self.ss = np.ascontiguousarray(pr.sigma_s, dtype=np.float64)
         self.s = _Prob(pr.p, pr.m, int(pr.nq if nq is None else nq), self.ec.shape[0], self.cp.shape[0],
                        self.cp.ctypes.data, self.ec.ctypes.data, self.om.shape[0], self.om.ctypes.data,
-                       self.wt.ctypes.data, self.st.ctypes.data, self.ss.ctypes.data, 1 if fixup else 0)
+                       self.wt.ctypes.data, self.st.ctypes.data, self.ss.ctypes.data, 1 if fixup else 0,
+                       1 if lag else 0)
         self.nq = self.s.nq if self.s.nq > 0 else pr.p + pr.m
         self.n = (pr.p + 1) ** 2
         self.Q = self.nq * self.nq
@@ -170,19 +171,31 @@ def geometry_report(pr, nq=None):
     return a.value, c.value, m.value
 
 
-def levels(pr, nq=None):
-    b = _Bound(pr, nq)
+def levels(pr, nq=None, lag=False):
+    b = _Bound(pr, nq, lag=lag)
     out = np.zeros(pr.n_dir, dtype=np.int32)
-    _check(lib().oracle_levels(b.ref, _iptr(out)), "levels")
+    _check(lib().oracle_levels(b.ref, _iptr(out), None), "levels")
+    return out
+
+
+def lagged_couplings(pr, nq=None):
+    """Lagged (element, face) couplings per direction of the lagged sweep order."""
+    b = _Bound(pr, nq, lag=True)
+    lv = np.zeros(pr.n_dir, dtype=np.int32)
+    out = np.zeros(pr.n_dir, dtype=np.int32)
+    _check(lib().oracle_levels(b.ref, _iptr(lv), _iptr(out)), "levels")
     return out
 
 
 def sweep(pr, phi_in=None, dirs=None, want_psi=True, nq=None, q_iso="problem", q_dir="problem",
-          psi_bc="problem", fixup=False):
+          psi_bc="problem", fixup=False, lag=False, psi_prev=None):
     """One sweep.  Returns dict(psi [n_sel,n_elem,n] or None, mom [6,n_elem,n],
     bnd [n_bf,nq,2], levels [n_sel]).  fixup: set-to-zero-and-scale
-    negative-flux fixup after each local solve."""
-    b = _Bound(pr, nq, fixup)
+    negative-flux fixup after each local solve.  lag: cyclic upwind graphs
+    are swept with lagged couplings, which read psi_prev [n_sel,n_elem,n]
+    (None = 0)."""
+    b = _Bound(pr, nq, fixup, lag)
+    psi_prev = _f64(psi_prev)
     q_iso = _f64(pr.q_iso if isinstance(q_iso, str) else q_iso)
     q_dir = _f64(pr.q_dir if isinstance(q_dir, str) else q_dir)
     psi_bc = _f64(pr.psi_bc if isinstance(psi_bc, str) else psi_bc)
@@ -195,7 +208,7 @@ def sweep(pr, phi_in=None, dirs=None, want_psi=True, nq=None, q_iso="problem", q
     bnd = np.zeros((nb, b.nq, 2))
     lv = np.zeros(n_sel, dtype=np.int32)
     rc = lib().oracle_sweep(b.ref, _dptr(phi_in), _dptr(q_iso), _dptr(q_dir), _dptr(psi_bc), _iptr(dl),
-                            n_sel, _dptr(psi), _dptr(mom), _dptr(bnd), _iptr(lv))
+                            n_sel, _dptr(psi_prev), _dptr(psi), _dptr(mom), _dptr(bnd), _iptr(lv))
     _check(rc, "sweep")
     return dict(psi=psi, mom=mom, bnd=bnd, levels=lv)
 
@@ -228,9 +241,16 @@ def closures(pr, mom, bnd, nq=None, q_iso="problem", q_dir="problem", psi_bc="pr
     return dict(E=E, Eb=Eb, Jin=Jin, Q0=Q0, Q1=Q1, n_nonpos=nn.value)
 
 
-def source_iteration(pr, n_iter, tol=0.0, phi0=None, nq=None, fixup=False):
-    """dict(mom [6,n_elem,n] of the last sweep, bnd, resid [iters], iters)."""
-    b = _Bound(pr, nq, fixup)
+def source_iteration(pr, n_iter, tol=0.0, phi0=None, nq=None, fixup=False, lag=False, psi0=None,
+                     want_psi=False):
+    """dict(mom [6,n_elem,n] of the last sweep, bnd, resid [iters], iters, psi).
+    lag: lagged sweeps of cyclic graphs; their first sweep reads psi0
+    [n_dir,n_elem,n] (None = 0).  psi: the last sweep's angular flux when
+    want_psi, else None."""
+    b = _Bound(pr, nq, fixup, lag)
+    psi = None
+    if want_psi or psi0 is not None:
+        psi = np.zeros((pr.n_dir, pr.n_elem, b.n)) if psi0 is None else np.array(psi0, dtype=np.float64)
     nb = n_boundary_faces(pr, nq)
     mom = np.zeros((6, pr.n_elem, b.n))
     bnd = np.zeros((nb, b.nq, 2))
@@ -238,6 +258,6 @@ def source_iteration(pr, n_iter, tol=0.0, phi0=None, nq=None, fixup=False):
     it = C.c_int()
     rc = lib().oracle_source_iteration(b.ref, _dptr(_f64(phi0)), _dptr(_f64(pr.q_iso)), _dptr(_f64(pr.q_dir)),
                                        _dptr(_f64(pr.psi_bc)), int(n_iter), float(tol), _dptr(mom),
-                                       _dptr(bnd), _dptr(res), C.byref(it))
+                                       _dptr(bnd), _dptr(res), C.byref(it), _dptr(psi))
     _check(rc, "source_iteration")
-    return dict(mom=mom, bnd=bnd, resid=res[:it.value], iters=it.value)
+    return dict(mom=mom, bnd=bnd, resid=res[:it.value], iters=it.value, psi=psi if want_psi else None)

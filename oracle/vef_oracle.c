@@ -32,7 +32,16 @@
  *   - dense Gaussian elimination with partial pivoting (first maximal entry);
  *   - optional negative-flux fixup (set to zero and scale, keeping the
  *     element's particle balance), in place of the paper's QP fixup
- *     (Sec. 8.4), which is not reproduced.
+ *     (Sec. 8.4), which is not reproduced;
+ *   - optional lagged sweeps of cyclic upwind graphs (re-entrant faces,
+ *     Sec. 8, thick diffusion limit): the elements are ordered by Kahn's
+ *     algorithm, and when every element left has an unsolved upwind
+ *     neighbour the one with the fewest (lowest id on ties) goes next; an
+ *     upwind neighbour not yet solved in the current sweep contributes its
+ *     angular flux of the previous iterate.  This is block Gauss-Seidel on
+ *     the global upwind system with the strictly upper block triangular part
+ *     (in the sweep order) lagged.  The paper's pseudo-optimal reordering
+ *     (from its graph-sweep reference) is not reproduced.
  *   Parity of the curved-face upwind rule is unpinned beyond its definition.
  */
 #include <math.h>
@@ -62,6 +71,7 @@ typedef struct {
   const double *sigma_t;
   const double *sigma_s;
   int fixup; /* 1: set-to-zero-and-scale negative-flux fixup after each local solve */
+  int lag;   /* 1: cyclic upwind graphs are swept with lagged couplings */
 } oracle_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -368,9 +378,14 @@ static int is_upwind(const conn_t *cn, int e, int f, double ox, double oy) {
 }
 
 /* Kahn topological order of the per-direction upwind graph, FIFO seeded with
- * the sources in increasing element id; level = 1 + max upwind level. */
+ * the sources in increasing element id; level = 1 + max level of the upwind
+ * neighbours solved before.  With pr->lag, when the FIFO runs dry before
+ * every element is ordered, the unordered element with the fewest unordered
+ * upwind neighbours (lowest id on ties) is appended; each of its inflow
+ * faces whose neighbour is still unordered counts as one lagged coupling
+ * (*n_lagged).  Without pr->lag a cycle is an error. */
 static int topo_order(const ctx_t *c, const conn_t *cn, double ox, double oy, int *order,
-                      int *indeg, int *level, int *max_level) {
+                      int *indeg, int *level, int *max_level, int *n_lagged) {
   int ne = c->pr->n_elem;
   for (int e = 0; e < ne; ++e) {
     indeg[e] = 0;
@@ -378,23 +393,35 @@ static int topo_order(const ctx_t *c, const conn_t *cn, double ox, double oy, in
     for (int f = 0; f < 4; ++f)
       if (cn->nbr[4 * e + f] >= 0 && !is_upwind(cn, e, f, ox, oy)) indeg[e]++;
   }
-  int head = 0, tail = 0;
+  int head = 0, tail = 0, lagged = 0;
   for (int e = 0; e < ne; ++e)
     if (indeg[e] == 0) order[tail++] = e;
   int ml = 0;
-  while (head < tail) {
-    int e = order[head++];
-    if (level[e] > ml) ml = level[e];
-    for (int f = 0; f < 4; ++f) {
-      int nb = cn->nbr[4 * e + f];
-      if (nb >= 0 && is_upwind(cn, e, f, ox, oy)) {
-        if (level[e] + 1 > level[nb]) level[nb] = level[e] + 1;
-        if (--indeg[nb] == 0) order[tail++] = nb;
+  for (;;) {
+    while (head < tail) {
+      int e = order[head++];
+      if (level[e] > ml) ml = level[e];
+      for (int f = 0; f < 4; ++f) {
+        int nb = cn->nbr[4 * e + f];
+        /* indeg < 0 marks an element appended by the release rule */
+        if (nb >= 0 && is_upwind(cn, e, f, ox, oy) && indeg[nb] > 0) {
+          if (level[e] + 1 > level[nb]) level[nb] = level[e] + 1;
+          if (--indeg[nb] == 0) order[tail++] = nb;
+        }
       }
     }
+    if (tail == ne) break;
+    if (!c->pr->lag) return ORACLE_ERR_CYCLE;
+    int best = -1;
+    for (int e = 0; e < ne; ++e)
+      if (indeg[e] > 0 && (best < 0 || indeg[e] < indeg[best])) best = e;
+    lagged += indeg[best];
+    indeg[best] = -1;
+    order[tail++] = best;
   }
   if (max_level) *max_level = ml;
-  return tail == ne ? ORACLE_OK : ORACLE_ERR_CYCLE;
+  if (n_lagged) *n_lagged = lagged;
+  return ORACLE_OK;
 }
 
 /* Gaussian elimination with partial pivoting (first maximal |a| wins). */
@@ -459,9 +486,13 @@ static void zero_and_scale(int n, const double *c, double *x) {
   for (int j = 0; j < n; ++j) x[j] = x[j] > 0.0 ? alpha * x[j] : 0.0;
 }
 
+/* Local solve of element e for direction d.  psi_d holds the angular flux of
+ * the elements solved so far in this sweep (solved[] = 1); an upwind
+ * neighbour not solved yet (a lagged coupling) is read from psi_prev_d, the
+ * previous iterate of the same direction (NULL = 0). */
 static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const double *phi_in,
                        const double *q_iso, const double *q_dir, const double *psi_bc,
-                       double *psi_d) {
+                       double *psi_d, const double *psi_prev_d, const unsigned char *solved) {
   const oracle_problem *pr = c->pr;
   int n = c->n, nq = c->nq;
   double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1];
@@ -527,7 +558,8 @@ static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const dou
         if (nb >= 0) {
           double s2 = cn->nbr_rev[4 * e + f] ? 1.0 - s : s, xi2, eta2;
           face_point(cn->nbr_face[4 * e + f], s2, &xi2, &eta2);
-          up = dg_eval(c, psi_d + (size_t)nb * n, xi2, eta2);
+          const double *src = solved[nb] ? psi_d : psi_prev_d;
+          up = src ? dg_eval(c, src + (size_t)nb * n, xi2, eta2) : 0.0;
         } else {
           int bf = cn->bf_id[4 * e + f];
           up = psi_bc ? psi_bc[((size_t)d * cn->n_bf + bf) * nq + qs] : 0.0;
@@ -557,6 +589,8 @@ static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const dou
  *   q_iso   [n_elem][n]    isotropic source, nodal (NULL = 0)
  *   q_dir   [n_dir][n_elem][Q] source at volume quadrature points (NULL = 0)
  *   psi_bc  [n_dir][n_bf][nq] inflow data at boundary-face points (NULL = 0)
+ *   psi_prev [n_sel][n_elem][n] previous iterate, read by lagged couplings
+ *           only (NULL = 0)
  * outputs (each may be NULL):
  *   psi_out [n_sel][n_elem][n], mom [6][n_elem][n] (phi, Jx, Jy, Pxx, Pxy,
  *   Pyy summed over the selected directions in list order),
@@ -564,7 +598,7 @@ static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const dou
  *   interior trace), levels [n_sel] (1 + deepest level). */
 int oracle_sweep(const oracle_problem *pr, const double *phi_in, const double *q_iso,
                  const double *q_dir, const double *psi_bc, const int *dir_list, int n_sel,
-                 double *psi_out, double *mom, double *bnd_acc, int *levels) {
+                 const double *psi_prev, double *psi_out, double *mom, double *bnd_acc, int *levels) {
   ctx_t c;
   int rc = ctx_init(&c, pr);
   if (rc) return rc;
@@ -576,7 +610,8 @@ int oracle_sweep(const oracle_problem *pr, const double *phi_in, const double *q
   double *psi_d = (double *)calloc((size_t)ne * n, sizeof(double));
   int *order = (int *)malloc(sizeof(int) * ne), *indeg = (int *)malloc(sizeof(int) * ne),
       *lev = (int *)malloc(sizeof(int) * ne);
-  if (!psi_d || !order || !indeg || !lev) { rc = ORACLE_ERR_OOM; goto done; }
+  unsigned char *solved = (unsigned char *)malloc(ne);
+  if (!psi_d || !order || !indeg || !lev || !solved) { rc = ORACLE_ERR_OOM; goto done; }
   if (mom) memset(mom, 0, sizeof(double) * 6 * (size_t)ne * n);
   if (bnd_acc) memset(bnd_acc, 0, sizeof(double) * 2 * (size_t)cn.n_bf * nq);
   for (int k = 0; k < n_sel; ++k) {
@@ -584,10 +619,15 @@ int oracle_sweep(const oracle_problem *pr, const double *phi_in, const double *q
     if (d < 0 || d >= pr->n_dir) { rc = ORACLE_ERR_INVALID; goto done; }
     double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1], w = pr->weight[d];
     int ml;
-    if ((rc = topo_order(&c, &cn, ox, oy, order, indeg, lev, &ml))) goto done;
+    if ((rc = topo_order(&c, &cn, ox, oy, order, indeg, lev, &ml, NULL))) goto done;
     if (levels) levels[k] = ml + 1;
-    for (int t = 0; t < ne; ++t)
-      if ((rc = local_solve(&c, &cn, order[t], d, phi_in, q_iso, q_dir, psi_bc, psi_d))) goto done;
+    memset(solved, 0, ne);
+    const double *prev = psi_prev ? psi_prev + (size_t)k * ne * n : NULL;
+    for (int t = 0; t < ne; ++t) {
+      if ((rc = local_solve(&c, &cn, order[t], d, phi_in, q_iso, q_dir, psi_bc, psi_d, prev, solved)))
+        goto done;
+      solved[order[t]] = 1;
+    }
     if (psi_out) memcpy(psi_out + (size_t)k * ne * n, psi_d, sizeof(double) * (size_t)ne * n);
     if (mom) {
       double fac[6] = {1.0, ox, oy, ox * ox, ox * oy, oy * oy};
@@ -614,7 +654,7 @@ int oracle_sweep(const oracle_problem *pr, const double *phi_in, const double *q
     }
   }
 done:
-  free(psi_d); free(order); free(indeg); free(lev);
+  free(psi_d); free(order); free(indeg); free(lev); free(solved);
   conn_free(&cn);
   return rc;
 }
@@ -719,8 +759,9 @@ int oracle_geometry_report(const oracle_problem *pr, double *area, double *max_c
   return ORACLE_OK;
 }
 
-/* Upwind-graph depth per direction (number of levels). */
-int oracle_levels(const oracle_problem *pr, int *levels) {
+/* Upwind-graph depth per direction (number of levels of the sweep order) and,
+ * when n_lagged is given, the lagged couplings per direction. */
+int oracle_levels(const oracle_problem *pr, int *levels, int *n_lagged) {
   ctx_t c;
   int rc = ctx_init(&c, pr);
   if (rc) return rc;
@@ -732,8 +773,10 @@ int oracle_levels(const oracle_problem *pr, int *levels) {
   if (!order || !indeg || !lev) rc = ORACLE_ERR_OOM;
   for (int d = 0; !rc && d < pr->n_dir; ++d) {
     int ml;
-    rc = topo_order(&c, &cn, pr->omega[2 * d], pr->omega[2 * d + 1], order, indeg, lev, &ml);
+    int nl = 0;
+    rc = topo_order(&c, &cn, pr->omega[2 * d], pr->omega[2 * d + 1], order, indeg, lev, &ml, &nl);
     if (!rc) levels[d] = ml + 1;
+    if (!rc && n_lagged) n_lagged[d] = nl;
   }
   free(order); free(indeg); free(lev);
   conn_free(&cn);
@@ -846,10 +889,14 @@ int oracle_closures(const oracle_problem *pr, const double *mom, const double *b
 /* Source iteration: phi^0 = phi0 (NULL = 0); phi^{k+1} = phi of the sweep
  * driven by phi^k; r_k = max_j |phi^{k+1}_j - phi^k_j| (max norm of successive
  * iterates); stops after n_iter sweeps or when r_k < tol (tol > 0).
- * mom receives the moments of the last sweep, resid [n_iter] the history. */
+ * mom receives the moments of the last sweep, resid [n_iter] the history.
+ * psi_io [n_dir][n_elem][n] (may be NULL): on entry the iterate that lagged
+ * couplings of the first sweep read (NULL = 0), on exit the angular flux of
+ * the last sweep. */
 int oracle_source_iteration(const oracle_problem *pr, const double *phi0, const double *q_iso,
                             const double *q_dir, const double *psi_bc, int n_iter, double tol,
-                            double *mom, double *bnd_acc, double *resid, int *iters_done) {
+                            double *mom, double *bnd_acc, double *resid, int *iters_done,
+                            double *psi_io) {
   ctx_t c;
   int rc = ctx_init(&c, pr);
   if (rc) return rc;
@@ -857,10 +904,25 @@ int oracle_source_iteration(const oracle_problem *pr, const double *phi0, const 
   double *phi = (double *)calloc(N, sizeof(double));
   if (!phi) return ORACLE_ERR_OOM;
   if (phi0) memcpy(phi, phi0, sizeof(double) * N);
+  /* previous and current angular flux, kept only when some sweep reads or
+   * returns it */
+  double *prev = NULL, *cur = NULL;
+  if (pr->lag || psi_io) {
+    prev = (double *)calloc(N * pr->n_dir, sizeof(double));
+    cur = (double *)calloc(N * pr->n_dir, sizeof(double));
+    if (!prev || !cur) {
+      free(phi); free(prev); free(cur);
+      return ORACLE_ERR_OOM;
+    }
+    if (psi_io) memcpy(prev, psi_io, sizeof(double) * N * pr->n_dir);
+  }
   int k = 0;
   for (; k < n_iter; ++k) {
-    rc = oracle_sweep(pr, phi, q_iso, q_dir, psi_bc, NULL, 0, NULL, mom, bnd_acc, NULL);
+    rc = oracle_sweep(pr, phi, q_iso, q_dir, psi_bc, NULL, 0, prev, cur, mom, bnd_acc, NULL);
     if (rc) break;
+    double *t = prev;
+    prev = cur;
+    cur = t;
     double r = 0.0;
     for (size_t i = 0; i < N; ++i) {
       double dlt = fabs(mom[i] - phi[i]);
@@ -871,6 +933,7 @@ int oracle_source_iteration(const oracle_problem *pr, const double *phi0, const 
     if (tol > 0.0 && r < tol) { ++k; break; }
   }
   if (iters_done) *iters_done = k;
-  free(phi);
+  if (psi_io && !rc) memcpy(psi_io, prev, sizeof(double) * N * pr->n_dir);
+  free(phi); free(prev); free(cur);
   return rc;
 }

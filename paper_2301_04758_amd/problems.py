@@ -148,6 +148,37 @@ def sine_warp(cp_xy: np.ndarray, amp: float, k: float = 1.0) -> np.ndarray:
     return out
 
 
+def taylor_green_mesh(n: int, m: int = 3, t_final: float = 0.3 * math.pi, steps: int = 300,
+                      vortices: int = 1):
+    """n-by-n order-m mesh of the unit square distorted by the Taylor-Green
+    vortex (Sec. 8, method of manufactured solutions): every control point is
+    advected by v = (sin x cos y, -cos x sin y) up to t_final with `steps`
+    forward Euler steps.
+
+    The printed velocity has no factor pi while the domain is the unit square;
+    the reading used here advects on [0, pi]^2, where v . n = 0 on the
+    boundary, and maps back to [0,1]^2, so the printed velocity and final
+    time stand and boundary points slide along the boundary.  `vortices` > 1
+    tiles vortices-by-vortices such cells (alternating sense of rotation), each
+    covering n/vortices elements per side.  Longer t_final on coarse cells
+    gives meshes with re-entrant faces (cyclic upwind graphs), like the
+    Lagrangian-hydrodynamics mesh of the thick-diffusion-limit study.
+    Returns (cp_xy, elem_cp) like quad_mesh."""
+    cp, ec = quad_mesh(n, n, m)
+    scale = math.pi * vortices
+    y = cp * scale
+    dt = t_final / steps
+    for _ in range(steps):
+        v = np.stack([np.sin(y[:, 0]) * np.cos(y[:, 1]), -np.cos(y[:, 0]) * np.sin(y[:, 1])], axis=1)
+        y = y + dt * v
+    out = y / scale
+    # boundary points stay on their side (v . n = 0 there up to rounding)
+    for k in range(2):
+        out[np.abs(cp[:, k]) == 0.0, k] = 0.0
+        out[cp[:, k] == 1.0, k] = 1.0
+    return np.ascontiguousarray(out), ec
+
+
 # --------------------------------------------------------------------------
 # level-symmetric angular sets
 # --------------------------------------------------------------------------
@@ -307,6 +338,30 @@ def make_problem(name, nx, ny, p, m, N, sigma_t, sigma_s, q=1.0, warp=0.0):
     ss = np.broadcast_to(np.asarray(sigma_s, dtype=np.float64), (nx * ny,)).copy()
     return Problem(name=name, p=p, m=m, cp_xy=cp, elem_cp=ec, omega=om, weight=wt,
                    sigma_t=st, sigma_s=ss, q_iso=_const_source(nx * ny, p, q), nx=nx, ny=ny)
+
+
+def make_tg_problem(name, n, p, m, N, sigma_t, sigma_s, q=1.0, t_final=0.3 * math.pi, vortices=1):
+    """Problem on taylor_green_mesh(n, m, t_final, vortices=vortices) with an
+    isotropic source q and vacuum inflow."""
+    cp, ec = taylor_green_mesh(n, m, t_final, vortices=vortices)
+    om, wt = level_symmetric_2d(N)
+    st = np.broadcast_to(np.asarray(sigma_t, dtype=np.float64), (n * n,)).copy()
+    ss = np.broadcast_to(np.asarray(sigma_s, dtype=np.float64), (n * n,)).copy()
+    return Problem(name=name, p=p, m=m, cp_xy=cp, elem_cp=ec, omega=om, weight=wt,
+                   sigma_t=st, sigma_s=ss, q_iso=_const_source(n * n, p, q), nx=n, ny=n)
+
+
+def reentrant_tg(n: int = 64, p: int = 2, N: int = 8, seed: Optional[int] = None):
+    """Workload with re-entrant faces: n-by-n cubic (m = 3) Taylor-Green mesh
+    of (n/8)^2 vortex cells of 8x8 elements advected to t = pi, p, S_N,
+    sigma_t log-uniform [0.1, 100] per 8x8 block, c = 0.9, unit isotropic
+    source, vacuum.  Its upwind graphs are cyclic for most directions."""
+    if n % 8:
+        raise ValueError("n must be a multiple of 8")
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7 if seed is None else seed))
+    st = block_log_uniform(n, n, 8, 0.1, 100.0, rng)
+    return make_tg_problem("tg_reentrant_%d" % n, n, p, 3, N, st, 0.9 * st, t_final=math.pi,
+                           vortices=n // 8)
 
 
 CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")

@@ -1,0 +1,351 @@
+"""Sweeps of cyclic upwind graphs with lagged couplings (re-entrant faces,
+Sec. 8, thick diffusion limit on the triple-point mesh: the strictly upper
+block triangular part of the streaming-collision operator is lagged).
+
+CPU pins of the oracle's lagged sweep:
+  * acyclic graphs: the lag option changes nothing, bit for bit;
+  * one lagged sweep is one block Gauss-Seidel step on the dense global upwind
+    system (independent numpy assembly), in the order of the release rule;
+  * the release rule lags a minimum feedback arc set on the 3x3 fixture
+    (brute force over arc subsets);
+  * fixed points: repeated lagged sweeps converge to the direct global solve,
+    and lagged source iteration to the coupled scattering solution;
+  * the Taylor-Green mesh generator: unit area, constant preservation.
+Host: the library's plan lags as many couplings as the oracle.
+GPU: parity of lagged source iterations with the oracle (fixture, Taylor-Green
+meshes with re-entrant faces, both schedules, FP64 and FP32-local, runs that
+continue earlier runs, the full-size workload).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import dg_numpy as D
+from cyclic_mesh import reentrant_problem
+from oracle import oracle as O
+from paper_2301_04758_amd import problems as P
+
+RNG = np.random.default_rng(20230111)
+
+
+def _with_source(pr, q=1.0, ss=None):
+    n = (pr.p + 1) ** 2
+    pr.q_iso = np.full((pr.n_elem, n), q)
+    if ss is not None:
+        pr.sigma_s = np.full(pr.n_elem, float(ss))
+    return pr
+
+
+def _fixture(p=2, ss=0.0):
+    """The 3x3 re-entrant fixture; its Jacobian stays positive at up to 4x4
+    Gauss points, so p = 3 uses nq = 4."""
+    pr = reentrant_problem(p)
+    if p >= 3:
+        pr.nq = 4
+    return _with_source(pr, ss=ss)
+
+
+def _tg(n=8, p=2, N=4, t_final=math.pi, vortices=1, st=1.0, ss=0.0):
+    return P.make_tg_problem("tg", n, p, 3, N, st, ss, t_final=t_final, vortices=vortices)
+
+
+# ------------------------------------------------------------ graph helpers
+
+
+def _upwind_graph(pr, d):
+    """Arcs (u, v, face of v) of the upwind relation of direction d from the
+    independent numpy mesh: u is upwind of v across face f of v."""
+    M = D.Mesh(pr)
+    om = np.asarray(pr.omega[d], dtype=float)
+    arcs = []
+    for (e, f), (e2, f2) in M.nbr.items():
+        if not M.upwind_is_self(e, f, om):
+            arcs.append((e2, e, f))
+    return arcs
+
+
+def _release_order(ne, arcs):
+    """Kahn's algorithm, FIFO from sources in id order; when stuck, release the
+    unordered element with the fewest unordered upwind neighbours (lowest id
+    on ties).  Returns (order, lagged arcs)."""
+    ups = {v: [] for v in range(ne)}
+    downs = {v: [] for v in range(ne)}
+    for u, v, f in arcs:
+        ups[v].append(u)
+        downs[u].append(v)
+    indeg = {v: len(ups[v]) for v in range(ne)}
+    placed = set()
+    order = [v for v in range(ne) if indeg[v] == 0]
+    placed.update(order)
+    lagged = []
+    head = 0
+    while True:
+        while head < len(order):
+            u = order[head]
+            head += 1
+            for v in downs[u]:
+                if v in placed:
+                    continue
+                indeg[v] -= 1
+                if indeg[v] == 0:
+                    order.append(v)
+                    placed.add(v)
+        if len(order) == ne:
+            return order, lagged
+        best = min((v for v in range(ne) if v not in placed), key=lambda v: (indeg[v], v))
+        lagged += [(u, best) for u in ups[best] if u not in placed]
+        order.append(best)
+        placed.add(best)
+
+
+def _is_acyclic(ne, arcs):
+    indeg = [0] * ne
+    for u, v in arcs:
+        indeg[v] += 1
+    stack = [v for v in range(ne) if indeg[v] == 0]
+    seen = 0
+    while stack:
+        u = stack.pop()
+        seen += 1
+        for a, b in arcs:
+            if a == u:
+                indeg[b] -= 1
+                if indeg[b] == 0:
+                    stack.append(b)
+    return seen == ne
+
+
+# ---------------------------------------------------------------- CPU pins
+
+
+def test_lag_changes_nothing_on_acyclic_graphs():
+    """Lagged couplings exist only on cycles: on acyclic graphs (straight and
+    Taylor-Green m = 3 meshes) the lagged sweep, fed an arbitrary previous
+    iterate, reproduces the plain sweep bit for bit."""
+    for pr in (_with_source(P.make_problem("s", 4, 4, 2, 1, 4, 1.0, 0.3)), _tg(4, 2, 4, t_final=0.3 * math.pi)):
+        assert not O.lagged_couplings(pr).any()
+        prev = RNG.normal(size=(pr.n_dir, pr.n_elem, (pr.p + 1) ** 2))
+        phi = RNG.uniform(0.5, 1.5, size=(pr.n_elem, (pr.p + 1) ** 2))
+        a = O.sweep(pr, phi_in=phi)
+        b = O.sweep(pr, phi_in=phi, lag=True, psi_prev=prev)
+        assert np.array_equal(a["psi"], b["psi"]) and np.array_equal(a["mom"], b["mom"])
+
+
+def test_plain_sweep_rejects_cycles():
+    pr = _fixture()
+    with pytest.raises(O.OracleError) as e:
+        O.sweep(pr)
+    assert e.value.code == O.ERR_CYCLE
+
+
+def test_release_rule_lags_a_minimum_feedback_arc_set():
+    """On the fixture, the couplings lagged per direction are as few as any
+    ordering allows (brute force over subsets of the arcs)."""
+    pr = _fixture()
+    counts = O.lagged_couplings(pr)
+    for d in range(pr.n_dir):
+        arcs = [(u, v) for u, v, _ in _upwind_graph(pr, d)]
+        best = None
+        for k in range(len(arcs) + 1):
+            if any(_is_acyclic(pr.n_elem, [a for i, a in enumerate(arcs) if i not in drop])
+                   for drop in itertools.combinations(range(len(arcs)), k)):
+                best = k
+                break
+        assert counts[d] == best
+    assert counts[0] >= 1 and counts[1] == 0
+
+
+@pytest.mark.parametrize("which", ["fixture", "tg"])
+def test_one_lagged_sweep_is_a_block_gauss_seidel_step(which):
+    """psi_new = (D + L)^{-1} (b - U psi_prev) on the dense global system of
+    each direction, with L / U the couplings to elements before / after in
+    the release order (independent numpy assembly and ordering).  Bound:
+    a backward-stable solve, 16 eps cond(D + L) relative (1e-12 at least);
+    the cubic Taylor-Green elements at t = pi are nearly degenerate, with
+    cond(D + L) up to about 1e6."""
+    pr = _fixture(p=2) if which == "fixture" else _with_source(_tg(8, 1, 8))
+    ne, n = pr.n_elem, (pr.p + 1) ** 2
+    assert O.lagged_couplings(pr).sum() > 0
+    prev = RNG.normal(size=(pr.n_dir, ne, n))
+    got = O.sweep(pr, lag=True, psi_prev=prev)["psi"]
+    for d in range(pr.n_dir):
+        order, lagged = _release_order(ne, _upwind_graph(pr, d))
+        A, b = D.global_system(pr, d, q_iso=pr.q_iso, nq=pr.nq or None)
+        pos = np.empty(ne, dtype=int)
+        pos[order] = np.arange(ne)
+        blk_later = np.repeat(pos, n)[None, :] > np.repeat(pos, n)[:, None]
+        U = np.where(blk_later, A, 0.0)
+        x = np.linalg.solve(A - U, b - U @ prev[d].ravel()).reshape(ne, n)
+        tol = max(1e-12, 16 * np.finfo(float).eps * np.linalg.cond(A - U))
+        assert np.abs(got[d] - x).max() <= tol * max(1.0, np.abs(x).max()), d
+
+
+def test_lagged_sweeps_converge_to_the_global_solve():
+    """Without scattering, repeated lagged sweeps are block Gauss-Seidel and
+    reach the direct solution of the global upwind system."""
+    pr = _fixture(p=3)
+    ne, n = pr.n_elem, 16
+    prev = np.zeros((pr.n_dir, ne, n))
+    for _ in range(30):
+        prev = O.sweep(pr, lag=True, psi_prev=prev)["psi"]
+    for d in range(pr.n_dir):
+        x = D.global_solve(pr, d, q_iso=pr.q_iso, nq=pr.nq or None)
+        assert np.abs(prev[d] - x).max() <= 1e-12 * np.abs(x).max()
+
+
+def test_lagged_source_iteration_reaches_the_coupled_solution():
+    """Lagged source iteration has the same fixed point as the exact one: the
+    solution with the scattering source implicit."""
+    pr = _fixture(p=1, ss=0.5)
+    r = O.source_iteration(pr, 80, lag=True)
+    ref = D.coupled_scattering_solve(pr, q_iso=pr.q_iso, nq=pr.nq or None)
+    assert np.abs(r["mom"][0] - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_source_iteration_resumes_from_psi():
+    """Two lagged source iterations, the second starting from the first's
+    angular flux and scalar flux, equal one longer iteration."""
+    pr = _fixture(p=1, ss=0.5)
+    a = O.source_iteration(pr, 5, lag=True)
+    b1 = O.source_iteration(pr, 2, lag=True, want_psi=True)
+    b2 = O.source_iteration(pr, 3, lag=True, phi0=b1["mom"][0], psi0=b1["psi"])
+    assert np.array_equal(a["mom"], b2["mom"])
+
+
+def test_taylor_green_mesh_area_and_constants():
+    """The advected mesh still tiles the unit square (boundary points slide
+    along the boundary): element areas sum to 1; a pure absorber with a
+    constant source keeps psi = q / sigma_t on it (constant preservation)."""
+    # at t = pi the block triangular system a sweep solves has condition
+    # numbers near 1e6 (rounding grows along the upwind chains through the
+    # stretched elements), so only the well-conditioned mesh gets 1e-12
+    for n, vort, t, tol in ((8, 1, 0.3 * math.pi, 1e-12), (16, 2, math.pi, 1e-7)):
+        pr = _tg(n, 2, 4, t_final=t, vortices=vort, st=2.0)
+        area, _, _ = O.geometry_report(pr)
+        assert abs(area - 1.0) < 1e-13
+        pr.q_iso = np.full((pr.n_elem, 9), 3.0)
+        pr.psi_bc = np.full((pr.n_dir, O.n_boundary_faces(pr), pr.p + pr.m), 1.5)
+        lag = bool(O.lagged_couplings(pr).any())
+        prev = np.full((pr.n_dir, pr.n_elem, 9), 1.5)
+        psi = O.sweep(pr, lag=lag, psi_prev=prev)["psi"]
+        assert np.abs(psi - 1.5).max() < tol
+
+
+# ------------------------------------------------------------------- host
+
+
+def _vef():
+    try:
+        from paper_2301_04758_amd import vef
+    except ImportError as e:
+        pytest.skip("library not built: %s" % e)
+    return vef
+
+
+def test_plan_lags_as_many_couplings_as_the_oracle():
+    vef = _vef()
+    for pr in (_fixture(), _tg(8, 2, 8), P.reentrant_tg(16)):
+        want = int(O.lagged_couplings(pr).sum())
+        assert want > 0
+        assert vef.vef_plan_query(pr, lag_cycles=True)["n_lagged"] == want
+        with pytest.raises(vef.VefError) as e:
+            vef.vef_plan_query(pr)
+        assert e.value.code == vef.VEF_ERR_CYCLE
+    pr = _tg(8, 2, 8, t_final=0.3 * math.pi)
+    assert vef.vef_plan_query(pr, lag_cycles=True)["n_lagged"] == 0
+
+
+# -------------------------------------------------------------------- GPU
+
+
+def _gpu_si(pr, n_iter, precision, schedule, psi0=None, phi0=None, internal=False, sw=None):
+    import torch
+    from paper_2301_04758_amd import vef
+    own = sw is None
+    if own:
+        sw = vef.Sweep([pr], precision=precision, schedule=schedule, lag_cycles=True)
+    io = sw.buffers(n_iter=n_iter, store_psi=not internal)
+    if psi0 is not None:
+        io[0]["psi_out"].copy_(torch.as_tensor(psi0).to(io[0]["psi_out"].dtype))
+    elif not internal:
+        io[0]["psi_out"].zero_()
+    if phi0 is not None:
+        io[0]["phi_in"] = torch.as_tensor(phi0, dtype=torch.float64, device=sw.device)
+    sw.run(io, n_iter=n_iter)
+    torch.cuda.synchronize()
+    sw.check()
+    out = dict(mom=io[0]["mom"].double().cpu().numpy(),
+               psi=None if internal else io[0]["psi_out"].double().cpu().numpy(),
+               resid=io[0]["resid"].cpu().numpy(), info=sw.info[0])
+    if own:
+        sw.close()
+    return out
+
+
+def _tol(precision):
+    return 1e-12 if precision == "fp64" else 1e-5
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("schedule", ["level", "dir"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_lagged_parity_fixture(p, schedule, precision):
+    pr = _fixture(p=p, ss=0.5)
+    ref = O.source_iteration(pr, 6, lag=True, want_psi=True)
+    got = _gpu_si(pr, 6, precision, schedule)
+    assert got["info"]["n_lagged"] == int(O.lagged_couplings(pr).sum())
+    assert _rel(got["mom"], ref["mom"]) <= _tol(precision)
+    assert _rel(got["psi"], ref["psi"]) <= _tol(precision)
+    assert np.abs(got["resid"] - ref["resid"]).max() <= _tol(precision) * np.abs(ref["mom"][0]).max()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("schedule", ["level", "dir"])
+def test_lagged_parity_taylor_green(schedule, precision):
+    """16x16 cubic Taylor-Green mesh of 2x2 vortex cells at t = pi (re-entrant
+    faces for most directions), p = 2, S8, c = 0.9."""
+    pr = P.reentrant_tg(16)
+    assert O.lagged_couplings(pr).sum() > 0
+    ref = O.source_iteration(pr, 4, lag=True, want_psi=True)
+    got = _gpu_si(pr, 4, precision, schedule)
+    assert _rel(got["mom"], ref["mom"]) <= _tol(precision)
+    assert _rel(got["psi"], ref["psi"]) <= _tol(precision)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("internal", [False, True])
+def test_lagged_runs_continue(internal):
+    """A run continues from the angular flux the previous run left (in the
+    caller's psi_out, or in the handle when psi_out is NULL): 2 + 3 sweeps
+    equal 5."""
+    from paper_2301_04758_amd import vef
+    pr = _fixture(p=2, ss=0.5)
+    ref = O.source_iteration(pr, 5, lag=True)
+    sw = vef.Sweep([pr], precision="fp64", schedule="dir", lag_cycles=True)
+    try:
+        a = _gpu_si(pr, 2, "fp64", "dir", internal=internal, sw=sw)
+        b = _gpu_si(pr, 3, "fp64", "dir", psi0=a["psi"], phi0=a["mom"][0], internal=internal, sw=sw)
+    finally:
+        sw.close()
+    assert _rel(b["mom"], ref["mom"]) <= 1e-12
+
+
+@pytest.mark.gpu
+def test_lagged_parity_full_size():
+    """The 64x64 re-entrant workload (p = 2, S8, 22% of the element-direction
+    pairs lagged), three source iterations, FP64 and FP32-local, every value
+    against the oracle."""
+    pr = P.reentrant_tg(64)
+    ref = O.source_iteration(pr, 3, lag=True)
+    for precision in ("fp64", "fp32"):
+        got = _gpu_si(pr, 3, precision, "auto")
+        assert got["info"]["n_lagged"] > 0.2 * pr.n_elem * pr.n_dir
+        assert _rel(got["mom"], ref["mom"]) <= _tol(precision), precision
