@@ -390,16 +390,36 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
   T rhs = T(0);
   const T *g5 = area + S::OFF_GEO;
   const T *srcq = area + S::OFF_SRC;
+  // A[(c,d)] = sum_q coef_q V_(c,d)(q) with the tensor basis V_(c,d)(qx,qy) =
+  // v1[qx][c] v1[qy][d] (v1 = the face table sF), summed by factors:
+  // first over qx for each qy (P1 values), then over qy.
 #pragma unroll S::QU
-  for (int q = 0; q < Q; ++q) {
-    const T wJ = g5[5 * q], a00 = g5[5 * q + 1], a01 = g5[5 * q + 2], a10 = g5[5 * q + 3], a11 = g5[5 * q + 4];
-    const T gx = a00 * ox + a01 * oy;
-    const T gy = a10 * ox + a11 * oy;
-    const T li = sV[q * N + rr];
-    const T c = st * wJ * li - (gx * sDx[q * N + rr] + gy * sDy[q * N + rr]);
-    rhs += wJ * li * srcq[q];
+  for (int qy = 0; qy < NQ; ++qy) {
+    T coef[NQ];
 #pragma unroll
-    for (int j = 0; j < N; ++j) A[j] += c * sV[q * N + j];
+    for (int qx = 0; qx < NQ; ++qx) {
+      const int q = qx + NQ * qy;
+      const T wJ = g5[5 * q], a00 = g5[5 * q + 1], a01 = g5[5 * q + 2], a10 = g5[5 * q + 3], a11 = g5[5 * q + 4];
+      const T gx = a00 * ox + a01 * oy;
+      const T gy = a10 * ox + a11 * oy;
+      const T li = sV[q * N + rr];
+      coef[qx] = st * wJ * li - (gx * sDx[q * N + rr] + gy * sDy[q * N + rr]);
+      rhs += wJ * li * srcq[q];
+    }
+    T trow[P1];
+#pragma unroll
+    for (int c = 0; c < P1; ++c) {
+      T acc = T(0);
+#pragma unroll
+      for (int qx = 0; qx < NQ; ++qx) acc += coef[qx] * sF[qx * P1 + c];
+      trow[c] = acc;
+    }
+#pragma unroll
+    for (int dd = 0; dd < P1; ++dd) {
+      const T vd = sF[qy * P1 + dd];
+#pragma unroll
+      for (int c = 0; c < P1; ++c) A[c + P1 * dd] += vd * trow[c];
+    }
   }
 
   // face terms
