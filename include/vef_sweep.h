@@ -56,7 +56,8 @@ typedef struct vef_sweep vef_sweep_t;
 enum {
   VEF_OK = 0,
   VEF_ERR_INVALID = -1,  /* bad argument, size or mesh */
-  VEF_ERR_CYCLE = -2,    /* upwind graph of some direction is cyclic */
+  VEF_ERR_CYCLE = -2,    /* upwind graph of some direction is cyclic (and
+                            vef_options.cycles is VEF_CYCLES_REJECT) */
   VEF_ERR_JACOBIAN = -3, /* element map with J <= 0 at a quadrature point */
   VEF_ERR_HIP = -4,      /* HIP runtime failure (no device, launch error) */
   VEF_ERR_OOM = -5,      /* device or host allocation failed */
@@ -64,6 +65,11 @@ enum {
 };
 
 enum { VEF_FP64 = 0, VEF_FP32_LOCAL = 1 };
+enum {
+  VEF_CYCLES_REJECT = 0, /* a cyclic upwind graph fails with VEF_ERR_CYCLE */
+  VEF_CYCLES_LAG = 1     /* a cyclic upwind graph is swept with lagged
+                            couplings (vef_options.cycles) */
+};
 enum {
   VEF_SCHEDULE_AUTO = 0, /* VEF_DIR_RESIDENT when every problem's mean level
                             width fits one round of a work-group, else
@@ -118,7 +124,25 @@ typedef struct {
                     u = 1) is unchanged; non-negative solutions are untouched.
                     A simpler stand-in for the paper's QP fixup (Sec. 8.4).
                     0 = off (default) */
-  int reserved[1];
+  int cycles;        /* what a cyclic upwind graph (re-entrant faces; Sec. 8,
+                    thick diffusion limit, triple-point mesh) does:
+                    VEF_CYCLES_REJECT (default): create fails with
+                    VEF_ERR_CYCLE.  VEF_CYCLES_LAG: the sweep lags the
+                    couplings that close cycles (the strictly upper block
+                    triangular part of the streaming-collision operator in
+                    the sweep order).  The order per direction: Kahn's
+                    algorithm on the upwind graph; whenever every element
+                    left has an unsolved upwind neighbour, the one with the
+                    fewest (lowest id on ties) is released, and its inflow
+                    faces from unsolved neighbours become lagged.  A lagged
+                    face reads the upwind element's angular flux as it was
+                    before the sweep: the previous sweep of the run, and for
+                    the first sweep of a run the contents of psi_out on entry
+                    (zero it to start from zero), or, when psi_out is NULL,
+                    the handle's own copy from the last run (zero after
+                    create).  Acyclic graphs are swept exactly as with
+                    VEF_CYCLES_REJECT.  The pipelined kernel is not used for a
+                    problem with lagged faces. */
 } vef_options;
 
 /* Per-problem device buffers of one run (device pointers owned by the caller).
@@ -132,7 +156,9 @@ typedef struct {
   const double *psi_bc; /* [n_dir][n_bf][nq] inflow data at boundary points; NULL = vacuum */
   double *mom;          /* [6][n_elem][n] out: phi, Jx, Jy, Pxx, Pxy, Pyy (nodal) */
   void *psi_out;        /* [n_dir][n_elem][n] out: angular flux, double (VEF_FP64)
-                           or float (VEF_FP32_LOCAL); NULL = kept internally */
+                           or float (VEF_FP32_LOCAL); NULL = kept internally.
+                           With lagged faces (vef_options.cycles) also an
+                           input: the previous iterate for the first sweep */
   double *resid;        /* [n_iter] out: max_j |phi_new_j - phi_in_j| per sweep; may be NULL */
 } vef_problem_io;
 
@@ -180,6 +206,8 @@ typedef struct {
                     vef_plan_query: VEF_SCHEDULE_AUTO */
   int kernel;    /* vef_problem_info: sweep kernel of this problem,
                     VEF_KERNEL_*; vef_plan_query: -1 */
+  long long n_lagged; /* lagged (direction, element, face) couplings; 0 for
+                    acyclic upwind graphs */
 } vef_info;
 
 /* Sweep kernels (vef_info.kernel). */
@@ -191,7 +219,7 @@ typedef struct {
                                        affine, p <= 2) */
 
 /* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
- * upwind graphs), build the sweep plan on the host and upload it to the
+ * upwind graphs unless opt->cycles lags them), build the sweep plan on the host and upload it to the
  * current HIP device.  Synchronous.  n_probs > 1 gives one batched handle
  * whose runs sweep all problems together.  opt may be NULL (defaults). */
 int vef_sweep_create(const vef_problem_desc *probs, int n_probs, const vef_options *opt,
@@ -212,8 +240,9 @@ int vef_sweep_destroy(vef_sweep_t *h);
 
 /* Host-only: validate one problem and build its plan without touching the
  * GPU; fills *info.  Returns the status vef_sweep_create would return for the
- * problem (except HIP and device-memory errors). */
-int vef_plan_query(const vef_problem_desc *prob, vef_info *info);
+ * problem with options opt (NULL = defaults; only opt->cycles is read),
+ * except HIP and device-memory errors. */
+int vef_plan_query(const vef_problem_desc *prob, const vef_options *opt, vef_info *info);
 
 /* Sizes of problem k of a handle. */
 int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info);

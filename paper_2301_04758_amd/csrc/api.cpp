@@ -38,7 +38,7 @@ struct Variant {
 int mode_of(const vefplan::ProblemPlan &pl, int schedule, bool pipeline = true) {
   if (!pl.nopivot) return 0;
   if (!pl.affine) return 1;
-  return (pipeline && schedule == VEF_DIR_RESIDENT && pl.p <= 2) ? 3 : 2;
+  return (pipeline && schedule == VEF_DIR_RESIDENT && pl.p <= 2 && pl.n_lagged == 0) ? 3 : 2;
 }
 
 struct LevelLaunch {
@@ -92,6 +92,7 @@ struct vef_sweep {
   int pipeline_waves = 0;
   int pipeline_ring = 0;
   int fixup = 0;
+  int cycles = VEF_CYCLES_REJECT;
   std::vector<hipEvent_t> events;  // [2 * iterations] of the last run
   int timed_iters = 0;
   int timed_launches = 0;
@@ -189,6 +190,9 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     h->pipeline_ring = opt->pipeline_ring;
     if (opt->fixup < 0 || opt->fixup > 1) return set_err(h, VEF_ERR_INVALID, "fixup must be 0 or 1");
     h->fixup = opt->fixup;
+    if (opt->cycles != VEF_CYCLES_REJECT && opt->cycles != VEF_CYCLES_LAG)
+      return set_err(h, VEF_ERR_INVALID, "cycles must be VEF_CYCLES_REJECT or VEF_CYCLES_LAG");
+    h->cycles = opt->cycles;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
   }
@@ -196,7 +200,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   h->plans.resize(n_probs);
   for (int k = 0; k < n_probs; ++k) {
     std::string e;
-    int rc = vefplan::build_problem_plan(probs[k], h->plans[k], e);
+    int rc = vefplan::build_problem_plan(probs[k], h->cycles == VEF_CYCLES_LAG, h->plans[k], e);
     if (rc) return set_err(h, rc, "problem " + std::to_string(k) + ": " + e);
   }
   hipError_t he = hipGetDevice(&h->device);
@@ -401,6 +405,22 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload direction tasks");
   h->psi_internal.assign(n_probs, nullptr);
+  // a problem with lagged couplings keeps its angular flux between runs when
+  // the caller passes none: allocated here, zero, so that lagged couplings of
+  // the first sweep read zero
+  for (int k = 0; k < n_probs; ++k) {
+    const auto &pl = h->plans[k];
+    if (!pl.n_lagged) continue;
+    const size_t bytes = std::max<size_t>((size_t)pl.nd * pl.ne * pl.n * (fp32 ? 4 : 8), 16);
+    he = hipMalloc(&h->psi_internal[k], bytes);
+    if (he != hipSuccess) {
+      h->psi_internal[k] = nullptr;
+      return hip_fail(h, he, "allocate angular flux");
+    }
+    he = hipMemset(h->psi_internal[k], 0, bytes);
+    if (he == hipSuccess) he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(h, he, "clear angular flux");
+  }
   h->resid_scratch.assign(n_probs, nullptr);
   h->resid_cap.assign(n_probs, 0);
   return VEF_OK;
@@ -603,13 +623,16 @@ int vef_sweep_destroy(vef_sweep_t *h) {
   return VEF_OK;
 }
 
-int vef_plan_query(const vef_problem_desc *prob, vef_info *info) {
+int vef_plan_query(const vef_problem_desc *prob, const vef_options *opt, vef_info *info) {
   if (!prob) return set_err(nullptr, VEF_ERR_INVALID, "prob is NULL");
+  const int cycles = opt ? opt->cycles : VEF_CYCLES_REJECT;
+  if (cycles != VEF_CYCLES_REJECT && cycles != VEF_CYCLES_LAG)
+    return set_err(nullptr, VEF_ERR_INVALID, "cycles must be VEF_CYCLES_REJECT or VEF_CYCLES_LAG");
   vefplan::ProblemPlan pl;
   std::string e;
   int rc;
   try {
-    rc = vefplan::build_problem_plan(*prob, pl, e);
+    rc = vefplan::build_problem_plan(*prob, cycles == VEF_CYCLES_LAG, pl, e);
   } catch (const std::bad_alloc &) {
     return set_err(nullptr, VEF_ERR_OOM, "host allocation failed");
   }
@@ -626,6 +649,7 @@ int vef_plan_query(const vef_problem_desc *prob, vef_info *info) {
     info->n_solves = (long long)pl.ne * pl.nd;
     info->schedule = VEF_SCHEDULE_AUTO;
     info->kernel = -1;
+    info->n_lagged = pl.n_lagged;
   }
   return VEF_OK;
 }
@@ -644,6 +668,7 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->n_solves = (long long)pl.ne * pl.nd;
   info->schedule = h->schedule;
   info->kernel = mode_of(pl, h->schedule, h->pipeline_waves >= 0);
+  info->n_lagged = pl.n_lagged;
   return VEF_OK;
 }
 

@@ -242,7 +242,7 @@ int build_tables(int p, int nq, Tables &t) {
   return VEF_OK;
 }
 
-int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &err) {
+int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, ProblemPlan &o, std::string &err) {
   if (d.p < 1 || d.p > kMaxP) return fail(err, VEF_ERR_INVALID, "p=%lld out of range 1..4", d.p);
   if (d.m < 1 || d.m > kMaxM) return fail(err, VEF_ERR_INVALID, "m=%lld out of range 1..3", d.m);
   const int nq = d.nq > 0 ? d.nq : d.p + d.m;
@@ -438,6 +438,9 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
   o.level_off.clear();
   o.n_levels = 0;
   std::vector<int> indeg(ne), queue(ne);
+  std::vector<uint8_t> placed(ne);
+  o.lag_mask.assign((size_t)o.n_groups * ne, 0);
+  o.n_lagged = 0;
   std::vector<std::vector<int>> offs(o.n_groups);
   for (int g = 0; g < o.n_groups; ++g) {
     const uint8_t *mk = &o.mask[(size_t)o.group_rep[g] * ne];
@@ -448,25 +451,72 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
         if ((mk[e] >> f & 1) && o.nbr[4 * e + f] >= 0) ++c;
       indeg[e] = c;
     }
-    int head = 0, tail = 0;
+    uint8_t *lagm = &o.lag_mask[(size_t)g * ne];
+    int head = 0, tail = 0, n_lag = 0;
     for (int e = 0; e < ne; ++e)
       if (!indeg[e]) queue[tail++] = e;
+    std::fill(placed.begin(), placed.end(), (uint8_t)0);
+    for (int t = 0; t < tail; ++t) placed[queue[t]] = 1;
     int maxl = 0;
-    while (head < tail) {
-      const int e = queue[head++];
-      maxl = std::max(maxl, (int)lev[e]);
-      for (int f = 0; f < 4; ++f) {
-        const int nb = o.nbr[4 * e + f];
-        if (nb < 0 || (mk[e] >> f & 1)) continue;  // boundary or inflow face of e
-        const int f2 = o.nbr_face[4 * e + f];
-        if (!(mk[nb] >> f2 & 1)) continue;  // tie-free by construction; defensive
-        lev[nb] = std::max(lev[nb], lev[e] + 1);
-        if (--indeg[nb] == 0) queue[tail++] = nb;
+    for (;;) {
+      while (head < tail) {
+        const int e = queue[head++];
+        maxl = std::max(maxl, (int)lev[e]);
+        for (int f = 0; f < 4; ++f) {
+          const int nb = o.nbr[4 * e + f];
+          if (nb < 0 || (mk[e] >> f & 1)) continue;  // boundary or inflow face of e
+          const int f2 = o.nbr_face[4 * e + f];
+          if (!(mk[nb] >> f2 & 1) || placed[nb]) continue;  // defensive; released elements are placed
+          lev[nb] = std::max(lev[nb], lev[e] + 1);
+          if (--indeg[nb] == 0) {
+            queue[tail++] = nb;
+            placed[nb] = 1;
+          }
+        }
       }
+      if (tail == ne) break;
+      if (!lag_cycles)
+        return fail(err, VEF_ERR_CYCLE, "upwind graph of direction %lld has a cycle (%lld elements left)",
+                    o.group_rep[g], ne - tail);
+      // Every element left waits on a cycle.  Release the one with the
+      // fewest unsolved upwind neighbours (lowest id on ties); its couplings
+      // to them are lagged: read from the previous sweep's angular flux.
+      int best = -1;
+      for (int e = 0; e < ne; ++e)
+        if (!placed[e] && (best < 0 || indeg[e] < indeg[best])) best = e;
+      for (int f = 0; f < 4; ++f) {
+        const int nb = o.nbr[4 * best + f];
+        if (nb >= 0 && (mk[best] >> f & 1) && !placed[nb]) {
+          lagm[best] |= (uint8_t)(1u << f);
+          ++n_lag;
+        }
+      }
+      indeg[best] = 0;
+      queue[tail++] = best;
+      placed[best] = 1;
     }
-    if (tail != ne)
-      return fail(err, VEF_ERR_CYCLE, "upwind graph of direction %lld has a cycle (%lld elements left)",
-                  o.group_rep[g], ne - tail);
+    if (n_lag) {
+      // Levels of the lagged order: an element follows its non-lagged upwind
+      // neighbours, and precedes the elements it reads lagged data from, so
+      // that those are overwritten only after the read.  queue holds a
+      // topological order of both relations.
+      std::fill(lev, lev + ne, 0);
+      maxl = 0;
+      for (int t = 0; t < ne; ++t) {
+        const int e = queue[t];
+        maxl = std::max(maxl, (int)lev[e]);
+        for (int f = 0; f < 4; ++f) {
+          const int nb = o.nbr[4 * e + f];
+          if (nb < 0) continue;
+          const bool inflow = mk[e] >> f & 1;
+          const bool after = inflow ? (lagm[e] >> f & 1) != 0 : !(lagm[nb] >> o.nbr_face[4 * e + f] & 1);
+          if (after) lev[nb] = std::max(lev[nb], lev[e] + 1);
+        }
+      }
+      long long nd_g = 0;
+      for (int k = 0; k < nd; ++k) nd_g += o.dir_group[k] == g;
+      o.n_lagged += nd_g * n_lag;
+    }
     o.n_levels_g[g] = maxl + 1;
     o.n_levels = std::max(o.n_levels, maxl + 1);
     // counting sort by level, ties by element id
@@ -494,6 +544,7 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
     const uint8_t *mk = &o.mask[(size_t)o.group_rep[g] * ne];
     const int32_t *ord = &o.order[(size_t)g * ne];
     const int32_t *lev = &o.level[(size_t)g * ne];
+    const uint8_t *lagm_g = &o.lag_mask[(size_t)g * ne];
     const int *lo = &o.level_off[(size_t)g * (o.n_levels + 1)];
     for (int t = 0; t < ne; ++t) pos_in_level[ord[t]] = t - lo[lev[ord[t]]];
     for (int t = 0; t < ne; ++t) {
@@ -504,7 +555,7 @@ int build_problem_plan(const vef_problem_desc &d, ProblemPlan &o, std::string &e
         const int nb = o.nbr[4 * e + f];
         o.desc_nb[((size_t)g * ne + t) * 4 + f] = nb;
         if (nb >= 0 && ((mk[e] >> f) & 1)) {
-          const int gap = lev[e] - lev[nb];
+          const int gap = (lagm_g[e] >> f & 1) ? 255 : lev[e] - lev[nb];
           o.max_gap = std::max(o.max_gap, gap);
           const uint32_t code = (uint32_t)std::min(gap, 255) | ((uint32_t)pos_in_level[nb] << 8) |
                                 ((uint32_t)(o.nbr_face[4 * e + f] & 3) << 30);

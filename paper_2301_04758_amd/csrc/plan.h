@@ -53,6 +53,8 @@ struct ProblemPlan {
   std::vector<uint32_t> desc_up;    // [n_groups][ne][4] in order, per inflow interior face: level gap
                                     // (bits 0-7, 255 = far), upwind position in its level (8-29),
                                     // upwind local face (30-31); 0 for other faces
+  std::vector<uint8_t> lag_mask;    // [n_groups][ne]: bit f set when inflow face f is lagged
+  long long n_lagged = 0;           // lagged (direction, element, face) couplings
   int max_gap = 0;                  // largest level gap of an upwind edge
   int max_width = 1;                // widest level over classes
   bool straight = true;             // every face of the mesh is a straight segment
@@ -65,8 +67,9 @@ struct ProblemPlan {
 
 int build_tables(int p, int nq, Tables &t);
 
-// Validates and plans one problem.  Returns VEF_OK or a VEF_ERR_* status and
-// a message in err.
-int build_problem_plan(const vef_problem_desc &d, ProblemPlan &out, std::string &err);
+// Validates and plans one problem.  lag_cycles: a cyclic upwind graph is
+// ordered by releasing elements with lagged couplings instead of failing with
+// VEF_ERR_CYCLE.  Returns VEF_OK or a VEF_ERR_* status and a message in err.
+int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, ProblemPlan &out, std::string &err);
 
 }  // namespace vefplan

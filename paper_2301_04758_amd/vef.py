@@ -27,6 +27,8 @@ VEF_ERR_OOM = -5
 VEF_ERR_TIMEOUT = -6
 VEF_FP64 = 0
 VEF_FP32_LOCAL = 1
+VEF_CYCLES_REJECT = 0
+VEF_CYCLES_LAG = 1
 VEF_SCHEDULE_AUTO = 0
 VEF_LEVEL_SYNC = 1
 VEF_DIR_RESIDENT = 2
@@ -51,7 +53,7 @@ class vef_problem_desc(C.Structure):
 class vef_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("schedule", C.c_int), ("block", C.c_int), ("timing", C.c_int),
                 ("pipeline_waves", C.c_int), ("pipeline_ring", C.c_int), ("fixup", C.c_int),
-                ("reserved", C.c_int * 1)]
+                ("cycles", C.c_int)]
 
 
 class vef_problem_io(C.Structure):
@@ -74,7 +76,7 @@ class vef_moment_io(C.Structure):
 class vef_info(C.Structure):
     _fields_ = [("n", C.c_int), ("nq", C.c_int), ("Q", C.c_int), ("n_bf", C.c_int), ("n_levels", C.c_int),
                 ("n_groups", C.c_int), ("pivoting", C.c_int), ("affine", C.c_int), ("n_solves", C.c_longlong),
-                ("schedule", C.c_int), ("kernel", C.c_int)]
+                ("schedule", C.c_int), ("kernel", C.c_int), ("n_lagged", C.c_longlong)]
 
 
 def _load():
@@ -87,7 +89,7 @@ def _load():
     L.vef_sweep_run.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p]
     L.vef_moments.argtypes = [H, C.POINTER(vef_moment_io), C.c_void_p]
     L.vef_sweep_destroy.argtypes = [H]
-    L.vef_plan_query.argtypes = [C.POINTER(vef_problem_desc), C.POINTER(vef_info)]
+    L.vef_plan_query.argtypes = [C.POINTER(vef_problem_desc), C.POINTER(vef_options), C.POINTER(vef_info)]
     L.vef_problem_info.argtypes = [H, C.c_int, C.POINTER(vef_info)]
     L.vef_boundary_faces.argtypes = [H, C.c_int, C.c_void_p]
     L.vef_sweep_check.argtypes = [H]
@@ -148,10 +150,12 @@ class _Desc:
 # ------------------------------------------------------------------ C names
 
 
-def vef_plan_query(problem) -> dict:
+def vef_plan_query(problem, lag_cycles: bool = False) -> dict:
     d = _Desc(problem)
     info = vef_info()
-    rc = lib.vef_plan_query(C.byref(d.s), C.byref(info))
+    opt = vef_options()
+    opt.cycles = VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT
+    rc = lib.vef_plan_query(C.byref(d.s), C.byref(opt), C.byref(info))
     if rc != VEF_OK:
         raise VefError(rc, lib.vef_last_error(None).decode())
     return {f: getattr(info, f) for f, _ in vef_info._fields_}
@@ -159,11 +163,11 @@ def vef_plan_query(problem) -> dict:
 
 def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
                      block: int = 0, timing: bool = False, pipeline_waves: int = 0,
-                     pipeline_ring: int = 0, fixup: bool = False) -> int:
+                     pipeline_ring: int = 0, fixup: bool = False, lag_cycles: bool = False) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
     opt = vef_options(precision, schedule, block, 1 if timing else 0, pipeline_waves, pipeline_ring,
-                      1 if fixup else 0)
+                      1 if fixup else 0, VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT)
     h = C.c_void_p()
     rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))
     if rc != VEF_OK:
@@ -267,7 +271,7 @@ class Sweep:
     """Owns one handle; allocates device buffers with torch for convenience."""
 
     def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto",
-                 pipeline_waves=0, pipeline_ring=0, fixup=False):
+                 pipeline_waves=0, pipeline_ring=0, fixup=False, lag_cycles=False):
         import torch
         self.torch = torch
         self.problems = list(problems)
@@ -276,7 +280,7 @@ class Sweep:
         with torch.cuda.device(self.device):
             self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64,
                                       SCHEDULES[schedule], block, timing, pipeline_waves, pipeline_ring,
-                                      fixup)
+                                      fixup, lag_cycles)
         self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
 
     def close(self):
