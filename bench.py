@@ -110,7 +110,7 @@ def measured_traffic(kernel):
     or None when the kernel differs or its sources changed since then."""
     import hashlib
     import re
-    if kernel != "k_sweep_pipe<2, 3, double>" or not os.path.exists(PROFILE):
+    if kernel != "k_sweep_pipe<2, 3, double, false>" or not os.path.exists(PROFILE):
         return None
     text = open(PROFILE).read()
     m = re.search(r"traffic_bytes_per_launch=([0-9.e+]+) kernel_sources_sha256_16=([0-9a-f]+)", text)
@@ -127,9 +127,77 @@ def kernel_name(g, pr):
     """Name of the sweep kernel that ran (as the profiler lists it)."""
     nq = pr.nq or pr.p + pr.m
     if g["schedule"] == "dir_resident" and g["kernel"] == 3:
-        return "k_sweep_pipe<%d, %d, double>" % (pr.p, nq)
+        return "k_sweep_pipe<%d, %d, double, false>" % (pr.p, nq)
     kind = "dir" if g["schedule"] == "dir_resident" else "level"
     return "k_sweep_%s<%d, %d, double, %d>" % (kind, pr.p, nq, g["kernel"])
+
+
+def fixup_leg(probs, n_iter, steps, ms_plain):
+    """The same FP64 workload with the negative-flux fixup inside the sweep:
+    time per step, and the smallest angular flux with and without it."""
+    import torch
+    from paper_2301_04758_amd import vef
+    out = {}
+    for fix in (False, True):
+        sw = vef.Sweep(probs, precision="fp64", fixup=fix)
+        io = sw.buffers(n_iter=n_iter, store_psi=True)
+        sw.autotune(io, n_iter=n_iter, reps=1)
+        sw.run(io, n_iter=n_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sw.run(io, n_iter=n_iter)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        sw.check()
+        out["fixed" if fix else "plain"] = dict(ms=ms, min_psi=float(io[0]["psi_out"].min().item()),
+                                                phi=io[0]["mom"][0].cpu().numpy())
+        sw.close()
+        del io
+    import numpy as np
+    p, f = out["plain"], out["fixed"]
+    return {"ms_per_step": f["ms"], "overhead_vs_plain": f["ms"] / p["ms"], "min_psi_plain": p["min_psi"],
+            "min_psi_fixed": f["min_psi"],
+            "rel_inf_phi_change": float(np.abs(f["phi"] - p["phi"]).max() / np.abs(p["phi"]).max())}
+
+
+def lagged_leg(steps, n_iter=5):
+    """The 64x64 random mesh with reflex corners (p = 2, S8, cyclic upwind
+    graphs, about an eighth of the element-direction pairs with a lagged
+    inflow face): source iterations with lagged couplings, FP64 and
+    FP32-local, time per sweep."""
+    import numpy as np
+    import torch
+    from paper_2301_04758_amd import problems as P
+    from paper_2301_04758_amd import vef
+    pr = P.reentrant_quads(64)
+    out = {"workload": "64x64 straight-sided quads, interior vertices moved up to 0.45 h (reflex corners), "
+                       "p=2, S8, sigma_t log-uniform [0.1,100] per 8x8 block, c=0.9; %d sweeps per step" % n_iter}
+    phi = {}
+    for prec in ("fp64", "fp32"):
+        sw = vef.Sweep([pr], precision=prec, lag_cycles=True)
+        io = sw.buffers(n_iter=n_iter, store_psi=True)
+        tuned = sw.autotune(io, n_iter=n_iter, reps=1)
+        io[0]["psi_out"].zero_()
+        sw.run(io, n_iter=n_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sw.run(io, n_iter=n_iter)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / (steps * n_iter)
+        sw.check()
+        inf = sw.info[0]
+        phi[prec] = io[0]["mom"][0].cpu().numpy()
+        out[prec] = {"ms_per_sweep": ms, "solves_per_s": pr.n_elem * pr.n_dir / (ms * 1e-3),
+                     "schedule": vef.SCHEDULE_NAMES[inf["schedule"]], "kernel": vef.KERNEL_NAMES[inf["kernel"]],
+                     "tuning": tuned}
+        out.update(n_lagged=inf["n_lagged"], lagged_frac=inf["n_lagged"] / (pr.n_elem * pr.n_dir),
+                   n_levels=inf["n_levels"])
+        sw.close()
+        del io
+    out["fp32_rel_inf_phi_vs_fp64"] = float(np.abs(phi["fp32"] - phi["fp64"]).max() / np.abs(phi["fp64"]).max())
+    return out
 
 
 def c4_batched(reps=3):
@@ -217,6 +285,8 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir"],
                     help="auto: the library's autotuner picks schedule and kernel before the timed steps")
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-problem batched FP32 vs one-by-one FP64 block")
+    ap.add_argument("--no-fixup", action="store_true", help="skip the negative-flux fixup leg")
+    ap.add_argument("--no-lagged", action="store_true", help="skip the re-entrant-mesh lagged-sweep leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (three times), the reference kernel "
                          "for scaling HBM byte counters")
@@ -286,6 +356,10 @@ def main():
         result["fp32_local"] = {"ms_per_step": ms32, "value": solves_per_step / (ms32 * 1e-3),
                                 "speedup_vs_fp64": ms_step / ms32,
                                 "rel_inf_phi_vs_fp64_path": err, "within_1e-5": err <= 1e-5}
+    if not args.no_fixup:
+        result["fixup_fp64"] = fixup_leg(probs, n_iter, args.steps, ms_step)
+    if not args.no_lagged:
+        result["lagged_reentrant"] = lagged_leg(args.steps)
     if not args.no_c4:
         result["c4_batched_fp32_vs_plain_fp64"] = c4_batched()
     if args.copy_calibration:

@@ -285,8 +285,9 @@ typedef struct {
  * direction-resident row-per-lane kernel, and (when some problem has affine
  * elements of degree <= 2) the pipelined kernel with 8, 6 or 4 waves.  Each
  * candidate runs once untimed and then reps (1..1000) times between HIP
- * events on stream; the fastest is kept by the handle for later runs
- * (results differ between kernels only by rounding).  Blocking.  The output
+ * events on stream; the fastest is kept by the handle for later runs when it
+ * beats the handle's configuration before the call by more than 2% (else
+ * that one stays; results differ between kernels only by rounding).  Blocking.  The output
  * buffers of a hold the last candidate's results.  out may be NULL.  Errors:
  * as vef_sweep_run and vef_sweep_check; the handle then keeps its previous
  * configuration. */

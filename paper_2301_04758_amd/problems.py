@@ -161,9 +161,8 @@ def taylor_green_mesh(n: int, m: int = 3, t_final: float = 0.3 * math.pi, steps:
     time stand and boundary points slide along the boundary.  `vortices` > 1
     tiles vortices-by-vortices such cells (alternating sense of rotation), each
     covering n/vortices elements per side.  Longer t_final on coarse cells
-    gives meshes with re-entrant faces (cyclic upwind graphs), like the
-    Lagrangian-hydrodynamics mesh of the thick-diffusion-limit study.
-    Returns (cp_xy, elem_cp) like quad_mesh."""
+    gives re-entrant faces (cyclic upwind graphs) but also nearly degenerate
+    elements.  Returns (cp_xy, elem_cp) like quad_mesh."""
     cp, ec = quad_mesh(n, n, m)
     scale = math.pi * vortices
     y = cp * scale
@@ -351,17 +350,44 @@ def make_tg_problem(name, n, p, m, N, sigma_t, sigma_s, q=1.0, t_final=0.3 * mat
                    sigma_t=st, sigma_s=ss, q_iso=_const_source(n * n, p, q), nx=n, ny=n)
 
 
-def reentrant_tg(n: int = 64, p: int = 2, N: int = 8, seed: Optional[int] = None):
-    """Workload with re-entrant faces: n-by-n cubic (m = 3) Taylor-Green mesh
-    of (n/8)^2 vortex cells of 8x8 elements advected to t = pi, p, S_N,
-    sigma_t log-uniform [0.1, 100] per 8x8 block, c = 0.9, unit isotropic
-    source, vacuum.  Its upwind graphs are cyclic for most directions."""
-    if n % 8:
-        raise ValueError("n must be a multiple of 8")
+def nonconvex_quad_mesh(n: int, amp: float, max_reflex: float, rng) -> tuple:
+    """n-by-n straight-sided (m = 1) mesh of the unit square whose interior
+    vertices are moved by independent uniform offsets in [-amp h, amp h]^2.
+    Quads may have one reflex corner, which makes some upwind graphs cyclic
+    (re-entrant faces, as on the Lagrangian-hydrodynamics mesh of the
+    thick-diffusion-limit study); a quad whose most negative corner area (the
+    cross product of the two edges leaving a corner) is below -max_reflex
+    times the mean of its four corner areas has the offsets of its vertices
+    halved, until none is.  Returns (cp_xy, elem_cp) like quad_mesh."""
+    cp, ec = quad_mesh(n, n, 1)
+    h = 1.0 / n
+    inner = (cp[:, 0] > 0.0) & (cp[:, 0] < 1.0) & (cp[:, 1] > 0.0) & (cp[:, 1] < 1.0)
+    disp = np.zeros_like(cp)
+    disp[inner] = rng.uniform(-amp * h, amp * h, size=(int(inner.sum()), 2))
+    ccw = ec[:, [0, 1, 3, 2]]
+    for _ in range(64):
+        x = (cp + disp)[ccw]
+        nxt = np.roll(x, -1, axis=1) - x
+        prv = np.roll(x, 1, axis=1) - x
+        area = nxt[..., 0] * prv[..., 1] - nxt[..., 1] * prv[..., 0]
+        bad = area.min(axis=1) < -max_reflex * area.mean(axis=1)
+        if not bad.any():
+            return np.ascontiguousarray(cp + disp), ec
+        disp[np.unique(ccw[bad])] *= 0.5
+    raise RuntimeError("nonconvex_quad_mesh: offsets did not settle")
+
+
+def reentrant_quads(n: int = 64, p: int = 2, N: int = 8, seed: Optional[int] = None):
+    """Workload with re-entrant faces: nonconvex_quad_mesh(n, 0.45, 0.2), p,
+    S_N, sigma_t log-uniform [0.1, 100] per 8x8 block, c = 0.9, unit
+    isotropic source, vacuum.  At 64x64 and S8 about an eighth of the
+    element-direction pairs have a lagged inflow face."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7 if seed is None else seed))
+    cp, ec = nonconvex_quad_mesh(n, 0.45, 0.2, rng)
+    om, wt = level_symmetric_2d(N)
     st = block_log_uniform(n, n, 8, 0.1, 100.0, rng)
-    return make_tg_problem("tg_reentrant_%d" % n, n, p, 3, N, st, 0.9 * st, t_final=math.pi,
-                           vortices=n // 8)
+    return Problem(name="reentrant_%d" % n, p=p, m=1, cp_xy=cp, elem_cp=ec, omega=om, weight=wt,
+                   sigma_t=st, sigma_s=0.9 * st, q_iso=_const_source(n * n, p, 1.0), nx=n, ny=n)
 
 
 CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")

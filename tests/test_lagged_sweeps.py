@@ -12,13 +12,13 @@ CPU pins of the oracle's lagged sweep:
     and lagged source iteration to the coupled scattering solution;
   * the Taylor-Green mesh generator: unit area, constant preservation.
 Host: the library's plan lags as many couplings as the oracle.
-GPU: parity of lagged source iterations with the oracle (fixture, Taylor-Green
-meshes with re-entrant faces, both schedules, FP64 and FP32-local, runs that
-continue earlier runs, the full-size workload).  The meshes with re-entrant
-faces have nearly degenerate elements whose local systems reach condition
-numbers near 1e4, so the bound is max(bar, 4 eps kappa_max) with kappa_max
-from the independently assembled local blocks (the bar alone where kappa is
-modest).
+GPU: parity of lagged source iterations with the oracle (fixture, random
+meshes with reflex corners, both schedules, FP64 and FP32-local, runs that
+continue earlier runs, the full-size workload), and of plain sweeps on the
+cubic Taylor-Green mesh.  The bound is max(bar, 4 eps kappa_max) with
+kappa_max from the independently assembled local blocks: the bar itself
+where the local systems are well conditioned, and more on the fixture at
+p = 3, whose Jacobian nearly vanishes at some Gauss points (kappa near 7e3).
 """
 import itertools
 import math
@@ -161,7 +161,7 @@ def test_release_rule_lags_a_minimum_feedback_arc_set():
     assert counts[0] >= 1 and counts[1] == 0
 
 
-@pytest.mark.parametrize("which", ["fixture", "tg"])
+@pytest.mark.parametrize("which", ["fixture", "tg", "nonconvex"])
 def test_one_lagged_sweep_is_a_block_gauss_seidel_step(which):
     """psi_new = (D + L)^{-1} (b - U psi_prev) on the dense global system of
     each direction, with L / U the couplings to elements before / after in
@@ -169,7 +169,8 @@ def test_one_lagged_sweep_is_a_block_gauss_seidel_step(which):
     a backward-stable solve, 16 eps cond(D + L) relative (1e-12 at least);
     the cubic Taylor-Green elements at t = pi are nearly degenerate, with
     cond(D + L) up to about 1e6."""
-    pr = _fixture(p=2) if which == "fixture" else _with_source(_tg(8, 1, 8))
+    pr = {"fixture": lambda: _fixture(p=2), "tg": lambda: _with_source(_tg(8, 1, 8)),
+          "nonconvex": lambda: P.reentrant_quads(12, p=1, N=2)}[which]()
     ne, n = pr.n_elem, (pr.p + 1) ** 2
     assert O.lagged_couplings(pr).sum() > 0
     prev = RNG.normal(size=(pr.n_dir, ne, n))
@@ -205,6 +206,18 @@ def test_lagged_source_iteration_reaches_the_coupled_solution():
     pr = _fixture(p=1, ss=0.5)
     r = O.source_iteration(pr, 80, lag=True)
     ref = D.coupled_scattering_solve(pr, q_iso=pr.q_iso, nq=pr.nq or None)
+    assert np.abs(r["mom"][0] - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_lagged_source_iteration_on_nonconvex_quads():
+    """The same fixed point on a random mesh with reflex corners (12x12, S2,
+    47 lagged couplings), where the lagged order is found by the release rule
+    in many places."""
+    pr = P.reentrant_quads(12, p=1, N=2)
+    pr.sigma_s = 0.5 * pr.sigma_t
+    assert O.lagged_couplings(pr).sum() > 0
+    r = O.source_iteration(pr, 90, lag=True)
+    ref = D.coupled_scattering_solve(pr, q_iso=pr.q_iso)
     assert np.abs(r["mom"][0] - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
@@ -250,7 +263,7 @@ def _vef():
 
 def test_plan_lags_as_many_couplings_as_the_oracle():
     vef = _vef()
-    for pr in (_fixture(), _tg(8, 2, 8), P.reentrant_tg(16)):
+    for pr in (_fixture(), _tg(8, 2, 8), P.reentrant_quads(16)):
         want = int(O.lagged_couplings(pr).sum())
         assert want > 0
         assert vef.vef_plan_query(pr, lag_cycles=True)["n_lagged"] == want
@@ -369,10 +382,10 @@ def test_lagged_parity_fixture(p, schedule, precision):
 @pytest.mark.gpu
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("schedule", ["level", "dir"])
-def test_lagged_parity_taylor_green(schedule, precision):
-    """16x16 cubic Taylor-Green mesh of 2x2 vortex cells at t = pi (re-entrant
-    faces for most directions), p = 2, S8, c = 0.9."""
-    pr = P.reentrant_tg(16)
+def test_lagged_parity_nonconvex(schedule, precision):
+    """32x32 random mesh with reflex corners (7% of the element-direction
+    pairs lagged), p = 2, S8, c = 0.9."""
+    pr = P.reentrant_quads(32)
     assert O.lagged_couplings(pr).sum() > 0
     ref = O.source_iteration(pr, 4, lag=True, want_psi=True)
     got = _gpu_si(pr, 4, precision, schedule)
@@ -401,15 +414,30 @@ def test_lagged_runs_continue(internal):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_taylor_green_mesh_parity(p, precision):
+    """The cubic Taylor-Green mesh of the manufactured-solution study (t =
+    0.3 pi, acyclic): two source iterations against the oracle."""
+    pr = _tg(16, p, 8, t_final=0.3 * math.pi, st=2.0, ss=1.0)
+    pr.q_iso = np.ones((pr.n_elem, (p + 1) ** 2))
+    ref = O.source_iteration(pr, 2)
+    for schedule in ("level", "dir"):
+        got = _gpu_si(pr, 2, precision, schedule)
+        assert got["info"]["n_lagged"] == 0
+        assert _rel(got["mom"], ref["mom"]) <= _tol_for(pr, precision), schedule
+
+
+@pytest.mark.gpu
 def test_lagged_parity_full_size():
-    """The 64x64 re-entrant workload (p = 2, S8, 22% of the element-direction
+    """The 64x64 re-entrant workload (p = 2, S8, 17% of the element-direction
     pairs lagged), three source iterations, FP64 and FP32-local, every value
     against the oracle."""
-    pr = P.reentrant_tg(64)
+    pr = P.reentrant_quads(64)
     ref = O.source_iteration(pr, 3, lag=True)
     kappa = _kappa_max(pr)
     for precision in ("fp64", "fp32"):
         got = _gpu_si(pr, 3, precision, "auto")
         eps = np.finfo(np.float64 if precision == "fp64" else np.float32).eps
-        assert got["info"]["n_lagged"] > 0.2 * pr.n_elem * pr.n_dir
+        assert got["info"]["n_lagged"] > 0.15 * pr.n_elem * pr.n_dir
         assert _rel(got["mom"], ref["mom"]) <= max(_tol(precision), 4 * eps * kappa), precision
