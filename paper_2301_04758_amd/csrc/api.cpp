@@ -574,8 +574,12 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
       he = vefk::launch_moments(fp32, h->d_probs, h->d_io, k, pl.ne * pl.n, it, stop, s);
       if (he != hipSuccess) return hip_fail(h, he, "launch moments");
     }
-    he = vefk::launch_finalize(h->d_io, np, it, a->tol, stop, iters, a->iters_done, s);
-    if (he != hipSuccess) return hip_fail(h, he, "launch finalize");
+    // the stop test needs a tolerance; without one only the count of sweeps
+    // is recorded, after the last
+    if (a->tol > 0.0 || it == a->n_iter - 1) {
+      he = vefk::launch_finalize(h->d_io, np, it, a->tol, stop, iters, a->iters_done, s);
+      if (he != hipSuccess) return hip_fail(h, he, "launch finalize");
+    }
   }
   // Boundary sums for E_b and J_in, once, from the angular flux of the last
   // sweep performed (later sweeps skipped by the tolerance test leave it).

@@ -12,55 +12,74 @@ namespace vefk {
 
 namespace {
 
-// Angular moments (fixed direction order, double accumulation) and the
-// max-norm change of the scalar flux; one thread per (element, node).
+// Angular moments (double accumulation) and the max-norm change of the
+// scalar flux.  A work-group of 4 waves covers 64 (element, node) entries.
+// The direction weights and cosines are staged in LDS first (the handle
+// allows at most 1024 directions).  Wave w sums the directions of its
+// quarter of the direction list in order, with loads unrolled so several are
+// in flight, and wave 0 adds the four partial sums in quarter order, so the
+// result does not depend on timing.
+constexpr int kMomWaves = 4;
+constexpr int kMaxMomDirs = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kMomWaves)
 k_moments(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob, int ne_n, int it,
           const int *__restrict__ stop) {
   if (*stop) return;
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int nd = pb.nd;
+  __shared__ double3 dirs[kMaxMomDirs];  // (w, w ox, w oy)
+  for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+    const double wt = pb.weight[d];
+    dirs[d] = make_double3(wt, pb.omega[2 * d], pb.omega[2 * d + 1]);
+  }
+  __syncthreads();
+  const int d0 = (nd * w) / kMomWaves, d1 = (nd * (w + 1)) / kMomWaves;
+  double m[6] = {0, 0, 0, 0, 0, 0};
+  if (i < ne_n) {
+    const T *psi = static_cast<const T *>(pio.psi) + i;
+#pragma unroll 8
+    for (int d = d0; d < d1; ++d) {
+      const double v = static_cast<double>(psi[(size_t)d * ne_n]);
+      const double3 c = dirs[d];
+      const double wv = c.x * v, ox = c.y, oy = c.z;
+      m[0] += wv;
+      m[1] += wv * ox;
+      m[2] += wv * oy;
+      m[3] += wv * ox * ox;
+      m[4] += wv * ox * oy;
+      m[5] += wv * oy * oy;
+    }
+  }
+  __shared__ double part[kMomWaves - 1][6][64];
+  if (w > 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) part[w - 1][k][lane] = m[k];
+  __syncthreads();
+  if (w != 0) return;
   double diff = 0.0;
   if (i < ne_n) {
-    const T *psi = static_cast<const T *>(pio.psi);
-    double m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0, m5 = 0;
-    for (int d = 0; d < pb.nd; ++d) {
-      const double v = static_cast<double>(psi[(size_t)d * ne_n + i]);
-      const double w = pb.weight[d], ox = pb.omega[2 * d], oy = pb.omega[2 * d + 1];
-      const double wv = w * v;
-      m0 += wv;
-      m1 += wv * ox;
-      m2 += wv * oy;
-      m3 += wv * ox * ox;
-      m4 += wv * ox * oy;
-      m5 += wv * oy * oy;
-    }
+#pragma unroll
+    for (int q = 0; q < kMomWaves - 1; ++q)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) m[k] += part[q][k][lane];
     const double *phi = it == 0 ? pio.phi_in : pio.mom;
     const double old = phi ? phi[i] : 0.0;
     double *mom = pio.mom;
-    mom[i] = m0;
-    mom[(size_t)ne_n + i] = m1;
-    mom[2 * (size_t)ne_n + i] = m2;
-    mom[3 * (size_t)ne_n + i] = m3;
-    mom[4 * (size_t)ne_n + i] = m4;
-    mom[5 * (size_t)ne_n + i] = m5;
-    diff = fabs(m0 - old);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) mom[(size_t)k * ne_n + i] = m[k];
+    diff = fabs(m[0] - old);
   }
-  // block max, then one atomic max on the bit pattern (non-negative doubles
+  // wave max, then one atomic max on the bit pattern (non-negative doubles
   // order like unsigned integers)
   for (int off = 32; off >= 1; off >>= 1) diff = fmax(diff, __shfl_xor(diff, off, 64));
-  __shared__ double wmax[16];
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = diff;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double mx = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, wmax[w]);
-    if (pio.resid)
-      atomicMax(reinterpret_cast<unsigned long long *>(pio.resid + it),
-                static_cast<unsigned long long>(__double_as_longlong(mx)));
-  }
+  if (lane == 0 && pio.resid)
+    atomicMax(reinterpret_cast<unsigned long long *>(pio.resid + it),
+              static_cast<unsigned long long>(__double_as_longlong(diff)));
 }
 
 // Boundary sums sum_d w |Omega.n| psi_d and sum_d w psi_d at boundary face
@@ -241,11 +260,11 @@ hipError_t launch_sweep_dir(const SweepLaunch &L) { return launch_sweep(L, true)
 
 hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob, int ne_n, int it,
                           const int *stop, hipStream_t s) {
-  const int grid = (ne_n + 255) / 256;
+  const int grid = (ne_n + 63) / 64;
   if (fp32)
-    hipLaunchKernelGGL(k_moments<float>, dim3(grid), dim3(256), 0, s, probs, io, prob, ne_n, it, stop);
+    hipLaunchKernelGGL(k_moments<float>, dim3(grid), dim3(64 * kMomWaves), 0, s, probs, io, prob, ne_n, it, stop);
   else
-    hipLaunchKernelGGL(k_moments<double>, dim3(grid), dim3(256), 0, s, probs, io, prob, ne_n, it, stop);
+    hipLaunchKernelGGL(k_moments<double>, dim3(grid), dim3(64 * kMomWaves), 0, s, probs, io, prob, ne_n, it, stop);
   return hipGetLastError();
 }
 
