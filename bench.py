@@ -61,10 +61,13 @@ def describe(name, probs, run):
     return "%s: %d problems, first %dx%d p=%d n_dir=%d" % (name, len(probs), pr.nx, pr.ny, pr.p, pr.n_dir)
 
 
+TIMING_STRIDE = 10  # HIP events around every 10th sweep of a step (each event costs device time)
+
+
 def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto", tune=True):
     import torch
     from paper_2301_04758_amd import vef
-    sw = vef.Sweep(probs, precision=precision, timing=timing, schedule=schedule)
+    sw = vef.Sweep(probs, precision=precision, timing=TIMING_STRIDE if timing else 0, schedule=schedule)
     io = sw.buffers(n_iter=n_iter, store_psi=True)
     mio = sw.moment_buffers(io)
     stream = torch.cuda.current_stream()
@@ -82,12 +85,13 @@ def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
-        if timing:
-            ms, nl = sw.timing()  # synchronises the stream after this step
-            sweep_ms += ms
-            launches += nl
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if timing:
+        # HIP events of the last timed step around every TIMING_STRIDE-th
+        # sweep (the handle reuses them per run, so reading them after every
+        # step would stall the queue)
+        sweep_ms, launches = sw.timing()
     sw.check()
     out = dict(seconds=t1 - t0, sweep_ms=sweep_ms, launches=launches,
                schedule=vef.SCHEDULE_NAMES[sw.info[0]["schedule"]], kernel=sw.info[0]["kernel"],
@@ -312,11 +316,12 @@ def main():
     value = solves_per_step * args.steps / g64["seconds"]
 
     # dominant kernel: the sweep kernel, timed by events on the run's stream
+    # over the last timed step
     F = sweep_flops_per_solve(pr.p)
     B = sweep_bytes_per_solve(pr.p, pr.m, pr.n_dir, 8)
     launches = max(g64["launches"], 1)
     avg_launch_s = g64["sweep_ms"] * 1e-3 / launches
-    solves_per_launch = solves_per_step * args.steps / launches
+    solves_per_launch = solves_per_step / launches
     achieved_tf = F * solves_per_launch / avg_launch_s / 1e12
     kname = kernel_name(g64, pr)
     sweeps_per_launch = solves_per_launch / sum(p.n_elem * p.n_dir for p in probs)
@@ -331,7 +336,7 @@ def main():
                 "binding": "critical path: %d dependent upwind levels per sweep" % g64["n_levels"],
                 "measured_peak": machine["fp64_fma_tflops"],
                 "frac_of_measured_peak": achieved_tf / machine["fp64_fma_tflops"],
-                "launches_per_step": launches / args.steps,
+                "launches_per_step": launches,
                 "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
                 "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
     hbm_gbs = B * solves_per_step / (ms_step * 1e-3) / 1e9

@@ -106,8 +106,10 @@ typedef struct {
                     closures in double. */
   int schedule;  /* VEF_SCHEDULE_AUTO, VEF_LEVEL_SYNC or VEF_DIR_RESIDENT */
   int block;     /* work-group size for the sweep kernels; 0 = default 256 */
-  int timing;    /* nonzero: runs record HIP events around the sweep kernels
-                    of every source iteration (read with vef_sweep_timing) */
+  int timing;    /* k > 0: runs record HIP events around the sweep kernels
+                    of every k-th source iteration and of the last one (read
+                    with vef_sweep_timing); 1 = every iteration; 0 = off.
+                    Each event costs a few microseconds of device time */
   int pipeline_waves; /* waves per work-group of the pipelined
                     direction-resident kernel (affine elements, p <= 2):
                     0 = default 8, 1..8; -1 = use the row-per-lane
@@ -228,11 +230,15 @@ int vef_sweep_create(const vef_problem_desc *probs, int n_probs, const vef_optio
 /* Enqueue n_iter sweeps (+ moments, residual, boundary sums) on stream
  * (a hipStream_t; NULL = default stream).  Asynchronous: outputs are valid
  * after the stream is synchronised.  The library keeps the boundary sums of
- * the last sweep for vef_moments. */
+ * the last sweep for vef_moments.  A call whose arguments equal the previous
+ * call's (on a handle created without timing) issues only kernel launches,
+ * so it can be captured in a HIP graph after one eager call. */
 int vef_sweep_run(vef_sweep_t *h, const vef_run_args *args, void *stream);
 
 /* Enqueue the closure kernels for every problem (io: host array [n_probs]),
- * reading the boundary sums of the last run on h. */
+ * reading the boundary sums of the last run on h.  A call whose pointers
+ * equal the previous call's issues only kernel launches, so it can be
+ * captured in a HIP graph together with vef_sweep_run. */
 int vef_moments(vef_sweep_t *h, const vef_moment_io *io, void *stream);
 
 /* Free all device and host memory of h.  NULL is a no-op. */
@@ -302,9 +308,9 @@ int vef_sweep_check(vef_sweep_t *h);
 
 /* Timing of the last run on a handle created with opt->timing != 0:
  * synchronises, then returns in *sweep_ms the summed device time from the
- * first to the last sweep kernel of each source iteration (HIP events on the
- * run's stream) and in *n_launches the number of sweep-kernel launches that
- * time covers.  Either pointer may be NULL. */
+ * first to the last sweep kernel of each timed source iteration (HIP events
+ * on the run's stream; see vef_options.timing) and in *n_launches the number
+ * of sweep-kernel launches that time covers.  Either pointer may be NULL. */
 int vef_sweep_timing(vef_sweep_t *h, double *sweep_ms, int *n_launches);
 
 const char *vef_last_error(const vef_sweep_t *h);

@@ -78,6 +78,8 @@ struct vef_sweep {
   hipEvent_t mio_uploaded = nullptr;
   std::vector<vefk::KIO> io_last;
   bool io_valid = false;
+  std::vector<vefk::KMomIO> mio_last;
+  bool mio_valid = false;
   int2 *d_solves = nullptr;
   std::vector<std::vector<LevelLaunch>> levels;
   int2 *d_dir_tasks = nullptr;
@@ -89,6 +91,7 @@ struct vef_sweep {
   int *d_flags = nullptr;  // [0] stop, [1] iterations done, [2] status
   hipStream_t last_stream = nullptr;
   bool timing = false;
+  int timing_stride = 0;  // time every timing_stride-th source iteration (and the last)
   int pipeline_waves = 0;
   int pipeline_ring = 0;
   int fixup = 0;
@@ -181,7 +184,9 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       return set_err(h, VEF_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
     h->precision = opt->precision;
     h->schedule = opt->schedule;
+    if (opt->timing < 0) return set_err(h, VEF_ERR_INVALID, "timing must be >= 0");
     h->timing = opt->timing != 0;
+    h->timing_stride = opt->timing;
     if (opt->pipeline_waves < -1 || opt->pipeline_waves > 8)
       return set_err(h, VEF_ERR_INVALID, "pipeline_waves must be -1..8");
     h->pipeline_waves = opt->pipeline_waves;
@@ -519,10 +524,13 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
     h->timed_iters = a->n_iter;
     h->timed_launches = 0;
   }
+  auto timed = [&](int it) {
+    return h->timing && ((it + 1) % h->timing_stride == 0 || it == a->n_iter - 1);
+  };
   he = vefk::launch_run_init(h->d_io, np, a->n_iter, stop, iters, s);
   if (he != hipSuccess) return hip_fail(h, he, "launch init");
   for (int it = 0; it < a->n_iter; ++it) {
-    if (h->timing && (he = hipEventRecord(h->events[2 * it], s)) != hipSuccess)
+    if (timed(it) && (he = hipEventRecord(h->events[2 * it], s)) != hipSuccess)
       return hip_fail(h, he, "record timing event");
     vefk::SweepLaunch SL{};
     SL.fp32 = fp32;
@@ -549,7 +557,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
           SL.tables = L.tab;
           he = vefk::launch_sweep_level(SL);
           if (he != hipSuccess) return hip_fail(h, he, "launch sweep");
-          if (h->timing) h->timed_launches++;
+          if (timed(it)) h->timed_launches++;
         }
     } else {
       for (auto &D : (h->pipeline_waves >= 0 ? h->dir_pipe : h->dir_rows)) {
@@ -564,10 +572,10 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
         SL.tables = D.tab;
         he = vefk::launch_sweep_dir(SL);
         if (he != hipSuccess) return hip_fail(h, he, "launch sweep");
-        if (h->timing) h->timed_launches++;
+        if (timed(it)) h->timed_launches++;
       }
     }
-    if (h->timing && (he = hipEventRecord(h->events[2 * it + 1], s)) != hipSuccess)
+    if (timed(it) && (he = hipEventRecord(h->events[2 * it + 1], s)) != hipSuccess)
       return hip_fail(h, he, "record timing event");
     for (int k = 0; k < np; ++k) {
       const auto &pl = h->plans[k];
@@ -603,12 +611,22 @@ int vef_moments(vef_sweep_t *h, const vef_moment_io *io, void *stream) {
     if (u.E && !u.mom) return set_err(h, VEF_ERR_INVALID, "E requested without mom");
     m[k] = vefk::KMomIO{u.mom, u.q_iso, u.q_dir, u.psi_bc, u.E, u.Eb, u.Jin, u.Q0, u.Q1, u.n_nonpos};
   }
-  hipError_t he = hipEventSynchronize(h->mio_uploaded);
-  if (he != hipSuccess) return hip_fail(h, he, "wait for previous upload");
-  std::memcpy(h->h_mio_pinned, m.data(), sizeof(vefk::KMomIO) * np);
-  he = hipMemcpyAsync(h->d_mio, h->h_mio_pinned, sizeof(vefk::KMomIO) * np, hipMemcpyHostToDevice, s);
-  if (he == hipSuccess) he = hipEventRecord(h->mio_uploaded, s);
-  if (he == hipSuccess) he = vefk::launch_zero_nonpos(h->d_mio, np, s);
+  // same pointers as the last call: kernel launches only (capturable)
+  bool changed = !h->mio_valid;
+  for (int k = 0; k < np && !changed; ++k)
+    changed = std::memcmp(&m[k], &h->mio_last[k], sizeof(vefk::KMomIO)) != 0;
+  hipError_t he = hipSuccess;
+  if (changed) {
+    he = hipEventSynchronize(h->mio_uploaded);
+    if (he != hipSuccess) return hip_fail(h, he, "wait for previous closure upload");
+    std::memcpy(h->h_mio_pinned, m.data(), sizeof(vefk::KMomIO) * np);
+    he = hipMemcpyAsync(h->d_mio, h->h_mio_pinned, sizeof(vefk::KMomIO) * np, hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipEventRecord(h->mio_uploaded, s);
+    if (he != hipSuccess) return hip_fail(h, he, "upload closure pointers");
+    h->mio_last = m;
+    h->mio_valid = true;
+  }
+  he = vefk::launch_zero_nonpos(h->d_mio, np, s);
   if (he != hipSuccess) return hip_fail(h, he, "upload closure pointers");
   for (int k = 0; k < np; ++k) {
     const auto &pl = h->plans[k];
@@ -781,6 +799,7 @@ int vef_sweep_timing(vef_sweep_t *h, double *sweep_ms, int *n_launches) {
   if (he != hipSuccess) return hip_fail(h, he, "stream synchronize");
   double tot = 0.0;
   for (int it = 0; it < h->timed_iters; ++it) {
+    if ((it + 1) % h->timing_stride != 0 && it != h->timed_iters - 1) continue;
     float ms = 0.0f;
     he = hipEventElapsedTime(&ms, h->events[2 * it], h->events[2 * it + 1]);
     if (he != hipSuccess) return hip_fail(h, he, "event elapsed time");

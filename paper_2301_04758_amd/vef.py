@@ -162,11 +162,11 @@ def vef_plan_query(problem, lag_cycles: bool = False) -> dict:
 
 
 def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
-                     block: int = 0, timing: bool = False, pipeline_waves: int = 0,
+                     block: int = 0, timing: int = 0, pipeline_waves: int = 0,
                      pipeline_ring: int = 0, fixup: bool = False, lag_cycles: bool = False) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
-    opt = vef_options(precision, schedule, block, 1 if timing else 0, pipeline_waves, pipeline_ring,
+    opt = vef_options(precision, schedule, block, int(timing), pipeline_waves, pipeline_ring,
                       1 if fixup else 0, VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT)
     h = C.c_void_p()
     rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))

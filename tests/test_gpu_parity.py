@@ -401,6 +401,29 @@ def test_probe_machine(torch):
     assert 1 < m["lds_handoff_ns"] < 100000
 
 
+@pytest.mark.parametrize("schedule", ["level", "dir"])
+def test_timing_stride(torch, schedule):
+    """vef_options.timing = k times the sweep kernels of every k-th source
+    iteration and of the last one; k = 1 times all.  Results do not depend
+    on it."""
+    from paper_2301_04758_amd import vef
+    pr = _small(12, 12, 2, 1, 4, st=2.0, ss=1.0)
+    out = {}
+    for k in (1, 3):
+        sw = vef.Sweep([pr], precision="fp64", schedule=schedule, timing=k)
+        io = sw.buffers(n_iter=7, store_psi=False)
+        sw.run(io, n_iter=7)
+        ms, nl = sw.timing()
+        sw.check()
+        out[k] = (ms, nl, io[0]["mom"].cpu().numpy())
+        sw.close()
+    per_sweep = out[1][1] // 7
+    assert out[1][1] == 7 * per_sweep and per_sweep >= 1
+    assert out[3][1] == 3 * per_sweep  # iterations 3, 6 and the last (7)
+    assert out[1][0] > 0 and out[3][0] > 0
+    assert np.array_equal(out[1][2], out[3][2])
+
+
 def _negative_flux_case(kind):
     """Thick cells with a source in one corner element: the unfixed solution
     dips below zero.  kind selects the kernel family that solves it."""
