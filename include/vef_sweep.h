@@ -257,6 +257,39 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info);
  * [n_bf][2]. */
 int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out);
 
+/* Element-local blocks of the hybridized Raviart-Thomas VEF method and their
+ * inverse (Sec. 7, "Implementation Details": Eq. eq:hyb_form and the blocks
+ * W, X, Y, Z of Eq. eq:block_inv), for every element of problem k, on the
+ * device, from the moments of a transport run on h.  Per element K:
+ *   A_ij  = int_K sigma_t v_i . v_j dx
+ *           + int_{dK cap Gamma_b} (1/E_b)(v_i . E n)(v_j . n) ds   (Eq. eq:A)
+ *   G_ij  = - int_K grad v_i : E u_j dx                               (hat G)
+ *   D_ij  = int_K u_i div v_j dx                                      (Eq. eq:D)
+ *   Ma_ij = int_K (sigma_t - sigma_s) u_i u_j dx                      (Eq. eq:Ma)
+ * with v_i the RT_p basis of D_p(K) (reference Q_{p+1,p} x Q_{p,p+1} under
+ * the contravariant Piola map, Eq. eq:piola; nodal at Gauss-Lobatto points
+ * along the component's direction and Gauss-Legendre points across it;
+ * xi-component functions first, node a + (p+2) b, then eta-component
+ * functions, node a + (p+1) b) and u_i the Lagrange basis of Q_p through the
+ * tensor Gauss-Legendre points (node a + (p+1) b).  E = P / phi at each
+ * quadrature point from mom (the isotropic I/3 where phi <= 0).  inv receives
+ * [[W, X], [Y, Z]] = [[A, G], [D, Ma]]^{-1}.
+ *   mom  device [6][n_elem][(p+1)^2]: moments of vef_sweep_run;
+ *   Eb   device [n_bf][nq]: E_b of vef_moments (values <= 0 taken as 1/2),
+ *        or NULL (1/2 everywhere);
+ *   inv  device out [n_elem][n][n] row major, n = 2(p+1)(p+2) + (p+1)^2.
+ * The inverse is formed by elimination in natural order (current unknowns
+ * first, then the Schur complement S = Ma - D A^{-1} G): like the block
+ * formulas, it assumes A and S non-singular (sigma_t > 0) and allows a
+ * singular Ma.  Quadrature: the handle's nq Gauss points per direction, which
+ * must be p + 2 or p + 3 (exact for the RT mass).  Requirements: every
+ * element map affine (vef_info.affine), p <= 3.  Asynchronous on stream; the
+ * first call for a problem uploads its geometry and tables (synchronous).
+ * Errors: VEF_ERR_INVALID (problem not affine, p or nq out of range, NULL
+ * pointers), VEF_ERR_HIP, VEF_ERR_OOM. */
+int vef_hrt_local_inverse(vef_sweep_t *h, int k, const double *mom, const double *Eb, double *inv,
+                          void *stream);
+
 /* Measured machine figures (vef_probe_machine). */
 typedef struct {
   int compute_units;      /* of the current device */

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvefsweep.so")
 SOURCES = ["plan.cpp", "kernels.hip", "sweep_p1.hip", "sweep_p2.hip", "sweep_p3.hip", "sweep_p4.hip", "probe.hip",
-           "api.cpp"]
+           "hrt.hip", "api.cpp"]
 ARCH = os.environ.get("VEF_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU forms.

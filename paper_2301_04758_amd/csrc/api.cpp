@@ -96,6 +96,8 @@ struct vef_sweep {
   int pipeline_ring = 0;
   int fixup = 0;
   int cycles = VEF_CYCLES_REJECT;
+  std::vector<double *> hrt_geo;               // per problem [ne][13], allocated on first need
+  std::map<std::pair<int, int>, double *> hrt_tab;  // (p, nq) -> HRT tables
   std::vector<hipEvent_t> events;  // [2 * iterations] of the last run
   int timed_iters = 0;
   int timed_launches = 0;
@@ -150,6 +152,11 @@ void free_all(vef_sweep *h) {
   for (void *p : h->psi_internal)
     if (p) (void)hipFree(p);
   h->psi_internal.clear();
+  for (double *p : h->hrt_geo)
+    if (p) (void)hipFree(p);
+  h->hrt_geo.clear();
+  for (auto &kv : h->hrt_tab) (void)hipFree(kv.second);
+  h->hrt_tab.clear();
   for (double *p : h->resid_scratch)
     if (p) (void)hipFree(p);
   h->resid_scratch.clear();
@@ -691,6 +698,55 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->schedule = h->schedule;
   info->kernel = mode_of(pl, h->schedule, h->pipeline_waves >= 0);
   info->n_lagged = pl.n_lagged;
+  return VEF_OK;
+}
+
+int vef_hrt_local_inverse(vef_sweep_t *h, int k, const double *mom, const double *Eb, double *inv,
+                          void *stream) {
+  if (!h) return VEF_ERR_INVALID;
+  if (k < 0 || k >= (int)h->plans.size()) return set_err(h, VEF_ERR_INVALID, "problem index out of range");
+  if (!mom || !inv) return set_err(h, VEF_ERR_INVALID, "mom and inv are required");
+  const auto &pl = h->plans[k];
+  if (!pl.affine) return set_err(h, VEF_ERR_INVALID, "HRT local blocks need affine elements");
+  vefplan::HrtSizes z;
+  if (vefplan::hrt_sizes(pl.p, pl.nq, z))
+    return set_err(h, VEF_ERR_INVALID, "HRT local blocks need p in 1..3 and nq = p + 2 or p + 3");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t he;
+  // set-up on first use (not in a captured region): affine geometry in
+  // double precision and the tables of (p, nq)
+  if (h->hrt_geo.size() != h->plans.size()) h->hrt_geo.assign(h->plans.size(), nullptr);
+  if (!h->hrt_geo[k]) {
+    std::vector<double> g((size_t)pl.ne * 13);
+    for (int e = 0; e < pl.ne; ++e)
+      for (int i = 0; i < 13; ++i) g[(size_t)e * 13 + i] = pl.geo_a[(size_t)e * 16 + i];
+    double *d = nullptr;
+    he = hipMalloc(&d, g.size() * sizeof(double));
+    if (he == hipSuccess) he = hipMemcpy(d, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      if (d) (void)hipFree(d);
+      return hip_fail(h, he, "upload HRT geometry");
+    }
+    h->hrt_geo[k] = d;
+  }
+  const auto key = std::make_pair(pl.p, pl.nq);
+  if (!h->hrt_tab.count(key)) {
+    std::vector<double> blob;
+    if (vefplan::build_hrt_tables(pl.p, pl.nq, blob)) return set_err(h, VEF_ERR_INVALID, "HRT tables");
+    double *d = nullptr;
+    he = hipMalloc(&d, blob.size() * sizeof(double));
+    if (he == hipSuccess) he = hipMemcpy(d, blob.data(), blob.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      if (d) (void)hipFree(d);
+      return hip_fail(h, he, "upload HRT tables");
+    }
+    h->hrt_tab[key] = d;
+  }
+  vefk::HrtLaunch L{pl.p, pl.nq, pl.ne, h->hrt_tab[key], h->hrt_geo[k], h->h_probs[k].sig, h->h_probs[k].nbr,
+                    mom, Eb, inv, s};
+  he = vefk::launch_hrt_inverse(L);
+  if (he != hipSuccess) return hip_fail(h, he, "launch HRT local inverse");
+  h->last_stream = s;
   return VEF_OK;
 }
 

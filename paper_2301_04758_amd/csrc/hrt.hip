@@ -1,0 +1,241 @@
+// Element-local blocks of the hybridized Raviart-Thomas VEF method and their
+// inverse (Olivier & Haut, Sec. 7, "Implementation Details": the local
+// matrices A_hat, G_hat, D_hat, M_a and the blocks W, X, Y, Z of Eq.
+// eq:block_inv), for affine elements.
+//
+// One wave per element; lane r owns row r of the local block matrix
+//   [[A, G], [D, Ma]]   (nv + nphi rows: RT_p current, then Q_p scalar flux).
+// On an affine element the contravariant Piola map (Eq. eq:piola) has a
+// constant F and J, and its gradient (Eq. eq:piola_grad) has no correction
+// term, so every entry is a reference-space sum:
+//   A_ij = sum_q w_q sigma_t / J  vh_i . (F^T F) vh_j
+//          + boundary faces: sum_q w_q |N_f| / (E_b J^2) (vh_i . F^T E n)(vh_j . F^T n)
+//   G_ij = - sum_q w_q (grad vh_i : F^T E F^{-T}) uh_j
+//   D_ij = sum_q w_q uh_i div vh_j,   Ma_ij = sum_q w_q sigma_a J uh_i uh_j.
+// E = P / phi at each point from the transport moments (isotropic I/3 where
+// phi <= 0); E_b as given by the closures (1/2 where not positive).
+//
+// The inverse is in-place Gauss-Jordan in natural order: the current
+// unknowns (A, symmetric positive definite for sigma_t > 0) are eliminated
+// first, then the Schur complement S = Ma - D A^{-1} G -- the block
+// elimination behind the formulas for W, X, Y, Z, which assume A and S
+// non-singular and allow a singular Ma.  The pivot row is broadcast with
+// readlane (fully unrolled, so every index is a compile-time constant).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace vefk {
+
+namespace {
+
+constexpr int kHrtWaves = 4;  // elements (waves) per work-group
+
+__device__ __forceinline__ double readlane_d(double x, int k) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int P, int NQ>
+struct Hrt {
+  static constexpr int NX = (P + 2) * (P + 1);
+  static constexpr int NV = 2 * NX;
+  static constexpr int NPHI = (P + 1) * (P + 1);
+  static constexpr int NT = (P + 1) * (P + 1);
+  static constexpr int N = NV + NPHI;
+  static constexpr int Q = NQ * NQ;
+  static constexpr int OFF_W = 0;
+  static constexpr int OFF_VR = OFF_W + Q;
+  static constexpr int OFF_DR = OFF_VR + Q * NV;
+  static constexpr int OFF_U = OFF_DR + 2 * Q * NV;
+  static constexpr int OFF_TV = OFF_U + Q * NPHI;
+  static constexpr int OFF_VRF = OFF_TV + Q * NT;
+  static constexpr int OFF_TF = OFF_VRF + 4 * NQ * NV;
+  static constexpr int OFF_WF = OFF_TF + 4 * NQ * NT;
+  static_assert(N <= 64, "one row per lane");
+};
+
+// E = P / phi at one point from nodal transport moments (basis values b)
+template <int NT>
+__device__ __forceinline__ void eddington_at(const double *__restrict__ mom, size_t ne_nt, size_t off,
+                                             const double *__restrict__ b, double &exx, double &exy, double &eyy) {
+  double ph = 0.0, pxx = 0.0, pxy = 0.0, pyy = 0.0;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    ph += b[j] * mom[off + j];
+    pxx += b[j] * mom[3 * ne_nt + off + j];
+    pxy += b[j] * mom[4 * ne_nt + off + j];
+    pyy += b[j] * mom[5 * ne_nt + off + j];
+  }
+  if (ph > 0.0) {
+    exx = pxx / ph;
+    exy = pxy / ph;
+    eyy = pyy / ph;
+  } else {
+    exx = eyy = 1.0 / 3.0;
+    exy = 0.0;
+  }
+}
+
+template <int P, int NQ>
+__global__ void __launch_bounds__(64 * kHrtWaves)
+k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, const double *__restrict__ sig,
+              const int32_t *__restrict__ nbr, const double *__restrict__ mom, const double *__restrict__ Eb,
+              int ne, double *__restrict__ out) {
+  using H = Hrt<P, NQ>;
+  constexpr int NX = H::NX, NV = H::NV, NPHI = H::NPHI, NT = H::NT, N = H::N, Q = H::Q;
+  __shared__ double sT[kHrtWaves][Q][4];   // F^T E F^{-T} at volume points
+  __shared__ double sF[kHrtWaves][NQ][4];  // E at the points of one boundary face, and 1 / E_b
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * kHrtWaves + w;
+  if (e >= ne) return;  // whole waves only; the kernel has no work-group barrier
+
+  const double *g = geo + (size_t)e * 13;  // J, adj(F) row major, face chords N_0..N_3
+  const double J = g[0];
+  const double F00 = g[4], F01 = -g[2], F10 = -g[3], F11 = g[1];
+  // F^{-T} = adj(F)^T / J
+  const double Fi00 = g[1] / J, Fi01 = g[3] / J, Fi10 = g[2] / J, Fi11 = g[4] / J;
+  const double G00 = F00 * F00 + F10 * F10, G01 = F00 * F01 + F10 * F11, G11 = F01 * F01 + F11 * F11;
+  const double st = sig[2 * (size_t)e], sa = st - sig[2 * (size_t)e + 1];
+  const size_t ne_nt = (size_t)ne * NT, off_e = (size_t)e * NT;
+
+  // E at the volume points, transformed: T = F^T E F^{-T}
+  if (lane < Q) {
+    double exx, exy, eyy;
+    eddington_at<NT>(mom, ne_nt, off_e, tab + H::OFF_TV + lane * NT, exx, exy, eyy);
+    // F^T E
+    const double a00 = F00 * exx + F10 * exy, a01 = F00 * exy + F10 * eyy;
+    const double a10 = F01 * exx + F11 * exy, a11 = F01 * exy + F11 * eyy;
+    sT[w][lane][0] = a00 * Fi00 + a01 * Fi10;
+    sT[w][lane][1] = a00 * Fi01 + a01 * Fi11;
+    sT[w][lane][2] = a10 * Fi00 + a11 * Fi10;
+    sT[w][lane][3] = a10 * Fi01 + a11 * Fi11;
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  const int r = lane;
+  const bool cur = r < NV;           // current test function v_r
+  const int rc = r < NX ? 0 : 1;     // its non-zero component
+  const int rv = cur ? r : 0;        // table index (clamped for other lanes)
+  const int rp = (r >= NV && r < N) ? r - NV : 0;
+  double a[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) a[j] = 0.0;
+
+#pragma unroll 1
+  for (int q = 0; q < Q; ++q) {
+    const double wq = tab[H::OFF_W + q];
+    const double *vr = tab + H::OFF_VR + q * NV;
+    const double *dr = tab + H::OFF_DR + q * NV * 2;
+    const double *u = tab + H::OFF_U + q * NPHI;
+    const double t00 = sT[w][q][0], t01 = sT[w][q][1], t10 = sT[w][q][2], t11 = sT[w][q][3];
+    if (cur) {
+      const double vi = vr[rv], dxi = dr[2 * rv], dyi = dr[2 * rv + 1];
+      const double gT = rc == 0 ? dxi * t00 + dyi * t01 : dxi * t10 + dyi * t11;
+      const double m = wq * st / J * vi;
+      const double c0 = m * (rc == 0 ? G00 : G01), c1 = m * (rc == 0 ? G01 : G11);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) a[j] += c0 * vr[j];
+#pragma unroll
+      for (int j = NX; j < NV; ++j) a[j] += c1 * vr[j];
+      const double cg = -wq * gT;
+#pragma unroll
+      for (int j = 0; j < NPHI; ++j) a[NV + j] += cg * u[j];
+    } else if (r < N) {
+      const double ui = wq * u[rp];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) a[j] += ui * dr[2 * j];
+#pragma unroll
+      for (int j = NX; j < NV; ++j) a[j] += ui * dr[2 * j + 1];
+      const double cm = ui * sa * J;
+#pragma unroll
+      for (int j = 0; j < NPHI; ++j) a[NV + j] += cm * u[j];
+    }
+  }
+
+  // boundary faces: (1/E_b) (v . E n)(J . n)
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const int nb = nbr[4 * (size_t)e + f];
+    if (nb >= 0) continue;
+    const int bf = -nb - 1;
+    if (lane < NQ) {
+      double exx, exy, eyy;
+      eddington_at<NT>(mom, ne_nt, off_e, tab + H::OFF_TF + (f * NQ + lane) * NT, exx, exy, eyy);
+      const double eb = Eb ? Eb[(size_t)bf * NQ + lane] : 0.5;
+      sF[w][lane][0] = exx;
+      sF[w][lane][1] = exy;
+      sF[w][lane][2] = eyy;
+      sF[w][lane][3] = 1.0 / (eb > 0.0 ? eb : 0.5);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double cx = g[5 + 2 * f], cy = g[6 + 2 * f];
+    const double len = sqrt(cx * cx + cy * cy), nx = cx / len, ny = cy / len;
+    const double tn0 = F00 * nx + F10 * ny, tn1 = F01 * nx + F11 * ny;  // t_c . n
+    if (cur) {
+#pragma unroll 1
+      for (int q = 0; q < NQ; ++q) {
+        const double *vf = tab + H::OFF_VRF + (f * NQ + q) * NV;
+        const double enx = sF[w][q][0] * nx + sF[w][q][1] * ny, eny = sF[w][q][1] * nx + sF[w][q][2] * ny;
+        const double ten = rc == 0 ? F00 * enx + F10 * eny : F01 * enx + F11 * eny;  // t_{c_r} . E n
+        const double c = tab[H::OFF_WF + q] * len * sF[w][q][3] / (J * J) * vf[rv] * ten;
+        const double c0 = c * tn0, c1 = c * tn1;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) a[j] += c0 * vf[j];
+#pragma unroll
+        for (int j = NX; j < NV; ++j) a[j] += c1 * vf[j];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // in-place Gauss-Jordan inversion, natural order
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double pinv = 1.0 / readlane_d(a[k], k);
+    const bool me = lane == k;
+    const double fk = a[k] * pinv;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (j == k) continue;
+      const double rk = readlane_d(a[j], k);
+      a[j] = me ? rk * pinv : a[j] - fk * rk;
+    }
+    a[k] = me ? pinv : -fk;
+  }
+
+  if (r < N) {
+    double *o = out + ((size_t)e * N + r) * N;
+#pragma unroll
+    for (int j = 0; j < N; ++j) o[j] = a[j];
+  }
+}
+
+template <int P, int NQ>
+hipError_t launch_hrt_t(const HrtLaunch &L) {
+  const int grid = (L.ne + kHrtWaves - 1) / kHrtWaves;
+  hipLaunchKernelGGL((k_hrt_inverse<P, NQ>), dim3(grid), dim3(64 * kHrtWaves), 0, L.stream, L.tab, L.geo, L.sig, L.nbr,
+                     L.mom, L.Eb, L.ne, L.out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_hrt_inverse(const HrtLaunch &L) {
+  if (L.ne <= 0) return hipSuccess;
+  switch (L.p * 16 + L.nq) {
+    case 1 * 16 + 3: return launch_hrt_t<1, 3>(L);
+    case 1 * 16 + 4: return launch_hrt_t<1, 4>(L);
+    case 2 * 16 + 4: return launch_hrt_t<2, 4>(L);
+    case 2 * 16 + 5: return launch_hrt_t<2, 5>(L);
+    case 3 * 16 + 5: return launch_hrt_t<3, 5>(L);
+    case 3 * 16 + 6: return launch_hrt_t<3, 6>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace vefk

@@ -91,4 +91,18 @@ hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int n
                            int nq, hipStream_t s);
 hipError_t launch_zero_nonpos(const KMomIO *io, int n_probs, hipStream_t s);
 
+// Element-local HRT VEF blocks and their inverse (hrt.hip), affine elements.
+struct HrtLaunch {
+  int p, nq, ne;
+  const double *tab;   // vefplan::build_hrt_tables blob
+  const double *geo;   // [ne][13]: J, adj(F) row major, face chords N_0..N_3
+  const double *sig;   // [ne][2]: sigma_t, sigma_s
+  const int32_t *nbr;  // [ne][4]: neighbour or -(boundary face + 1)
+  const double *mom;   // [6][ne][(p+1)^2] transport moments
+  const double *Eb;    // [nbf][nq] or NULL
+  double *out;         // [ne][n][n]
+  hipStream_t stream;
+};
+hipError_t launch_hrt_inverse(const HrtLaunch &L);
+
 }  // namespace vefk

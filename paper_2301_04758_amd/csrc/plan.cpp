@@ -242,6 +242,102 @@ int build_tables(int p, int nq, Tables &t) {
   return VEF_OK;
 }
 
+int hrt_sizes(int p, int nq, HrtSizes &z) {
+  if (p < 1 || p > 3 || nq < p + 2 || nq > p + 3) return VEF_ERR_INVALID;
+  z.p = p;
+  z.nq = nq;
+  z.nx = (p + 2) * (p + 1);
+  z.nv = 2 * z.nx;
+  z.nphi = (p + 1) * (p + 1);
+  z.nt = (p + 1) * (p + 1);
+  const int Q = nq * nq;
+  z.off_w = 0;
+  z.off_vr = z.off_w + Q;
+  z.off_dr = z.off_vr + Q * z.nv;
+  z.off_u = z.off_dr + 2 * Q * z.nv;
+  z.off_tv = z.off_u + Q * z.nphi;
+  z.off_vrf = z.off_tv + Q * z.nt;
+  z.off_tf = z.off_vrf + 4 * nq * z.nv;
+  z.off_wf = z.off_tf + 4 * nq * z.nt;
+  z.total = z.off_wf + nq;
+  return VEF_OK;
+}
+
+int build_hrt_tables(int p, int nq, std::vector<double> &blob) {
+  HrtSizes z;
+  if (hrt_sizes(p, nq, z)) return VEF_ERR_INVALID;
+  std::vector<double> lob1, lob, gx, gw, leg, lw;
+  gauss_lobatto01(p + 1, lob1);  // RT normal direction: degree p + 1, closed points
+  gauss_lobatto01(p, lob);       // transport basis: degree p, closed points
+  gauss_legendre01(nq, gx, gw);  // quadrature
+  gauss_legendre01(p + 1, leg, lw);  // RT tangential direction and phi: p + 1 open points
+  const int Q = nq * nq;
+  blob.assign(z.total, 0.0);
+  // 1D values and derivatives at a point
+  auto eval = [](const std::vector<double> &nodes, double x, std::vector<double> &v, std::vector<double> &d) {
+    v.assign(nodes.size(), 0.0);
+    d.assign(nodes.size(), 0.0);
+    bary_eval(nodes, x, v.data(), d.data());
+  };
+  // one RT function's non-zero component and its (xi, eta) derivatives at (x, y)
+  std::vector<double> L1x, dL1x, L1y, dL1y, Gx, dGx, Gy, dGy, Tx, dTx, Ty, dTy;
+  auto rt_at = [&](double x, double y, double *val, double *dval) {
+    eval(lob1, x, L1x, dL1x);
+    eval(lob1, y, L1y, dL1y);
+    eval(leg, x, Gx, dGx);
+    eval(leg, y, Gy, dGy);
+    int i = 0;
+    for (int b = 0; b <= p; ++b)
+      for (int a = 0; a <= p + 1; ++a, ++i) {  // xi component
+        val[i] = L1x[a] * Gy[b];
+        if (dval) {
+          dval[2 * i] = dL1x[a] * Gy[b];
+          dval[2 * i + 1] = L1x[a] * dGy[b];
+        }
+      }
+    for (int b = 0; b <= p + 1; ++b)
+      for (int a = 0; a <= p; ++a, ++i) {  // eta component
+        val[i] = Gx[a] * L1y[b];
+        if (dval) {
+          dval[2 * i] = dGx[a] * L1y[b];
+          dval[2 * i + 1] = Gx[a] * dL1y[b];
+        }
+      }
+  };
+  auto tensor = [&](const std::vector<double> &nodes, double x, double y, double *out) {
+    eval(nodes, x, Tx, dTx);
+    eval(nodes, y, Ty, dTy);
+    const int k = (int)nodes.size();
+    for (int b = 0; b < k; ++b)
+      for (int a = 0; a < k; ++a) out[a + k * b] = Tx[a] * Ty[b];
+  };
+  for (int qy = 0; qy < nq; ++qy)
+    for (int qx = 0; qx < nq; ++qx) {
+      const int q = qx + nq * qy;
+      const double x = gx[qx], y = gx[qy];
+      blob[z.off_w + q] = gw[qx] * gw[qy];
+      rt_at(x, y, &blob[z.off_vr + (size_t)q * z.nv], &blob[z.off_dr + (size_t)q * z.nv * 2]);
+      tensor(leg, x, y, &blob[z.off_u + (size_t)q * z.nphi]);
+      tensor(lob, x, y, &blob[z.off_tv + (size_t)q * z.nt]);
+    }
+  for (int f = 0; f < 4; ++f)
+    for (int q = 0; q < nq; ++q) {
+      const double s = gx[q];
+      double x, y;  // counter-clockwise face parameter
+      switch (f) {
+        case 0: x = s; y = 0.0; break;
+        case 1: x = 1.0; y = s; break;
+        case 2: x = 1.0 - s; y = 1.0; break;
+        default: x = 0.0; y = 1.0 - s; break;
+      }
+      rt_at(x, y, &blob[z.off_vrf + ((size_t)f * nq + q) * z.nv], nullptr);
+      tensor(lob, x, y, &blob[z.off_tf + ((size_t)f * nq + q) * z.nt]);
+    }
+  for (int q = 0; q < nq; ++q) blob[z.off_wf + q] = gw[q];
+  (void)Q;
+  return VEF_OK;
+}
+
 int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, ProblemPlan &o, std::string &err) {
   if (d.p < 1 || d.p > kMaxP) return fail(err, VEF_ERR_INVALID, "p=%lld out of range 1..4", d.p);
   if (d.m < 1 || d.m > kMaxM) return fail(err, VEF_ERR_INVALID, "m=%lld out of range 1..3", d.m);

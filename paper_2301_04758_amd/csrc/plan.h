@@ -67,6 +67,22 @@ struct ProblemPlan {
 
 int build_tables(int p, int nq, Tables &t);
 
+// Tables of the element-local HRT VEF blocks for degree p (1..3) and nq
+// Gauss points per direction (p + 2 or p + 3), one blob of doubles:
+//   w [Q] tensor weights; vr [Q][nv] the non-zero component of each reference
+//   RT_p function (xi-component functions first, node a + (p+2) b, then
+//   eta-component functions, node a + (p+1) b); dr [Q][nv][2] its xi and eta
+//   derivatives; u [Q][nphi] the Gauss-Legendre nodal phi basis; tv [Q][nt]
+//   the transport (Gauss-Lobatto nodal) basis; vrf [4][nq][nv] and
+//   tf [4][nq][nt] the same at face points (counter-clockwise parameter);
+//   wf [nq] 1D weights.  Q = nq^2.
+struct HrtSizes {
+  int p = 0, nq = 0, nx = 0, nv = 0, nphi = 0, nt = 0;
+  int off_w = 0, off_vr = 0, off_dr = 0, off_u = 0, off_tv = 0, off_vrf = 0, off_tf = 0, off_wf = 0, total = 0;
+};
+int hrt_sizes(int p, int nq, HrtSizes &z);
+int build_hrt_tables(int p, int nq, std::vector<double> &blob);
+
 // Validates and plans one problem.  lag_cycles: a cyclic upwind graph is
 // ordered by releasing elements with lagged couplings instead of failing with
 // VEF_ERR_CYCLE.  Returns VEF_OK or a VEF_ERR_* status and a message in err.

@@ -40,7 +40,8 @@ KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KE
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
-            "vef_sweep_autotune", "vef_probe_machine", "vef_last_error", "vef_status_string")
+            "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_last_error",
+            "vef_status_string")
 
 
 class vef_problem_desc(C.Structure):
@@ -96,12 +97,14 @@ def _load():
     L.vef_sweep_timing.argtypes = [H, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.vef_sweep_autotune.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p, C.c_int, C.c_void_p]
     L.vef_probe_machine.argtypes = [C.c_void_p, C.c_void_p]
+    L.vef_hrt_local_inverse.argtypes = [H, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.vef_last_error.argtypes = [H]
     L.vef_last_error.restype = C.c_char_p
     L.vef_status_string.argtypes = [C.c_int]
     L.vef_status_string.restype = C.c_char_p
     for f in ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
-              "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing"):
+              "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
+              "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -258,6 +261,14 @@ def vef_probe_machine(stream=None) -> dict:
     return {f: getattr(m, f) for f, _ in vef_machine._fields_}
 
 
+def vef_hrt_local_inverse(h: int, k: int, mom, Eb, inv, stream=None):
+    """Device pointers (int) or torch tensors; see include/vef_sweep.h."""
+    rc = lib.vef_hrt_local_inverse(C.c_void_p(h), int(k), C.c_void_p(_ptr(mom)), C.c_void_p(_ptr(Eb)),
+                                   C.c_void_p(_ptr(inv)), C.c_void_p(_stream_handle(stream)))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+
+
 def vef_sweep_check(h: int):
     rc = lib.vef_sweep_check(C.c_void_p(h))
     if rc != VEF_OK:
@@ -337,6 +348,19 @@ class Sweep:
 
     def moments(self, mio, stream=None):
         vef_moments(self.h, mio, stream)
+
+    def hrt_local_inverse(self, k, mom, Eb=None, stream=None):
+        """[[W, X], [Y, Z]] of every element of problem k: a [n_elem, n, n]
+        float64 tensor, n = 2(p+1)(p+2) + (p+1)^2 (vef_hrt_local_inverse)."""
+        t = self.torch
+        pr = self.problems[k]
+        p = pr.p
+        n = 2 * (p + 1) * (p + 2) + (p + 1) ** 2
+        out = t.empty((pr.n_elem, n, n), dtype=t.float64, device=self.device)
+        mom = mom.contiguous()
+        Eb = None if Eb is None else Eb.contiguous()
+        vef_hrt_local_inverse(self.h, k, mom, Eb, out, stream)
+        return out
 
     def check(self):
         vef_sweep_check(self.h)

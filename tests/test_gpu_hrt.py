@@ -1,0 +1,125 @@
+"""GPU parity of the element-local HRT block inverse (vef_hrt_local_inverse)
+with the oracle (oracle/hrt_oracle.py): every entry of [[W, X], [Y, Z]] of
+every element, with E from the moments of a real transport run and E_b from
+vef_moments.  Bound per element: max(1e-12, 16 eps kappa) relative to the
+element's largest entry, kappa the condition number of its block matrix
+(two backward-stable inversions differ by a few eps kappa)."""
+import numpy as np
+import pytest
+
+from oracle import hrt_oracle as H
+from paper_2301_04758_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _sheared(n, p, nq, N=4, seed=0, c=0.6):
+    cp, ec = P.quad_mesh(n, n, 1)
+    cp = cp @ np.array([[1.7, 0.35], [0.2, 1.0]]).T + np.array([3.0, -1.0])
+    om, wt = P.level_symmetric_2d(N)
+    ne = ec.shape[0]
+    rng = np.random.default_rng(seed)
+    st = rng.uniform(0.5, 5.0, ne)
+    pr = P.Problem("sheared", p, 1, cp, ec, om, wt, st, c * st, nx=n, ny=n, nq=nq)
+    pr.q_iso = np.ones((ne, (p + 1) ** 2))
+    # an inflow on part of the boundary makes the angular flux anisotropic
+    return pr
+
+
+def _moments(torch, pr, n_iter=2):
+    from paper_2301_04758_amd import vef
+    sw = vef.Sweep([pr], precision="fp64")
+    io = sw.buffers(n_iter=n_iter, store_psi=False)
+    sw.run(io, n_iter=n_iter)
+    mio = sw.moment_buffers(io)
+    sw.moments(mio)
+    torch.cuda.synchronize()
+    sw.check()
+    return sw, io, mio
+
+
+def _compare(inv_gpu, inv_ref, blk):
+    full = H.assemble_full(blk)
+    kappa = np.linalg.cond(full)
+    err = np.abs(inv_gpu - inv_ref).max(axis=(1, 2)) / np.abs(inv_ref).max(axis=(1, 2))
+    bound = np.maximum(1e-12, 16 * np.finfo(float).eps * kappa)
+    worst = int(np.argmax(err / bound))
+    assert (err <= bound).all(), (worst, err[worst], bound[worst], kappa[worst])
+    return float(err.max()), float(kappa.max())
+
+
+@pytest.mark.parametrize("p,nq", [(1, 3), (1, 4), (2, 4), (2, 5), (3, 5)])
+def test_hrt_inverse_parity_sheared(torch, p, nq):
+    pr = _sheared(6, p, nq)
+    sw, io, mio = _moments(torch, pr)
+    try:
+        inv = sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"])
+        torch.cuda.synchronize()
+        got = inv.cpu().numpy()
+        mom = io[0]["mom"].cpu().numpy()
+        Eb = mio[0]["Eb"].cpu().numpy()
+    finally:
+        sw.close()
+    ref, blk = H.local_inverse(pr, nq, mom, Eb)
+    err, kappa = _compare(got, ref, blk)
+    print("p=%d nq=%d max rel err %.2e max kappa %.2e" % (p, nq, err, kappa), flush=True)
+
+
+def test_hrt_inverse_without_Eb(torch):
+    pr = _sheared(4, 2, 4)
+    sw, io, mio = _moments(torch, pr)
+    try:
+        got = sw.hrt_local_inverse(0, io[0]["mom"], None).cpu().numpy()
+        mom = io[0]["mom"].cpu().numpy()
+    finally:
+        sw.close()
+    ref, blk = H.local_inverse(pr, 4, mom, np.full((4 * 4, 4), 0.5))
+    _compare(got, ref, blk)
+
+
+def test_hrt_inverse_full_c2_mesh(torch):
+    """The 64x64 C2 mesh and materials (p = 2, S8, sigma_t log-uniform per
+    8x8 block, c = 0.9) with nq = 4, moments of 3 source iterations: all
+    4096 elements."""
+    (pr,), _ = P.make_config("c2")
+    pr.nq = 4
+    sw, io, mio = _moments(torch, pr, n_iter=3)
+    try:
+        got = sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"]).cpu().numpy()
+        mom = io[0]["mom"].cpu().numpy()
+        Eb = mio[0]["Eb"].cpu().numpy()
+    finally:
+        sw.close()
+    ref, blk = H.local_inverse(pr, 4, mom, Eb)
+    err, kappa = _compare(got, ref, blk)
+    print("c2 mesh: max rel err %.2e max kappa %.2e" % (err, kappa), flush=True)
+
+
+def test_hrt_inverse_rejects(torch):
+    from paper_2301_04758_amd import vef
+    pr = _sheared(3, 2, 3)  # nq = p + 1: the RT mass would be under-integrated
+    sw, io, mio = _moments(torch, pr)
+    try:
+        with pytest.raises(vef.VefError) as e:
+            sw.hrt_local_inverse(0, io[0]["mom"], None)
+        assert e.value.code == vef.VEF_ERR_INVALID
+    finally:
+        sw.close()
+    cp, ec = P.quad_mesh(3, 3, 2)
+    pr = P.make_problem("curved", 3, 3, 1, 2, 4, 1.0, 0.5, warp=0.1)
+    pr.nq = 3
+    sw, io, mio = _moments(torch, pr)
+    try:
+        with pytest.raises(vef.VefError) as e:
+            sw.hrt_local_inverse(0, io[0]["mom"], None)
+        assert "affine" in str(e.value)
+    finally:
+        sw.close()
