@@ -204,6 +204,62 @@ def lagged_leg(steps, n_iter=5):
     return out
 
 
+def hrt_flops_bytes(p, nq):
+    """Algorithmic flops and HBM bytes of one element of the HRT local block
+    inverse: assembly 2 Q N^2 (every row against every trial function at
+    every Gauss point), in-place Gauss-Jordan 2 N^3; bytes: the N x N
+    inverse written, the element's moments, geometry, cross sections and
+    neighbours read."""
+    n = 2 * (p + 1) * (p + 2) + (p + 1) ** 2
+    Q = nq * nq
+    return 2 * Q * n * n + 2 * n ** 3, 8 * n * n + 6 * (p + 1) ** 2 * 8 + 13 * 8 + 16 + 16
+
+
+def hrt_leg(reps=5):
+    """Element-local HRT VEF block inverse (W, X, Y, Z) on the C2 mesh and a
+    512x512 affine mesh, p = 2, nq = 4, E from the moments of one transport
+    sweep: time per launch from HIP events on the launch stream."""
+    import numpy as np
+    import torch
+    from paper_2301_04758_amd import problems as P
+    from paper_2301_04758_amd import vef
+    (c2,), _ = P.make_config("c2")
+    big = P.make_problem("affine_512", 512, 512, 2, 1, 8, 1.0, 0.9)
+    rng = np.random.Generator(np.random.PCG64(P.SEED_BASE + 11))
+    big.sigma_t = P.block_log_uniform(512, 512, 8, 0.1, 100.0, rng)
+    big.sigma_s = 0.9 * big.sigma_t
+    out = {}
+    for name, pr in (("c2_64x64", c2), ("affine_512x512", big)):
+        pr.nq = 4
+        sw = vef.Sweep([pr], precision="fp64")
+        io = sw.buffers(n_iter=1, store_psi=False)
+        sw.run(io, n_iter=1)
+        mio = sw.moment_buffers(io)
+        sw.moments(mio)
+        inv = sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"])
+        b.record()
+        torch.cuda.synchronize()
+        sw.check()
+        ms = a.elapsed_time(b) / reps
+        F, B = hrt_flops_bytes(pr.p, pr.nq)
+        tf = F * pr.n_elem / (ms * 1e-3) / 1e12
+        gbs = B * pr.n_elem / (ms * 1e-3) / 1e9
+        out[name] = {"elements": pr.n_elem, "n": inv.shape[1], "ms_per_launch": ms,
+                     "elements_per_s": pr.n_elem / (ms * 1e-3),
+                     "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / FP64_PEAK_TFLOPS, "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                                  "algorithmic_flops_per_element": F, "algorithmic_bytes_per_element": B}}
+        del inv
+        sw.close()
+        del io, mio
+    return out
+
+
 def c4_batched(reps=3):
     """The 64-problem batch: plain FP64 level-synchronous sweeps one problem at
     a time, against all 64 in one FP32-local handle whose run is captured in a
@@ -291,6 +347,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-problem batched FP32 vs one-by-one FP64 block")
     ap.add_argument("--no-fixup", action="store_true", help="skip the negative-flux fixup leg")
     ap.add_argument("--no-lagged", action="store_true", help="skip the re-entrant-mesh lagged-sweep leg")
+    ap.add_argument("--no-hrt", action="store_true", help="skip the HRT local block inverse leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (three times), the reference kernel "
                          "for scaling HBM byte counters")
@@ -365,6 +422,8 @@ def main():
         result["fixup_fp64"] = fixup_leg(probs, n_iter, args.steps, ms_step)
     if not args.no_lagged:
         result["lagged_reentrant"] = lagged_leg(args.steps)
+    if not args.no_hrt:
+        result["hrt_local_inverse"] = hrt_leg()
     if not args.no_c4:
         result["c4_batched_fp32_vs_plain_fp64"] = c4_batched()
     if args.copy_calibration:

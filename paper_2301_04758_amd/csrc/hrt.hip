@@ -19,8 +19,8 @@
 // unknowns (A, symmetric positive definite for sigma_t > 0) are eliminated
 // first, then the Schur complement S = Ma - D A^{-1} G -- the block
 // elimination behind the formulas for W, X, Y, Z, which assume A and S
-// non-singular and allow a singular Ma.  The pivot row is broadcast with
-// readlane (fully unrolled, so every index is a compile-time constant).
+// non-singular and allow a singular Ma.  The pivot row goes through LDS
+// (fully unrolled, so every index is a compile-time constant).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -32,13 +32,6 @@ namespace vefk {
 namespace {
 
 constexpr int kHrtWaves = 4;  // elements (waves) per work-group
-
-__device__ __forceinline__ double readlane_d(double x, int k) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 template <int P, int NQ>
 struct Hrt {
@@ -90,6 +83,9 @@ k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, co
   constexpr int NX = H::NX, NV = H::NV, NPHI = H::NPHI, NT = H::NT, N = H::N, Q = H::Q;
   __shared__ double sT[kHrtWaves][Q][4];   // F^T E F^{-T} at volume points
   __shared__ double sF[kHrtWaves][NQ][4];  // E at the points of one boundary face, and 1 / E_b
+  __shared__ __align__(16) double sRow[kHrtWaves][N + 1];  // pivot row of the elimination
+  constexpr int kTile = (N * N * kHrtWaves * 8 <= 40 * 1024) ? N * N : 1;
+  __shared__ __align__(16) double sTile[kHrtWaves][kTile];  // output block of one element
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e = blockIdx.x * kHrtWaves + w;
   if (e >= ne) return;  // whole waves only; the kernel has no work-group barrier
@@ -193,25 +189,45 @@ k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, co
     __builtin_amdgcn_wave_barrier();
   }
 
-  // in-place Gauss-Jordan inversion, natural order
+  // in-place Gauss-Jordan inversion, natural order.  Step k: the pivot lane
+  // writes its row to LDS; every lane reads it back (one address for the
+  // whole wave: a broadcast) and updates its own row without branches:
+  //   a_j <- m a_j - g row_j,  m = 0, g = -1 / a_kk on the pivot lane (its
+  //   row is normalised), m = 1, g = a_k / a_kk elsewhere (entry k
+  //   eliminated); column k becomes 1 / a_kk resp. -a_k / a_kk.
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const double pinv = 1.0 / readlane_d(a[k], k);
-    const bool me = lane == k;
-    const double fk = a[k] * pinv;
+    if (lane == k) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      if (j == k) continue;
-      const double rk = readlane_d(a[j], k);
-      a[j] = me ? rk * pinv : a[j] - fk * rk;
+      for (int j = 0; j < N; ++j) sRow[w][j] = a[j];
     }
-    a[k] = me ? pinv : -fk;
+    __builtin_amdgcn_wave_barrier();
+    const bool me = lane == k;
+    const double pinv = 1.0 / sRow[w][k];
+    const double m = me ? 0.0 : 1.0;
+    const double gk = me ? -pinv : a[k] * pinv;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j != k) a[j] = fma(-gk, sRow[w][j], a[j] * m);
+    a[k] = me ? pinv : -gk;
+    __builtin_amdgcn_wave_barrier();
   }
 
-  if (r < N) {
-    double *o = out + ((size_t)e * N + r) * N;
+  double *o = out + (size_t)e * N * N;
+  if constexpr (N * N * kHrtWaves * 8 <= 40 * 1024) {
+    // through LDS, so that the element's N x N block is written contiguously
+    // (each store instruction covers 64 consecutive doubles)
+    double *tile = sTile[w];
+    if (r < N) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) o[j] = a[j];
+      for (int j = 0; j < N; ++j) tile[r * N + j] = a[j];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = lane; i < N * N; i += 64) o[i] = tile[i];
+  } else if (r < N) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) o[r * N + j] = a[j];
   }
 }
 
