@@ -1,0 +1,144 @@
+"""Pins of the oracle's hybridized-RT VEF global solve and outer iteration
+(oracle/vef_outer_oracle.py):
+
+  * exactness: with a constant Eddington tensor E0 (isotropic or not) and
+    constant sigma_t, phi = c0 + c . x and J = -E0 c / sigma_t solve the
+    VEF equations with Q1 = 0, Q0 = sigma_a phi, and the Miften-Larsen
+    boundary condition holds when J_in = (J . n - E_b phi) / 2; the discrete
+    solution reproduces them (and lambda = phi on interior faces) on sheared
+    meshes, which pins C1, C2, the boundary terms and the global assembly;
+  * the global solve equals the element-local elimination through the
+    block inverse (the paper's reduced system for lambda), computed here
+    with numpy from the oracle's blocks;
+  * thick diffusion limit: the outer iteration converges in a handful of
+    iterations where plain source iteration would need thousands.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hrt_oracle as H
+from oracle import oracle as O
+from oracle import vef_outer_oracle as V
+from paper_2301_04758_amd import problems as P
+
+
+def _sheared(n, p, st=2.0, sa=0.3, nq=None):
+    cp, ec = P.quad_mesh(n, n, 1)
+    cp = cp @ np.array([[1.3, 0.3], [0.15, 1.0]]).T + np.array([0.5, 0.25])
+    om, wt = P.level_symmetric_2d(4)
+    ne = ec.shape[0]
+    pr = P.Problem("sheared", p, 1, cp, ec, om, wt, np.full(ne, st), np.full(ne, st - sa), nx=n, ny=n,
+                   nq=nq or p + 2)
+    return pr
+
+
+def _linear_case(pr, E0, c0=0.8, c=(0.25, -0.4)):
+    nq = pr.nq
+    c = np.asarray(c)
+    st = pr.sigma_t[0]
+    sa = pr.sigma_t - pr.sigma_s
+    Jex = -E0 @ c / st
+    x0, F = H.affine_frames(pr)
+    gx, gw = O.gauss_rule(nq)
+    XI, ETA = np.meshgrid(gx, gx, indexing="xy")
+    xi, eta = XI.ravel(), ETA.ravel()
+    ne = pr.n_elem
+    xq = x0[:, None, :] + np.einsum("ekl,ql->eqk", F, np.stack([xi, eta], 1))
+    phi_q = c0 + xq @ c
+    E_vol = np.broadcast_to(E0, (ne, nq * nq, 2, 2)).copy()
+    bfs = O.boundary_faces(pr)
+    Eb = np.full((len(bfs), nq), 0.55)
+    Jin = np.zeros((len(bfs), nq))
+    for k, (e, f) in enumerate(bfs):
+        fx, fy = H.face_points(f, gx)
+        x = x0[e] + np.stack([fx, fy], 1) @ F[e].T
+        tang = {0: F[e][:, 0], 1: F[e][:, 1], 2: -F[e][:, 0], 3: -F[e][:, 1]}[f]
+        n = np.array([tang[1], -tang[0]]) / np.hypot(*tang)
+        Jin[k] = (Jex @ n - Eb[k] * (c0 + x @ c)) / 2.0
+    Q0 = sa[:, None] * phi_q
+    Q1 = np.zeros((2, ne, nq * nq))
+    out = V.global_solve(pr, nq, E_vol, lambda e, f: np.broadcast_to(E0, (nq, 2, 2)), Eb, Jin, Q0, Q1)
+    return out, Jex, c0, c, x0, F
+
+
+@pytest.mark.parametrize("E0", [((1 / 3, 0), (0, 1 / 3)), ((0.45, 0.1), (0.1, 0.3))])
+@pytest.mark.parametrize("p", [1, 2])
+def test_global_solve_reproduces_linear_solution(p, E0):
+    E0 = np.array(E0, float)
+    pr = _sheared(3, p)
+    out, Jex, c0, c, x0, F = _linear_case(pr, E0)
+    leg = H.legendre_points(p + 1)
+    LX, LY = np.meshgrid(leg, leg, indexing="xy")
+    nodes = np.stack([LX.ravel(), LY.ravel()], 1)
+    for e in range(pr.n_elem):
+        want_phi = c0 + (x0[e] + nodes @ F[e].T) @ c
+        assert np.allclose(out["phi"][e], want_phi, rtol=1e-11, atol=1e-12)
+        vhat = np.linalg.det(F[e]) * np.linalg.solve(F[e], Jex)
+        nx = (p + 2) * (p + 1)
+        assert np.allclose(out["J"][e], np.concatenate([np.full(nx, vhat[0]), np.full(nx, vhat[1])]),
+                           rtol=1e-11, atol=1e-12)
+    # lambda = phi at the face nodes
+    nbr, interior = V._faces(pr)
+    for k, (e1, f1, e2, f2) in enumerate(interior):
+        fx, fy = H.face_points(f1, leg)
+        x = x0[e1] + np.stack([fx, fy], 1) @ F[e1].T
+        assert np.allclose(out["lam"][k], c0 + x @ c, rtol=1e-11, atol=1e-12)
+
+
+def test_global_solve_equals_local_elimination():
+    """The direct solve and the reduced lambda system through the block
+    inverse (Sec. 7: H lambda = C1 (W g + X f)) give the same phi."""
+    p = 2
+    pr = _sheared(3, p, st=1.5, sa=0.2)
+    pr.sigma_t = pr.sigma_t * np.linspace(0.8, 1.6, pr.n_elem)
+    pr.sigma_s = pr.sigma_t - 0.2
+    pr.q_iso = np.ones((pr.n_elem, 9))
+    nq = pr.nq
+    r = O.sweep(pr, want_psi=False, nq=nq)
+    cl = O.closures(pr, r["mom"], r["bnd"], nq=nq)
+    gx, _ = O.gauss_rule(nq)
+    XI, ETA = np.meshgrid(gx, gx, indexing="xy")
+    E_vol = H.eddington_from_moments(pr, r["mom"], XI.ravel(), ETA.ravel())
+
+    def E_face(e, f):
+        fx, fy = H.face_points(f, gx)
+        return H.eddington_from_moments(pr, r["mom"][:, e:e + 1], fx, fy)[0]
+
+    d = V.global_solve(pr, nq, E_vol, E_face, cl["Eb"], cl["Jin"], cl["Q0"], cl["Q1"], return_system=True)
+    M, b, nloc = d["M"], d["b"], d["nloc"]
+    ne = pr.n_elem
+    nl = M.shape[0] - ne * nloc
+    inv, _ = H.local_inverse(pr, nq, r["mom"], cl["Eb"])
+    Hred = np.zeros((nl, nl))
+    rhs = np.zeros(nl)
+    for e in range(ne):
+        sl = slice(e * nloc, (e + 1) * nloc)
+        C2 = M[sl, ne * nloc:]          # [[C2], [0]] columns of element e
+        C1 = M[ne * nloc:, sl]          # [C1, 0] rows
+        Hred += C1 @ inv[e] @ C2
+        rhs += C1 @ inv[e] @ b[sl]
+    lam = np.linalg.solve(Hred, rhs)
+    assert np.allclose(lam, d["lam"].ravel(), rtol=1e-10, atol=1e-12 * np.abs(lam).max())
+    for e in range(ne):
+        sl = slice(e * nloc, (e + 1) * nloc)
+        x = inv[e] @ (b[sl] - M[sl, ne * nloc:] @ lam)
+        assert np.allclose(x[nloc - (p + 1) ** 2:], d["phi"][e], rtol=1e-10, atol=1e-12)
+
+
+def test_thick_diffusion_limit_converges_fast():
+    """sigma_t = 1/eps, sigma_a = eps, q = eps on an 8x8 unit square (Sec. 8,
+    thick diffusion limit): the outer iteration settles within a few
+    iterations for eps = 1e-2, where source iteration's spectral radius is
+    1 - eps^2."""
+    eps = 1e-2
+    cp, ec = P.quad_mesh(8, 8, 1)
+    om, wt = P.level_symmetric_2d(4)
+    ne = ec.shape[0]
+    pr = P.Problem("tdl", 1, 1, cp, ec, om, wt, np.full(ne, 1 / eps), np.full(ne, 1 / eps - eps), nx=8, ny=8, nq=3)
+    pr.q_iso = np.full((ne, 4), eps / (4 * math.pi))
+    hist = V.outer_iteration(pr, 3, 10)
+    changes = [np.abs(hist[k + 1] - hist[k]).max() / np.abs(hist[k + 1]).max() for k in range(len(hist) - 1)]
+    assert changes[-1] < 1e-6, changes
+    assert all(np.isfinite(h).all() for h in hist)
