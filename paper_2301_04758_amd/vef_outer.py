@@ -1,0 +1,290 @@
+"""Host outer iteration of the transport / hybridized-RT VEF method (Sec. 2's
+three-stage fixed point, with the hybridized discretisation of Sec. 7).
+
+Each outer iteration:
+  1. one transport sweep on the GPU (vef_sweep_run) whose scattering source
+     is the previous VEF scalar flux, then the closures (vef_moments: E_b,
+     J_in, Q_0, Q_1);
+  2. the element-local HRT blocks and their inverse [[W, X], [Y, Z]] on the
+     GPU (vef_hrt_local_inverse), E = P / phi from the sweep's moments;
+  3. on the host: the interior-face couplings C_1 (Eq. eq:hyb_cts_n_vef) and
+     C_2 (the lambda term of the local first-moment equation, with the
+     average of E n from both sides), the right-hand sides g (Q_1 and the
+     Miften-Larsen inflow term with J_in) and f (Q_0), the reduced system
+     H lambda = sum_K C_1 (W g + X f), H = sum_K C_1 W C_2 (scipy sparse
+     direct solve in place of the paper's AMG), and per element
+     [J; phi] = [[W, X], [Y, Z]] [g - C_2 lambda; f];
+  4. phi (Gauss-Legendre nodal Q_p) evaluated at the transport's
+     Gauss-Lobatto nodes (the same polynomial) becomes the next scattering
+     source.
+Affine meshes only, like vef_hrt_local_inverse.  The lambda space on each
+interior face is Lagrange of degree p through the Gauss-Legendre points in the
+counter-clockwise parameter of the face's lower-numbered element.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import vef
+
+
+def _gauss(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def _lobatto(k):
+    inner = np.polynomial.legendre.Legendre.basis(k).deriv().roots()
+    return np.sort(np.concatenate([[0.0], 0.5 * (np.real(inner) + 1.0), [1.0]]))
+
+
+def _lagrange(z, x):
+    """Values and derivatives [len(x), len(z)] (barycentric form)."""
+    z = np.asarray(z, float)
+    x = np.atleast_1d(np.asarray(x, float))
+    k = len(z)
+    bw = np.array([1.0 / np.prod([z[j] - z[l] for l in range(k) if l != j]) for j in range(k)])
+    val = np.zeros((len(x), k))
+    der = np.zeros((len(x), k))
+    for i, xi in enumerate(x):
+        d = xi - z
+        hit = np.nonzero(d == 0.0)[0]
+        if len(hit):
+            j = hit[0]
+            val[i, j] = 1.0
+            for l in range(k):
+                if l != j:
+                    der[i, l] = (bw[l] / bw[j]) / (z[j] - z[l])
+            der[i, j] = -der[i].sum()
+            continue
+        t = bw / d
+        val[i] = t / t.sum()
+        for j in range(k):
+            der[i, j] = val[i, j] * sum(1.0 / d[l] for l in range(k) if l != j)
+    return val, der
+
+
+class _Ref:
+    """Reference tables of degree p with nq Gauss points per direction."""
+
+    def __init__(self, p, nq):
+        self.p, self.nq = p, nq
+        self.gx, self.gw = _gauss(nq)
+        self.lob1 = _lobatto(p + 1)
+        self.lob = _lobatto(p)
+        self.leg, _ = _gauss(p + 1)
+        self.nx = (p + 2) * (p + 1)
+        self.nv = 2 * self.nx
+        self.nphi = (p + 1) ** 2
+        XI, ETA = np.meshgrid(self.gx, self.gx, indexing="xy")
+        self.vxi, self.veta = XI.ravel(), ETA.ravel()
+        self.W = np.outer(self.gw, self.gw).ravel()
+        self.rt_vol = self.rt(self.vxi, self.veta)
+        self.u_vol = self.tensor(self.leg, self.vxi, self.veta)
+        self.leg_at_lob = self.tensor(self.leg, *self._grid(self.lob))  # [nT, nphi]
+
+    @staticmethod
+    def _grid(z):
+        X, Y = np.meshgrid(z, z, indexing="xy")
+        return X.ravel(), Y.ravel()
+
+    def rt(self, x, y):
+        """Reference RT_p vectors [npt, nv, 2] (xi-component functions first)."""
+        p = self.p
+        Lx, _ = _lagrange(self.lob1, x)
+        Ly, _ = _lagrange(self.lob1, y)
+        Gx, _ = _lagrange(self.leg, x)
+        Gy, _ = _lagrange(self.leg, y)
+        v = np.zeros((len(x), self.nv, 2))
+        i = 0
+        for b in range(p + 1):
+            for a in range(p + 2):
+                v[:, i, 0] = Lx[:, a] * Gy[:, b]
+                i += 1
+        for b in range(p + 2):
+            for a in range(p + 1):
+                v[:, i, 1] = Gx[:, a] * Ly[:, b]
+                i += 1
+        return v
+
+    @staticmethod
+    def tensor(z, x, y):
+        Lx, _ = _lagrange(z, x)
+        Ly, _ = _lagrange(z, y)
+        return (Ly[:, :, None] * Lx[:, None, :]).reshape(len(x), -1)
+
+    @staticmethod
+    def face_xy(f, s):
+        s = np.asarray(s, float)
+        return {0: (s, 0 * s), 1: (1 + 0 * s, s), 2: (1 - s, 1 + 0 * s), 3: (0 * s, 1 - s)}[f]
+
+
+def _eddington(Tb, mom_e):
+    """E [npt, 2, 2] from the transport basis values Tb [npt, nT] and one
+    element's moments [6, nT]; I/3 where phi <= 0."""
+    ph = Tb @ mom_e[0]
+    pxx, pxy, pyy = Tb @ mom_e[3], Tb @ mom_e[4], Tb @ mom_e[5]
+    E = np.zeros((len(ph), 2, 2))
+    pos = ph > 0
+    s = np.where(pos, ph, 1.0)
+    E[:, 0, 0] = np.where(pos, pxx / s, 1 / 3)
+    E[:, 1, 1] = np.where(pos, pyy / s, 1 / 3)
+    E[:, 0, 1] = E[:, 1, 0] = np.where(pos, pxy / s, 0.0)
+    return E
+
+
+class VefOuter:
+    """Transport + HRT VEF outer iteration for one affine problem."""
+
+    def __init__(self, problem, nq=None, precision="fp64"):
+        import scipy.sparse  # noqa: F401  (fail early if missing)
+        p = problem.p
+        if nq is None:
+            nq = p + 2
+        problem.nq = nq
+        self.pr = problem
+        self.ref = _Ref(p, nq)
+        self.sw = vef.Sweep([problem], precision=precision)
+        if not self.sw.info[0]["affine"]:
+            self.sw.close()
+            raise ValueError("the HRT outer iteration needs an affine mesh")
+        m = problem.m
+        ec = np.asarray(problem.elem_cp)
+        cp = np.asarray(problem.cp_xy, float)
+        x00, x10, x01 = cp[ec[:, 0]], cp[ec[:, m]], cp[ec[:, m * (m + 1)]]
+        self.F = np.stack([x10 - x00, x01 - x00], axis=-1)
+        self.J = np.linalg.det(self.F)
+        corner = {0: (0, m), 1: (m, (m + 1) ** 2 - 1), 2: ((m + 1) ** 2 - 1, m * (m + 1)), 3: (m * (m + 1), 0)}
+        first = {}
+        self.nbr = -np.ones((problem.n_elem, 4), dtype=np.int64)
+        self.nbr_face = -np.ones((problem.n_elem, 4), dtype=np.int64)
+        for e in range(problem.n_elem):
+            for f in range(4):
+                key = frozenset((int(ec[e, corner[f][0]]), int(ec[e, corner[f][1]])))
+                if key in first:
+                    e2, f2 = first.pop(key)
+                    self.nbr[e, f], self.nbr_face[e, f] = e2, f2
+                    self.nbr[e2, f2], self.nbr_face[e2, f2] = e, f
+                else:
+                    first[key] = (e, f)
+        # interior faces, numbered by (lower element, its face)
+        self.face_id = -np.ones((problem.n_elem, 4), dtype=np.int64)
+        nf = 0
+        for e in range(problem.n_elem):
+            for f in range(4):
+                e2 = self.nbr[e, f]
+                if e2 > e:
+                    self.face_id[e, f] = nf
+                    self.face_id[e2, self.nbr_face[e, f]] = nf
+                    nf += 1
+        self.n_faces = nf
+        self.bf = vef.vef_boundary_faces(self.sw.h, 0)
+        self.bf_index = {(int(e), int(f)): k for k, (e, f) in enumerate(self.bf)}
+        self.history = []
+
+    def close(self):
+        self.sw.close()
+
+    # ------------------------------------------------------------ geometry
+    def _face(self, e, f):
+        """(v [nq, nv, 2] physical RT values at the face points, n, |N|)."""
+        F, J = self.F[e], self.J[e]
+        fx, fy = _Ref.face_xy(f, self.ref.gx)
+        v = np.einsum("kl,qil->qik", F, self.ref.rt(fx, fy)) / J
+        tang = {0: F[:, 0], 1: F[:, 1], 2: -F[:, 0], 3: -F[:, 1]}[f]
+        N = np.array([tang[1], -tang[0]])
+        length = np.hypot(*N)
+        return v, N / length, length
+
+    def _tb(self, f, s):
+        return _Ref.tensor(self.ref.lob, *_Ref.face_xy(f, s))
+
+    # ------------------------------------------------------------- one step
+    def step(self, phi_lob=None):
+        """One outer iteration from the transport scattering flux phi_lob
+        [n_elem, (p+1)^2] (Gauss-Lobatto nodal; None = 0).  Returns the VEF
+        scalar flux at the Gauss-Lobatto nodes and at the Gauss-Legendre
+        nodes, and the current."""
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spl
+        import torch
+        pr, ref = self.pr, self.ref
+        p, nq, nv, nphi = pr.p, ref.nq, ref.nv, ref.nphi
+        io = self.sw.buffers(n_iter=1, store_psi=False, phi_in=phi_lob)
+        self.sw.run(io, n_iter=1)
+        mio = self.sw.moment_buffers(io)
+        self.sw.moments(mio)
+        inv = self.sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"])
+        torch.cuda.synchronize()
+        self.sw.check()
+        inv = inv.cpu().numpy()
+        mom = io[0]["mom"].cpu().numpy()
+        Eb = mio[0]["Eb"].cpu().numpy()
+        Jin = mio[0]["Jin"].cpu().numpy()
+        Q0 = mio[0]["Q0"].cpu().numpy()
+        Q1 = mio[0]["Q1"].cpu().numpy()
+        ne = pr.n_elem
+        P1 = p + 1
+        # right-hand sides g, f and the face couplings C1_K, C2_K (local slots f*(p+1)+t)
+        vvol = np.einsum("ekl,qil->eqik", self.F, ref.rt_vol) / self.J[:, None, None, None]
+        wJ = ref.W[None, :] * self.J[:, None]
+        g = np.einsum("eq,eqik,keq->ei", wJ, vvol, Q1)
+        fr = np.einsum("eq,qi,eq->ei", wJ, ref.u_vol, Q0)
+        C1 = np.zeros((ne, 4 * P1, nv))
+        C2 = np.zeros((ne, nv, 4 * P1))
+        for e in range(ne):
+            for f in range(4):
+                v, n, length = self._face(e, f)
+                w = ref.gw * length
+                e2 = self.nbr[e, f]
+                if e2 < 0:
+                    k = self.bf_index[(e, f)]
+                    E = _eddington(self._tb(f, ref.gx), mom[:, e])
+                    eb = np.where(Eb[k] > 0, Eb[k], 0.5)
+                    vEn = np.einsum("qik,qkl,l->qi", v, E, n)
+                    g[e] += np.einsum("q,qi,q->i", 2.0 * w / eb, vEn, Jin[k])
+                    continue
+                f2 = self.nbr_face[e, f]
+                E = _eddington(self._tb(f, ref.gx), mom[:, e])
+                E2 = _eddington(self._tb(f2, 1.0 - ref.gx), mom[:, e2])
+                En = np.einsum("qkl,l->qk", 0.5 * (E + E2), n)
+                s = ref.gx if e < e2 else 1.0 - ref.gx
+                lam, _ = _lagrange(ref.leg, s)
+                C2[e][:, f * P1:(f + 1) * P1] = np.einsum("q,qik,qk,qt->it", w, v, En, lam)
+                C1[e][f * P1:(f + 1) * P1, :] = np.einsum("q,qt,qik,k->ti", w, lam, v, n)
+        W_, X_ = inv[:, :nv, :nv], inv[:, :nv, nv:]
+        Hloc = np.einsum("eti,eij,ejs->ets", C1, W_, C2)
+        rloc = np.einsum("eti,ei->et", C1, np.einsum("eij,ej->ei", W_, g) + np.einsum("eij,ej->ei", X_, fr))
+        gidx = (self.face_id[:, :, None] * P1 + np.arange(P1)[None, None, :]).reshape(ne, 4 * P1)
+        ok = gidx >= 0
+        rows = np.repeat(gidx[:, :, None], 4 * P1, axis=2)
+        cols = np.repeat(gidx[:, None, :], 4 * P1, axis=1)
+        mask = ok[:, :, None] & ok[:, None, :]
+        nl = self.n_faces * P1
+        H = sp.csr_matrix((Hloc[mask], (rows[mask], cols[mask])), shape=(nl, nl))
+        rhs = np.zeros(nl)
+        np.add.at(rhs, gidx[ok], rloc[ok])
+        lam_g = spl.spsolve(H.tocsc(), rhs) if nl else np.zeros(0)
+        lam_loc = np.where(ok, lam_g[np.where(ok, gidx, 0)] if nl else 0.0, 0.0)
+        top = g - np.einsum("eit,et->ei", C2, lam_loc)
+        sol = np.einsum("eij,ej->ei", inv, np.concatenate([top, fr], axis=1))
+        Jc, phi_leg = sol[:, :nv], sol[:, nv:]
+        phi_lob = phi_leg @ ref.leg_at_lob.T
+        return phi_lob, phi_leg, Jc
+
+    def solve(self, max_outer=50, tol=1e-8, phi0=None):
+        """Outer iterations until max|phi_new - phi_old| <= tol max|phi_new|
+        (VEF scalar flux at the Gauss-Legendre nodes).  Returns dict(phi_leg,
+        phi_lob, J, iterations, history)."""
+        phi_lob = phi0
+        prev = None
+        self.history = []
+        for it in range(1, max_outer + 1):
+            phi_lob, phi_leg, Jc = self.step(phi_lob)
+            if prev is not None:
+                r = float(np.abs(phi_leg - prev).max() / max(np.abs(phi_leg).max(), 1e-300))
+                self.history.append(r)
+                if r <= tol:
+                    return dict(phi_leg=phi_leg, phi_lob=phi_lob, J=Jc, iterations=it, history=self.history)
+            prev = phi_leg
+        return dict(phi_leg=phi_leg, phi_lob=phi_lob, J=Jc, iterations=max_outer, history=self.history)

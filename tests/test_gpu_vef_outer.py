@@ -1,0 +1,98 @@
+"""GPU parity of the transport / hybridized-RT VEF outer iteration
+(paper_2301_04758_amd.vef_outer: GPU sweeps, closures and element-local
+block inverses, host reduced lambda system) with the oracle's iteration
+(oracle sweep and closures, direct solve of the full hybridized system):
+the VEF scalar flux after every outer iteration.  Bound: relative max norm
+max(1e-12, 64 eps kappa), kappa the condition number of the oracle's global
+hybridized matrix of the first iteration (the two routes solve it
+differently)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import vef_outer_oracle as V
+from oracle import hrt_oracle as H
+from oracle import oracle as O
+from paper_2301_04758_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _tdl(n, p, eps):
+    cp, ec = P.quad_mesh(n, n, 1)
+    om, wt = P.level_symmetric_2d(4)
+    ne = ec.shape[0]
+    pr = P.Problem("tdl", p, 1, cp, ec, om, wt, np.full(ne, 1 / eps), np.full(ne, 1 / eps - eps), nx=n, ny=n,
+                   nq=p + 2)
+    pr.q_iso = np.full((ne, (p + 1) ** 2), eps / (4 * math.pi))
+    return pr
+
+
+def _sheared(n, p, seed=3):
+    cp, ec = P.quad_mesh(n, n, 1)
+    cp = cp @ np.array([[1.4, 0.3], [0.1, 1.0]]).T
+    om, wt = P.level_symmetric_2d(6)
+    ne = ec.shape[0]
+    rng = np.random.default_rng(seed)
+    st = rng.uniform(1.0, 20.0, ne)
+    pr = P.Problem("sheared", p, 1, cp, ec, om, wt, st, 0.95 * st, nx=n, ny=n, nq=p + 2)
+    pr.q_iso = np.ones((ne, (p + 1) ** 2))
+    return pr
+
+
+def _kappa(pr):
+    nq = pr.nq
+    r = O.sweep(pr, want_psi=False, nq=nq)
+    cl = O.closures(pr, r["mom"], r["bnd"], nq=nq)
+    gx, _ = O.gauss_rule(nq)
+    XI, ETA = np.meshgrid(gx, gx, indexing="xy")
+    E_vol = H.eddington_from_moments(pr, r["mom"], XI.ravel(), ETA.ravel())
+
+    def E_face(e, f):
+        fx, fy = H.face_points(f, gx)
+        return H.eddington_from_moments(pr, r["mom"][:, e:e + 1], fx, fy)[0]
+
+    d = V.global_solve(pr, nq, E_vol, E_face, cl["Eb"], cl["Jin"], cl["Q0"], cl["Q1"], return_system=True)
+    return float(np.linalg.cond(d["M"]))
+
+
+@pytest.mark.parametrize("case", ["tdl_p1", "tdl_p2", "sheared_p2"])
+def test_outer_iteration_parity(torch, case):
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    pr = {"tdl_p1": lambda: _tdl(8, 1, 1e-2), "tdl_p2": lambda: _tdl(6, 2, 1e-3),
+          "sheared_p2": lambda: _sheared(6, 2)}[case]()
+    n_outer = 4
+    ref = V.outer_iteration(pr, pr.nq, n_outer)
+    tol = max(1e-12, 64 * np.finfo(float).eps * _kappa(pr))
+    drv = VefOuter(pr)
+    try:
+        phi_lob = None
+        for k in range(n_outer):
+            phi_lob, phi_leg, _ = drv.step(phi_lob)
+            err = np.abs(phi_leg - ref[k]).max() / np.abs(ref[k]).max()
+            print("%s iteration %d rel err %.2e (bound %.1e)" % (case, k + 1, err, tol), flush=True)
+            assert err <= tol, (k, err, tol)
+    finally:
+        drv.close()
+
+
+def test_thick_limit_converges_in_few_outer_iterations(torch):
+    """The GPU-driven iteration on the 8x8 thick-diffusion-limit problem
+    (eps = 1e-3) reaches a relative change of 1e-8 within 8 iterations."""
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    drv = VefOuter(_tdl(8, 1, 1e-3))
+    try:
+        out = drv.solve(max_outer=12, tol=1e-8)
+    finally:
+        drv.close()
+    print("iterations", out["iterations"], "history", out["history"], flush=True)
+    assert out["iterations"] <= 8 and out["history"][-1] <= 1e-8
