@@ -260,6 +260,37 @@ def hrt_leg(reps=5):
     return out
 
 
+def outer_leg():
+    """Transport / hybridized-RT VEF outer iteration in the thick diffusion
+    limit (Sec. 8): 64x64 unit square, p = 2, S8, sigma_t = 1/eps, sigma_a =
+    eps, q = eps, eps = 1e-3, vacuum; outer iterations to a relative change of
+    1e-8, with the time split between the device part and the host part."""
+    import numpy as np
+    from paper_2301_04758_amd import problems as P
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    eps = 1e-3
+    pr = P.make_problem("tdl_64", 64, 64, 2, 1, 8, 1.0 / eps, 1.0 / eps - eps, q=eps / (4 * math.pi))
+    drv = VefOuter(pr)
+    try:
+        drv.step(None)  # warm-up (tables, geometry, allocations)
+        t0 = time.perf_counter()
+        out = drv.solve(max_outer=20, tol=1e-8)
+        total = time.perf_counter() - t0
+        dev, host = [], []
+        phi = None
+        for _ in range(3):
+            phi, _, _ = drv.step(phi)
+            dev.append(drv.last_times["device_s"])
+            host.append(drv.last_times["host_s"])
+    finally:
+        drv.close()
+    return {"workload": "64x64, p=2, S8, sigma_t=1/eps, sigma_a=eps, q=eps, eps=1e-3 (thick diffusion limit)",
+            "outer_iterations": out["iterations"], "history": out["history"],
+            "seconds_total": total, "ms_per_outer_iteration": 1e3 * total / out["iterations"],
+            "device_ms": 1e3 * float(np.median(dev)), "host_ms": 1e3 * float(np.median(host)),
+            "lambda_unknowns": drv.n_faces * (pr.p + 1)}
+
+
 def c4_batched(reps=3):
     """The 64-problem batch: plain FP64 level-synchronous sweeps one problem at
     a time, against all 64 in one FP32-local handle whose run is captured in a
@@ -348,6 +379,7 @@ def main():
     ap.add_argument("--no-fixup", action="store_true", help="skip the negative-flux fixup leg")
     ap.add_argument("--no-lagged", action="store_true", help="skip the re-entrant-mesh lagged-sweep leg")
     ap.add_argument("--no-hrt", action="store_true", help="skip the HRT local block inverse leg")
+    ap.add_argument("--no-outer", action="store_true", help="skip the transport / VEF outer iteration leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (three times), the reference kernel "
                          "for scaling HBM byte counters")
@@ -424,6 +456,8 @@ def main():
         result["lagged_reentrant"] = lagged_leg(args.steps)
     if not args.no_hrt:
         result["hrt_local_inverse"] = hrt_leg()
+    if not args.no_outer:
+        result["vef_outer_thick_limit"] = outer_leg()
     if not args.no_c4:
         result["c4_batched_fp32_vs_plain_fp64"] = c4_batched()
     if args.copy_calibration:

@@ -119,20 +119,6 @@ class _Ref:
         return {0: (s, 0 * s), 1: (1 + 0 * s, s), 2: (1 - s, 1 + 0 * s), 3: (0 * s, 1 - s)}[f]
 
 
-def _eddington(Tb, mom_e):
-    """E [npt, 2, 2] from the transport basis values Tb [npt, nT] and one
-    element's moments [6, nT]; I/3 where phi <= 0."""
-    ph = Tb @ mom_e[0]
-    pxx, pxy, pyy = Tb @ mom_e[3], Tb @ mom_e[4], Tb @ mom_e[5]
-    E = np.zeros((len(ph), 2, 2))
-    pos = ph > 0
-    s = np.where(pos, ph, 1.0)
-    E[:, 0, 0] = np.where(pos, pxx / s, 1 / 3)
-    E[:, 1, 1] = np.where(pos, pyy / s, 1 / 3)
-    E[:, 0, 1] = E[:, 1, 0] = np.where(pos, pxy / s, 0.0)
-    return E
-
-
 class VefOuter:
     """Transport + HRT VEF outer iteration for one affine problem."""
 
@@ -179,22 +165,30 @@ class VefOuter:
                     nf += 1
         self.n_faces = nf
         self.bf = vef.vef_boundary_faces(self.sw.h, 0)
-        self.bf_index = {(int(e), int(f)): k for k, (e, f) in enumerate(self.bf)}
+        self.bf_of = -np.ones((problem.n_elem, 4), dtype=np.int64)
+        for k, (e, f) in enumerate(self.bf):
+            self.bf_of[int(e), int(f)] = k
         self.history = []
 
     def close(self):
         self.sw.close()
 
     # ------------------------------------------------------------ geometry
-    def _face(self, e, f):
-        """(v [nq, nv, 2] physical RT values at the face points, n, |N|)."""
-        F, J = self.F[e], self.J[e]
-        fx, fy = _Ref.face_xy(f, self.ref.gx)
-        v = np.einsum("kl,qil->qik", F, self.ref.rt(fx, fy)) / J
-        tang = {0: F[:, 0], 1: F[:, 1], 2: -F[:, 0], 3: -F[:, 1]}[f]
-        N = np.array([tang[1], -tang[0]])
-        length = np.hypot(*N)
-        return v, N / length, length
+    @staticmethod
+    def _eddington_all(Tb, mom):
+        """E [ne, npt, 2, 2] = P / phi from basis values Tb [npt, nT] and
+        moments [6, ne, nT]; I/3 where phi <= 0."""
+        ph = np.einsum("qj,ej->eq", Tb, mom[0])
+        pxx = np.einsum("qj,ej->eq", Tb, mom[3])
+        pxy = np.einsum("qj,ej->eq", Tb, mom[4])
+        pyy = np.einsum("qj,ej->eq", Tb, mom[5])
+        E = np.zeros(ph.shape + (2, 2))
+        pos = ph > 0
+        safe = np.where(pos, ph, 1.0)
+        E[..., 0, 0] = np.where(pos, pxx / safe, 1 / 3)
+        E[..., 1, 1] = np.where(pos, pyy / safe, 1 / 3)
+        E[..., 0, 1] = E[..., 1, 0] = np.where(pos, pxy / safe, 0.0)
+        return E
 
     def _tb(self, f, s):
         return _Ref.tensor(self.ref.lob, *_Ref.face_xy(f, s))
@@ -210,6 +204,8 @@ class VefOuter:
         import torch
         pr, ref = self.pr, self.ref
         p, nq, nv, nphi = pr.p, ref.nq, ref.nv, ref.nphi
+        import time
+        t0 = time.perf_counter()
         io = self.sw.buffers(n_iter=1, store_psi=False, phi_in=phi_lob)
         self.sw.run(io, n_iter=1)
         mio = self.sw.moment_buffers(io)
@@ -223,6 +219,7 @@ class VefOuter:
         Jin = mio[0]["Jin"].cpu().numpy()
         Q0 = mio[0]["Q0"].cpu().numpy()
         Q1 = mio[0]["Q1"].cpu().numpy()
+        t1 = time.perf_counter()
         ne = pr.n_elem
         P1 = p + 1
         # right-hand sides g, f and the face couplings C1_K, C2_K (local slots f*(p+1)+t)
@@ -232,26 +229,36 @@ class VefOuter:
         fr = np.einsum("eq,qi,eq->ei", wJ, ref.u_vol, Q0)
         C1 = np.zeros((ne, 4 * P1, nv))
         C2 = np.zeros((ne, nv, 4 * P1))
-        for e in range(ne):
-            for f in range(4):
-                v, n, length = self._face(e, f)
-                w = ref.gw * length
-                e2 = self.nbr[e, f]
-                if e2 < 0:
-                    k = self.bf_index[(e, f)]
-                    E = _eddington(self._tb(f, ref.gx), mom[:, e])
-                    eb = np.where(Eb[k] > 0, Eb[k], 0.5)
-                    vEn = np.einsum("qik,qkl,l->qi", v, E, n)
-                    g[e] += np.einsum("q,qi,q->i", 2.0 * w / eb, vEn, Jin[k])
+        lam_fwd, _ = _lagrange(ref.leg, ref.gx)
+        lam_rev, _ = _lagrange(ref.leg, 1.0 - ref.gx)
+        ids = np.arange(ne)
+        for f in range(4):
+            fx, fy = _Ref.face_xy(f, ref.gx)
+            v = np.einsum("ekl,qil->eqik", self.F, ref.rt(fx, fy)) / self.J[:, None, None, None]
+            tang = self.F[:, :, f % 2] * (1.0 if f < 2 else -1.0)
+            N = np.stack([tang[:, 1], -tang[:, 0]], axis=1)
+            length = np.hypot(N[:, 0], N[:, 1])
+            n = N / length[:, None]
+            w = ref.gw[None, :] * length[:, None]
+            E = self._eddington_all(self._tb(f, ref.gx), mom)
+            bnd = self.nbr[:, f] < 0
+            if bnd.any():
+                e = ids[bnd]
+                k = self.bf_of[e, f]
+                eb = np.where(Eb[k] > 0, Eb[k], 0.5)
+                vEn = np.einsum("eqik,eqkl,el->eqi", v[e], E[e], n[e])
+                g[e] += np.einsum("eq,eqi,eq->ei", 2.0 * w[e] / eb, vEn, Jin[k])
+            for f2 in range(4):
+                sel = (~bnd) & (self.nbr_face[:, f] == f2)
+                if not sel.any():
                     continue
-                f2 = self.nbr_face[e, f]
-                E = _eddington(self._tb(f, ref.gx), mom[:, e])
-                E2 = _eddington(self._tb(f2, 1.0 - ref.gx), mom[:, e2])
-                En = np.einsum("qkl,l->qk", 0.5 * (E + E2), n)
-                s = ref.gx if e < e2 else 1.0 - ref.gx
-                lam, _ = _lagrange(ref.leg, s)
-                C2[e][:, f * P1:(f + 1) * P1] = np.einsum("q,qik,qk,qt->it", w, v, En, lam)
-                C1[e][f * P1:(f + 1) * P1, :] = np.einsum("q,qt,qik,k->ti", w, lam, v, n)
+                e = ids[sel]
+                e2 = self.nbr[e, f]
+                E2 = self._eddington_all(self._tb(f2, 1.0 - ref.gx), mom[:, e2])
+                En = np.einsum("eqkl,el->eqk", 0.5 * (E[e] + E2), n[e])
+                lam = np.where((e < e2)[:, None, None], lam_fwd[None], lam_rev[None])
+                C2[e, :, f * P1:(f + 1) * P1] = np.einsum("eq,eqik,eqk,eqt->eit", w[e], v[e], En, lam)
+                C1[e, f * P1:(f + 1) * P1, :] = np.einsum("eq,eqt,eqik,ek->eti", w[e], lam, v[e], n[e])
         W_, X_ = inv[:, :nv, :nv], inv[:, :nv, nv:]
         Hloc = np.einsum("eti,eij,ejs->ets", C1, W_, C2)
         rloc = np.einsum("eti,ei->et", C1, np.einsum("eij,ej->ei", W_, g) + np.einsum("eij,ej->ei", X_, fr))
@@ -270,6 +277,9 @@ class VefOuter:
         sol = np.einsum("eij,ej->ei", inv, np.concatenate([top, fr], axis=1))
         Jc, phi_leg = sol[:, :nv], sol[:, nv:]
         phi_lob = phi_leg @ ref.leg_at_lob.T
+        # wall time of the device part (sweep, closures, block inverses and
+        # their copies to the host) and of the host part
+        self.last_times = dict(device_s=t1 - t0, host_s=time.perf_counter() - t1)
         return phi_lob, phi_leg, Jc
 
     def solve(self, max_outer=50, tol=1e-8, phi0=None):
