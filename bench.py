@@ -410,7 +410,8 @@ def main():
     B = sweep_bytes_per_solve(pr.p, pr.m, pr.n_dir, 8)
     launches = max(g64["launches"], 1)
     avg_launch_s = g64["sweep_ms"] * 1e-3 / launches
-    solves_per_launch = solves_per_step / launches
+    n_timed = sum(1 for it in range(n_iter) if (it + 1) % TIMING_STRIDE == 0 or it == n_iter - 1)
+    solves_per_launch = solves_per_step / n_iter * n_timed / launches
     achieved_tf = F * solves_per_launch / avg_launch_s / 1e12
     kname = kernel_name(g64, pr)
     sweeps_per_launch = solves_per_launch / sum(p.n_elem * p.n_dir for p in probs)
@@ -425,7 +426,7 @@ def main():
                 "binding": "critical path: %d dependent upwind levels per sweep" % g64["n_levels"],
                 "measured_peak": machine["fp64_fma_tflops"],
                 "frac_of_measured_peak": achieved_tf / machine["fp64_fma_tflops"],
-                "launches_per_step": launches,
+                "launches_per_step": launches / n_timed * n_iter,
                 "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
                 "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
     hbm_gbs = B * solves_per_step / (ms_step * 1e-3) / 1e9

@@ -81,6 +81,11 @@ class vef_info(C.Structure):
 
 
 def _load():
+    # The library and torch must share one HIP runtime: torch ships its own,
+    # so it is loaded first and the library's HIP dependency resolves to it
+    # (with the library loaded first, the process holds two runtimes and the
+    # library's finds no device).
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libvefsweep.so is not built (run __graft_entry__.build() or "
                           "python -m paper_2301_04758_amd.build)")

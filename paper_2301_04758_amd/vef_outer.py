@@ -123,7 +123,6 @@ class VefOuter:
     """Transport + HRT VEF outer iteration for one affine problem."""
 
     def __init__(self, problem, nq=None, precision="fp64"):
-        import scipy.sparse  # noqa: F401  (fail early if missing)
         p = problem.p
         if nq is None:
             nq = p + 2
@@ -131,6 +130,7 @@ class VefOuter:
         self.pr = problem
         self.ref = _Ref(p, nq)
         self.sw = vef.Sweep([problem], precision=precision)
+        import scipy.sparse  # noqa: F401  (after the device is set up; fail early if missing)
         if not self.sw.info[0]["affine"]:
             self.sw.close()
             raise ValueError("the HRT outer iteration needs an affine mesh")
@@ -225,8 +225,8 @@ class VefOuter:
         # right-hand sides g, f and the face couplings C1_K, C2_K (local slots f*(p+1)+t)
         vvol = np.einsum("ekl,qil->eqik", self.F, ref.rt_vol) / self.J[:, None, None, None]
         wJ = ref.W[None, :] * self.J[:, None]
-        g = np.einsum("eq,eqik,keq->ei", wJ, vvol, Q1)
-        fr = np.einsum("eq,qi,eq->ei", wJ, ref.u_vol, Q0)
+        g = np.einsum("eq,eqik,keq->ei", wJ, vvol, Q1, optimize=True)
+        fr = np.einsum("eq,qi,eq->ei", wJ, ref.u_vol, Q0, optimize=True)
         C1 = np.zeros((ne, 4 * P1, nv))
         C2 = np.zeros((ne, nv, 4 * P1))
         lam_fwd, _ = _lagrange(ref.leg, ref.gx)
@@ -246,8 +246,8 @@ class VefOuter:
                 e = ids[bnd]
                 k = self.bf_of[e, f]
                 eb = np.where(Eb[k] > 0, Eb[k], 0.5)
-                vEn = np.einsum("eqik,eqkl,el->eqi", v[e], E[e], n[e])
-                g[e] += np.einsum("eq,eqi,eq->ei", 2.0 * w[e] / eb, vEn, Jin[k])
+                vEn = np.einsum("eqik,eqkl,el->eqi", v[e], E[e], n[e], optimize=True)
+                g[e] += np.einsum("eq,eqi,eq->ei", 2.0 * w[e] / eb, vEn, Jin[k], optimize=True)
             for f2 in range(4):
                 sel = (~bnd) & (self.nbr_face[:, f] == f2)
                 if not sel.any():
@@ -257,11 +257,11 @@ class VefOuter:
                 E2 = self._eddington_all(self._tb(f2, 1.0 - ref.gx), mom[:, e2])
                 En = np.einsum("eqkl,el->eqk", 0.5 * (E[e] + E2), n[e])
                 lam = np.where((e < e2)[:, None, None], lam_fwd[None], lam_rev[None])
-                C2[e, :, f * P1:(f + 1) * P1] = np.einsum("eq,eqik,eqk,eqt->eit", w[e], v[e], En, lam)
-                C1[e, f * P1:(f + 1) * P1, :] = np.einsum("eq,eqt,eqik,ek->eti", w[e], lam, v[e], n[e])
+                C2[e, :, f * P1:(f + 1) * P1] = np.einsum("eq,eqik,eqk,eqt->eit", w[e], v[e], En, lam, optimize=True)
+                C1[e, f * P1:(f + 1) * P1, :] = np.einsum("eq,eqt,eqik,ek->eti", w[e], lam, v[e], n[e], optimize=True)
         W_, X_ = inv[:, :nv, :nv], inv[:, :nv, nv:]
-        Hloc = np.einsum("eti,eij,ejs->ets", C1, W_, C2)
-        rloc = np.einsum("eti,ei->et", C1, np.einsum("eij,ej->ei", W_, g) + np.einsum("eij,ej->ei", X_, fr))
+        Hloc = np.matmul(np.matmul(C1, W_), C2)
+        rloc = np.matmul(C1, (np.matmul(W_, g[:, :, None]) + np.matmul(X_, fr[:, :, None])))[:, :, 0]
         gidx = (self.face_id[:, :, None] * P1 + np.arange(P1)[None, None, :]).reshape(ne, 4 * P1)
         ok = gidx >= 0
         rows = np.repeat(gidx[:, :, None], 4 * P1, axis=2)
@@ -274,7 +274,7 @@ class VefOuter:
         lam_g = spl.spsolve(H.tocsc(), rhs) if nl else np.zeros(0)
         lam_loc = np.where(ok, lam_g[np.where(ok, gidx, 0)] if nl else 0.0, 0.0)
         top = g - np.einsum("eit,et->ei", C2, lam_loc)
-        sol = np.einsum("eij,ej->ei", inv, np.concatenate([top, fr], axis=1))
+        sol = np.matmul(inv, np.concatenate([top, fr], axis=1)[:, :, None])[:, :, 0]
         Jc, phi_leg = sol[:, :nv], sol[:, nv:]
         phi_lob = phi_leg @ ref.leg_at_lob.T
         # wall time of the device part (sweep, closures, block inverses and
