@@ -134,6 +134,26 @@ class VefOuter:
         if not self.sw.info[0]["affine"]:
             self.sw.close()
             raise ValueError("the HRT outer iteration needs an affine mesh")
+        self._setup_host(vef.vef_boundary_faces(self.sw.h, 0))
+        self.history = []
+
+    @classmethod
+    def host_only(cls, problem, bf, nq=None):
+        """The host stage alone (host_stage), with no device handle: for
+        driving it from closures and block inverses computed elsewhere."""
+        self = cls.__new__(cls)
+        problem.nq = nq or problem.p + 2
+        self.pr = problem
+        self.ref = _Ref(problem.p, problem.nq)
+        self.sw = None
+        self._setup_host(bf)
+        self.history = []
+        return self
+
+    def _setup_host(self, bf):
+        """Geometry and face numbering of the host stage; bf [n_bf, 2] the
+        boundary faces (element, face) in the order of the closures."""
+        problem = self.pr
         m = problem.m
         ec = np.asarray(problem.elem_cp)
         cp = np.asarray(problem.cp_xy, float)
@@ -164,14 +184,14 @@ class VefOuter:
                     self.face_id[e2, self.nbr_face[e, f]] = nf
                     nf += 1
         self.n_faces = nf
-        self.bf = vef.vef_boundary_faces(self.sw.h, 0)
+        self.bf = np.asarray(bf)
         self.bf_of = -np.ones((problem.n_elem, 4), dtype=np.int64)
         for k, (e, f) in enumerate(self.bf):
             self.bf_of[int(e), int(f)] = k
-        self.history = []
 
     def close(self):
-        self.sw.close()
+        if self.sw is not None:
+            self.sw.close()
 
     # ------------------------------------------------------------ geometry
     @staticmethod
@@ -199,13 +219,19 @@ class VefOuter:
         [n_elem, (p+1)^2] (Gauss-Lobatto nodal; None = 0).  Returns the VEF
         scalar flux at the Gauss-Lobatto nodes and at the Gauss-Legendre
         nodes, and the current."""
-        import scipy.sparse as sp
-        import scipy.sparse.linalg as spl
-        import torch
-        pr, ref = self.pr, self.ref
-        p, nq, nv, nphi = pr.p, ref.nq, ref.nv, ref.nphi
         import time
         t0 = time.perf_counter()
+        d = self._device_stage(phi_lob)
+        t1 = time.perf_counter()
+        out = self.host_stage(**d)
+        # wall time of the device part (sweep, closures, block inverses and
+        # their copies to the host) and of the host part
+        self.last_times = dict(device_s=t1 - t0, host_s=time.perf_counter() - t1)
+        return out
+
+    def _device_stage(self, phi_lob):
+        """Sweep, closures and block inverses on the GPU, copied to the host."""
+        import torch
         io = self.sw.buffers(n_iter=1, store_psi=False, phi_in=phi_lob)
         self.sw.run(io, n_iter=1)
         mio = self.sw.moment_buffers(io)
@@ -219,14 +245,28 @@ class VefOuter:
         Jin = mio[0]["Jin"].cpu().numpy()
         Q0 = mio[0]["Q0"].cpu().numpy()
         Q1 = mio[0]["Q1"].cpu().numpy()
-        t1 = time.perf_counter()
+        return dict(inv=inv, mom=mom, Eb=Eb, Jin=Jin, Q0=Q0, Q1=Q1)
+
+    def host_stage(self, inv, mom, Eb, Jin, Q0, Q1):
+        """Face couplings, right-hand sides, the reduced lambda system and its
+        solve, and the element-by-element recovery of [J; phi].  inv
+        [ne, n, n] the block inverses; mom [6, ne, (p+1)^2] the transport
+        moments; Eb, Jin [n_bf, nq]; Q0 [ne, nq^2]; Q1 [2, ne, nq^2]."""
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spl
+        pr, ref = self.pr, self.ref
+        p, nv = pr.p, ref.nv
         ne = pr.n_elem
         P1 = p + 1
         # right-hand sides g, f and the face couplings C1_K, C2_K (local slots f*(p+1)+t)
-        vvol = np.einsum("ekl,qil->eqik", self.F, ref.rt_vol) / self.J[:, None, None, None]
-        wJ = ref.W[None, :] * self.J[:, None]
-        g = np.einsum("eq,eqik,keq->ei", wJ, vvol, Q1, optimize=True)
-        fr = np.einsum("eq,qi,eq->ei", wJ, ref.u_vol, Q0, optimize=True)
+        # The Piola map v = F v_hat / J gives v . a = v_hat . (F^T a) / J, so
+        # every integral below is a product with the reference RT table
+        # R [(q, l), i] of the physical vectors pulled back by F^T / J.
+        Jinv = 1.0 / self.J
+        Rvol = ref.rt_vol.transpose(0, 2, 1).reshape(-1, nv)
+        FQ = np.einsum("ekl,keq->eql", self.F, Q1) * ref.W[None, :, None]
+        g = FQ.reshape(ne, -1) @ Rvol
+        fr = (ref.W[None, :] * self.J[:, None] * Q0) @ ref.u_vol
         C1 = np.zeros((ne, 4 * P1, nv))
         C2 = np.zeros((ne, nv, 4 * P1))
         lam_fwd, _ = _lagrange(ref.leg, ref.gx)
@@ -234,7 +274,7 @@ class VefOuter:
         ids = np.arange(ne)
         for f in range(4):
             fx, fy = _Ref.face_xy(f, ref.gx)
-            v = np.einsum("ekl,qil->eqik", self.F, ref.rt(fx, fy)) / self.J[:, None, None, None]
+            R = ref.rt(fx, fy).transpose(0, 2, 1).reshape(-1, nv)          # [(q, l), i]
             tang = self.F[:, :, f % 2] * (1.0 if f < 2 else -1.0)
             N = np.stack([tang[:, 1], -tang[:, 0]], axis=1)
             length = np.hypot(N[:, 0], N[:, 1])
@@ -246,8 +286,10 @@ class VefOuter:
                 e = ids[bnd]
                 k = self.bf_of[e, f]
                 eb = np.where(Eb[k] > 0, Eb[k], 0.5)
-                vEn = np.einsum("eqik,eqkl,el->eqi", v[e], E[e], n[e], optimize=True)
-                g[e] += np.einsum("eq,eqi,eq->ei", 2.0 * w[e] / eb, vEn, Jin[k], optimize=True)
+                FtEn = np.einsum("ekl,eqkm,em->eql", self.F[e], E[e], n[e])
+                c = (2.0 * w[e] / eb * Jin[k] * Jinv[e][:, None])[:, :, None]
+                g[e] += (c * FtEn).reshape(len(e), -1) @ R
+            Ftn = np.einsum("ekl,ek->el", self.F, n) * Jinv[:, None]
             for f2 in range(4):
                 sel = (~bnd) & (self.nbr_face[:, f] == f2)
                 if not sel.any():
@@ -255,10 +297,13 @@ class VefOuter:
                 e = ids[sel]
                 e2 = self.nbr[e, f]
                 E2 = self._eddington_all(self._tb(f2, 1.0 - ref.gx), mom[:, e2])
-                En = np.einsum("eqkl,el->eqk", 0.5 * (E[e] + E2), n[e])
-                lam = np.where((e < e2)[:, None, None], lam_fwd[None], lam_rev[None])
-                C2[e, :, f * P1:(f + 1) * P1] = np.einsum("eq,eqik,eqk,eqt->eit", w[e], v[e], En, lam, optimize=True)
-                C1[e, f * P1:(f + 1) * P1, :] = np.einsum("eq,eqt,eqik,ek->eti", w[e], lam, v[e], n[e], optimize=True)
+                FtEn = np.einsum("ekl,eqkm,em->eql", self.F[e], 0.5 * (E[e] + E2), n[e])
+                lam = np.where((e < e2)[:, None, None], lam_fwd[None], lam_rev[None]) \
+                    * (w[e] * Jinv[e][:, None])[:, :, None]                       # [e, q, t]
+                T = (FtEn[:, :, :, None] * lam[:, :, None, :]).reshape(len(e), -1, P1)
+                C2[e, :, f * P1:(f + 1) * P1] = np.matmul(R.T[None], T)
+                U = (lam[:, :, None, :] * Ftn[e][:, None, :, None]).reshape(len(e), -1, P1)
+                C1[e, f * P1:(f + 1) * P1, :] = np.matmul(U.transpose(0, 2, 1), R[None])
         W_, X_ = inv[:, :nv, :nv], inv[:, :nv, nv:]
         Hloc = np.matmul(np.matmul(C1, W_), C2)
         rloc = np.matmul(C1, (np.matmul(W_, g[:, :, None]) + np.matmul(X_, fr[:, :, None])))[:, :, 0]
@@ -271,15 +316,12 @@ class VefOuter:
         H = sp.csr_matrix((Hloc[mask], (rows[mask], cols[mask])), shape=(nl, nl))
         rhs = np.zeros(nl)
         np.add.at(rhs, gidx[ok], rloc[ok])
-        lam_g = spl.spsolve(H.tocsc(), rhs) if nl else np.zeros(0)
+        lam_g = spl.spsolve(H.tocsc(), rhs, permc_spec="MMD_AT_PLUS_A") if nl else np.zeros(0)
         lam_loc = np.where(ok, lam_g[np.where(ok, gidx, 0)] if nl else 0.0, 0.0)
         top = g - np.einsum("eit,et->ei", C2, lam_loc)
         sol = np.matmul(inv, np.concatenate([top, fr], axis=1)[:, :, None])[:, :, 0]
         Jc, phi_leg = sol[:, :nv], sol[:, nv:]
         phi_lob = phi_leg @ ref.leg_at_lob.T
-        # wall time of the device part (sweep, closures, block inverses and
-        # their copies to the host) and of the host part
-        self.last_times = dict(device_s=t1 - t0, host_s=time.perf_counter() - t1)
         return phi_lob, phi_leg, Jc
 
     def solve(self, max_outer=50, tol=1e-8, phi0=None):

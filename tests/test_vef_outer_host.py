@@ -1,0 +1,71 @@
+"""The outer driver's host stage (VefOuter.host_stage: face couplings,
+right-hand sides, reduced lambda system, element recovery) fed with the
+oracle's sweep moments, closures and block inverses reproduces the oracle's
+direct solve of the whole hybridized system (Sec. 7): the same discrete
+problem reached by element-local elimination instead of one dense solve.
+Bound: relative max norm max(1e-12, 64 eps kappa), kappa the condition number
+of the oracle's global matrix.  Runs on the CPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hrt_oracle as H
+from oracle import oracle as O
+from oracle import vef_outer_oracle as V
+from paper_2301_04758_amd import problems as P
+from paper_2301_04758_amd.vef_outer import VefOuter
+
+
+def _problem(case):
+    if case == "tdl_p1":
+        n, p, eps = 5, 1, 1e-2
+        cp, ec = P.quad_mesh(n, n, 1)
+        om, wt = P.level_symmetric_2d(4)
+        ne = ec.shape[0]
+        pr = P.Problem("tdl", p, 1, cp, ec, om, wt, np.full(ne, 1 / eps), np.full(ne, 1 / eps - eps),
+                       nx=n, ny=n, nq=p + 2)
+        pr.q_iso = np.full((ne, (p + 1) ** 2), eps / (4 * math.pi))
+        return pr
+    n, p = (4, 2) if case == "sheared_p2" else (3, 3)
+    cp, ec = P.quad_mesh(n, n, 1)
+    cp = cp @ np.array([[1.4, 0.3], [0.1, 1.0]]).T
+    om, wt = P.level_symmetric_2d(6)
+    ne = ec.shape[0]
+    rng = np.random.default_rng(11)
+    st = rng.uniform(1.0, 20.0, ne)
+    pr = P.Problem("sheared", p, 1, cp, ec, om, wt, st, 0.9 * st, nx=n, ny=n, nq=p + 2)
+    pr.q_iso = rng.uniform(0.5, 1.5, (ne, (p + 1) ** 2))
+    return pr
+
+
+@pytest.mark.parametrize("case", ["tdl_p1", "sheared_p2", "sheared_p3"])
+def test_host_stage_matches_global_solve(case):
+    pr = _problem(case)
+    nq = pr.nq
+    phi_in = None
+    if case != "tdl_p1":
+        phi_in = np.random.default_rng(5).uniform(0.2, 1.0, (pr.n_elem, (pr.p + 1) ** 2))
+    r = O.sweep(pr, phi_in=phi_in, want_psi=False, nq=nq)
+    cl = O.closures(pr, r["mom"], r["bnd"], nq=nq)
+    gx, _ = O.gauss_rule(nq)
+    XI, ETA = np.meshgrid(gx, gx, indexing="xy")
+    E_vol = H.eddington_from_moments(pr, r["mom"], XI.ravel(), ETA.ravel())
+
+    def E_face(e, f):
+        fx, fy = H.face_points(f, gx)
+        return H.eddington_from_moments(pr, r["mom"][:, e:e + 1], fx, fy)[0]
+
+    ref = V.global_solve(pr, nq, E_vol, E_face, cl["Eb"], cl["Jin"], cl["Q0"], cl["Q1"], return_system=True)
+    kappa = float(np.linalg.cond(ref["M"]))
+    tol = max(1e-12, 64 * np.finfo(float).eps * kappa)
+    inv, _ = H.local_inverse(pr, nq, r["mom"], cl["Eb"])
+    drv = VefOuter.host_only(pr, np.array(O.boundary_faces(pr)), nq=nq)
+    phi_lob, phi_leg, J = drv.host_stage(inv=inv, mom=r["mom"], Eb=cl["Eb"], Jin=cl["Jin"], Q0=cl["Q0"],
+                                         Q1=cl["Q1"])
+    err_phi = np.abs(phi_leg - ref["phi"]).max() / np.abs(ref["phi"]).max()
+    err_J = np.abs(J - ref["J"]).max() / np.abs(ref["J"]).max()
+    print(case, "kappa %.2e phi %.2e J %.2e bound %.1e" % (kappa, err_phi, err_J, tol))
+    assert err_phi <= tol and err_J <= tol
+    # the next scattering source is the same polynomial at the Gauss-Lobatto nodes
+    assert np.allclose(phi_lob, ref["phi"] @ V.legendre_to_lobatto(pr.p).T, rtol=0, atol=tol * np.abs(phi_lob).max())
