@@ -15,7 +15,8 @@ n_K from both sides), mu^T C1 J = int_F mu (J . n_K) ds, g = int v . Q1 +
 Bases and readings as in hrt_oracle; lambda is Lagrange through the
 Gauss-Legendre points in the counter-clockwise parameter of the face's lower
 numbered element.  The outer iteration (Sec. 2) alternates an oracle
-transport sweep driven by the VEF scalar flux with this solve.
+transport sweep driven by the VEF scalar flux with this solve, plain or
+Anderson-accelerated (Sec. 8).
 """
 from __future__ import annotations
 
@@ -145,12 +146,48 @@ def outer_step(pr, nq, phi_lob):
     return out["phi"] @ legendre_to_lobatto(pr.p).T, out
 
 
-def outer_iteration(pr, nq, n_outer, phi0=None):
-    """n_outer outer iterations; returns the list of VEF scalar fluxes
-    (Gauss-Legendre nodal) after each."""
-    phi_lob = phi0
-    hist = []
-    for _ in range(n_outer):
-        phi_lob, out = outer_step(pr, nq, phi_lob)
-        hist.append(out["phi"])
-    return hist
+def anderson(G, x0, m, n_iter):
+    """Anderson-accelerated fixed-point iteration for x = G(x) with memory m
+    (the outer solver the paper takes from KINSOL, Sec. 8; algorithm of
+    Walker and Ni, SIAM J. Numer. Anal. 49 (2011)): with residuals
+    f_i = G(x_i) - x_i, the weights alpha minimise |sum_i alpha_i f_i|_2 over
+    the last min(m, k) + 1 residuals subject to sum_i alpha_i = 1, and
+    x_{k+1} = sum_i alpha_i G(x_i).  m = 0 is the plain iteration
+    x_{k+1} = G(x_k).  Returns the iterates [x_1, ..., x_n_iter] and the
+    evaluations [G(x_0), ..., G(x_{n_iter-1})]."""
+    xs = [np.asarray(x0, dtype=float)]
+    gs, fs = [], []
+    for k in range(n_iter):
+        gs.append(np.asarray(G(xs[k]), dtype=float))
+        fs.append(gs[k] - xs[k])
+        mk = min(m, k)
+        if mk == 0:
+            xs.append(gs[k])
+            continue
+        Fm = np.stack(fs[k - mk:k + 1], axis=1)            # [n, mk + 1]
+        # equality-constrained least squares through its KKT system
+        K = np.zeros((mk + 2, mk + 2))
+        K[:mk + 1, :mk + 1] = 2.0 * Fm.T @ Fm
+        K[:mk + 1, mk + 1] = 1.0
+        K[mk + 1, :mk + 1] = 1.0
+        rhs = np.zeros(mk + 2)
+        rhs[mk + 1] = 1.0
+        alpha = np.linalg.solve(K, rhs)[:mk + 1]
+        xs.append(sum(alpha[i] * gs[k - mk + i] for i in range(mk + 1)))
+    return xs[1:], gs
+
+
+def outer_iteration(pr, nq, n_outer, phi0=None, m_anderson=0):
+    """n_outer outer iterations on the VEF scalar flux (Gauss-Legendre nodal,
+    phi0 None = 0), Anderson-accelerated with memory m_anderson (0 = the
+    plain fixed point of Sec. 2); returns the list of iterates."""
+    L = legendre_to_lobatto(pr.p)
+    shape = (pr.n_elem, (pr.p + 1) ** 2)
+
+    def G(x):
+        _, out = outer_step(pr, nq, x.reshape(shape) @ L.T)
+        return out["phi"].ravel()
+
+    x0 = np.zeros(shape) if phi0 is None else np.asarray(phi0, dtype=float)
+    xs, _ = anderson(G, x0.ravel(), m_anderson, n_outer)
+    return [x.reshape(shape) for x in xs]

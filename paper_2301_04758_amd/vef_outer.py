@@ -324,19 +324,41 @@ class VefOuter:
         phi_lob = phi_leg @ ref.leg_at_lob.T
         return phi_lob, phi_leg, Jc
 
-    def solve(self, max_outer=50, tol=1e-8, phi0=None):
-        """Outer iterations until max|phi_new - phi_old| <= tol max|phi_new|
-        (VEF scalar flux at the Gauss-Legendre nodes).  Returns dict(phi_leg,
-        phi_lob, J, iterations, history)."""
-        phi_lob = phi0
-        prev = None
+    def solve(self, max_outer=50, tol=1e-8, phi0=None, anderson=0):
+        """Outer iterations on the VEF scalar flux x (Gauss-Legendre nodal;
+        phi0 None = 0) until max|x_new - x_old| <= tol max|x_new|.  anderson
+        > 0 accelerates the fixed point x = G(x) (G: sweep, closures, VEF
+        solve) with that many difference vectors, as the paper's outer solver
+        does (Sec. 8 uses two): x_new = G(x) - dG gamma, gamma the least-squares
+        fit of the residual f = G(x) - x by the last differences dF of
+        residuals (dG the differences of G values).  anderson = 0 is the plain
+        fixed point of Sec. 2.  Returns dict(phi_leg, phi_lob, J (of the last
+        evaluation of G), iterations, history)."""
+        ref = self.ref
+        shape = (self.pr.n_elem, ref.nphi)
+        x = np.zeros(shape) if phi0 is None else np.asarray(phi0, dtype=float).reshape(shape)
+        dF, dG = [], []
+        f_prev = g_prev = None
         self.history = []
         for it in range(1, max_outer + 1):
-            phi_lob, phi_leg, Jc = self.step(phi_lob)
-            if prev is not None:
-                r = float(np.abs(phi_leg - prev).max() / max(np.abs(phi_leg).max(), 1e-300))
+            _, g, Jc = self.step(None if (it == 1 and phi0 is None) else x @ ref.leg_at_lob.T)
+            f = g - x
+            x_new = g
+            if anderson > 0 and f_prev is not None:
+                dF.append((f - f_prev).ravel())
+                dG.append((g - g_prev).ravel())
+                if len(dF) > anderson:
+                    dF.pop(0)
+                    dG.pop(0)
+                gamma = np.linalg.lstsq(np.stack(dF, axis=1), f.ravel(), rcond=None)[0]
+                x_new = g - (np.stack(dG, axis=1) @ gamma).reshape(shape)
+            f_prev, g_prev = f, g
+            done = False
+            if it > 1:
+                r = float(np.abs(x_new - x).max() / max(np.abs(x_new).max(), 1e-300))
                 self.history.append(r)
-                if r <= tol:
-                    return dict(phi_leg=phi_leg, phi_lob=phi_lob, J=Jc, iterations=it, history=self.history)
-            prev = phi_leg
-        return dict(phi_leg=phi_leg, phi_lob=phi_lob, J=Jc, iterations=max_outer, history=self.history)
+                done = r <= tol
+            x = x_new
+            if done:
+                break
+        return dict(phi_leg=x, phi_lob=x @ ref.leg_at_lob.T, J=Jc, iterations=it, history=self.history)

@@ -96,3 +96,21 @@ def test_thick_limit_converges_in_few_outer_iterations(torch):
         drv.close()
     print("iterations", out["iterations"], "history", out["history"], flush=True)
     assert out["iterations"] <= 8 and out["history"][-1] <= 1e-8
+
+
+def test_anderson_outer_iteration_parity(torch):
+    """Two Anderson vectors (the paper's setting): the GPU-driven iterates
+    against the oracle's Anderson iteration after 5 outer iterations."""
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    pr = _tdl(8, 1, 1e-2)
+    n_outer = 5
+    ref = V.outer_iteration(pr, pr.nq, n_outer, m_anderson=2)
+    tol = max(1e-12, 64 * np.finfo(float).eps * _kappa(pr))
+    drv = VefOuter(pr)
+    try:
+        out = drv.solve(max_outer=n_outer, tol=0.0, anderson=2)
+    finally:
+        drv.close()
+    err = np.abs(out["phi_leg"] - ref[-1]).max() / np.abs(ref[-1]).max()
+    print("anderson iteration %d rel err %.2e (bound %.1e)" % (n_outer, err, tol), flush=True)
+    assert out["iterations"] == n_outer and err <= tol

@@ -69,3 +69,36 @@ def test_host_stage_matches_global_solve(case):
     assert err_phi <= tol and err_J <= tol
     # the next scattering source is the same polynomial at the Gauss-Lobatto nodes
     assert np.allclose(phi_lob, ref["phi"] @ V.legendre_to_lobatto(pr.p).T, rtol=0, atol=tol * np.abs(phi_lob).max())
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", ["linear", "nonlinear"])
+def test_anderson_loop_matches_oracle(m, kind):
+    """VefOuter.solve's Anderson loop (least squares on residual differences)
+    against the oracle's constrained form, with the outer step replaced by a
+    fixed-point map of the flux: the same iterates."""
+    pr = _problem("tdl_p1")
+    drv = VefOuter.host_only(pr, np.array(O.boundary_faces(pr)))
+    shape = (pr.n_elem, (pr.p + 1) ** 2)
+    n = shape[0] * shape[1]
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((n, n))
+    M *= 0.9 / max(abs(np.linalg.eigvals(M)))
+    b = rng.standard_normal(n)
+    if kind == "linear":
+        G = lambda x: M @ x + b  # noqa: E731
+    else:
+        G = lambda x: 0.5 * np.tanh(M @ x) + b  # noqa: E731
+    L = drv.ref.leg_at_lob
+
+    def fake_step(phi_lob):
+        x = np.zeros(n) if phi_lob is None else np.linalg.solve(L, phi_lob.T).T.ravel()
+        return None, G(x).reshape(shape), None
+
+    drv.step = fake_step
+    k = 8
+    out = drv.solve(max_outer=k, tol=0.0, anderson=m)
+    xs, _ = V.anderson(G, np.zeros(n), m, k)
+    assert out["iterations"] == k and len(out["history"]) == k - 1
+    err = np.abs(out["phi_leg"].ravel() - xs[-1]).max() / np.abs(xs[-1]).max()
+    assert err <= 1e-11, err

@@ -142,3 +142,71 @@ def test_thick_diffusion_limit_converges_fast():
     changes = [np.abs(hist[k + 1] - hist[k]).max() / np.abs(hist[k + 1]).max() for k in range(len(hist) - 1)]
     assert changes[-1] < 1e-6, changes
     assert all(np.isfinite(h).all() for h in hist)
+
+
+# --------------------------------------------------------------- Anderson
+def test_anderson_scalar_linear_map_is_exact_after_one_secant_step():
+    """x = a x + b with memory 1: the constrained weights make the affine
+    residual vanish, so the second iterate is the fixed point b / (1 - a)."""
+    a, b, x0 = 0.9, 0.7, np.array([0.3])
+    xs, _ = V.anderson(lambda x: a * x + b, x0, 1, 3)
+    assert abs(xs[0][0] - (a * 0.3 + b)) < 1e-15
+    assert abs(xs[1][0] - b / (1 - a)) < 1e-13
+
+
+def _gmres_iterate(A, rhs, x0, k):
+    """The GMRES iterate by its definition: x0 + z, z in the Krylov space
+    K_k(A, r0), minimising |rhs - A x|_2 (plain least squares on the
+    orthonormalised Krylov basis)."""
+    r0 = rhs - A @ x0
+    K = np.stack([np.linalg.matrix_power(A, j) @ r0 for j in range(k)], axis=1)
+    Qk, _ = np.linalg.qr(K)
+    y, *_ = np.linalg.lstsq(A @ Qk, r0, rcond=None)
+    return x0 + Qk @ y
+
+
+def test_anderson_on_a_linear_map_is_G_of_the_gmres_iterate():
+    """Walker and Ni (2011), Sec. 4: on G(x) = M x + b with unbounded memory,
+    x_{k+1} = G(xbar_k) with xbar_k the k-th GMRES iterate of (I - M) x = b
+    from x0; after n steps that is the fixed point itself."""
+    rng = np.random.default_rng(2)
+    n = 6
+    M = rng.standard_normal((n, n))
+    M *= 0.8 / max(abs(np.linalg.eigvals(M)))
+    b = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    G = lambda x: M @ x + b  # noqa: E731
+    xs, gs = V.anderson(G, x0, n, n + 1)
+    A = np.eye(n) - M
+    for k in range(1, n):
+        want = G(_gmres_iterate(A, b, x0, k))
+        assert np.allclose(xs[k], want, rtol=0, atol=1e-10 * np.abs(want).max()), k
+    xstar = np.linalg.solve(A, b)
+    assert np.abs(xs[n] - xstar).max() < 1e-9 * np.abs(xstar).max()
+    # memory 0 is the plain iteration
+    xp, _ = V.anderson(G, x0, 0, 3)
+    assert np.allclose(xp[2], G(G(G(x0))), rtol=0, atol=1e-15)
+
+
+def test_anderson_outer_iteration_converges_no_slower():
+    """On the thick-diffusion-limit problem (eps = 1e-2, 8x8) the outer
+    iteration with two Anderson vectors reaches a relative change of 1e-8 in
+    no more iterations than the plain one, to the same flux."""
+    eps = 1e-2
+    cp, ec = P.quad_mesh(8, 8, 1)
+    om, wt = P.level_symmetric_2d(4)
+    ne = ec.shape[0]
+    pr = P.Problem("tdl", 1, 1, cp, ec, om, wt, np.full(ne, 1 / eps), np.full(ne, 1 / eps - eps), nx=8, ny=8, nq=3)
+    pr.q_iso = np.full((ne, 4), eps / (4 * math.pi))
+
+    def first_below(hist, tol=1e-8):
+        for k in range(1, len(hist)):
+            if np.abs(hist[k] - hist[k - 1]).max() <= tol * np.abs(hist[k]).max():
+                return k + 1
+        return None
+
+    plain = V.outer_iteration(pr, 3, 10)
+    acc = V.outer_iteration(pr, 3, 10, m_anderson=2)
+    kp, ka = first_below(plain), first_below(acc)
+    assert kp is not None and ka is not None and ka <= kp, (kp, ka)
+    assert np.abs(acc[ka - 1] - plain[-1]).max() <= 1e-7 * np.abs(plain[-1]).max()
