@@ -16,6 +16,11 @@ ARCH = os.environ.get("VEF_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU forms.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source flags: the HRT elimination is a fully unrolled loop over the
+# 56 rows of the p = 3 block matrix, above the default limit on the size of a
+# pragma-requested unroll (a rolled loop indexes the row array at run time,
+# which puts it in scratch memory).
+SOURCE_FLAGS = {"hrt.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 
 
 def hipcc():
@@ -29,7 +34,7 @@ def _compile(src, verbose):
     obj = os.path.join(HERE, "_build", os.path.splitext(src)[0] + ".o")
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-c",
            "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-command-line-argument"]
-    cmd += DEVICE_FLAGS
+    cmd += DEVICE_FLAGS + SOURCE_FLAGS.get(src, [])
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     cmd += [os.path.join(CSRC, src), "-o", obj]

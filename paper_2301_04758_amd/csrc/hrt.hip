@@ -32,6 +32,11 @@ namespace vefk {
 namespace {
 
 constexpr int kHrtWaves = 4;  // elements (waves) per work-group
+// Resident waves per SIMD the register allocation must allow (512 / w
+// VGPRs each): the elimination is a chain of LDS round trips and dependent
+// FMAs whose latency the other waves hide; the row of the block matrix
+// (2 (p+1)(p+2) + (p+1)^2 doubles per lane) sets how many fit without spills.
+constexpr int hrt_waves_per_simd(int p) { return p == 1 ? 4 : p == 2 ? 3 : 2; }
 
 template <int P, int NQ>
 struct Hrt {
@@ -51,6 +56,22 @@ struct Hrt {
   static constexpr int OFF_WF = OFF_TF + 4 * NQ * NT;
   static_assert(N <= 64, "one row per lane");
 };
+
+// 1 / d: the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - d r) (each roughly doubles the correct bits).
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// The value of x in lane src (uniform), as two 32-bit lane reads.
+__device__ __forceinline__ double lane_value(double x, int src) {
+  const unsigned long long b = __double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readlane(static_cast<unsigned>(b), src);
+  const unsigned hi = __builtin_amdgcn_readlane(static_cast<unsigned>(b >> 32), src);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
 
 // E = P / phi at one point from nodal transport moments (basis values b)
 template <int NT>
@@ -75,7 +96,7 @@ __device__ __forceinline__ void eddington_at(const double *__restrict__ mom, siz
 }
 
 template <int P, int NQ>
-__global__ void __launch_bounds__(64 * kHrtWaves)
+__global__ void __launch_bounds__(64 * kHrtWaves, hrt_waves_per_simd(P))
 k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, const double *__restrict__ sig,
               const int32_t *__restrict__ nbr, const double *__restrict__ mom, const double *__restrict__ Eb,
               int ne, double *__restrict__ out) {
@@ -83,7 +104,6 @@ k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, co
   constexpr int NX = H::NX, NV = H::NV, NPHI = H::NPHI, NT = H::NT, N = H::N, Q = H::Q;
   __shared__ double sT[kHrtWaves][Q][4];   // F^T E F^{-T} at volume points
   __shared__ double sF[kHrtWaves][NQ][4];  // E at the points of one boundary face, and 1 / E_b
-  __shared__ __align__(16) double sRow[kHrtWaves][N + 1];  // pivot row of the elimination
   constexpr int kTile = (N * N * kHrtWaves * 8 <= 40 * 1024) ? N * N : 1;
   __shared__ __align__(16) double sTile[kHrtWaves][kTile];  // output block of one element
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -189,29 +209,31 @@ k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, co
     __builtin_amdgcn_wave_barrier();
   }
 
-  // in-place Gauss-Jordan inversion, natural order.  Step k: the pivot lane
-  // writes its row to LDS; every lane reads it back (one address for the
-  // whole wave: a broadcast) and updates its own row without branches:
-  //   a_j <- m a_j - g row_j,  m = 0, g = -1 / a_kk on the pivot lane (its
-  //   row is normalised), m = 1, g = a_k / a_kk elsewhere (entry k
-  //   eliminated); column k becomes 1 / a_kk resp. -a_k / a_kk.
+  // in-place Gauss-Jordan inversion, natural order.  Step k: every lane
+  // reads the pivot row from lane k's registers (readlane: no LDS round trip
+  // on the dependency chain of the steps) and eliminates entry k from its
+  // own row,  a_j <- a_j - g row_j,  g = a_k / a_kk,  a_k <- -g.
+  // The pivot row is not divided by a_kk at its step: it keeps its values
+  // with a 1 in column k, and its lane remembers 1 / a_kk.  Later steps treat
+  // the row linearly, so one multiplication by that factor at the end gives
+  // the row of the inverse; this saves a multiply per entry and step.
+  double rscale = 1.0;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    if (lane == k) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) sRow[w][j] = a[j];
-    }
-    __builtin_amdgcn_wave_barrier();
     const bool me = lane == k;
-    const double pinv = 1.0 / sRow[w][k];
-    const double m = me ? 0.0 : 1.0;
-    const double gk = me ? -pinv : a[k] * pinv;
+    double row[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) row[j] = lane_value(a[j], k);
+    const double pinv = recip(row[k]);
+    const double gk = me ? 0.0 : a[k] * pinv;
 #pragma unroll
     for (int j = 0; j < N; ++j)
-      if (j != k) a[j] = fma(-gk, sRow[w][j], a[j] * m);
-    a[k] = me ? pinv : -gk;
-    __builtin_amdgcn_wave_barrier();
+      if (j != k) a[j] = fma(-gk, row[j], a[j]);
+    a[k] = me ? 1.0 : -gk;
+    rscale = me ? pinv : rscale;
   }
+#pragma unroll
+  for (int j = 0; j < N; ++j) a[j] *= rscale;
 
   double *o = out + (size_t)e * N * N;
   if constexpr (N * N * kHrtWaves * 8 <= 40 * 1024) {
@@ -224,7 +246,10 @@ k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, co
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int i = lane; i < N * N; i += 64) o[i] = tile[i];
+    for (int t = 0; t < (N * N + 63) / 64; ++t) {
+      const int i = lane + 64 * t;
+      if (i < N * N) o[i] = tile[i];
+    }
   } else if (r < N) {
 #pragma unroll
     for (int j = 0; j < N; ++j) o[r * N + j] = a[j];
