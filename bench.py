@@ -206,13 +206,16 @@ def lagged_leg(steps, n_iter=5):
 
 def hrt_flops_bytes(p, nq):
     """Algorithmic flops and HBM bytes of one element of the HRT local block
-    inverse: assembly 2 Q N^2 (every row against every trial function at
-    every Gauss point), in-place Gauss-Jordan 2 N^3; bytes: the N x N
+    inverse on an affine element: the G block summed over the Gauss points
+    (2 Q nv nphi: E varies from point to point), A and Ma scaled from reference
+    matrices (nv^2 + nphi^2), in-place Gauss-Jordan 2 N^3; bytes: the N x N
     inverse written, the element's moments, geometry, cross sections and
     neighbours read."""
-    n = 2 * (p + 1) * (p + 2) + (p + 1) ** 2
+    nv, nphi = 2 * (p + 1) * (p + 2), (p + 1) ** 2
+    n = nv + nphi
     Q = nq * nq
-    return 2 * Q * n * n + 2 * n ** 3, 8 * n * n + 6 * (p + 1) ** 2 * 8 + 13 * 8 + 16 + 16
+    return (2 * Q * nv * nphi + nv * nv + nphi * nphi + 2 * n ** 3,
+            8 * n * n + 6 * (p + 1) ** 2 * 8 + 13 * 8 + 16 + 16)
 
 
 def hrt_leg(reps=5):

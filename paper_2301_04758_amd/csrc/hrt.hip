@@ -54,6 +54,9 @@ struct Hrt {
   static constexpr int OFF_VRF = OFF_TV + Q * NT;
   static constexpr int OFF_TF = OFF_VRF + 4 * NQ * NV;
   static constexpr int OFF_WF = OFF_TF + 4 * NQ * NT;
+  static constexpr int OFF_MV = OFF_WF + NQ;
+  static constexpr int OFF_DV = OFF_MV + NV * NV;
+  static constexpr int OFF_MU = OFF_DV + NPHI * NV;
   static_assert(N <= 64, "one row per lane");
 };
 
@@ -138,38 +141,37 @@ k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, co
   const int rc = r < NX ? 0 : 1;     // its non-zero component
   const int rv = cur ? r : 0;        // table index (clamped for other lanes)
   const int rp = (r >= NV && r < N) ? r - NV : 0;
+  // Volume terms.  Only G needs the sum over the points (E varies); A, D
+  // and Ma are reference matrices scaled by the element's constants:
+  //   A_ij = sigma_t / J (F^T F)_{c_i c_j} MV_ij, D = DV, Ma = sigma_a J MU.
   double a[N];
+  if (cur) {
+    const double *mv = tab + H::OFF_MV + rv * NV;
+    const double s0 = st / J * (rc == 0 ? G00 : G01), s1 = st / J * (rc == 0 ? G01 : G11);
 #pragma unroll
-  for (int j = 0; j < N; ++j) a[j] = 0.0;
-
+    for (int j = 0; j < NX; ++j) a[j] = s0 * mv[j];
+#pragma unroll
+    for (int j = NX; j < NV; ++j) a[j] = s1 * mv[j];
+  } else {
+    const double *dv = tab + H::OFF_DV + rp * NV;
+    const double *mu = tab + H::OFF_MU + rp * NPHI;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) a[j] = dv[j];
+#pragma unroll
+    for (int j = 0; j < NPHI; ++j) a[NV + j] = sa * J * mu[j];
+  }
+  if (cur) {
+#pragma unroll
+    for (int j = 0; j < NPHI; ++j) a[NV + j] = 0.0;
 #pragma unroll 1
-  for (int q = 0; q < Q; ++q) {
-    const double wq = tab[H::OFF_W + q];
-    const double *vr = tab + H::OFF_VR + q * NV;
-    const double *dr = tab + H::OFF_DR + q * NV * 2;
-    const double *u = tab + H::OFF_U + q * NPHI;
-    const double t00 = sT[w][q][0], t01 = sT[w][q][1], t10 = sT[w][q][2], t11 = sT[w][q][3];
-    if (cur) {
-      const double vi = vr[rv], dxi = dr[2 * rv], dyi = dr[2 * rv + 1];
-      const double gT = rc == 0 ? dxi * t00 + dyi * t01 : dxi * t10 + dyi * t11;
-      const double m = wq * st / J * vi;
-      const double c0 = m * (rc == 0 ? G00 : G01), c1 = m * (rc == 0 ? G01 : G11);
-#pragma unroll
-      for (int j = 0; j < NX; ++j) a[j] += c0 * vr[j];
-#pragma unroll
-      for (int j = NX; j < NV; ++j) a[j] += c1 * vr[j];
-      const double cg = -wq * gT;
+    for (int q = 0; q < Q; ++q) {
+      const double *dr = tab + H::OFF_DR + q * NV * 2;
+      const double *u = tab + H::OFF_U + q * NPHI;
+      const double dxi = dr[2 * rv], dyi = dr[2 * rv + 1];
+      const double gT = rc == 0 ? dxi * sT[w][q][0] + dyi * sT[w][q][1] : dxi * sT[w][q][2] + dyi * sT[w][q][3];
+      const double cg = -tab[H::OFF_W + q] * gT;
 #pragma unroll
       for (int j = 0; j < NPHI; ++j) a[NV + j] += cg * u[j];
-    } else if (r < N) {
-      const double ui = wq * u[rp];
-#pragma unroll
-      for (int j = 0; j < NX; ++j) a[j] += ui * dr[2 * j];
-#pragma unroll
-      for (int j = NX; j < NV; ++j) a[j] += ui * dr[2 * j + 1];
-      const double cm = ui * sa * J;
-#pragma unroll
-      for (int j = 0; j < NPHI; ++j) a[NV + j] += cm * u[j];
     }
   }
 

@@ -259,7 +259,10 @@ int hrt_sizes(int p, int nq, HrtSizes &z) {
   z.off_vrf = z.off_tv + Q * z.nt;
   z.off_tf = z.off_vrf + 4 * nq * z.nv;
   z.off_wf = z.off_tf + 4 * nq * z.nt;
-  z.total = z.off_wf + nq;
+  z.off_mv = z.off_wf + nq;               // [nv][nv] sum_q w vr_i vr_j
+  z.off_dv = z.off_mv + z.nv * z.nv;      // [nphi][nv] sum_q w u_i div vr_j
+  z.off_mu = z.off_dv + z.nphi * z.nv;    // [nphi][nphi] sum_q w u_i u_j
+  z.total = z.off_mu + z.nphi * z.nphi;
   return VEF_OK;
 }
 
@@ -334,7 +337,22 @@ int build_hrt_tables(int p, int nq, std::vector<double> &blob) {
       tensor(lob, x, y, &blob[z.off_tf + ((size_t)f * nq + q) * z.nt]);
     }
   for (int q = 0; q < nq; ++q) blob[z.off_wf + q] = gw[q];
-  (void)Q;
+  // Reference matrices of the element-independent parts of the affine
+  // blocks: the RT mass of the non-zero components (A = sigma_t / J
+  // (F^T F)_{c_i c_j} times it), D, and the Q_p mass (Ma = sigma_a J times it).
+  for (int q = 0; q < Q; ++q) {
+    const double w = blob[z.off_w + q];
+    const double *vr = &blob[z.off_vr + (size_t)q * z.nv];
+    const double *dr = &blob[z.off_dr + (size_t)q * z.nv * 2];
+    const double *u = &blob[z.off_u + (size_t)q * z.nphi];
+    for (int i = 0; i < z.nv; ++i)
+      for (int j = 0; j < z.nv; ++j) blob[z.off_mv + (size_t)i * z.nv + j] += w * vr[i] * vr[j];
+    for (int i = 0; i < z.nphi; ++i)
+      for (int j = 0; j < z.nv; ++j)
+        blob[z.off_dv + (size_t)i * z.nv + j] += w * u[i] * dr[2 * j + (j < z.nx ? 0 : 1)];
+    for (int i = 0; i < z.nphi; ++i)
+      for (int j = 0; j < z.nphi; ++j) blob[z.off_mu + (size_t)i * z.nphi + j] += w * u[i] * u[j];
+  }
   return VEF_OK;
 }
 
