@@ -204,6 +204,52 @@ def lagged_leg(steps, n_iter=5):
     return out
 
 
+def pointwise_leg(steps, n_iter=5):
+    """Pointwise against whole-face upwinding on a curved mesh: the 64x64
+    cubic Taylor-Green mesh (t = 0.3 pi), p = 2, S8, sigma_t log-uniform
+    [0.1, 100] per 8x8 block, c = 0.9.  Whole-face upwinding gives acyclic
+    graphs there; the pointwise rule couples both elements of every face
+    along which Omega . n changes sign, and those couplings are lagged.  FP64
+    source iterations, time per sweep."""
+    import numpy as np
+    import torch
+    from paper_2301_04758_amd import problems as P
+    from paper_2301_04758_amd import vef
+    cp, ec = P.taylor_green_mesh(64, 3, t_final=0.3 * math.pi)
+    om, wt = P.level_symmetric_2d(8)
+    rng = np.random.Generator(np.random.PCG64(P.SEED_BASE + 13))
+    st = P.block_log_uniform(64, 64, 8, 0.1, 100.0, rng)
+    pr = P.Problem("tg64_m3_p2_S8", 2, 3, cp, ec, om, wt, st, 0.9 * st, nx=64, ny=64)
+    pr.q_iso = np.ones((pr.n_elem, 9))
+    out = {"workload": "64x64 cubic Taylor-Green mesh (t = 0.3 pi), p=2, S8, sigma_t log-uniform [0.1,100] per "
+                       "8x8 block, c=0.9, FP64; %d sweeps per step" % n_iter}
+    phi = {}
+    for rule, pointwise in (("whole_face", False), ("pointwise", True)):
+        sw = vef.Sweep([pr], precision="fp64", lag_cycles=True, pointwise=pointwise)
+        io = sw.buffers(n_iter=n_iter, store_psi=True)
+        tuned = sw.autotune(io, n_iter=n_iter, reps=1)
+        io[0]["psi_out"].zero_()
+        sw.run(io, n_iter=n_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sw.run(io, n_iter=n_iter)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / (steps * n_iter)
+        sw.check()
+        inf = sw.info[0]
+        phi[rule] = io[0]["mom"][0].cpu().numpy()
+        out[rule] = {"ms_per_sweep": ms, "solves_per_s": pr.n_elem * pr.n_dir / (ms * 1e-3),
+                     "schedule": vef.SCHEDULE_NAMES[inf["schedule"]], "kernel": vef.KERNEL_NAMES[inf["kernel"]],
+                     "n_lagged": inf["n_lagged"], "lagged_frac": inf["n_lagged"] / (pr.n_elem * pr.n_dir),
+                     "n_levels": inf["n_levels"], "tuning": tuned}
+        sw.close()
+        del io
+    out["rel_inf_phi_pointwise_vs_whole_face"] = float(np.abs(phi["pointwise"] - phi["whole_face"]).max()
+                                                       / np.abs(phi["whole_face"]).max())
+    return out
+
+
 def hrt_flops_bytes(p, nq):
     """Algorithmic flops and HBM bytes of one element of the HRT local block
     inverse on an affine element: the G block summed over the Gauss points
@@ -386,6 +432,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 64-problem batched FP32 vs one-by-one FP64 block")
     ap.add_argument("--no-fixup", action="store_true", help="skip the negative-flux fixup leg")
     ap.add_argument("--no-lagged", action="store_true", help="skip the re-entrant-mesh lagged-sweep leg")
+    ap.add_argument("--no-pointwise", action="store_true", help="skip the pointwise-upwinding leg")
     ap.add_argument("--no-hrt", action="store_true", help="skip the HRT local block inverse leg")
     ap.add_argument("--no-outer", action="store_true", help="skip the transport / VEF outer iteration leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -463,6 +510,8 @@ def main():
         result["fixup_fp64"] = fixup_leg(probs, n_iter, args.steps, ms_step)
     if not args.no_lagged:
         result["lagged_reentrant"] = lagged_leg(args.steps)
+    if not args.no_pointwise:
+        result["pointwise_upwinding"] = pointwise_leg(args.steps)
     if not args.no_hrt:
         result["hrt_local_inverse"] = hrt_leg()
     if not args.no_outer:

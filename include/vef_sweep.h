@@ -71,6 +71,11 @@ enum {
                             couplings (vef_options.cycles) */
 };
 enum {
+  VEF_UPWIND_FACE = 0,  /* one upwind side per face, from the rotated chord */
+  VEF_UPWIND_POINT = 1  /* the upwind side at each face quadrature point
+                           (vef_options.upwind) */
+};
+enum {
   VEF_SCHEDULE_AUTO = 0, /* VEF_DIR_RESIDENT when every problem's mean level
                             width fits one round of a work-group, else
                             VEF_LEVEL_SYNC */
@@ -145,6 +150,16 @@ typedef struct {
                     create).  Acyclic graphs are swept exactly as with
                     VEF_CYCLES_REJECT.  The pipelined kernel is not used for a
                     problem with lagged faces. */
+  int upwind;        /* VEF_UPWIND_FACE (default): the upwind side of a face is
+                    chosen for the whole face from the sign of Omega . N_F,
+                    N_F the rotated chord (lower element id upwind on a zero
+                    product).  VEF_UPWIND_POINT: chosen at each face
+                    quadrature point from the sign of Omega . n there; on a
+                    curved face whose points have both signs each element
+                    takes the other's trace where it is downwind, so both
+                    depend on each other and the sweep needs
+                    VEF_CYCLES_LAG.  Straight faces give the same result
+                    under both rules.  Not combined with the fixup. */
 } vef_options;
 
 /* Per-problem device buffers of one run (device pointers owned by the caller).

@@ -26,7 +26,10 @@
  *   - the upwind side of a face is chosen for the whole face from the sign of
  *     Omega . N_F, N_F the rotated chord of the face (= integral of n ds);
  *     a zero product makes the lower element id upwind; a boundary face is
- *     inflow when Omega . N_F < 0;
+ *     inflow when Omega . N_F < 0.  Optionally (pointwise upwinding) the side
+ *     is chosen at each face quadrature point from the sign of Omega . n
+ *     there; a face with both signs couples both of its elements, and the
+ *     lagged sweeps below break the resulting cycles;
  *   - tensor Gauss-Lobatto nodal basis of degree p on [0,1]^2, tensor
  *     Gauss-Legendre quadrature with nq points per direction (default p+m);
  *   - dense Gaussian elimination with partial pivoting (first maximal entry);
@@ -42,7 +45,9 @@
  *     the global upwind system with the strictly upper block triangular part
  *     (in the sweep order) lagged.  The paper's pseudo-optimal reordering
  *     (from its graph-sweep reference) is not reproduced.
- *   Parity of the curved-face upwind rule is unpinned beyond its definition.
+ *   Parity of the whole-face rule on curved faces is unpinned beyond its
+ *   definition; the pointwise rule is pinned against an independent dense
+ *   global solve.
  */
 #include <math.h>
 #include <stdint.h>
@@ -72,6 +77,8 @@ typedef struct {
   const double *sigma_s;
   int fixup; /* 1: set-to-zero-and-scale negative-flux fixup after each local solve */
   int lag;   /* 1: cyclic upwind graphs are swept with lagged couplings */
+  int pointwise; /* 1: the upwind side is chosen at each face quadrature point
+                    from the sign of Omega . n there (0: for the whole face) */
 } oracle_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -271,6 +278,7 @@ typedef struct {
   int *nbr_rev;  /* [n_elem][4] 1 if the neighbour runs the face the other way */
   int *bf_id;    /* [n_elem][4] boundary face index or -1 */
   double *chord; /* [n_elem][4][2] N_F = rotated chord */
+  double *fnds;  /* [n_elem][4][nq][2] n ds at the face quadrature points */
   int n_bf;
 } conn_t;
 
@@ -285,7 +293,7 @@ static int fkey_cmp(const void *a, const void *b) {
 }
 
 static void conn_free(conn_t *c) {
-  free(c->nbr); free(c->nbr_face); free(c->nbr_rev); free(c->bf_id); free(c->chord);
+  free(c->nbr); free(c->nbr_face); free(c->nbr_rev); free(c->bf_id); free(c->chord); free(c->fnds);
   memset(c, 0, sizeof(*c));
 }
 
@@ -352,6 +360,17 @@ static int build_conn(const ctx_t *c, conn_t *cn) {
     for (int f = 0; f < 4; ++f)
       if (cn->nbr[4 * e + f] < 0) cn->bf_id[4 * e + f] = nb++;
   cn->n_bf = nb;
+  cn->fnds = (double *)malloc(sizeof(double) * 8 * (size_t)c->nq * ne);
+  if (!cn->fnds) { conn_free(cn); return ORACLE_ERR_OOM; }
+  for (int e = 0; e < ne; ++e)
+    for (int f = 0; f < 4; ++f)
+      for (int q = 0; q < c->nq; ++q) {
+        double xi, eta, F[2][2];
+        face_point(f, c->gx[q], &xi, &eta);
+        map_point(c, e, xi, eta, NULL, F);
+        double *o = cn->fnds + 2 * (((size_t)e * 4 + f) * c->nq + q);
+        face_nds(F, f, &o[0], &o[1]);
+      }
   return ORACLE_OK;
 }
 
@@ -377,6 +396,22 @@ static int is_upwind(const conn_t *cn, int e, int f, double ox, double oy) {
   return e < cn->nbr[4 * e + f];
 }
 
+/* Does face f of element e take upwind data for direction (ox, oy)?  Whole
+ * face: interior faces by is_upwind, boundary faces when Omega . N_F < 0.
+ * Pointwise: when Omega . n < 0 at some face quadrature point (a face with
+ * both signs makes each side depend on the other). */
+static int has_inflow(const ctx_t *c, const conn_t *cn, int e, int f, double ox, double oy) {
+  if (c->pr->pointwise) {
+    for (int q = 0; q < c->nq; ++q) {
+      const double *o = cn->fnds + 2 * (((size_t)e * 4 + f) * c->nq + q);
+      if (ox * o[0] + oy * o[1] < 0.0) return 1;
+    }
+    return 0;
+  }
+  if (cn->nbr[4 * e + f] >= 0) return !is_upwind(cn, e, f, ox, oy);
+  return ox * cn->chord[8 * e + 2 * f] + oy * cn->chord[8 * e + 2 * f + 1] < 0.0;
+}
+
 /* Kahn topological order of the per-direction upwind graph, FIFO seeded with
  * the sources in increasing element id; level = 1 + max level of the upwind
  * neighbours solved before.  With pr->lag, when the FIFO runs dry before
@@ -391,7 +426,7 @@ static int topo_order(const ctx_t *c, const conn_t *cn, double ox, double oy, in
     indeg[e] = 0;
     level[e] = 0;
     for (int f = 0; f < 4; ++f)
-      if (cn->nbr[4 * e + f] >= 0 && !is_upwind(cn, e, f, ox, oy)) indeg[e]++;
+      if (cn->nbr[4 * e + f] >= 0 && has_inflow(c, cn, e, f, ox, oy)) indeg[e]++;
   }
   int head = 0, tail = 0, lagged = 0;
   for (int e = 0; e < ne; ++e)
@@ -404,7 +439,7 @@ static int topo_order(const ctx_t *c, const conn_t *cn, double ox, double oy, in
       for (int f = 0; f < 4; ++f) {
         int nb = cn->nbr[4 * e + f];
         /* indeg < 0 marks an element appended by the release rule */
-        if (nb >= 0 && is_upwind(cn, e, f, ox, oy) && indeg[nb] > 0) {
+        if (nb >= 0 && has_inflow(c, cn, nb, cn->nbr_face[4 * e + f], ox, oy) && indeg[nb] > 0) {
           if (level[e] + 1 > level[nb]) level[nb] = level[e] + 1;
           if (--indeg[nb] == 0) order[tail++] = nb;
         }
@@ -550,7 +585,8 @@ static int local_solve(const ctx_t *c, const conn_t *cn, int e, int d, const dou
       face_nds(F, f, &nx, &ny);
       double on = ox * nx + oy * ny;
       basis2d(c->zp, pr->p, xi, eta, v, NULL, NULL);
-      if (outflow) {
+      /* pointwise: the side is chosen here, from Omega . n at this point */
+      if (pr->pointwise ? !(on < 0.0) : outflow) {
         for (int i = 0; i < n; ++i)
           for (int j = 0; j < n; ++j) A[i * n + j] += ws * on * v[i] * v[j];
       } else {

@@ -96,6 +96,7 @@ struct vef_sweep {
   int pipeline_ring = 0;
   int fixup = 0;
   int cycles = VEF_CYCLES_REJECT;
+  int upwind = VEF_UPWIND_FACE;
   std::vector<double *> hrt_geo;               // per problem [ne][13], allocated on first need
   std::map<std::pair<int, int>, double *> hrt_tab;  // (p, nq) -> HRT tables
   std::vector<hipEvent_t> events;  // [2 * iterations] of the last run
@@ -205,6 +206,11 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (opt->cycles != VEF_CYCLES_REJECT && opt->cycles != VEF_CYCLES_LAG)
       return set_err(h, VEF_ERR_INVALID, "cycles must be VEF_CYCLES_REJECT or VEF_CYCLES_LAG");
     h->cycles = opt->cycles;
+    if (opt->upwind != VEF_UPWIND_FACE && opt->upwind != VEF_UPWIND_POINT)
+      return set_err(h, VEF_ERR_INVALID, "unknown upwind rule");
+    if (opt->upwind == VEF_UPWIND_POINT && opt->fixup)
+      return set_err(h, VEF_ERR_INVALID, "the fixup is not available with pointwise upwinding");
+    h->upwind = opt->upwind;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
   }
@@ -212,7 +218,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   h->plans.resize(n_probs);
   for (int k = 0; k < n_probs; ++k) {
     std::string e;
-    int rc = vefplan::build_problem_plan(probs[k], h->cycles == VEF_CYCLES_LAG, h->plans[k], e);
+    int rc = vefplan::build_problem_plan(probs[k], h->cycles == VEF_CYCLES_LAG, h->upwind == VEF_UPWIND_POINT,
+                                         h->plans[k], e);
     if (rc) return set_err(h, rc, "problem " + std::to_string(k) + ": " + e);
   }
   hipError_t he = hipGetDevice(&h->device);
@@ -250,6 +257,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     kp.Q = pl.Q;
     kp.nq = pl.nq;
     kp.p = pl.p;
+    kp.pointwise = h->upwind == VEF_UPWIND_POINT ? 1 : 0;
     void *gv = nullptr, *gf = nullptr;
     he = fp32 ? upload_as<float>(h, &gv, pl.geo_v) : upload_as<double>(h, &gv, pl.geo_v);
     if (he == hipSuccess) he = fp32 ? upload_as<float>(h, &gf, pl.geo_f) : upload_as<double>(h, &gf, pl.geo_f);
@@ -657,11 +665,14 @@ int vef_plan_query(const vef_problem_desc *prob, const vef_options *opt, vef_inf
   const int cycles = opt ? opt->cycles : VEF_CYCLES_REJECT;
   if (cycles != VEF_CYCLES_REJECT && cycles != VEF_CYCLES_LAG)
     return set_err(nullptr, VEF_ERR_INVALID, "cycles must be VEF_CYCLES_REJECT or VEF_CYCLES_LAG");
+  const int upwind = opt ? opt->upwind : VEF_UPWIND_FACE;
+  if (upwind != VEF_UPWIND_FACE && upwind != VEF_UPWIND_POINT)
+    return set_err(nullptr, VEF_ERR_INVALID, "unknown upwind rule");
   vefplan::ProblemPlan pl;
   std::string e;
   int rc;
   try {
-    rc = vefplan::build_problem_plan(*prob, cycles == VEF_CYCLES_LAG, pl, e);
+    rc = vefplan::build_problem_plan(*prob, cycles == VEF_CYCLES_LAG, upwind == VEF_UPWIND_POINT, pl, e);
   } catch (const std::bad_alloc &) {
     return set_err(nullptr, VEF_ERR_OOM, "host allocation failed");
   }

@@ -9,7 +9,7 @@ namespace vefk {
 
 // Per-problem constant data (device pointers), one entry per problem of a handle.
 struct KProb {
-  int ne, nd, nbf, n, Q, nq, p, pad;
+  int ne, nd, nbf, n, Q, nq, p, pointwise;  // pointwise: upwind side per face point (general kernels)
   const void *geo_v;       // T [ne][Q][5]: w J, w adj(F) (row major)
   const void *geo_f;       // T [ne][4][nq][2]: w_s n ds
   const void *geo_a;       // T [ne][16]: J, adj(F) (row major), face chords N_0..N_3 (affine meshes)

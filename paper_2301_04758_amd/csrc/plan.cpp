@@ -356,7 +356,8 @@ int build_hrt_tables(int p, int nq, std::vector<double> &blob) {
   return VEF_OK;
 }
 
-int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, ProblemPlan &o, std::string &err) {
+int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, bool pointwise, ProblemPlan &o,
+                       std::string &err) {
   if (d.p < 1 || d.p > kMaxP) return fail(err, VEF_ERR_INVALID, "p=%lld out of range 1..4", d.p);
   if (d.m < 1 || d.m > kMaxM) return fail(err, VEF_ERR_INVALID, "m=%lld out of range 1..3", d.m);
   const int nq = d.nq > 0 ? d.nq : d.p + d.m;
@@ -504,10 +505,23 @@ int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, ProblemPlan &
     }
 
   // ---- upwind masks per direction; one decision per interior face pair
+  // (pointwise: an inflow bit wherever some face point has Omega . n < 0)
   o.mask.assign((size_t)nd * ne, 0);
   for (int k = 0; k < nd; ++k) {
     const double ox = d.omega[2 * k], oy = d.omega[2 * k + 1];
     uint8_t *mk = &o.mask[(size_t)k * ne];
+    if (pointwise) {
+      for (int e = 0; e < ne; ++e)
+        for (int f = 0; f < 4; ++f)
+          for (int q = 0; q < nq; ++q) {
+            const double *g = &o.geo_f[(((size_t)e * 4 + f) * nq + q) * 2];
+            if (ox * g[0] + oy * g[1] < 0.0) {
+              mk[e] |= (uint8_t)(1u << f);
+              break;
+            }
+          }
+      continue;
+    }
     for (int e = 0; e < ne; ++e)
       for (int f = 0; f < 4; ++f) {
         const int nb = o.nbr[4 * e + f];
@@ -578,9 +592,12 @@ int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, ProblemPlan &
         maxl = std::max(maxl, (int)lev[e]);
         for (int f = 0; f < 4; ++f) {
           const int nb = o.nbr[4 * e + f];
-          if (nb < 0 || (mk[e] >> f & 1)) continue;  // boundary or inflow face of e
+          if (nb < 0) continue;
+          // nb waits on e when its face toward e is an inflow face (with
+          // whole-face upwinding exactly when e's face is not; a pointwise
+          // face with both signs is an inflow face of both)
           const int f2 = o.nbr_face[4 * e + f];
-          if (!(mk[nb] >> f2 & 1) || placed[nb]) continue;  // defensive; released elements are placed
+          if (!(mk[nb] >> f2 & 1) || placed[nb]) continue;  // released elements are placed
           lev[nb] = std::max(lev[nb], lev[e] + 1);
           if (--indeg[nb] == 0) {
             queue[tail++] = nb;

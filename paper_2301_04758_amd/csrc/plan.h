@@ -87,6 +87,9 @@ int build_hrt_tables(int p, int nq, std::vector<double> &blob);
 // Validates and plans one problem.  lag_cycles: a cyclic upwind graph is
 // ordered by releasing elements with lagged couplings instead of failing with
 // VEF_ERR_CYCLE.  Returns VEF_OK or a VEF_ERR_* status and a message in err.
-int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, ProblemPlan &out, std::string &err);
+// pointwise: the upwind side is chosen at each face quadrature point (a face
+// with points of both signs is an inflow face of both of its elements).
+int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, bool pointwise, ProblemPlan &out,
+                       std::string &err);
 
 }  // namespace vefplan

@@ -437,6 +437,28 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
 #pragma unroll
         for (int c = 0; c < P1; ++c) A[face_node<P>(f, c)] += t * sF[q * P1 + c];
       }
+    } else if (pb.pointwise) {
+      // an inflow face with pointwise upwinding: each point takes the
+      // upwind value where Omega . n < 0 and the element's own trace (a
+      // matrix term) elsewhere
+      const double *bc = (in.nb[f] < 0 && pio.psi_bc) ? pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ
+                                                      : nullptr;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T on = ox * gf[2 * q] + oy * gf[2 * q + 1];
+        const T t = on * sF[q * P1 + pos];
+        if (!(on < T(0))) {
+#pragma unroll
+          for (int c = 0; c < P1; ++c) A[face_node<P>(f, c)] += t * sF[q * P1 + c];
+        } else if (in.nb[f] >= 0) {
+          T ph = T(0);
+#pragma unroll
+          for (int c = 0; c < P1; ++c) ph += tr[f][c] * sF[q * P1 + c];
+          rhs -= t * ph;
+        } else if (bc) {
+          rhs -= t * static_cast<T>(bc[q]);
+        }
+      }
     } else if (in.nb[f] >= 0) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {

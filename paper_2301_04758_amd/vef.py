@@ -29,6 +29,7 @@ VEF_FP64 = 0
 VEF_FP32_LOCAL = 1
 VEF_CYCLES_REJECT = 0
 VEF_CYCLES_LAG = 1
+VEF_UPWIND_FACE, VEF_UPWIND_POINT = 0, 1
 VEF_SCHEDULE_AUTO = 0
 VEF_LEVEL_SYNC = 1
 VEF_DIR_RESIDENT = 2
@@ -54,7 +55,7 @@ class vef_problem_desc(C.Structure):
 class vef_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("schedule", C.c_int), ("block", C.c_int), ("timing", C.c_int),
                 ("pipeline_waves", C.c_int), ("pipeline_ring", C.c_int), ("fixup", C.c_int),
-                ("cycles", C.c_int)]
+                ("cycles", C.c_int), ("upwind", C.c_int)]
 
 
 class vef_problem_io(C.Structure):
@@ -158,11 +159,12 @@ class _Desc:
 # ------------------------------------------------------------------ C names
 
 
-def vef_plan_query(problem, lag_cycles: bool = False) -> dict:
+def vef_plan_query(problem, lag_cycles: bool = False, pointwise: bool = False) -> dict:
     d = _Desc(problem)
     info = vef_info()
     opt = vef_options()
     opt.cycles = VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT
+    opt.upwind = VEF_UPWIND_POINT if pointwise else VEF_UPWIND_FACE
     rc = lib.vef_plan_query(C.byref(d.s), C.byref(opt), C.byref(info))
     if rc != VEF_OK:
         raise VefError(rc, lib.vef_last_error(None).decode())
@@ -171,11 +173,13 @@ def vef_plan_query(problem, lag_cycles: bool = False) -> dict:
 
 def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
                      block: int = 0, timing: int = 0, pipeline_waves: int = 0,
-                     pipeline_ring: int = 0, fixup: bool = False, lag_cycles: bool = False) -> int:
+                     pipeline_ring: int = 0, fixup: bool = False, lag_cycles: bool = False,
+                     pointwise: bool = False) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
     opt = vef_options(precision, schedule, block, int(timing), pipeline_waves, pipeline_ring,
-                      1 if fixup else 0, VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT)
+                      1 if fixup else 0, VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT,
+                      VEF_UPWIND_POINT if pointwise else VEF_UPWIND_FACE)
     h = C.c_void_p()
     rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))
     if rc != VEF_OK:
@@ -287,7 +291,7 @@ class Sweep:
     """Owns one handle; allocates device buffers with torch for convenience."""
 
     def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto",
-                 pipeline_waves=0, pipeline_ring=0, fixup=False, lag_cycles=False):
+                 pipeline_waves=0, pipeline_ring=0, fixup=False, lag_cycles=False, pointwise=False):
         import torch
         self.torch = torch
         self.problems = list(problems)
@@ -296,7 +300,7 @@ class Sweep:
         with torch.cuda.device(self.device):
             self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64,
                                       SCHEDULES[schedule], block, timing, pipeline_waves, pipeline_ring,
-                                      fixup, lag_cycles)
+                                      fixup, lag_cycles, pointwise)
         self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
 
     def close(self):

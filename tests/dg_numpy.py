@@ -166,9 +166,9 @@ class Mesh:
         return out
 
 
-def global_solve(pr, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=None, nq=None):
+def global_solve(pr, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=None, nq=None, pointwise=False):
     """Dense global upwind-DG system for direction d, solved directly. Returns psi [n_elem, n]."""
-    A, b = global_system(pr, d, phi_in, q_iso, q_dir, psi_bc, nq)
+    A, b = global_system(pr, d, phi_in, q_iso, q_dir, psi_bc, nq, pointwise=pointwise)
     return np.linalg.solve(A, b).reshape(pr.n_elem, -1)
 
 
@@ -203,8 +203,10 @@ def coupled_scattering_solve(pr, q_iso=None, q_dir=None, psi_bc=None, nq=None):
     return np.einsum("d,den->en", pr.weight, psi)
 
 
-def global_system(pr, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=None, nq=None):
-    """Dense global upwind-DG matrix and right-hand side for direction d."""
+def global_system(pr, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=None, nq=None, pointwise=False):
+    """Dense global upwind-DG matrix and right-hand side for direction d.
+    pointwise: the upwind side is taken at each face point from the sign of
+    Omega . n there (else for the whole face, from the rotated chord)."""
     M = Mesh(pr, nq)
     n, ne = M.n, pr.n_elem
     om = np.asarray(pr.omega[d], dtype=float)
@@ -228,23 +230,27 @@ def global_system(pr, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=None, nq=No
             fxi, feta, fx, nds = M.face_data(e, f)
             on = nds @ om
             vf = tensor_vals(M.Bp, fxi, feta)[0]
-            if M.upwind_is_self(e, f, om):
-                blk += np.einsum("q,qi,qj->ij", M.gw * on, vf, vf)
-            elif (e, f) in M.nbr:
+            if pointwise:
+                own = (on >= 0).astype(float)
+            else:
+                own = np.full(len(on), 1.0 if M.upwind_is_self(e, f, om) else 0.0)
+            blk += np.einsum("q,qi,qj->ij", M.gw * on * own, vf, vf)
+            up = 1.0 - own
+            if (e, f) in M.nbr:
                 e2, xi2, eta2 = M.neighbour_points(e, f)
                 v2 = tensor_vals(M.Bp, xi2, eta2)[0]
-                A[e * n:(e + 1) * n, e2 * n:(e2 + 1) * n] += np.einsum("q,qi,qj->ij", M.gw * on, vf, v2)
-            else:
-                if psi_bc is not None:
-                    bf = M.bf_index[(e, f)]
-                    b[e * n:(e + 1) * n] -= np.einsum("q,qi->i", M.gw * on * psi_bc[d, bf], vf)
+                A[e * n:(e + 1) * n, e2 * n:(e2 + 1) * n] += np.einsum("q,qi,qj->ij", M.gw * on * up, vf, v2)
+            elif psi_bc is not None:
+                bf = M.bf_index[(e, f)]
+                b[e * n:(e + 1) * n] -= np.einsum("q,qi->i", M.gw * on * up * psi_bc[d, bf], vf)
         A[e * n:(e + 1) * n, e * n:(e + 1) * n] += blk
     return A, b
 
 
-def balance_residuals(pr, psi, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=None, nq=None):
+def balance_residuals(pr, psi, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=None, nq=None, pointwise=False):
     """Per-element particle balance (test function u = 1) for direction d:
-    outflow - inflow + absorption - source, relative to the source scale."""
+    outflow - inflow + absorption - source, relative to the source scale
+    (pointwise: upwind trace chosen at each face point)."""
     M = Mesh(pr, nq)
     om = np.asarray(pr.omega[d], dtype=float)
     res = np.zeros(pr.n_elem)
@@ -264,13 +270,16 @@ def balance_residuals(pr, psi, d, phi_in=None, q_iso=None, q_dir=None, psi_bc=No
         for f in range(4):
             fxi, feta, fx, nds = M.face_data(e, f)
             on = nds @ om
-            if M.upwind_is_self(e, f, om):
-                tr = tensor_vals(M.Bp, fxi, feta)[0] @ psi[e]
-            elif (e, f) in M.nbr:
+            mine = tensor_vals(M.Bp, fxi, feta)[0] @ psi[e]
+            if (e, f) in M.nbr:
                 e2, xi2, eta2 = M.neighbour_points(e, f)
-                tr = tensor_vals(M.Bp, xi2, eta2)[0] @ psi[e2]
+                other = tensor_vals(M.Bp, xi2, eta2)[0] @ psi[e2]
             else:
-                tr = psi_bc[d, M.bf_index[(e, f)]] if psi_bc is not None else np.zeros(M.nq)
+                other = psi_bc[d, M.bf_index[(e, f)]] if psi_bc is not None else np.zeros(M.nq)
+            if pointwise:
+                tr = np.where(on >= 0, mine, other)
+            else:
+                tr = mine if M.upwind_is_self(e, f, om) else other
             flux = np.sum(M.gw * on * tr)
             tot += flux
             sc += abs(flux)

@@ -1,0 +1,127 @@
+"""Pointwise upwinding (the upwind side chosen at each face quadrature point
+from the sign of Omega . n there; a face whose points have both signs couples
+both of its elements, and lagged sweeps break the cycles this makes): pins of
+the oracle against an independent dense numpy assembly of the same global
+system (tests/dg_numpy.py, pointwise=True).
+
+  * on straight-sided meshes Omega . n is constant along a face, so the
+    pointwise rule is the whole-face rule: identical sweeps;
+  * a lagged pointwise sweep whose lagged reads see the dense global solution
+    returns that solution (the sweep is an exact block Gauss-Seidel step);
+  * repeated lagged pointwise sweeps converge to the dense global solution;
+  * the converged solution keeps every element's particle balance with the
+    pointwise upwind fluxes;
+  * on Taylor-Green meshes (curved faces along which Omega . n changes sign)
+    the two rules give different solutions.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dg_numpy as D
+from oracle import oracle as O
+from paper_2301_04758_amd import problems as P
+
+
+def _tg(n=3, m=2, p=2, N=4, st=2.0):
+    cp, ec = P.taylor_green_mesh(n, m, t_final=0.3 * math.pi)
+    om, wt = P.level_symmetric_2d(N)
+    ne = ec.shape[0]
+    pr = P.Problem("tg_%d_m%d_p%d" % (n, m, p), p, m, cp, ec, om, wt, np.full(ne, st), np.zeros(ne), nx=n, ny=n)
+    pr.q_iso = np.ones((ne, (p + 1) ** 2))
+    return pr
+
+
+def _mixed_faces(pr):
+    M = D.Mesh(pr)
+    k = 0
+    for d in range(pr.n_dir):
+        o = np.asarray(pr.omega[d])
+        for e in range(pr.n_elem):
+            for f in range(4):
+                on = M.face_data(e, f)[3] @ o
+                k += int((on > 0).any() and (on < 0).any())
+    return k
+
+
+@pytest.mark.parametrize("p,m,kind", [(1, 1, "sheared"), (2, 1, "bilinear"), (3, 2, "grid")])
+def test_straight_meshes_pointwise_equals_whole_face(p, m, kind):
+    cp, ec = P.quad_mesh(5, 4, m)
+    if kind == "sheared":  # parallelograms
+        cp = cp @ np.array([[1.3, 0.2], [0.1, 1.0]]).T
+    elif kind == "bilinear":  # straight-sided quadrilaterals: interior corners moved
+        rng = np.random.default_rng(1)
+        inner = (cp[:, 0] > 0) & (cp[:, 0] < 1) & (cp[:, 1] > 0) & (cp[:, 1] < 1)
+        cp = cp.copy()
+        cp[inner] += rng.uniform(-0.03, 0.03, (inner.sum(), 2))
+    om, wt = P.level_symmetric_2d(6)
+    ne = ec.shape[0]
+    pr = P.Problem("straight", p, m, cp, ec, om, wt, np.full(ne, 3.0), np.full(ne, 1.0), nx=5, ny=4)
+    pr.q_iso = np.ones((ne, (p + 1) ** 2))
+    a = O.sweep(pr)
+    b = O.sweep(pr, pointwise=True)
+    assert np.array_equal(a["psi"], b["psi"])
+    assert np.array_equal(a["levels"], b["levels"])
+
+
+def test_taylor_green_meshes_have_mixed_faces_and_the_rules_differ():
+    pr = _tg()
+    assert _mixed_faces(pr) > 0
+    d = 0
+    a = D.global_solve(pr, d, q_iso=pr.q_iso)
+    b = D.global_solve(pr, d, q_iso=pr.q_iso, pointwise=True)
+    assert np.abs(a - b).max() > 1e-6 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("p,m", [(1, 2), (2, 2), (2, 3)])
+def test_lagged_pointwise_sweep_fixed_point(p, m):
+    """psi_prev = the dense pointwise solution: one lagged sweep returns it."""
+    pr = _tg(3, m, p)
+    assert O.lagged_couplings(pr, pointwise=True).sum() > 0
+    ref = np.stack([D.global_solve(pr, d, q_iso=pr.q_iso, pointwise=True) for d in range(pr.n_dir)])
+    out = O.sweep(pr, lag=True, pointwise=True, psi_prev=ref)
+    err = np.abs(out["psi"] - ref).max() / np.abs(ref).max()
+    assert err <= 1e-11, err
+
+
+def test_lagged_pointwise_sweeps_converge_to_global_solve_and_keep_balance():
+    pr = _tg(4, 3, 2, st=3.0)
+    ref = np.stack([D.global_solve(pr, d, q_iso=pr.q_iso, pointwise=True) for d in range(pr.n_dir)])
+    psi = np.zeros_like(ref)
+    for _ in range(60):
+        new = O.sweep(pr, lag=True, pointwise=True, psi_prev=psi)["psi"]
+        change = np.abs(new - psi).max()
+        psi = new
+        if change <= 1e-14 * np.abs(psi).max():
+            break
+    assert np.abs(psi - ref).max() <= 1e-11 * np.abs(ref).max()
+    for d in range(pr.n_dir):
+        res, scale = D.balance_residuals(pr, psi[d], d, q_iso=pr.q_iso, pointwise=True)
+        assert np.all(np.abs(res) <= 1e-11 * scale), d
+
+
+def _vef():
+    try:
+        from paper_2301_04758_amd import vef
+    except ImportError as e:
+        pytest.skip("library not built: %s" % e)
+    return vef
+
+
+def test_library_plan_lags_as_many_couplings_as_the_oracle():
+    """The library's plan under pointwise upwinding (host only): the same
+    number of lagged couplings as the oracle's order; without lagging a
+    mesh with mixed faces is rejected as cyclic; on a straight mesh the
+    plan is the whole-face plan."""
+    vef = _vef()
+    for pr in (_tg(3, 2, 2), _tg(4, 3, 2, N=6)):
+        want = int(O.lagged_couplings(pr, pointwise=True).sum())
+        assert want > 0
+        assert vef.vef_plan_query(pr, lag_cycles=True, pointwise=True)["n_lagged"] == want
+        with pytest.raises(vef.VefError) as e:
+            vef.vef_plan_query(pr, pointwise=True)
+        assert e.value.code == vef.VEF_ERR_CYCLE
+    pr = P.make_problem("straight", 6, 5, 2, 1, 6, 1.0, 0.5)
+    a, b = vef.vef_plan_query(pr), vef.vef_plan_query(pr, pointwise=True)
+    assert a["n_levels"] == b["n_levels"] and b["n_lagged"] == 0
