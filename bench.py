@@ -345,6 +345,26 @@ def outer_leg():
                           "rel_diff_vs_plain": diff}}
 
 
+def tdl_table(tol=1e-6):
+    """The thick-diffusion-limit experiment of Sec. 8 (its table of
+    fixed-point iteration counts): 8x8 orthogonal mesh of the unit square,
+    p = 2, S4, sigma_t = 1/eps, sigma_a = eps, q = eps, vacuum; plain fixed
+    point until the relative change of the VEF scalar flux is <= tol."""
+    from paper_2301_04758_amd import problems as P
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    out = {"workload": "8x8 unit square, p=2, S4, sigma_t=1/eps, sigma_a=eps, q=eps, vacuum; fixed point to a "
+                       "relative change of %g" % tol, "iterations": {}}
+    for eps in (1e-1, 1e-2, 1e-3, 1e-4):
+        pr = P.make_problem("tdl_8", 8, 8, 2, 1, 4, 1.0 / eps, 1.0 / eps - eps, q=eps)
+        drv = VefOuter(pr)
+        try:
+            r = drv.solve(max_outer=40, tol=tol)
+        finally:
+            drv.close()
+        out["iterations"]["%g" % eps] = r["iterations"]
+    return out
+
+
 def c4_batched(reps=3):
     """The 64-problem batch: plain FP64 level-synchronous sweeps one problem at
     a time, against all 64 in one FP32-local handle whose run is captured in a
@@ -516,6 +536,7 @@ def main():
         result["hrt_local_inverse"] = hrt_leg()
     if not args.no_outer:
         result["vef_outer_thick_limit"] = outer_leg()
+        result["vef_outer_thick_limit"]["eps_table"] = tdl_table()
     if not args.no_c4:
         result["c4_batched_fp32_vs_plain_fp64"] = c4_batched()
     if args.copy_calibration:

@@ -114,3 +114,25 @@ def test_anderson_outer_iteration_parity(torch):
     err = np.abs(out["phi_leg"] - ref[-1]).max() / np.abs(ref[-1]).max()
     print("anderson iteration %d rel err %.2e (bound %.1e)" % (n_outer, err, tol), flush=True)
     assert out["iterations"] == n_outer and err <= tol
+
+
+def test_thick_limit_iteration_counts_match_the_paper_table(torch):
+    """The GPU-driven fixed point on the paper's thick-diffusion-limit setup
+    (8x8 orthogonal mesh, p = 2, S4, relative change 1e-6): within one
+    iteration of the paper's HRT counts (tests/golden)."""
+    import os
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_tdl_iterations.txt")):
+        line = line.split("#")[0].split()
+        if line:
+            rows.append((float(line[0]), int(line[1])))
+    for eps, want in rows:
+        pr = P.make_problem("tdl_8", 8, 8, 2, 1, 4, 1.0 / eps, 1.0 / eps - eps, q=eps)
+        drv = VefOuter(pr)
+        try:
+            got = drv.solve(max_outer=want + 4, tol=1e-6)["iterations"]
+        finally:
+            drv.close()
+        print("eps %g: %d iterations (paper %d)" % (eps, got, want), flush=True)
+        assert abs(got - want) <= 1

@@ -210,3 +210,34 @@ def test_anderson_outer_iteration_converges_no_slower():
     kp, ka = first_below(plain), first_below(acc)
     assert kp is not None and ka is not None and ka <= kp, (kp, ka)
     assert np.abs(acc[ka - 1] - plain[-1]).max() <= 1e-7 * np.abs(plain[-1]).max()
+
+
+def _paper_tdl_table():
+    import os
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_tdl_iterations.txt")):
+        line = line.split("#")[0].split()
+        if line:
+            rows.append((float(line[0]), int(line[1])))
+    return rows
+
+
+def _tdl8(eps):
+    pr = P.make_problem("tdl_8", 8, 8, 2, 1, 4, 1.0 / eps, 1.0 / eps - eps, q=eps)
+    pr.nq = 4
+    return pr
+
+
+def test_thick_limit_iteration_counts_match_the_paper_table():
+    """The oracle's fixed point on the paper's thick-diffusion-limit setup
+    (8x8 orthogonal mesh, p = 2, S4) converges to a relative change of 1e-6
+    within one iteration of the paper's HRT counts (tests/golden)."""
+    for eps, want in _paper_tdl_table():
+        pr = _tdl8(eps)
+        hist = V.outer_iteration(pr, pr.nq, want + 2)
+        got = None
+        for k in range(1, len(hist)):
+            if np.abs(hist[k] - hist[k - 1]).max() <= 1e-6 * np.abs(hist[k]).max():
+                got = k + 1
+                break
+        assert got is not None and abs(got - want) <= 1, (eps, got, want)
