@@ -13,14 +13,17 @@
 //   G_ij = - sum_q w_q (grad vh_i : F^T E F^{-T}) uh_j
 //   D_ij = sum_q w_q uh_i div vh_j,   Ma_ij = sum_q w_q sigma_a J uh_i uh_j.
 // E = P / phi at each point from the transport moments (isotropic I/3 where
-// phi <= 0); E_b as given by the closures (1/2 where not positive).
+// phi <= 0); E_b as given by the closures (1/2 where not positive).  Only G
+// varies from point to point with E; the volume parts of A, D and Ma are
+// reference matrices (built on the host) scaled by the element's constants.
 //
 // The inverse is in-place Gauss-Jordan in natural order: the current
 // unknowns (A, symmetric positive definite for sigma_t > 0) are eliminated
 // first, then the Schur complement S = Ma - D A^{-1} G -- the block
 // elimination behind the formulas for W, X, Y, Z, which assume A and S
-// non-singular and allow a singular Ma.  The pivot row goes through LDS
-// (fully unrolled, so every index is a compile-time constant).
+// non-singular and allow a singular Ma.  Every lane reads the pivot row from
+// the pivot lane's registers (fully unrolled, so every index is a
+// compile-time constant).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -33,8 +36,8 @@ namespace {
 
 constexpr int kHrtWaves = 4;  // elements (waves) per work-group
 // Resident waves per SIMD the register allocation must allow (512 / w
-// VGPRs each): the elimination is a chain of LDS round trips and dependent
-// FMAs whose latency the other waves hide; the row of the block matrix
+// VGPRs each): the elimination is a chain of lane reads and dependent FMAs
+// whose latency the other waves hide; the row of the block matrix
 // (2 (p+1)(p+2) + (p+1)^2 doubles per lane) sets how many fit without spills.
 constexpr int hrt_waves_per_simd(int p) { return p == 1 ? 4 : p == 2 ? 3 : 2; }
 
