@@ -305,6 +305,35 @@ int vef_boundary_faces(const vef_sweep_t *h, int k, int32_t *out);
 int vef_hrt_local_inverse(vef_sweep_t *h, int k, const double *mom, const double *Eb, double *inv,
                           void *stream);
 
+/* Element-local part of the hybridized solve (Sec. 7, "Implementation
+ * Details": the reduced system H lambda = r for the face multipliers and the
+ * element-by-element recovery), for every element of problem k, on the
+ * device.  With the interior-face multiplier mu (Lagrange of degree p through
+ * the Gauss-Legendre points of the face, in the counter-clockwise parameter
+ * of its lower-numbered element) and per element K, slot s = (f, t) for node
+ * t of local face f:
+ *   C1[s][i] = int_F mu_t (v_i . n) ds,  C2[i][s] = int_F (v_i . <E n>) mu_t ds
+ *   (interior faces; <E n> the average of E n over the face's two sides, E =
+ *   P / phi from mom; zero on boundary faces),
+ *   g_i = int_K v_i . Q1 dx + sum over boundary faces
+ *         2 int_F (1/E_b)(v_i . E n) J_in ds,   f_j = int_K u_j Q0 dx
+ * (bases as vef_hrt_local_inverse) and, from inv = [[W, X], [Y, Z]]:
+ *   sol0 = inv [g; f],   resp = inv [C2; 0],
+ *   hloc = C1 W C2,   rloc = C1 (W g + X f),
+ * so that H = sum_K hloc, r = sum_K rloc (assembled by slot) and the
+ * element's [J; phi] = sol0 - resp lambda_K.
+ *   mom  device [6][n_elem][(p+1)^2]: moments of vef_sweep_run;
+ *   Eb, Jin, Q0, Q1  device: closures of vef_moments ([n_bf][nq], [n_bf][nq],
+ *        [n_elem][nq^2], [2][n_elem][nq^2]); Eb may be NULL (1/2);
+ *   inv  device [n_elem][n][n]: block inverses of vef_hrt_local_inverse;
+ *   hloc device out [n_elem][4(p+1)][4(p+1)], rloc [n_elem][4(p+1)],
+ *   sol0 device out [n_elem][n], resp [n_elem][n][4(p+1)].
+ * Requirements, asynchrony and errors as vef_hrt_local_inverse (Jin, Q0, Q1,
+ * inv and the outputs must not be NULL). */
+int vef_hrt_reduce(vef_sweep_t *h, int k, const double *mom, const double *Eb, const double *Jin,
+                   const double *Q0, const double *Q1, const double *inv, double *hloc, double *rloc,
+                   double *sol0, double *resp, void *stream);
+
 /* Measured machine figures (vef_probe_machine). */
 typedef struct {
   int compute_units;      /* of the current device */

@@ -712,17 +712,8 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   return VEF_OK;
 }
 
-int vef_hrt_local_inverse(vef_sweep_t *h, int k, const double *mom, const double *Eb, double *inv,
-                          void *stream) {
-  if (!h) return VEF_ERR_INVALID;
-  if (k < 0 || k >= (int)h->plans.size()) return set_err(h, VEF_ERR_INVALID, "problem index out of range");
-  if (!mom || !inv) return set_err(h, VEF_ERR_INVALID, "mom and inv are required");
+static int hrt_setup(vef_sweep_t *h, int k) {
   const auto &pl = h->plans[k];
-  if (!pl.affine) return set_err(h, VEF_ERR_INVALID, "HRT local blocks need affine elements");
-  vefplan::HrtSizes z;
-  if (vefplan::hrt_sizes(pl.p, pl.nq, z))
-    return set_err(h, VEF_ERR_INVALID, "HRT local blocks need p in 1..3 and nq = p + 2 or p + 3");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t he;
   // set-up on first use (not in a captured region): affine geometry in
   // double precision and the tables of (p, nq)
@@ -753,10 +744,52 @@ int vef_hrt_local_inverse(vef_sweep_t *h, int k, const double *mom, const double
     }
     h->hrt_tab[key] = d;
   }
+  return VEF_OK;
+}
+
+int vef_hrt_local_inverse(vef_sweep_t *h, int k, const double *mom, const double *Eb, double *inv,
+                          void *stream) {
+  if (!h) return VEF_ERR_INVALID;
+  if (k < 0 || k >= (int)h->plans.size()) return set_err(h, VEF_ERR_INVALID, "problem index out of range");
+  if (!mom || !inv) return set_err(h, VEF_ERR_INVALID, "mom and inv are required");
+  const auto &pl = h->plans[k];
+  if (!pl.affine) return set_err(h, VEF_ERR_INVALID, "HRT local blocks need affine elements");
+  vefplan::HrtSizes z;
+  if (vefplan::hrt_sizes(pl.p, pl.nq, z))
+    return set_err(h, VEF_ERR_INVALID, "HRT local blocks need p in 1..3 and nq = p + 2 or p + 3");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t he;
+  const int rs = hrt_setup(h, k);
+  if (rs != VEF_OK) return rs;
+  const auto key = std::make_pair(pl.p, pl.nq);
   vefk::HrtLaunch L{pl.p, pl.nq, pl.ne, h->hrt_tab[key], h->hrt_geo[k], h->h_probs[k].sig, h->h_probs[k].nbr,
                     mom, Eb, inv, s};
   he = vefk::launch_hrt_inverse(L);
   if (he != hipSuccess) return hip_fail(h, he, "launch HRT local inverse");
+  h->last_stream = s;
+  return VEF_OK;
+}
+
+int vef_hrt_reduce(vef_sweep_t *h, int k, const double *mom, const double *Eb, const double *Jin,
+                   const double *Q0, const double *Q1, const double *inv, double *hloc, double *rloc,
+                   double *sol0, double *resp, void *stream) {
+  if (!h) return VEF_ERR_INVALID;
+  if (k < 0 || k >= (int)h->plans.size()) return set_err(h, VEF_ERR_INVALID, "problem index out of range");
+  if (!mom || !Jin || !Q0 || !Q1 || !inv || !hloc || !rloc || !sol0 || !resp)
+    return set_err(h, VEF_ERR_INVALID, "mom, Jin, Q0, Q1, inv and the outputs are required");
+  const auto &pl = h->plans[k];
+  if (!pl.affine) return set_err(h, VEF_ERR_INVALID, "HRT local blocks need affine elements");
+  vefplan::HrtSizes z;
+  if (vefplan::hrt_sizes(pl.p, pl.nq, z))
+    return set_err(h, VEF_ERR_INVALID, "HRT local blocks need p in 1..3 and nq = p + 2 or p + 3");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int rs = hrt_setup(h, k);
+  if (rs != VEF_OK) return rs;
+  const auto key = std::make_pair(pl.p, pl.nq);
+  vefk::HrtReduceLaunch L{pl.p, pl.nq, pl.ne, h->hrt_tab[key], h->hrt_geo[k], h->h_probs[k].nbr,
+                          h->h_probs[k].nbr_face, mom, Eb, Jin, Q0, Q1, inv, hloc, rloc, sol0, resp, s};
+  const hipError_t he = vefk::launch_hrt_reduce(L);
+  if (he != hipSuccess) return hip_fail(h, he, "launch HRT reduction");
   h->last_stream = s;
   return VEF_OK;
 }

@@ -60,6 +60,8 @@ struct Hrt {
   static constexpr int OFF_MV = OFF_WF + NQ;
   static constexpr int OFF_DV = OFF_MV + NV * NV;
   static constexpr int OFF_MU = OFF_DV + NPHI * NV;
+  static constexpr int OFF_LF = OFF_MU + NPHI * NPHI;
+  static constexpr int OFF_LR = OFF_LF + NQ * (P + 1);
   static_assert(N <= 64, "one row per lane");
 };
 
@@ -261,6 +263,174 @@ k_hrt_inverse(const double *__restrict__ tab, const double *__restrict__ geo, co
   }
 }
 
+// Element-local part of the hybridized solve (Sec. 7): the couplings of the
+// element's current to the multipliers of its interior faces,
+//   C1[(f,t)][i] = int_F mu_t (v_i . n) ds,
+//   C2[i][(f,t)] = int_F (v_i . <E n>) mu_t ds   (<E n>: E n averaged over
+//                                                  the face's two sides),
+// the right-hand sides g_i = int v_i . Q1 + boundary faces
+// 2 int (1/E_b) (v_i . E n) J_in ds and f_j = int u_j Q0, and from the
+// block inverse inv = [[W, X], [Y, Z]]:
+//   sol0 = inv [g; f],  resp = inv [C2; 0]      (the element's [J; phi] is
+//                                                 sol0 - resp lambda),
+//   hloc = C1 resp_J = C1 W C2,  rloc = C1 sol0_J = C1 (W g + X f),
+// the element's contributions to H lambda = r.  One wave per element; lane i
+// owns test function i for C1, C2, g and f, and row i of the products.
+template <int P, int NQ>
+__global__ void __launch_bounds__(64 * kHrtWaves)
+k_hrt_reduce(const double *__restrict__ tab, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
+             const int8_t *__restrict__ nbr_face, const double *__restrict__ mom, const double *__restrict__ Eb,
+             const double *__restrict__ Jin, const double *__restrict__ Q0, const double *__restrict__ Q1, int ne,
+             const double *__restrict__ inv, double *__restrict__ hloc, double *__restrict__ rloc,
+             double *__restrict__ sol0, double *__restrict__ resp) {
+  using H = Hrt<P, NQ>;
+  constexpr int NX = H::NX, NV = H::NV, NPHI = H::NPHI, NT = H::NT, N = H::N, Q = H::Q, P1 = P + 1;
+  constexpr int NL = 4 * P1;  // multiplier slots of the element: (face, node)
+  __shared__ double sE[kHrtWaves][2][4][NQ][3];  // E at the face points: own side, other side
+  __shared__ double sB[kHrtWaves][N];             // [g; f]
+  __shared__ double sC1[kHrtWaves][NL][NV];
+  __shared__ double sC2[kHrtWaves][NV][NL];
+  __shared__ double sR[kHrtWaves][NV][NL];        // resp rows of the current unknowns
+  __shared__ double sS[kHrtWaves][NV];            // sol0 of the current unknowns
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * kHrtWaves + w;
+  if (e >= ne) return;  // whole waves only; the kernel has no work-group barrier
+  const double *g = geo + (size_t)e * 13;
+  const double J = g[0];
+  const double F00 = g[4], F01 = -g[2], F10 = -g[3], F11 = g[1];
+  const size_t ne_nt = (size_t)ne * NT;
+
+  // E at the face points, this element's side and the neighbour's (the
+  // neighbour runs the face the other way: its point NQ-1-q is point q here)
+  if (lane < 8 * NQ) {
+    const int side = lane / (4 * NQ), f = (lane / NQ) & 3, q = lane % NQ;
+    int el = e, ff = f, qq = q;
+    const int nb = nbr[4 * (size_t)e + f];
+    if (side == 1) {
+      if (nb >= 0) {
+        el = nb;
+        ff = nbr_face[4 * (size_t)e + f];
+        qq = NQ - 1 - q;
+      }
+    }
+    double exx, exy, eyy;
+    eddington_at<NT>(mom, ne_nt, (size_t)el * NT, tab + H::OFF_TF + (ff * NQ + qq) * NT, exx, exy, eyy);
+    sE[w][side][f][q][0] = exx;
+    sE[w][side][f][q][1] = exy;
+    sE[w][side][f][q][2] = eyy;
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  const int r = lane;
+  const bool cur = r < NV;
+  const int rc = r < NX ? 0 : 1;  // non-zero component of v_r
+  const int rv = cur ? r : 0;
+  // (F^T a)_c / J for the component c of v_r: v_r . a = vhat_r (F^T a)_c / J
+  auto ft = [&](double ax, double ay) { return (rc == 0 ? F00 * ax + F10 * ay : F01 * ax + F11 * ay) / J; };
+  double bval = 0.0;
+  if (cur) {
+    // volume: g_r = sum_q w_q vhat_r(q) (F^T Q1_q)_c
+    for (int q = 0; q < Q; ++q) {
+      const double qx = Q1[(size_t)e * Q + q], qy = Q1[((size_t)ne + e) * Q + q];
+      bval += tab[H::OFF_W + q] * tab[H::OFF_VR + q * NV + rv] * (rc == 0 ? F00 * qx + F10 * qy : F01 * qx + F11 * qy);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const double cx = g[5 + 2 * f], cy = g[6 + 2 * f];
+      const double len = sqrt(cx * cx + cy * cy), nx = cx / len, ny = cy / len;
+      const int nb = nbr[4 * (size_t)e + f];
+      double c1[P1], c2[P1];
+#pragma unroll
+      for (int t = 0; t < P1; ++t) c1[t] = c2[t] = 0.0;
+      if (nb >= 0) {
+        const double *lam = tab + (e < nb ? H::OFF_LF : H::OFF_LR);
+        const double vn = ft(nx, ny);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const double wv = tab[H::OFF_WF + q] * len * tab[H::OFF_VRF + (f * NQ + q) * NV + rv];
+          const double *a = sE[w][0][f][q], *b = sE[w][1][f][q];
+          const double exx = 0.5 * (a[0] + b[0]), exy = 0.5 * (a[1] + b[1]), eyy = 0.5 * (a[2] + b[2]);
+          const double ven = ft(exx * nx + exy * ny, exy * nx + eyy * ny);
+#pragma unroll
+          for (int t = 0; t < P1; ++t) {
+            c1[t] += wv * lam[q * P1 + t] * vn;
+            c2[t] += wv * lam[q * P1 + t] * ven;
+          }
+        }
+      } else {
+        const int bf = -nb - 1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const double eb0 = Eb ? Eb[(size_t)bf * NQ + q] : 0.5;
+          const double eb = eb0 > 0.0 ? eb0 : 0.5;
+          const double *a = sE[w][0][f][q];
+          const double ven = ft(a[0] * nx + a[1] * ny, a[1] * nx + a[2] * ny);
+          bval += 2.0 * tab[H::OFF_WF + q] * len / eb * tab[H::OFF_VRF + (f * NQ + q) * NV + rv] * ven *
+                  Jin[(size_t)bf * NQ + q];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < P1; ++t) {
+        sC1[w][f * P1 + t][rv] = c1[t];
+        sC2[w][rv][f * P1 + t] = c2[t];
+      }
+    }
+  } else if (r < N) {
+    // f_j = sum_q w_q J Q0_q u_j(q)
+    const int j = r - NV;
+    for (int q = 0; q < Q; ++q) bval += tab[H::OFF_W + q] * J * Q0[(size_t)e * Q + q] * tab[H::OFF_U + q * NPHI + j];
+  }
+  if (r < N) sB[w][r] = bval;
+  __builtin_amdgcn_wave_barrier();
+
+  // row r of sol0 = inv [g; f] and of resp = inv [C2; 0]
+  if (r < N) {
+    const double *ir = inv + ((size_t)e * N + r) * N;
+    double s0 = 0.0, rr[NL];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) rr[a] = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const double x = ir[j];
+      s0 += x * sB[w][j];
+      if (j < NV) {
+#pragma unroll
+        for (int a = 0; a < NL; ++a) rr[a] += x * sC2[w][j][a];
+      }
+    }
+    sol0[(size_t)e * N + r] = s0;
+#pragma unroll
+    for (int a = 0; a < NL; ++a) resp[((size_t)e * N + r) * NL + a] = rr[a];
+    if (r < NV) {
+      sS[w][r] = s0;
+#pragma unroll
+      for (int a = 0; a < NL; ++a) sR[w][r][a] = rr[a];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  // hloc = C1 resp_J, rloc = C1 sol0_J
+  for (int idx = lane; idx < NL * NL + NL; idx += 64) {
+    const int a = idx < NL * NL ? idx / NL : idx - NL * NL;
+    const int b = idx < NL * NL ? idx % NL : -1;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc += sC1[w][a][i] * (b >= 0 ? sR[w][i][b] : sS[w][i]);
+    if (b >= 0)
+      hloc[((size_t)e * NL + a) * NL + b] = acc;
+    else
+      rloc[(size_t)e * NL + a] = acc;
+  }
+}
+
+template <int P, int NQ>
+hipError_t launch_reduce_t(const HrtReduceLaunch &L) {
+  const int grid = (L.ne + kHrtWaves - 1) / kHrtWaves;
+  hipLaunchKernelGGL((k_hrt_reduce<P, NQ>), dim3(grid), dim3(64 * kHrtWaves), 0, L.stream, L.tab, L.geo, L.nbr,
+                     L.nbr_face, L.mom, L.Eb, L.Jin, L.Q0, L.Q1, L.ne, L.inv, L.hloc, L.rloc, L.sol0, L.resp);
+  return hipGetLastError();
+}
+
 template <int P, int NQ>
 hipError_t launch_hrt_t(const HrtLaunch &L) {
   const int grid = (L.ne + kHrtWaves - 1) / kHrtWaves;
@@ -270,6 +440,19 @@ hipError_t launch_hrt_t(const HrtLaunch &L) {
 }
 
 }  // namespace
+
+hipError_t launch_hrt_reduce(const HrtReduceLaunch &L) {
+  if (L.ne <= 0) return hipSuccess;
+  switch (L.p * 16 + L.nq) {
+    case 1 * 16 + 3: return launch_reduce_t<1, 3>(L);
+    case 1 * 16 + 4: return launch_reduce_t<1, 4>(L);
+    case 2 * 16 + 4: return launch_reduce_t<2, 4>(L);
+    case 2 * 16 + 5: return launch_reduce_t<2, 5>(L);
+    case 3 * 16 + 5: return launch_reduce_t<3, 5>(L);
+    case 3 * 16 + 6: return launch_reduce_t<3, 6>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_hrt_inverse(const HrtLaunch &L) {
   if (L.ne <= 0) return hipSuccess;

@@ -105,4 +105,18 @@ struct HrtLaunch {
 };
 hipError_t launch_hrt_inverse(const HrtLaunch &L);
 
+// Element-local part of the hybridized solve (couplings to the face
+// multipliers, right-hand sides, the element's H and r contributions and the
+// pieces of its recovery), from the block inverses of launch_hrt_inverse.
+struct HrtReduceLaunch {
+  int p, nq, ne;
+  const double *tab, *geo;
+  const int32_t *nbr;
+  const int8_t *nbr_face;
+  const double *mom, *Eb, *Jin, *Q0, *Q1, *inv;
+  double *hloc, *rloc, *sol0, *resp;
+  hipStream_t stream;
+};
+hipError_t launch_hrt_reduce(const HrtReduceLaunch &L);
+
 }  // namespace vefk

@@ -262,7 +262,9 @@ int hrt_sizes(int p, int nq, HrtSizes &z) {
   z.off_mv = z.off_wf + nq;               // [nv][nv] sum_q w vr_i vr_j
   z.off_dv = z.off_mv + z.nv * z.nv;      // [nphi][nv] sum_q w u_i div vr_j
   z.off_mu = z.off_dv + z.nphi * z.nv;    // [nphi][nphi] sum_q w u_i u_j
-  z.total = z.off_mu + z.nphi * z.nphi;
+  z.off_lf = z.off_mu + z.nphi * z.nphi;  // [nq][p+1] face multiplier basis at the Gauss points
+  z.off_lr = z.off_lf + nq * (p + 1);     // [nq][p+1] the same at 1 - (Gauss points)
+  z.total = z.off_lr + nq * (p + 1);
   return VEF_OK;
 }
 
@@ -337,6 +339,18 @@ int build_hrt_tables(int p, int nq, std::vector<double> &blob) {
       tensor(lob, x, y, &blob[z.off_tf + ((size_t)f * nq + q) * z.nt]);
     }
   for (int q = 0; q < nq; ++q) blob[z.off_wf + q] = gw[q];
+  // The interior-face multiplier: Lagrange of degree p through the
+  // Gauss-Legendre points of the face, in the counter-clockwise parameter of
+  // the face's lower-numbered element (its other element sees 1 - s).
+  {
+    std::vector<double> v, dv;
+    for (int q = 0; q < nq; ++q) {
+      eval(leg, gx[q], v, dv);
+      for (int t = 0; t <= p; ++t) blob[z.off_lf + (size_t)q * (p + 1) + t] = v[t];
+      eval(leg, 1.0 - gx[q], v, dv);
+      for (int t = 0; t <= p; ++t) blob[z.off_lr + (size_t)q * (p + 1) + t] = v[t];
+    }
+  }
   // Reference matrices of the element-independent parts of the affine
   // blocks: the RT mass of the non-zero components (A = sigma_t / J
   // (F^T F)_{c_i c_j} times it), D, and the Q_p mass (Ma = sigma_a J times it).

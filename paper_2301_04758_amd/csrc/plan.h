@@ -79,7 +79,7 @@ int build_tables(int p, int nq, Tables &t);
 struct HrtSizes {
   int p = 0, nq = 0, nx = 0, nv = 0, nphi = 0, nt = 0;
   int off_w = 0, off_vr = 0, off_dr = 0, off_u = 0, off_tv = 0, off_vrf = 0, off_tf = 0, off_wf = 0;
-  int off_mv = 0, off_dv = 0, off_mu = 0, total = 0;
+  int off_mv = 0, off_dv = 0, off_mu = 0, off_lf = 0, off_lr = 0, total = 0;
 };
 int hrt_sizes(int p, int nq, HrtSizes &z);
 int build_hrt_tables(int p, int nq, std::vector<double> &blob);

@@ -41,7 +41,7 @@ KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KE
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
-            "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_last_error",
+            "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_hrt_reduce", "vef_last_error",
             "vef_status_string")
 
 
@@ -104,13 +104,14 @@ def _load():
     L.vef_sweep_autotune.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p, C.c_int, C.c_void_p]
     L.vef_probe_machine.argtypes = [C.c_void_p, C.c_void_p]
     L.vef_hrt_local_inverse.argtypes = [H, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.vef_hrt_reduce.argtypes = [H, C.c_int] + [C.c_void_p] * 11
     L.vef_last_error.argtypes = [H]
     L.vef_last_error.restype = C.c_char_p
     L.vef_status_string.argtypes = [C.c_int]
     L.vef_status_string.restype = C.c_char_p
     for f in ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
               "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
-              "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse"):
+              "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_hrt_reduce"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -278,6 +279,15 @@ def vef_hrt_local_inverse(h: int, k: int, mom, Eb, inv, stream=None):
         raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
 
 
+def vef_hrt_reduce(h: int, k: int, mom, Eb, Jin, Q0, Q1, inv, hloc, rloc, sol0, resp, stream=None):
+    """Device pointers (int) or torch tensors; see include/vef_sweep.h."""
+    rc = lib.vef_hrt_reduce(C.c_void_p(h), int(k), *[C.c_void_p(_ptr(x)) for x in
+                                                     (mom, Eb, Jin, Q0, Q1, inv, hloc, rloc, sol0, resp)],
+                            C.c_void_p(_stream_handle(stream)))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+
+
 def vef_sweep_check(h: int):
     rc = lib.vef_sweep_check(C.c_void_p(h))
     if rc != VEF_OK:
@@ -369,6 +379,23 @@ class Sweep:
         mom = mom.contiguous()
         Eb = None if Eb is None else Eb.contiguous()
         vef_hrt_local_inverse(self.h, k, mom, Eb, out, stream)
+        return out
+
+    def hrt_reduce(self, k, mom, mio, inv, stream=None):
+        """Element-local part of the hybridized solve (vef_hrt_reduce) from the
+        run's moments, the closures of moment_buffers()[k] and the block
+        inverses: dict of tensors hloc [n_elem, 4(p+1), 4(p+1)], rloc
+        [n_elem, 4(p+1)], sol0 [n_elem, n], resp [n_elem, n, 4(p+1)]."""
+        t = self.torch
+        pr = self.problems[k]
+        p = pr.p
+        n = 2 * (p + 1) * (p + 2) + (p + 1) ** 2
+        nl = 4 * (p + 1)
+        kw = dict(dtype=t.float64, device=self.device)
+        out = dict(hloc=t.empty((pr.n_elem, nl, nl), **kw), rloc=t.empty((pr.n_elem, nl), **kw),
+                   sol0=t.empty((pr.n_elem, n), **kw), resp=t.empty((pr.n_elem, n, nl), **kw))
+        vef_hrt_reduce(self.h, k, mom.contiguous(), mio["Eb"], mio["Jin"], mio["Q0"], mio["Q1"], inv.contiguous(),
+                       out["hloc"], out["rloc"], out["sol0"], out["resp"], stream)
         return out
 
     def check(self):

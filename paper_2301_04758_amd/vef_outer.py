@@ -122,13 +122,14 @@ class _Ref:
 class VefOuter:
     """Transport + HRT VEF outer iteration for one affine problem."""
 
-    def __init__(self, problem, nq=None, precision="fp64"):
+    def __init__(self, problem, nq=None, precision="fp64", device_reduce=True):
         p = problem.p
         if nq is None:
             nq = p + 2
         problem.nq = nq
         self.pr = problem
         self.ref = _Ref(p, nq)
+        self.device_reduce = device_reduce
         self.sw = vef.Sweep([problem], precision=precision)
         import scipy.sparse  # noqa: F401  (after the device is set up; fail early if missing)
         if not self.sw.info[0]["affine"]:
@@ -142,6 +143,7 @@ class VefOuter:
         """The host stage alone (host_stage), with no device handle: for
         driving it from closures and block inverses computed elsewhere."""
         self = cls.__new__(cls)
+        self.device_reduce = False
         problem.nq = nq or problem.p + 2
         self.pr = problem
         self.ref = _Ref(problem.p, problem.nq)
@@ -223,20 +225,27 @@ class VefOuter:
         t0 = time.perf_counter()
         d = self._device_stage(phi_lob)
         t1 = time.perf_counter()
-        out = self.host_stage(**d)
+        out = self._solve_reduced(**d) if "hloc" in d else self.host_stage(**d)
         # wall time of the device part (sweep, closures, block inverses and
         # their copies to the host) and of the host part
         self.last_times = dict(device_s=t1 - t0, host_s=time.perf_counter() - t1)
         return out
 
     def _device_stage(self, phi_lob):
-        """Sweep, closures and block inverses on the GPU, copied to the host."""
+        """Sweep, closures and block inverses on the GPU, and with
+        device_reduce the element-local reduction too (vef_hrt_reduce);
+        copied to the host."""
         import torch
         io = self.sw.buffers(n_iter=1, store_psi=False, phi_in=phi_lob)
         self.sw.run(io, n_iter=1)
         mio = self.sw.moment_buffers(io)
         self.sw.moments(mio)
         inv = self.sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"])
+        if self.device_reduce:
+            red = self.sw.hrt_reduce(0, io[0]["mom"], mio[0], inv)
+            torch.cuda.synchronize()
+            self.sw.check()
+            return {k: v.cpu().numpy() for k, v in red.items()}
         torch.cuda.synchronize()
         self.sw.check()
         inv = inv.cpu().numpy()
@@ -289,7 +298,7 @@ class VefOuter:
                 FtEn = np.einsum("ekl,eqkm,em->eql", self.F[e], E[e], n[e])
                 c = (2.0 * w[e] / eb * Jin[k] * Jinv[e][:, None])[:, :, None]
                 g[e] += (c * FtEn).reshape(len(e), -1) @ R
-            Ftn = np.einsum("ekl,ek->el", self.F, n) * Jinv[:, None]
+            Ftn = np.einsum("ekl,ek->el", self.F, n)  # (the 1 / J is in lam below)
             for f2 in range(4):
                 sel = (~bnd) & (self.nbr_face[:, f] == f2)
                 if not sel.any():
@@ -304,9 +313,22 @@ class VefOuter:
                 C2[e, :, f * P1:(f + 1) * P1] = np.matmul(R.T[None], T)
                 U = (lam[:, :, None, :] * Ftn[e][:, None, :, None]).reshape(len(e), -1, P1)
                 C1[e, f * P1:(f + 1) * P1, :] = np.matmul(U.transpose(0, 2, 1), R[None])
-        W_, X_ = inv[:, :nv, :nv], inv[:, :nv, nv:]
-        Hloc = np.matmul(np.matmul(C1, W_), C2)
-        rloc = np.matmul(C1, (np.matmul(W_, g[:, :, None]) + np.matmul(X_, fr[:, :, None])))[:, :, 0]
+        # sol0 = inv [g; f], resp = inv [C2; 0]: the element's [J; phi] is
+        # sol0 - resp lambda; H and r collect C1 W C2 and C1 (W g + X f)
+        sol0 = np.matmul(inv, np.concatenate([g, fr], axis=1)[:, :, None])[:, :, 0]
+        resp = np.matmul(inv[:, :, :nv], C2)
+        return self._solve_reduced(hloc=np.matmul(C1, resp[:, :nv]), rloc=np.matmul(C1, sol0[:, :nv, None])[:, :, 0],
+                                   sol0=sol0, resp=resp)
+
+    def _solve_reduced(self, hloc, rloc, sol0, resp):
+        """Assemble H lambda = r from the elements' hloc [ne, 4(p+1), 4(p+1)]
+        and rloc [ne, 4(p+1)] by interior-face slot, solve it (scipy sparse
+        LU), and recover [J; phi] = sol0 - resp lambda per element."""
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spl
+        pr, ref = self.pr, self.ref
+        ne, P1, nv = pr.n_elem, pr.p + 1, ref.nv
+        Hloc, rloc = hloc, rloc
         gidx = (self.face_id[:, :, None] * P1 + np.arange(P1)[None, None, :]).reshape(ne, 4 * P1)
         ok = gidx >= 0
         rows = np.repeat(gidx[:, :, None], 4 * P1, axis=2)
@@ -318,8 +340,7 @@ class VefOuter:
         np.add.at(rhs, gidx[ok], rloc[ok])
         lam_g = spl.spsolve(H.tocsc(), rhs, permc_spec="MMD_AT_PLUS_A") if nl else np.zeros(0)
         lam_loc = np.where(ok, lam_g[np.where(ok, gidx, 0)] if nl else 0.0, 0.0)
-        top = g - np.einsum("eit,et->ei", C2, lam_loc)
-        sol = np.matmul(inv, np.concatenate([top, fr], axis=1)[:, :, None])[:, :, 0]
+        sol = sol0 - np.matmul(resp, lam_loc[:, :, None])[:, :, 0]
         Jc, phi_leg = sol[:, :nv], sol[:, nv:]
         phi_lob = phi_leg @ ref.leg_at_lob.T
         return phi_lob, phi_leg, Jc

@@ -49,6 +49,22 @@ def _sheared(n, p, seed=3):
     return pr
 
 
+def _graded(n, p, seed=4):
+    """Rectangles of different sizes, sheared: the Jacobian varies from
+    element to element."""
+    cp, ec = P.quad_mesh(n, n, 1)
+    cp = cp.copy()
+    cp[:, 0] = cp[:, 0] ** 1.7
+    cp[:, 1] = 0.5 * (cp[:, 1] + cp[:, 1] ** 2)
+    cp = cp @ np.array([[1.3, 0.2], [0.1, 1.0]]).T
+    om, wt = P.level_symmetric_2d(4)
+    ne = ec.shape[0]
+    st = np.random.default_rng(seed).uniform(1.0, 20.0, ne)
+    pr = P.Problem("graded", p, 1, cp, ec, om, wt, st, 0.9 * st, nx=n, ny=n, nq=p + 2)
+    pr.q_iso = np.ones((ne, (p + 1) ** 2))
+    return pr
+
+
 def _kappa(pr):
     nq = pr.nq
     r = O.sweep(pr, want_psi=False, nq=nq)
@@ -65,11 +81,11 @@ def _kappa(pr):
     return float(np.linalg.cond(d["M"]))
 
 
-@pytest.mark.parametrize("case", ["tdl_p1", "tdl_p2", "sheared_p2"])
+@pytest.mark.parametrize("case", ["tdl_p1", "tdl_p2", "sheared_p2", "graded_p2"])
 def test_outer_iteration_parity(torch, case):
     from paper_2301_04758_amd.vef_outer import VefOuter
     pr = {"tdl_p1": lambda: _tdl(8, 1, 1e-2), "tdl_p2": lambda: _tdl(6, 2, 1e-3),
-          "sheared_p2": lambda: _sheared(6, 2)}[case]()
+          "sheared_p2": lambda: _sheared(6, 2), "graded_p2": lambda: _graded(6, 2)}[case]()
     n_outer = 4
     ref = V.outer_iteration(pr, pr.nq, n_outer)
     tol = max(1e-12, 64 * np.finfo(float).eps * _kappa(pr))
@@ -136,3 +152,37 @@ def test_thick_limit_iteration_counts_match_the_paper_table(torch):
             drv.close()
         print("eps %g: %d iterations (paper %d)" % (eps, got, want), flush=True)
         assert abs(got - want) <= 1
+
+
+@pytest.mark.parametrize("case", ["tdl_p1", "sheared_p2", "graded_p2"])
+def test_device_reduction_matches_host_reduction(torch, case):
+    """vef_hrt_reduce (the element-local reduction on the GPU) against the
+    host's numpy reduction of the same closures and block inverses, and the
+    outer iterates of the two paths."""
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    pr = {"tdl_p1": lambda: _tdl(8, 1, 1e-2), "sheared_p2": lambda: _sheared(6, 2),
+          "graded_p2": lambda: _graded(6, 2)}[case]()
+    drv = VefOuter(pr, device_reduce=True)
+    try:
+        drv.device_reduce = False
+        d = drv._device_stage(None)
+        drv.device_reduce = True
+        red = drv._device_stage(None)
+        captured = {}
+        orig = drv._solve_reduced
+
+        def grab(**kw):
+            captured.update(kw)
+            return orig(**kw)
+
+        drv._solve_reduced = grab
+        host = drv.host_stage(**d)
+        for key in ("hloc", "rloc", "sol0", "resp"):
+            ref = captured[key]
+            err = np.abs(red[key] - ref).max() / max(np.abs(ref).max(), 1e-300)
+            print(case, key, "rel err %.2e" % err, flush=True)
+            assert err <= 1e-12, key
+        dev = orig(**red)
+        assert np.abs(dev[1] - host[1]).max() <= 1e-12 * np.abs(host[1]).max()
+    finally:
+        drv.close()

@@ -27,8 +27,14 @@ def _problem(case):
                        nx=n, ny=n, nq=p + 2)
         pr.q_iso = np.full((ne, (p + 1) ** 2), eps / (4 * math.pi))
         return pr
-    n, p = (4, 2) if case == "sheared_p2" else (3, 3)
+    n, p = (4, 2) if case in ("sheared_p2", "graded_p2") else (3, 3)
     cp, ec = P.quad_mesh(n, n, 1)
+    if case == "graded_p2":
+        # rectangles of different sizes (the Jacobian varies from element to
+        # element), then sheared
+        cp = cp.copy()
+        cp[:, 0] = cp[:, 0] ** 1.7
+        cp[:, 1] = 0.5 * (cp[:, 1] + cp[:, 1] ** 2)
     cp = cp @ np.array([[1.4, 0.3], [0.1, 1.0]]).T
     om, wt = P.level_symmetric_2d(6)
     ne = ec.shape[0]
@@ -39,7 +45,7 @@ def _problem(case):
     return pr
 
 
-@pytest.mark.parametrize("case", ["tdl_p1", "sheared_p2", "sheared_p3"])
+@pytest.mark.parametrize("case", ["tdl_p1", "sheared_p2", "sheared_p3", "graded_p2"])
 def test_host_stage_matches_global_solve(case):
     pr = _problem(case)
     nq = pr.nq
