@@ -24,8 +24,12 @@ from oracle import vef_outer_oracle as V
 from paper_2301_04758_amd import problems as P
 
 
-def _sheared(n, p, st=2.0, sa=0.3, nq=None):
+def _sheared(n, p, st=2.0, sa=0.3, nq=None, graded=False):
     cp, ec = P.quad_mesh(n, n, 1)
+    if graded:  # rectangles of different sizes: the Jacobian varies by element
+        cp = cp.copy()
+        cp[:, 0] = cp[:, 0] ** 1.7
+        cp[:, 1] = 0.5 * (cp[:, 1] + cp[:, 1] ** 2)
     cp = cp @ np.array([[1.3, 0.3], [0.15, 1.0]]).T + np.array([0.5, 0.25])
     om, wt = P.level_symmetric_2d(4)
     ne = ec.shape[0]
@@ -63,11 +67,12 @@ def _linear_case(pr, E0, c0=0.8, c=(0.25, -0.4)):
     return out, Jex, c0, c, x0, F
 
 
+@pytest.mark.parametrize("graded", [False, True])
 @pytest.mark.parametrize("E0", [((1 / 3, 0), (0, 1 / 3)), ((0.45, 0.1), (0.1, 0.3))])
 @pytest.mark.parametrize("p", [1, 2])
-def test_global_solve_reproduces_linear_solution(p, E0):
+def test_global_solve_reproduces_linear_solution(p, E0, graded):
     E0 = np.array(E0, float)
-    pr = _sheared(3, p)
+    pr = _sheared(3, p, graded=graded)
     out, Jex, c0, c, x0, F = _linear_case(pr, E0)
     leg = H.legendre_points(p + 1)
     LX, LY = np.meshgrid(leg, leg, indexing="xy")
