@@ -492,13 +492,18 @@ def main():
     sweeps_per_launch = solves_per_launch / sum(p.n_elem * p.n_dir for p in probs)
     t_bw = B * solves_per_launch / (HBM_PEAK_GBS * 1e9)
     t_flop = F * solves_per_launch / (FP64_PEAK_TFLOPS * 1e12)
+    # the chain of dependent levels can go no faster than one measured
+    # wave-to-wave hand-off per level (vef_probe_machine)
+    t_cp = g64["n_levels"] * sweeps_per_launch * machine["lds_handoff_ns"] * 1e-9
     roofline = {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": measured_traffic(kname),
                 "kernel": kname, "avg_launch_us": avg_launch_s * 1e6,
                 "levels_per_sweep": g64["n_levels"],
                 "us_per_level": avg_launch_s * 1e6 / (g64["n_levels"] * sweeps_per_launch),
-                "lower_bounds_us": {"hbm": t_bw * 1e6, "fp64_alu": t_flop * 1e6},
+                "lower_bounds_us": {"hbm": t_bw * 1e6, "fp64_alu": t_flop * 1e6,
+                                    "critical_path_handoff": t_cp * 1e6},
                 "binding": "critical path: %d dependent upwind levels per sweep" % g64["n_levels"],
+                "frac_of_critical_path_bound": t_cp / avg_launch_s,
                 "measured_peak": machine["fp64_fma_tflops"],
                 "frac_of_measured_peak": achieved_tf / machine["fp64_fma_tflops"],
                 "launches_per_step": launches / n_timed * n_iter,
