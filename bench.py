@@ -303,7 +303,16 @@ def hrt_leg(reps=5):
                      "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                   "frac": tf / FP64_PEAK_TFLOPS, "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                                   "algorithmic_flops_per_element": F, "algorithmic_bytes_per_element": B}}
-        del inv
+        # the element-local reduction of the hybridized solve from these inverses
+        red = sw.hrt_reduce(0, io[0]["mom"], mio[0], inv)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            sw.hrt_reduce(0, io[0]["mom"], mio[0], inv)
+        b.record()
+        torch.cuda.synchronize()
+        out[name]["reduce_ms_per_launch"] = a.elapsed_time(b) / reps
+        del inv, red
         sw.close()
         del io, mio
     return out

@@ -123,3 +123,38 @@ def test_hrt_inverse_rejects(torch):
         assert "affine" in str(e.value)
     finally:
         sw.close()
+
+
+def test_hrt_reduce_rejects(torch):
+    """vef_hrt_reduce: missing closures or outputs, a bad problem index and a
+    curved problem fail with VEF_ERR_INVALID before any launch."""
+    from paper_2301_04758_amd import vef
+    pr = _sheared(3, 2, 4)
+    sw, io, mio = _moments(torch, pr)
+    try:
+        inv = sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"])
+        out = sw.hrt_reduce(0, io[0]["mom"], mio[0], inv)  # a valid call first
+        torch.cuda.synchronize()
+        assert torch.isfinite(out["hloc"]).all()
+        for bad in ("Jin", "Q0", "Q1"):
+            m = dict(mio[0])
+            m[bad] = None
+            with pytest.raises(vef.VefError) as e:
+                sw.hrt_reduce(0, io[0]["mom"], m, inv)
+            assert e.value.code == vef.VEF_ERR_INVALID, bad
+        with pytest.raises(vef.VefError) as e:
+            vef.vef_hrt_reduce(sw.h, 5, io[0]["mom"], None, mio[0]["Jin"], mio[0]["Q0"], mio[0]["Q1"], inv,
+                               out["hloc"], out["rloc"], out["sol0"], out["resp"])
+        assert e.value.code == vef.VEF_ERR_INVALID
+    finally:
+        sw.close()
+    pr = P.make_problem("curved", 3, 3, 1, 2, 4, 1.0, 0.5, warp=0.1)
+    pr.nq = 3
+    sw, io, mio = _moments(torch, pr)
+    try:
+        z = torch.zeros(1, dtype=torch.float64, device="cuda")
+        with pytest.raises(vef.VefError) as e:
+            vef.vef_hrt_reduce(sw.h, 0, io[0]["mom"], None, mio[0]["Jin"], mio[0]["Q0"], mio[0]["Q1"], z, z, z, z, z)
+        assert "affine" in str(e.value)
+    finally:
+        sw.close()
