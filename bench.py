@@ -114,7 +114,7 @@ def measured_traffic(kernel):
     or None when the kernel differs or its sources changed since then."""
     import hashlib
     import re
-    if kernel != "k_sweep_pipe<2, 3, double, false>" or not os.path.exists(PROFILE):
+    if kernel != "k_sweep_pipe<2, 3, double, false, false>" or not os.path.exists(PROFILE):
         return None
     text = open(PROFILE).read()
     m = re.search(r"traffic_bytes_per_launch=([0-9.e+]+) kernel_sources_sha256_16=([0-9a-f]+)", text)
@@ -130,8 +130,8 @@ def measured_traffic(kernel):
 def kernel_name(g, pr):
     """Name of the sweep kernel that ran (as the profiler lists it)."""
     nq = pr.nq or pr.p + pr.m
-    if g["schedule"] == "dir_resident" and g["kernel"] == 3:
-        return "k_sweep_pipe<%d, %d, double, false>" % (pr.p, nq)
+    if g["schedule"] == "dir_resident" and g["kernel"] in (3, 4):
+        return "k_sweep_pipe<%d, %d, double, false, %s>" % (pr.p, nq, "true" if g["kernel"] == 4 else "false")
     kind = "dir" if g["schedule"] == "dir_resident" else "level"
     return "k_sweep_%s<%d, %d, double, %d>" % (kind, pr.p, nq, g["kernel"])
 

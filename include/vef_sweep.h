@@ -234,6 +234,9 @@ typedef struct {
 #define VEF_KERNEL_AFFINE_PIPELINE 3 /* element per lane, LU ahead of the
                                        upwind data (direction-resident,
                                        affine, p <= 2) */
+#define VEF_KERNEL_BILINEAR_PIPELINE 4 /* the same for straight-sided
+                                       bilinear elements (m = 1), volume
+                                       terms by quadrature */
 
 /* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
  * upwind graphs unless opt->cycles lags them), build the sweep plan on the host and upload it to the

@@ -35,10 +35,14 @@ struct Variant {
   }
 };
 
-int mode_of(const vefplan::ProblemPlan &pl, int schedule, bool pipeline = true) {
+int mode_of(const vefplan::ProblemPlan &pl, int schedule, bool pipeline = true, bool fixup = false) {
   if (!pl.nopivot) return 0;
-  if (!pl.affine) return 1;
-  return (pipeline && schedule == VEF_DIR_RESIDENT && pl.p <= 2 && pl.n_lagged == 0) ? 3 : 2;
+  const bool pipe = pipeline && schedule == VEF_DIR_RESIDENT && pl.p <= 2;
+  // straight-sided bilinear elements: the pipelined kernel with quadrature
+  // assembly (lagged couplings read the previous sweep from global memory);
+  // its fixup would need the balance weights at the quadrature points
+  if (!pl.affine) return (pipe && pl.m == 1 && !fixup) ? 4 : 1;
+  return (pipe && pl.n_lagged == 0) ? 3 : 2;
 }
 
 struct LevelLaunch {
@@ -54,6 +58,7 @@ struct DirLaunch {  // one direction-resident launch: all (problem, direction) p
   int max_levels;  // deepest level count among them
   int max_gap;     // largest upwind level gap among them
   const void *tab;
+  const void *tab_g;  // general tables of (p, nq)
 };
 
 }  // namespace
@@ -338,7 +343,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     bool narrow = true;
     for (auto &pl : h->plans) {
       const double width = (double)pl.ne / pl.n_levels;
-      if (mode_of(pl, VEF_DIR_RESIDENT, h->pipeline_waves >= 0) == 3) {
+      if (mode_of(pl, VEF_DIR_RESIDENT, h->pipeline_waves >= 0, h->fixup) >= 3) {
         if (width > 256.0) narrow = false;
         continue;
       }
@@ -358,7 +363,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     std::map<Variant, int> vs;
     for (auto &pl : h->plans) {
       vs[Variant{pl.p, pl.nq, mode_of(pl, VEF_DIR_RESIDENT, false)}] = 1;
-      vs[Variant{pl.p, pl.nq, mode_of(pl, VEF_DIR_RESIDENT, true)}] = 1;
+      vs[Variant{pl.p, pl.nq, mode_of(pl, VEF_DIR_RESIDENT, true, h->fixup)}] = 1;
     }
     for (auto &kv : vs) variants.push_back(kv.first);
   }
@@ -409,7 +414,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       int width = 1, maxl = 1, gap = 0;
       for (int k = 0; k < n_probs; ++k) {
         const auto &pl = h->plans[k];
-        if (!(pl.p == var.p && pl.nq == var.nq && mode_of(pl, VEF_DIR_RESIDENT, pipe != 0) == var.mode)) continue;
+        if (!(pl.p == var.p && pl.nq == var.nq && mode_of(pl, VEF_DIR_RESIDENT, pipe != 0, h->fixup) == var.mode)) continue;
         for (int d = 0; d < pl.nd; ++d) tasks.push_back(make_int2(k, d));
         width = std::max(width, pl.max_width);
         maxl = std::max(maxl, pl.n_levels);
@@ -419,7 +424,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       if (cnt > 0) {
         const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
         (pipe ? h->dir_pipe : h->dir_rows)
-            .push_back({var, off, cnt, width, maxl, gap, var.mode >= 2 ? ts.dev_A : ts.dev_T});
+            .push_back({var, off, cnt, width, maxl, gap, var.mode >= 2 ? ts.dev_A : ts.dev_T, ts.dev_T});
       }
     }
   he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
@@ -585,6 +590,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
         SL.max_levels = D.max_levels;
         SL.max_gap = D.max_gap;
         SL.tables = D.tab;
+        SL.tables_g = D.tab_g;
         he = vefk::launch_sweep_dir(SL);
         if (he != hipSuccess) return hip_fail(h, he, "launch sweep");
         if (timed(it)) h->timed_launches++;
@@ -707,7 +713,7 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->affine = pl.affine ? 1 : 0;
   info->n_solves = (long long)pl.ne * pl.nd;
   info->schedule = h->schedule;
-  info->kernel = mode_of(pl, h->schedule, h->pipeline_waves >= 0);
+  info->kernel = mode_of(pl, h->schedule, h->pipeline_waves >= 0, h->fixup);
   info->n_lagged = pl.n_lagged;
   return VEF_OK;
 }
@@ -814,7 +820,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
   };
   const Cand before{h->schedule, h->pipeline_waves, h->block};
   bool any_pipe = false;
-  for (auto &pl : h->plans) any_pipe |= mode_of(pl, VEF_DIR_RESIDENT, true) == 3;
+  for (auto &pl : h->plans) any_pipe |= mode_of(pl, VEF_DIR_RESIDENT, true, h->fixup) >= 3;
   std::vector<Cand> cands{before};
   auto add = [&](Cand c) {
     for (auto &x : cands)

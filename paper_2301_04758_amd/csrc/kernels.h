@@ -61,7 +61,7 @@ struct SweepLaunch {
   int count;
   int width;       // direction-resident: widest upwind level
   int max_levels;  // direction-resident: deepest level count (offsets staged in LDS)
-  int max_gap;     // pipelined: largest level gap of an upwind edge
+  int max_gap;     // pipelined: largest level gap of an upwind edge that is not lagged
   int waves;       // pipelined: waves per work-group (0 = default)
   int ring;        // pipelined: trace ring depth in levels (0 = default)
   int fixup;       // 1: negative-flux fixup after each local solve (kernel variant)
@@ -69,6 +69,7 @@ struct SweepLaunch {
   const KProb *probs;
   const KIO *io;
   const void *tables;
+  const void *tables_g;  // general-element tables (the pipelined kernel on general elements)
   int it;
   const int *stop;
   int *status;

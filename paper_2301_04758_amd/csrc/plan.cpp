@@ -700,8 +700,9 @@ int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, bool pointwis
         const int nb = o.nbr[4 * e + f];
         o.desc_nb[((size_t)g * ne + t) * 4 + f] = nb;
         if (nb >= 0 && ((mk[e] >> f) & 1)) {
-          const int gap = (lagm_g[e] >> f & 1) ? 255 : lev[e] - lev[nb];
-          o.max_gap = std::max(o.max_gap, gap);
+          const bool lagged = lagm_g[e] >> f & 1;
+          const int gap = lagged ? 255 : lev[e] - lev[nb];
+          if (!lagged) o.max_gap = std::max(o.max_gap, gap);
           const uint32_t code = (uint32_t)std::min(gap, 255) | ((uint32_t)pos_in_level[nb] << 8) |
                                 ((uint32_t)(o.nbr_face[4 * e + f] & 3) << 30);
           o.desc_up[((size_t)g * ne + t) * 4 + f] = code;

@@ -52,6 +52,7 @@ enum : int {
   MODE_GENERAL_NOPIVOT = 1,
   MODE_AFFINE_NOPIVOT = 2,
   MODE_AFFINE_PIPELINE = 3,  // direction-resident schedule only, p <= 2
+  MODE_GENERAL_PIPELINE = 4, // the same for straight-sided bilinear elements (m = 1)
   MODE_KIND = 7,             // mask of the kernel kind above
   MODE_FIX = 8               // flag: negative-flux fixup after each local solve
 };
@@ -873,10 +874,16 @@ constexpr int pipe_max_waves() {
   return kPipeMaxWaves;
 }
 
-template <int P, int NQ, typename T, bool FIX>
+// GEN: straight-sided bilinear elements.  The face terms are those of the
+// affine case (n ds is constant along a straight edge of a bilinear map, so a
+// face contributes (Omega . N_f) times the 1D face mass); the volume terms
+// and the source are summed over the quadrature points with the element's
+// geometry there (tables_g: V, Dxi, Deta at the points).  Only the prep
+// differs; the critical part is the affine one.
+template <int P, int NQ, typename T, bool FIX, bool GEN>
 __global__ void __launch_bounds__((pipe_max_waves<P, T>() * 64))
 k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
-             const KIO *__restrict__ io, const T *__restrict__ tables, int it,
+             const KIO *__restrict__ io, const T *__restrict__ tables, const T *__restrict__ tables_g, int it,
              const int *__restrict__ stop, int *__restrict__ status, int ring_levels, int ring_width,
              int global_sync, long long wait_spins) {
   using S = Shape<P, NQ>;
@@ -970,10 +977,15 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
           up[f] = dup[4 * t + f];
         }
       }
-      const VEF_GLOBAL T *ga = gmem(static_cast<const T *>(pb.geo_a) + (size_t)e * 16);
       T gv[13];
+      if constexpr (!GEN) {
+        const VEF_GLOBAL T *ga = gmem(static_cast<const T *>(pb.geo_a) + (size_t)e * 16);
 #pragma unroll
-      for (int k = 0; k < 13; ++k) gv[k] = ga[k];
+        for (int k = 0; k < 13; ++k) gv[k] = ga[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 13; ++k) gv[k] = T(0);
+      }
       const T st = static_cast<T>(sig[2 * e]);
       const T ss = static_cast<T>(sig[2 * e + 1] * kInv4Pi);
       // nodal source s_j = sigma_s / (4 pi) phi_j + q_j.  One branch per
@@ -997,49 +1009,79 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       T sj[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) sj[j] = ss * static_cast<T>(pv[j]) + static_cast<T>(qv[j]);
-      const T J = gv[0];
-      const T stJ = st * J;
-      const T gx = gv[1] * ox + gv[2] * oy;
-      const T gy = gv[3] * ox + gv[4] * oy;
       T on[4];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) on[f] = ox * gv[5 + 2 * f] + oy * gv[6 + 2 * f];
-      // Right-hand side first: every branch of the prep happens while only
-      // these N values are live, the matrix below is straight-line code.
-      // b = J (m (x) m) s by sum factorisation: node (a, b) = a + P1 * b.
       T b[N];
-      {
-        T h[P1][P1];  // h[a][d] = sum_c m[a][c] s[c][d]
+      T stJ = T(0), gx = T(0), gy = T(0);
+      T A[N][N];
+      if constexpr (!GEN) {
+        const T J = gv[0];
+        stJ = st * J;
+        gx = gv[1] * ox + gv[2] * oy;
+        gy = gv[3] * ox + gv[4] * oy;
 #pragma unroll
-        for (int a = 0; a < P1; ++a)
+        for (int f = 0; f < 4; ++f) on[f] = ox * gv[5 + 2 * f] + oy * gv[6 + 2 * f];
+        // Right-hand side first: every branch of the prep happens while only
+        // these N values are live, the matrix below is straight-line code.
+        // b = J (m (x) m) s by sum factorisation: node (a, b) = a + P1 * b.
+        {
+          T h[P1][P1];  // h[a][d] = sum_c m[a][c] s[c][d]
 #pragma unroll
-          for (int dd = 0; dd < P1; ++dd) {
+          for (int a = 0; a < P1; ++a)
+#pragma unroll
+            for (int dd = 0; dd < P1; ++dd) {
+              T acc = T(0);
+#pragma unroll
+              for (int c = 0; c < P1; ++c) acc += m1[a * P1 + c] * sj[c + P1 * dd];
+              h[a][dd] = acc;
+            }
+#pragma unroll
+          for (int a = 0; a < P1; ++a)
+#pragma unroll
+            for (int bb = 0; bb < P1; ++bb) {
+              T acc = T(0);
+#pragma unroll
+              for (int dd = 0; dd < P1; ++dd) acc += m1[bb * P1 + dd] * h[a][dd];
+              b[a + P1 * bb] = J * acc;
+            }
+        }
+        if (pio.q_dir) {
+          const VEF_GLOBAL double *qd = gmem(pio.q_dir + ((size_t)d * ne + e) * Q);
+          T qv[Q];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) qv[q] = static_cast<T>(qd[q]);
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
             T acc = T(0);
 #pragma unroll
-            for (int c = 0; c < P1; ++c) acc += m1[a * P1 + c] * sj[c + P1 * dd];
-            h[a][dd] = acc;
+            for (int q = 0; q < Q; ++q) acc += WV[q * N + i] * qv[q];
+            b[i] += J * acc;
           }
+        }
+      } else {
+        // Omega . N_f: n ds is constant along the edge and the face weights sum to one
+        const VEF_GLOBAL T *gfq = gmem(static_cast<const T *>(pb.geo_f) + (size_t)e * 8 * NQ);
 #pragma unroll
-        for (int a = 0; a < P1; ++a)
-#pragma unroll
-          for (int bb = 0; bb < P1; ++bb) {
-            T acc = T(0);
-#pragma unroll
-            for (int dd = 0; dd < P1; ++dd) acc += m1[bb * P1 + dd] * h[a][dd];
-            b[a + P1 * bb] = J * acc;
-          }
-      }
-      if (pio.q_dir) {
-        const VEF_GLOBAL double *qd = gmem(pio.q_dir + ((size_t)d * ne + e) * Q);
-        T qv[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) qv[q] = static_cast<T>(qd[q]);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
+        for (int f = 0; f < 4; ++f) {
           T acc = T(0);
 #pragma unroll
-          for (int q = 0; q < Q; ++q) acc += WV[q * N + i] * qv[q];
-          b[i] += J * acc;
+          for (int q = 0; q < NQ; ++q) acc += ox * gfq[(f * NQ + q) * 2] + oy * gfq[(f * NQ + q) * 2 + 1];
+          on[f] = acc;
+        }
+        const VEF_GLOBAL T *gq = gmem(static_cast<const T *>(pb.geo_v) + (size_t)e * Q * 5);
+        const VEF_CONST T *tg = (const VEF_CONST T *)tables_g;  // V, Dxi, Deta [Q][N]
+        const VEF_GLOBAL double *qdp = pio.q_dir ? gmem(pio.q_dir + ((size_t)d * ne + e) * Q) : nullptr;
+#pragma unroll
+        for (int i = 0; i < N; ++i) b[i] = T(0);
+        // b_i = sum_q wJ_q V_qi (sum_j V_qj s_j + q_dir,q)
+#pragma unroll 1
+        for (int q = 0; q < Q; ++q) {
+          const T wJ = gq[5 * q];
+          T src = qdp ? static_cast<T>(qdp[q]) : T(0);
+#pragma unroll
+          for (int j = 0; j < N; ++j) src += tg[q * N + j] * sj[j];
+          src *= wJ;
+#pragma unroll
+          for (int i = 0; i < N; ++i) b[i] += tg[q * N + i] * src;
         }
       }
       if (pio.psi_bc) {
@@ -1067,22 +1109,43 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       for (int f = 0; f < 4; ++f) cf[f] = ((flags >> f) & 1) ? T(0) : on[f];
       // A[(a,b)][(c,d)] = stJ m_ac m_bd - gx gd_ac m_bd - gy m_ac gd_bd
       //                  = m_bd X_ac - gd_bd Y_ac
-      T X[P1 * P1], Y[P1 * P1];
+      if constexpr (!GEN) {
+        T X[P1 * P1], Y[P1 * P1];
 #pragma unroll
-      for (int k = 0; k < P1 * P1; ++k) {
-        X[k] = stJ * m1[k] - gx * gd[k];
-        Y[k] = gy * m1[k];
+        for (int k = 0; k < P1 * P1; ++k) {
+          X[k] = stJ * m1[k] - gx * gd[k];
+          Y[k] = gy * m1[k];
+        }
+#pragma unroll
+        for (int bb = 0; bb < P1; ++bb)
+#pragma unroll
+          for (int a = 0; a < P1; ++a)
+#pragma unroll
+            for (int dd = 0; dd < P1; ++dd)
+#pragma unroll
+              for (int c = 0; c < P1; ++c)
+                A[a + P1 * bb][c + P1 * dd] = m1[bb * P1 + dd] * X[a * P1 + c] - gd[bb * P1 + dd] * Y[a * P1 + c];
+      } else {
+        // A_ij = sum_q (sigma_t wJ_q V_qi - (adj(F)_q Omega) . grad V_qi) V_qj
+        const VEF_GLOBAL T *gq = gmem(static_cast<const T *>(pb.geo_v) + (size_t)e * Q * 5);
+        const VEF_CONST T *tg = (const VEF_CONST T *)tables_g;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int j = 0; j < N; ++j) A[i][j] = T(0);
+#pragma unroll 1
+        for (int q = 0; q < Q; ++q) {
+          const T wJ = gq[5 * q], a00 = gq[5 * q + 1], a01 = gq[5 * q + 2], a10 = gq[5 * q + 3],
+                  a11 = gq[5 * q + 4];
+          const T sw = st * wJ, gxq = a00 * ox + a01 * oy, gyq = a10 * ox + a11 * oy;
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            const T ci = sw * tg[q * N + i] - (gxq * tg[(Q + q) * N + i] + gyq * tg[(2 * Q + q) * N + i]);
+#pragma unroll
+            for (int j = 0; j < N; ++j) A[i][j] += ci * tg[q * N + j];
+          }
+        }
       }
-      T A[N][N];
-#pragma unroll
-      for (int bb = 0; bb < P1; ++bb)
-#pragma unroll
-        for (int a = 0; a < P1; ++a)
-#pragma unroll
-          for (int dd = 0; dd < P1; ++dd)
-#pragma unroll
-            for (int c = 0; c < P1; ++c)
-              A[a + P1 * bb][c + P1 * dd] = m1[bb * P1 + dd] * X[a * P1 + c] - gd[bb * P1 + dd] * Y[a * P1 + c];
 #pragma unroll
       for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -1244,13 +1307,27 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
 template <int P, int NQ, typename T, int MODE>
 hipError_t launch_dir_t(const SweepLaunch &L);
 
-template <int P, int NQ, typename T, bool FIX>
+template <int P, int NQ, typename T, bool FIX, bool GEN>
 hipError_t launch_pipe_t(const SweepLaunch &L) {
   if constexpr (P > 2) {
     return hipErrorInvalidValue;
   } else {
     if (L.count == 0) return hipSuccess;
     using S = Shape<P, NQ>;
+    // the row-per-lane kernel of the same elements (general ones read the
+    // general tables)
+    auto rows = [&]() {
+      if constexpr (GEN) {
+        SweepLaunch G = L;
+        G.tables = L.tables_g;
+        return launch_dir_t<P, NQ, T, MODE_GENERAL_NOPIVOT | (FIX ? MODE_FIX : 0)>(G);
+      } else {
+        return launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT | (FIX ? MODE_FIX : 0)>(L);
+      }
+    };
+    if constexpr (GEN && FIX) {
+      return rows();  // the fixup's balance weights assume affine elements
+    } else {
     constexpr int maxw = pipe_max_waves<P, T>();
     const int waves = L.waves > 0 ? (L.waves > maxw ? maxw : L.waves) : maxw;
     const size_t ring_bytes_per_level = (size_t)L.width * 4 * S::P1 * sizeof(T);
@@ -1259,14 +1336,17 @@ hipError_t launch_pipe_t(const SweepLaunch &L) {
     R = R >= 4 ? 4 : (R >= 2 ? 2 : 1);  // a power of two: the slot of a level is a mask
     while (R > 1 && fixed + R * ring_bytes_per_level > L.lds_max) R >>= 1;
     // a level too wide for even one ring slot: the row-per-lane kernel
-    if (fixed + R * ring_bytes_per_level > L.lds_max)
-      return launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT | (FIX ? MODE_FIX : 0)>(L);
+    if (fixed + R * ring_bytes_per_level > L.lds_max) return rows();
+    // lagged couplings (level gap 255) read the previous sweep from global
+    // memory and need no store before publishing: max_gap counts only the
+    // others
     const int global_sync = (L.max_gap >= R) ? 1 : 0;
     const size_t bytes = fixed + R * ring_bytes_per_level;
-    hipLaunchKernelGGL((k_sweep_pipe<P, NQ, T, FIX>), dim3(L.count), dim3(waves * 64), bytes, L.stream, L.list, L.probs,
-                       L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status, R, L.width, global_sync,
-                       L.wait_spins);
+    hipLaunchKernelGGL((k_sweep_pipe<P, NQ, T, FIX, GEN>), dim3(L.count), dim3(waves * 64), bytes, L.stream, L.list,
+                       L.probs, L.io, static_cast<const T *>(L.tables), static_cast<const T *>(L.tables_g), L.it,
+                       L.stop, L.status, R, L.width, global_sync, L.wait_spins);
     return hipGetLastError();
+    }
   }
 }
 
@@ -1328,7 +1408,9 @@ hipError_t launch_mode_fx(const SweepLaunch &L) {
       return DIR ? launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT | FX>(L)
                  : launch_level_t<P, NQ, T, MODE_AFFINE_NOPIVOT | FX>(L);
     case MODE_AFFINE_PIPELINE:
-      return DIR ? launch_pipe_t<P, NQ, T, FX != 0>(L) : hipErrorInvalidValue;
+      return DIR ? launch_pipe_t<P, NQ, T, FX != 0, false>(L) : hipErrorInvalidValue;
+    case MODE_GENERAL_PIPELINE:
+      return DIR ? launch_pipe_t<P, NQ, T, FX != 0, true>(L) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

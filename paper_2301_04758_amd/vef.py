@@ -36,8 +36,9 @@ VEF_DIR_RESIDENT = 2
 SCHEDULES = {"auto": VEF_SCHEDULE_AUTO, "level": VEF_LEVEL_SYNC, "dir": VEF_DIR_RESIDENT}
 SCHEDULE_NAMES = {VEF_LEVEL_SYNC: "level_sync", VEF_DIR_RESIDENT: "dir_resident"}
 VEF_KERNEL_PIVOT, VEF_KERNEL_NOPIVOT, VEF_KERNEL_AFFINE, VEF_KERNEL_AFFINE_PIPELINE = 0, 1, 2, 3
+VEF_KERNEL_BILINEAR_PIPELINE = 4
 KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KERNEL_AFFINE: "affine",
-                VEF_KERNEL_AFFINE_PIPELINE: "affine_pipeline"}
+                VEF_KERNEL_AFFINE_PIPELINE: "affine_pipeline", VEF_KERNEL_BILINEAR_PIPELINE: "bilinear_pipeline"}
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",

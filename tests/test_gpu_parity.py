@@ -304,6 +304,44 @@ def test_pipeline_depths_bitwise(torch, precision, case):
         assert rel_inf(runs[0]["psi_out"], ref["psi"]) <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p,nx,N", [(1, 23, 6), (2, 90, 4), (2, 7, 8)])
+def test_bilinear_pipeline(torch, precision, p, nx, N):
+    """Straight-sided bilinear elements (trapezoids) on the direction-resident
+    schedule: the pipelined kernel with quadrature assembly, identical bits for
+    1..8 waves and ring depths 1..4, and oracle parity with a direction
+    dependent source and boundary inflow (nx = 90: levels wider than one wave,
+    ragged last chunks)."""
+    from test_library_host import _trapezoids
+    from paper_2301_04758_amd import vef
+    cp, ec = _trapezoids(nx, 0.2, seed=nx)
+    om, wt = P.level_symmetric_2d(N)
+    ne = ec.shape[0]
+    rng = np.random.default_rng(p + nx)
+    st = rng.uniform(0.5, 20, ne)
+    nq = p + 2 if nx == 7 else p + 1
+    pr = P.Problem("trap_pipe", p, 1, cp, ec, om, wt, st, 0.7 * st, q_iso=rng.uniform(0, 1, (ne, (p + 1) ** 2)),
+                   nq=nq)
+    pr.q_dir = rng.uniform(0, 1, (pr.n_dir, ne, nq * nq))
+    pr.psi_bc = rng.uniform(0, 1, (pr.n_dir, O.n_boundary_faces(pr), nq))
+    phi = rng.uniform(0, 2, (ne, (p + 1) ** 2))
+    runs = []
+    for w, r in PIPE_CASES:
+        (g,), out = gpu_run(torch, [pr], precision, phi_in=phi, schedule="dir", pipeline_waves=w, pipeline_ring=r)
+        assert out["info"][0]["kernel"] == vef.VEF_KERNEL_BILINEAR_PIPELINE
+        runs.append(g)
+    for k in range(1, len(runs)):
+        assert np.array_equal(runs[0]["psi_out"], runs[k]["psi_out"]), PIPE_CASES[k]
+        assert np.array_equal(runs[0]["mom"], runs[k]["mom"]), PIPE_CASES[k]
+    ref = O.sweep(pr, phi_in=phi, nq=nq)
+    assert rel_inf(runs[0]["psi_out"], ref["psi"]) <= TOL[precision]
+    assert rel_inf(runs[0]["mom"][0], ref["mom"][0]) <= TOL[precision]
+    # the row-per-lane kernel of the same problem (pipelining off)
+    (g,), out = gpu_run(torch, [pr], precision, phi_in=phi, schedule="dir", pipeline_waves=-1)
+    assert out["info"][0]["kernel"] == vef.VEF_KERNEL_NOPIVOT
+    assert rel_inf(g["psi_out"], runs[0]["psi_out"]) <= TOL[precision]
+
+
 @pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("p,m,warp", [(3, 2, 0.08), (2, 1, 0.0), (1, 3, 0.05)])
 def test_translation_invariance(torch, schedule, p, m, warp):
