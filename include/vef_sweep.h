@@ -337,6 +337,56 @@ int vef_hrt_reduce(vef_sweep_t *h, int k, const double *mom, const double *Eb, c
                    const double *Q0, const double *Q1, const double *inv, double *hloc, double *rloc,
                    double *sol0, double *resp, void *stream);
 
+/* Device solver of the reduced hybridized system of Sec. 7 (the face
+ * unknowns lambda of Eq. eq:hyb_form once every element's [J; phi] has been
+ * eliminated, as vef_hrt_reduce leaves them): H lambda = r, H and r the sums
+ * of the element contributions hloc, rloc over the interior-face slots of
+ * each element, then [J; phi]_K = sol0_K - resp_K lambda_K per element.
+ * The sparsity pattern of H is fixed by the mesh, so a host factorisation
+ * P H0 Q = L U of one matrix of that pattern (for instance SuperLU's, with
+ * its fill-reducing column order) is re-used: each solve re-factorises the
+ * new values numerically with that pivot order and fill (rocSOLVER csrrf)
+ * and solves on the device.  The re-used pivot order is only as good as it
+ * is for the new matrix: the backward error returned by vef_lambda_solve
+ * tells the caller when to factorise on the host again.
+ *
+ * vef_lambda_create arguments (host arrays unless stated):
+ *   n        unknowns (interior faces x (p+1)); ne elements; k = 4(p+1)
+ *            slots per element; nloc = local unknowns of [J; phi];
+ *   gidx     [ne][k] unknown of each slot (face f, point t at f(p+1)+t),
+ *            -1 for slots on the boundary; an unknown belongs to at most
+ *            two elements;
+ *   nnz_t, ptr_t [n+1], ind_t [nnz_t], val_t [nnz_t]: the factors as one CSR
+ *            matrix T = (L - I) + U (unit diagonal of L not stored, columns
+ *            ascending in each row) of P H0 Q = L U;
+ *   piv_p, piv_q [n]: row piv_p[i] of H0 is row i of P H0, column piv_q[j]
+ *            of H0 is column j of H0 Q (permutations of 0..n-1);
+ *   hloc0, rloc0 (device): the element contributions of H0 and of one r,
+ *            laid out as for vef_lambda_solve;
+ *   stream   where the set-up runs (blocking);
+ *   *out     the handle (vef_lambda_destroy frees it).
+ * vef_lambda_solve arguments (device arrays):
+ *   hloc [ne][k][k], rloc [ne][k]: this matrix and right-hand side;
+ *   lam [n] out: the solution lambda;
+ *   sol0 [ne][nloc], resp [ne][nloc][k], sol [ne][nloc] out: the recovery
+ *            (all three NULL to skip it);
+ *   rel_resid (host, may be NULL): the normwise backward error
+ *            |r - H lambda|_inf / (|H|_inf |lambda|_inf + |r|_inf)
+ *            (the call then blocks until it is known);
+ *   stream   where it runs (asynchronous when rel_resid is NULL).
+ * Errors: VEF_ERR_INVALID (sizes, NULL, gidx out of range, T not a sorted
+ * CSR pattern, pivots not permutations), VEF_ERR_OOM, VEF_ERR_HIP (a HIP,
+ * rocBLAS or rocSOLVER call failed).  vef_lambda_error gives the message
+ * (h NULL: the last failed create). */
+typedef struct vef_lambda vef_lambda_t;
+int vef_lambda_create(int n, int ne, int k, int nloc, const int32_t *gidx, int nnz_t, const int32_t *ptr_t,
+                      const int32_t *ind_t, const double *val_t, const int32_t *piv_p, const int32_t *piv_q,
+                      const double *hloc0, const double *rloc0, void *stream, vef_lambda_t **out);
+int vef_lambda_solve(vef_lambda_t *h, const double *hloc, const double *rloc, const double *sol0, const double *resp,
+                     double *lam, double *sol, double *rel_resid, void *stream);
+int vef_lambda_destroy(vef_lambda_t *h);
+const char *vef_lambda_error(const vef_lambda_t *h);
+
 /* Measured machine figures (vef_probe_machine). */
 typedef struct {
   int compute_units;      /* of the current device */

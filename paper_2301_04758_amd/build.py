@@ -11,8 +11,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvefsweep.so")
 SOURCES = ["plan.cpp", "kernels.hip", "sweep_p1.hip", "sweep_p2.hip", "sweep_p3.hip", "sweep_p4.hip", "probe.hip",
-           "hrt.hip", "api.cpp"]
+           "hrt.hip", "lambda.hip", "api.cpp"]
 ARCH = os.environ.get("VEF_OFFLOAD_ARCH", "gfx950")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU forms.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -51,7 +52,10 @@ def build(verbose: bool = False, out: str = LIB, jobs: int = 0) -> str:
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = out + ".tmp"
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    # rocSOLVER (sparse re-factorisation of the reduced VEF system) and the
+    # rocBLAS handle it runs on
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L" + os.path.join(ROCM, "lib"), "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -43,7 +43,7 @@ KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KE
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
             "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_hrt_reduce", "vef_last_error",
-            "vef_status_string")
+            "vef_status_string", "vef_lambda_create", "vef_lambda_solve", "vef_lambda_destroy", "vef_lambda_error")
 
 
 class vef_problem_desc(C.Structure):
@@ -106,13 +106,19 @@ def _load():
     L.vef_probe_machine.argtypes = [C.c_void_p, C.c_void_p]
     L.vef_hrt_local_inverse.argtypes = [H, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.vef_hrt_reduce.argtypes = [H, C.c_int] + [C.c_void_p] * 11
+    L.vef_lambda_create.argtypes = [C.c_int] * 4 + [C.c_void_p, C.c_int] + [C.c_void_p] * 8 + [C.POINTER(H)]
+    L.vef_lambda_solve.argtypes = [H] + [C.c_void_p] * 6 + [C.POINTER(C.c_double), C.c_void_p]
+    L.vef_lambda_destroy.argtypes = [H]
+    L.vef_lambda_error.argtypes = [H]
+    L.vef_lambda_error.restype = C.c_char_p
     L.vef_last_error.argtypes = [H]
     L.vef_last_error.restype = C.c_char_p
     L.vef_status_string.argtypes = [C.c_int]
     L.vef_status_string.restype = C.c_char_p
     for f in ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
               "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
-              "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_hrt_reduce"):
+              "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_hrt_reduce",
+              "vef_lambda_create", "vef_lambda_solve", "vef_lambda_destroy"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -287,6 +293,66 @@ def vef_hrt_reduce(h: int, k: int, mom, Eb, Jin, Q0, Q1, inv, hloc, rloc, sol0, 
                             C.c_void_p(_stream_handle(stream)))
     if rc != VEF_OK:
         raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+
+
+class LambdaSolver:
+    """The reduced hybridized system H lambda = r on the device
+    (vef_lambda_create / vef_lambda_solve, include/vef_sweep.h).  gidx [ne,
+    k] the unknown of each element slot (-1: boundary); the factors of one
+    matrix H0 of the pattern as a scipy LU (splu) of H0 assembled from the
+    same gidx; hloc0, rloc0 its element contributions (device tensors)."""
+
+    def __init__(self, gidx, nloc, lu, hloc0, rloc0, stream=None):
+        import numpy as np
+        import scipy.sparse as sp
+        gidx = np.ascontiguousarray(gidx, dtype=np.int32)
+        ne, k = gidx.shape
+        n = lu.shape[0]
+        Lc, Uc = lu.L.tocoo(), lu.U.tocoo()
+        low = Lc.col < Lc.row
+        T = sp.csr_matrix((np.concatenate([Lc.data[low], Uc.data]), (np.concatenate([Lc.row[low], Uc.row]),
+                          np.concatenate([Lc.col[low], Uc.col]))), shape=(n, n))
+        T.sort_indices()
+        ptr = np.ascontiguousarray(T.indptr, dtype=np.int32)
+        ind = np.ascontiguousarray(T.indices, dtype=np.int32)
+        val = np.ascontiguousarray(T.data, dtype=np.float64)
+        piv_p = np.ascontiguousarray(np.argsort(lu.perm_r), dtype=np.int32)
+        piv_q = np.ascontiguousarray(np.argsort(lu.perm_c), dtype=np.int32)
+        self.n, self.ne, self.k, self.nloc = n, ne, k, nloc
+        h = C.c_void_p()
+        rc = lib.vef_lambda_create(n, ne, k, nloc, gidx.ctypes.data, int(T.nnz), ptr.ctypes.data, ind.ctypes.data,
+                                   val.ctypes.data, piv_p.ctypes.data, piv_q.ctypes.data, _ptr(hloc0.contiguous()),
+                                   _ptr(rloc0.contiguous()), _stream_handle(stream), C.byref(h))
+        if rc != VEF_OK:
+            raise VefError(rc, lib.vef_lambda_error(None).decode())
+        self.h = h
+
+    def solve(self, hloc, rloc, sol0=None, resp=None, want_resid=True, stream=None):
+        """Returns (lam [n], sol [ne, nloc] or None, relative residual or
+        None) as device tensors."""
+        import torch
+        dev = hloc.device
+        lam = torch.empty(self.n, dtype=torch.float64, device=dev)
+        sol = torch.empty((self.ne, self.nloc), dtype=torch.float64, device=dev) if sol0 is not None else None
+        r = C.c_double(0.0)
+        rc = lib.vef_lambda_solve(self.h, _ptr(hloc.contiguous()), _ptr(rloc.contiguous()),
+                                  _ptr(sol0.contiguous()) if sol0 is not None else None,
+                                  _ptr(resp.contiguous()) if resp is not None else None, _ptr(lam), _ptr(sol),
+                                  C.byref(r) if want_resid else None, _stream_handle(stream))
+        if rc != VEF_OK:
+            raise VefError(rc, lib.vef_lambda_error(self.h).decode())
+        return lam, sol, (r.value if want_resid else None)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.vef_lambda_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def vef_sweep_check(h: int):

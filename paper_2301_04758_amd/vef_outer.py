@@ -122,7 +122,12 @@ class _Ref:
 class VefOuter:
     """Transport + HRT VEF outer iteration for one affine problem."""
 
-    def __init__(self, problem, nq=None, precision="fp64", device_reduce=True):
+    # normwise backward error of the device lambda solve above which its
+    # re-used pivot order is replaced by a new host factorisation (a stable
+    # LU stays within a small multiple of the unit round-off)
+    REFACTOR_RESID = 1e-12
+
+    def __init__(self, problem, nq=None, precision="fp64", device_reduce=True, lambda_solve="device"):
         p = problem.p
         if nq is None:
             nq = p + 2
@@ -130,6 +135,12 @@ class VefOuter:
         self.pr = problem
         self.ref = _Ref(p, nq)
         self.device_reduce = device_reduce
+        if lambda_solve not in ("device", "host"):
+            raise ValueError("lambda_solve is 'device' or 'host'")
+        self.lambda_solve = lambda_solve
+        self._lam = None
+        self.host_factorisations = 0
+        self.last_resid = None
         self.sw = vef.Sweep([problem], precision=precision)
         import scipy.sparse  # noqa: F401  (after the device is set up; fail early if missing)
         if not self.sw.info[0]["affine"]:
@@ -144,6 +155,8 @@ class VefOuter:
         driving it from closures and block inverses computed elsewhere."""
         self = cls.__new__(cls)
         self.device_reduce = False
+        self.lambda_solve = "host"
+        self._lam = None
         problem.nq = nq or problem.p + 2
         self.pr = problem
         self.ref = _Ref(problem.p, problem.nq)
@@ -192,6 +205,9 @@ class VefOuter:
             self.bf_of[int(e), int(f)] = k
 
     def close(self):
+        if getattr(self, "_lam", None) is not None:
+            self._lam.close()
+            self._lam = None
         if self.sw is not None:
             self.sw.close()
 
@@ -223,18 +239,27 @@ class VefOuter:
         nodes, and the current."""
         import time
         t0 = time.perf_counter()
-        d = self._device_stage(phi_lob)
+        on_device = self.device_reduce and self.lambda_solve == "device" and self.n_faces > 0
+        d = self._device_stage(phi_lob, keep_device=on_device)
+        if on_device:
+            import torch
+            torch.cuda.synchronize()
         t1 = time.perf_counter()
-        out = self._solve_reduced(**d) if "hloc" in d else self.host_stage(**d)
-        # wall time of the device part (sweep, closures, block inverses and
-        # their copies to the host) and of the host part
-        self.last_times = dict(device_s=t1 - t0, host_s=time.perf_counter() - t1)
+        if on_device:
+            out = self._solve_device(d)
+        else:
+            out = self._solve_reduced(**d) if "hloc" in d else self.host_stage(**d)
+        # wall time of the transport and element-local stage (sweep,
+        # closures, block inverses, reduction, and copies to the host where
+        # the lambda system is solved there) and of the lambda solve with the
+        # recovery of [J; phi]
+        self.last_times = dict(stage_s=t1 - t0, solve_s=time.perf_counter() - t1)
         return out
 
-    def _device_stage(self, phi_lob):
+    def _device_stage(self, phi_lob, keep_device=False):
         """Sweep, closures and block inverses on the GPU, and with
         device_reduce the element-local reduction too (vef_hrt_reduce);
-        copied to the host."""
+        copied to the host unless keep_device (reduction results only)."""
         import torch
         io = self.sw.buffers(n_iter=1, store_psi=False, phi_in=phi_lob)
         self.sw.run(io, n_iter=1)
@@ -243,6 +268,8 @@ class VefOuter:
         inv = self.sw.hrt_local_inverse(0, io[0]["mom"], mio[0]["Eb"])
         if self.device_reduce:
             red = self.sw.hrt_reduce(0, io[0]["mom"], mio[0], inv)
+            if keep_device:
+                return red
             torch.cuda.synchronize()
             self.sw.check()
             return {k: v.cpu().numpy() for k, v in red.items()}
@@ -320,24 +347,69 @@ class VefOuter:
         return self._solve_reduced(hloc=np.matmul(C1, resp[:, :nv]), rloc=np.matmul(C1, sol0[:, :nv, None])[:, :, 0],
                                    sol0=sol0, resp=resp)
 
-    def _solve_reduced(self, hloc, rloc, sol0, resp):
-        """Assemble H lambda = r from the elements' hloc [ne, 4(p+1), 4(p+1)]
-        and rloc [ne, 4(p+1)] by interior-face slot, solve it (scipy sparse
-        LU), and recover [J; phi] = sol0 - resp lambda per element."""
+    def _gidx(self):
+        """[ne, 4(p+1)]: the lambda unknown of each element slot f(p+1)+t
+        (-1 on boundary faces)."""
+        P1 = self.pr.p + 1
+        fid = self.face_id[:, :, None]
+        g = np.where(fid >= 0, fid * P1 + np.arange(P1)[None, None, :], -1)
+        return g.reshape(self.pr.n_elem, 4 * P1)
+
+    def _assemble_host(self, hloc, rloc):
+        """H [n, n] (CSR) and r from the element contributions."""
         import scipy.sparse as sp
-        import scipy.sparse.linalg as spl
-        pr, ref = self.pr, self.ref
-        ne, P1, nv = pr.n_elem, pr.p + 1, ref.nv
-        Hloc, rloc = hloc, rloc
-        gidx = (self.face_id[:, :, None] * P1 + np.arange(P1)[None, None, :]).reshape(ne, 4 * P1)
+        P1 = self.pr.p + 1
+        gidx = self._gidx()
         ok = gidx >= 0
         rows = np.repeat(gidx[:, :, None], 4 * P1, axis=2)
         cols = np.repeat(gidx[:, None, :], 4 * P1, axis=1)
         mask = ok[:, :, None] & ok[:, None, :]
         nl = self.n_faces * P1
-        H = sp.csr_matrix((Hloc[mask], (rows[mask], cols[mask])), shape=(nl, nl))
+        H = sp.csr_matrix((hloc[mask], (rows[mask], cols[mask])), shape=(nl, nl))
         rhs = np.zeros(nl)
         np.add.at(rhs, gidx[ok], rloc[ok])
+        return H, rhs
+
+    def _solve_device(self, red):
+        """The reduced system on the device (vef.LambdaSolver): the first
+        call factorises H on the host (SuperLU, fill-reducing column order)
+        and later calls re-factorise with that pivot order; a relative
+        residual above REFACTOR_RESID factorises the current H on the host
+        again."""
+        import scipy.sparse.linalg as spl
+        ref = self.ref
+
+        def factorise():
+            H, _ = self._assemble_host(red["hloc"].cpu().numpy(), red["rloc"].cpu().numpy())
+            lu = spl.splu(H.tocsc(), permc_spec="MMD_AT_PLUS_A")
+            if self._lam is not None:
+                self._lam.close()
+            self._lam = vef.LambdaSolver(self._gidx(), ref.nv + ref.nphi, lu, red["hloc"], red["rloc"])
+            self.host_factorisations += 1
+
+        if self._lam is None:
+            factorise()
+        _, sol, resid = self._lam.solve(red["hloc"], red["rloc"], red["sol0"], red["resp"])
+        if not resid <= self.REFACTOR_RESID:
+            factorise()
+            _, sol, resid = self._lam.solve(red["hloc"], red["rloc"], red["sol0"], red["resp"])
+        self.sw.check()
+        self.last_resid = resid
+        sol = sol.cpu().numpy()
+        Jc, phi_leg = sol[:, :ref.nv], sol[:, ref.nv:]
+        return phi_leg @ ref.leg_at_lob.T, phi_leg, Jc
+
+    def _solve_reduced(self, hloc, rloc, sol0, resp):
+        """Assemble H lambda = r from the elements' hloc [ne, 4(p+1), 4(p+1)]
+        and rloc [ne, 4(p+1)] by interior-face slot, solve it (scipy sparse
+        LU), and recover [J; phi] = sol0 - resp lambda per element."""
+        import scipy.sparse.linalg as spl
+        pr, ref = self.pr, self.ref
+        ne, P1, nv = pr.n_elem, pr.p + 1, ref.nv
+        gidx = self._gidx()
+        ok = gidx >= 0
+        nl = self.n_faces * P1
+        H, rhs = self._assemble_host(hloc, rloc)
         lam_g = spl.spsolve(H.tocsc(), rhs, permc_spec="MMD_AT_PLUS_A") if nl else np.zeros(0)
         lam_loc = np.where(ok, lam_g[np.where(ok, gidx, 0)] if nl else 0.0, 0.0)
         sol = sol0 - np.matmul(resp, lam_loc[:, :, None])[:, :, 0]

@@ -186,3 +186,50 @@ def test_device_reduction_matches_host_reduction(torch, case):
         assert np.abs(dev[1] - host[1]).max() <= 1e-12 * np.abs(host[1]).max()
     finally:
         drv.close()
+
+
+@pytest.mark.parametrize("case", ["tdl_p1", "sheared_p2", "graded_p2"])
+def test_device_lambda_solve_matches_host_solve(torch, case):
+    """The reduced lambda system solved on the device (vef_lambda_*: one host
+    factorisation, then re-factorisations with its pivot order) against the
+    host's sparse solve of the same system, iterate by iterate; the pivot
+    order of the first iteration serves all later ones here (no second host
+    factorisation) and the residuals stay at rounding level."""
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    pr = {"tdl_p1": lambda: _tdl(8, 1, 1e-2), "sheared_p2": lambda: _sheared(6, 2),
+          "graded_p2": lambda: _graded(6, 2)}[case]()
+    tol = max(1e-12, 64 * np.finfo(float).eps * _kappa(pr))
+    dev, host = VefOuter(pr), VefOuter(pr, lambda_solve="host")
+    try:
+        a = b = None
+        for k in range(4):
+            a, leg_a, J_a = dev.step(a)
+            b, leg_b, J_b = host.step(b)
+            err = np.abs(leg_a - leg_b).max() / np.abs(leg_b).max()
+            errJ = np.abs(J_a - J_b).max() / np.abs(J_b).max()
+            print("%s iteration %d phi %.2e J %.2e resid %.2e" % (case, k + 1, err, errJ, dev.last_resid), flush=True)
+            assert err <= tol and errJ <= tol, (k, err, errJ, tol)
+            assert dev.last_resid <= dev.REFACTOR_RESID
+        assert dev.host_factorisations == 1
+    finally:
+        dev.close()
+        host.close()
+
+
+def test_device_lambda_solve_refactorises_when_the_residual_grows(torch):
+    """A residual threshold below rounding level forces a new host
+    factorisation on every call; the iterates are those of the host solve."""
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    pr = _sheared(5, 2)
+    dev, host = VefOuter(pr), VefOuter(pr, lambda_solve="host")
+    dev.REFACTOR_RESID = 0.0
+    try:
+        a = b = None
+        for k in range(2):
+            a, leg_a, _ = dev.step(a)
+            b, leg_b, _ = host.step(b)
+            assert np.abs(leg_a - leg_b).max() <= 1e-10 * np.abs(leg_b).max()
+        assert dev.host_factorisations == 3  # the first call's two, then one per call
+    finally:
+        dev.close()
+        host.close()

@@ -173,3 +173,31 @@ def test_affine_classification_fine_meshes(n, m, shift):
         cp2[k, 0] += (1e-9 if shift == 0 else 1e-7) / n
         i2 = vef.vef_plan_query(P.Problem("fine", 1, m, cp2, ec, om, wt, np.ones(ne), np.zeros(ne)))
         assert i2["affine"] == 0
+
+
+def test_lambda_create_rejects_bad_arguments():
+    """vef_lambda_create checks its host arrays before any device call:
+    slot indices out of range, pivots that are not permutations and an
+    unsorted factor pattern are rejected with VEF_ERR_INVALID."""
+    vef = _vef()
+    n, ne, k = 4, 2, 4
+    gidx = np.array([[0, 1, -1, -1], [2, 3, 0, -1]], dtype=np.int32)
+    ptr = np.array([0, 1, 2, 3, 4], dtype=np.int32)
+    ind = np.array([0, 1, 2, 3], dtype=np.int32)
+    val = np.ones(4)
+    piv = np.arange(4, dtype=np.int32)
+
+    def create(g=gidx, pt=ptr, it=ind, pp=piv, pq=piv):
+        h = C.c_void_p()
+        rc = vef.lib.vef_lambda_create(n, ne, k, 3, g.ctypes.data, int(it.size), pt.ctypes.data, it.ctypes.data,
+                                       val.ctypes.data, pp.ctypes.data, pq.ctypes.data, 16, 16, None, C.byref(h))
+        return rc, vef.lib.vef_lambda_error(None).decode()
+
+    bad = gidx.copy()
+    bad[0, 0] = 4
+    assert create(g=bad)[0] == vef.VEF_ERR_INVALID
+    assert create(pp=np.array([0, 1, 1, 3], dtype=np.int32))[0] == vef.VEF_ERR_INVALID
+    assert create(pq=np.array([0, 1, 2, 4], dtype=np.int32))[0] == vef.VEF_ERR_INVALID
+    rc, msg = create(pt=np.array([0, 2, 2, 3, 4], dtype=np.int32), it=np.array([1, 0, 2, 3], dtype=np.int32))
+    assert rc == vef.VEF_ERR_INVALID and "CSR" in msg
+    assert vef.lib.vef_lambda_destroy(None) == vef.VEF_OK
