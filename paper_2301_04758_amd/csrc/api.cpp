@@ -39,9 +39,9 @@ int mode_of(const vefplan::ProblemPlan &pl, int schedule, bool pipeline = true, 
   if (!pl.nopivot) return 0;
   const bool pipe = pipeline && schedule == VEF_DIR_RESIDENT && pl.p <= 2;
   // straight-sided bilinear elements: the pipelined kernel with quadrature
-  // assembly (lagged couplings read the previous sweep from global memory);
-  // its fixup would need the balance weights at the quadrature points
-  if (!pl.affine) return (pipe && pl.m == 1 && !fixup) ? 4 : 1;
+  // assembly (lagged couplings read the previous sweep from global memory)
+  (void)fixup;
+  if (!pl.affine) return (pipe && pl.m == 1) ? 4 : 1;
   return (pipe && pl.n_lagged == 0) ? 3 : 2;
 }
 

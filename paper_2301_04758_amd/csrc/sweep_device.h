@@ -1238,18 +1238,31 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
 #pragma unroll
         for (int i = 0; i < N; ++i) neg |= b[i] < T(0);
         if (neg) {
-          const T stJ = static_cast<T>(sig[2 * e]) * gmem(static_cast<const T *>(pb.geo_a))[(size_t)e * 16];
-          // balance weight of node (a, b): stJ sm_a sm_b plus (Omega . N_f) sm_pos
-          // for each outflow face f through it (sm = row sums of m)
+          // balance weight of node (a, b): sigma_t times the integral of its
+          // basis function (affine: J sm_a sm_b, sm = row sums of m; bilinear:
+          // the quadrature sum with wJ at each point) plus (Omega . N_f) sm_pos
+          // for each outflow face f through it
+          const T ste = static_cast<T>(sig[2 * e]);
+          T stJ = T(0);
+          if constexpr (!GEN) stJ = ste * gmem(static_cast<const T *>(pb.geo_a))[(size_t)e * 16];
           T cx = T(0), cp = T(0);
           for (int i = 0; i < N; ++i) {
             const int a = i % P1, bb = i / P1;
-            T sa = T(0), sb = T(0);
-            for (int c = 0; c < P1; ++c) {
-              sa += m1[a * P1 + c];
-              sb += m1[bb * P1 + c];
+            T cw;
+            if constexpr (GEN) {
+              const VEF_GLOBAL T *gq = gmem(static_cast<const T *>(pb.geo_v) + (size_t)e * Q * 5);
+              const VEF_CONST T *tg = (const VEF_CONST T *)tables_g;
+              T cv = T(0);
+              for (int q = 0; q < Q; ++q) cv += gq[5 * q] * tg[q * N + i];
+              cw = ste * cv;
+            } else {
+              T sa = T(0), sb = T(0);
+              for (int c = 0; c < P1; ++c) {
+                sa += m1[a * P1 + c];
+                sb += m1[bb * P1 + c];
+              }
+              cw = stJ * sa * sb;
             }
-            T cw = stJ * sa * sb;
             for (int f = 0; f < 4; ++f) {
               const bool on_face = (f == 0) ? (bb == 0) : (f == 1) ? (a == P) : (f == 2) ? (bb == P) : (a == 0);
               if (!on_face || ((flags >> f) & 1)) continue;
@@ -1325,9 +1338,7 @@ hipError_t launch_pipe_t(const SweepLaunch &L) {
         return launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT | (FIX ? MODE_FIX : 0)>(L);
       }
     };
-    if constexpr (GEN && FIX) {
-      return rows();  // the fixup's balance weights assume affine elements
-    } else {
+    {
     constexpr int maxw = pipe_max_waves<P, T>();
     const int waves = L.waves > 0 ? (L.waves > maxw ? maxw : L.waves) : maxw;
     const size_t ring_bytes_per_level = (size_t)L.width * 4 * S::P1 * sizeof(T);

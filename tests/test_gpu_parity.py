@@ -465,13 +465,14 @@ def test_timing_stride(torch, schedule):
 def _negative_flux_case(kind):
     """Thick cells with a source in one corner element: the unfixed solution
     dips below zero.  kind selects the kernel family that solves it."""
-    if kind == "trap":  # straight, non-affine: general pivot-free rows
+    if kind in ("trap", "trap1"):  # straight, non-affine (bilinear elements)
         from test_library_host import _trapezoids
+        p = 2 if kind == "trap" else 1
         cp, ec = _trapezoids(7, 0.2, seed=4)
         om, wt = P.level_symmetric_2d(4)
         ne = ec.shape[0]
-        pr = P.Problem("trap_fix", 2, 1, cp, ec, om, wt, np.full(ne, 200.0), np.zeros(ne))
-        pr.q_iso = np.zeros((ne, 9))
+        pr = P.Problem("trap_fix", p, 1, cp, ec, om, wt, np.full(ne, 200.0), np.zeros(ne))
+        pr.q_iso = np.zeros((ne, (p + 1) ** 2))
     else:
         p, m, warp = {"p1": (1, 1, 0.0), "p2": (2, 1, 0.0), "p4": (4, 1, 0.0), "curved": (3, 2, 0.06)}[kind]
         pr = _small(7, 7, p, m, 4, st=200.0, warp=warp, q=0.0)
@@ -481,12 +482,12 @@ def _negative_flux_case(kind):
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("kind", ["p1", "p2", "p4", "trap", "curved"])
+@pytest.mark.parametrize("kind", ["p1", "p2", "p4", "trap", "trap1", "curved"])
 def test_fixup_parity(torch, precision, kind, schedule):
     """Set-to-zero-and-scale fixup inside the sweep against the oracle's, on
     problems whose unfixed solution is negative somewhere (pipelined kernel
-    for affine p <= 2 under the direction-resident schedule, row-per-lane
-    kernels otherwise, pivoting on the curved mesh)."""
+    for affine and bilinear elements with p <= 2 under the direction-resident
+    schedule, row-per-lane kernels otherwise, pivoting on the curved mesh)."""
     from paper_2301_04758_amd import vef
     pr = _negative_flux_case(kind)
     ref = O.sweep(pr, fixup=True)
@@ -498,7 +499,11 @@ def test_fixup_parity(torch, precision, kind, schedule):
     torch.cuda.synchronize()
     sw.check()
     psi = io[0]["psi_out"].double().cpu().numpy()
+    kernel = sw.info[0]["kernel"]
     sw.close()
+    if schedule == "dir" and kind in ("p1", "p2", "trap", "trap1"):
+        assert kernel == (vef.VEF_KERNEL_BILINEAR_PIPELINE if kind.startswith("trap")
+                          else vef.VEF_KERNEL_AFFINE_PIPELINE)
     assert psi.min() >= 0.0
     assert rel_inf(psi, ref["psi"]) <= TOL[precision]
 
