@@ -82,23 +82,30 @@ __global__ void k_recover(const double *__restrict__ sol0, const double *__restr
 }
 
 // Normwise backward error of lambda: out[0] = max_i |r_i - (H lambda)_i|,
-// out[1] = max_i |r_i|, out[2] = max_i sum_j |H_ij|, out[3] = max_i |lambda_i|
-// (one work-group)
-__global__ void __launch_bounds__(1024) k_residual(const int *__restrict__ ptr, const int *__restrict__ ind,
-                                                   const double *__restrict__ val, const double *__restrict__ lam,
-                                                   const double *__restrict__ rhs, int n, double *__restrict__ out) {
-  __shared__ double s_m[4][1024];
+// out[1] = max_i |r_i|, out[2] = max_i sum_j |H_ij|, out[3] = max_i |lambda_i|,
+// as the bit patterns of non-negative doubles (whose unsigned order is their
+// numeric order), so that work-groups combine by atomic max; out starts at 0.
+__global__ void k_zero4(unsigned long long *out) {
+  if (threadIdx.x < 4) out[threadIdx.x] = 0ull;
+}
+
+__global__ void __launch_bounds__(256) k_residual(const int *__restrict__ ptr, const int *__restrict__ ind,
+                                                  const double *__restrict__ val, const double *__restrict__ lam,
+                                                  const double *__restrict__ rhs, int n,
+                                                  unsigned long long *__restrict__ out) {
+  __shared__ double s_m[4][256];
   double m[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
     double acc = rhs[i], rs = 0.0;
     for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
       acc -= val[j] * lam[ind[j]];
       rs += fabs(val[j]);
     }
-    m[0] = fmax(m[0], fabs(acc));
-    m[1] = fmax(m[1], fabs(rhs[i]));
-    m[2] = fmax(m[2], rs);
-    m[3] = fmax(m[3], fabs(lam[i]));
+    m[0] = fabs(acc);
+    m[1] = fabs(rhs[i]);
+    m[2] = rs;
+    m[3] = fabs(lam[i]);
   }
   for (int c = 0; c < 4; ++c) s_m[c][threadIdx.x] = m[c];
   __syncthreads();
@@ -107,7 +114,7 @@ __global__ void __launch_bounds__(1024) k_residual(const int *__restrict__ ptr, 
       for (int c = 0; c < 4; ++c) s_m[c][threadIdx.x] = fmax(s_m[c][threadIdx.x], s_m[c][threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x < 4) out[threadIdx.x] = s_m[threadIdx.x][0];
+  if (threadIdx.x < 4) atomicMax(out + threadIdx.x, (unsigned long long)__double_as_longlong(s_m[threadIdx.x][0]));
 }
 
 template <typename X>
@@ -296,7 +303,10 @@ int vef_lambda_solve(vef_lambda_t *h, const double *hloc, const double *rloc, co
     if (he != hipSuccess) return lam_hip(h, he, "launch recovery");
   }
   if (rel_resid) {
-    hipLaunchKernelGGL(k_residual, dim3(1), dim3(1024), 0, s, h->ptr, h->ind, h->val, lam, h->rhs, h->n, h->red);
+    auto *red = reinterpret_cast<unsigned long long *>(h->red);
+    hipLaunchKernelGGL(k_zero4, dim3(1), dim3(64), 0, s, red);
+    hipLaunchKernelGGL(k_residual, dim3((h->n + 255) / 256), dim3(256), 0, s, h->ptr, h->ind, h->val, lam, h->rhs,
+                       h->n, red);
     double r[4] = {0.0, 0.0, 0.0, 0.0};
     he = hipGetLastError();
     if (he == hipSuccess) he = hipMemcpyAsync(r, h->red, sizeof(r), hipMemcpyDeviceToHost, s);
