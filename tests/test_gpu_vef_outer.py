@@ -233,3 +233,75 @@ def test_device_lambda_solve_refactorises_when_the_residual_grows(torch):
     finally:
         dev.close()
         host.close()
+
+
+@pytest.mark.parametrize("n_side,k", [(6, 8), (11, 12)])
+def test_lambda_solver_c_abi(torch, n_side, k):
+    """vef_lambda_create / vef_lambda_solve on a synthetic element-assembled
+    system (k slots per element on a periodic-free grid of elements that
+    share slots with their right and upper neighbours): the device solve of
+    a second matrix of the same pattern, re-factorised with the pivots of
+    the first, against scipy's sparse solve; the recovery against numpy."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    from paper_2301_04758_amd import vef
+    rng = np.random.default_rng(n_side + k)
+    P1 = k // 4
+    # faces of an n_side x n_side grid: horizontal then vertical, interior only
+    def hface(i, j):  # between element (i, j) and (i, j + 1)
+        return i * (n_side - 1) + j
+    def vface(i, j):  # between element (i, j) and (i + 1, j)
+        return n_side * (n_side - 1) + i * n_side + j
+    ne = n_side * n_side
+    fid = -np.ones((ne, 4), dtype=np.int64)
+    for i in range(n_side):
+        for j in range(n_side):
+            e = i * n_side + j
+            if i > 0: fid[e, 0] = vface(i - 1, j)
+            if j < n_side - 1: fid[e, 1] = hface(i, j)
+            if i < n_side - 1: fid[e, 2] = vface(i, j)
+            if j > 0: fid[e, 3] = hface(i, j - 1)
+    n = 2 * n_side * (n_side - 1) * P1
+    gidx = np.where(fid[:, :, None] >= 0, fid[:, :, None] * P1 + np.arange(P1), -1).reshape(ne, k)
+    ok = gidx >= 0
+
+    def system(h, r):
+        rows = np.repeat(gidx[:, :, None], k, axis=2)
+        cols = np.repeat(gidx[:, None, :], k, axis=1)
+        m = ok[:, :, None] & ok[:, None, :]
+        H = sp.csr_matrix((h[m], (rows[m], cols[m])), shape=(n, n))
+        b = np.zeros(n)
+        np.add.at(b, gidx[ok], r[ok])
+        return H.tocsc(), b
+
+    h0 = rng.standard_normal((ne, k, k)) + 6 * np.eye(k)
+    r0 = rng.standard_normal((ne, k))
+    H0, _ = system(h0, r0)
+    lu = spl.splu(H0, permc_spec="MMD_AT_PLUS_A")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nloc = 5
+    solver = vef.LambdaSolver(gidx, nloc, lu, dev(h0), dev(r0))
+    try:
+        h1 = h0 * (1 + 0.1 * rng.standard_normal(h0.shape))
+        r1 = rng.standard_normal((ne, k))
+        sol0 = rng.standard_normal((ne, nloc))
+        resp = rng.standard_normal((ne, nloc, k))
+        lam, sol, eta = solver.solve(dev(h1), dev(r1), dev(sol0), dev(resp))
+        torch.cuda.synchronize()
+        H1, b1 = system(h1, r1)
+        ref = spl.spsolve(H1, b1)
+        lam = lam.cpu().numpy()
+        print("n %d rel err %.2e backward error %.2e" % (n, np.abs(lam - ref).max() / np.abs(ref).max(), eta),
+              flush=True)
+        assert np.abs(lam - ref).max() <= 1e-9 * np.abs(ref).max()
+        assert eta <= 1e-13
+        lam_loc = np.where(ok, lam[np.maximum(gidx, 0)], 0.0)
+        want = sol0 - np.einsum("erk,ek->er", resp, lam_loc)
+        assert np.abs(sol.cpu().numpy() - want).max() <= 1e-12 * np.abs(want).max()
+        # without the recovery and the residual
+        lam2, sol2, eta2 = solver.solve(dev(h1), dev(r1), want_resid=False)
+        torch.cuda.synchronize()
+        assert sol2 is None and eta2 is None
+        assert np.array_equal(lam2.cpu().numpy(), lam)
+    finally:
+        solver.close()
