@@ -305,3 +305,32 @@ def test_lambda_solver_c_abi(torch, n_side, k):
         assert np.array_equal(lam2.cpu().numpy(), lam)
     finally:
         solver.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (1, 3)])
+def test_outer_iteration_on_tiny_meshes(torch, nx, ny):
+    """Edge cases of the reduced system: no interior face (1 x 1: the
+    driver solves the empty system on the host), a single interior face
+    (2 x 1: one (p+1)-block) and a strip; iterates against the oracle's."""
+    from paper_2301_04758_amd.vef_outer import VefOuter
+    cp, ec = P.quad_mesh(nx, ny, 1)
+    om, wt = P.level_symmetric_2d(4)
+    ne = ec.shape[0]
+    eps = 1e-2
+    pr = P.Problem("tiny", 2, 1, cp, ec, om, wt, np.full(ne, 1 / eps), np.full(ne, 1 / eps - eps), nx=nx, ny=ny,
+                   nq=4)
+    pr.q_iso = np.full((ne, 9), eps / (4 * math.pi))
+    ref = V.outer_iteration(pr, 4, 3)
+    tol = max(1e-12, 64 * np.finfo(float).eps * _kappa(pr))
+    drv = VefOuter(pr)
+    try:
+        assert drv.n_faces == (nx - 1) * ny + nx * (ny - 1)
+        phi = None
+        for k in range(3):
+            phi, leg, _ = drv.step(phi)
+            err = np.abs(leg - ref[k]).max() / np.abs(ref[k]).max()
+            print("%dx%d iteration %d rel err %.2e (bound %.1e)" % (nx, ny, k + 1, err, tol), flush=True)
+            assert err <= tol
+        assert drv.host_factorisations == (1 if drv.n_faces else 0)
+    finally:
+        drv.close()
