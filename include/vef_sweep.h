@@ -61,7 +61,9 @@ enum {
   VEF_ERR_JACOBIAN = -3, /* element map with J <= 0 at a quadrature point */
   VEF_ERR_HIP = -4,      /* HIP runtime failure (no device, launch error) */
   VEF_ERR_OOM = -5,      /* device or host allocation failed */
-  VEF_ERR_TIMEOUT = -6   /* reserved: bounded device wait expired */
+  VEF_ERR_TIMEOUT = -6   /* a bounded device-side wait of a sweep kernel
+                            expired (vef_sweep_check; bound set by
+                            vef_options.wait_polls) */
 };
 
 enum { VEF_FP64 = 0, VEF_FP32_LOCAL = 1 };
@@ -160,6 +162,14 @@ typedef struct {
                     depend on each other and the sweep needs
                     VEF_CYCLES_LAG.  Straight faces give the same result
                     under both rules.  Not combined with the fixup. */
+  long long wait_polls; /* bound of one device-side wait of a sweep kernel
+                    that waits for upwind work of other waves (the pipelined
+                    kernel), in polls of about 64 clocks each; 0 = default
+                    2^26 (seconds: a healthy wait takes microseconds).  When a
+                    wait exceeds it the kernel stops its sweep early, every
+                    wave exits normally and vef_sweep_check reports
+                    VEF_ERR_TIMEOUT (the outputs of that run are then
+                    incomplete).  Small values exist to test that path. */
 } vef_options;
 
 /* Per-problem device buffers of one run (device pointers owned by the caller).
@@ -429,11 +439,12 @@ typedef struct {
  * configuration. */
 int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int reps, vef_tune_result *out);
 
-/* Synchronise the handle's last stream and return the device status word:
- * VEF_OK; VEF_ERR_INVALID when a local solve produced a non-finite unknown
- * (singular or overflowing local system); VEF_ERR_TIMEOUT when a bounded
- * device-side wait of the pipelined kernel expired (the kernel then exits
- * without finishing the sweep). */
+/* Synchronise the handle's last stream and return the device status word of
+ * the last run (each run clears it when it starts): VEF_OK; VEF_ERR_INVALID
+ * when a local solve produced a non-finite unknown (singular or overflowing
+ * local system); VEF_ERR_TIMEOUT when a bounded device-side wait of a sweep
+ * kernel expired (vef_options.wait_polls; the kernel then exits without
+ * finishing the sweep). */
 int vef_sweep_check(vef_sweep_t *h);
 
 /* Timing of the last run on a handle created with opt->timing != 0:

@@ -94,6 +94,7 @@ struct vef_sweep {
   std::vector<double *> resid_scratch;
   std::vector<int> resid_cap;
   int *d_flags = nullptr;  // [0] stop, [1] iterations done, [2] status
+  long long wait_polls = 1LL << 26;  // bound of one device-side wait (polls)
   hipStream_t last_stream = nullptr;
   bool timing = false;
   int timing_stride = 0;  // time every timing_stride-th source iteration (and the last)
@@ -216,6 +217,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (opt->upwind == VEF_UPWIND_POINT && opt->fixup)
       return set_err(h, VEF_ERR_INVALID, "the fixup is not available with pointwise upwinding");
     h->upwind = opt->upwind;
+    if (opt->wait_polls < 0) return set_err(h, VEF_ERR_INVALID, "wait_polls must be >= 0");
+    if (opt->wait_polls > 0) h->wait_polls = opt->wait_polls;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
   }
@@ -480,13 +483,19 @@ int vef_sweep_create(const vef_problem_desc *probs, int n_probs, const vef_optio
   return VEF_OK;
 }
 
-int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// One run (vef_sweep_run).
+int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream) {
   if (!h) return VEF_ERR_INVALID;
   if (!a || !a->io || a->n_iter < 1) return set_err(h, VEF_ERR_INVALID, "bad run arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int np = (int)h->plans.size();
   const bool fp32 = h->precision == VEF_FP32_LOCAL;
   const size_t esz = fp32 ? sizeof(float) : sizeof(double);
+  const bool timing = h->timing;
   hipError_t he;
   std::vector<vefk::KIO> io(np);
   for (int k = 0; k < np; ++k) {
@@ -534,7 +543,8 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
     h->io_valid = true;
   }
   int *stop = h->d_flags, *iters = h->d_flags + 1, *status = h->d_flags + 2;
-  if (h->timing) {
+  if (!timing) h->timed_iters = 0;
+  if (timing) {
     while ((int)h->events.size() < 2 * a->n_iter) {
       hipEvent_t ev;
       he = hipEventCreate(&ev);
@@ -545,9 +555,9 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
     h->timed_launches = 0;
   }
   auto timed = [&](int it) {
-    return h->timing && ((it + 1) % h->timing_stride == 0 || it == a->n_iter - 1);
+    return timing && ((it + 1) % h->timing_stride == 0 || it == a->n_iter - 1);
   };
-  he = vefk::launch_run_init(h->d_io, np, a->n_iter, stop, iters, s);
+  he = vefk::launch_run_init(h->d_io, np, a->n_iter, stop, iters, status, s);
   if (he != hipSuccess) return hip_fail(h, he, "launch init");
   for (int it = 0; it < a->n_iter; ++it) {
     if (timed(it) && (he = hipEventRecord(h->events[2 * it], s)) != hipSuccess)
@@ -565,7 +575,7 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
     SL.waves = h->pipeline_waves > 0 ? h->pipeline_waves : 0;
     SL.ring = h->pipeline_ring;
     SL.fixup = h->fixup;
-    SL.wait_spins = 1LL << 26;  // seconds of polling: a healthy wait takes microseconds
+    SL.wait_spins = h->wait_polls;
     if (h->schedule == VEF_LEVEL_SYNC) {
       for (auto &lv : h->levels)
         for (auto &L : lv) {
@@ -620,6 +630,12 @@ int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) {
   h->last_stream = s;
   return VEF_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) { return run_impl(h, a, stream); }
 
 int vef_moments(vef_sweep_t *h, const vef_moment_io *io, void *stream) {
   if (!h) return VEF_ERR_INVALID;

@@ -84,7 +84,7 @@ hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob
                           const int *stop, hipStream_t s);
 hipError_t launch_boundary(bool fp32, const KProb *probs, const KIO *io, int prob, int nbf, int nq,
                            int p, const int *stop, hipStream_t s);
-hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, int *iters,
+hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, int *iters, int *status,
                            hipStream_t s);
 hipError_t launch_finalize(const KIO *io, int n_probs, int it, double tol, int *stop, int *iters,
                            int *iters_user, hipStream_t s);

@@ -124,11 +124,12 @@ k_boundary(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob
 }
 
 __global__ void k_run_init(const KIO *__restrict__ io, int n_probs, int n_iter, int *stop,
-                           int *iters) {
+                           int *iters, int *status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     *stop = 0;
     *iters = 0;
+    *status = 0;  // the status word reports the current run only
   }
   if (i < n_probs * n_iter) {
     double *r = io[i / n_iter].resid;
@@ -280,11 +281,11 @@ hipError_t launch_boundary(bool fp32, const KProb *probs, const KIO *io, int pro
   return hipGetLastError();
 }
 
-hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, int *iters,
+hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, int *iters, int *status,
                            hipStream_t s) {
   const int tot = n_probs * n_iter;
   const int grid = (tot + 255) / 256 > 0 ? (tot + 255) / 256 : 1;
-  hipLaunchKernelGGL(k_run_init, dim3(grid), dim3(256), 0, s, io, n_probs, n_iter, stop, iters);
+  hipLaunchKernelGGL(k_run_init, dim3(grid), dim3(256), 0, s, io, n_probs, n_iter, stop, iters, status);
   return hipGetLastError();
 }
 

@@ -1180,14 +1180,13 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       if (L > 0) {
         long long spins = 0;
         while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < before) {
-          if ((++spins & 63) == 0) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
-            if (spins > wait_spins) {
-              __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-              if (lane == 0) atomicOr(status, 2);
-              return;
-            }
+          if (++spins > wait_spins) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lane == 0) atomicOr(status, 2);
+            return;
           }
+          if ((spins & 63) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
           __builtin_amdgcn_s_sleep(1);
         }
       }

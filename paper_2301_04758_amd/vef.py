@@ -56,7 +56,7 @@ class vef_problem_desc(C.Structure):
 class vef_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("schedule", C.c_int), ("block", C.c_int), ("timing", C.c_int),
                 ("pipeline_waves", C.c_int), ("pipeline_ring", C.c_int), ("fixup", C.c_int),
-                ("cycles", C.c_int), ("upwind", C.c_int)]
+                ("cycles", C.c_int), ("upwind", C.c_int), ("wait_polls", C.c_longlong)]
 
 
 class vef_problem_io(C.Structure):
@@ -182,12 +182,12 @@ def vef_plan_query(problem, lag_cycles: bool = False, pointwise: bool = False) -
 def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
                      block: int = 0, timing: int = 0, pipeline_waves: int = 0,
                      pipeline_ring: int = 0, fixup: bool = False, lag_cycles: bool = False,
-                     pointwise: bool = False) -> int:
+                     pointwise: bool = False, wait_polls: int = 0) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
     opt = vef_options(precision, schedule, block, int(timing), pipeline_waves, pipeline_ring,
                       1 if fixup else 0, VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT,
-                      VEF_UPWIND_POINT if pointwise else VEF_UPWIND_FACE)
+                      VEF_UPWIND_POINT if pointwise else VEF_UPWIND_FACE, int(wait_polls))
     h = C.c_void_p()
     rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))
     if rc != VEF_OK:
@@ -195,12 +195,16 @@ def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: in
     return h.value
 
 
-def vef_sweep_run(h: int, io: Sequence[dict], n_iter: int = 1, tol: float = 0.0, iters_done=None, stream=None):
+def _run_args(io, n_iter, tol, iters_done):
     arr = (vef_problem_io * len(io))()
     for k, b in enumerate(io):
         arr[k] = vef_problem_io(_ptr(b.get("phi_in")), _ptr(b.get("q_iso")), _ptr(b.get("q_dir")),
                                 _ptr(b.get("psi_bc")), _ptr(b["mom"]), _ptr(b.get("psi_out")), _ptr(b.get("resid")))
-    args = vef_run_args(arr, int(n_iter), float(tol), _ptr(iters_done))
+    return vef_run_args(arr, int(n_iter), float(tol), _ptr(iters_done)), arr
+
+
+def vef_sweep_run(h: int, io: Sequence[dict], n_iter: int = 1, tol: float = 0.0, iters_done=None, stream=None):
+    args, _keep = _run_args(io, n_iter, tol, iters_done)
     rc = lib.vef_sweep_run(C.c_void_p(h), C.byref(args), C.c_void_p(_stream_handle(stream)))
     if rc != VEF_OK:
         raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
@@ -368,7 +372,7 @@ class Sweep:
     """Owns one handle; allocates device buffers with torch for convenience."""
 
     def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto",
-                 pipeline_waves=0, pipeline_ring=0, fixup=False, lag_cycles=False, pointwise=False):
+                 pipeline_waves=0, pipeline_ring=0, fixup=False, lag_cycles=False, pointwise=False, wait_polls=0):
         import torch
         self.torch = torch
         self.problems = list(problems)
@@ -377,7 +381,7 @@ class Sweep:
         with torch.cuda.device(self.device):
             self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64,
                                       SCHEDULES[schedule], block, timing, pipeline_waves, pipeline_ring,
-                                      fixup, lag_cycles, pointwise)
+                                      fixup, lag_cycles, pointwise, wait_polls)
         self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
 
     def close(self):

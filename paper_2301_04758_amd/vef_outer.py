@@ -417,9 +417,12 @@ class VefOuter:
         phi_lob = phi_leg @ ref.leg_at_lob.T
         return phi_lob, phi_leg, Jc
 
-    def solve(self, max_outer=50, tol=1e-8, phi0=None, anderson=0):
+    def solve(self, max_outer=50, tol=1e-8, phi0=None, anderson=0, stop="relative"):
         """Outer iterations on the VEF scalar flux x (Gauss-Legendre nodal;
-        phi0 None = 0) until max|x_new - x_old| <= tol max|x_new|.  anderson
+        phi0 None = 0) until max|x_new - x_old| <= tol max|x_new| (stop =
+        "relative"), or until max|x_new - x_old| <= tol (stop = "max_norm":
+        the max norm of the difference of successive iterates, the paper's
+        termination rule in Sec. 8).  anderson
         > 0 accelerates the fixed point x = G(x) (G: sweep, closures, VEF
         solve) with that many difference vectors, as the paper's outer solver
         does (Sec. 8 uses two): x_new = G(x) - dG gamma, gamma the least-squares
@@ -427,6 +430,8 @@ class VefOuter:
         residuals (dG the differences of G values).  anderson = 0 is the plain
         fixed point of Sec. 2.  Returns dict(phi_leg, phi_lob, J (of the last
         evaluation of G), iterations, history)."""
+        if stop not in ("relative", "max_norm"):
+            raise ValueError("stop must be 'relative' or 'max_norm'")
         ref = self.ref
         shape = (self.pr.n_elem, ref.nphi)
         x = np.zeros(shape) if phi0 is None else np.asarray(phi0, dtype=float).reshape(shape)
@@ -448,7 +453,9 @@ class VefOuter:
             f_prev, g_prev = f, g
             done = False
             if it > 1:
-                r = float(np.abs(x_new - x).max() / max(np.abs(x_new).max(), 1e-300))
+                r = float(np.abs(x_new - x).max())
+                if stop == "relative":
+                    r /= max(float(np.abs(x_new).max()), 1e-300)
                 self.history.append(r)
                 done = r <= tol
             x = x_new
