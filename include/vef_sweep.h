@@ -263,6 +263,26 @@ int vef_sweep_create(const vef_problem_desc *probs, int n_probs, const vef_optio
  * so it can be captured in a HIP graph after one eager call. */
 int vef_sweep_run(vef_sweep_t *h, const vef_run_args *args, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * run as vef_sweep_run, with the same kernels and results, that calls no
+ * hipMalloc, hipFree or other allocating routine.  Differences:
+ *   - a problem whose io.resid is NULL gets its per-sweep residuals (used by
+ *     the device-side stop test) in a static device array of the library,
+ *     VEF_STATIC_RESID_MAX doubles per GPU, shared by every handle and every
+ *     call on that GPU and cleared by each run before use; the run fails with
+ *     VEF_ERR_INVALID when the problems with a NULL resid need more than
+ *     n_iter x (their count) > VEF_STATIC_RESID_MAX doubles.  Calls that
+ *     overlap on one GPU (other streams, other threads) race on that array;
+ *   - io.psi_out may be NULL only for a problem whose handle already holds its
+ *     own angular flux (a problem with lagged couplings, or after an earlier
+ *     vef_sweep_run with psi_out NULL); otherwise VEF_ERR_INVALID;
+ *   - no timing events are recorded (vef_options.timing is ignored).
+ * The static array's device address is looked up once per device when the
+ * first handle on that device is created. */
+#define VEF_STATIC_RESID_MAX 65536
+int vef_sweep_run_static(vef_sweep_t *h, const vef_run_args *args, void *stream);
+
 /* Enqueue the closure kernels for every problem (io: host array [n_probs]),
  * reading the boundary sums of the last run on h.  A call whose pointers
  * equal the previous call's issues only kernel launches, so it can be

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -95,6 +96,7 @@ struct vef_sweep {
   std::vector<int> resid_cap;
   int *d_flags = nullptr;  // [0] stop, [1] iterations done, [2] status
   long long wait_polls = 1LL << 26;  // bound of one device-side wait (polls)
+  double *static_resid = nullptr;    // this device's copy of `scratch` (vef_sweep_run_static)
   hipStream_t last_stream = nullptr;
   bool timing = false;
   int timing_stride = 0;  // time every timing_stride-th source iteration (and the last)
@@ -110,7 +112,33 @@ struct vef_sweep {
   int timed_launches = 0;
 };
 
+// Per-sweep residuals of runs whose caller passes no residual buffer, for
+// vef_sweep_run_static (no allocation in that call).  One copy per GPU, held
+// until the process ends; every handle and call on that GPU shares it.  Host
+// code never passes the array's name to a kernel: it uses the device address
+// returned by hipGetSymbolAddress for the device that is current.
+static __device__ __align__(256) double scratch[VEF_STATIC_RESID_MAX];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_addr;  // device -> address of its `scratch`
+
+// Address of `scratch` on `device`, which must be the current device; looked
+// up once per device.
+hipError_t static_scratch_address(int device, double **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it == g_scratch_addr.end()) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    it = g_scratch_addr.emplace(device, static_cast<double *>(ptr)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
 
 int set_err(vef_sweep *h, int code, const std::string &msg) {
   if (h)
@@ -232,6 +260,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   }
   hipError_t he = hipGetDevice(&h->device);
   if (he != hipSuccess) return hip_fail(h, he, "hipGetDevice");
+  he = static_scratch_address(h->device, &h->static_resid);
+  if (he != hipSuccess) return hip_fail(h, he, "hipGetSymbolAddress of the static residual array");
   int lds = 0;
   he = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
   if (he != hipSuccess) return hip_fail(h, he, "hipDeviceGetAttribute");
@@ -487,21 +517,38 @@ int vef_sweep_create(const vef_problem_desc *probs, int n_probs, const vef_optio
 
 namespace {
 
-// One run (vef_sweep_run).
-int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream) {
+// One run (vef_sweep_run).  no_alloc (vef_sweep_run_static): residuals of
+// problems without a caller buffer go to the static array, an internal
+// angular flux must already exist, and no timing events are recorded, so that
+// the call allocates nothing.
+int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc) {
   if (!h) return VEF_ERR_INVALID;
   if (!a || !a->io || a->n_iter < 1) return set_err(h, VEF_ERR_INVALID, "bad run arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int np = (int)h->plans.size();
   const bool fp32 = h->precision == VEF_FP32_LOCAL;
   const size_t esz = fp32 ? sizeof(float) : sizeof(double);
-  const bool timing = h->timing;
+  const bool timing = h->timing && !no_alloc;
   hipError_t he;
   std::vector<vefk::KIO> io(np);
+  size_t static_used = 0;
+  for (int k = 0; k < np; ++k) {
+    const vef_problem_io &u = a->io[k];
+    if (!u.mom) return set_err(h, VEF_ERR_INVALID, "mom is NULL for problem " + std::to_string(k));
+    if (no_alloc && !u.psi_out && !h->psi_internal[k])
+      return set_err(h, VEF_ERR_INVALID, "psi_out is NULL for problem " + std::to_string(k) +
+                                             ", which has no internal angular flux yet");
+    if (no_alloc && !u.resid) {
+      if (static_used + (size_t)a->n_iter > (size_t)VEF_STATIC_RESID_MAX)
+        return set_err(h, VEF_ERR_INVALID, "the residuals of problems without a resid buffer need more than "
+                                           "VEF_STATIC_RESID_MAX doubles");
+      static_used += (size_t)a->n_iter;
+    }
+  }
+  static_used = 0;
   for (int k = 0; k < np; ++k) {
     const vef_problem_io &u = a->io[k];
     const auto &pl = h->plans[k];
-    if (!u.mom) return set_err(h, VEF_ERR_INVALID, "mom is NULL for problem " + std::to_string(k));
     void *psi = u.psi_out;
     if (!psi) {
       if (!h->psi_internal[k]) {
@@ -514,7 +561,10 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream) {
       psi = h->psi_internal[k];
     }
     double *resid = u.resid;
-    if (!resid) {
+    if (!resid && no_alloc) {
+      resid = h->static_resid + static_used;
+      static_used += (size_t)a->n_iter;
+    } else if (!resid) {
       if (h->resid_cap[k] < a->n_iter) {
         if (h->resid_scratch[k]) {
           (void)hipDeviceSynchronize();
@@ -635,7 +685,11 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream) {
 
 extern "C" {
 
-int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) { return run_impl(h, a, stream); }
+int vef_sweep_run(vef_sweep_t *h, const vef_run_args *a, void *stream) { return run_impl(h, a, stream, false); }
+
+int vef_sweep_run_static(vef_sweep_t *h, const vef_run_args *a, void *stream) {
+  return run_impl(h, a, stream, true);
+}
 
 int vef_moments(vef_sweep_t *h, const vef_moment_io *io, void *stream) {
   if (!h) return VEF_ERR_INVALID;

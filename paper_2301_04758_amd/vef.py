@@ -25,6 +25,7 @@ VEF_ERR_JACOBIAN = -3
 VEF_ERR_HIP = -4
 VEF_ERR_OOM = -5
 VEF_ERR_TIMEOUT = -6
+VEF_STATIC_RESID_MAX = 65536  # doubles of the static residual array (vef_sweep_run_static)
 VEF_FP64 = 0
 VEF_FP32_LOCAL = 1
 VEF_CYCLES_REJECT = 0
@@ -40,7 +41,7 @@ VEF_KERNEL_BILINEAR_PIPELINE = 4
 KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KERNEL_AFFINE: "affine",
                 VEF_KERNEL_AFFINE_PIPELINE: "affine_pipeline", VEF_KERNEL_BILINEAR_PIPELINE: "bilinear_pipeline"}
 
-EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
+EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_sweep_run_static", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
             "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_hrt_reduce", "vef_last_error",
             "vef_status_string", "vef_lambda_create", "vef_lambda_solve", "vef_lambda_destroy", "vef_lambda_error")
@@ -95,6 +96,7 @@ def _load():
     H = C.c_void_p
     L.vef_sweep_create.argtypes = [C.POINTER(vef_problem_desc), C.c_int, C.POINTER(vef_options), C.POINTER(H)]
     L.vef_sweep_run.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p]
+    L.vef_sweep_run_static.argtypes = [H, C.POINTER(vef_run_args), C.c_void_p]
     L.vef_moments.argtypes = [H, C.POINTER(vef_moment_io), C.c_void_p]
     L.vef_sweep_destroy.argtypes = [H]
     L.vef_plan_query.argtypes = [C.POINTER(vef_problem_desc), C.POINTER(vef_options), C.POINTER(vef_info)]
@@ -115,7 +117,7 @@ def _load():
     L.vef_last_error.restype = C.c_char_p
     L.vef_status_string.argtypes = [C.c_int]
     L.vef_status_string.restype = C.c_char_p
-    for f in ("vef_sweep_create", "vef_sweep_run", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
+    for f in ("vef_sweep_create", "vef_sweep_run", "vef_sweep_run_static", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
               "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
               "vef_sweep_autotune", "vef_probe_machine", "vef_hrt_local_inverse", "vef_hrt_reduce",
               "vef_lambda_create", "vef_lambda_solve", "vef_lambda_destroy"):
@@ -206,6 +208,16 @@ def _run_args(io, n_iter, tol, iters_done):
 def vef_sweep_run(h: int, io: Sequence[dict], n_iter: int = 1, tol: float = 0.0, iters_done=None, stream=None):
     args, _keep = _run_args(io, n_iter, tol, iters_done)
     rc = lib.vef_sweep_run(C.c_void_p(h), C.byref(args), C.c_void_p(_stream_handle(stream)))
+    if rc != VEF_OK:
+        raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
+
+
+def vef_sweep_run_static(h: int, io: Sequence[dict], n_iter: int = 1, tol: float = 0.0, iters_done=None,
+                         stream=None):
+    """The run of vef_sweep_run without any device allocation (residuals of
+    problems without a "resid" buffer in the library's static array)."""
+    args, _keep = _run_args(io, n_iter, tol, iters_done)
+    rc = lib.vef_sweep_run_static(C.c_void_p(h), C.byref(args), C.c_void_p(_stream_handle(stream)))
     if rc != VEF_OK:
         raise VefError(rc, lib.vef_last_error(C.c_void_p(h)).decode())
 

@@ -201,3 +201,11 @@ def test_lambda_create_rejects_bad_arguments():
     rc, msg = create(pt=np.array([0, 2, 2, 3, 4], dtype=np.int32), it=np.array([1, 0, 2, 3], dtype=np.int32))
     assert rc == vef.VEF_ERR_INVALID and "CSR" in msg
     assert vef.lib.vef_lambda_destroy(None) == vef.VEF_OK
+
+
+def test_static_resid_limit_matches_header():
+    """The binding's copy of VEF_STATIC_RESID_MAX (vef_sweep_run_static) is
+    the header's."""
+    vef = _vef()
+    m = re.search(r"#define\s+VEF_STATIC_RESID_MAX\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == vef.VEF_STATIC_RESID_MAX
