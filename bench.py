@@ -2,17 +2,21 @@
 """Benchmark of the DG S_N sweep + VEF-moment path on one MI355X.
 
 One step = one full pass of the hot path over the synthetic workload with all
-inputs already in HBM: for the default workload (64x64 quadrilaterals, p = 2,
-level-symmetric S8 = 40 directions, sigma_t log-uniform in [0.1, 100] per 8x8
-block, scattering ratio 0.9, isotropic source 1, vacuum boundaries) that is 50
-source iterations -- each a full transport sweep (assembly + local solve of
-every element-direction pair in upwind order), the angular moments, the
-boundary sums and the max-norm residual -- followed by the VEF closures.
-The handle (host plan + upload) is created outside the timed region.
+inputs already in HBM.  The default workload is the largest single-GPU
+configuration, the thick diffusive regime: 512x512 quadrilaterals, p = 4 (25
+unknowns per element), the 144-direction level-symmetric S16 set,
+sigma_t = 1000, sigma_s = 999.9, isotropic source 1, vacuum boundaries; a step
+is one transport sweep (assembly + local solve of every element-direction
+pair in upwind order) with the angular moments, the boundary sums, the
+max-norm residual and the VEF closures.  The handle (host plan + upload) is
+created outside the timed region.
 
 Prints one JSON line.  Metric: element-direction solves per second
 (elements x directions x sweeps / time).  The roofline object refers to the
-dominant kernel (the sweep kernel), timed with HIP events on its own stream.
+sweep kernel, timed with HIP events on the stream it is launched on; its
+algorithmic flops and bytes per solve are those of the method (pivoted LU,
+two triangular solves, assembly from element matrices, face terms, moments),
+not of the implementation.
 """
 import argparse
 import json
@@ -26,25 +30,66 @@ sys.path.insert(0, ROOT)
 
 METRIC = "element-direction solves/sec and HBM GB/s; FP32 batched vs FP64 sweep at 1e-5"
 FP64_PEAK_TFLOPS = 78.6    # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
-FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (packed forms)
 HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+WORKLOADS = {
+    "c5": dict(n_iter=1, fixture="c5_full.json",
+               text="512x512 straight quads, p=4 (25 unknowns/element), S16 (144 directions, LS16-moment set), "
+                    "sigma_t=1000, sigma_s=999.9 (c=0.9999), isotropic source 1, vacuum; one transport sweep "
+                    "with moments, boundary sums, residual and VEF closures per step"),
+    "c3": dict(n_iter=1, fixture="c3_full.json",
+               text="256x256 quads curved by 0.1 sin(pi x) sin(pi y)(1,1) (quadratic geometry), p=3, S12 "
+                    "(84 directions), sigma_t U[1,10] per element, c=0.5, isotropic source 1, vacuum; one sweep "
+                    "with moments and closures per step"),
+    "c2": dict(n_iter=50, fixture="c2_full.json",
+               text="64x64 quads, p=2, S8 (40 directions), sigma_t log-uniform [0.1,100] per 8x8 block, c=0.9, "
+                    "isotropic source 1, vacuum; 50 source iterations + closures per step"),
+}
 
 
-def sweep_flops_per_solve(p):
-    """Algorithmic flops of one element-direction solve in the sweep kernel:
-    LU with pivoting (2/3 n^3) + two triangular solves (2 n^2) + A = sigma_t M +
-    Omega_x G^x + Omega_y G^y (6 n^2) + b = M s (2 n^2) + four face terms (12 (p+1)^2)."""
+def flops_per_solve(p):
+    """Algorithmic flops of one element-direction solve: LU (2/3 n^3), two
+    triangular solves (2 n^2), A = sigma_t M + Omega_x G^x + Omega_y G^y
+    (6 n^2), b = M s (2 n^2), two outflow and two inflow face terms
+    (12 (p+1)^2) and the six angular moments (12 n)."""
     n = (p + 1) ** 2
-    return (2.0 / 3.0) * n ** 3 + 2 * n * n + 6 * n * n + 2 * n * n + 12 * (p + 1) ** 2
+    return (2.0 / 3.0) * n ** 3 + 2 * n * n + 6 * n * n + 2 * n * n + 12 * (p + 1) ** 2 + 12 * n
 
 
-def sweep_bytes_per_solve(p, m, n_dir, s):
-    """Algorithmic HBM bytes of one solve in the sweep kernel: psi write (n s),
-    upwind trace read (2 (p+1) s), and the element data (control points,
-    cross sections, scalar-flux coefficients) amortised over the n_dir/4
-    directions of a quadrant that visit the element together."""
+def bytes_per_solve(p, m, n_dir, s):
+    """Algorithmic HBM bytes of one solve: the angular flux written (n s), the
+    upwind trace read (2 (p+1) s), and per element the control points, cross
+    sections, scalar-flux coefficients and six moments (48 n), amortised over
+    the n_dir / 4 directions of a quadrant that visit the element together.
+    s = 8 (double) or 4 (float angular flux)."""
     n = (p + 1) ** 2
-    return n * s + 2 * (p + 1) * s + ((m + 1) ** 2 * 16 + 16 + 8 * n) / (n_dir / 4.0)
+    return n * s + 2 * (p + 1) * s + ((m + 1) ** 2 * 16 + 16 + 8 * n + 48 * n) / (n_dir / 4.0)
+
+
+def roofline(probs, s, sweep_s, launches_per_sweep, kernel, alu_peak, traffic=None):
+    """Roofline of the sweep kernel over one sweep of probs: algorithmic flops
+    and bytes per launch against the average launch duration; the bound is
+    the ALU when F/B exceeds the machine balance, else HBM."""
+    F = sum(pr.n_elem * pr.n_dir * flops_per_solve(pr.p) for pr in probs)
+    B = sum(pr.n_elem * pr.n_dir * bytes_per_solve(pr.p, pr.m, pr.n_dir, s) for pr in probs)
+    solves = sum(pr.n_elem * pr.n_dir for pr in probs)
+    L = max(launches_per_sweep, 1)
+    avg = sweep_s / L
+    balance = alu_peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if F / B > balance:
+        out = {"bound": "alu", "achieved": F / L / avg / 1e12, "peak": alu_peak, "unit": "TFLOP/s"}
+    else:
+        out = {"bound": "hbm", "achieved": B / L / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    out["frac"] = out["achieved"] / out["peak"]
+    out["traffic"] = traffic
+    out.update(kernel=kernel, launches_per_sweep=L, avg_launch_us=avg * 1e6,
+               algorithmic_flops_per_solve=F / solves, algorithmic_bytes_per_solve=B / solves,
+               flop_per_byte=F / B, machine_balance_flop_per_byte=balance,
+               algorithmic_hbm_gbs=B / sweep_s / 1e9, hbm_frac=B / sweep_s / 1e9 / HBM_PEAK_GBS,
+               alu_tflops=F / sweep_s / 1e12, alu_frac=F / sweep_s / 1e12 / alu_peak)
+    return out
 
 
 def workload(name):
@@ -53,12 +98,21 @@ def workload(name):
     return probs, run
 
 
-def describe(name, probs, run):
-    pr = probs[0]
-    if name == "c2":
-        return ("64x64 quads, p=2, S8 (40 dirs), sigma_t log-uniform [0.1,100] per 8x8 block, c=0.9, "
-                "isotropic source 1, vacuum; 50 source iterations + closures")
-    return "%s: %d problems, first %dx%d p=%d n_dir=%d" % (name, len(probs), pr.nx, pr.ny, pr.p, pr.n_dir)
+def fixture_error(name, mom_list):
+    """rel_inf of the moments against the oracle's sampled values of the same
+    workload (tests/golden, written from oracle/ only): max over the six
+    moments of max|gpu - oracle| at the sampled nodes / max|oracle phi|."""
+    import numpy as np
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    idx = np.asarray(g["index"])
+    flat = mom_list[0].reshape(6, -1)
+    scale = g["mom_absmax"][0]
+    phi_err = float(np.abs(flat[0, idx] - np.asarray(g["mom"][0])).max() / scale)
+    all_err = max(float(np.abs(flat[k, idx] - np.asarray(g["mom"][k])).max() / scale) for k in range(6))
+    return {"phi": phi_err, "all_moments": all_err, "fixture": "tests/golden/" + name}
 
 
 TIMING_STRIDE = 10  # HIP events around every 10th sweep of a step (each event costs device time)
@@ -93,47 +147,81 @@ def run_gpu(probs, n_iter, precision, steps, warmup, timing=True, schedule="auto
         # step would stall the queue)
         sweep_ms, launches = sw.timing()
     sw.check()
-    out = dict(seconds=t1 - t0, sweep_ms=sweep_ms, launches=launches,
+    n_timed = sum(1 for it in range(n_iter) if (it + 1) % TIMING_STRIDE == 0 or it == n_iter - 1)
+    out = dict(seconds=t1 - t0, sweep_ms=sweep_ms / n_timed, launches=launches / n_timed,
                schedule=vef.SCHEDULE_NAMES[sw.info[0]["schedule"]], kernel=sw.info[0]["kernel"],
                n_levels=sw.info[0]["n_levels"], tuned=tuned,
+               mom=[b["mom"].cpu().numpy() for b in io],
                phi=[b["mom"][0].double().cpu().numpy() for b in io],
                resid=[b["resid"].cpu().numpy() for b in io])
     sw.close()
     return out
 
 
-PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                       "k_sweep_pipe_c2_64x64_p2_S8_fp64.md")
-KERNEL_SOURCES = ["paper_2301_04758_amd/csrc/sweep_device.h", "paper_2301_04758_amd/csrc/sweep_p2.hip",
-                  "paper_2301_04758_amd/csrc/kernels.h"]
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_2301_04758_amd/csrc/sweep_device.h", "paper_2301_04758_amd/csrc/kernels.h"]
+
+
+def sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of the C2 pipelined kernel from the committed
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy kernel),
-    or None when the kernel differs or its sources changed since then."""
-    import hashlib
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by what the same counters read for a
+    plain copy kernel), or None when none covers it or the kernel sources
+    changed since it was taken."""
     import re
-    if kernel != "k_sweep_pipe<2, 3, double, false, false>" or not os.path.exists(PROFILE):
+    if not os.path.isdir(PROFILES):
         return None
-    text = open(PROFILE).read()
-    m = re.search(r"traffic_bytes_per_launch=([0-9.e+]+) kernel_sources_sha256_16=([0-9a-f]+)", text)
-    if not m:
-        return None
-    h = hashlib.sha256()
-    root = os.path.dirname(os.path.abspath(__file__))
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(root, f), "rb").read())
-    return float(m.group(1)) if h.hexdigest()[:16] == m.group(2) else None
+    want = sources_hash()
+    for f in sorted(os.listdir(PROFILES)):
+        text = open(os.path.join(PROFILES, f)).read()
+        for m in re.finditer(r"traffic kernel=(\S+) traffic_bytes_per_launch=([0-9.e+]+) "
+                             r"kernel_sources_sha256_16=([0-9a-f]+)", text):
+            if m.group(1) == kernel.replace(" ", "") and m.group(3) == want:
+                return float(m.group(2))
+    return None
 
 
-def kernel_name(g, pr):
+def kernel_name(g, pr, dtype="double"):
     """Name of the sweep kernel that ran (as the profiler lists it)."""
     nq = pr.nq or pr.p + pr.m
     if g["schedule"] == "dir_resident" and g["kernel"] in (3, 4):
-        return "k_sweep_pipe<%d, %d, double, false, %s>" % (pr.p, nq, "true" if g["kernel"] == 4 else "false")
-    kind = "dir" if g["schedule"] == "dir_resident" else "level"
-    return "k_sweep_%s<%d, %d, double, %d>" % (kind, pr.p, nq, g["kernel"])
+        return "k_sweep_pipe<%d, %d, %s, false, %s>" % (pr.p, nq, dtype, "true" if g["kernel"] == 4 else "false")
+    if g["kernel"] == 5:
+        kind = {"dir_resident": "dir_lu", "persistent": "flow", "level_sync": "level_lu"}[g["schedule"]]
+        if kind == "flow":
+            return "k_sweep_flow<%d, %d, %s, 5>" % (pr.p, nq, dtype)
+        return "k_sweep_%s<%d, %d, %s, false>" % (kind, pr.p, nq, dtype)
+    kind = {"dir_resident": "dir", "persistent": "flow", "level_sync": "level"}[g["schedule"]]
+    return "k_sweep_%s<%d, %d, %s, %d>" % (kind, pr.p, nq, dtype, g["kernel"])
+
+
+def workload_leg(name, steps, warmup, schedule):
+    """FP64 and FP32-local runs of one configuration: time per step, solves/s,
+    roofline of the sweep kernel, error of the moments against the oracle's
+    sampled values."""
+    probs, _ = workload(name)
+    cfg = WORKLOADS[name]
+    n_iter = cfg["n_iter"]
+    solves = sum(p.n_elem * p.n_dir for p in probs) * n_iter
+    out = {"workload": cfg["text"]}
+    for prec, s, peak, dt in (("fp64", 8, FP64_PEAK_TFLOPS, "double"), ("fp32", 4, FP32_PEAK_TFLOPS, "float")):
+        g = run_gpu(probs, n_iter, prec, steps, warmup, schedule=schedule)
+        ms = 1e3 * g["seconds"] / steps
+        kname = kernel_name(g, probs[0], dt)
+        out[prec] = {"ms_per_step": ms, "solves_per_s": solves / (ms * 1e-3), "schedule": g["schedule"],
+                     "tuning": g["tuned"], "sweep_ms": g["sweep_ms"],
+                     "roofline": roofline(probs, s, g["sweep_ms"] * 1e-3, g["launches"], kname, peak,
+                                          measured_traffic(kname)),
+                     "rel_inf_vs_oracle": fixture_error(cfg["fixture"], g["mom"])}
+    out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
+    return out
 
 
 def fixup_leg(probs, n_iter, steps, ms_plain):
@@ -439,29 +527,71 @@ def c4_batched(reps=3):
     err = max(float(np.abs(io[k]["mom"][0].cpu().numpy() - phi64[k]).max() / np.abs(phi64[k]).max())
               for k in range(len(probs)))
     solves = sum(p.n_elem * p.n_dir for p in probs)
+    # error of the batch (and of the plain runs) against the oracle's sampled
+    # values of the problems the fixture holds
+    ora = {}
+    path = os.path.join(GOLDEN, "c4_some.json")
+    if os.path.exists(path):
+        g = json.load(open(path))
+        e32 = e64 = 0.0
+        for item in g["problems"]:
+            k, idx = item["problem"], np.asarray(item["index"])
+            ref, scale = np.asarray(item["mom"][0]), item["mom_absmax"][0]
+            e32 = max(e32, float(np.abs(io[k]["mom"][0].cpu().numpy().reshape(-1)[idx] - ref).max() / scale))
+            e64 = max(e64, float(np.abs(phi64[k].reshape(-1)[idx] - ref).max() / scale))
+        ora = {"batched_fp32": e32, "plain_fp64": e64, "problems_checked": len(g["problems"]),
+               "fixture": "tests/golden/c4_some.json"}
     out = {"problems": len(probs), "solves_per_sweep": solves, "plain_fp64_one_by_one_ms": t_plain,
            "batched_fp32_graph_ms": t_batch, "schedule": vef.SCHEDULE_NAMES[sw.info[0]["schedule"]],
            "tuning": tuned,
-           "rel_inf_phi_vs_fp64": err, "within_1e-5": err <= 1e-5,
+           "rel_inf_phi_vs_fp64": err, "within_1e-5": err <= 1e-5, "rel_inf_phi_vs_oracle": ora,
            "speedup": (t_plain / t_batch) if err <= 1e-5 else None,
-           "batched_solves_per_s": solves / (t_batch * 1e-3)}
+           "batched_solves_per_s": solves / (t_batch * 1e-3),
+           # the replayed graph holds the sweep kernels and the moment kernels of all 64 problems
+           "roofline_graph": roofline(probs, 4, t_batch * 1e-3, 1, "graph replay (sweep + moments, 64 problems)",
+                                      FP32_PEAK_TFLOPS)}
     del g
     sw.close()
     return out
 
 
-def cpu_baseline(probs, iters):
-    """The oracle (serial double-precision C, gcc -O2) on the host, on the first
-    `iters` source iterations of the same workload."""
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(probs, n_dirs=16, max_threads=16):
+    """The oracle (double-precision C, gcc -O2, OpenMP over directions) on the
+    host cores, on a bounded sample of the same workload: one sweep of n_dirs
+    of its directions (evenly spaced over the set, so every quadrant is in it)
+    from phi = 0, all cores; and one direction on one core."""
+    import numpy as np
     from oracle import oracle as O
     pr = probs[0]
+    threads = max(1, min(max_threads, os.cpu_count() or 1, n_dirs))
+    dirs = np.linspace(0, pr.n_dir - 1, n_dirs).round().astype(np.int32)
     t0 = time.perf_counter()
-    r = O.source_iteration(pr, iters)
+    O.sweep(pr, dirs=dirs, want_psi=False, threads=threads)
     dt = time.perf_counter() - t0
-    solves = pr.n_elem * pr.n_dir * r["iters"]
-    return dict(value=solves / dt, unit="element-direction solves/s", cores=1, kind="oracle",
-                sample="first %d of the 50 source iterations of the same workload (%d solves, %.1f s)"
-                % (r["iters"], solves, dt))
+    solves = pr.n_elem * len(dirs)
+    t0 = time.perf_counter()
+    O.sweep(pr, dirs=dirs[:1], want_psi=False, threads=1)
+    dt1 = time.perf_counter() - t0
+    out = dict(value=solves / dt, unit="element-direction solves/s", cores=threads, kind="oracle",
+               sample="one sweep of %d of the %d directions of the same workload from phi = 0 (%d solves, "
+                      "%.1f s, %d OpenMP threads, one direction per thread)" % (len(dirs), pr.n_dir, solves, dt,
+                                                                               threads),
+               serial={"value": pr.n_elem / dt1, "cores": 1, "sample": "one direction (%d solves, %.1f s)"
+                       % (pr.n_elem, dt1)})
+    out.update(cpu_info())
+    return out
 
 
 def main():
@@ -469,18 +599,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=30)
-    ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir"],
+    ap.add_argument("--schedule", default="auto", choices=["auto", "level", "dir", "persistent"],
                     help="auto: the library's autotuner picks schedule and kernel before the timed steps")
-    ap.add_argument("--no-c4", action="store_true", help="skip the 64-problem batched FP32 vs one-by-one FP64 block")
-    ap.add_argument("--no-fixup", action="store_true", help="skip the negative-flux fixup leg")
-    ap.add_argument("--no-lagged", action="store_true", help="skip the re-entrant-mesh lagged-sweep leg")
-    ap.add_argument("--no-pointwise", action="store_true", help="skip the pointwise-upwinding leg")
-    ap.add_argument("--no-hrt", action="store_true", help="skip the HRT local block inverse leg")
-    ap.add_argument("--no-outer", action="store_true", help="skip the transport / VEF outer iteration leg")
+    ap.add_argument("--legs", default="c3,c2,c4,fixup,lagged,pointwise,hrt,outer",
+                    help="comma-separated extra legs (c3, c2: the same measurements on those configurations; "
+                         "c4: 64-problem batched FP32 graph vs one-by-one FP64; fixup, lagged, pointwise, hrt, "
+                         "outer); 'none' for the headline only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (three times), the reference kernel "
                          "for scaling HBM byte counters")
@@ -493,9 +620,11 @@ def main():
     import numpy as np
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    legs = set() if args.legs == "none" else set(args.legs.split(","))
 
-    probs, run = workload(args.workload)
-    n_iter = run["n_iter"]
+    cfg = WORKLOADS[args.workload]
+    probs, _ = workload(args.workload)
+    n_iter = cfg["n_iter"]
     pr = probs[0]
     solves_per_step = sum(p.n_elem * p.n_dir for p in probs) * n_iter
 
@@ -504,71 +633,59 @@ def main():
     g64 = run_gpu(probs, n_iter, "fp64", args.steps, args.warmup, schedule=args.schedule)
     ms_step = 1e3 * g64["seconds"] / args.steps
     value = solves_per_step * args.steps / g64["seconds"]
-
-    # dominant kernel: the sweep kernel, timed by events on the run's stream
-    # over the last timed step
-    F = sweep_flops_per_solve(pr.p)
-    B = sweep_bytes_per_solve(pr.p, pr.m, pr.n_dir, 8)
-    launches = max(g64["launches"], 1)
-    avg_launch_s = g64["sweep_ms"] * 1e-3 / launches
-    n_timed = sum(1 for it in range(n_iter) if (it + 1) % TIMING_STRIDE == 0 or it == n_iter - 1)
-    solves_per_launch = solves_per_step / n_iter * n_timed / launches
-    achieved_tf = F * solves_per_launch / avg_launch_s / 1e12
     kname = kernel_name(g64, pr)
-    sweeps_per_launch = solves_per_launch / sum(p.n_elem * p.n_dir for p in probs)
-    t_bw = B * solves_per_launch / (HBM_PEAK_GBS * 1e9)
-    t_flop = F * solves_per_launch / (FP64_PEAK_TFLOPS * 1e12)
-    # the chain of dependent levels can go no faster than one measured
-    # wave-to-wave hand-off per level (vef_probe_machine)
-    t_cp = g64["n_levels"] * sweeps_per_launch * machine["lds_handoff_ns"] * 1e-9
-    roofline = {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": measured_traffic(kname),
-                "kernel": kname, "avg_launch_us": avg_launch_s * 1e6,
-                "levels_per_sweep": g64["n_levels"],
-                "us_per_level": avg_launch_s * 1e6 / (g64["n_levels"] * sweeps_per_launch),
-                "lower_bounds_us": {"hbm": t_bw * 1e6, "fp64_alu": t_flop * 1e6,
-                                    "critical_path_handoff": t_cp * 1e6},
-                "binding": "critical path: %d dependent upwind levels per sweep" % g64["n_levels"],
-                "frac_of_critical_path_bound": t_cp / avg_launch_s,
-                "measured_peak": machine["fp64_fma_tflops"],
-                "frac_of_measured_peak": achieved_tf / machine["fp64_fma_tflops"],
-                "launches_per_step": launches / n_timed * n_iter,
-                "algorithmic_flops_per_solve": F, "algorithmic_bytes_per_solve": B,
-                "hbm_frac": (B * solves_per_launch / avg_launch_s / 1e9) / HBM_PEAK_GBS}
-    hbm_gbs = B * solves_per_step / (ms_step * 1e-3) / 1e9
-
+    roof = roofline(probs, 8, g64["sweep_ms"] * 1e-3, g64["launches"], kname, FP64_PEAK_TFLOPS,
+                    measured_traffic(kname))
+    roof.update(levels_per_sweep=g64["n_levels"], measured_peak=machine["fp64_fma_tflops"],
+                frac_of_measured_peak=roof["alu_tflops"] / machine["fp64_fma_tflops"],
+                # lower bounds of one sweep: HBM traffic, FP64 ALU work, and the chain of dependent
+                # levels at one measured wave-to-wave hand-off each
+                lower_bounds_us={"hbm": 1e6 * roof["algorithmic_bytes_per_solve"] * solves_per_step / n_iter
+                                 / (HBM_PEAK_GBS * 1e9),
+                                 "fp64_alu": 1e6 * roof["algorithmic_flops_per_solve"] * solves_per_step / n_iter
+                                 / (FP64_PEAK_TFLOPS * 1e12),
+                                 "critical_path_handoff": g64["n_levels"] * machine["lds_handoff_ns"] * 1e-3})
     result = {
         "metric": METRIC, "value": value, "unit": "element-direction solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": describe(args.workload, probs, run), "n_elem": pr.n_elem, "p": pr.p,
+        "config": {"workload": cfg["text"], "name": args.workload, "n_elem": pr.n_elem, "p": pr.p,
                    "n_dir": pr.n_dir, "sweeps_per_step": n_iter,
                    "schedule": ("autotuned: " if g64["tuned"] else "") + g64["schedule"],
-                   "tuning": g64["tuned"],
-                   "precision": "fp64"},
-        "hbm_gbs_algorithmic": hbm_gbs,
-        "roofline": roofline,
+                   "tuning": g64["tuned"], "precision": "fp64"},
+        "rel_inf_vs_oracle": fixture_error(cfg["fixture"], g64["mom"]),
+        "roofline": roof,
         "machine": machine,
     }
     if not args.no_fp32:
         g32 = run_gpu(probs, n_iter, "fp32", args.steps, args.warmup, schedule=args.schedule)
         ms32 = 1e3 * g32["seconds"] / args.steps
         err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(g32["phi"], g64["phi"]))
+        ora = fixture_error(cfg["fixture"], g32["mom"])
+        k32 = kernel_name(g32, pr, "float")
         result["fp32_local"] = {"ms_per_step": ms32, "value": solves_per_step / (ms32 * 1e-3),
-                                "speedup_vs_fp64": ms_step / ms32,
-                                "rel_inf_phi_vs_fp64_path": err, "within_1e-5": err <= 1e-5}
-    if not args.no_fixup:
-        result["fixup_fp64"] = fixup_leg(probs, n_iter, args.steps, ms_step)
-    if not args.no_lagged:
+                                "speedup_vs_fp64": ms_step / ms32, "schedule": g32["schedule"],
+                                "rel_inf_vs_oracle": ora,
+                                "within_1e-5_of_oracle": (ora["phi"] <= 1e-5) if ora else None,
+                                "rel_inf_phi_vs_fp64_path": err,
+                                "roofline": roofline(probs, 4, g32["sweep_ms"] * 1e-3, g32["launches"], k32,
+                                                     FP32_PEAK_TFLOPS, measured_traffic(k32))}
+    for leg in ("c3", "c2"):
+        if leg in legs and leg != args.workload:
+            result["workload_" + leg] = workload_leg(leg, args.steps, args.warmup, args.schedule)
+    if "fixup" in legs:
+        p2, r2 = workload("c2")
+        result["fixup_fp64"] = fixup_leg(p2, r2["n_iter"], args.steps, None)
+    if "lagged" in legs:
         result["lagged_reentrant"] = lagged_leg(args.steps)
-    if not args.no_pointwise:
+    if "pointwise" in legs:
         result["pointwise_upwinding"] = pointwise_leg(args.steps)
-    if not args.no_hrt:
+    if "hrt" in legs:
         result["hrt_local_inverse"] = hrt_leg()
-    if not args.no_outer:
+    if "outer" in legs:
         result["vef_outer_thick_limit"] = outer_leg()
         result["vef_outer_thick_limit"]["eps_table"] = tdl_table()
-    if not args.no_c4:
+    if "c4" in legs:
         result["c4_batched_fp32_vs_plain_fp64"] = c4_batched()
     if args.copy_calibration:
         n = 256 << 20
@@ -583,7 +700,7 @@ def main():
                                       "gbs": 2 * n * 3 / (time.perf_counter() - t0) / 1e9}
         del src, dst
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(probs, args.cpu_iters)
+        result["cpu_baseline"] = cpu_baseline(probs)
     print(json.dumps(result), flush=True)
 
 

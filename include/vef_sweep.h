@@ -82,9 +82,17 @@ enum {
                             width fits one round of a work-group, else
                             VEF_LEVEL_SYNC */
   VEF_LEVEL_SYNC = 1,    /* one launch per upwind level over all directions */
-  VEF_DIR_RESIDENT = 2   /* one launch per sweep; one work-group per (problem,
+  VEF_DIR_RESIDENT = 2,  /* one launch per sweep; one work-group per (problem,
                             direction) walks all upwind levels with work-group
                             barriers between levels */
+  VEF_PERSISTENT = 3     /* one launch per sweep and kernel variant: every
+                            resident wave takes tasks of consecutive solves
+                            in upwind-level order and waits on dependency
+                            counters in global memory (agent-scope
+                            release/acquire, bounded by
+                            vef_options.wait_polls); variants without a
+                            persistent kernel (affine p <= 2, the fixup)
+                            run level-synchronously */
 };
 
 /* One transport problem (host pointers, copied by vef_sweep_create and not
@@ -111,7 +119,8 @@ typedef struct {
                     assembly and solves in float with float accumulation,
                     angular flux stored as float; moments, residual and
                     closures in double. */
-  int schedule;  /* VEF_SCHEDULE_AUTO, VEF_LEVEL_SYNC or VEF_DIR_RESIDENT */
+  int schedule;  /* VEF_SCHEDULE_AUTO, VEF_LEVEL_SYNC, VEF_DIR_RESIDENT or
+                    VEF_PERSISTENT */
   int block;     /* work-group size for the sweep kernels; 0 = default 256 */
   int timing;    /* k > 0: runs record HIP events around the sweep kernels
                     of every k-th source iteration and of the last one (read
@@ -164,7 +173,8 @@ typedef struct {
                     under both rules.  Not combined with the fixup. */
   long long wait_polls; /* bound of one device-side wait of a sweep kernel
                     that waits for upwind work of other waves (the pipelined
-                    kernel), in polls of about 64 clocks each; 0 = default
+                    and persistent kernels), in polls of about 64 clocks
+                    each; 0 = default
                     2^26 (seconds: a healthy wait takes microseconds).  When a
                     wait exceeds it the kernel stops its sweep early, every
                     wave exits normally and vef_sweep_check reports
@@ -229,7 +239,8 @@ typedef struct {
                     matrices scaled by the element's J and adj(F) */
   long long n_solves; /* n_elem * n_dir */
   int schedule;  /* vef_problem_info: the handle's schedule as resolved at
-                    create (VEF_LEVEL_SYNC or VEF_DIR_RESIDENT);
+                    create (VEF_LEVEL_SYNC, VEF_DIR_RESIDENT or
+                    VEF_PERSISTENT);
                     vef_plan_query: VEF_SCHEDULE_AUTO */
   int kernel;    /* vef_problem_info: sweep kernel of this problem,
                     VEF_KERNEL_*; vef_plan_query: -1 */
@@ -247,6 +258,9 @@ typedef struct {
 #define VEF_KERNEL_BILINEAR_PIPELINE 4 /* the same for straight-sided
                                        bilinear elements (m = 1), volume
                                        terms by quadrature */
+#define VEF_KERNEL_AFFINE_LU 5       /* affine, p >= 3: a 16-lane slot per
+                                       solve holding one or two rows per
+                                       lane, LU in natural order */
 
 /* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
  * upwind graphs unless opt->cycles lags them), build the sweep plan on the host and upload it to the
@@ -437,7 +451,7 @@ int vef_probe_machine(vef_machine *out, void *stream);
 
 /* Result of vef_sweep_autotune. */
 typedef struct {
-  int schedule;       /* chosen: VEF_LEVEL_SYNC or VEF_DIR_RESIDENT */
+  int schedule;       /* chosen: VEF_LEVEL_SYNC, VEF_DIR_RESIDENT or VEF_PERSISTENT */
   int pipeline_waves; /* chosen waves of the pipelined kernel; -1 = row-per-lane kernel */
   int block;          /* chosen work-group size of the level-synchronous kernels */
   int n_candidates;   /* configurations timed */
@@ -448,7 +462,8 @@ typedef struct {
 /* Same operation as vef_sweep_run (the sweep of Sec. 5 with the moments of
  * Eq. eq:vef_disc), run repeatedly to choose how it is scheduled: the
  * level-synchronous kernels with 128 or 256 threads per work-group, the
- * direction-resident row-per-lane kernel, and (when some problem has affine
+ * direction-resident row-per-lane kernel, the persistent schedule (when some
+ * variant has a persistent kernel) and (when some problem has affine
  * elements of degree <= 2) the pipelined kernel with 8, 6 or 4 waves.  Each
  * candidate runs once untimed and then reps (1..1000) times between HIP
  * events on stream; the fastest is kept by the handle for later runs when it

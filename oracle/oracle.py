@@ -31,7 +31,7 @@ class OracleError(RuntimeError):
 
 
 def build_oracle(out=_LIB):
-    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-o", out, _SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared", "-o", out, _SRC, "-lm"]
     subprocess.check_call(cmd)
     return out
 
@@ -55,7 +55,7 @@ class _Prob(C.Structure):
                 ("cp_xy", C.c_void_p), ("elem_cp", C.c_void_p),
                 ("n_dir", C.c_int), ("omega", C.c_void_p), ("weight", C.c_void_p),
                 ("sigma_t", C.c_void_p), ("sigma_s", C.c_void_p), ("fixup", C.c_int), ("lag", C.c_int),
-                ("pointwise", C.c_int)]
+                ("pointwise", C.c_int), ("threads", C.c_int)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -100,7 +100,7 @@ def _f64(a):
 class _Bound:
     """Keeps the numpy arrays behind an oracle_problem struct alive."""
 
-    def __init__(self, pr, nq=None, fixup=False, lag=False, pointwise=False):
+    def __init__(self, pr, nq=None, fixup=False, lag=False, pointwise=False, threads=1):
         self.cp = np.ascontiguousarray(pr.cp_xy, dtype=np.float64)
         self.ec = np.ascontiguousarray(pr.elem_cp, dtype=np.int32)
         self.om = np.ascontiguousarray(pr.omega, dtype=np.float64)
@@ -110,7 +110,7 @@ class _Bound:
         self.s = _Prob(pr.p, pr.m, int(pr.nq if nq is None else nq), self.ec.shape[0], self.cp.shape[0],
                        self.cp.ctypes.data, self.ec.ctypes.data, self.om.shape[0], self.om.ctypes.data,
                        self.wt.ctypes.data, self.st.ctypes.data, self.ss.ctypes.data, 1 if fixup else 0,
-                       1 if lag else 0, 1 if pointwise else 0)
+                       1 if lag else 0, 1 if pointwise else 0, int(threads))
         self.nq = self.s.nq if self.s.nq > 0 else pr.p + pr.m
         self.n = (pr.p + 1) ** 2
         self.Q = self.nq * self.nq
@@ -189,14 +189,15 @@ def lagged_couplings(pr, nq=None, pointwise=False):
 
 
 def sweep(pr, phi_in=None, dirs=None, want_psi=True, nq=None, q_iso="problem", q_dir="problem",
-          psi_bc="problem", fixup=False, lag=False, psi_prev=None, pointwise=False):
+          psi_bc="problem", fixup=False, lag=False, psi_prev=None, pointwise=False, threads=1):
     """One sweep.  Returns dict(psi [n_sel,n_elem,n] or None, mom [6,n_elem,n],
     bnd [n_bf,nq,2], levels [n_sel]).  fixup: set-to-zero-and-scale
     negative-flux fixup after each local solve.  lag: cyclic upwind graphs
     are swept with lagged couplings, which read psi_prev [n_sel,n_elem,n]
     (None = 0).  pointwise: the upwind side is chosen at each face point
-    (faces with both signs need lag)."""
-    b = _Bound(pr, nq, fixup, lag, pointwise)
+    (faces with both signs need lag).  threads > 1: that many directions at
+    a time on OpenMP threads (same results, summed in direction order)."""
+    b = _Bound(pr, nq, fixup, lag, pointwise, threads)
     psi_prev = _f64(psi_prev)
     q_iso = _f64(pr.q_iso if isinstance(q_iso, str) else q_iso)
     q_dir = _f64(pr.q_dir if isinstance(q_dir, str) else q_dir)
@@ -244,12 +245,12 @@ def closures(pr, mom, bnd, nq=None, q_iso="problem", q_dir="problem", psi_bc="pr
 
 
 def source_iteration(pr, n_iter, tol=0.0, phi0=None, nq=None, fixup=False, lag=False, psi0=None,
-                     want_psi=False, pointwise=False):
+                     want_psi=False, pointwise=False, threads=1):
     """dict(mom [6,n_elem,n] of the last sweep, bnd, resid [iters], iters, psi).
     lag: lagged sweeps of cyclic graphs; their first sweep reads psi0
     [n_dir,n_elem,n] (None = 0).  psi: the last sweep's angular flux when
-    want_psi, else None.  pointwise: as in sweep."""
-    b = _Bound(pr, nq, fixup, lag, pointwise)
+    want_psi, else None.  pointwise, threads: as in sweep."""
+    b = _Bound(pr, nq, fixup, lag, pointwise, threads)
     psi = None
     if want_psi or psi0 is not None:
         psi = np.zeros((pr.n_dir, pr.n_elem, b.n)) if psi0 is None else np.array(psi0, dtype=np.float64)

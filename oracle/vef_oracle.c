@@ -79,6 +79,9 @@ typedef struct {
   int lag;   /* 1: cyclic upwind graphs are swept with lagged couplings */
   int pointwise; /* 1: the upwind side is chosen at each face quadrature point
                     from the sign of Omega . n there (0: for the whole face) */
+  int threads;   /* > 1: sweep that many directions at a time on separate
+                    threads (OpenMP); the results are summed in direction
+                    order afterwards, so they do not depend on it */
 } oracle_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -643,54 +646,78 @@ int oracle_sweep(const oracle_problem *pr, const double *phi_in, const double *q
   if ((rc = build_conn(&c, &cn))) return rc;
   int ne = pr->n_elem, n = c.n, nq = c.nq;
   if (!dir_list) n_sel = pr->n_dir;
-  double *psi_d = (double *)calloc((size_t)ne * n, sizeof(double));
-  int *order = (int *)malloc(sizeof(int) * ne), *indeg = (int *)malloc(sizeof(int) * ne),
-      *lev = (int *)malloc(sizeof(int) * ne);
-  unsigned char *solved = (unsigned char *)malloc(ne);
-  if (!psi_d || !order || !indeg || !lev || !solved) { rc = ORACLE_ERR_OOM; goto done; }
-  if (mom) memset(mom, 0, sizeof(double) * 6 * (size_t)ne * n);
-  if (bnd_acc) memset(bnd_acc, 0, sizeof(double) * 2 * (size_t)cn.n_bf * nq);
   for (int k = 0; k < n_sel; ++k) {
     int d = dir_list ? dir_list[k] : k;
-    if (d < 0 || d >= pr->n_dir) { rc = ORACLE_ERR_INVALID; goto done; }
-    double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1], w = pr->weight[d];
-    int ml;
-    if ((rc = topo_order(&c, &cn, ox, oy, order, indeg, lev, &ml, NULL))) goto done;
-    if (levels) levels[k] = ml + 1;
-    memset(solved, 0, ne);
-    const double *prev = psi_prev ? psi_prev + (size_t)k * ne * n : NULL;
-    for (int t = 0; t < ne; ++t) {
-      if ((rc = local_solve(&c, &cn, order[t], d, phi_in, q_iso, q_dir, psi_bc, psi_d, prev, solved)))
-        goto done;
-      solved[order[t]] = 1;
+    if (d < 0 || d >= pr->n_dir) { conn_free(&cn); return ORACLE_ERR_INVALID; }
+  }
+  /* directions are independent within a sweep: T of them at a time, each
+   * with its own angular-flux buffer and ordering scratch */
+  int T = pr->threads > 1 ? pr->threads : 1;
+  if (T > n_sel) T = n_sel > 0 ? n_sel : 1;
+  double *psi_all = (double *)calloc((size_t)T * ne * n, sizeof(double));
+  int *order_all = (int *)malloc(sizeof(int) * (size_t)T * ne), *indeg_all = (int *)malloc(sizeof(int) * (size_t)T * ne),
+      *lev_all = (int *)malloc(sizeof(int) * (size_t)T * ne);
+  unsigned char *solved_all = (unsigned char *)malloc((size_t)T * ne);
+  int *rc_t = (int *)calloc((size_t)T, sizeof(int)), *ml_t = (int *)calloc((size_t)T, sizeof(int));
+  if (!psi_all || !order_all || !indeg_all || !lev_all || !solved_all || !rc_t || !ml_t) { rc = ORACLE_ERR_OOM; goto done; }
+  if (mom) memset(mom, 0, sizeof(double) * 6 * (size_t)ne * n);
+  if (bnd_acc) memset(bnd_acc, 0, sizeof(double) * 2 * (size_t)cn.n_bf * nq);
+  for (int k0 = 0; k0 < n_sel; k0 += T) {
+    int kn = n_sel - k0 < T ? n_sel - k0 : T;
+#pragma omp parallel for num_threads(kn) schedule(static, 1)
+    for (int t = 0; t < kn; ++t) {
+      int k = k0 + t;
+      int d = dir_list ? dir_list[k] : k;
+      double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1];
+      double *psi_d = psi_all + (size_t)t * ne * n;
+      int *order = order_all + (size_t)t * ne, *indeg = indeg_all + (size_t)t * ne, *lev = lev_all + (size_t)t * ne;
+      unsigned char *solved = solved_all + (size_t)t * ne;
+      memset(psi_d, 0, sizeof(double) * (size_t)ne * n);
+      int r = topo_order(&c, &cn, ox, oy, order, indeg, lev, &ml_t[t], NULL);
+      memset(solved, 0, ne);
+      const double *prev = psi_prev ? psi_prev + (size_t)k * ne * n : NULL;
+      for (int i = 0; i < ne && !r; ++i) {
+        r = local_solve(&c, &cn, order[i], d, phi_in, q_iso, q_dir, psi_bc, psi_d, prev, solved);
+        solved[order[i]] = 1;
+      }
+      rc_t[t] = r;
     }
-    if (psi_out) memcpy(psi_out + (size_t)k * ne * n, psi_d, sizeof(double) * (size_t)ne * n);
-    if (mom) {
-      double fac[6] = {1.0, ox, oy, ox * ox, ox * oy, oy * oy};
-      for (int f = 0; f < 6; ++f)
-        for (size_t i = 0; i < (size_t)ne * n; ++i) mom[f * (size_t)ne * n + i] += w * fac[f] * psi_d[i];
-    }
-    if (bnd_acc) {
-      for (int e = 0; e < ne; ++e)
-        for (int f = 0; f < 4; ++f) {
-          int bf = cn.bf_id[4 * e + f];
-          if (bf < 0) continue;
-          for (int qs = 0; qs < nq; ++qs) {
-            double xi, eta, F[2][2], nx, ny;
-            face_point(f, c.gx[qs], &xi, &eta);
-            map_point(&c, e, xi, eta, NULL, F);
-            face_nds(F, f, &nx, &ny);
-            double len = sqrt(nx * nx + ny * ny);
-            double on = fabs(ox * nx / len + oy * ny / len);
-            double val = dg_eval(&c, psi_d + (size_t)e * n, xi, eta);
-            bnd_acc[((size_t)bf * nq + qs) * 2 + 0] += w * on * val;
-            bnd_acc[((size_t)bf * nq + qs) * 2 + 1] += w * val;
+    /* reductions in direction order */
+    for (int t = 0; t < kn; ++t) {
+      if (rc_t[t]) { rc = rc_t[t]; goto done; }
+      int k = k0 + t;
+      int d = dir_list ? dir_list[k] : k;
+      double ox = pr->omega[2 * d], oy = pr->omega[2 * d + 1], w = pr->weight[d];
+      const double *psi_d = psi_all + (size_t)t * ne * n;
+      if (levels) levels[k] = ml_t[t] + 1;
+      if (psi_out) memcpy(psi_out + (size_t)k * ne * n, psi_d, sizeof(double) * (size_t)ne * n);
+      if (mom) {
+        double fac[6] = {1.0, ox, oy, ox * ox, ox * oy, oy * oy};
+        for (int f = 0; f < 6; ++f)
+          for (size_t i = 0; i < (size_t)ne * n; ++i) mom[f * (size_t)ne * n + i] += w * fac[f] * psi_d[i];
+      }
+      if (bnd_acc) {
+        for (int e = 0; e < ne; ++e)
+          for (int f = 0; f < 4; ++f) {
+            int bf = cn.bf_id[4 * e + f];
+            if (bf < 0) continue;
+            for (int qs = 0; qs < nq; ++qs) {
+              double xi, eta, F[2][2], nx, ny;
+              face_point(f, c.gx[qs], &xi, &eta);
+              map_point(&c, e, xi, eta, NULL, F);
+              face_nds(F, f, &nx, &ny);
+              double len = sqrt(nx * nx + ny * ny);
+              double on = fabs(ox * nx / len + oy * ny / len);
+              double val = dg_eval(&c, psi_d + (size_t)e * n, xi, eta);
+              bnd_acc[((size_t)bf * nq + qs) * 2 + 0] += w * on * val;
+              bnd_acc[((size_t)bf * nq + qs) * 2 + 1] += w * val;
+            }
           }
-        }
+      }
     }
   }
 done:
-  free(psi_d); free(order); free(indeg); free(lev); free(solved);
+  free(psi_all); free(order_all); free(indeg_all); free(lev_all); free(solved_all); free(rc_t); free(ml_t);
   conn_free(&cn);
   return rc;
 }

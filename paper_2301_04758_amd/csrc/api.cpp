@@ -43,6 +43,7 @@ int mode_of(const vefplan::ProblemPlan &pl, int schedule, bool pipeline = true, 
   // assembly (lagged couplings read the previous sweep from global memory)
   (void)fixup;
   if (!pl.affine) return (pipe && pl.m == 1) ? 4 : 1;
+  if (pl.p >= 3) return 5;  // row-set LU with fused broadcasts
   return (pipe && pl.n_lagged == 0) ? 3 : 2;
 }
 
@@ -50,7 +51,25 @@ struct LevelLaunch {
   Variant v;
   int off, cnt;
   const void *tab;
+  bool flow;  // its problems run in persistent launches under VEF_PERSISTENT
 };
+
+struct FlowLaunch {  // one persistent launch: the tasks of a variant (row-per-lane or row-set LU modes)
+  Variant v;
+  int off, cnt;  // into d_flow_tasks (off is also the flag index of the first task)
+  const void *tab;
+};
+
+// Modes with a persistent kernel (no fixup variant).
+bool flow_mode(int mode, int fixup) { return !fixup && (mode == 0 || mode == 1 || mode == 5); }
+
+// Solves per round of one wave of a kernel mode: 16-lane slots for the
+// row-set LU, otherwise the power-of-two slot >= n of the row-per-lane kernels.
+int solves_per_round(int mode, int n) {
+  if (mode == 5) return 4;
+  return 64 / (n <= 4 ? 4 : (n <= 8 ? 8 : (n <= 16 ? 16 : 32)));
+}
+constexpr int kFlowRounds = 2;  // rounds of solves per persistent task
 
 struct DirLaunch {  // one direction-resident launch: all (problem, direction) pairs of a variant
   Variant v;
@@ -89,6 +108,13 @@ struct vef_sweep {
   int2 *d_solves = nullptr;
   std::vector<std::vector<LevelLaunch>> levels;
   int2 *d_dir_tasks = nullptr;
+  std::vector<FlowLaunch> flow;   // persistent schedule
+  int2 *d_flow_tasks = nullptr;   // [n_flow_tasks] (first solve, solves)
+  int *d_pred_ptr = nullptr;      // [n_flow_tasks + 1]
+  int *d_pred_idx = nullptr;      // predecessor tasks of each task
+  int *d_flow_flags = nullptr;    // [n_flow_tasks + 1]: sweep number per task, then the abort flag
+  int n_flow_tasks = 0;
+  int n_cu = 0;
   std::vector<DirLaunch> dir_rows;  // direction-resident, row-per-lane kernels only
   std::vector<DirLaunch> dir_pipe;  // direction-resident, pipelined kernel where it applies
   std::vector<void *> psi_internal;   // per problem, allocated on first need
@@ -220,7 +246,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (opt->precision != VEF_FP64 && opt->precision != VEF_FP32_LOCAL)
       return set_err(h, VEF_ERR_INVALID, "unknown precision");
     if (opt->schedule != VEF_SCHEDULE_AUTO && opt->schedule != VEF_LEVEL_SYNC &&
-        opt->schedule != VEF_DIR_RESIDENT)
+        opt->schedule != VEF_DIR_RESIDENT && opt->schedule != VEF_PERSISTENT)
       return set_err(h, VEF_ERR_INVALID, "unknown schedule");
     if (opt->block != 0 && (opt->block < 64 || opt->block > 1024 || opt->block % 64))
       return set_err(h, VEF_ERR_INVALID, "block must be a multiple of 64 in 64..1024");
@@ -266,6 +292,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   he = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
   if (he != hipSuccess) return hip_fail(h, he, "hipDeviceGetAttribute");
   h->lds_max = (size_t)lds;
+  he = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+  if (he != hipSuccess) return hip_fail(h, he, "hipDeviceGetAttribute");
   const bool fp32 = h->precision == VEF_FP32_LOCAL;
 
   // tables per (p, nq)
@@ -380,7 +408,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         if (width > 256.0) narrow = false;
         continue;
       }
-      const int slot = pl.n <= 4 ? 4 : (pl.n <= 8 ? 8 : (pl.n <= 16 ? 16 : 32));
+      const int slot = pl.n <= 4 ? 4 : (pl.n <= 8 ? 8 : (pl.n <= 16 || (pl.affine && pl.p >= 3) ? 16 : 32));
       const int slots = (fp32 ? 1024 : 512) / slot;
       if (width > slots) narrow = false;
     }
@@ -416,29 +444,123 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   std::vector<int2> solves;
   solves.reserve(total);
   h->levels.assign(max_levels, {});
+  // persistent schedule: tasks of kFlowRounds rounds of consecutive solves of
+  // one (problem, class, level) block, per variant in level order; problems
+  // with lagged couplings stay level-synchronous (a lagged read must precede
+  // the re-solve of its upwind element, which only the level order enforces)
+  std::vector<int> blk_first(n_probs, 0);
+  int n_blk = 0;
+  for (int k = 0; k < n_probs; ++k) {
+    blk_first[k] = n_blk;
+    n_blk += h->plans[k].n_groups * h->plans[k].n_levels;
+  }
+  std::vector<int> blk_solve0(n_blk, -1), blk_task0(n_blk, -1);
+  std::map<Variant, std::vector<int2>> flow_tasks;
+  std::map<Variant, std::vector<int>> flow_task_blk;
+  auto flow_ok = [&](const vefplan::ProblemPlan &pl, const Variant &v) {
+    return flow_mode(v.mode, h->fixup) && pl.n_lagged == 0;
+  };
+  // per level and variant, two level-synchronous launches: the problems the
+  // persistent schedule covers, then the others
   for (int L = 0; L < max_levels; ++L)
-    for (auto &var : variants) {
+    for (auto &var : variants)
+      for (int pass = 0; pass < 2; ++pass) {
+      const bool pass_flow = pass == 0;
       const int off = (int)solves.size();
       for (int k = 0; k < n_probs; ++k) {
         const auto &pl = h->plans[k];
         if (!in_level_variant(pl, var) || L >= pl.n_levels) continue;
+        if (flow_ok(pl, var) != pass_flow) continue;
         for (int g = 0; g < pl.n_groups; ++g) {
           const int *lo = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
           const int32_t *ord = &pl.order[(size_t)g * pl.ne];
+          const int b0 = (int)solves.size();
           for (int t = lo[L]; t < lo[L + 1]; ++t)
             for (int d : dirs_of[k][g]) solves.push_back(make_int2(ord[t], d | (k << 16)));
+          const int b1 = (int)solves.size();
+          if (flow_ok(pl, var) && b1 > b0) {
+            const int blk = blk_first[k] + g * pl.n_levels + L;
+            const int ts = solves_per_round(var.mode, pl.n) * kFlowRounds;
+            auto &tl = flow_tasks[var];
+            blk_solve0[blk] = b0;
+            blk_task0[blk] = (int)tl.size();
+            for (int x = b0; x < b1; x += ts) {
+              tl.push_back(make_int2(x, std::min(ts, b1 - x)));
+              flow_task_blk[var].push_back(blk);
+            }
+          }
         }
       }
       const int cnt = (int)solves.size() - off;
       if (cnt > 0) {
         const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
-        h->levels[L].push_back({var, off, cnt, var.mode >= 2 ? ts.dev_A : ts.dev_T});
+        h->levels[L].push_back({var, off, cnt, var.mode >= 2 ? ts.dev_A : ts.dev_T, pass_flow});
       }
-    }
+      }
   if (solves.size() != total) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
   if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
   he = upload(h, &h->d_solves, solves.data(), solves.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload solve lists");
+  if (!flow_tasks.empty()) {
+    // predecessors of a task: for each of its solves (e, d) and each inflow
+    // face of e with an upwind element u, the task holding the solve (u, d)
+    // (same class, so the same position of d in the class's direction list)
+    std::vector<std::vector<int>> rank(n_probs);  // [class][element]: position within its level
+    for (int k = 0; k < n_probs; ++k) {
+      const auto &pl = h->plans[k];
+      rank[k].assign((size_t)pl.n_groups * pl.ne, 0);
+      for (int g = 0; g < pl.n_groups; ++g) {
+        const int *lo = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
+        const int32_t *ord = &pl.order[(size_t)g * pl.ne];
+        for (int L = 0; L < pl.n_levels; ++L)
+          for (int t = lo[L]; t < lo[L + 1]; ++t) rank[k][(size_t)g * pl.ne + ord[t]] = t - lo[L];
+      }
+    }
+    std::vector<int2> ft;
+    std::vector<int> pptr(1, 0), pidx;
+    for (auto &kv : flow_tasks) {
+      const Variant &var = kv.first;
+      const int base = (int)ft.size();
+      const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
+      h->flow.push_back({var, base, (int)kv.second.size(), var.mode >= 2 ? ts.dev_A : ts.dev_T});
+      const int tsz = solves_per_round(var.mode, (var.p + 1) * (var.p + 1)) * kFlowRounds;
+      const auto &blks = flow_task_blk[var];
+      std::vector<int> pre;
+      for (size_t i = 0; i < kv.second.size(); ++i) {
+        const int2 tk = kv.second[i];
+        const int blk = blks[i];
+        const int k = (int)(std::upper_bound(blk_first.begin(), blk_first.end(), blk) - blk_first.begin()) - 1;
+        const auto &pl = h->plans[k];
+        const int g = (blk - blk_first[k]) / pl.n_levels;
+        const int nd_g = (int)dirs_of[k][g].size();
+        pre.clear();
+        for (int x = tk.x; x < tk.x + tk.y; ++x) {
+          const int e = solves[x].x, d = solves[x].y & 0xffff;
+          const int di = (x - blk_solve0[blk]) % nd_g;
+          const unsigned inflow = pl.mask[(size_t)d * pl.ne + e] & 15u;
+          for (int f = 0; f < 4; ++f) {
+            const int u = pl.nbr[4 * (size_t)e + f];
+            if (!((inflow >> f) & 1u) || u < 0) continue;
+            const int Lu = pl.level[(size_t)g * pl.ne + u];
+            const int bu = blk_first[k] + g * pl.n_levels + Lu;
+            const int pos = rank[k][(size_t)g * pl.ne + u] * nd_g + di;
+            const int pt = base + blk_task0[bu] + pos / tsz;
+            if (std::find(pre.begin(), pre.end(), pt) == pre.end()) pre.push_back(pt);
+          }
+        }
+        pidx.insert(pidx.end(), pre.begin(), pre.end());
+        pptr.push_back((int)pidx.size());
+      }
+      ft.insert(ft.end(), kv.second.begin(), kv.second.end());
+    }
+    h->n_flow_tasks = (int)ft.size();
+    he = upload(h, &h->d_flow_tasks, ft.data(), ft.size());
+    if (he == hipSuccess) he = upload(h, &h->d_pred_ptr, pptr.data(), pptr.size());
+    if (he == hipSuccess) he = upload(h, &h->d_pred_idx, pidx.data(), pidx.size());
+    if (he == hipSuccess) he = dev_alloc(h, &h->d_flow_flags, (size_t)h->n_flow_tasks + 1);
+    if (he == hipSuccess) he = hipMemset(h->d_flow_flags, 0, sizeof(int) * ((size_t)h->n_flow_tasks + 1));
+    if (he != hipSuccess) return hip_fail(h, he, "upload persistent task lists");
+  }
   // direction-resident tasks: (problem, direction) per variant, one list per kernel choice
   std::vector<int2> tasks;
   for (int pipe = 0; pipe < 2; ++pipe)
@@ -609,6 +731,12 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
   };
   he = vefk::launch_run_init(h->d_io, np, a->n_iter, stop, iters, status, s);
   if (he != hipSuccess) return hip_fail(h, he, "launch init");
+  const bool persistent = h->schedule == VEF_PERSISTENT;
+  if (persistent && !h->flow.empty()) {
+    // task flags and the abort flag start from zero in every run
+    he = vefk::launch_zero_ints(h->d_flow_flags, h->n_flow_tasks + 1, s);
+    if (he != hipSuccess) return hip_fail(h, he, "launch flag reset");
+  }
   for (int it = 0; it < a->n_iter; ++it) {
     if (timed(it) && (he = hipEventRecord(h->events[2 * it], s)) != hipSuccess)
       return hip_fail(h, he, "record timing event");
@@ -626,9 +754,32 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
     SL.ring = h->pipeline_ring;
     SL.fixup = h->fixup;
     SL.wait_spins = h->wait_polls;
-    if (h->schedule == VEF_LEVEL_SYNC) {
+    if (persistent) {
+      for (auto &F : h->flow) {
+        SL.p = F.v.p;
+        SL.nq = F.v.nq;
+        SL.mode = F.v.mode;
+        SL.flow = true;
+        SL.list = h->d_solves;
+        SL.tasks = h->d_flow_tasks + F.off;
+        SL.count = F.cnt;
+        SL.pred_ptr = h->d_pred_ptr + F.off;
+        SL.pred_idx = h->d_pred_idx;
+        SL.flags = h->d_flow_flags;
+        SL.own_base = F.off;
+        SL.abort_flag = h->d_flow_flags + h->n_flow_tasks;
+        SL.n_cu = h->n_cu;
+        SL.tables = F.tab;
+        he = vefk::launch_sweep_level(SL);
+        if (he != hipSuccess) return hip_fail(h, he, "launch persistent sweep");
+        if (timed(it)) h->timed_launches++;
+      }
+      SL.flow = false;
+    }
+    if (h->schedule == VEF_LEVEL_SYNC || persistent) {
       for (auto &lv : h->levels)
         for (auto &L : lv) {
+          if (persistent && L.flow) continue;  // in a persistent launch
           SL.p = L.v.p;
           SL.nq = L.v.nq;
           SL.mode = L.v.mode;
@@ -900,6 +1051,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
   add({VEF_LEVEL_SYNC, before.waves, 256});
   add({VEF_LEVEL_SYNC, before.waves, 128});
   add({VEF_DIR_RESIDENT, -1, before.block});
+  if (!h->flow.empty()) add({VEF_PERSISTENT, before.waves, 256});
   if (any_pipe)
     for (int w : {8, 6, 4}) add({VEF_DIR_RESIDENT, w, before.block});
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -58,7 +58,7 @@ struct SweepLaunch {
   int mode;          // 0: general elements, pivoting; 1: general, pivot-free; 2: affine, pivot-free
   const int2 *list;  // level schedule: (element, direction | problem << 16) pairs of one level;
                      // direction-resident schedule: (problem, direction) tasks
-  int count;
+  int count;       // level: solves; direction-resident: tasks; persistent: tasks
   int width;       // direction-resident: widest upwind level
   int max_levels;  // direction-resident: deepest level count (offsets staged in LDS)
   int max_gap;     // pipelined: largest level gap of an upwind edge that is not lagged
@@ -66,6 +66,14 @@ struct SweepLaunch {
   int ring;        // pipelined: trace ring depth in levels (0 = default)
   int fixup;       // 1: negative-flux fixup after each local solve (kernel variant)
   long long wait_spins;   // pipelined: bound of a wait, in polls of about 64 clocks each
+  bool flow;             // persistent schedule: list = every solve of the handle in level order
+  const int2 *tasks;     // persistent: (first solve, solves) of this variant's tasks
+  const int *pred_ptr;   // persistent: [count + 1] offsets into pred_idx
+  const int *pred_idx;   // persistent: flag indices of each task's predecessor tasks
+  int *flags;            // persistent: per task of the handle, sweep number when done (zeroed by each run)
+  int own_base;          // persistent: flag index of this variant's first task
+  int *abort_flag;       // persistent: set when a wait expires (zeroed by each run)
+  int n_cu;              // persistent: compute units of the device
   const KProb *probs;
   const KIO *io;
   const void *tables;
@@ -86,6 +94,9 @@ hipError_t launch_boundary(bool fp32, const KProb *probs, const KIO *io, int pro
                            int p, const int *stop, hipStream_t s);
 hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, int *iters, int *status,
                            hipStream_t s);
+// Zero n ints (counters of the persistent schedule) with a kernel, not a
+// memset node, so that a captured run replays correctly.
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 hipError_t launch_finalize(const KIO *io, int n_probs, int it, double tol, int *stop, int *iters,
                            int *iters_user, hipStream_t s);
 hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int nbf,

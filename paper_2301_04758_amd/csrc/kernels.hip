@@ -137,6 +137,11 @@ __global__ void k_run_init(const KIO *__restrict__ io, int n_probs, int n_iter, 
   }
 }
 
+__global__ void k_zero_ints(int *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 __global__ void k_finalize(const KIO *__restrict__ io, int n_probs, int it, double tol, int *stop,
                            int *iters, int *iters_user) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -286,6 +291,12 @@ hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, in
   const int tot = n_probs * n_iter;
   const int grid = (tot + 255) / 256 > 0 ? (tot + 255) / 256 : 1;
   hipLaunchKernelGGL(k_run_init, dim3(grid), dim3(256), 0, s, io, n_probs, n_iter, stop, iters, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_ints, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ enum : int {
   MODE_AFFINE_NOPIVOT = 2,
   MODE_AFFINE_PIPELINE = 3,  // direction-resident schedule only, p <= 2
   MODE_GENERAL_PIPELINE = 4, // the same for straight-sided bilinear elements (m = 1)
+  MODE_AFFINE_LU = 5,        // affine, pivot-free, p >= 3: row-set LU with fused broadcasts
   MODE_KIND = 7,             // mask of the kernel kind above
   MODE_FIX = 8               // flag: negative-flux fixup after each local solve
 };
@@ -208,6 +209,25 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Angular-flux accesses that other work-groups of the same launch may read
+// (COH: the persistent schedule) are agent-scope atomic loads and stores:
+// each goes to the device's coherence point by itself, so no cache-wide
+// fence is needed around them.
+template <bool COH, typename T>
+__device__ __forceinline__ T ld_psi(const T *p) {
+  if constexpr (COH)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <bool COH, typename T>
+__device__ __forceinline__ void st_psi(T *p, T v) {
+  if constexpr (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
 // Step K of the pivot-free Gauss-Jordan elimination: lane K's row is the
 // pivot row; every lane subtracts l times it, where the pivot lane's own l
 // turns its row into the row divided by its pivot.
@@ -322,7 +342,7 @@ __device__ __forceinline__ void load_one(SolveIn<P, NQ, T> &in, int d, const KPr
 // Assemble and solve one element-direction system from prefetched inputs.
 // All lanes of the slot must call it; slots with in.valid == false store
 // nothing.  Uses only the slot's LDS area (no work-group barrier inside).
-template <int P, int NQ, typename T, bool PIVOT, bool FIX>
+template <int P, int NQ, typename T, bool PIVOT, bool FIX, bool COH = false>
 __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, const KProb &pb,
                                            const KIO &pio, T *lds, int r, int slot, int *status) {
   using S = Shape<P, NQ>;
@@ -352,7 +372,7 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
       const int f2 = (in.flags >> (4 + 2 * f)) & 3;
       const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
 #pragma unroll
-      for (int c = 0; c < P1; ++c) tr[f][c] = up[face_node<P>(f2, P - c)];
+      for (int c = 0; c < P1; ++c) tr[f][c] = ld_psi<COH>(up + face_node<P>(f2, P - c));
     }
   }
 
@@ -514,7 +534,7 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
   }
   if (row_ok) {
     T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
-    out[my_k] = rhs;
+    st_psi<COH>(out + my_k, rhs);
     if (!__builtin_isfinite(rhs)) atomicOr(status, 1);  // non-finite unknown
   }
 }
@@ -559,7 +579,7 @@ __device__ __forceinline__ void load_one(SolveInA<P, NQ, T> &in, int d, const KP
 }
 
 // Solve on an affine element (see the file comment); pivot-free.
-template <int P, int NQ, typename T, bool PIVOT, bool FIX>
+template <int P, int NQ, typename T, bool PIVOT, bool FIX, bool COH = false>
 __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, const KProb &pb,
                                           const KIO &pio, T *lds, int r, int slot, int *status) {
   using S = Shape<P, NQ>;
@@ -589,7 +609,7 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
       const int f2 = (in.flags >> (4 + 2 * f)) & 3;
       const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
 #pragma unroll
-      for (int c = 0; c < P1; ++c) tr[f][c] = up[face_node<P>(f2, P - c)];
+      for (int c = 0; c < P1; ++c) tr[f][c] = ld_psi<COH>(up + face_node<P>(f2, P - c));
     }
   }
 
@@ -698,7 +718,7 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
   }
   if (row_ok) {
     T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
-    out[r] = rhs;
+    st_psi<COH>(out + r, rhs);
     if (!__builtin_isfinite(rhs)) atomicOr(status, 1);  // non-finite unknown
   }
 }
@@ -1316,6 +1336,663 @@ k_sweep_pipe(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row-set LU for affine elements of degree 3 and 4 (pivot-free, as the other
+// affine kernels: straight faces and sigma_t > 0).  A slot is one 16-lane DPP
+// row; lane l holds RS rows of the augmented system [A | b], row l + s H of
+// set s (RS = 1, H = 16 for p = 3; RS = 2, H = 13 for p = 4).  Step K of the
+// right-looking elimination broadcasts pivot row K from its lane with
+// row_newbcast fused into the multiply-add (v_fmac_*_dpp), so an update costs
+// one instruction and no lane moves; rows of the mixed set below the pivot
+// take the multipliers, the other sets' rows are all below it (or all above,
+// and skip the step).  The pivot entry and the multipliers of the mixed set
+// are cleared as they are used, and the reciprocal pivots are kept, so the
+// back substitution is the same broadcast update on the right-hand side
+// column.  Work per slot: n^2 (n + 3)/3 fused updates for p = 4 spread over
+// 13 lanes (2/3 n^3 flops for LU plus 2 n^2 for the substitutions).
+// ---------------------------------------------------------------------------
+
+template <int P>
+struct LuShape {
+  static constexpr int P1 = P + 1, N = P1 * P1;
+  static constexpr int SLOT = 16, SPW = 4;
+  static constexpr int RS = (N + SLOT - 1) / SLOT;  // rows held per lane
+  static constexpr int H = (N + RS - 1) / RS;       // lanes holding rows
+};
+
+template <int P, int NQ>
+struct LuLds {
+  static constexpr int P1 = P + 1, N = P1 * P1, Q = NQ * NQ;
+  // tables: 1D mass m [P1][P1], 1D derivative table gd [P1][P1], boundary
+  // table w_q l_a(s_q) [NQ][P1]
+  static constexpr int T_M = 0, T_GD = P1 * P1, T_WL = 2 * P1 * P1, TAB = 2 * P1 * P1 + NQ * P1;
+  // per slot: geometry [16] (J, adj(F), face chords), nodal source [N], q_dir [Q]
+  static constexpr int A_G = 0, A_S = 16, A_QD = 16 + N, AREA = ((16 + N + Q + 1) / 2) * 2;
+};
+
+template <int B, int E, int S = 1, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr ((S > 0 && B < E) || (S < 0 && B > E)) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + S, E, S>(f);
+  }
+}
+
+// acc -= src[lane K of the 16-lane row] * mul, the broadcast fused into the
+// multiply-add.  The s_nop provides the two wait states a DPP read needs after
+// a VALU write of its source (the compiler does not insert them for asm).
+template <int K>
+__device__ __forceinline__ void fnma_bcast(double &acc, double src, double mul) {
+  asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(src), "v"(mul), "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void fnma_bcast(float &acc, float src, float mul) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(src), "v"(mul), "i"(K));
+}
+
+// Per-lane inputs of one solve (loaded ahead of it).
+template <int P, int NQ, typename T>
+struct SolveInL {
+  static constexpr int Q = NQ * NQ, QD = (Q + 15) / 16;
+  int e, flags;
+  int nb[4];
+  bool valid;
+  T g;      // geometry value r of the element (16 per element)
+  T s[2];   // nodal source at nodes r and r + 16
+  T qd[QD]; // q_dir at volume points r, r + 16, ...
+};
+
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void load_one(SolveInL<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio, int it,
+                                         int r) {
+  constexpr int N = LuShape<P>::N, Q = NQ * NQ;
+  const int e = in.e;
+  if (!in.valid) return;
+  in.g = static_cast<const T *>(pb.geo_a)[(size_t)e * 16 + r];
+  const double *phi = it == 0 ? pio.phi_in : pio.mom;
+  const double ss = pb.sig[2 * e + 1] * kInv4Pi;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int node = r + 16 * k;
+    T sv = T(0);
+    if (node < N) {
+      if (phi) sv = static_cast<T>(ss) * static_cast<T>(phi[(size_t)e * N + node]);
+      if (pio.q_iso) sv += static_cast<T>(pio.q_iso[(size_t)e * N + node]);
+    }
+    in.s[k] = sv;
+  }
+#pragma unroll
+  for (int k = 0; k < SolveInL<P, NQ, T>::QD; ++k) {
+    const int q = r + 16 * k;
+    in.qd[k] = (pio.q_dir && q < Q) ? static_cast<T>(pio.q_dir[((size_t)d * pb.ne + e) * Q + q]) : T(0);
+  }
+}
+
+// Assemble and solve one element-direction system (all 16 lanes of the slot
+// call it).  tab: the LDS tables (LuLds), wv: w V [Q][n] in global memory
+// (direction-dependent source only), area: the slot's LDS area.
+template <int P, int NQ, typename T, bool FIX, bool COH = false>
+__device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio,
+                                             const T *tab, const T *wv, T *area, int r, int *status) {
+  using S = LuShape<P>;
+  using LD = LuLds<P, NQ>;
+  constexpr int P1 = S::P1, N = S::N, RS = S::RS, H = S::H, Q = NQ * NQ;
+  const T *m1 = tab + LD::T_M;
+  const T *gdt = tab + LD::T_GD;
+  const T *WL = tab + LD::T_WL;
+  const int ne = pb.ne;
+  const int e = in.e;
+  const bool valid = in.valid;
+  const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
+
+  // staging (wave-local)
+  area[LD::A_G + r] = in.g;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (r + 16 * k < N) area[LD::A_S + r + 16 * k] = in.s[k];
+  if (pio.q_dir) {
+#pragma unroll
+    for (int k = 0; k < SolveInL<P, NQ, T>::QD; ++k)
+      if (r + 16 * k < Q) area[LD::A_QD + r + 16 * k] = in.qd[k];
+  }
+  wave_sync_lds();
+
+  // upwind traces of the inflow faces (every lane reads them all)
+  const T *psi = static_cast<const T *>(pio.psi);
+  T tr[4][P1];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+#pragma unroll
+    for (int c = 0; c < P1; ++c) tr[f][c] = T(0);
+    if (valid && ((mask >> f) & 1u) && in.nb[f] >= 0) {
+      const int f2 = (in.flags >> (4 + 2 * f)) & 3;
+      const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
+#pragma unroll
+      for (int c = 0; c < P1; ++c) tr[f][c] = ld_psi<COH>(up + face_node<P>(f2, P - c));
+    }
+  }
+
+  const T ox = static_cast<T>(pb.omega[2 * d]);
+  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
+  const T st = static_cast<T>(pb.sig[2 * (valid ? e : 0)]);
+  const T *g = area + LD::A_G;
+  const T J = g[0];
+  const T stJ = st * J;
+  const T gx = g[1] * ox + g[2] * oy;
+  const T gy = g[3] * ox + g[4] * oy;
+  T on[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) on[f] = ox * g[5 + 2 * f] + oy * g[6 + 2 * f];
+
+  // assembly of the lane's rows: A[(a,b)][(c,d)] = m_bd (stJ m_ac - gx gd_ac)
+  // - gd_bd (gy m_ac) (test index first), plus (Omega . N_f) m on outflow
+  // faces; b = J (m (x) m) s + J (w V)^T q_dir - inflow face terms
+  T A[RS][N + 1];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int row = r + s * H;
+    const bool row_ok = valid && r < H && row < N;
+    const int rr = (r < H && row < N) ? row : N - 1;
+    const int a = rr % P1, b = rr / P1;
+    T Xa[P1], Ya[P1], mb[P1], gb[P1], ma[P1];
+#pragma unroll
+    for (int c = 0; c < P1; ++c) {
+      ma[c] = m1[a * P1 + c];
+      Xa[c] = stJ * ma[c] - gx * gdt[a * P1 + c];
+      Ya[c] = gy * ma[c];
+      mb[c] = m1[b * P1 + c];
+      gb[c] = gdt[b * P1 + c];
+    }
+    T rhs = T(0);
+#pragma unroll
+    for (int dd = 0; dd < P1; ++dd) {
+      T acc = T(0);
+#pragma unroll
+      for (int c = 0; c < P1; ++c) {
+        A[s][c + P1 * dd] = mb[dd] * Xa[c] - gb[dd] * Ya[c];
+        acc += ma[c] * area[LD::A_S + c + P1 * dd];
+      }
+      rhs += mb[dd] * acc;
+    }
+    rhs *= J;
+    if (pio.q_dir) {
+      T acc = T(0);
+      for (int q = 0; q < Q; ++q) acc += wv[q * N + rr] * area[LD::A_QD + q];
+      rhs += J * acc;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+      const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+      if (!((mask >> f) & 1u)) {
+        // outflow face: a multiply by zero off the face instead of a branch
+        const T cf = on_face ? on[f] : T(0);
+#pragma unroll
+        for (int c = 0; c < P1; ++c) A[s][face_node<P>(f, c)] += cf * m1[pos * P1 + c];
+      } else if (row_ok && on_face) {
+        if (in.nb[f] >= 0) {
+          T acc = T(0);
+#pragma unroll
+          for (int c = 0; c < P1; ++c) acc += m1[pos * P1 + c] * tr[f][c];
+          rhs -= on[f] * acc;
+        } else if (pio.psi_bc) {
+          const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
+          T acc = T(0);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) acc += WL[q * P1 + pos] * static_cast<T>(bc[q]);
+          rhs -= on[f] * acc;
+        }
+      }
+    }
+    A[s][N] = rhs;
+  }
+
+  // LU of [A | b] in natural order
+  T idg[RS];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) idg[s] = T(0);
+  static_for<0, N>([&](auto kk) {
+    constexpr int K = decltype(kk)::value;
+    constexpr int SA = K / H, LK = K % H;
+    const T inv = slot_bcast<16, LK>(recip(A[SA][K]));
+    if (r == LK) idg[SA] = inv;
+    T l[RS];
+#pragma unroll
+    for (int s = SA; s < RS; ++s) l[s] = A[s][K] * inv;
+    l[SA] = r > LK ? l[SA] : T(0);
+    A[SA][K] = r >= LK ? T(0) : A[SA][K];
+    static_for<K + 1, N + 1>([&](auto jj) {
+      constexpr int J = decltype(jj)::value;
+      static_for<SA + 1, RS>([&](auto ss) { fnma_bcast<LK>(A[decltype(ss)::value][J], A[SA][J], l[decltype(ss)::value]); });
+      fnma_bcast<LK>(A[SA][J], A[SA][J], l[SA]);
+    });
+  });
+  // back substitution U x = y on the right-hand side column
+  static_for<N - 1, -1, -1>([&](auto ii) {
+    constexpr int I = decltype(ii)::value;
+    constexpr int SA = I / H, LI = I % H;
+    const T t = A[SA][N] * idg[SA];
+    static_for<0, SA + 1>([&](auto ss) { fnma_bcast<LI>(A[decltype(ss)::value][N], t, A[decltype(ss)::value][I]); });
+  });
+  T x[RS];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) x[s] = A[s][N] * idg[s];
+
+  if constexpr (FIX) {
+    // negative-flux fixup (see zero_and_scale_slot) over the slot's rows:
+    // balance weight of node (a, b) = stJ sm_a sm_b + outflow faces through
+    // it (Omega . N_f) sm_pos, sm = row sums of m
+    bool neg = false;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int row = r + s * H;
+      neg |= valid && r < H && row < N && x[s] < T(0);
+    }
+    if (__builtin_amdgcn_ballot_w64(neg) != 0) {
+      T cx = T(0), cp = T(0);
+      int nneg = 0;
+#pragma unroll
+      for (int s = 0; s < RS; ++s) {
+        const int row = r + s * H;
+        const bool row_ok = valid && r < H && row < N;
+        const int rr = row_ok ? row : 0;
+        const int a = rr % P1, b = rr / P1;
+        T sa = T(0), sb = T(0);
+        for (int c = 0; c < P1; ++c) {
+          sa += m1[a * P1 + c];
+          sb += m1[b * P1 + c];
+        }
+        T c0 = stJ * sa * sb;
+        for (int f = 0; f < 4; ++f) {
+          const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+          if (!on_face || ((mask >> f) & 1u)) continue;
+          const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+          T sp = T(0);
+          for (int c = 0; c < P1; ++c) sp += m1[pos * P1 + c];
+          c0 += on[f] * sp;
+        }
+        if (row_ok) {
+          cx += c0 * x[s];
+          if (x[s] > T(0)) cp += c0 * x[s];
+          nneg += x[s] < T(0) ? 1 : 0;
+        }
+      }
+#pragma unroll
+      for (int m = 1; m < 16; m <<= 1) {
+        cx += __shfl_xor(cx, m);
+        cp += __shfl_xor(cp, m);
+        nneg += __shfl_xor(nneg, m);
+      }
+      if (nneg > 0) {
+        const T alpha = (cx > T(0) && cp > T(0)) ? cx / cp : T(0);
+#pragma unroll
+        for (int s = 0; s < RS; ++s) x[s] = x[s] > T(0) ? alpha * x[s] : T(0);
+      }
+    }
+  }
+  T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int row = r + s * H;
+    if (valid && r < H && row < N) {
+      st_psi<COH>(out + row, x[s]);
+      if (!__builtin_isfinite(x[s])) atomicOr(status, 1);  // non-finite unknown
+    }
+  }
+}
+
+// Stage the LU tables (m, gd, w l) from the affine table blob into LDS.
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void stage_tables_lu(const T *__restrict__ tables, T *lds) {
+  using S = Shape<P, NQ>;
+  using LD = LuLds<P, NQ>;
+  constexpr int PP = S::P1 * S::P1;
+  for (int i = threadIdx.x; i < LD::TAB; i += blockDim.x) {
+    T v;
+    if (i < PP)
+      v = tables[S::A_M1 + i];
+    else if (i < 2 * PP)
+      v = tables[S::A_GD1 + i - PP];
+    else
+      v = tables[S::A_WL + i - 2 * PP];
+    lds[i] = v;
+  }
+}
+
+// Level-synchronous schedule with the row-set LU (one slot per solve).
+template <int P, int NQ, typename T, bool FIX>
+__global__ void __launch_bounds__(256)
+k_sweep_level_lu(const int2 *__restrict__ solves, int n_solves, const KProb *__restrict__ probs,
+                 const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
+                 int *__restrict__ status) {
+  using S = LuShape<P>;
+  using LD = LuLds<P, NQ>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  if (*stop) return;
+  stage_tables_lu<P, NQ, T>(tables, lds);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;
+  const int slot = (threadIdx.x >> 6) * S::SPW + (lane >> 4);
+  const int sid = blockIdx.x * ((blockDim.x >> 6) * S::SPW) + slot;
+  SolveInL<P, NQ, T> in;
+  in.valid = sid < n_solves;
+  int d = 0, prob = 0;
+  in.e = 0;
+  in.flags = 0;
+  if (in.valid) {
+    const int2 sv = solves[sid];
+    in.e = sv.x;
+    d = sv.y & 0xffff;
+    prob = sv.y >> 16;
+  }
+  const KProb &pb = probs[prob];
+  const KIO &pio = io[prob];
+  if (in.valid) {
+    in.flags = pb.mask[(size_t)d * pb.ne + in.e];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      in.nb[f] = pb.nbr[4 * in.e + f];
+      in.flags |= ((int)pb.nbr_face[4 * in.e + f] & 3) << (4 + 2 * f);
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) in.nb[f] = -1;
+  }
+  load_one<P, NQ, T>(in, d, pb, pio, it, r);
+  solve_one_lu<P, NQ, T, FIX>(in, d, pb, pio, lds, tables + Shape<P, NQ>::A_WV, lds + LD::TAB + (size_t)slot * LD::AREA,
+                              r, status);
+}
+
+// Direction-resident schedule with the row-set LU (as k_sweep_dir).
+template <int P, int NQ, typename T, bool FIX>
+__global__ void __launch_bounds__(256)
+k_sweep_dir_lu(const int2 *__restrict__ tasks, const KProb *__restrict__ probs, const KIO *__restrict__ io,
+               const T *__restrict__ tables, int it, const int *__restrict__ stop, int *__restrict__ status) {
+  using S = LuShape<P>;
+  using LD = LuLds<P, NQ>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  if (*stop) return;
+  const int2 tk = tasks[blockIdx.x];
+  const int prob = tk.x, d = tk.y;
+  const KProb &pb = probs[prob];
+  const KIO &pio = io[prob];
+  const int g = pb.dir_group[d];
+  const int nl = pb.n_levels_g[g];
+  const int slots = (blockDim.x >> 6) * S::SPW;
+  int *lo = reinterpret_cast<int *>(lds + LD::TAB + (size_t)slots * LD::AREA);
+  stage_tables_lu<P, NQ, T>(tables, lds);
+  const int32_t *lo_g = pb.level_off + (size_t)g * (pb.n_levels + 1);
+  for (int i = threadIdx.x; i <= nl; i += blockDim.x) lo[i] = lo_g[i];
+  __syncthreads();
+  const int2 *dsc = pb.desc_ef + (size_t)g * pb.ne;
+  const int4 *dnb = pb.desc_nb + (size_t)g * pb.ne;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;
+  const int slot = (threadIdx.x >> 6) * S::SPW + (lane >> 4);
+  T *area = lds + LD::TAB + (size_t)slot * LD::AREA;
+  const T *wv = tables + Shape<P, NQ>::A_WV;
+
+  auto fetch = [&](SolveInL<P, NQ, T> &in, int L, int t) {
+    in.valid = L < nl && t < lo[L + 1];
+    in.e = 0;
+    in.flags = 0;
+    in.nb[0] = in.nb[1] = in.nb[2] = in.nb[3] = -1;
+    if (in.valid) {
+      const int2 ef = dsc[t];
+      const int4 nb = dnb[t];
+      in.e = ef.x;
+      in.flags = ef.y;
+      in.nb[0] = nb.x;
+      in.nb[1] = nb.y;
+      in.nb[2] = nb.z;
+      in.nb[3] = nb.w;
+    }
+    load_one<P, NQ, T>(in, d, pb, pio, it, r);
+  };
+
+  SolveInL<P, NQ, T> cur, nxt;
+  int L = 0, base = 0;
+  fetch(cur, 0, slot);
+  while (L < nl) {
+    int L2 = L, base2 = base + slots;
+    if (base2 >= lo[L + 1]) {
+      L2 = L + 1;
+      base2 = L2 < nl ? lo[L2] : 0;
+    }
+    fetch(nxt, L2, base2 + slot);
+    solve_one_lu<P, NQ, T, FIX>(cur, d, pb, pio, lds, wv, area, r, status);
+    if (L2 != L) __syncthreads();  // the level's fluxes are upwind values of the next
+    cur = nxt;
+    L = L2;
+    base = base2;
+  }
+}
+
+template <int P, int NQ, typename T, bool FIX>
+hipError_t launch_level_lu_t(const SweepLaunch &L) {
+  if constexpr (P < 3) {
+    return hipErrorInvalidValue;
+  } else {
+    using LD = LuLds<P, NQ>;
+    const int block = L.block > 256 ? 256 : (L.block < 64 ? 64 : L.block);
+    const int per_block = (block / 64) * LuShape<P>::SPW;
+    const size_t bytes = sizeof(T) * ((size_t)LD::TAB + (size_t)LD::AREA * per_block);
+    if (bytes > L.lds_max) return hipErrorInvalidValue;
+    const int grid = (L.count + per_block - 1) / per_block;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep_level_lu<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes, L.stream, L.list, L.count,
+                       L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
+    return hipGetLastError();
+  }
+}
+
+template <int P, int NQ, typename T, bool FIX>
+hipError_t launch_dir_lu_t(const SweepLaunch &L) {
+  if constexpr (P < 3) {
+    return hipErrorInvalidValue;
+  } else {
+    if (L.count == 0) return hipSuccess;
+    using LD = LuLds<P, NQ>;
+    int block = ((L.width * 16 + 63) / 64) * 64;
+    block = block < 64 ? 64 : (block > 256 ? 256 : block);
+    for (; block >= 64; block -= 64) {
+      const size_t bytes = sizeof(T) * ((size_t)LD::TAB + (size_t)LD::AREA * (block / 64) * LuShape<P>::SPW) +
+                           sizeof(int) * ((size_t)L.max_levels + 1);
+      if (bytes <= L.lds_max) {
+        hipLaunchKernelGGL((k_sweep_dir_lu<P, NQ, T, FIX>), dim3(L.count), dim3(block), bytes, L.stream, L.list,
+                           L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
+        return hipGetLastError();
+      }
+    }
+    return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent schedule: one launch per sweep (and kernel variant) with every
+// resident wave a worker.  The solves of each (problem, direction class,
+// upwind level) are cut into tasks of a few rounds of consecutive solves
+// (element-major, all directions of the class); the tasks, sorted by level,
+// are dealt round-robin to the workers (wave w takes tasks w, w + W, ...).
+// A task waits only for the tasks that hold its upwind elements' solves of
+// the same directions (a predecessor list made at create), through one flag
+// per task set to the sweep number when the task is done.  A predecessor is
+// on a lower level, so it precedes the task in every worker's list, and all
+// tasks finish provided every worker is resident: the grid is sized from the
+// kernel's occupancy.  The angular flux that crosses work-groups is written
+// and read with agent-scope atomic stores and loads, and a task's flag is
+// stored once its stores have completed, so no cache-wide fence is needed.
+// Waits are bounded: on expiry a wave sets the status word and a global
+// abort flag that makes every other wave leave as well.  Each wave loads the
+// inputs of its next solves (element data, not the upwind traces) while it
+// solves the current ones.
+// ---------------------------------------------------------------------------
+
+// Per-variant solve policy: the row-set LU (affine, p >= 3) or the
+// row-per-lane kernels (general elements).
+template <int P, int NQ, typename T, int MODE, bool LU = ((MODE & MODE_KIND) == MODE_AFFINE_LU)>
+struct FlowPolicy;
+
+template <int P, int NQ, typename T, int MODE>
+struct FlowPolicy<P, NQ, T, MODE, true> {
+  static constexpr int SLOT = 16, SPW = 4;
+  static constexpr int TAB = LuLds<P, NQ>::TAB, AREA = LuLds<P, NQ>::AREA;
+  using In = SolveInL<P, NQ, T>;
+  static __device__ __forceinline__ void stage(const T *tables, T *lds) { stage_tables_lu<P, NQ, T>(tables, lds); }
+  static __device__ __forceinline__ void solve(const In &in, int d, const KProb &pb, const KIO &pio,
+                                               const T *tables, T *lds, int r, int slot, int *status) {
+    solve_one_lu<P, NQ, T, false, true>(in, d, pb, pio, lds, tables + Shape<P, NQ>::A_WV,
+                                        lds + TAB + (size_t)slot * AREA, r, status);
+  }
+};
+
+template <int P, int NQ, typename T, int MODE>
+struct FlowPolicy<P, NQ, T, MODE, false> {
+  static constexpr int SLOT = Shape<P, NQ>::SLOT, SPW = Shape<P, NQ>::SPW;
+  static constexpr int TAB = Lds<P, NQ, MODE>::TAB, AREA = Lds<P, NQ, MODE>::AREA;
+  using In = InputsOf<P, NQ, T, MODE>;
+  static __device__ __forceinline__ void stage(const T *tables, T *lds) { stage_tables<P, NQ, T, MODE>(tables, lds); }
+  static __device__ __forceinline__ void solve(const In &in, int d, const KProb &pb, const KIO &pio,
+                                               const T *tables, T *lds, int r, int slot, int *status) {
+    (void)tables;
+    solve_one<P, NQ, T, (MODE & MODE_KIND) == MODE_GENERAL_PIVOT, false, true>(in, d, pb, pio, lds, r, slot, status);
+  }
+};
+
+// One slot's work item: the solve's inputs and its direction and problem.
+template <typename In>
+struct FlowItem {
+  In in;
+  int d, prob;
+};
+
+template <int P, int NQ, typename T, int MODE>
+__global__ void __launch_bounds__(256)
+k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, int n_tasks,
+             const int *__restrict__ pred_ptr, const int *__restrict__ pred_idx, int *__restrict__ flags,
+             int own_base, int *__restrict__ abort_flag, const KProb *__restrict__ probs,
+             const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
+             int *__restrict__ status, long long wait_spins) {
+  using Pol = FlowPolicy<P, NQ, T, MODE>;
+  using Item = FlowItem<typename Pol::In>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  if (*stop) return;
+  Pol::stage(tables, lds);
+  __syncthreads();  // the only work-group barrier: waves work independently from here on
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int W = gridDim.x * (blockDim.x >> 6);
+  const int w = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int r = lane & (Pol::SLOT - 1);
+  const int sw = lane / Pol::SLOT;         // slot within the wave
+  const int slot = wave * Pol::SPW + sw;  // slot within the work-group (LDS area)
+  const int epoch = it + 1;               // flag value of a task done in this sweep
+  if (w >= n_tasks) return;
+
+  auto fetch = [&](Item &x, const int2 &tk, int rd) {
+    const int k = rd * Pol::SPW + sw;
+    x.in.valid = k < tk.y;
+    x.in.e = 0;
+    x.in.flags = 0;
+    x.d = 0;
+    x.prob = 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) x.in.nb[f] = -1;
+    if (x.in.valid) {
+      const int2 sv = solves[tk.x + k];
+      x.in.e = sv.x;
+      x.d = sv.y & 0xffff;
+      x.prob = sv.y >> 16;
+    }
+    const KProb &pb = probs[x.prob];
+    if (x.in.valid) {
+      x.in.flags = pb.mask[(size_t)x.d * pb.ne + x.in.e];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        x.in.nb[f] = pb.nbr[4 * x.in.e + f];
+        x.in.flags |= ((int)pb.nbr_face[4 * x.in.e + f] & 3) << (4 + 2 * f);
+      }
+    }
+    load_one<P, NQ, T>(x.in, x.d, pb, io[x.prob], it, r);
+  };
+
+  int t = w, rd = 0;
+  int2 tk = tasks[t];  // (first solve, solves)
+  Item cur, nxt;
+  fetch(cur, tk, 0);
+  for (;;) {
+    int t2 = t, rd2 = rd + 1;
+    int2 tk2 = tk;
+    if (rd2 * Pol::SPW >= tk.y) {
+      t2 = t + W;
+      rd2 = 0;
+      if (t2 < n_tasks) tk2 = tasks[t2];
+    }
+    const bool more = t2 < n_tasks;
+    if (more) fetch(nxt, tk2, rd2);
+    if (rd == 0) {
+      // the tasks holding this task's upwind fluxes are done in this sweep
+      const int q1 = pred_ptr[t + 1];
+      for (int q = pred_ptr[t]; q < q1; ++q) {
+        const int pt = pred_idx[q];
+        long long spins = 0;
+        while (__hip_atomic_load(flags + pt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+          if (++spins > wait_spins) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) atomicOr(status, 2);
+            return;
+          }
+          if ((spins & 63) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the trace loads stay after the waits
+    }
+    Pol::solve(cur.in, cur.d, probs[cur.prob], io[cur.prob], tables, lds, r, slot, status);
+    if ((rd + 1) * Pol::SPW >= tk.y) {
+      // task complete once this wave's angular-flux stores have completed
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane == 0) __hip_atomic_store(flags + own_base + t, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!more) break;
+    cur = nxt;
+    t = t2;
+    rd = rd2;
+    tk = tk2;
+  }
+}
+
+template <int P, int NQ, typename T, int MODE>
+hipError_t launch_flow_t(const SweepLaunch &L) {
+  if (L.count == 0) return hipSuccess;
+  using Pol = FlowPolicy<P, NQ, T, MODE>;
+  constexpr int block = 256;
+  const size_t bytes = sizeof(T) * ((size_t)Pol::TAB + (size_t)Pol::AREA * (block / 64) * Pol::SPW);
+  if (bytes > L.lds_max) return hipErrorInvalidValue;
+  // every worker must be resident: as many work-groups as fit on the device
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_flow<P, NQ, T, MODE>, block, bytes);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  int grid = per_cu * L.n_cu;
+  const int need = (L.count + (block / 64) - 1) / (block / 64);
+  if (grid > need) grid = need;
+  hipLaunchKernelGGL((k_sweep_flow<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.list, L.tasks,
+                     L.count, L.pred_ptr, L.pred_idx, L.flags, L.own_base, L.abort_flag, L.probs, L.io,
+                     static_cast<const T *>(L.tables), L.it, L.stop, L.status, L.wait_spins);
+  return hipGetLastError();
+}
+
 template <int P, int NQ, typename T, int MODE>
 hipError_t launch_dir_t(const SweepLaunch &L);
 
@@ -1407,6 +2084,20 @@ hipError_t launch_dir_t(const SweepLaunch &L) {
 
 template <int P, int NQ, typename T, bool DIR, int FX>
 hipError_t launch_mode_fx(const SweepLaunch &L) {
+  if (L.flow) {  // persistent schedule: row-per-lane general kernels and the row-set LU, without the fixup
+    if constexpr (FX != 0) {
+      return hipErrorInvalidValue;
+    } else {
+      switch (L.mode) {
+        case MODE_GENERAL_PIVOT: return launch_flow_t<P, NQ, T, MODE_GENERAL_PIVOT>(L);
+        case MODE_GENERAL_NOPIVOT: return launch_flow_t<P, NQ, T, MODE_GENERAL_NOPIVOT>(L);
+        case MODE_AFFINE_LU:
+          if constexpr (P >= 3) return launch_flow_t<P, NQ, T, MODE_AFFINE_LU>(L);
+          return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
   switch (L.mode) {
     case MODE_GENERAL_PIVOT:
       return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_PIVOT | FX>(L)
@@ -1421,6 +2112,8 @@ hipError_t launch_mode_fx(const SweepLaunch &L) {
       return DIR ? launch_pipe_t<P, NQ, T, FX != 0, false>(L) : hipErrorInvalidValue;
     case MODE_GENERAL_PIPELINE:
       return DIR ? launch_pipe_t<P, NQ, T, FX != 0, true>(L) : hipErrorInvalidValue;
+    case MODE_AFFINE_LU:
+      return DIR ? launch_dir_lu_t<P, NQ, T, FX != 0>(L) : launch_level_lu_t<P, NQ, T, FX != 0>(L);
     default: return hipErrorInvalidValue;
   }
 }

@@ -34,12 +34,15 @@ VEF_UPWIND_FACE, VEF_UPWIND_POINT = 0, 1
 VEF_SCHEDULE_AUTO = 0
 VEF_LEVEL_SYNC = 1
 VEF_DIR_RESIDENT = 2
-SCHEDULES = {"auto": VEF_SCHEDULE_AUTO, "level": VEF_LEVEL_SYNC, "dir": VEF_DIR_RESIDENT}
-SCHEDULE_NAMES = {VEF_LEVEL_SYNC: "level_sync", VEF_DIR_RESIDENT: "dir_resident"}
+VEF_PERSISTENT = 3
+SCHEDULES = {"auto": VEF_SCHEDULE_AUTO, "level": VEF_LEVEL_SYNC, "dir": VEF_DIR_RESIDENT, "persistent": VEF_PERSISTENT}
+SCHEDULE_NAMES = {VEF_LEVEL_SYNC: "level_sync", VEF_DIR_RESIDENT: "dir_resident", VEF_PERSISTENT: "persistent"}
 VEF_KERNEL_PIVOT, VEF_KERNEL_NOPIVOT, VEF_KERNEL_AFFINE, VEF_KERNEL_AFFINE_PIPELINE = 0, 1, 2, 3
 VEF_KERNEL_BILINEAR_PIPELINE = 4
+VEF_KERNEL_AFFINE_LU = 5
 KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KERNEL_AFFINE: "affine",
-                VEF_KERNEL_AFFINE_PIPELINE: "affine_pipeline", VEF_KERNEL_BILINEAR_PIPELINE: "bilinear_pipeline"}
+                VEF_KERNEL_AFFINE_PIPELINE: "affine_pipeline", VEF_KERNEL_BILINEAR_PIPELINE: "bilinear_pipeline",
+                VEF_KERNEL_AFFINE_LU: "affine_lu"}
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_sweep_run_static", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",

@@ -16,8 +16,17 @@ sizes can be checked element by element:
                 directions swept in full: angular flux at sampled nodes
   c4_some.json  the 64-problem batch, one sweep from phi = 0, for a subset
                 of the problems: moments at sampled nodes
+  c5_full.json  512x512, p=4, S16, one sweep of all 144 directions from
+                phi = 0: moments at sampled nodes
+  c5_si5.json   the same, 5 source iterations: residual history and moments
+                at sampled nodes after each iteration
+  c3_si10.json  256x256 curved, p=3, S12, 10 source iterations: residual
+                history and scalar flux at sampled nodes after the last
 
-Usage: python tests/golden/make_golden.py [c2 c3 c4 c5]   (all by default)
+Usage: python tests/golden/make_golden.py [--threads T] [c2 c3 c4 c5 c5_full c5_si5 c3_si10]
+(c2 c4 c5 c3 by default).  --threads sweeps T directions at a time on OpenMP
+threads; the oracle sums them in direction order, so the values do not
+depend on T.
 """
 import json
 import os
@@ -127,7 +136,62 @@ def make_c4():
     _write("c4_some.json", out)
 
 
+THREADS = 1
+
+
+def make_c5_full():
+    (pr,), _ = P.make_config("c5")
+    t = time.time()
+    r = O.sweep(pr, want_psi=False, threads=THREADS)
+    rng = np.random.default_rng(SAMPLE_SEED + 51)
+    idx = _sample_nodes(rng, pr.n_elem, pr.n, 400)
+    mom = r["mom"].reshape(6, -1)
+    out = _header("c5", "one sweep of every direction from phi = 0; moments at sampled flat indices")
+    out.update(index=idx.tolist(), mom=[mom[k, idx].tolist() for k in range(6)],
+               mom_absmax=[float(np.abs(mom[k]).max()) for k in range(6)], oracle_seconds=time.time() - t)
+    _write("c5_full.json", out)
+
+
+def _si_fixture(cfg, n_iter, seed, name, what):
+    (pr,), _ = P.make_config(cfg)
+    t = time.time()
+    rng = np.random.default_rng(seed)
+    idx = _sample_nodes(rng, pr.n_elem, pr.n, 400)
+    phi_hist, mom = [], None
+    phi = None
+    resid = []
+    for k in range(n_iter):
+        r = O.source_iteration(pr, 1, phi0=phi, threads=THREADS)
+        mom = r["mom"]
+        resid.append(float(r["resid"][0]))
+        phi = mom[0].copy()
+        phi_hist.append(phi.reshape(-1)[idx].tolist())
+        print(name, "iteration", k + 1, "resid %.6e" % resid[-1], "%.0f s" % (time.time() - t), flush=True)
+    flat = mom.reshape(6, -1)
+    out = _header(cfg, what)
+    out.update(n_iter=n_iter, resid=resid, index=idx.tolist(), phi=phi_hist,
+               phi_absmax=float(np.abs(flat[0]).max()), mom=[flat[k, idx].tolist() for k in range(6)],
+               mom_absmax=[float(np.abs(flat[k]).max()) for k in range(6)], oracle_seconds=time.time() - t)
+    _write(name, out)
+
+
+def make_c5_si5():
+    _si_fixture("c5", 5, SAMPLE_SEED + 52, "c5_si5.json",
+                "5 source iterations from phi = 0; residual history, scalar flux at sampled flat indices after "
+                "each iteration, moments of the last")
+
+
+def make_c3_si10():
+    _si_fixture("c3", 10, SAMPLE_SEED + 31, "c3_si10.json",
+                "10 source iterations from phi = 0; residual history, scalar flux at sampled flat indices after "
+                "each iteration, moments of the last")
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c2", "c4", "c5", "c3"]
+    args = sys.argv[1:]
+    if args[:1] == ["--threads"]:
+        THREADS = int(args[1])
+        args = args[2:]
+    which = args or ["c2", "c4", "c5", "c3"]
     for w in which:
         globals()["make_" + w]()

@@ -263,6 +263,10 @@ def test_schedules_agree(torch, precision, cfg, scale):
     (pr,), _ = P.make_config(cfg, scale=scale)
     (a,), _ = gpu_run(torch, [pr], precision, n_iter=2, schedule="level")
     (b,), _ = gpu_run(torch, [pr], precision, n_iter=2, schedule="dir")
+    # the persistent schedule runs the level-synchronous kernels' arithmetic
+    (c,), _ = gpu_run(torch, [pr], precision, n_iter=2, schedule="persistent")
+    for key in ("psi_out", "mom", "resid"):
+        assert np.array_equal(a[key], c[key]), key
     info = vef.vef_plan_query(pr)
     if info["affine"] and pr.p <= 2:
         assert rel_inf(b["psi_out"], a["psi_out"]) <= TOL[precision]
