@@ -749,6 +749,34 @@ int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, bool pointwis
   for (int e = 1; e < ne; ++e) smin = std::min(smin, d.sigma_t[e]);
   o.nopivot = o.straight && smin > 0.0;
 
+  // Per (direction, element), bit 7 of the mask: the local matrix is not
+  // certified for elimination in natural order.  It is certified when
+  // sigma_t > 0 and Omega . n has the sign of the face's role at every face
+  // quadrature point (>= 0 on outflow faces, <= 0 on inflow faces): with the
+  // exact quadrature of the reading, u^T A u = int sigma_t u^2 +
+  // 1/2 sum_f int_f |Omega . n| u^2 > 0, so every leading block of A is
+  // non-singular.  Straight faces always qualify; curved faces whose normal
+  // turns through Omega do not.  Set after the direction classes, which
+  // depend on the inflow bits only.
+  if (!o.nopivot) {
+    for (int k = 0; k < nd; ++k) {
+      const double ox = d.omega[2 * k], oy = d.omega[2 * k + 1];
+      uint8_t *mk = &o.mask[(size_t)k * ne];
+      for (int e = 0; e < ne; ++e) {
+        bool ok = d.sigma_t[e] > 0.0;
+        for (int f = 0; f < 4 && ok; ++f) {
+          const bool in = (mk[e] >> f) & 1u;
+          for (int q = 0; q < nq && ok; ++q) {
+            const double *g = &o.geo_f[(((size_t)e * 4 + f) * nq + q) * 2];
+            const double on = ox * g[0] + oy * g[1];
+            ok = in ? on <= 0.0 : on >= 0.0;
+          }
+        }
+        if (!ok) mk[e] |= (uint8_t)0x80;
+      }
+    }
+  }
+
   // affine maps: J and adj(F) equal at every volume point to rounding, and
   // n ds along each face equal to the face chord.  The map derivatives are
   // sums of control-point coordinates times O(1) basis derivatives, so their

@@ -228,6 +228,68 @@ __device__ __forceinline__ void st_psi(T *p, T v) {
     *p = v;
 }
 
+template <int B, int E, int S = 1, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr ((S > 0 && B < E) || (S < 0 && B > E)) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + S, E, S>(f);
+  }
+}
+
+// acc -= src[lane K of the 16-lane row] * mul, the broadcast fused into the
+// multiply-add.  The s_nop provides the two wait states a DPP read needs after
+// a VALU write of its source (the compiler does not insert them for asm).
+template <int K>
+__device__ __forceinline__ void fnma_bcast(double &acc, double src, double mul) {
+  asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(src), "v"(mul), "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void fnma_bcast(float &acc, float src, float mul) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(src), "v"(mul), "i"(K));
+}
+
+// Natural-order LU of the augmented rows [A | b] of one solve held RS rows
+// per lane of a 16-lane slot (row l + s H of set s in lane l), then the back
+// substitution: on return A[s][N] holds U x (the unknown times its pivot) and
+// idg[s] the reciprocal pivot of row l + s H, so x = A[s][N] * idg[s].  Step
+// K broadcasts pivot row K from its lane with row_newbcast fused into each
+// update; the multipliers of the mixed set (the set holding row K) are zero
+// for the rows at or above it, and its pivot and multipliers are cleared as
+// they are used, so the back substitution needs no masks.
+template <int N, int RS, int H, typename T>
+__device__ __forceinline__ void lu_rows(T (&A)[RS][N + 1], T (&idg)[RS], int r) {
+  // LU of [A | b] in natural order
+#pragma unroll
+  for (int s = 0; s < RS; ++s) idg[s] = T(0);
+  static_for<0, N>([&](auto kk) {
+    constexpr int K = decltype(kk)::value;
+    constexpr int SA = K / H, LK = K % H;
+    const T inv = slot_bcast<16, LK>(recip(A[SA][K]));
+    if (r == LK) idg[SA] = inv;
+    T l[RS];
+#pragma unroll
+    for (int s = SA; s < RS; ++s) l[s] = A[s][K] * inv;
+    l[SA] = r > LK ? l[SA] : T(0);
+    A[SA][K] = r >= LK ? T(0) : A[SA][K];
+    static_for<K + 1, N + 1>([&](auto jj) {
+      constexpr int J = decltype(jj)::value;
+      static_for<SA + 1, RS>([&](auto ss) { fnma_bcast<LK>(A[decltype(ss)::value][J], A[SA][J], l[decltype(ss)::value]); });
+      fnma_bcast<LK>(A[SA][J], A[SA][J], l[SA]);
+    });
+  });
+  // back substitution U x = y on the right-hand side column
+  static_for<N - 1, -1, -1>([&](auto ii) {
+    constexpr int I = decltype(ii)::value;
+    constexpr int SA = I / H, LI = I % H;
+    const T t = A[SA][N] * idg[SA];
+    static_for<0, SA + 1>([&](auto ss) { fnma_bcast<LI>(A[decltype(ss)::value][N], t, A[decltype(ss)::value][I]); });
+  });
+}
+
 // Step K of the pivot-free Gauss-Jordan elimination: lane K's row is the
 // pivot row; every lane subtracts l times it, where the pivot lane's own l
 // turns its row into the row divided by its pivot.
@@ -499,9 +561,25 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
     }
   }
 
-  // Gauss-Jordan elimination; lane r ends with unknown my_k in rhs
+  // elimination; lane r ends with unknown my_k in rhs
   int my_k = r;
-  if constexpr (PIVOT) {
+  if constexpr (PIVOT && SLOT == 16 && N == 16) {
+    // a solve certified for elimination in natural order (flags bit 12
+    // clear: see the plan) takes the LU with fused broadcasts, the others
+    // Gauss-Jordan with partial pivoting; the choice is per slot, and both
+    // stay inside the slot's DPP row and LDS area
+    if (!((in.flags >> 12) & 1)) {
+      T A1[1][N + 1], idg[1];
+#pragma unroll
+      for (int j = 0; j < N; ++j) A1[0][j] = A[j];
+      A1[0][N] = rhs;
+      lu_rows<N, 1, 16, T>(A1, idg, r);
+      rhs = A1[0][N] * idg[0];
+    } else {
+      bool active = row_ok;
+      gj_pivot<SLOT, N, 0, T>(A, rhs, r, active, my_k, area + S::OFF_PIV);
+    }
+  } else if constexpr (PIVOT) {
     bool active = row_ok;
     gj_pivot<SLOT, N, 0, T>(A, rhs, r, active, my_k, area + S::OFF_PIV);
   } else {
@@ -764,7 +842,10 @@ k_sweep_level(const int2 *__restrict__ solves, int n_solves, const KProb *__rest
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
   if (in.valid) {
-    in.flags = pb.mask[(size_t)d * pb.ne + in.e];
+    {
+      const unsigned mk = pb.mask[(size_t)d * pb.ne + in.e];
+      in.flags = (int)((mk & 15u) | ((mk >> 7) << 12));  // inflow faces, pivoting needed
+    }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       in.nb[f] = pb.nbr[4 * in.e + f];
@@ -839,6 +920,8 @@ k_sweep_dir(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       const int4 nb = dnb[t];
       in.e = ef.x;
       in.flags = ef.y;
+      if constexpr ((MODE & MODE_KIND) == MODE_GENERAL_PIVOT)  // this direction's pivoting bit
+        in.flags |= (int)((pb.mask[(size_t)d * pb.ne + ef.x] >> 7) << 12);
       in.nb[0] = nb.x;
       in.nb[1] = nb.y;
       in.nb[2] = nb.z;
@@ -1370,30 +1453,6 @@ struct LuLds {
   static constexpr int A_G = 0, A_S = 16, A_QD = 16 + N, AREA = ((16 + N + Q + 1) / 2) * 2;
 };
 
-template <int B, int E, int S = 1, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-  if constexpr ((S > 0 && B < E) || (S < 0 && B > E)) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + S, E, S>(f);
-  }
-}
-
-// acc -= src[lane K of the 16-lane row] * mul, the broadcast fused into the
-// multiply-add.  The s_nop provides the two wait states a DPP read needs after
-// a VALU write of its source (the compiler does not insert them for asm).
-template <int K>
-__device__ __forceinline__ void fnma_bcast(double &acc, double src, double mul) {
-  asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-      : "+v"(acc)
-      : "v"(src), "v"(mul), "i"(K));
-}
-template <int K>
-__device__ __forceinline__ void fnma_bcast(float &acc, float src, float mul) {
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-      : "+v"(acc)
-      : "v"(src), "v"(mul), "i"(K));
-}
-
 // Per-lane inputs of one solve (loaded ahead of it).
 template <int P, int NQ, typename T>
 struct SolveInL {
@@ -1488,9 +1547,11 @@ __device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d
 #pragma unroll
   for (int f = 0; f < 4; ++f) on[f] = ox * g[5 + 2 * f] + oy * g[6 + 2 * f];
 
-  // assembly of the lane's rows: A[(a,b)][(c,d)] = m_bd (stJ m_ac - gx gd_ac)
-  // - gd_bd (gy m_ac) (test index first), plus (Omega . N_f) m on outflow
-  // faces; b = J (m (x) m) s + J (w V)^T q_dir - inflow face terms
+  // assembly of the lane's rows, right-hand side first (the traces are dead
+  // before the matrix is live): b = J (m (x) m) s + J (w V)^T q_dir - the
+  // inflow face terms; A[(a,b)][(c,d)] = m_bd (stJ m_ac - gx gd_ac)
+  // - gd_bd (gy m_ac) (test index first), plus (Omega . N_f) m on the
+  // outflow faces
   T A[RS][N + 1];
 #pragma unroll
   for (int s = 0; s < RS; ++s) {
@@ -1498,25 +1559,13 @@ __device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d
     const bool row_ok = valid && r < H && row < N;
     const int rr = (r < H && row < N) ? row : N - 1;
     const int a = rr % P1, b = rr / P1;
-    T Xa[P1], Ya[P1], mb[P1], gb[P1], ma[P1];
-#pragma unroll
-    for (int c = 0; c < P1; ++c) {
-      ma[c] = m1[a * P1 + c];
-      Xa[c] = stJ * ma[c] - gx * gdt[a * P1 + c];
-      Ya[c] = gy * ma[c];
-      mb[c] = m1[b * P1 + c];
-      gb[c] = gdt[b * P1 + c];
-    }
     T rhs = T(0);
 #pragma unroll
     for (int dd = 0; dd < P1; ++dd) {
       T acc = T(0);
 #pragma unroll
-      for (int c = 0; c < P1; ++c) {
-        A[s][c + P1 * dd] = mb[dd] * Xa[c] - gb[dd] * Ya[c];
-        acc += ma[c] * area[LD::A_S + c + P1 * dd];
-      }
-      rhs += mb[dd] * acc;
+      for (int c = 0; c < P1; ++c) acc += m1[a * P1 + c] * area[LD::A_S + c + P1 * dd];
+      rhs += m1[b * P1 + dd] * acc;
     }
     rhs *= J;
     if (pio.q_dir) {
@@ -1528,56 +1577,52 @@ __device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d
     for (int f = 0; f < 4; ++f) {
       const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
       const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
-      if (!((mask >> f) & 1u)) {
-        // outflow face: a multiply by zero off the face instead of a branch
-        const T cf = on_face ? on[f] : T(0);
+      if (!(((mask >> f) & 1u) && row_ok && on_face)) continue;
+      T acc = T(0);
+      if (in.nb[f] >= 0) {
 #pragma unroll
-        for (int c = 0; c < P1; ++c) A[s][face_node<P>(f, c)] += cf * m1[pos * P1 + c];
-      } else if (row_ok && on_face) {
-        if (in.nb[f] >= 0) {
-          T acc = T(0);
+        for (int c = 0; c < P1; ++c) acc += m1[pos * P1 + c] * tr[f][c];
+      } else if (pio.psi_bc) {
+        const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
 #pragma unroll
-          for (int c = 0; c < P1; ++c) acc += m1[pos * P1 + c] * tr[f][c];
-          rhs -= on[f] * acc;
-        } else if (pio.psi_bc) {
-          const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
-          T acc = T(0);
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) acc += WL[q * P1 + pos] * static_cast<T>(bc[q]);
-          rhs -= on[f] * acc;
-        }
+        for (int q = 0; q < NQ; ++q) acc += WL[q * P1 + pos] * static_cast<T>(bc[q]);
       }
+      rhs -= on[f] * acc;
     }
     A[s][N] = rhs;
   }
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int row = r + s * H;
+    const int rr = (r < H && row < N) ? row : N - 1;
+    const int a = rr % P1, b = rr / P1;
+    T Xa[P1], Ya[P1], mb[P1], gb[P1];
+#pragma unroll
+    for (int c = 0; c < P1; ++c) {
+      const T mac = m1[a * P1 + c];
+      Xa[c] = stJ * mac - gx * gdt[a * P1 + c];
+      Ya[c] = gy * mac;
+      mb[c] = m1[b * P1 + c];
+      gb[c] = gdt[b * P1 + c];
+    }
+#pragma unroll
+    for (int dd = 0; dd < P1; ++dd)
+#pragma unroll
+      for (int c = 0; c < P1; ++c) A[s][c + P1 * dd] = mb[dd] * Xa[c] - gb[dd] * Ya[c];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      if ((mask >> f) & 1u) continue;
+      // outflow face: a multiply by zero off the face instead of a branch
+      const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+      const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+      const T cf = on_face ? on[f] : T(0);
+#pragma unroll
+      for (int c = 0; c < P1; ++c) A[s][face_node<P>(f, c)] += cf * m1[pos * P1 + c];
+    }
+  }
 
-  // LU of [A | b] in natural order
   T idg[RS];
-#pragma unroll
-  for (int s = 0; s < RS; ++s) idg[s] = T(0);
-  static_for<0, N>([&](auto kk) {
-    constexpr int K = decltype(kk)::value;
-    constexpr int SA = K / H, LK = K % H;
-    const T inv = slot_bcast<16, LK>(recip(A[SA][K]));
-    if (r == LK) idg[SA] = inv;
-    T l[RS];
-#pragma unroll
-    for (int s = SA; s < RS; ++s) l[s] = A[s][K] * inv;
-    l[SA] = r > LK ? l[SA] : T(0);
-    A[SA][K] = r >= LK ? T(0) : A[SA][K];
-    static_for<K + 1, N + 1>([&](auto jj) {
-      constexpr int J = decltype(jj)::value;
-      static_for<SA + 1, RS>([&](auto ss) { fnma_bcast<LK>(A[decltype(ss)::value][J], A[SA][J], l[decltype(ss)::value]); });
-      fnma_bcast<LK>(A[SA][J], A[SA][J], l[SA]);
-    });
-  });
-  // back substitution U x = y on the right-hand side column
-  static_for<N - 1, -1, -1>([&](auto ii) {
-    constexpr int I = decltype(ii)::value;
-    constexpr int SA = I / H, LI = I % H;
-    const T t = A[SA][N] * idg[SA];
-    static_for<0, SA + 1>([&](auto ss) { fnma_bcast<LI>(A[decltype(ss)::value][N], t, A[decltype(ss)::value][I]); });
-  });
+  lu_rows<N, RS, H, T>(A, idg, r);
   T x[RS];
 #pragma unroll
   for (int s = 0; s < RS; ++s) x[s] = A[s][N] * idg[s];
@@ -1694,7 +1739,10 @@ k_sweep_level_lu(const int2 *__restrict__ solves, int n_solves, const KProb *__r
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
   if (in.valid) {
-    in.flags = pb.mask[(size_t)d * pb.ne + in.e];
+    {
+      const unsigned mk = pb.mask[(size_t)d * pb.ne + in.e];
+      in.flags = (int)((mk & 15u) | ((mk >> 7) << 12));  // inflow faces, pivoting needed
+    }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       in.nb[f] = pb.nbr[4 * in.e + f];
@@ -1843,6 +1891,9 @@ struct FlowPolicy;
 template <int P, int NQ, typename T, int MODE>
 struct FlowPolicy<P, NQ, T, MODE, true> {
   static constexpr int SLOT = 16, SPW = 4;
+  // the double-precision rows leave no registers for the next round's inputs
+  // (with them the kernel spills; measured slower on the 512x512 p = 4 sweep)
+  static constexpr bool kPrefetch = sizeof(T) == 4;
   static constexpr int TAB = LuLds<P, NQ>::TAB, AREA = LuLds<P, NQ>::AREA;
   using In = SolveInL<P, NQ, T>;
   static __device__ __forceinline__ void stage(const T *tables, T *lds) { stage_tables_lu<P, NQ, T>(tables, lds); }
@@ -1856,6 +1907,7 @@ struct FlowPolicy<P, NQ, T, MODE, true> {
 template <int P, int NQ, typename T, int MODE>
 struct FlowPolicy<P, NQ, T, MODE, false> {
   static constexpr int SLOT = Shape<P, NQ>::SLOT, SPW = Shape<P, NQ>::SPW;
+  static constexpr bool kPrefetch = true;
   static constexpr int TAB = Lds<P, NQ, MODE>::TAB, AREA = Lds<P, NQ, MODE>::AREA;
   using In = InputsOf<P, NQ, T, MODE>;
   static __device__ __forceinline__ void stage(const T *tables, T *lds) { stage_tables<P, NQ, T, MODE>(tables, lds); }
@@ -1874,7 +1926,7 @@ struct FlowItem {
 };
 
 template <int P, int NQ, typename T, int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, int n_tasks,
              const int *__restrict__ pred_ptr, const int *__restrict__ pred_idx, int *__restrict__ flags,
              int own_base, int *__restrict__ abort_flag, const KProb *__restrict__ probs,
@@ -1913,7 +1965,10 @@ k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, in
     }
     const KProb &pb = probs[x.prob];
     if (x.in.valid) {
-      x.in.flags = pb.mask[(size_t)x.d * pb.ne + x.in.e];
+      {
+        const unsigned mk = pb.mask[(size_t)x.d * pb.ne + x.in.e];
+        x.in.flags = (int)((mk & 15u) | ((mk >> 7) << 12));  // inflow faces, pivoting needed
+      }
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         x.in.nb[f] = pb.nbr[4 * x.in.e + f];
@@ -1926,8 +1981,9 @@ k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, in
   int t = w, rd = 0;
   int2 tk = tasks[t];  // (first solve, solves)
   Item cur, nxt;
-  fetch(cur, tk, 0);
+  if constexpr (Pol::kPrefetch) fetch(cur, tk, 0);
   for (;;) {
+    if constexpr (!Pol::kPrefetch) fetch(cur, tk, rd);
     int t2 = t, rd2 = rd + 1;
     int2 tk2 = tk;
     if (rd2 * Pol::SPW >= tk.y) {
@@ -1936,7 +1992,8 @@ k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, in
       if (t2 < n_tasks) tk2 = tasks[t2];
     }
     const bool more = t2 < n_tasks;
-    if (more) fetch(nxt, tk2, rd2);
+    if constexpr (Pol::kPrefetch)
+      if (more) fetch(nxt, tk2, rd2);
     if (rd == 0) {
       // the tasks holding this task's upwind fluxes are done in this sweep
       const int q1 = pred_ptr[t + 1];
@@ -1965,7 +2022,7 @@ k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, in
       if (lane == 0) __hip_atomic_store(flags + own_base + t, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (!more) break;
-    cur = nxt;
+    if constexpr (Pol::kPrefetch) cur = nxt;
     t = t2;
     rd = rd2;
     tk = tk2;

@@ -76,9 +76,7 @@ def test_c2_full_source_iteration(torch, precision):
     (r,) = run(torch, probs, precision, n_iter=runcfg["n_iter"])
     resid = np.asarray(g["resid"])
     assert np.abs(r["resid"] - resid).max() <= TOL[precision] * resid.max()
-    # float local solves: the error of each sweep is amplified by source
-    # iteration up to 1/(1 - c) = 10 for c = 0.9
-    check_moments(r["mom"], g, TOL[precision] * (10 if precision == "fp32" else 1))
+    check_moments(r["mom"], g, TOL[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -129,52 +127,80 @@ def test_c4_batched_equals_single(torch, precision):
         assert np.array_equal(batch[k]["resid"], alone["resid"])
 
 
-def _si_history(torch, probs, precision, n_iter, closures=False):
+def _check_si_fixture(name, r, precision):
+    """Scalar flux after each source iteration and the residual history
+    against the oracle's (tests/golden), relative to max|phi| of the last
+    iteration; both precisions at their bars."""
+    g = gold(name)
+    idx = np.asarray(g["index"])
+    scale = g["phi_absmax"]
+    for k, phi in enumerate(r["phi_hist"]):
+        err = np.abs(phi.reshape(-1)[idx] - np.asarray(g["phi"][k])).max() / scale
+        print(name, precision, "iteration", k + 1, "rel_inf(phi - oracle) = %.3g" % err, flush=True)
+        assert err <= TOL[precision], (k, err)
+    # a residual is a difference of scalar-flux iterates: its error is
+    # bounded by theirs, so it is measured against max|phi| too
+    resid = np.asarray(g["resid"])
+    assert np.abs(r["resid"] - resid).max() <= 2 * TOL[precision] * scale
+
+
+def _si_phi_history(torch, probs, precision, n_iter, closures=False):
+    """Source iterations one sweep at a time (phi of each kept), as the
+    oracle fixtures were made."""
     from paper_2301_04758_amd import vef
     print("SI history", probs[0].name, precision, n_iter, flush=True)
     sw = vef.Sweep(probs, precision=precision)
-    io = sw.buffers(n_iter=n_iter, store_psi=False)
-    sw.run(io, n_iter=n_iter)
-    out = {}
+    io = sw.buffers(n_iter=1, store_psi=False)
+    phi_hist, resid = [], []
+    for k in range(n_iter):
+        if k > 0:
+            io[0]["phi_in"] = io[0]["mom"][0].clone()
+        sw.run(io, n_iter=1)
+        torch.cuda.synchronize()
+        sw.check()
+        phi_hist.append(io[0]["mom"][0].cpu().numpy())
+        resid.append(float(io[0]["resid"][0].item()))
+    out = dict(phi_hist=phi_hist, resid=np.asarray(resid), n_levels=sw.info[0]["n_levels"])
     if closures:
         mio = sw.moment_buffers(io)
         sw.moments(mio)
-        out["n_nonpos"] = mio[0]
-    torch.cuda.synchronize()
-    sw.check()
-    out.update(phi=io[0]["mom"][0].cpu().numpy(), resid=io[0]["resid"].cpu().numpy(), n_levels=sw.info[0]["n_levels"])
-    if closures:
-        out["n_nonpos"] = int(out["n_nonpos"]["n_nonpos"].item())
+        torch.cuda.synchronize()
+        out["n_nonpos"] = int(mio[0]["n_nonpos"].item())
     sw.close()
     del io
     torch.cuda.empty_cache()
     return out
 
 
-def test_c3_fp32_vs_fp64_ten_source_iterations(torch):
-    """C3 accuracy run: 10 source iterations with float local solves against
-    the double path (itself pinned to the oracle on the first sweep): phi and
-    every residual within 1e-5 (the sweep error is amplified by at most
-    1/(1 - c) = 2 for c = 0.5)."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c3_ten_source_iterations_against_oracle(torch, precision):
+    """C3 accuracy run: 10 source iterations, FP64 and FP32-local, the scalar
+    flux after every iteration and the residual history against the oracle's
+    (the float sweep error is amplified by at most 1/(1 - c) = 2 for c = 0.5)."""
     probs, _ = P.make_config("c3")
-    a = _si_history(torch, probs, "fp64", 10)
-    b = _si_history(torch, probs, "fp32", 10)
-    assert a["n_levels"] >= 2 * 256 - 1  # per-direction upwind depth of the 256 x 256 mesh
-    assert np.abs(b["phi"] - a["phi"]).max() <= 1e-5 * np.abs(a["phi"]).max()
-    assert np.abs(b["resid"] - a["resid"]).max() <= 1e-5 * a["resid"].max()
+    r = _si_phi_history(torch, probs, precision, 10)
+    assert r["n_levels"] >= 2 * 256 - 1  # per-direction upwind depth of the 256 x 256 mesh
+    _check_si_fixture("c3_si10.json", r, precision)
 
 
-def test_c5_fp32_vs_fp64_per_iteration(torch):
-    """C5 (c = 0.9999): after each of 5 source iterations, float local solves
-    against the double path within 1e-5 on phi; residual history and the
-    count of non-positive points reported by the closures."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_five_source_iterations_against_oracle(torch, precision):
+    """C5 (c = 0.9999): after each of 5 source iterations, FP64 and FP32
+    local solves against the oracle's scalar flux (amplification at most 5);
+    the residual history; the count of non-positive points from the
+    closures."""
     probs, _ = P.make_config("c5")
-    for k in range(1, 6):
-        a = _si_history(torch, probs, "fp64", k, closures=(k == 5))
-        b = _si_history(torch, probs, "fp32", k, closures=(k == 5))
-        err = np.abs(b["phi"] - a["phi"]).max() / np.abs(a["phi"]).max()
-        print("C5 iteration", k, "rel_inf(phi fp32 - fp64) = %.3g" % err, "resid", a["resid"][-1], flush=True)
-        assert err <= 1e-5, (k, err)
-    assert np.abs(b["resid"] - a["resid"]).max() <= 1e-5 * a["resid"].max()
-    print("C5 n_nonpos fp64", a["n_nonpos"], "fp32", b["n_nonpos"], flush=True)
-    assert a["n_nonpos"] >= 0 and b["n_nonpos"] >= 0
+    r = _si_phi_history(torch, probs, precision, 5, closures=True)
+    _check_si_fixture("c5_si5.json", r, precision)
+    print("C5 n_nonpos", precision, r["n_nonpos"], flush=True)
+    assert r["n_nonpos"] >= 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_full_sweep_moments_against_oracle(torch, precision):
+    """C5, one sweep of all 144 directions: the six moments at sampled nodes
+    against the oracle's (tests/golden/c5_full.json)."""
+    g = gold("c5_full.json")
+    probs, _ = P.make_config("c5")
+    (r,) = run(torch, probs, precision)
+    check_moments(r["mom"], g, TOL[precision])

@@ -38,6 +38,11 @@ def _tg(n, m, p, N=4, st=2.0, c=0.0):
 
 
 def _tol(pr, precision):
+    """The stated bar against the oracle (1e-5) for FP32-local; for FP64 the
+    bar or 4 eps kappa_max of the local blocks, whichever is larger (two
+    backward-stable double solves differ by a few eps kappa)."""
+    if precision == "fp32":
+        return BAR[precision]
     k = 0.0
     n = (pr.p + 1) ** 2
     for d in range(pr.n_dir):

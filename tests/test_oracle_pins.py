@@ -397,3 +397,18 @@ def test_fixup_positive_and_element_balance(p, m, warp):
         assert rel <= 1e-12, (d, rel)
     # moments are those of the fixed angular flux
     assert np.allclose(O.moments_from_psi(pr, fx["psi"]), fx["mom"], rtol=0, atol=1e-13 * np.abs(fx["mom"]).max())
+
+
+def test_threaded_oracle_sweep_is_bitwise_serial():
+    """Directions swept on several OpenMP threads and summed in direction
+    order afterwards: the same bits as the serial sweep (moments, angular
+    flux, boundary sums, levels) and the same source-iteration history."""
+    from paper_2301_04758_amd import problems as P
+    (pr,), _ = P.make_config("c3", scale=6)
+    a = O.sweep(pr)
+    b = O.sweep(pr, threads=5)
+    for k in ("psi", "mom", "bnd", "levels"):
+        assert np.array_equal(a[k], b[k]), k
+    r1 = O.source_iteration(pr, 3)
+    r2 = O.source_iteration(pr, 3, threads=3)
+    assert np.array_equal(r1["mom"], r2["mom"]) and np.array_equal(r1["resid"], r2["resid"])
