@@ -754,6 +754,8 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
     SL.ring = h->pipeline_ring;
     SL.fixup = h->fixup;
     SL.wait_spins = h->wait_polls;
+    SL.n_cu = h->n_cu;
+    SL.single = h->h_probs.size() == 1;
     if (persistent) {
       for (auto &F : h->flow) {
         SL.p = F.v.p;

@@ -73,7 +73,8 @@ struct SweepLaunch {
   int *flags;            // persistent: per task of the handle, sweep number when done (zeroed by each run)
   int own_base;          // persistent: flag index of this variant's first task
   int *abort_flag;       // persistent: set when a wait expires (zeroed by each run)
-  int n_cu;              // persistent: compute units of the device
+  int n_cu;              // persistent and streaming level launches: compute units of the device
+  bool single;           // the handle holds one problem (streaming level kernels)
   const KProb *probs;
   const KIO *io;
   const void *tables;

@@ -125,6 +125,15 @@ __device__ __forceinline__ int face_node(int f, int c) {
   }
 }
 
+// face_node without branches (selects), for a runtime face
+template <int P>
+__device__ __forceinline__ int face_node_sel(int f, int c) {
+  constexpr int P1 = P + 1;
+  const int base = f == 0 ? 0 : f == 1 ? P : f == 2 ? P + P1 * P : P1 * P;
+  const int step = f == 0 ? 1 : f == 1 ? P1 : f == 2 ? -1 : -P1;
+  return base + step * c;
+}
+
 // DPP lane moves (whole-wave, all lanes active)
 template <int CTRL>
 __device__ __forceinline__ int dpp_mov(int v) {
@@ -213,19 +222,32 @@ __device__ __forceinline__ void wave_sync_lds() {
 // (COH: the persistent schedule) are agent-scope atomic loads and stores:
 // each goes to the device's coherence point by itself, so no cache-wide
 // fence is needed around them.
+// Loads and stores through global-address-space pointers.  A pointer taken
+// from a descriptor in memory is generic, and a generic (flat) access counts
+// against the LDS counter as well, so a wait for an LDS read would also wait
+// for it; the streaming kernels keep loads in flight across LDS work.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p) {
+  return *gmem(p);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, T v) {
+  *gmem(p) = v;
+}
+
 template <bool COH, typename T>
 __device__ __forceinline__ T ld_psi(const T *p) {
   if constexpr (COH)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   else
-    return *p;
+    return gload(p);
 }
 template <bool COH, typename T>
 __device__ __forceinline__ void st_psi(T *p, T v) {
   if constexpr (COH)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   else
-    *p = v;
+    gstore(p, v);
 }
 
 template <int B, int E, int S = 1, typename F>
@@ -252,6 +274,52 @@ __device__ __forceinline__ void fnma_bcast(float &acc, float src, float mul) {
       : "v"(src), "v"(mul), "i"(K));
 }
 
+// Blocks of the same update over several columns J in one asm statement:
+// within a block no instruction reads a register written by the one before
+// it (each column's updates write different registers from those the next
+// column's read), so a single s_nop at the start covers the whole block.
+// fnma_bcast_2x4: columns j = 0..3, hi[j] -= bcast(lo[j]) * lh, then
+// lo[j] -= bcast(lo[j]) * ll (the pivot set's rows last).
+#define VEF_FMAC_DPP(OP, ACC, SRC, MUL) \
+  OP " " ACC ", " SRC ", -" MUL " row_newbcast:%[k] row_mask:0xf bank_mask:0xf\n\t"
+#define VEF_BCAST_2X4(OP)                                                                                    \
+  "s_nop 1\n\t" VEF_FMAC_DPP(OP, "%[h0]", "%[o0]", "%[lh]") VEF_FMAC_DPP(OP, "%[o0]", "%[o0]", "%[ll]")  \
+      VEF_FMAC_DPP(OP, "%[h1]", "%[o1]", "%[lh]") VEF_FMAC_DPP(OP, "%[o1]", "%[o1]", "%[ll]")              \
+          VEF_FMAC_DPP(OP, "%[h2]", "%[o2]", "%[lh]") VEF_FMAC_DPP(OP, "%[o2]", "%[o2]", "%[ll]")          \
+              VEF_FMAC_DPP(OP, "%[h3]", "%[o3]", "%[lh]") VEF_FMAC_DPP(OP, "%[o3]", "%[o3]", "%[ll]")
+#define VEF_BCAST_1X8(OP)                                                                                    \
+  "s_nop 1\n\t" VEF_FMAC_DPP(OP, "%[o0]", "%[o0]", "%[ll]") VEF_FMAC_DPP(OP, "%[o1]", "%[o1]", "%[ll]")  \
+      VEF_FMAC_DPP(OP, "%[o2]", "%[o2]", "%[ll]") VEF_FMAC_DPP(OP, "%[o3]", "%[o3]", "%[ll]")              \
+          VEF_FMAC_DPP(OP, "%[o4]", "%[o4]", "%[ll]") VEF_FMAC_DPP(OP, "%[o5]", "%[o5]", "%[ll]")          \
+              VEF_FMAC_DPP(OP, "%[o6]", "%[o6]", "%[ll]") VEF_FMAC_DPP(OP, "%[o7]", "%[o7]", "%[ll]")
+
+template <int K, typename T>
+__device__ __forceinline__ void fnma_bcast_2x4(T &o0, T &o1, T &o2, T &o3, T &h0, T &h1, T &h2, T &h3, T ll, T lh) {
+  if constexpr (sizeof(T) == 8)
+    asm(VEF_BCAST_2X4("v_fmac_f64_dpp")
+        : [o0] "+v"(o0), [o1] "+v"(o1), [o2] "+v"(o2), [o3] "+v"(o3), [h0] "+v"(h0), [h1] "+v"(h1), [h2] "+v"(h2),
+          [h3] "+v"(h3)
+        : [ll] "v"(ll), [lh] "v"(lh), [k] "i"(K));
+  else
+    asm(VEF_BCAST_2X4("v_fmac_f32_dpp")
+        : [o0] "+v"(o0), [o1] "+v"(o1), [o2] "+v"(o2), [o3] "+v"(o3), [h0] "+v"(h0), [h1] "+v"(h1), [h2] "+v"(h2),
+          [h3] "+v"(h3)
+        : [ll] "v"(ll), [lh] "v"(lh), [k] "i"(K));
+}
+template <int K, typename T>
+__device__ __forceinline__ void fnma_bcast_1x8(T &o0, T &o1, T &o2, T &o3, T &o4, T &o5, T &o6, T &o7, T ll) {
+  if constexpr (sizeof(T) == 8)
+    asm(VEF_BCAST_1X8("v_fmac_f64_dpp")
+        : [o0] "+v"(o0), [o1] "+v"(o1), [o2] "+v"(o2), [o3] "+v"(o3), [o4] "+v"(o4), [o5] "+v"(o5), [o6] "+v"(o6),
+          [o7] "+v"(o7)
+        : [ll] "v"(ll), [k] "i"(K));
+  else
+    asm(VEF_BCAST_1X8("v_fmac_f32_dpp")
+        : [o0] "+v"(o0), [o1] "+v"(o1), [o2] "+v"(o2), [o3] "+v"(o3), [o4] "+v"(o4), [o5] "+v"(o5), [o6] "+v"(o6),
+          [o7] "+v"(o7)
+        : [ll] "v"(ll), [k] "i"(K));
+}
+
 // Natural-order LU of the augmented rows [A | b] of one solve held RS rows
 // per lane of a 16-lane slot (row l + s H of set s in lane l), then the back
 // substitution: on return A[s][N] holds U x (the unknown times its pivot) and
@@ -275,7 +343,23 @@ __device__ __forceinline__ void lu_rows(T (&A)[RS][N + 1], T (&idg)[RS], int r) 
     for (int s = SA; s < RS; ++s) l[s] = A[s][K] * inv;
     l[SA] = r > LK ? l[SA] : T(0);
     A[SA][K] = r >= LK ? T(0) : A[SA][K];
-    static_for<K + 1, N + 1>([&](auto jj) {
+    // the trailing columns K + 1 .. N: blocks of columns, then one at a time
+    constexpr int NB = RS - SA == 2 ? 4 : RS - SA == 1 ? 8 : 1;  // columns per block
+    constexpr int JB = NB > 1 ? K + 1 + ((N - K) / NB) * NB : K + 1;  // first column after the blocks
+    if constexpr (NB == 4) {
+      static_for<K + 1, JB, 4>([&](auto jj) {
+        constexpr int J = decltype(jj)::value;
+        fnma_bcast_2x4<LK>(A[SA][J], A[SA][J + 1], A[SA][J + 2], A[SA][J + 3], A[SA + 1][J], A[SA + 1][J + 1],
+                           A[SA + 1][J + 2], A[SA + 1][J + 3], l[SA], l[SA + 1]);
+      });
+    } else if constexpr (NB == 8) {
+      static_for<K + 1, JB, 8>([&](auto jj) {
+        constexpr int J = decltype(jj)::value;
+        fnma_bcast_1x8<LK>(A[SA][J], A[SA][J + 1], A[SA][J + 2], A[SA][J + 3], A[SA][J + 4], A[SA][J + 5],
+                           A[SA][J + 6], A[SA][J + 7], l[SA]);
+      });
+    }
+    static_for<JB, N + 1>([&](auto jj) {
       constexpr int J = decltype(jj)::value;
       static_for<SA + 1, RS>([&](auto ss) { fnma_bcast<LK>(A[decltype(ss)::value][J], A[SA][J], l[decltype(ss)::value]); });
       fnma_bcast<LK>(A[SA][J], A[SA][J], l[SA]);
@@ -1449,8 +1533,11 @@ struct LuLds {
   // tables: 1D mass m [P1][P1], 1D derivative table gd [P1][P1], boundary
   // table w_q l_a(s_q) [NQ][P1]
   static constexpr int T_M = 0, T_GD = P1 * P1, T_WL = 2 * P1 * P1, TAB = 2 * P1 * P1 + NQ * P1;
-  // per slot: geometry [16] (J, adj(F), face chords), nodal source [N], q_dir [Q]
-  static constexpr int A_G = 0, A_S = 16, A_QD = 16 + N, AREA = ((16 + N + Q + 1) / 2) * 2;
+  // per slot: geometry [16] (J, adj(F), face chords), nodal source [N], q_dir [Q],
+  // upwind traces or boundary data of the four faces [4][TW] (streaming kernel)
+  static constexpr int TW = P1 > NQ ? P1 : NQ;
+  static constexpr int A_G = 0, A_S = 16, A_QD = 16 + N, A_TR = 16 + N + Q, A_SC = A_TR + 4 * TW;
+  static constexpr int AREA = ((A_SC + 3 + 1) / 2) * 2;  // A_SC: sigma_t, Omega_x, Omega_y
 };
 
 // Per-lane inputs of one solve (loaded ahead of it).
@@ -1468,6 +1555,7 @@ struct SolveInL {
 template <int P, int NQ, typename T>
 __device__ __forceinline__ void load_one(SolveInL<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio, int it,
                                          int r) {
+#pragma clang fp contract(off)  // the same rounding as the streaming kernel's staging
   constexpr int N = LuShape<P>::N, Q = NQ * NQ;
   const int e = in.e;
   if (!in.valid) return;
@@ -1491,12 +1579,18 @@ __device__ __forceinline__ void load_one(SolveInL<P, NQ, T> &in, int d, const KP
   }
 }
 
-// Assemble and solve one element-direction system (all 16 lanes of the slot
-// call it).  tab: the LDS tables (LuLds), wv: w V [Q][n] in global memory
-// (direction-dependent source only), area: the slot's LDS area.
-template <int P, int NQ, typename T, bool FIX, bool COH = false>
-__device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio,
-                                             const T *tab, const T *wv, T *area, int r, int *status) {
+// Assemble and solve one element-direction system from the slot's staged
+// geometry and sources (all 16 lanes of the slot call it).  tab: the LDS
+// tables (LuLds), wv: w V [Q][n] in global memory (direction-dependent source
+// only), area: the slot's LDS area.  The upwind traces of the inflow faces
+// (face node c of face f, in the face order of the downwind element) are
+// read from the angular flux here (SRC_LDS false; boundary data then from
+// pio.psi_bc) or come from the area's trace buffer, which also holds the
+// inflow data of boundary faces (SRC_LDS true).
+template <int P, int NQ, typename T, bool FIX, bool COH, bool SRC_LDS>
+__device__ __forceinline__ void lu_core(int e, int d, bool valid, int flags, const int (&nb)[4], T ox, T oy, T st,
+                                        const KProb &pb, const KIO &pio, const T *tab, const T *wv, T *area, int r,
+                                        int *status) {
   using S = LuShape<P>;
   using LD = LuLds<P, NQ>;
   constexpr int P1 = S::P1, N = S::N, RS = S::RS, H = S::H, Q = NQ * NQ;
@@ -1504,40 +1598,23 @@ __device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d
   const T *gdt = tab + LD::T_GD;
   const T *WL = tab + LD::T_WL;
   const int ne = pb.ne;
-  const int e = in.e;
-  const bool valid = in.valid;
-  const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
-
-  // staging (wave-local)
-  area[LD::A_G + r] = in.g;
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-    if (r + 16 * k < N) area[LD::A_S + r + 16 * k] = in.s[k];
-  if (pio.q_dir) {
-#pragma unroll
-    for (int k = 0; k < SolveInL<P, NQ, T>::QD; ++k)
-      if (r + 16 * k < Q) area[LD::A_QD + r + 16 * k] = in.qd[k];
-  }
-  wave_sync_lds();
-
-  // upwind traces of the inflow faces (every lane reads them all)
-  const T *psi = static_cast<const T *>(pio.psi);
+  const unsigned mask = valid ? (unsigned)flags & 15u : 0u;
   T tr[4][P1];
+  if constexpr (!SRC_LDS) {
+    // every lane reads them all
+    const T *psi = static_cast<const T *>(pio.psi);
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 4; ++f) {
 #pragma unroll
-    for (int c = 0; c < P1; ++c) tr[f][c] = T(0);
-    if (valid && ((mask >> f) & 1u) && in.nb[f] >= 0) {
-      const int f2 = (in.flags >> (4 + 2 * f)) & 3;
-      const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
+      for (int c = 0; c < P1; ++c) tr[f][c] = T(0);
+      if (valid && ((mask >> f) & 1u) && nb[f] >= 0) {
+        const int f2 = (flags >> (4 + 2 * f)) & 3;
+        const T *up = psi + ((size_t)d * ne + nb[f]) * N;
 #pragma unroll
-      for (int c = 0; c < P1; ++c) tr[f][c] = ld_psi<COH>(up + face_node<P>(f2, P - c));
+        for (int c = 0; c < P1; ++c) tr[f][c] = ld_psi<COH>(up + face_node<P>(f2, P - c));
+      }
     }
   }
-
-  const T ox = static_cast<T>(pb.omega[2 * d]);
-  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
-  const T st = static_cast<T>(pb.sig[2 * (valid ? e : 0)]);
   const T *g = area + LD::A_G;
   const T J = g[0];
   const T stJ = st * J;
@@ -1579,13 +1656,24 @@ __device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d
       const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
       if (!(((mask >> f) & 1u) && row_ok && on_face)) continue;
       T acc = T(0);
-      if (in.nb[f] >= 0) {
+      const T *trl = area + LD::A_TR + f * LD::TW;
+      if (nb[f] >= 0) {
 #pragma unroll
-        for (int c = 0; c < P1; ++c) acc += m1[pos * P1 + c] * tr[f][c];
+        for (int c = 0; c < P1; ++c) {
+          if constexpr (SRC_LDS)
+            acc += m1[pos * P1 + c] * trl[c];
+          else
+            acc += m1[pos * P1 + c] * tr[f][c];
+        }
       } else if (pio.psi_bc) {
-        const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
+        const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-nb[f] - 1)) * NQ;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc += WL[q * P1 + pos] * static_cast<T>(bc[q]);
+        for (int q = 0; q < NQ; ++q) {
+          if constexpr (SRC_LDS)
+            acc += WL[q * P1 + pos] * trl[q];
+          else
+            acc += WL[q * P1 + pos] * static_cast<T>(bc[q]);
+        }
       }
       rhs -= on[f] * acc;
     }
@@ -1690,6 +1778,35 @@ __device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d
   }
 }
 
+// One solve from its loaded inputs: stage them in the slot's LDS area, read
+// the upwind traces (every lane reads them all), assemble and solve.
+template <int P, int NQ, typename T, bool FIX, bool COH = false>
+__device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio,
+                                             const T *tab, const T *wv, T *area, int r, int *status) {
+  using LD = LuLds<P, NQ>;
+  constexpr int P1 = P + 1, N = P1 * P1, Q = NQ * NQ;
+  const int ne = pb.ne;
+  const int e = in.e;
+  const bool valid = in.valid;
+  const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
+
+  // staging (wave-local)
+  area[LD::A_G + r] = in.g;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (r + 16 * k < N) area[LD::A_S + r + 16 * k] = in.s[k];
+  if (pio.q_dir) {
+#pragma unroll
+    for (int k = 0; k < SolveInL<P, NQ, T>::QD; ++k)
+      if (r + 16 * k < Q) area[LD::A_QD + r + 16 * k] = in.qd[k];
+  }
+  wave_sync_lds();
+  const T ox = static_cast<T>(pb.omega[2 * d]);
+  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
+  const T st = static_cast<T>(pb.sig[2 * (valid ? e : 0)]);
+  lu_core<P, NQ, T, FIX, COH, false>(e, d, valid, in.flags, in.nb, ox, oy, st, pb, pio, tab, wv, area, r, status);
+}
+
 // Stage the LU tables (m, gd, w l) from the affine table blob into LDS.
 template <int P, int NQ, typename T>
 __device__ __forceinline__ void stage_tables_lu(const T *__restrict__ tables, T *lds) {
@@ -1755,6 +1872,203 @@ k_sweep_level_lu(const int2 *__restrict__ solves, int n_solves, const KProb *__r
   load_one<P, NQ, T>(in, d, pb, pio, it, r);
   solve_one_lu<P, NQ, T, FIX>(in, d, pb, pio, lds, tables + Shape<P, NQ>::A_WV, lds + LD::TAB + (size_t)slot * LD::AREA,
                               r, status);
+}
+
+// Level-synchronous schedule, streaming form (handles of one problem): a
+// launch of at most the resident work-groups, each slot taking the level's
+// solves sid, sid + S, ... (S slots in the grid, at most 16 solves a slot).
+// The 16 lanes of a slot load the descriptors of the slot's solves at the
+// start (lane k those of its k-th solve); the inputs of the next solve,
+// upwind traces included (written by earlier launches), are loaded while the
+// current one is factored, so the chain of dependent loads is paid once per
+// launch and not once per solve.
+template <int P, int NQ, typename T>
+struct LuPre {
+  static constexpr int TW = LuLds<P, NQ>::TW, NT = (4 * TW + 15) / 16;
+  // raw loaded values: every lane issues the same loads on every solve (an
+  // unused one reads a valid dummy address), and nothing is computed from a
+  // load until the solve is staged, so that no wait for them comes before the
+  // current solve's work
+  T g, sc;               // sc: sigma_t (lane 0), Omega_x (lane 1), Omega_y (lane 2)
+  T tr[NT];              // upwind trace values
+  double bc[sizeof(T) == sizeof(double) ? 1 : NT];  // boundary inflow data (double precision: in tr)
+  double phi[2], qi[2];  // scalar flux and isotropic source at nodes r, r + 16
+  double ss;             // sigma_s
+  int use;               // bit k: tr[k] used, bit 8 + k: bc[k] used, bit 16: phi present
+};
+
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void lu_prefetch(LuPre<P, NQ, T> &x, int e, int d, int flags, const int (&nb)[4],
+                                            bool valid, const KProb &pb, const KIO &pio, int it, int r) {
+  using X = LuPre<P, NQ, T>;
+  constexpr int P1 = P + 1, N = P1 * P1, TW = X::TW;
+  constexpr bool kWide = sizeof(T) == sizeof(double);  // boundary data and traces share one load
+  if (!valid) {
+    e = 0;
+    d = 0;
+    flags = 0;
+  }
+  const double *dummy = pb.sig;
+  x.g = gload(static_cast<const T *>(pb.geo_a) + (size_t)e * 16 + r);
+  x.sc = static_cast<T>(gload(r == 0 ? pb.sig + 2 * e : pb.omega + 2 * d + (r == 2 ? 1 : 0)));
+  x.ss = gload(pb.sig + 2 * e + 1);
+  const double *phi = it == 0 ? pio.phi_in : pio.mom;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int node = r + 16 * k < N ? r + 16 * k : 0;
+    x.phi[k] = gload(phi ? phi + (size_t)e * N + node : dummy);
+    x.qi[k] = gload(pio.q_iso ? pio.q_iso + (size_t)e * N + node : dummy);
+  }
+  // trace entry i = f TW + c: upwind value at face node c, or inflow data at
+  // quadrature point c of a boundary face
+  const T *psi = static_cast<const T *>(pio.psi);
+  int use = 0;
+#pragma unroll
+  for (int k = 0; k < X::NT; ++k) {
+    const int i = r + 16 * k;
+    const int f = (i < 4 * TW ? i : 0) / TW, c = (i < 4 * TW ? i : 0) - f * TW;
+    const int u = f == 0 ? nb[0] : f == 1 ? nb[1] : f == 2 ? nb[2] : nb[3];
+    const bool inflow = i < 4 * TW && ((flags >> f) & 1);
+    const bool up = inflow && u >= 0 && c < P1;
+    const bool bnd = inflow && u < 0 && pio.psi_bc && c < NQ;
+    const int f2 = (flags >> (4 + 2 * f)) & 3;
+    const T *pa = up ? psi + ((size_t)d * pb.ne + u) * N + face_node_sel<P>(f2, P - c) : static_cast<const T *>(pb.geo_a);
+    const double *pbnd = bnd ? pio.psi_bc + ((size_t)d * pb.nbf + (-u - 1)) * NQ + c : dummy;
+    if constexpr (kWide) {
+      x.tr[k] = gload(bnd ? reinterpret_cast<const T *>(pbnd) : pa);
+    } else {
+      x.tr[k] = gload(pa);
+      x.bc[k] = gload(pbnd);
+    }
+    use |= (up || (kWide && bnd) ? 1 : 0) << k;
+    use |= (bnd ? 1 : 0) << (8 + k);
+  }
+  use |= (phi ? 1 : 0) << 16;
+  x.use = valid ? use : 0;
+}
+
+// Stage a prefetched solve in the slot's area; the direction-dependent
+// source q_dir (not prefetched) is read here.
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void lu_stage(const LuPre<P, NQ, T> &x, T *area, const KProb &pb, const KIO &pio, int e,
+                                         int d, bool valid, int r) {
+#pragma clang fp contract(off)
+  using X = LuPre<P, NQ, T>;
+  using LD = LuLds<P, NQ>;
+  constexpr int N = (P + 1) * (P + 1), Q = NQ * NQ;
+  constexpr bool kWide = sizeof(T) == sizeof(double);
+  area[LD::A_G + r] = x.g;
+  // nodal source sigma_s / (4 pi) phi + q_iso, rounded as in load_one
+  const double ss = x.ss * kInv4Pi;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (r + 16 * k < N) {
+      T sv = T(0);
+      if ((x.use >> 16) & 1) sv = static_cast<T>(ss) * static_cast<T>(x.phi[k]);
+      if (pio.q_iso) sv += static_cast<T>(x.qi[k]);
+      area[LD::A_S + r + 16 * k] = valid ? sv : T(0);
+    }
+  if (pio.q_dir) {
+#pragma unroll
+    for (int k = 0; k < (Q + 15) / 16; ++k) {
+      const int q = r + 16 * k;
+      if (q < Q) area[LD::A_QD + q] = valid ? static_cast<T>(gload(pio.q_dir + ((size_t)d * pb.ne + e) * Q + q)) : T(0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < X::NT; ++k)
+    if (r + 16 * k < 4 * X::TW) {
+      T v = T(0);
+      if ((x.use >> k) & 1) v = x.tr[k];  // (double precision: boundary data as well)
+      if constexpr (!kWide) {
+        if ((x.use >> (8 + k)) & 1) v = static_cast<T>(x.bc[k]);
+      }
+      area[LD::A_TR + r + 16 * k] = v;
+    }
+  if (r < 3) area[LD::A_SC + r] = x.sc;
+}
+
+constexpr int kLuStreamMax = 16;  // solves per slot and launch (one per lane of the slot)
+
+template <int P, int NQ, typename T, bool FIX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
+k_sweep_level_lus(const int2 *__restrict__ solves, int n_solves, const KProb *__restrict__ probs,
+                  const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
+                  int *__restrict__ status) {
+  using S = LuShape<P>;
+  using LD = LuLds<P, NQ>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  if (*stop) return;
+  stage_tables_lu<P, NQ, T>(tables, lds);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;
+  const int slot = (threadIdx.x >> 6) * S::SPW + (lane >> 4);
+  const int per_block = (blockDim.x >> 6) * S::SPW;
+  const int n_slots = gridDim.x * per_block;
+  const int sid0 = blockIdx.x * per_block + slot;
+  const int sidw = blockIdx.x * per_block + (threadIdx.x >> 6) * S::SPW;  // first slot of the wave
+  // the host sizes the grid so that no slot has more than kLuStreamMax solves
+  const int n_it = sidw < n_solves ? (n_solves - sidw + n_slots - 1) / n_slots : 0;
+  const KProb &pb = probs[0];
+  const KIO &pio = io[0];
+
+  // descriptors of the slot's solves, in LDS after the slot areas: lane k
+  // writes those of the slot's k-th solve (element, direction, flags,
+  // neighbours; flags: inflow faces, neighbour faces << 4, pivoting bit 12,
+  // boundary faces << 16)
+  int *dtab = reinterpret_cast<int *>(lds + LD::TAB + (size_t)per_block * LD::AREA) + slot * (kLuStreamMax * 8);
+  {
+    int de = 0, dd = 0, dfl = 0, dnb[4] = {-1, -1, -1, -1};
+    const long long sid = (long long)sid0 + (long long)r * n_slots;
+    if (sid < n_solves) {
+      const int2 sv = solves[sid];
+      de = sv.x;
+      dd = sv.y & 0xffff;
+      const unsigned mk = pb.mask[(size_t)dd * pb.ne + de];
+      const int4 nb4 = *reinterpret_cast<const int4 *>(pb.nbr + 4 * (size_t)de);
+      const unsigned nf = *reinterpret_cast<const unsigned *>(pb.nbr_face + 4 * (size_t)de);
+      dfl = (int)((mk & 15u) | ((mk >> 7) << 12));
+#pragma unroll
+      for (int f = 0; f < 4; ++f) dfl |= (int)((nf >> (8 * f)) & 3u) << (4 + 2 * f);
+      dnb[0] = nb4.x;
+      dnb[1] = nb4.y;
+      dnb[2] = nb4.z;
+      dnb[3] = nb4.w;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) dfl |= (dnb[f] < 0 ? 1 : 0) << (16 + f);
+    }
+    int4 *w = reinterpret_cast<int4 *>(dtab + r * 8);
+    w[0] = make_int4(de, dd, dfl, 0);
+    w[1] = make_int4(dnb[0], dnb[1], dnb[2], dnb[3]);
+  }
+  wave_sync_lds();
+  T *area = lds + LD::TAB + (size_t)slot * LD::AREA;
+  const T *wv = tables + Shape<P, NQ>::A_WV;
+  LuPre<P, NQ, T> nx;
+  auto prefetch = [&](int k) __attribute__((always_inline)) {
+    const int4 a = reinterpret_cast<const int4 *>(dtab + k * 8)[0];
+    const int4 b = reinterpret_cast<const int4 *>(dtab + k * 8)[1];
+    const int nb[4] = {b.x, b.y, b.z, b.w};
+    lu_prefetch<P, NQ, T>(nx, a.x, a.y, a.z, nb, (long long)sid0 + (long long)k * n_slots < n_solves, pb, pio, it,
+                          r);
+  };
+  prefetch(0);
+  for (int k = 0; k < n_it; ++k) {
+    const int4 a = reinterpret_cast<const int4 *>(dtab + k * 8)[0];
+    const int e = a.x, d = a.y, fl = a.z;
+    const bool valid = (long long)sid0 + (long long)k * n_slots < n_solves;
+    wave_sync_lds();  // the previous solve is done with the area
+    lu_stage<P, NQ, T>(nx, area, pb, pio, e, d, valid, r);
+    wave_sync_lds();
+    if (k + 1 < n_it) prefetch(k + 1);
+    // only the sign of a neighbour index is used by the solve
+    const int nb[4] = {(fl >> 16) & 1 ? -1 : 0, (fl >> 17) & 1 ? -1 : 0, (fl >> 18) & 1 ? -1 : 0,
+                       (fl >> 19) & 1 ? -1 : 0};
+    lu_core<P, NQ, T, FIX, false, true>(e, d, valid, fl, nb, area[LD::A_SC + 1], area[LD::A_SC + 2], area[LD::A_SC],
+                                        pb, pio, lds, wv, area, r, status);
+  }
 }
 
 // Direction-resident schedule with the row-set LU (as k_sweep_dir).
@@ -1833,8 +2147,25 @@ hipError_t launch_level_lu_t(const SweepLaunch &L) {
     const int per_block = (block / 64) * LuShape<P>::SPW;
     const size_t bytes = sizeof(T) * ((size_t)LD::TAB + (size_t)LD::AREA * per_block);
     if (bytes > L.lds_max) return hipErrorInvalidValue;
-    const int grid = (L.count + per_block - 1) / per_block;
+    int grid = (L.count + per_block - 1) / per_block;
     if (grid == 0) return hipSuccess;
+    const size_t bytes_s = bytes + sizeof(int) * 8 * kLuStreamMax * per_block;  // + the descriptor tables
+    if (L.single && L.n_cu > 0 && bytes_s <= L.lds_max) {
+      // streaming form: the resident work-groups, and enough of them that a
+      // slot has at most kLuStreamMax solves
+      int per_cu = 0;
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_level_lus<P, NQ, T, FIX>, block,
+                                                                  bytes_s);
+      if (e != hipSuccess) return e;
+      if (per_cu < 1) return hipErrorInvalidConfiguration;
+      const int cap = per_block * kLuStreamMax;
+      const int lo = (L.count + cap - 1) / cap;
+      const int res = per_cu * L.n_cu;
+      if (grid > res) grid = res > lo ? res : lo;
+      hipLaunchKernelGGL((k_sweep_level_lus<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes_s, L.stream, L.list,
+                         L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
+      return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_sweep_level_lu<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes, L.stream, L.list, L.count,
                        L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
     return hipGetLastError();
