@@ -180,6 +180,14 @@ typedef struct {
                     wave exits normally and vef_sweep_check reports
                     VEF_ERR_TIMEOUT (the outputs of that run are then
                     incomplete).  Small values exist to test that path. */
+  int elem_matrices; /* general (curved) elements of degree 3 with the
+                    whole-face upwind rule: 0 (default) = form each element's
+                    direction-independent matrices (mass, the two streaming
+                    matrices, face matrices) once at create, on the matrix
+                    cores, and assemble each local system from them
+                    (VEF_KERNEL_GENERAL_MAT); -1 = assemble every local system
+                    by quadrature (VEF_KERNEL_PIVOT / VEF_KERNEL_NOPIVOT).
+                    Costs 6 KB (double) or 3 KB (float) per element. */
 } vef_options;
 
 /* Per-problem device buffers of one run (device pointers owned by the caller).
@@ -261,6 +269,10 @@ typedef struct {
 #define VEF_KERNEL_AFFINE_LU 5       /* affine, p >= 3: a 16-lane slot per
                                        solve holding one or two rows per
                                        lane, LU in natural order */
+#define VEF_KERNEL_GENERAL_MAT 6     /* general elements, p = 3: row per lane
+                                       from precomputed element matrices;
+                                       LU in natural order where the plan
+                                       certifies it, else partial pivoting */
 
 /* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
  * upwind graphs unless opt->cycles lags them), build the sweep plan on the host and upload it to the

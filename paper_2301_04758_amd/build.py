@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvefsweep.so")
-SOURCES = ["plan.cpp", "kernels.hip", "sweep_p1.hip", "sweep_p2.hip", "sweep_p3.hip", "sweep_p4.hip", "probe.hip",
+SOURCES = ["plan.cpp", "kernels.hip", "sweep_p1.hip", "sweep_p2.hip", "sweep_p3.hip", "sweep_p4.hip", "probe.hip", "emat.hip",
            "hrt.hip", "lambda.hip", "api.cpp"]
 ARCH = os.environ.get("VEF_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")

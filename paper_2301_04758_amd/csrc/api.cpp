@@ -37,6 +37,7 @@ struct Variant {
 };
 
 int mode_of(const vefplan::ProblemPlan &pl, int schedule, bool pipeline = true, bool fixup = false) {
+  if (pl.elem_mat) return 6;  // general elements, p = 3, precomputed element matrices
   if (!pl.nopivot) return 0;
   const bool pipe = pipeline && schedule == VEF_DIR_RESIDENT && pl.p <= 2;
   // straight-sided bilinear elements: the pipelined kernel with quadrature
@@ -60,8 +61,12 @@ struct FlowLaunch {  // one persistent launch: the tasks of a variant (row-per-l
   const void *tab;
 };
 
+// Modes whose kernels stage the affine table blob (reference matrices);
+// the others stage the quadrature tables (V, Dx, Dy, F).
+bool affine_tables(int mode) { return mode >= 2 && mode <= 5; }
+
 // Modes with a persistent kernel (no fixup variant).
-bool flow_mode(int mode, int fixup) { return !fixup && (mode == 0 || mode == 1 || mode == 5); }
+bool flow_mode(int mode, int fixup) { return !fixup && (mode == 0 || mode == 1 || mode == 5 || mode == 6); }
 
 // Solves per round of one wave of a kernel mode: 16-lane slots for the
 // row-set LU, otherwise the power-of-two slot >= n of the row-per-lane kernels.
@@ -122,6 +127,7 @@ struct vef_sweep {
   std::vector<int> resid_cap;
   int *d_flags = nullptr;  // [0] stop, [1] iterations done, [2] status
   long long wait_polls = 1LL << 26;  // bound of one device-side wait (polls)
+  bool elem_matrices = true;         // precomputed element matrices where available
   double *static_resid = nullptr;    // this device's copy of `scratch` (vef_sweep_run_static)
   hipStream_t last_stream = nullptr;
   bool timing = false;
@@ -273,6 +279,9 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     h->upwind = opt->upwind;
     if (opt->wait_polls < 0) return set_err(h, VEF_ERR_INVALID, "wait_polls must be >= 0");
     if (opt->wait_polls > 0) h->wait_polls = opt->wait_polls;
+    if (opt->elem_matrices != 0 && opt->elem_matrices != -1)
+      return set_err(h, VEF_ERR_INVALID, "elem_matrices must be 0 or -1");
+    h->elem_matrices = opt->elem_matrices == 0;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
   }
@@ -283,6 +292,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     int rc = vefplan::build_problem_plan(probs[k], h->cycles == VEF_CYCLES_LAG, h->upwind == VEF_UPWIND_POINT,
                                          h->plans[k], e);
     if (rc) return set_err(h, rc, "problem " + std::to_string(k) + ": " + e);
+    auto &pl = h->plans[k];
+    pl.elem_mat = h->elem_matrices && !pl.affine && pl.p == 3 && h->upwind == VEF_UPWIND_FACE;
   }
   hipError_t he = hipGetDevice(&h->device);
   if (he != hipSuccess) return hip_fail(h, he, "hipGetDevice");
@@ -380,6 +391,30 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     kp.bf_ef = bfe;
     kp.bnd = bnd;
     kp.tab_d = h->tables[std::make_pair(pl.p, pl.nq)].dev_d;
+    if (pl.elem_mat) {
+      // direction-independent element matrices, formed once from double
+      // geometry (a temporary double copy of the volume geometry for float)
+      const size_t per = 3 * (size_t)pl.n * pl.n + 8 * (size_t)(pl.p + 1) * (pl.p + 1);
+      void *em = nullptr;
+      he = fp32 ? dev_alloc(h, reinterpret_cast<float **>(&em), per * pl.ne)
+                : dev_alloc(h, reinterpret_cast<double **>(&em), per * pl.ne);
+      const double *gvd = static_cast<const double *>(gv);
+      double *tmp = nullptr;
+      if (he == hipSuccess && fp32) {
+        he = hipMalloc((void **)&tmp, sizeof(double) * pl.geo_v.size());
+        if (he == hipSuccess)
+          he = hipMemcpy(tmp, pl.geo_v.data(), sizeof(double) * pl.geo_v.size(), hipMemcpyHostToDevice);
+        gvd = tmp;
+      }
+      if (he == hipSuccess) he = vefk::launch_elem_mat(pl.p, pl.nq, fp32, pl.ne, kp.tab_d, gvd, gfd, em, 0);
+      if (he == hipSuccess) he = hipDeviceSynchronize();
+      if (tmp) {
+        const hipError_t fe = hipFree(tmp);
+        if (he == hipSuccess) he = fe;
+      }
+      if (he != hipSuccess) return hip_fail(h, he, "element matrices");
+      kp.emat = em;
+    }
     h->h_probs[k] = kp;
   }
   he = upload(h, &h->d_probs, h->h_probs.data(), h->h_probs.size());
@@ -404,7 +439,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     bool narrow = true;
     for (auto &pl : h->plans) {
       const double width = (double)pl.ne / pl.n_levels;
-      if (mode_of(pl, VEF_DIR_RESIDENT, h->pipeline_waves >= 0, h->fixup) >= 3) {
+      const int md = mode_of(pl, VEF_DIR_RESIDENT, h->pipeline_waves >= 0, h->fixup);
+      if (md >= 3 && md <= 5) {
         if (width > 256.0) narrow = false;
         continue;
       }
@@ -494,7 +530,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       const int cnt = (int)solves.size() - off;
       if (cnt > 0) {
         const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
-        h->levels[L].push_back({var, off, cnt, var.mode >= 2 ? ts.dev_A : ts.dev_T, pass_flow});
+        h->levels[L].push_back({var, off, cnt, affine_tables(var.mode) ? ts.dev_A : ts.dev_T, pass_flow});
       }
       }
   if (solves.size() != total) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
@@ -522,7 +558,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       const Variant &var = kv.first;
       const int base = (int)ft.size();
       const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
-      h->flow.push_back({var, base, (int)kv.second.size(), var.mode >= 2 ? ts.dev_A : ts.dev_T});
+      h->flow.push_back({var, base, (int)kv.second.size(), affine_tables(var.mode) ? ts.dev_A : ts.dev_T});
       const int tsz = solves_per_round(var.mode, (var.p + 1) * (var.p + 1)) * kFlowRounds;
       const auto &blks = flow_task_blk[var];
       std::vector<int> pre;
@@ -579,7 +615,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       if (cnt > 0) {
         const TableSet &ts = h->tables[std::make_pair(var.p, var.nq)];
         (pipe ? h->dir_pipe : h->dir_rows)
-            .push_back({var, off, cnt, width, maxl, gap, var.mode >= 2 ? ts.dev_A : ts.dev_T, ts.dev_T});
+            .push_back({var, off, cnt, width, maxl, gap, affine_tables(var.mode) ? ts.dev_A : ts.dev_T, ts.dev_T});
       }
     }
   he = upload(h, &h->d_dir_tasks, tasks.data(), tasks.size());
@@ -1043,7 +1079,10 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
   };
   const Cand before{h->schedule, h->pipeline_waves, h->block};
   bool any_pipe = false;
-  for (auto &pl : h->plans) any_pipe |= mode_of(pl, VEF_DIR_RESIDENT, true, h->fixup) >= 3;
+  for (auto &pl : h->plans) {
+    const int md = mode_of(pl, VEF_DIR_RESIDENT, true, h->fixup);
+    any_pipe |= md == 3 || md == 4;
+  }
   std::vector<Cand> cands{before};
   auto add = [&](Cand c) {
     for (auto &x : cands)

@@ -13,6 +13,7 @@ struct KProb {
   const void *geo_v;       // T [ne][Q][5]: w J, w adj(F) (row major)
   const void *geo_f;       // T [ne][4][nq][2]: w_s n ds
   const void *geo_a;       // T [ne][16]: J, adj(F) (row major), face chords N_0..N_3 (affine meshes)
+  const void *emat;        // T [ne][3 n n + 8 (p+1)^2]: element matrices (general elements, p = 3), or NULL
   const double *geo_fd;    // double copy of geo_f
   const int32_t *nbr;      // [ne][4] neighbour or -(bf+1)
   const int8_t *nbr_face;  // [ne][4]
@@ -103,6 +104,14 @@ hipError_t launch_finalize(const KIO *io, int n_probs, int it, double tol, int *
 hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int nbf,
                            int nq, hipStream_t s);
 hipError_t launch_zero_nonpos(const KMomIO *io, int n_probs, hipStream_t s);
+
+// Direction-independent element matrices of general elements of degree 3
+// (emat.hip): M, G^x, G^y [n][n] and the face matrices [4][2][p+1][p+1] of
+// each element from the double volume geometry geo_vd [ne][Q][5] (w J,
+// w adj(F)), the double face geometry geo_fd [ne][4][nq][2] and the double
+// tables of (p, nq); written in float or double.
+hipError_t launch_elem_mat(int p, int nq, bool fp32, int ne, const double *tab_d, const double *geo_vd,
+                           const double *geo_fd, void *out, hipStream_t s);
 
 // Element-local HRT VEF blocks and their inverse (hrt.hip), affine elements.
 struct HrtLaunch {

@@ -60,6 +60,7 @@ struct ProblemPlan {
   bool straight = true;             // every face of the mesh is a straight segment
   bool nopivot = false;             // straight faces and sigma_t > 0 everywhere
   bool affine = false;              // every element map is affine (constant J and adj(F))
+  bool elem_mat = false;            // solved from precomputed element matrices (set by the handle)
   std::vector<double> geo_a;        // [ne][16] J, adj(F), chords (when affine)
   std::vector<double> omega, weight, sigma_t, sigma_s;
   Tables tab;

@@ -54,6 +54,7 @@ enum : int {
   MODE_AFFINE_PIPELINE = 3,  // direction-resident schedule only, p <= 2
   MODE_GENERAL_PIPELINE = 4, // the same for straight-sided bilinear elements (m = 1)
   MODE_AFFINE_LU = 5,        // affine, pivot-free, p >= 3: row-set LU with fused broadcasts
+  MODE_GENERAL_MAT = 6,      // general elements, p = 3: precomputed element matrices, per-solve pivoting choice
   MODE_KIND = 7,             // mask of the kernel kind above
   MODE_FIX = 8               // flag: negative-flux fixup after each local solve
 };
@@ -701,6 +702,193 @@ __device__ __forceinline__ void solve_one(const SolveIn<P, NQ, T> &in, int d, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// General elements with precomputed element matrices (degree 3).  The
+// direction-independent parts of the local system are formed once per
+// element (k_elem_mat, matrix cores): the mass matrix M_ij = int phi_i phi_j,
+// the streaming matrices G^x_ij, G^y_ij = int (dphi_i / dx or dy) phi_j
+// (adj(F)^T grad^ phi_i at the volume points), and per face f the face mass
+// weighted by each normal component, F^x_f, F^y_f [p+1][p+1] (w_s n ds at
+// the face points).  A solve then assembles
+//   A = sigma_t M - Omega_x G^x - Omega_y G^y + sum over outflow faces of
+//       (Omega_x F^x_f + Omega_y F^y_f) on the face nodes,
+//   b = M s - sum over inflow faces of (Omega_x F^x_f + Omega_y F^y_f) times
+//       the upwind trace (boundary data by face quadrature),
+// three multiply-adds per entry in place of the quadrature sums.  Layout per
+// element: M, G^x, G^y [n][n] row major, then [4][2][p+1][p+1].
+// ---------------------------------------------------------------------------
+template <int P>
+struct EMat {
+  static constexpr int P1 = P + 1, N = P1 * P1;
+  static constexpr int OFF_GX = N * N, OFF_GY = 2 * N * N, OFF_F = 3 * N * N;
+  static constexpr int SIZE = 3 * N * N + 8 * P1 * P1;  // values per element
+};
+
+template <int P, int NQ, typename T>
+struct SolveInM {
+  int e, flags;  // flags as SolveIn
+  int nb[4];
+  bool valid;
+  T s;  // nodal source at node r
+};
+
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void load_one(SolveInM<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio, int it,
+                                         int r) {
+  constexpr int N = (P + 1) * (P + 1);
+  (void)d;
+  if (!in.valid) return;
+  const int e = in.e;
+  const double *phi = it == 0 ? pio.phi_in : pio.mom;
+  T sv = T(0);
+  if (r < N) {
+    if (phi) sv = static_cast<T>(pb.sig[2 * e + 1] * kInv4Pi) * static_cast<T>(phi[(size_t)e * N + r]);
+    if (pio.q_iso) sv += static_cast<T>(pio.q_iso[(size_t)e * N + r]);
+  }
+  in.s = sv;
+}
+
+template <int P, int NQ, typename T, bool PIVOT, bool FIX, bool COH = false>
+__device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio,
+                                          T *lds, int r, int slot, int *status) {
+  using S = Shape<P, NQ>;
+  using EM = EMat<P>;
+  constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
+  static_assert(N == 16 && SLOT == 16, "element matrices: degree 3");
+  const T *sV = lds;
+  const T *sF = lds + 3 * Q * N;
+  T *area = lds + S::TAB + (size_t)slot * S::SLOT_AREA;
+  const int ne = pb.ne;
+  const int e = in.e;
+  const bool valid = in.valid;
+  const bool row_ok = valid && r < N;
+  const int rr = r < N ? r : N - 1;
+  const int a = rr % P1, b = rr / P1;
+  const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
+
+  // the lane's rows of M, G^x, G^y and of the face matrices of its faces
+  const T *em = static_cast<const T *>(pb.emat) + (size_t)(valid ? e : 0) * EM::SIZE;
+  T mr[N], gx[N], gy[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    mr[j] = gload(em + rr * N + j);
+    gx[j] = gload(em + EM::OFF_GX + rr * N + j);
+    gy[j] = gload(em + EM::OFF_GY + rr * N + j);
+  }
+  T fx[4][P1], fy[4][P1];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+    const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+#pragma unroll
+    for (int c = 0; c < P1; ++c) {
+      fx[f][c] = on_face ? gload(em + EM::OFF_F + (2 * f) * P1 * P1 + pos * P1 + c) : T(0);
+      fy[f][c] = on_face ? gload(em + EM::OFF_F + (2 * f + 1) * P1 * P1 + pos * P1 + c) : T(0);
+    }
+  }
+  // upwind traces
+  const T *psi = static_cast<const T *>(pio.psi);
+  T tr[4][P1];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+#pragma unroll
+    for (int c = 0; c < P1; ++c) tr[f][c] = T(0);
+    if (row_ok && on_face && ((mask >> f) & 1u) && in.nb[f] >= 0) {
+      const int f2 = (in.flags >> (4 + 2 * f)) & 3;
+      const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
+#pragma unroll
+      for (int c = 0; c < P1; ++c) tr[f][c] = ld_psi<COH>(up + face_node<P>(f2, P - c));
+    }
+  }
+  if (r < N) area[S::OFF_S + r] = in.s;
+  wave_sync_lds();
+
+  const T ox = static_cast<T>(pb.omega[2 * d]);
+  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
+  const T st = static_cast<T>(pb.sig[2 * (valid ? e : 0)]);
+  T A[N];
+  T rhs = T(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    A[j] = st * mr[j] - (ox * gx[j] + oy * gy[j]);
+    rhs += mr[j] * area[S::OFF_S + j];
+  }
+  if (pio.q_dir && row_ok) {
+    // direction-dependent source at the volume points: int phi_r q_dir
+    const T *g5 = static_cast<const T *>(pb.geo_v) + (size_t)e * Q * 5;
+    const double *qd = pio.q_dir + ((size_t)d * ne + e) * Q;
+    T acc = T(0);
+    for (int q = 0; q < Q; ++q) acc += g5[5 * q] * sV[q * N + rr] * static_cast<T>(qd[q]);
+    rhs += acc;
+  }
+  T cw = T(0);  // outflow part of the balance weight (fixup)
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+    const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+    if (!(row_ok && on_face)) continue;
+    if (!((mask >> f) & 1u)) {
+#pragma unroll
+      for (int c = 0; c < P1; ++c) {
+        const T t = ox * fx[f][c] + oy * fy[f][c];
+        A[face_node<P>(f, c)] += t;
+        if constexpr (FIX) cw += t;
+      }
+    } else if (in.nb[f] >= 0) {
+#pragma unroll
+      for (int c = 0; c < P1; ++c) rhs -= (ox * fx[f][c] + oy * fy[f][c]) * tr[f][c];
+    } else if (pio.psi_bc) {
+      const T *gf = static_cast<const T *>(pb.geo_f) + (size_t)e * 8 * NQ + f * NQ * 2;
+      const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const T on = ox * gf[2 * q] + oy * gf[2 * q + 1];
+        rhs -= on * sF[q * P1 + pos] * static_cast<T>(bc[q]);
+      }
+    }
+  }
+
+  // elimination: the certified LU with fused broadcasts, or Gauss-Jordan
+  // with partial pivoting (see the general solve)
+  int my_k = r;
+  if (!PIVOT || !((in.flags >> 12) & 1)) {
+    T A1[1][N + 1], idg[1];
+#pragma unroll
+    for (int j = 0; j < N; ++j) A1[0][j] = A[j];
+    A1[0][N] = rhs;
+    lu_rows<N, 1, 16, T>(A1, idg, r);
+    rhs = A1[0][N] * idg[0];
+  } else if constexpr (PIVOT) {
+    bool active = row_ok;
+    gj_pivot<SLOT, N, 0, T>(A, rhs, r, active, my_k, area + S::OFF_PIV);
+  }
+  if constexpr (FIX) {
+    // balance weight of unknown rr: sigma_t int phi_rr (a row sum of M, the
+    // basis summing to one) plus the outflow terms
+    T cr = T(0);
+    if (row_ok) {
+      T sm = T(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) sm += mr[j];
+      cr = st * sm + cw;
+    }
+    if constexpr (PIVOT) {  // lane r holds unknown my_k: fetch its weight
+      T *cwl = area + S::OFF_PIV;
+      if (row_ok) cwl[r] = cr;
+      wave_sync_lds();
+      cr = cwl[my_k];
+      __builtin_amdgcn_wave_barrier();
+    }
+    zero_and_scale_slot<SLOT, T>(rhs, cr, row_ok);
+  }
+  if (row_ok) {
+    T *out = static_cast<T *>(pio.psi) + ((size_t)d * ne + e) * N;
+    st_psi<COH>(out + my_k, rhs);
+    if (!__builtin_isfinite(rhs)) atomicOr(status, 1);  // non-finite unknown
+  }
+}
+
 // Per-lane inputs of one solve on an affine element.
 template <int P, int NQ, typename T>
 struct SolveInA {
@@ -886,7 +1074,14 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
 }
 
 template <int P, int NQ, typename T, int MODE>
-using InputsOf = std::conditional_t<(MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT, SolveInA<P, NQ, T>, SolveIn<P, NQ, T>>;
+using InputsOf = std::conditional_t<
+    (MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT, SolveInA<P, NQ, T>,
+    std::conditional_t<(MODE & MODE_KIND) == MODE_GENERAL_MAT, SolveInM<P, NQ, T>, SolveIn<P, NQ, T>>>;
+
+// Modes whose solves may pivot (per solve: see the plan's certification bit).
+constexpr bool mode_pivots(int mode) {
+  return (mode & MODE_KIND) == MODE_GENERAL_PIVOT || (mode & MODE_KIND) == MODE_GENERAL_MAT;
+}
 
 // Stage the tables of a variant into LDS.
 template <int P, int NQ, typename T, int MODE>
@@ -940,7 +1135,7 @@ k_sweep_level(const int2 *__restrict__ solves, int n_solves, const KProb *__rest
     for (int f = 0; f < 4; ++f) in.nb[f] = -1;
   }
   load_one<P, NQ, T>(in, d, pb, pio, it, r);
-  solve_one<P, NQ, T, (MODE & MODE_KIND) == MODE_GENERAL_PIVOT, (MODE & MODE_FIX) != 0>(in, d, pb, pio, lds, r, slot,
+  solve_one<P, NQ, T, mode_pivots(MODE), (MODE & MODE_FIX) != 0>(in, d, pb, pio, lds, r, slot,
                                                                                      status);
 }
 
@@ -1004,7 +1199,7 @@ k_sweep_dir(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       const int4 nb = dnb[t];
       in.e = ef.x;
       in.flags = ef.y;
-      if constexpr ((MODE & MODE_KIND) == MODE_GENERAL_PIVOT)  // this direction's pivoting bit
+      if constexpr (mode_pivots(MODE))  // this direction's pivoting bit
         in.flags |= (int)((pb.mask[(size_t)d * pb.ne + ef.x] >> 7) << 12);
       in.nb[0] = nb.x;
       in.nb[1] = nb.y;
@@ -1025,7 +1220,7 @@ k_sweep_dir(const int2 *__restrict__ tasks, const KProb *__restrict__ probs,
       base2 = L2 < nl ? lo[L2] : 0;
     }
     fetch(nxt, L2, base2 + slot);
-    solve_one<P, NQ, T, (MODE & MODE_KIND) == MODE_GENERAL_PIVOT, (MODE & MODE_FIX) != 0>(cur, d, pb, pio, lds, r,
+    solve_one<P, NQ, T, mode_pivots(MODE), (MODE & MODE_FIX) != 0>(cur, d, pb, pio, lds, r,
                                                                                        slot, status);
     if (L2 != L) __syncthreads();  // the level's fluxes are upwind values of the next
     cur = nxt;
@@ -2245,7 +2440,7 @@ struct FlowPolicy<P, NQ, T, MODE, false> {
   static __device__ __forceinline__ void solve(const In &in, int d, const KProb &pb, const KIO &pio,
                                                const T *tables, T *lds, int r, int slot, int *status) {
     (void)tables;
-    solve_one<P, NQ, T, (MODE & MODE_KIND) == MODE_GENERAL_PIVOT, false, true>(in, d, pb, pio, lds, r, slot, status);
+    solve_one<P, NQ, T, mode_pivots(MODE), false, true>(in, d, pb, pio, lds, r, slot, status);
   }
 };
 
@@ -2479,6 +2674,9 @@ hipError_t launch_mode_fx(const SweepLaunch &L) {
       switch (L.mode) {
         case MODE_GENERAL_PIVOT: return launch_flow_t<P, NQ, T, MODE_GENERAL_PIVOT>(L);
         case MODE_GENERAL_NOPIVOT: return launch_flow_t<P, NQ, T, MODE_GENERAL_NOPIVOT>(L);
+        case MODE_GENERAL_MAT:
+          if constexpr (P == 3) return launch_flow_t<P, NQ, T, MODE_GENERAL_MAT>(L);
+          return hipErrorInvalidValue;
         case MODE_AFFINE_LU:
           if constexpr (P >= 3) return launch_flow_t<P, NQ, T, MODE_AFFINE_LU>(L);
           return hipErrorInvalidValue;
@@ -2496,6 +2694,11 @@ hipError_t launch_mode_fx(const SweepLaunch &L) {
     case MODE_AFFINE_NOPIVOT:
       return DIR ? launch_dir_t<P, NQ, T, MODE_AFFINE_NOPIVOT | FX>(L)
                  : launch_level_t<P, NQ, T, MODE_AFFINE_NOPIVOT | FX>(L);
+    case MODE_GENERAL_MAT:
+      if constexpr (P == 3)
+        return DIR ? launch_dir_t<P, NQ, T, MODE_GENERAL_MAT | FX>(L)
+                   : launch_level_t<P, NQ, T, MODE_GENERAL_MAT | FX>(L);
+      return hipErrorInvalidValue;
     case MODE_AFFINE_PIPELINE:
       return DIR ? launch_pipe_t<P, NQ, T, FX != 0, false>(L) : hipErrorInvalidValue;
     case MODE_GENERAL_PIPELINE:
