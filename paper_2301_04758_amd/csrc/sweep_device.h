@@ -755,7 +755,6 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
   using EM = EMat<P>;
   constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
   static_assert(N == 16 && SLOT == 16, "element matrices: degree 3");
-  const T *sV = lds;
   const T *sF = lds + 3 * Q * N;
   T *area = lds + S::TAB + (size_t)slot * S::SLOT_AREA;
   const int ne = pb.ne;
@@ -815,11 +814,12 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
     rhs += mr[j] * area[S::OFF_S + j];
   }
   if (pio.q_dir && row_ok) {
-    // direction-dependent source at the volume points: int phi_r q_dir
+    // direction-dependent source at the volume points: int phi_r q_dir (V
+    // from the double tables: only the face table is staged)
     const T *g5 = static_cast<const T *>(pb.geo_v) + (size_t)e * Q * 5;
     const double *qd = pio.q_dir + ((size_t)d * ne + e) * Q;
     T acc = T(0);
-    for (int q = 0; q < Q; ++q) acc += g5[5 * q] * sV[q * N + rr] * static_cast<T>(qd[q]);
+    for (int q = 0; q < Q; ++q) acc += g5[5 * q] * static_cast<T>(pb.tab_d[q * N + rr]) * static_cast<T>(qd[q]);
     rhs += acc;
   }
   T cw = T(0);  // outflow part of the balance weight (fixup)
@@ -1087,7 +1087,9 @@ constexpr bool mode_pivots(int mode) {
 template <int P, int NQ, typename T, int MODE>
 __device__ __forceinline__ void stage_tables(const T *__restrict__ tables, T *lds) {
   constexpr int TAB = Lds<P, NQ, MODE>::TAB;
-  for (int i = threadIdx.x; i < TAB; i += blockDim.x) lds[i] = tables[i];
+  // the element-matrix kernels read only the face table F (after V, Dx, Dy)
+  constexpr int FIRST = (MODE & MODE_KIND) == MODE_GENERAL_MAT ? 3 * NQ * NQ * (P + 1) * (P + 1) : 0;
+  for (int i = FIRST + threadIdx.x; i < TAB; i += blockDim.x) lds[i] = tables[i];
 }
 
 // Level-synchronous schedule: one launch per upwind level over the list of
