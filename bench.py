@@ -188,13 +188,16 @@ def measured_traffic(kernel):
     return None
 
 
-def kernel_name(g, pr, dtype="double"):
-    """Name of the sweep kernel that ran (as the profiler lists it)."""
+def kernel_name(g, pr, dtype="double", single=True):
+    """Name of the sweep kernel that ran (as the profiler lists it); single:
+    the handle holds one problem (the level-synchronous row-set LU then runs
+    in its streaming form)."""
     nq = pr.nq or pr.p + pr.m
     if g["schedule"] == "dir_resident" and g["kernel"] in (3, 4):
         return "k_sweep_pipe<%d, %d, %s, false, %s>" % (pr.p, nq, dtype, "true" if g["kernel"] == 4 else "false")
     if g["kernel"] == 5:
-        kind = {"dir_resident": "dir_lu", "persistent": "flow", "level_sync": "level_lu"}[g["schedule"]]
+        level = "level_lus" if single else "level_lu"
+        kind = {"dir_resident": "dir_lu", "persistent": "flow", "level_sync": level}[g["schedule"]]
         if kind == "flow":
             return "k_sweep_flow<%d, %d, %s, 5>" % (pr.p, nq, dtype)
         return "k_sweep_%s<%d, %d, %s, false>" % (kind, pr.p, nq, dtype)
@@ -214,7 +217,7 @@ def workload_leg(name, steps, warmup, schedule):
     for prec, s, peak, dt in (("fp64", 8, FP64_PEAK_TFLOPS, "double"), ("fp32", 4, FP32_PEAK_TFLOPS, "float")):
         g = run_gpu(probs, n_iter, prec, steps, warmup, schedule=schedule)
         ms = 1e3 * g["seconds"] / steps
-        kname = kernel_name(g, probs[0], dt)
+        kname = kernel_name(g, probs[0], dt, single=len(probs) == 1)
         out[prec] = {"ms_per_step": ms, "solves_per_s": solves / (ms * 1e-3), "schedule": g["schedule"],
                      "tuning": g["tuned"], "sweep_ms": g["sweep_ms"],
                      "roofline": roofline(probs, s, g["sweep_ms"] * 1e-3, g["launches"], kname, peak,
