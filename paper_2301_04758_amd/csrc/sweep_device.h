@@ -35,6 +35,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <type_traits>
 
@@ -2364,11 +2365,21 @@ hipError_t launch_level_lu_t(const SweepLaunch &L) {
     if (L.single && L.n_cu > 0 && bytes_s <= L.lds_max) {
       // streaming form: the resident work-groups, and enough of them that a
       // slot has at most kLuStreamMax solves
-      int per_cu = 0;
-      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_level_lus<P, NQ, T, FIX>, block,
-                                                                  bytes_s);
+      // resident blocks per CU: a host query, cached per device and block
+      // size (a level-synchronous sweep launches once per level)
+      static std::atomic<int> cache[64][4];
+      int dev = 0;
+      hipError_t e = hipGetDevice(&dev);
       if (e != hipSuccess) return e;
-      if (per_cu < 1) return hipErrorInvalidConfiguration;
+      if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+      const bool cacheable = block % 64 == 0;
+      int per_cu = cacheable ? cache[dev][block / 64 - 1].load(std::memory_order_relaxed) : 0;
+      if (per_cu == 0) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_level_lus<P, NQ, T, FIX>, block, bytes_s);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) return hipErrorInvalidConfiguration;
+        if (cacheable) cache[dev][block / 64 - 1].store(per_cu, std::memory_order_relaxed);
+      }
       const int cap = per_block * kLuStreamMax;
       const int lo = (L.count + cap - 1) / cap;
       const int res = per_cu * L.n_cu;
