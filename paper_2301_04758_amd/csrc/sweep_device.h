@@ -79,6 +79,11 @@ struct Shape {
   static constexpr int OFF_S = OFF_SRC + Q;         // [N] nodal source coefficients
   static constexpr int OFF_PIV = ((OFF_S + N + 1) / 2) * 2;  // [N + 1] pivot row + rhs
   static constexpr int SLOT_AREA = ((OFF_PIV + N + 1 + 1) / 2) * 2;
+  // element-matrix path: face matrices [4][2][P1][P1], traces [4][P1], nodal
+  // source [N], pivot row [N + 1]
+  static constexpr int OFF_S_M = 8 * P1 * P1 + 4 * P1;
+  static constexpr int OFF_PIV_M = ((OFF_S_M + N + 1) / 2) * 2;
+  static constexpr int SLOT_AREA_M = ((OFF_PIV_M + N + 1 + 1) / 2) * 2;
   static constexpr int QU = P <= 2 ? Q : 1;  // volume loop fully unrolled for small elements
   // affine path: 16 values per element (J, adj(F), four face chords)
   static constexpr int GA = (16 + SLOT - 1) / SLOT;
@@ -96,7 +101,9 @@ template <int P, int NQ, int MODE>
 struct Lds {
   using S = Shape<P, NQ>;
   static constexpr int TAB = (MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT ? S::TAB_A : S::TAB;
-  static constexpr int AREA = (MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT ? S::SLOT_AREA_A : S::SLOT_AREA;
+  static constexpr int AREA = (MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT ? S::SLOT_AREA_A
+                             : (MODE & MODE_KIND) == MODE_GENERAL_MAT  ? S::SLOT_AREA_M
+                                                                       : S::SLOT_AREA;
 };
 
 template <typename T>
@@ -769,7 +776,7 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
   constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
   static_assert(N == 16 && SLOT == 16, "element matrices: degree 3");
   const T *sF = lds + 3 * Q * N;
-  T *area = lds + S::TAB + (size_t)slot * S::SLOT_AREA;
+  T *area = lds + S::TAB + (size_t)slot * S::SLOT_AREA_M;
   const int ne = pb.ne;
   const int e = in.e;
   const bool valid = in.valid;
@@ -787,33 +794,29 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
     gx[j] = gload(em + EM::OFF_GX + rr * N + j);
     gy[j] = gload(em + EM::OFF_GY + rr * N + j);
   }
-  T fx[4][P1], fy[4][P1];
+  // the face matrices [4][2][P1][P1] and the upwind traces [4][P1] go
+  // through the slot's LDS area, each lane loading a share, so that they hold
+  // no registers across the assembly
+  constexpr int FM = 8 * P1 * P1, A_FM = 0, A_TR = FM;
+  static_assert(A_TR + 4 * P1 <= S::OFF_S_M && P1 * 4 == 16, "element-matrix staging layout");
+  T fm[FM / 16];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
-    const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
-#pragma unroll
-    for (int c = 0; c < P1; ++c) {
-      fx[f][c] = on_face ? gload(em + EM::OFF_F + (2 * f) * P1 * P1 + pos * P1 + c) : T(0);
-      fy[f][c] = on_face ? gload(em + EM::OFF_F + (2 * f + 1) * P1 * P1 + pos * P1 + c) : T(0);
-    }
-  }
-  // upwind traces
-  const T *psi = static_cast<const T *>(pio.psi);
-  T tr[4][P1];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
-#pragma unroll
-    for (int c = 0; c < P1; ++c) tr[f][c] = T(0);
-    if (row_ok && on_face && ((mask >> f) & 1u) && in.nb[f] >= 0) {
+  for (int k = 0; k < FM / 16; ++k) fm[k] = gload(em + EM::OFF_F + r + 16 * k);
+  T trv = T(0);
+  {
+    // trace entry r: face r / P1, face node r % P1 (P1 = 4: one per lane)
+    const int f = r / P1, c = r % P1;
+    const int n0 = in.nb[0], n1 = in.nb[1], n2 = in.nb[2], n3 = in.nb[3];  // values, not addresses, selected
+    const int u = f == 0 ? n0 : f == 1 ? n1 : f == 2 ? n2 : n3;
+    if (valid && ((mask >> f) & 1u) && u >= 0) {
       const int f2 = (in.flags >> (4 + 2 * f)) & 3;
-      const T *up = psi + ((size_t)d * ne + in.nb[f]) * N;
-#pragma unroll
-      for (int c = 0; c < P1; ++c) tr[f][c] = ld_psi<COH>(up + face_node<P>(f2, P - c));
+      trv = ld_psi<COH>(static_cast<const T *>(pio.psi) + ((size_t)d * ne + u) * N + face_node_sel<P>(f2, P - c));
     }
   }
-  if (r < N) area[S::OFF_S + r] = in.s;
+#pragma unroll
+  for (int k = 0; k < FM / 16; ++k) area[A_FM + r + 16 * k] = fm[k];
+  area[A_TR + r] = trv;
+  if (r < N) area[S::OFF_S_M + r] = in.s;
   wave_sync_lds();
 
   const T ox = static_cast<T>(pb.omega[2 * d]);
@@ -824,7 +827,7 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     A[j] = st * mr[j] - (ox * gx[j] + oy * gy[j]);
-    rhs += mr[j] * area[S::OFF_S + j];
+    rhs += mr[j] * area[S::OFF_S_M + j];
   }
   if (pio.q_dir && row_ok) {
     // direction-dependent source at the volume points: int phi_r q_dir (V
@@ -841,16 +844,18 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
     const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
     const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
     if (!(row_ok && on_face)) continue;
+    const T *fxr = area + A_FM + (2 * f) * P1 * P1 + pos * P1;
+    const T *fyr = fxr + P1 * P1;
     if (!((mask >> f) & 1u)) {
 #pragma unroll
       for (int c = 0; c < P1; ++c) {
-        const T t = ox * fx[f][c] + oy * fy[f][c];
+        const T t = ox * fxr[c] + oy * fyr[c];
         A[face_node<P>(f, c)] += t;
         if constexpr (FIX) cw += t;
       }
     } else if (in.nb[f] >= 0) {
 #pragma unroll
-      for (int c = 0; c < P1; ++c) rhs -= (ox * fx[f][c] + oy * fy[f][c]) * tr[f][c];
+      for (int c = 0; c < P1; ++c) rhs -= (ox * fxr[c] + oy * fyr[c]) * area[A_TR + f * P1 + c];
     } else if (pio.psi_bc) {
       const T *gf = static_cast<const T *>(pb.geo_f) + (size_t)e * 8 * NQ + f * NQ * 2;
       const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
@@ -874,7 +879,7 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
     rhs = A1[0][N] * idg[0];
   } else if constexpr (PIVOT) {
     bool active = row_ok;
-    gj_pivot<SLOT, N, 0, T>(A, rhs, r, active, my_k, area + S::OFF_PIV);
+    gj_pivot<SLOT, N, 0, T>(A, rhs, r, active, my_k, area + S::OFF_PIV_M);
   }
   if constexpr (FIX) {
     // balance weight of unknown rr: sigma_t int phi_rr (a row sum of M, the
@@ -887,7 +892,7 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
       cr = st * sm + cw;
     }
     if constexpr (PIVOT) {  // lane r holds unknown my_k: fetch its weight
-      T *cwl = area + S::OFF_PIV;
+      T *cwl = area + S::OFF_PIV_M;
       if (row_ok) cwl[r] = cr;
       wave_sync_lds();
       cr = cwl[my_k];
