@@ -111,6 +111,7 @@ struct vef_sweep {
   std::vector<vefk::KMomIO> mio_last;
   bool mio_valid = false;
   int2 *d_solves = nullptr;
+  int4 *d_solve_desc = nullptr;  // per entry of d_solves: (element, direction | problem << 16, flags, 0), neighbours
   std::vector<std::vector<LevelLaunch>> levels;
   int2 *d_dir_tasks = nullptr;
   std::vector<FlowLaunch> flow;   // persistent schedule
@@ -537,6 +538,29 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
   he = upload(h, &h->d_solves, solves.data(), solves.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload solve lists");
+  {
+    // descriptors of the level lists' solves, so that a level launch reads
+    // one record per solve instead of the list and then the element's masks
+    // and neighbours: flags = inflow faces | neighbour faces << 4 |
+    // pivoting needed << 12 | boundary faces << 16
+    std::vector<int4> desc(2 * solves.size());
+    for (size_t i = 0; i < solves.size(); ++i) {
+      const int e = solves[i].x, d = solves[i].y & 0xffff, k = solves[i].y >> 16;
+      const auto &pl = h->plans[k];
+      const unsigned mk = pl.mask[(size_t)d * pl.ne + e];
+      int fl = (int)((mk & 15u) | ((mk >> 7) << 12));
+      int nb[4];
+      for (int f = 0; f < 4; ++f) {
+        nb[f] = pl.nbr[4 * (size_t)e + f];
+        fl |= ((int)pl.nbr_face[4 * (size_t)e + f] & 3) << (4 + 2 * f);
+        fl |= (nb[f] < 0 ? 1 : 0) << (16 + f);
+      }
+      desc[2 * i] = make_int4(e, solves[i].y, fl, 0);
+      desc[2 * i + 1] = make_int4(nb[0], nb[1], nb[2], nb[3]);
+    }
+    he = upload(h, &h->d_solve_desc, desc.data(), desc.size());
+    if (he != hipSuccess) return hip_fail(h, he, "upload solve descriptors");
+  }
   if (!flow_tasks.empty()) {
     // predecessors of a task: for each of its solves (e, d) and each inflow
     // face of e with an upwind element u, the task holding the solve (u, d)
@@ -822,6 +846,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
           SL.nq = L.v.nq;
           SL.mode = L.v.mode;
           SL.list = h->d_solves + L.off;
+          SL.desc = h->d_solve_desc + 2 * (size_t)L.off;
           SL.count = L.cnt;
           SL.tables = L.tab;
           he = vefk::launch_sweep_level(SL);

@@ -57,6 +57,8 @@ struct SweepLaunch {
   int p, nq;
   bool fp32;
   int mode;          // 0: general elements, pivoting; 1: general, pivot-free; 2: affine, pivot-free
+  const int4 *desc;  // level schedule: two records per entry of list (element, direction | problem << 16,
+                     // flags, 0), (neighbours); flags as the kernels' SolveIn flags, boundary faces << 16
   const int2 *list;  // level schedule: (element, direction | problem << 16) pairs of one level;
                      // direction-resident schedule: (problem, direction) tasks
   int count;       // level: solves; direction-resident: tasks; persistent: tasks

@@ -1114,46 +1114,36 @@ __device__ __forceinline__ void stage_tables(const T *__restrict__ tables, T *ld
 // (element, direction | problem << 16) pairs of that level.
 template <int P, int NQ, typename T, int MODE>
 __global__ void __launch_bounds__(256)
-k_sweep_level(const int2 *__restrict__ solves, int n_solves, const KProb *__restrict__ probs,
+k_sweep_level(const int4 *__restrict__ desc, int n_solves, const KProb *__restrict__ probs,
               const KIO *__restrict__ io, const T *__restrict__ tables, int it,
               const int *__restrict__ stop, int *__restrict__ status) {
   using S = Shape<P, NQ>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
-  if (*stop) return;
-  stage_tables<P, NQ, T, MODE>(tables, lds);
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int r = lane & (S::SLOT - 1);
   const int slot = (threadIdx.x >> 6) * S::SPW + lane / S::SLOT;
   const int sid = xcd_block(blockIdx.x, gridDim.x) * ((blockDim.x >> 6) * S::SPW) + slot;
   InputsOf<P, NQ, T, MODE> in;
   in.valid = sid < n_solves;
-  int d = 0, prob = 0;
-  in.e = 0;
-  in.flags = 0;
+  // the solve's descriptor, read before the stop flag so the two loads overlap
+  int4 da = make_int4(0, 0, 0, 0), db = make_int4(-1, -1, -1, -1);
   if (in.valid) {
-    const int2 sv = solves[sid];
-    in.e = sv.x;
-    d = sv.y & 0xffff;
-    prob = sv.y >> 16;
+    da = desc[2 * (size_t)sid];
+    db = desc[2 * (size_t)sid + 1];
   }
+  if (*stop) return;
+  stage_tables<P, NQ, T, MODE>(tables, lds);
+  __syncthreads();
+  in.e = da.x;
+  const int d = da.y & 0xffff, prob = da.y >> 16;
+  in.flags = da.z & 0xffff;  // inflow faces, neighbour faces, pivoting needed
+  in.nb[0] = db.x;
+  in.nb[1] = db.y;
+  in.nb[2] = db.z;
+  in.nb[3] = db.w;
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
-  if (in.valid) {
-    {
-      const unsigned mk = pb.mask[(size_t)d * pb.ne + in.e];
-      in.flags = (int)((mk & 15u) | ((mk >> 7) << 12));  // inflow faces, pivoting needed
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      in.nb[f] = pb.nbr[4 * in.e + f];
-      in.flags |= ((int)pb.nbr_face[4 * in.e + f] & 3) << (4 + 2 * f);
-    }
-  } else {
-#pragma unroll
-    for (int f = 0; f < 4; ++f) in.nb[f] = -1;
-  }
   load_one<P, NQ, T>(in, d, pb, pio, it, r);
   solve_one<P, NQ, T, mode_pivots(MODE), (MODE & MODE_FIX) != 0>(in, d, pb, pio, lds, r, slot,
                                                                                      status);
@@ -2043,47 +2033,36 @@ __device__ __forceinline__ void stage_tables_lu(const T *__restrict__ tables, T 
 // Level-synchronous schedule with the row-set LU (one slot per solve).
 template <int P, int NQ, typename T, bool FIX>
 __global__ void __launch_bounds__(256)
-k_sweep_level_lu(const int2 *__restrict__ solves, int n_solves, const KProb *__restrict__ probs,
+k_sweep_level_lu(const int4 *__restrict__ desc, int n_solves, const KProb *__restrict__ probs,
                  const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
                  int *__restrict__ status) {
   using S = LuShape<P>;
   using LD = LuLds<P, NQ>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
-  if (*stop) return;
-  stage_tables_lu<P, NQ, T>(tables, lds);
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
   const int slot = (threadIdx.x >> 6) * S::SPW + (lane >> 4);
   const int sid = xcd_block(blockIdx.x, gridDim.x) * ((blockDim.x >> 6) * S::SPW) + slot;
   SolveInL<P, NQ, T> in;
   in.valid = sid < n_solves;
-  int d = 0, prob = 0;
-  in.e = 0;
-  in.flags = 0;
+  int4 da = make_int4(0, 0, 0, 0), db = make_int4(-1, -1, -1, -1);
   if (in.valid) {
-    const int2 sv = solves[sid];
-    in.e = sv.x;
-    d = sv.y & 0xffff;
-    prob = sv.y >> 16;
+    da = desc[2 * (size_t)sid];
+    db = desc[2 * (size_t)sid + 1];
   }
+  if (*stop) return;
+  stage_tables_lu<P, NQ, T>(tables, lds);
+  __syncthreads();
+  in.e = da.x;
+  const int d = da.y & 0xffff, prob = da.y >> 16;
+  in.flags = da.z & 0xffff;
+  in.nb[0] = db.x;
+  in.nb[1] = db.y;
+  in.nb[2] = db.z;
+  in.nb[3] = db.w;
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
-  if (in.valid) {
-    {
-      const unsigned mk = pb.mask[(size_t)d * pb.ne + in.e];
-      in.flags = (int)((mk & 15u) | ((mk >> 7) << 12));  // inflow faces, pivoting needed
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      in.nb[f] = pb.nbr[4 * in.e + f];
-      in.flags |= ((int)pb.nbr_face[4 * in.e + f] & 3) << (4 + 2 * f);
-    }
-  } else {
-#pragma unroll
-    for (int f = 0; f < 4; ++f) in.nb[f] = -1;
-  }
   load_one<P, NQ, T>(in, d, pb, pio, it, r);
   solve_one_lu<P, NQ, T, FIX>(in, d, pb, pio, lds, tables + Shape<P, NQ>::A_WV, lds + LD::TAB + (size_t)slot * LD::AREA,
                               r, status);
@@ -2207,16 +2186,13 @@ constexpr int kLuStreamMax = 16;  // solves per slot and launch (one per lane of
 
 template <int P, int NQ, typename T, bool FIX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
-k_sweep_level_lus(const int2 *__restrict__ solves, int n_solves, const KProb *__restrict__ probs,
+k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__restrict__ probs,
                   const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
                   int *__restrict__ status) {
   using S = LuShape<P>;
   using LD = LuLds<P, NQ>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
-  if (*stop) return;
-  stage_tables_lu<P, NQ, T>(tables, lds);
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
   const int slot = (threadIdx.x >> 6) * S::SPW + (lane >> 4);
@@ -2234,33 +2210,24 @@ k_sweep_level_lus(const int2 *__restrict__ solves, int n_solves, const KProb *__
   // descriptors of the slot's solves, in LDS after the slot areas: lane k
   // writes those of the slot's k-th solve (element, direction, flags,
   // neighbours; flags: inflow faces, neighbour faces << 4, pivoting bit 12,
-  // boundary faces << 16)
+  // boundary faces << 16), loaded before the stop flag is read
   int *dtab = reinterpret_cast<int *>(lds + LD::TAB + (size_t)per_block * LD::AREA) + slot * (kLuStreamMax * 8);
+  int4 da = make_int4(0, 0, 0, 0), db = make_int4(-1, -1, -1, -1);
   {
-    int de = 0, dd = 0, dfl = 0, dnb[4] = {-1, -1, -1, -1};
     const long long sid = (long long)sid0 + (long long)r * n_slots;
     if (sid < n_solves) {
-      const int2 sv = solves[sid];
-      de = sv.x;
-      dd = sv.y & 0xffff;
-      const unsigned mk = pb.mask[(size_t)dd * pb.ne + de];
-      const int4 nb4 = *reinterpret_cast<const int4 *>(pb.nbr + 4 * (size_t)de);
-      const unsigned nf = *reinterpret_cast<const unsigned *>(pb.nbr_face + 4 * (size_t)de);
-      dfl = (int)((mk & 15u) | ((mk >> 7) << 12));
-#pragma unroll
-      for (int f = 0; f < 4; ++f) dfl |= (int)((nf >> (8 * f)) & 3u) << (4 + 2 * f);
-      dnb[0] = nb4.x;
-      dnb[1] = nb4.y;
-      dnb[2] = nb4.z;
-      dnb[3] = nb4.w;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) dfl |= (dnb[f] < 0 ? 1 : 0) << (16 + f);
+      da = desc[2 * sid];
+      db = desc[2 * sid + 1];
     }
-    int4 *w = reinterpret_cast<int4 *>(dtab + r * 8);
-    w[0] = make_int4(de, dd, dfl, 0);
-    w[1] = make_int4(dnb[0], dnb[1], dnb[2], dnb[3]);
   }
-  wave_sync_lds();
+  if (*stop) return;
+  stage_tables_lu<P, NQ, T>(tables, lds);
+  {
+    int4 *w = reinterpret_cast<int4 *>(dtab + r * 8);
+    w[0] = make_int4(da.x, da.y & 0xffff, da.z, 0);
+    w[1] = db;
+  }
+  __syncthreads();
   T *area = lds + LD::TAB + (size_t)slot * LD::AREA;
   const T *wv = tables + Shape<P, NQ>::A_WV;
   LuPre<P, NQ, T> nx;
@@ -2366,6 +2333,7 @@ hipError_t launch_level_lu_t(const SweepLaunch &L) {
     if (bytes > L.lds_max) return hipErrorInvalidValue;
     int grid = (L.count + per_block - 1) / per_block;
     if (grid == 0) return hipSuccess;
+    if (!L.desc) return hipErrorInvalidValue;
     const size_t bytes_s = bytes + sizeof(int) * 8 * kLuStreamMax * per_block;  // + the descriptor tables
     if (L.single && L.n_cu > 0 && bytes_s <= L.lds_max) {
       // streaming form: the resident work-groups, and enough of them that a
@@ -2389,11 +2357,11 @@ hipError_t launch_level_lu_t(const SweepLaunch &L) {
       const int lo = (L.count + cap - 1) / cap;
       const int res = per_cu * L.n_cu;
       if (grid > res) grid = res > lo ? res : lo;
-      hipLaunchKernelGGL((k_sweep_level_lus<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes_s, L.stream, L.list,
+      hipLaunchKernelGGL((k_sweep_level_lus<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes_s, L.stream, L.desc,
                          L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
       return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_sweep_level_lu<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes, L.stream, L.list, L.count,
+    hipLaunchKernelGGL((k_sweep_level_lu<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes, L.stream, L.desc, L.count,
                        L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
     return hipGetLastError();
   }
@@ -2677,7 +2645,8 @@ hipError_t launch_level_t(const SweepLaunch &L) {
   const int per_block = (block / 64) * Shape<P, NQ>::SPW;
   const int grid = (L.count + per_block - 1) / per_block;
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_sweep_level<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.list,
+  if (!L.desc) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep_level<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.desc,
                      L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
   return hipGetLastError();
 }
