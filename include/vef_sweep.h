@@ -254,6 +254,12 @@ typedef struct {
                     VEF_KERNEL_*; vef_plan_query: -1 */
   long long n_lagged; /* lagged (direction, element, face) couplings; 0 for
                     acyclic upwind graphs */
+  long long n_pivoting; /* (direction, element) pairs whose local system is
+                    solved with partial pivoting: those the plan cannot
+                    certify for elimination in natural order (sigma_t = 0,
+                    or a curved face along which Omega . n changes sign or
+                    takes the other role's sign); 0 when every face is
+                    straight and sigma_t > 0 */
 } vef_info;
 
 /* Sweep kernels (vef_info.kernel). */

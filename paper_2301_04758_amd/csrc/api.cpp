@@ -980,6 +980,7 @@ int vef_plan_query(const vef_problem_desc *prob, const vef_options *opt, vef_inf
     info->schedule = VEF_SCHEDULE_AUTO;
     info->kernel = -1;
     info->n_lagged = pl.n_lagged;
+    info->n_pivoting = pl.nopivot ? 0 : pl.n_pivoting;
   }
   return VEF_OK;
 }
@@ -999,6 +1000,7 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->schedule = h->schedule;
   info->kernel = mode_of(pl, h->schedule, h->pipeline_waves >= 0, h->fixup);
   info->n_lagged = pl.n_lagged;
+  info->n_pivoting = pl.nopivot ? 0 : pl.n_pivoting;
   return VEF_OK;
 }
 

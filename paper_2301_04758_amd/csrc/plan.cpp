@@ -772,7 +772,10 @@ int build_problem_plan(const vef_problem_desc &d, bool lag_cycles, bool pointwis
             ok = in ? on <= 0.0 : on >= 0.0;
           }
         }
-        if (!ok) mk[e] |= (uint8_t)0x80;
+        if (!ok) {
+          mk[e] |= (uint8_t)0x80;
+          ++o.n_pivoting;
+        }
       }
     }
   }

@@ -55,6 +55,7 @@ struct ProblemPlan {
                                     // upwind local face (30-31); 0 for other faces
   std::vector<uint8_t> lag_mask;    // [n_groups][ne]: bit f set when inflow face f is lagged
   long long n_lagged = 0;           // lagged (direction, element, face) couplings
+  long long n_pivoting = 0;         // (direction, element) pairs not certified for natural-order elimination
   int max_gap = 0;                  // largest level gap of an upwind edge that is not lagged
   int max_width = 1;                // widest level over classes
   bool straight = true;             // every face of the mesh is a straight segment

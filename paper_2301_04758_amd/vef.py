@@ -85,7 +85,8 @@ class vef_moment_io(C.Structure):
 class vef_info(C.Structure):
     _fields_ = [("n", C.c_int), ("nq", C.c_int), ("Q", C.c_int), ("n_bf", C.c_int), ("n_levels", C.c_int),
                 ("n_groups", C.c_int), ("pivoting", C.c_int), ("affine", C.c_int), ("n_solves", C.c_longlong),
-                ("schedule", C.c_int), ("kernel", C.c_int), ("n_lagged", C.c_longlong)]
+                ("schedule", C.c_int), ("kernel", C.c_int), ("n_lagged", C.c_longlong),
+                ("n_pivoting", C.c_longlong)]
 
 
 def _load():

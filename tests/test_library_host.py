@@ -75,6 +75,48 @@ def test_pivoting_choice():
     assert vef.vef_plan_query(q)["pivoting"] == 0
 
 
+def _certification_count(pr):
+    """Pairs (direction, element) whose local system the plan may not eliminate
+    in natural order, counted from the independent numpy geometry: sigma_t = 0,
+    or a face quadrature point where Omega . n ds has the sign of the other
+    role (inflow faces need <= 0, outflow faces >= 0)."""
+    import dg_numpy as D
+    mesh = D.Mesh(pr)
+    faces = {(e, f): mesh.face_data(e, f)[3] for e in range(pr.n_elem) for f in range(4)}
+    n = 0
+    for om in np.asarray(pr.omega):
+        for e in range(pr.n_elem):
+            ok = pr.sigma_t[e] > 0.0
+            for f in range(4):
+                on = faces[(e, f)] @ om
+                inflow = not mesh.upwind_is_self(e, f, om)
+                ok = ok and bool(np.all(on <= 0.0) if inflow else np.all(on >= 0.0))
+            n += 0 if ok else 1
+    return n
+
+
+def test_pivoting_certification_counts():
+    """vef_info.n_pivoting against a count from the definition, on straight,
+    curved and sigma_t = 0 inputs."""
+    import copy
+    vef = _vef()
+    (pr,), _ = P.make_config("c1")
+    assert vef.vef_plan_query(pr)["n_pivoting"] == 0
+    q = copy.deepcopy(pr)
+    q.sigma_t = q.sigma_t.copy()
+    q.sigma_t[5] = 0.0
+    assert vef.vef_plan_query(q)["n_pivoting"] == q.n_dir == _certification_count(q)
+    for warp, N in ((0.12, 8), (0.2, 12)):
+        cp, ec = P.quad_mesh(10, 9, 2)
+        cp = P.sine_warp(cp, warp)
+        om, wt = P.level_symmetric_2d(N)
+        c = P.Problem("warp", 3, 2, cp, ec, om, wt, np.ones(90), np.zeros(90), nx=10, ny=9)
+        got = vef.vef_plan_query(c)["n_pivoting"]
+        want = _certification_count(c)
+        assert got == want, (warp, N, got, want)
+        assert 0 < got < c.n_elem * c.n_dir
+
+
 def _bad(pr, code):
     vef = _vef()
     with pytest.raises(vef.VefError) as ei:
