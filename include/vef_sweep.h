@@ -472,6 +472,9 @@ typedef struct {
   int schedule;       /* chosen: VEF_LEVEL_SYNC, VEF_DIR_RESIDENT or VEF_PERSISTENT */
   int pipeline_waves; /* chosen waves of the pipelined kernel; -1 = row-per-lane kernel */
   int block;          /* chosen work-group size of the level-synchronous kernels */
+  int elem_matrices;  /* for problems built with element matrices (vef_options.
+                         elem_matrices): 1 = the element-matrix kernel was
+                         chosen, 0 = the quadrature kernel; -1 = no such problem */
   int n_candidates;   /* configurations timed */
   double best_ms;     /* one run of the given arguments with the choice (mean of reps) */
   double before_ms;   /* the same with the configuration the handle had before */
@@ -482,7 +485,9 @@ typedef struct {
  * level-synchronous kernels with 128 or 256 threads per work-group, the
  * direction-resident row-per-lane kernel, the persistent schedule (when some
  * variant has a persistent kernel) and (when some problem has affine
- * elements of degree <= 2) the pipelined kernel with 8, 6 or 4 waves.  Each
+ * elements of degree <= 2) the pipelined kernel with 8, 6 or 4 waves; where
+ * a problem was built with element matrices (Sec. 3.2, formed on the matrix
+ * cores), each schedule also with the quadrature-assembly kernel instead.  Each
  * candidate runs once untimed and then reps (1..1000) times between HIP
  * events on stream; the fastest is kept by the handle for later runs when it
  * beats the handle's configuration before the call by more than 2% (else

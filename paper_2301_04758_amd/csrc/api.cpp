@@ -68,6 +68,12 @@ bool affine_tables(int mode) { return mode >= 2 && mode <= 5; }
 // Modes with a persistent kernel (no fixup variant).
 bool flow_mode(int mode, int fixup) { return !fixup && (mode == 0 || mode == 1 || mode == 5 || mode == 6); }
 
+// Kernel mode a launch of variant mode `mode` runs with: problems built for
+// the element-matrix kernel (6) take the quadrature kernel with per-solve
+// pivoting (0) when the handle's autotuner chose it; the two use the same
+// lists, tables and slot shape.
+int launch_mode(bool mat_quadrature, int mode) { return (mode == 6 && mat_quadrature) ? 0 : mode; }
+
 // Solves per round of one wave of a kernel mode: 16-lane slots for the
 // row-set LU, otherwise the power-of-two slot >= n of the row-per-lane kernels.
 int solves_per_round(int mode, int n) {
@@ -129,6 +135,7 @@ struct vef_sweep {
   int *d_flags = nullptr;  // [0] stop, [1] iterations done, [2] status
   long long wait_polls = 1LL << 26;  // bound of one device-side wait (polls)
   bool elem_matrices = true;         // precomputed element matrices where available
+  bool mat_quadrature = false;       // run-time choice (autotune): their problems take the quadrature kernel
   double *static_resid = nullptr;    // this device's copy of `scratch` (vef_sweep_run_static)
   hipStream_t last_stream = nullptr;
   bool timing = false;
@@ -820,7 +827,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
       for (auto &F : h->flow) {
         SL.p = F.v.p;
         SL.nq = F.v.nq;
-        SL.mode = F.v.mode;
+        SL.mode = launch_mode(h->mat_quadrature, F.v.mode);
         SL.flow = true;
         SL.list = h->d_solves;
         SL.tasks = h->d_flow_tasks + F.off;
@@ -844,7 +851,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
           if (persistent && L.flow) continue;  // in a persistent launch
           SL.p = L.v.p;
           SL.nq = L.v.nq;
-          SL.mode = L.v.mode;
+          SL.mode = launch_mode(h->mat_quadrature, L.v.mode);
           SL.list = h->d_solves + L.off;
           SL.desc = h->d_solve_desc + 2 * (size_t)L.off;
           SL.count = L.cnt;
@@ -857,7 +864,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
       for (auto &D : (h->pipeline_waves >= 0 ? h->dir_pipe : h->dir_rows)) {
         SL.p = D.v.p;
         SL.nq = D.v.nq;
-        SL.mode = D.v.mode;
+        SL.mode = launch_mode(h->mat_quadrature, D.v.mode);
         SL.list = h->d_dir_tasks + D.off;
         SL.count = D.cnt;
         SL.width = D.width;
@@ -998,7 +1005,7 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->affine = pl.affine ? 1 : 0;
   info->n_solves = (long long)pl.ne * pl.nd;
   info->schedule = h->schedule;
-  info->kernel = mode_of(pl, h->schedule, h->pipeline_waves >= 0, h->fixup);
+  info->kernel = launch_mode(h->mat_quadrature, mode_of(pl, h->schedule, h->pipeline_waves >= 0, h->fixup));
   info->n_lagged = pl.n_lagged;
   info->n_pivoting = pl.nopivot ? 0 : pl.n_pivoting;
   return VEF_OK;
@@ -1102,13 +1109,17 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
   hipStream_t s = static_cast<hipStream_t>(stream);
   struct Cand {
     int schedule, waves, block;
-    bool operator==(const Cand &o) const { return schedule == o.schedule && waves == o.waves && block == o.block; }
+    bool quad;  // problems with element matrices take the quadrature kernel
+    bool operator==(const Cand &o) const {
+      return schedule == o.schedule && waves == o.waves && block == o.block && quad == o.quad;
+    }
   };
-  const Cand before{h->schedule, h->pipeline_waves, h->block};
-  bool any_pipe = false;
+  const Cand before{h->schedule, h->pipeline_waves, h->block, h->mat_quadrature};
+  bool any_pipe = false, any_mat = false;
   for (auto &pl : h->plans) {
     const int md = mode_of(pl, VEF_DIR_RESIDENT, true, h->fixup);
     any_pipe |= md == 3 || md == 4;
+    any_mat |= pl.elem_mat;
   }
   std::vector<Cand> cands{before};
   auto add = [&](Cand c) {
@@ -1116,12 +1127,17 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
       if (x == c) return;
     cands.push_back(c);
   };
-  add({VEF_LEVEL_SYNC, before.waves, 256});
-  add({VEF_LEVEL_SYNC, before.waves, 128});
-  add({VEF_DIR_RESIDENT, -1, before.block});
-  if (!h->flow.empty()) add({VEF_PERSISTENT, before.waves, 256});
+  for (bool quad : {false, true}) {
+    // the element-matrix kernel against quadrature assembly (matrix cores
+    // against the vector units) where some problem has both
+    if (quad && !any_mat) continue;
+    add({VEF_LEVEL_SYNC, before.waves, 256, quad});
+    add({VEF_LEVEL_SYNC, before.waves, 128, quad});
+    add({VEF_DIR_RESIDENT, -1, before.block, quad});
+    if (!h->flow.empty()) add({VEF_PERSISTENT, before.waves, 256, quad});
+  }
   if (any_pipe)
-    for (int w : {8, 6, 4}) add({VEF_DIR_RESIDENT, w, before.block});
+    for (int w : {8, 6, 4}) add({VEF_DIR_RESIDENT, w, before.block, before.quad});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
@@ -1133,6 +1149,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     h->schedule = c.schedule;
     h->pipeline_waves = c.waves;
     h->block = c.block;
+    h->mat_quadrature = c.quad;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
@@ -1143,6 +1160,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     h->schedule = c.schedule;
     h->pipeline_waves = c.waves;
     h->block = c.block;
+    h->mat_quadrature = c.quad;
     int rc = vef_sweep_run(h, a, stream);  // warm-up (uploads, first-touch)
     if (rc == VEF_OK && (he = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(h, he, "record tuning event");
     for (int r = 0; r < reps && rc == VEF_OK; ++r) rc = vef_sweep_run(h, a, stream);
@@ -1169,6 +1187,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     out->schedule = bestc.schedule;
     out->pipeline_waves = bestc.waves;
     out->block = bestc.block;
+    out->elem_matrices = any_mat ? (bestc.quad ? 0 : 1) : -1;
     out->n_candidates = (int)cands.size();
     out->best_ms = best;
     out->before_ms = before_ms;

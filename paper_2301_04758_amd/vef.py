@@ -270,8 +270,9 @@ def vef_sweep_timing(h: int):
 
 
 class vef_tune_result(C.Structure):
-    _fields_ = [("schedule", C.c_int), ("pipeline_waves", C.c_int), ("block", C.c_int), ("n_candidates", C.c_int),
-                ("best_ms", C.c_double), ("before_ms", C.c_double)]
+    _fields_ = [("schedule", C.c_int), ("pipeline_waves", C.c_int), ("block", C.c_int),
+                ("elem_matrices", C.c_int), ("n_candidates", C.c_int), ("best_ms", C.c_double),
+                ("before_ms", C.c_double)]
 
 
 def vef_sweep_autotune(h: int, io: Sequence[dict], n_iter: int = 1, reps: int = 3, stream=None) -> dict:

@@ -130,3 +130,27 @@ def test_c3_sized_elem_matrices_agree_with_fixture(torch):
     scale = g["mom_absmax"][0]
     for k in range(6):
         assert np.abs(flat[k, idx] - np.asarray(g["mom"][k])).max() / scale <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_weighs_element_matrices_against_quadrature(torch, precision):
+    """The autotuner times every schedule with the element-matrix kernel and
+    with the quadrature kernel; the handle then runs what it reports, and
+    stays at the bar against the oracle."""
+    from paper_2301_04758_amd import vef
+    pr, phi = _curved_case(seed=5)
+    ref = O.sweep(pr, phi_in=phi)
+    print("autotune elem_mat", precision, flush=True)
+    sw = vef.Sweep([pr], precision=precision)
+    io = sw.buffers(n_iter=1, phi_in=phi)
+    res = sw.autotune(io, n_iter=1, reps=2)
+    assert res["elem_matrices"] in (0, 1)
+    assert res["n_candidates"] >= 7  # level x 2 blocks, dir, persistent; each with both assemblies
+    kernel = vef.KERNEL_NAMES[sw.info[0]["kernel"]]
+    assert (kernel == "general_mat") == (res["elem_matrices"] == 1), (kernel, res)
+    sw.run(io, n_iter=1)
+    torch.cuda.synchronize()
+    sw.check()
+    psi = io[0]["psi_out"].double().cpu().numpy()
+    sw.close()
+    assert rel_inf(psi, ref["psi"]) <= TOL[precision]
