@@ -195,11 +195,15 @@ def kernel_name(g, pr, dtype="double", single=True):
     nq = pr.nq or pr.p + pr.m
     if g["schedule"] == "dir_resident" and g["kernel"] in (3, 4):
         return "k_sweep_pipe<%d, %d, %s, false, %s>" % (pr.p, nq, dtype, "true" if g["kernel"] == 4 else "false")
-    if g["kernel"] == 5:
+    if g["kernel"] in (5, 7):
         level = "level_lus" if single else "level_lu"
         kind = {"dir_resident": "dir_lu", "persistent": "flow", "level_sync": level}[g["schedule"]]
         if kind == "flow":
             return "k_sweep_flow<%d, %d, %s, 5>" % (pr.p, nq, dtype)
+        if kind == "level_lus":
+            # last template argument: solves by the class inverses
+            return "k_sweep_level_lus<%d, %d, %s, false, %s>" % (pr.p, nq, dtype,
+                                                                 "true" if g["kernel"] == 7 else "false")
         return "k_sweep_%s<%d, %d, %s, false>" % (kind, pr.p, nq, dtype)
     kind = {"dir_resident": "dir", "persistent": "flow", "level_sync": "level"}[g["schedule"]]
     return "k_sweep_%s<%d, %d, %s, %d>" % (kind, pr.p, nq, dtype, g["kernel"])

@@ -188,6 +188,21 @@ typedef struct {
                     (VEF_KERNEL_GENERAL_MAT); -1 = assemble every local system
                     by quadrature (VEF_KERNEL_PIVOT / VEF_KERNEL_NOPIVOT).
                     Costs 6 KB (double) or 3 KB (float) per element. */
+  int shared_matrices; /* affine elements of degree 3 or 4, one problem per
+                    handle: 0 (default) = where many (direction, element)
+                    pairs have the same local matrix (same sigma_t, same
+                    affine geometry, same direction, hence the same outflow
+                    faces; a uniform grid with few materials), group them into
+                    classes at create, and in every run invert one matrix per
+                    class (double, Gauss-Jordan with partial pivoting) before
+                    the first sweep; the level-synchronous sweep then solves
+                    each local system as a product with its class's inverse
+                    (VEF_KERNEL_AFFINE_SHARED).  Used when there are at most
+                    4096 element classes, the solves number at least 8 per
+                    class and the inverses take at most 8 MiB.  The
+                    local systems and their right-hand sides are the same;
+                    results differ from the row-set LU only by rounding.
+                    -1 = never (VEF_KERNEL_AFFINE_LU). */
 } vef_options;
 
 /* Per-problem device buffers of one run (device pointers owned by the caller).
@@ -260,6 +275,11 @@ typedef struct {
                     or a curved face along which Omega . n changes sign or
                     takes the other role's sign); 0 when every face is
                     straight and sigma_t > 0 */
+  int n_classes;    /* vef_problem_info: classes of (direction, element)
+                    pairs sharing one local matrix (vef_options.
+                    shared_matrices), 0 when the problem has none;
+                    vef_plan_query: those a one-problem handle created
+                    with the same options would form */
 } vef_info;
 
 /* Sweep kernels (vef_info.kernel). */
@@ -279,6 +299,11 @@ typedef struct {
                                        from precomputed element matrices;
                                        LU in natural order where the plan
                                        certifies it, else partial pivoting */
+#define VEF_KERNEL_AFFINE_SHARED 7   /* affine, p >= 3, level-synchronous: a
+                                       16-lane slot per solve assembles the
+                                       right-hand side and multiplies it by
+                                       the inverse of the local matrix its
+                                       class shares */
 
 /* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
  * upwind graphs unless opt->cycles lags them), build the sweep plan on the host and upload it to the
@@ -475,6 +500,10 @@ typedef struct {
   int elem_matrices;  /* for problems built with element matrices (vef_options.
                          elem_matrices): 1 = the element-matrix kernel was
                          chosen, 0 = the quadrature kernel; -1 = no such problem */
+  int shared_matrices; /* for a problem with classes of shared local matrices
+                         (vef_info.n_classes > 0): 1 = solves by the class
+                         inverses were chosen, 0 = the row-set LU; -1 = no
+                         such problem */
   int n_candidates;   /* configurations timed */
   double best_ms;     /* one run of the given arguments with the choice (mean of reps) */
   double before_ms;   /* the same with the configuration the handle had before */
@@ -487,7 +516,9 @@ typedef struct {
  * variant has a persistent kernel) and (when some problem has affine
  * elements of degree <= 2) the pipelined kernel with 8, 6 or 4 waves; where
  * a problem was built with element matrices (Sec. 3.2, formed on the matrix
- * cores), each schedule also with the quadrature-assembly kernel instead.  Each
+ * cores), each schedule also with the quadrature-assembly kernel instead;
+ * where a problem has classes of shared local matrices, the level-synchronous
+ * kernels also with the row-set LU instead of the class inverses.  Each
  * candidate runs once untimed and then reps (1..1000) times between HIP
  * events on stream; the fastest is kept by the handle for later runs when it
  * beats the handle's configuration before the call by more than 2% (else

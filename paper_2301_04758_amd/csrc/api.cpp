@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -136,6 +137,11 @@ struct vef_sweep {
   long long wait_polls = 1LL << 26;  // bound of one device-side wait (polls)
   bool elem_matrices = true;         // precomputed element matrices where available
   bool mat_quadrature = false;       // run-time choice (autotune): their problems take the quadrature kernel
+  bool shared_matrices = true;       // classes of shared local matrices where a problem has them
+  bool shared_lu = false;            // run-time choice (autotune): the row-set LU instead of the class inverses
+  int n_cls = 0;                     // classes of shared local matrices of problem 0 (0: none)
+  int4 *d_cls_rep = nullptr;         // [n_cls] representative (element, direction, inflow faces, 0)
+  void *d_cls_inv = nullptr;         // T [n_cls][n][16][RS] class inverses (written by every run)
   double *static_resid = nullptr;    // this device's copy of `scratch` (vef_sweep_run_static)
   hipStream_t last_stream = nullptr;
   bool timing = false;
@@ -255,6 +261,55 @@ std::vector<double> table_blob(const vefplan::Tables &t) {
   return b;
 }
 
+// Classes of (direction, element) pairs that share one local matrix (row-set
+// LU problems): on affine elements the matrix depends only on sigma_t, the
+// element's J, adj(F) and face chords, the direction and which faces are
+// inflow.  Element classes group equal bit patterns of the first four;
+// solve classes add the direction and the inflow faces.
+struct SharedClasses {
+  int nd = 0, n_cls = 0;
+  std::vector<int> ecls;  // [ne] element class
+  std::vector<int> tab;   // [n_ecls][nd][16] solve class, or -1
+  std::vector<int4> rep;  // [n_cls] (element, direction, inflow faces, 0)
+  int of(const vefplan::ProblemPlan &pl, int e, int d) const {
+    return tab[((size_t)ecls[e] * nd + d) * 16 + (pl.mask[(size_t)d * pl.ne + e] & 15u)];
+  }
+};
+
+constexpr int kMaxElemClasses = 4096;
+constexpr int kMinSolvesPerClass = 8;
+constexpr size_t kMaxClassInvBytes = size_t(8) << 20;
+
+// True when the problem has few enough classes for the class inverses to pay.
+bool find_shared_classes(const vefplan::ProblemPlan &pl, size_t inv_bytes, SharedClasses &sc) {
+  if (!pl.affine || pl.geo_a.size() != (size_t)pl.ne * 16) return false;
+  std::map<std::array<uint64_t, 14>, int> keys;
+  sc.ecls.assign(pl.ne, 0);
+  for (int e = 0; e < pl.ne; ++e) {
+    std::array<uint64_t, 14> k;
+    std::memcpy(&k[0], &pl.sigma_t[e], sizeof(double));
+    std::memcpy(&k[1], &pl.geo_a[(size_t)e * 16], 13 * sizeof(double));
+    auto it = keys.emplace(k, (int)keys.size()).first;
+    sc.ecls[e] = it->second;
+    if ((int)keys.size() > kMaxElemClasses) return false;
+  }
+  if (keys.size() * (size_t)pl.nd * 16 > (size_t(1) << 24)) return false;
+  sc.nd = pl.nd;
+  sc.tab.assign(keys.size() * pl.nd * 16, -1);
+  sc.rep.clear();
+  for (int d = 0; d < pl.nd; ++d)
+    for (int e = 0; e < pl.ne; ++e) {
+      const unsigned m = pl.mask[(size_t)d * pl.ne + e] & 15u;
+      int &c = sc.tab[((size_t)sc.ecls[e] * pl.nd + d) * 16 + m];
+      if (c >= 0) continue;
+      c = (int)sc.rep.size();
+      sc.rep.push_back(make_int4(e, d, (int)m, 0));
+    }
+  sc.n_cls = (int)sc.rep.size();
+  return (long long)sc.n_cls * kMinSolvesPerClass <= (long long)pl.ne * pl.nd &&
+         (size_t)sc.n_cls * inv_bytes <= kMaxClassInvBytes;
+}
+
 int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *opt, vef_sweep *h) {
   if (opt) {
     if (opt->precision != VEF_FP64 && opt->precision != VEF_FP32_LOCAL)
@@ -290,6 +345,9 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     if (opt->elem_matrices != 0 && opt->elem_matrices != -1)
       return set_err(h, VEF_ERR_INVALID, "elem_matrices must be 0 or -1");
     h->elem_matrices = opt->elem_matrices == 0;
+    if (opt->shared_matrices != 0 && opt->shared_matrices != -1)
+      return set_err(h, VEF_ERR_INVALID, "shared_matrices must be 0 or -1");
+    h->shared_matrices = opt->shared_matrices == 0;
     h->block = opt->block ? opt->block : 256;
     if (h->block > 256) h->block = 256;  // kernels are built for at most 256 threads
   }
@@ -328,6 +386,22 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     he = upload(h, &ts.dev_d, blob.data(), blob.size());
     if (he != hipSuccess) return hip_fail(h, he, "upload tables");
     h->tables[key] = ts;
+  }
+
+  // classes of shared local matrices (one-problem handles, row-set LU)
+  SharedClasses shared;
+  if (h->shared_matrices && n_probs == 1 && mode_of(h->plans[0], VEF_LEVEL_SYNC) == 5) {
+    const auto &pl = h->plans[0];
+    const int rs = (pl.n + 15) / 16;
+    const size_t inv_bytes = (size_t)pl.n * 16 * rs * (fp32 ? sizeof(float) : sizeof(double));
+    if (find_shared_classes(pl, inv_bytes, shared)) {
+      h->n_cls = shared.n_cls;
+      he = upload(h, &h->d_cls_rep, shared.rep.data(), shared.rep.size());
+      if (he == hipSuccess)
+        he = fp32 ? dev_alloc(h, reinterpret_cast<float **>(&h->d_cls_inv), (size_t)h->n_cls * pl.n * 16 * rs)
+                  : dev_alloc(h, reinterpret_cast<double **>(&h->d_cls_inv), (size_t)h->n_cls * pl.n * 16 * rs);
+      if (he != hipSuccess) return hip_fail(h, he, "allocate class inverses");
+    }
   }
 
   // per-problem constant data
@@ -423,6 +497,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       if (he != hipSuccess) return hip_fail(h, he, "element matrices");
       kp.emat = em;
     }
+    kp.cls_inv = h->n_cls > 0 ? h->d_cls_inv : nullptr;
     h->h_probs[k] = kp;
   }
   he = upload(h, &h->d_probs, h->h_probs.data(), h->h_probs.size());
@@ -504,6 +579,11 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   auto flow_ok = [&](const vefplan::ProblemPlan &pl, const Variant &v) {
     return flow_mode(v.mode, h->fixup) && pl.n_lagged == 0;
   };
+  // The solves of a (problem, class, level) block are listed element by
+  // element (an element's directions together: they share its data), or,
+  // on a handle with shared local matrices, direction by direction
+  // (consecutive slots then read the same class inverse).
+  const bool dir_major = h->n_cls > 0;
   // per level and variant, two level-synchronous launches: the problems the
   // persistent schedule covers, then the others
   for (int L = 0; L < max_levels; ++L)
@@ -519,8 +599,13 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
           const int *lo = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
           const int32_t *ord = &pl.order[(size_t)g * pl.ne];
           const int b0 = (int)solves.size();
-          for (int t = lo[L]; t < lo[L + 1]; ++t)
-            for (int d : dirs_of[k][g]) solves.push_back(make_int2(ord[t], d | (k << 16)));
+          if (dir_major) {
+            for (int d : dirs_of[k][g])
+              for (int t = lo[L]; t < lo[L + 1]; ++t) solves.push_back(make_int2(ord[t], d | (k << 16)));
+          } else {
+            for (int t = lo[L]; t < lo[L + 1]; ++t)
+              for (int d : dirs_of[k][g]) solves.push_back(make_int2(ord[t], d | (k << 16)));
+          }
           const int b1 = (int)solves.size();
           if (flow_ok(pl, var) && b1 > b0) {
             const int blk = blk_first[k] + g * pl.n_levels + L;
@@ -549,7 +634,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     // descriptors of the level lists' solves, so that a level launch reads
     // one record per solve instead of the list and then the element's masks
     // and neighbours: flags = inflow faces | neighbour faces << 4 |
-    // pivoting needed << 12 | boundary faces << 16
+    // pivoting needed << 12 | boundary faces << 16; then the solve's class
+    // of shared local matrices
     std::vector<int4> desc(2 * solves.size());
     for (size_t i = 0; i < solves.size(); ++i) {
       const int e = solves[i].x, d = solves[i].y & 0xffff, k = solves[i].y >> 16;
@@ -562,7 +648,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         fl |= ((int)pl.nbr_face[4 * (size_t)e + f] & 3) << (4 + 2 * f);
         fl |= (nb[f] < 0 ? 1 : 0) << (16 + f);
       }
-      desc[2 * i] = make_int4(e, solves[i].y, fl, 0);
+      desc[2 * i] = make_int4(e, solves[i].y, fl, h->n_cls > 0 ? shared.of(pl, e, d) : 0);
       desc[2 * i + 1] = make_int4(nb[0], nb[1], nb[2], nb[3]);
     }
     he = upload(h, &h->d_solve_desc, desc.data(), desc.size());
@@ -600,17 +686,21 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         const auto &pl = h->plans[k];
         const int g = (blk - blk_first[k]) / pl.n_levels;
         const int nd_g = (int)dirs_of[k][g].size();
+        const int *lo_g = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
+        const int Lb = (blk - blk_first[k]) % pl.n_levels;
+        const int wb = lo_g[Lb + 1] - lo_g[Lb];  // elements of the task's level
         pre.clear();
         for (int x = tk.x; x < tk.x + tk.y; ++x) {
           const int e = solves[x].x, d = solves[x].y & 0xffff;
-          const int di = (x - blk_solve0[blk]) % nd_g;
+          const int di = dir_major ? (x - blk_solve0[blk]) / wb : (x - blk_solve0[blk]) % nd_g;
           const unsigned inflow = pl.mask[(size_t)d * pl.ne + e] & 15u;
           for (int f = 0; f < 4; ++f) {
             const int u = pl.nbr[4 * (size_t)e + f];
             if (!((inflow >> f) & 1u) || u < 0) continue;
             const int Lu = pl.level[(size_t)g * pl.ne + u];
             const int bu = blk_first[k] + g * pl.n_levels + Lu;
-            const int pos = rank[k][(size_t)g * pl.ne + u] * nd_g + di;
+            const int ru = rank[k][(size_t)g * pl.ne + u];
+            const int pos = dir_major ? di * (lo_g[Lu + 1] - lo_g[Lu]) + ru : ru * nd_g + di;
             const int pt = base + blk_task0[bu] + pos / tsz;
             if (std::find(pre.begin(), pre.end(), pt) == pre.end()) pre.push_back(pt);
           }
@@ -799,6 +889,9 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
   he = vefk::launch_run_init(h->d_io, np, a->n_iter, stop, iters, status, s);
   if (he != hipSuccess) return hip_fail(h, he, "launch init");
   const bool persistent = h->schedule == VEF_PERSISTENT;
+  // level-synchronous row-set LU launches solve with the class inverses,
+  // which every run forms before its first sweep
+  const bool use_cls = h->n_cls > 0 && !h->shared_lu && h->schedule == VEF_LEVEL_SYNC;
   if (persistent && !h->flow.empty()) {
     // task flags and the abort flag start from zero in every run
     he = vefk::launch_zero_ints(h->d_flow_flags, h->n_flow_tasks + 1, s);
@@ -823,6 +916,23 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
     SL.wait_spins = h->wait_polls;
     SL.n_cu = h->n_cu;
     SL.single = h->h_probs.size() == 1;
+    if (use_cls && it == 0) {
+      const auto &pl = h->plans[0];
+      vefk::ClassInvLaunch C{};
+      C.p = pl.p;
+      C.nq = pl.nq;
+      C.fp32 = fp32;
+      C.n_cls = h->n_cls;
+      C.rep = h->d_cls_rep;
+      C.probs = h->d_probs;
+      C.tables = h->tables[std::make_pair(pl.p, pl.nq)].dev_A;
+      C.out = h->d_cls_inv;
+      C.status = status;
+      C.stream = s;
+      he = vefk::launch_class_inv(C);
+      if (he != hipSuccess) return hip_fail(h, he, "launch class inverses");
+      if (timed(it)) h->timed_launches++;
+    }
     if (persistent) {
       for (auto &F : h->flow) {
         SL.p = F.v.p;
@@ -852,6 +962,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
           SL.p = L.v.p;
           SL.nq = L.v.nq;
           SL.mode = launch_mode(h->mat_quadrature, L.v.mode);
+          SL.shared = use_cls && L.v.mode == 5;
           SL.list = h->d_solves + L.off;
           SL.desc = h->d_solve_desc + 2 * (size_t)L.off;
           SL.count = L.cnt;
@@ -988,6 +1099,17 @@ int vef_plan_query(const vef_problem_desc *prob, const vef_options *opt, vef_inf
     info->kernel = -1;
     info->n_lagged = pl.n_lagged;
     info->n_pivoting = pl.nopivot ? 0 : pl.n_pivoting;
+    info->n_classes = 0;
+    if ((!opt || opt->shared_matrices == 0) && mode_of(pl, VEF_LEVEL_SYNC) == 5) {
+      const bool fp32 = opt && opt->precision == VEF_FP32_LOCAL;
+      const size_t inv_bytes = (size_t)pl.n * 16 * ((pl.n + 15) / 16) * (fp32 ? sizeof(float) : sizeof(double));
+      SharedClasses sc;
+      try {
+        if (find_shared_classes(pl, inv_bytes, sc)) info->n_classes = sc.n_cls;
+      } catch (const std::bad_alloc &) {
+        return set_err(nullptr, VEF_ERR_OOM, "host allocation failed");
+      }
+    }
   }
   return VEF_OK;
 }
@@ -1006,8 +1128,11 @@ int vef_problem_info(const vef_sweep_t *h, int k, vef_info *info) {
   info->n_solves = (long long)pl.ne * pl.nd;
   info->schedule = h->schedule;
   info->kernel = launch_mode(h->mat_quadrature, mode_of(pl, h->schedule, h->pipeline_waves >= 0, h->fixup));
+  if (info->kernel == VEF_KERNEL_AFFINE_LU && h->n_cls > 0 && !h->shared_lu && h->schedule == VEF_LEVEL_SYNC)
+    info->kernel = VEF_KERNEL_AFFINE_SHARED;
   info->n_lagged = pl.n_lagged;
   info->n_pivoting = pl.nopivot ? 0 : pl.n_pivoting;
+  info->n_classes = h->n_cls;
   return VEF_OK;
 }
 
@@ -1110,11 +1235,12 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
   struct Cand {
     int schedule, waves, block;
     bool quad;  // problems with element matrices take the quadrature kernel
+    bool lu;    // problems with shared local matrices take the row-set LU
     bool operator==(const Cand &o) const {
-      return schedule == o.schedule && waves == o.waves && block == o.block && quad == o.quad;
+      return schedule == o.schedule && waves == o.waves && block == o.block && quad == o.quad && lu == o.lu;
     }
   };
-  const Cand before{h->schedule, h->pipeline_waves, h->block, h->mat_quadrature};
+  const Cand before{h->schedule, h->pipeline_waves, h->block, h->mat_quadrature, h->shared_lu};
   bool any_pipe = false, any_mat = false;
   for (auto &pl : h->plans) {
     const int md = mode_of(pl, VEF_DIR_RESIDENT, true, h->fixup);
@@ -1131,13 +1257,17 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     // the element-matrix kernel against quadrature assembly (matrix cores
     // against the vector units) where some problem has both
     if (quad && !any_mat) continue;
-    add({VEF_LEVEL_SYNC, before.waves, 256, quad});
-    add({VEF_LEVEL_SYNC, before.waves, 128, quad});
-    add({VEF_DIR_RESIDENT, -1, before.block, quad});
-    if (!h->flow.empty()) add({VEF_PERSISTENT, before.waves, 256, quad});
+    // class inverses against the row-set LU (level-synchronous only)
+    for (bool lu : {false, true}) {
+      if (lu && h->n_cls == 0) continue;
+      add({VEF_LEVEL_SYNC, before.waves, 256, quad, lu});
+      add({VEF_LEVEL_SYNC, before.waves, 128, quad, lu});
+    }
+    add({VEF_DIR_RESIDENT, -1, before.block, quad, before.lu});
+    if (!h->flow.empty()) add({VEF_PERSISTENT, before.waves, 256, quad, before.lu});
   }
   if (any_pipe)
-    for (int w : {8, 6, 4}) add({VEF_DIR_RESIDENT, w, before.block, before.quad});
+    for (int w : {8, 6, 4}) add({VEF_DIR_RESIDENT, w, before.block, before.quad, before.lu});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
@@ -1150,6 +1280,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     h->pipeline_waves = c.waves;
     h->block = c.block;
     h->mat_quadrature = c.quad;
+    h->shared_lu = c.lu;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
@@ -1161,6 +1292,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     h->pipeline_waves = c.waves;
     h->block = c.block;
     h->mat_quadrature = c.quad;
+    h->shared_lu = c.lu;
     int rc = vef_sweep_run(h, a, stream);  // warm-up (uploads, first-touch)
     if (rc == VEF_OK && (he = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(h, he, "record tuning event");
     for (int r = 0; r < reps && rc == VEF_OK; ++r) rc = vef_sweep_run(h, a, stream);
@@ -1188,6 +1320,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     out->pipeline_waves = bestc.waves;
     out->block = bestc.block;
     out->elem_matrices = any_mat ? (bestc.quad ? 0 : 1) : -1;
+    out->shared_matrices = h->n_cls > 0 ? (bestc.lu || bestc.schedule != VEF_LEVEL_SYNC ? 0 : 1) : -1;
     out->n_candidates = (int)cands.size();
     out->best_ms = best;
     out->before_ms = before_ms;

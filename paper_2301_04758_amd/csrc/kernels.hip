@@ -261,6 +261,17 @@ static hipError_t launch_sweep(const SweepLaunch &L, bool dir) {
   }
 }
 
+hipError_t launch_class_inv_p3(const ClassInvLaunch &C);
+hipError_t launch_class_inv_p4(const ClassInvLaunch &C);
+
+hipError_t launch_class_inv(const ClassInvLaunch &C) {
+  switch (C.p) {
+    case 3: return launch_class_inv_p3(C);
+    case 4: return launch_class_inv_p4(C);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_sweep_level(const SweepLaunch &L) { return launch_sweep(L, false); }
 hipError_t launch_sweep_dir(const SweepLaunch &L) { return launch_sweep(L, true); }
 

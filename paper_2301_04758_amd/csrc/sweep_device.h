@@ -1784,18 +1784,55 @@ __device__ __forceinline__ void load_one(SolveInL<P, NQ, T> &in, int d, const KP
   }
 }
 
+// Row rr = node (a, b) of an affine element's local matrix (test index
+// first), without the right-hand side: A[(a,b)][(c,d)] = m_bd (stJ m_ac -
+// gx gd_ac) - gd_bd (gy m_ac), plus (Omega . N_f) m_{pos,c} at face node c of
+// each outflow face f (bit f of inflow clear) through (a, b), pos the node's
+// position on that face.  m, gd: the 1D mass and derivative tables.
+template <int P, typename T>
+__device__ __forceinline__ void affine_lu_row(T *row, int rr, const T *m1, const T *gdt, T stJ, T gx, T gy,
+                                              const T (&on)[4], unsigned inflow) {
+  constexpr int P1 = P + 1;
+  const int a = rr % P1, b = rr / P1;
+  T Xa[P1], Ya[P1], mb[P1], gb[P1];
+#pragma unroll
+  for (int c = 0; c < P1; ++c) {
+    const T mac = m1[a * P1 + c];
+    Xa[c] = stJ * mac - gx * gdt[a * P1 + c];
+    Ya[c] = gy * mac;
+    mb[c] = m1[b * P1 + c];
+    gb[c] = gdt[b * P1 + c];
+  }
+#pragma unroll
+  for (int dd = 0; dd < P1; ++dd)
+#pragma unroll
+    for (int c = 0; c < P1; ++c) row[c + P1 * dd] = mb[dd] * Xa[c] - gb[dd] * Ya[c];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    if ((inflow >> f) & 1u) continue;
+    // outflow face: a multiply by zero off the face instead of a branch
+    const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+    const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+    const T cf = on_face ? on[f] : T(0);
+#pragma unroll
+    for (int c = 0; c < P1; ++c) row[face_node<P>(f, c)] += cf * m1[pos * P1 + c];
+  }
+}
+
 // Assemble and solve one element-direction system from the slot's staged
-// geometry and sources (all 16 lanes of the slot call it).  tab: the LDS
+// geometry and sources (all 16 lanes of the slot call it).  CLS: the solve's
+// local matrix is shared by its class (index cls) and the handle holds the
+// classes' inverses (pb.cls_inv); only the right-hand side is assembled.  tab: the LDS
 // tables (LuLds), wv: w V [Q][n] in global memory (direction-dependent source
 // only), area: the slot's LDS area.  The upwind traces of the inflow faces
 // (face node c of face f, in the face order of the downwind element) are
 // read from the angular flux here (SRC_LDS false; boundary data then from
 // pio.psi_bc) or come from the area's trace buffer, which also holds the
 // inflow data of boundary faces (SRC_LDS true).
-template <int P, int NQ, typename T, bool FIX, bool COH, bool SRC_LDS>
+template <int P, int NQ, typename T, bool FIX, bool COH, bool SRC_LDS, bool CLS = false>
 __device__ __forceinline__ void lu_core(int e, int d, bool valid, int flags, const int (&nb)[4], T ox, T oy, T st,
                                         const KProb &pb, const KIO &pio, const T *tab, const T *wv, T *area, int r,
-                                        int *status) {
+                                        int *status, int cls = 0) {
   using S = LuShape<P>;
   using LD = LuLds<P, NQ>;
   constexpr int P1 = S::P1, N = S::N, RS = S::RS, H = S::H, Q = NQ * NQ;
@@ -1884,41 +1921,46 @@ __device__ __forceinline__ void lu_core(int e, int d, bool valid, int flags, con
     }
     A[s][N] = rhs;
   }
-#pragma unroll
-  for (int s = 0; s < RS; ++s) {
-    const int row = r + s * H;
-    const int rr = (r < H && row < N) ? row : N - 1;
-    const int a = rr % P1, b = rr / P1;
-    T Xa[P1], Ya[P1], mb[P1], gb[P1];
-#pragma unroll
-    for (int c = 0; c < P1; ++c) {
-      const T mac = m1[a * P1 + c];
-      Xa[c] = stJ * mac - gx * gdt[a * P1 + c];
-      Ya[c] = gy * mac;
-      mb[c] = m1[b * P1 + c];
-      gb[c] = gdt[b * P1 + c];
-    }
-#pragma unroll
-    for (int dd = 0; dd < P1; ++dd)
-#pragma unroll
-      for (int c = 0; c < P1; ++c) A[s][c + P1 * dd] = mb[dd] * Xa[c] - gb[dd] * Ya[c];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      if ((mask >> f) & 1u) continue;
-      // outflow face: a multiply by zero off the face instead of a branch
-      const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
-      const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
-      const T cf = on_face ? on[f] : T(0);
-#pragma unroll
-      for (int c = 0; c < P1; ++c) A[s][face_node<P>(f, c)] += cf * m1[pos * P1 + c];
-    }
-  }
-
-  T idg[RS];
-  lu_rows<N, RS, H, T>(A, idg, r);
   T x[RS];
+  if constexpr (CLS) {
+    // a shared local matrix: x = A^-1 b with the inverse of the solve's
+    // class (block [n][16][RS]: entry [j][r][s] = (A^-1)[r + s H][j]), b
+    // broadcast from the slot's area once every lane has read the sources
+    wave_sync_lds();
 #pragma unroll
-  for (int s = 0; s < RS; ++s) x[s] = A[s][N] * idg[s];
+    for (int s = 0; s < RS; ++s) {
+      const int row = r + s * H;
+      if (r < H && row < N) area[LD::A_S + row] = A[s][N];
+    }
+    wave_sync_lds();
+    const T *iv = static_cast<const T *>(pb.cls_inv) + (size_t)cls * (N * 16 * RS) + r * RS;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) x[s] = T(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const T bj = area[LD::A_S + j];
+      if constexpr (RS == 2) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        const V2 v = gload(reinterpret_cast<const V2 *>(iv + j * 16 * RS));
+        x[0] += v.x * bj;
+        x[1] += v.y * bj;
+      } else {
+#pragma unroll
+        for (int s = 0; s < RS; ++s) x[s] += gload(iv + j * 16 * RS + s) * bj;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int row = r + s * H;
+      const int rr = (r < H && row < N) ? row : N - 1;
+      affine_lu_row<P, T>(A[s], rr, m1, gdt, stJ, gx, gy, on, mask);
+    }
+    T idg[RS];
+    lu_rows<N, RS, H, T>(A, idg, r);
+#pragma unroll
+    for (int s = 0; s < RS; ++s) x[s] = A[s][N] * idg[s];
+  }
 
   if constexpr (FIX) {
     // negative-flux fixup (see zero_and_scale_slot) over the slot's rows:
@@ -2184,7 +2226,7 @@ __device__ __forceinline__ void lu_stage(const LuPre<P, NQ, T> &x, T *area, cons
 
 constexpr int kLuStreamMax = 16;  // solves per slot and launch (one per lane of the slot)
 
-template <int P, int NQ, typename T, bool FIX>
+template <int P, int NQ, typename T, bool FIX, bool CLS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
 k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__restrict__ probs,
                   const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
@@ -2208,7 +2250,7 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
   const KIO &pio = io[0];
 
   // descriptors of the slot's solves, in LDS after the slot areas: lane k
-  // writes those of the slot's k-th solve (element, direction, flags,
+  // writes those of the slot's k-th solve (element, direction, flags, class;
   // neighbours; flags: inflow faces, neighbour faces << 4, pivoting bit 12,
   // boundary faces << 16), loaded before the stop flag is read
   int *dtab = reinterpret_cast<int *>(lds + LD::TAB + (size_t)per_block * LD::AREA) + slot * (kLuStreamMax * 8);
@@ -2224,7 +2266,7 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
   stage_tables_lu<P, NQ, T>(tables, lds);
   {
     int4 *w = reinterpret_cast<int4 *>(dtab + r * 8);
-    w[0] = make_int4(da.x, da.y & 0xffff, da.z, 0);
+    w[0] = make_int4(da.x, da.y & 0xffff, da.z, CLS ? da.w : 0);
     w[1] = db;
   }
   __syncthreads();
@@ -2250,8 +2292,101 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
     // only the sign of a neighbour index is used by the solve
     const int nb[4] = {(fl >> 16) & 1 ? -1 : 0, (fl >> 17) & 1 ? -1 : 0, (fl >> 18) & 1 ? -1 : 0,
                        (fl >> 19) & 1 ? -1 : 0};
-    lu_core<P, NQ, T, FIX, false, true>(e, d, valid, fl, nb, area[LD::A_SC + 1], area[LD::A_SC + 2], area[LD::A_SC],
-                                        pb, pio, lds, wv, area, r, status);
+    lu_core<P, NQ, T, FIX, false, true, CLS>(e, d, valid, fl, nb, area[LD::A_SC + 1], area[LD::A_SC + 2],
+                                             area[LD::A_SC], pb, pio, lds, wv, area, r, status, a.w);
+  }
+}
+
+// Inverse of the local matrix of one class of solves that share it (one
+// work-group of 64 threads per class, see ClassInvLaunch): thread i < n
+// assembles row i in double from the element's geometry, sigma_t and the
+// direction, as the row-set LU does; then Gauss-Jordan elimination with
+// partial pivoting on [A | I] in LDS.
+template <int P, int NQ, typename T>
+__global__ void __launch_bounds__(64)
+k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const T *__restrict__ tables,
+            T *__restrict__ out, int *__restrict__ status) {
+  using S = LuShape<P>;
+  constexpr int P1 = S::P1, N = S::N, RS = S::RS, H = S::H, W = 2 * N;
+  __shared__ double m1[P1 * P1], gd[P1 * P1];
+  __shared__ double M[N][W + 1];
+  __shared__ double fac[N];
+  __shared__ int piv;
+  const int t = threadIdx.x;
+  const int4 rp = rep[blockIdx.x];
+  const KProb &pb = probs[0];
+  for (int i = t; i < P1 * P1; i += 64) {
+    m1[i] = static_cast<double>(tables[Shape<P, NQ>::A_M1 + i]);
+    gd[i] = static_cast<double>(tables[Shape<P, NQ>::A_GD1 + i]);
+  }
+  __syncthreads();
+  if (t < N) {
+    const T *g = static_cast<const T *>(pb.geo_a) + (size_t)rp.x * 16;
+    const double ox = pb.omega[2 * rp.y], oy = pb.omega[2 * rp.y + 1];
+    const double stJ = pb.sig[2 * rp.x] * static_cast<double>(g[0]);
+    const double gx = static_cast<double>(g[1]) * ox + static_cast<double>(g[2]) * oy;
+    const double gy = static_cast<double>(g[3]) * ox + static_cast<double>(g[4]) * oy;
+    double on[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) on[f] = ox * static_cast<double>(g[5 + 2 * f]) + oy * static_cast<double>(g[6 + 2 * f]);
+    double row[N];
+    affine_lu_row<P, double>(row, t, m1, gd, stJ, gx, gy, on, (unsigned)rp.z & 15u);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      M[t][j] = row[j];
+      M[t][N + j] = j == t ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    if (t == 0) {
+      int pr = k;
+      double best = fabs(M[k][k]);
+      for (int i = k + 1; i < N; ++i)
+        if (fabs(M[i][k]) > best) {
+          best = fabs(M[i][k]);
+          pr = i;
+        }
+      piv = pr;
+      if (best == 0.0) atomicOr(status, 1);
+    }
+    __syncthreads();
+    const int pr = piv;
+    if (pr != k)
+      for (int j = t; j < W; j += 64) {
+        const double v = M[k][j];
+        M[k][j] = M[pr][j];
+        M[pr][j] = v;
+      }
+    __syncthreads();
+    const double pk = M[k][k];
+    if (t < N) fac[t] = t == k ? 0.0 : M[t][k] / pk;
+    __syncthreads();
+    for (int x = t; x < N * W; x += 64) {
+      const int i = x / W, j = x - i * W;
+      if (i != k) M[i][j] -= fac[i] * M[k][j];
+    }
+    __syncthreads();
+    for (int j = t; j < W; j += 64) M[k][j] /= pk;
+    __syncthreads();
+  }
+  T *o = out + (size_t)blockIdx.x * (N * 16 * RS);
+  for (int x = t; x < N * 16 * RS; x += 64) {
+    const int j = x / (16 * RS), r = (x / RS) % 16, s = x % RS;
+    const int row = r + s * H;
+    o[x] = (r < H && row < N) ? static_cast<T>(M[row][N + j]) : T(0);
+  }
+}
+
+template <int P, int NQ, typename T>
+hipError_t launch_class_inv_t(const ClassInvLaunch &C) {
+  if constexpr (P < 3) {
+    return hipErrorInvalidValue;
+  } else {
+    if (C.n_cls <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_class_inv<P, NQ, T>), dim3(C.n_cls), dim3(64), 0, C.stream, C.rep, C.probs,
+                       static_cast<const T *>(C.tables), static_cast<T *>(C.out), C.status);
+    return hipGetLastError();
   }
 }
 
@@ -2340,27 +2475,37 @@ hipError_t launch_level_lu_t(const SweepLaunch &L) {
       // slot has at most kLuStreamMax solves
       // resident blocks per CU: a host query, cached per device and block
       // size (a level-synchronous sweep launches once per level)
-      static std::atomic<int> cache[64][4];
+      static std::atomic<int> cache[64][4][2];
       int dev = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e != hipSuccess) return e;
       if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
       const bool cacheable = block % 64 == 0;
-      int per_cu = cacheable ? cache[dev][block / 64 - 1].load(std::memory_order_relaxed) : 0;
+      const int cv = L.shared ? 1 : 0;
+      int per_cu = cacheable ? cache[dev][block / 64 - 1][cv].load(std::memory_order_relaxed) : 0;
       if (per_cu == 0) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_level_lus<P, NQ, T, FIX>, block, bytes_s);
+        e = L.shared ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_level_lus<P, NQ, T, FIX, true>,
+                                                                   block, bytes_s)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_level_lus<P, NQ, T, FIX, false>,
+                                                                   block, bytes_s);
         if (e != hipSuccess) return e;
         if (per_cu < 1) return hipErrorInvalidConfiguration;
-        if (cacheable) cache[dev][block / 64 - 1].store(per_cu, std::memory_order_relaxed);
+        if (cacheable) cache[dev][block / 64 - 1][cv].store(per_cu, std::memory_order_relaxed);
       }
       const int cap = per_block * kLuStreamMax;
       const int lo = (L.count + cap - 1) / cap;
       const int res = per_cu * L.n_cu;
       if (grid > res) grid = res > lo ? res : lo;
-      hipLaunchKernelGGL((k_sweep_level_lus<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes_s, L.stream, L.desc,
-                         L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
+      if (L.shared)
+        hipLaunchKernelGGL((k_sweep_level_lus<P, NQ, T, FIX, true>), dim3(grid), dim3(block), bytes_s, L.stream,
+                           L.desc, L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
+      else
+        hipLaunchKernelGGL((k_sweep_level_lus<P, NQ, T, FIX, false>), dim3(grid), dim3(block), bytes_s, L.stream,
+                           L.desc, L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
       return hipGetLastError();
     }
+    // the class inverses are used by the streaming form only
+    if (L.shared) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_sweep_level_lu<P, NQ, T, FIX>), dim3(grid), dim3(block), bytes, L.stream, L.desc, L.count,
                        L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
     return hipGetLastError();
@@ -2714,6 +2859,16 @@ hipError_t launch_mode_fx(const SweepLaunch &L) {
 template <int P, int NQ, typename T, bool DIR>
 hipError_t launch_mode(const SweepLaunch &L) {
   return L.fixup ? launch_mode_fx<P, NQ, T, DIR, MODE_FIX>(L) : launch_mode_fx<P, NQ, T, DIR, 0>(L);
+}
+
+template <int P>
+hipError_t launch_class_p(const ClassInvLaunch &C) {
+  switch (C.nq - P) {
+    case 1: return C.fp32 ? launch_class_inv_t<P, P + 1, float>(C) : launch_class_inv_t<P, P + 1, double>(C);
+    case 2: return C.fp32 ? launch_class_inv_t<P, P + 2, float>(C) : launch_class_inv_t<P, P + 2, double>(C);
+    case 3: return C.fp32 ? launch_class_inv_t<P, P + 3, float>(C) : launch_class_inv_t<P, P + 3, double>(C);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int P, bool DIR>

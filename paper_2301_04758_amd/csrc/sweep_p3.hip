@@ -7,4 +7,6 @@ hipError_t launch_sweep_p3(const SweepLaunch &L, bool dir) {
   return dir ? launch_p<3, true>(L) : launch_p<3, false>(L);
 }
 
+hipError_t launch_class_inv_p3(const ClassInvLaunch &C) { return launch_class_p<3>(C); }
+
 }  // namespace vefk

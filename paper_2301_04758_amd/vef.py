@@ -41,9 +41,11 @@ VEF_KERNEL_PIVOT, VEF_KERNEL_NOPIVOT, VEF_KERNEL_AFFINE, VEF_KERNEL_AFFINE_PIPEL
 VEF_KERNEL_BILINEAR_PIPELINE = 4
 VEF_KERNEL_AFFINE_LU = 5
 VEF_KERNEL_GENERAL_MAT = 6
+VEF_KERNEL_AFFINE_SHARED = 7
 KERNEL_NAMES = {VEF_KERNEL_PIVOT: "pivot", VEF_KERNEL_NOPIVOT: "nopivot", VEF_KERNEL_AFFINE: "affine",
                 VEF_KERNEL_AFFINE_PIPELINE: "affine_pipeline", VEF_KERNEL_BILINEAR_PIPELINE: "bilinear_pipeline",
-                VEF_KERNEL_AFFINE_LU: "affine_lu", VEF_KERNEL_GENERAL_MAT: "general_mat"}
+                VEF_KERNEL_AFFINE_LU: "affine_lu", VEF_KERNEL_GENERAL_MAT: "general_mat",
+                VEF_KERNEL_AFFINE_SHARED: "affine_shared"}
 
 EXPORTED = ("vef_sweep_create", "vef_sweep_run", "vef_sweep_run_static", "vef_moments", "vef_sweep_destroy", "vef_plan_query",
             "vef_problem_info", "vef_boundary_faces", "vef_sweep_check", "vef_sweep_timing",
@@ -62,7 +64,7 @@ class vef_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("schedule", C.c_int), ("block", C.c_int), ("timing", C.c_int),
                 ("pipeline_waves", C.c_int), ("pipeline_ring", C.c_int), ("fixup", C.c_int),
                 ("cycles", C.c_int), ("upwind", C.c_int), ("wait_polls", C.c_longlong),
-                ("elem_matrices", C.c_int)]
+                ("elem_matrices", C.c_int), ("shared_matrices", C.c_int)]
 
 
 class vef_problem_io(C.Structure):
@@ -86,7 +88,7 @@ class vef_info(C.Structure):
     _fields_ = [("n", C.c_int), ("nq", C.c_int), ("Q", C.c_int), ("n_bf", C.c_int), ("n_levels", C.c_int),
                 ("n_groups", C.c_int), ("pivoting", C.c_int), ("affine", C.c_int), ("n_solves", C.c_longlong),
                 ("schedule", C.c_int), ("kernel", C.c_int), ("n_lagged", C.c_longlong),
-                ("n_pivoting", C.c_longlong)]
+                ("n_pivoting", C.c_longlong), ("n_classes", C.c_int)]
 
 
 def _load():
@@ -175,12 +177,15 @@ class _Desc:
 # ------------------------------------------------------------------ C names
 
 
-def vef_plan_query(problem, lag_cycles: bool = False, pointwise: bool = False) -> dict:
+def vef_plan_query(problem, lag_cycles: bool = False, pointwise: bool = False, precision: int = VEF_FP64,
+                   shared_matrices: bool = True) -> dict:
     d = _Desc(problem)
     info = vef_info()
     opt = vef_options()
+    opt.precision = precision
     opt.cycles = VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT
     opt.upwind = VEF_UPWIND_POINT if pointwise else VEF_UPWIND_FACE
+    opt.shared_matrices = 0 if shared_matrices else -1
     rc = lib.vef_plan_query(C.byref(d.s), C.byref(opt), C.byref(info))
     if rc != VEF_OK:
         raise VefError(rc, lib.vef_last_error(None).decode())
@@ -190,13 +195,14 @@ def vef_plan_query(problem, lag_cycles: bool = False, pointwise: bool = False) -
 def vef_sweep_create(problems: Sequence, precision: int = VEF_FP64, schedule: int = VEF_SCHEDULE_AUTO,
                      block: int = 0, timing: int = 0, pipeline_waves: int = 0,
                      pipeline_ring: int = 0, fixup: bool = False, lag_cycles: bool = False,
-                     pointwise: bool = False, wait_polls: int = 0, elem_matrices: bool = True) -> int:
+                     pointwise: bool = False, wait_polls: int = 0, elem_matrices: bool = True,
+                     shared_matrices: bool = True) -> int:
     descs = [_Desc(p) for p in problems]
     arr = (vef_problem_desc * len(descs))(*[d.s for d in descs])
     opt = vef_options(precision, schedule, block, int(timing), pipeline_waves, pipeline_ring,
                       1 if fixup else 0, VEF_CYCLES_LAG if lag_cycles else VEF_CYCLES_REJECT,
                       VEF_UPWIND_POINT if pointwise else VEF_UPWIND_FACE, int(wait_polls),
-                      0 if elem_matrices else -1)
+                      0 if elem_matrices else -1, 0 if shared_matrices else -1)
     h = C.c_void_p()
     rc = lib.vef_sweep_create(arr, len(descs), C.byref(opt), C.byref(h))
     if rc != VEF_OK:
@@ -271,7 +277,8 @@ def vef_sweep_timing(h: int):
 
 class vef_tune_result(C.Structure):
     _fields_ = [("schedule", C.c_int), ("pipeline_waves", C.c_int), ("block", C.c_int),
-                ("elem_matrices", C.c_int), ("n_candidates", C.c_int), ("best_ms", C.c_double),
+                ("elem_matrices", C.c_int), ("shared_matrices", C.c_int), ("n_candidates", C.c_int),
+                ("best_ms", C.c_double),
                 ("before_ms", C.c_double)]
 
 
@@ -393,7 +400,7 @@ class Sweep:
 
     def __init__(self, problems, precision="fp64", block=0, device=None, timing=False, schedule="auto",
                  pipeline_waves=0, pipeline_ring=0, fixup=False, lag_cycles=False, pointwise=False, wait_polls=0,
-                 elem_matrices=True):
+                 elem_matrices=True, shared_matrices=True):
         import torch
         self.torch = torch
         self.problems = list(problems)
@@ -402,7 +409,8 @@ class Sweep:
         with torch.cuda.device(self.device):
             self.h = vef_sweep_create(self.problems, VEF_FP32_LOCAL if self.fp32 else VEF_FP64,
                                       SCHEDULES[schedule], block, timing, pipeline_waves, pipeline_ring,
-                                      fixup, lag_cycles, pointwise, wait_polls, elem_matrices)
+                                      fixup, lag_cycles, pointwise, wait_polls, elem_matrices,
+                                      shared_matrices)
         self.info = [vef_problem_info(self.h, k) for k in range(len(self.problems))]
 
     def close(self):

@@ -117,6 +117,58 @@ def test_pivoting_certification_counts():
         assert 0 < got < c.n_elem * c.n_dir
 
 
+def _shared_class_count(pr, s=8):
+    """Classes of (direction, element) pairs with equal local matrices, from
+    the definition on numpy geometry: equal sigma_t, an equal element shape
+    (the corners' offsets from the first corner, compared exactly) and the
+    same direction, which then fixes the inflow faces.  0 where the
+    library's rule declines them (more than 4096 element classes, fewer than
+    8 solves per class, or more than 8 MiB of inverses)."""
+    xy = pr.cp_xy[pr.elem_cp]  # [ne][(m+1)^2][2]
+    shape = xy - xy[:, :1, :]
+    keys = {}
+    for e in range(pr.n_elem):
+        keys.setdefault((pr.sigma_t[e],) + tuple(shape[e].ravel()), len(keys))
+    n_cls = len(keys) * pr.n_dir
+    n = (pr.p + 1) ** 2
+    inv_bytes = n * 16 * ((n + 15) // 16) * s
+    if len(keys) > 4096 or n_cls * 8 > pr.n_elem * pr.n_dir or n_cls * inv_bytes > (8 << 20):
+        return 0
+    return n_cls
+
+
+def test_shared_matrix_class_counts():
+    """vef_info.n_classes of vef_plan_query against a count from the
+    definition: uniform grids with one or a few materials (one class per
+    material and direction), sigma_t on every element different (declined),
+    spacings that are not exact in binary (element shapes differ in the last
+    bit: many classes, declined), degrees without the row-set LU and the
+    option off."""
+    vef = _vef()
+
+    def grid(n, p, N, st):
+        cp, ec = P.quad_mesh(n, n, 1)
+        om, wt = P.level_symmetric_2d(N)
+        st = np.broadcast_to(np.asarray(st, float), (n * n,)).copy()
+        return P.Problem("grid", p, 1, cp, ec, om, wt, st, 0.5 * st, nx=n, ny=n)
+
+    rng = np.random.default_rng(5)
+    cases = [grid(8, 4, 8, 1.0), grid(16, 3, 6, rng.choice([0.5, 3.0, 40.0], 256)), grid(8, 4, 4, rng.uniform(1, 2, 64)),
+             grid(12, 4, 4, 2.0), grid(32, 3, 12, 1000.0)]
+    for c in cases:
+        want = _shared_class_count(c)
+        assert vef.vef_plan_query(c)["n_classes"] == want, c.sigma_t[:3]
+        assert vef.vef_plan_query(c, shared_matrices=False)["n_classes"] == 0
+        assert vef.vef_plan_query(c, precision=vef.VEF_FP32_LOCAL)["n_classes"] == _shared_class_count(c, 4)
+    assert _shared_class_count(cases[0]) == cases[0].n_dir
+    assert _shared_class_count(cases[1]) == 3 * cases[1].n_dir
+    assert _shared_class_count(cases[2]) == 0
+    assert _shared_class_count(cases[4]) == cases[4].n_dir
+    assert vef.vef_plan_query(grid(8, 2, 8, 1.0))["n_classes"] == 0  # p = 2: no row-set LU
+    (c3,), _ = P.make_config("c3")
+    assert vef.vef_plan_query(c3)["n_classes"] == 0  # curved
+
+
 def _bad(pr, code):
     vef = _vef()
     with pytest.raises(vef.VefError) as ei:
