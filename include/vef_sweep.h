@@ -193,15 +193,20 @@ typedef struct {
                     pairs have the same local matrix (same sigma_t, same
                     affine geometry, same direction, hence the same outflow
                     faces; a uniform grid with few materials), group them into
-                    classes at create, and in every run invert one matrix per
-                    class (double, Gauss-Jordan with partial pivoting) before
-                    the first sweep; the level-synchronous sweep then solves
-                    each local system as a product with its class's inverse
+                    classes at create, and in every run form one matrix per
+                    class before the first sweep: K = A^-1 R, R the linear
+                    map from a solve's inputs (nodal source, upwind traces,
+                    boundary data, q_dir) to its right-hand side (double,
+                    Gauss-Jordan with partial pivoting on [A | R]); the
+                    level-synchronous sweep then computes each local
+                    solution as K times the solve's inputs
                     (VEF_KERNEL_AFFINE_SHARED).  Used when there are at most
                     4096 element classes, the solves number at least 8 per
-                    class and the inverses take at most 8 MiB.  The
-                    local systems and their right-hand sides are the same;
-                    results differ from the row-set LU only by rounding.
+                    class and the class matrices take at most 16 MiB
+                    ((n + 8 max(p + 1, nq) + nq^2) x 16 x ceil(n / 16)
+                    entries each).  The local systems and their right-hand
+                    sides are the same; results differ from the row-set LU
+                    only by rounding.
                     -1 = never (VEF_KERNEL_AFFINE_LU). */
 } vef_options;
 
@@ -300,10 +305,10 @@ typedef struct {
                                        LU in natural order where the plan
                                        certifies it, else partial pivoting */
 #define VEF_KERNEL_AFFINE_SHARED 7   /* affine, p >= 3, level-synchronous: a
-                                       16-lane slot per solve assembles the
-                                       right-hand side and multiplies it by
-                                       the inverse of the local matrix its
-                                       class shares */
+                                       16-lane slot per solve; the solution
+                                       is the matrix of the solve's class
+                                       (A^-1 times the map from inputs to
+                                       right-hand side) times its inputs */
 
 /* Validate the problems (sizes, weights, J > 0 at every volume point, acyclic
  * upwind graphs unless opt->cycles lags them), build the sweep plan on the host and upload it to the
@@ -502,7 +507,7 @@ typedef struct {
                          chosen, 0 = the quadrature kernel; -1 = no such problem */
   int shared_matrices; /* for a problem with classes of shared local matrices
                          (vef_info.n_classes > 0): 1 = solves by the class
-                         inverses were chosen, 0 = the row-set LU; -1 = no
+                         matrices were chosen, 0 = the row-set LU; -1 = no
                          such problem */
   int n_candidates;   /* configurations timed */
   double best_ms;     /* one run of the given arguments with the choice (mean of reps) */
@@ -518,7 +523,7 @@ typedef struct {
  * a problem was built with element matrices (Sec. 3.2, formed on the matrix
  * cores), each schedule also with the quadrature-assembly kernel instead;
  * where a problem has classes of shared local matrices, the level-synchronous
- * kernels also with the row-set LU instead of the class inverses.  Each
+ * kernels also with the row-set LU instead of the class matrices.  Each
  * candidate runs once untimed and then reps (1..1000) times between HIP
  * events on stream; the fastest is kept by the handle for later runs when it
  * beats the handle's configuration before the call by more than 2% (else

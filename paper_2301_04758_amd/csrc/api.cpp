@@ -138,10 +138,10 @@ struct vef_sweep {
   bool elem_matrices = true;         // precomputed element matrices where available
   bool mat_quadrature = false;       // run-time choice (autotune): their problems take the quadrature kernel
   bool shared_matrices = true;       // classes of shared local matrices where a problem has them
-  bool shared_lu = false;            // run-time choice (autotune): the row-set LU instead of the class inverses
+  bool shared_lu = false;            // run-time choice (autotune): the row-set LU instead of the class matrices
   int n_cls = 0;                     // classes of shared local matrices of problem 0 (0: none)
   int4 *d_cls_rep = nullptr;         // [n_cls] representative (element, direction, inflow faces, 0)
-  void *d_cls_inv = nullptr;         // T [n_cls][n][16][RS] class inverses (written by every run)
+  void *d_cls_inv = nullptr;         // T [n_cls][ncol][16][RS] class matrices (written by every run)
   double *static_resid = nullptr;    // this device's copy of `scratch` (vef_sweep_run_static)
   hipStream_t last_stream = nullptr;
   bool timing = false;
@@ -276,11 +276,18 @@ struct SharedClasses {
   }
 };
 
+// Entries of one class matrix (kernels.h ClassInvLaunch): [ncol][16][RS].
+size_t class_matrix_entries(const vefplan::ProblemPlan &pl) {
+  const int tw = std::max(pl.p + 1, pl.nq);
+  return (size_t)(pl.n + 8 * tw + pl.nq * pl.nq) * 16 * ((pl.n + 15) / 16);
+}
+
 constexpr int kMaxElemClasses = 4096;
 constexpr int kMinSolvesPerClass = 8;
-constexpr size_t kMaxClassInvBytes = size_t(8) << 20;
+constexpr size_t kMaxClassInvBytes = size_t(16) << 20;
 
-// True when the problem has few enough classes for the class inverses to pay.
+// True when the problem has few enough classes for the class matrices to pay
+// (inv_bytes: bytes of one class matrix).
 bool find_shared_classes(const vefplan::ProblemPlan &pl, size_t inv_bytes, SharedClasses &sc) {
   if (!pl.affine || pl.geo_a.size() != (size_t)pl.ne * 16) return false;
   std::map<std::array<uint64_t, 14>, int> keys;
@@ -392,15 +399,14 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   SharedClasses shared;
   if (h->shared_matrices && n_probs == 1 && mode_of(h->plans[0], VEF_LEVEL_SYNC) == 5) {
     const auto &pl = h->plans[0];
-    const int rs = (pl.n + 15) / 16;
-    const size_t inv_bytes = (size_t)pl.n * 16 * rs * (fp32 ? sizeof(float) : sizeof(double));
-    if (find_shared_classes(pl, inv_bytes, shared)) {
+    const size_t per = class_matrix_entries(pl);
+    if (find_shared_classes(pl, per * (fp32 ? sizeof(float) : sizeof(double)), shared)) {
       h->n_cls = shared.n_cls;
       he = upload(h, &h->d_cls_rep, shared.rep.data(), shared.rep.size());
       if (he == hipSuccess)
-        he = fp32 ? dev_alloc(h, reinterpret_cast<float **>(&h->d_cls_inv), (size_t)h->n_cls * pl.n * 16 * rs)
-                  : dev_alloc(h, reinterpret_cast<double **>(&h->d_cls_inv), (size_t)h->n_cls * pl.n * 16 * rs);
-      if (he != hipSuccess) return hip_fail(h, he, "allocate class inverses");
+        he = fp32 ? dev_alloc(h, reinterpret_cast<float **>(&h->d_cls_inv), (size_t)h->n_cls * per)
+                  : dev_alloc(h, reinterpret_cast<double **>(&h->d_cls_inv), (size_t)h->n_cls * per);
+      if (he != hipSuccess) return hip_fail(h, he, "allocate class matrices");
     }
   }
 
@@ -582,7 +588,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   // The solves of a (problem, class, level) block are listed element by
   // element (an element's directions together: they share its data), or,
   // on a handle with shared local matrices, direction by direction
-  // (consecutive slots then read the same class inverse).
+  // (consecutive slots then read the same class matrix).
   const bool dir_major = h->n_cls > 0;
   // per level and variant, two level-synchronous launches: the problems the
   // persistent schedule covers, then the others
@@ -889,7 +895,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
   he = vefk::launch_run_init(h->d_io, np, a->n_iter, stop, iters, status, s);
   if (he != hipSuccess) return hip_fail(h, he, "launch init");
   const bool persistent = h->schedule == VEF_PERSISTENT;
-  // level-synchronous row-set LU launches solve with the class inverses,
+  // level-synchronous row-set LU launches solve with the class matrices,
   // which every run forms before its first sweep
   const bool use_cls = h->n_cls > 0 && !h->shared_lu && h->schedule == VEF_LEVEL_SYNC;
   if (persistent && !h->flow.empty()) {
@@ -930,7 +936,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
       C.status = status;
       C.stream = s;
       he = vefk::launch_class_inv(C);
-      if (he != hipSuccess) return hip_fail(h, he, "launch class inverses");
+      if (he != hipSuccess) return hip_fail(h, he, "launch class matrices");
       if (timed(it)) h->timed_launches++;
     }
     if (persistent) {
@@ -1102,10 +1108,10 @@ int vef_plan_query(const vef_problem_desc *prob, const vef_options *opt, vef_inf
     info->n_classes = 0;
     if ((!opt || opt->shared_matrices == 0) && mode_of(pl, VEF_LEVEL_SYNC) == 5) {
       const bool fp32 = opt && opt->precision == VEF_FP32_LOCAL;
-      const size_t inv_bytes = (size_t)pl.n * 16 * ((pl.n + 15) / 16) * (fp32 ? sizeof(float) : sizeof(double));
       SharedClasses sc;
       try {
-        if (find_shared_classes(pl, inv_bytes, sc)) info->n_classes = sc.n_cls;
+        if (find_shared_classes(pl, class_matrix_entries(pl) * (fp32 ? sizeof(float) : sizeof(double)), sc))
+          info->n_classes = sc.n_cls;
       } catch (const std::bad_alloc &) {
         return set_err(nullptr, VEF_ERR_OOM, "host allocation failed");
       }
@@ -1257,7 +1263,7 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
     // the element-matrix kernel against quadrature assembly (matrix cores
     // against the vector units) where some problem has both
     if (quad && !any_mat) continue;
-    // class inverses against the row-set LU (level-synchronous only)
+    // class matrices against the row-set LU (level-synchronous only)
     for (bool lu : {false, true}) {
       if (lu && h->n_cls == 0) continue;
       add({VEF_LEVEL_SYNC, before.waves, 256, quad, lu});

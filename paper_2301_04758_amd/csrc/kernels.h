@@ -14,7 +14,7 @@ struct KProb {
   const void *geo_f;       // T [ne][4][nq][2]: w_s n ds
   const void *geo_a;       // T [ne][16]: J, adj(F) (row major), face chords N_0..N_3 (affine meshes)
   const void *emat;        // T [ne][3 n n + 8 (p+1)^2]: element matrices (general elements, p = 3), or NULL
-  const void *cls_inv;     // T [n_cls][n][16][RS]: inverses of the shared local matrices (affine, p >= 3), or NULL
+  const void *cls_inv;     // T [n_cls][ncol][16][RS]: class matrices of shared local matrices (affine, p >= 3), or NULL
   const double *geo_fd;    // double copy of geo_f
   const int32_t *nbr;      // [ne][4] neighbour or -(bf+1)
   const int8_t *nbr_face;  // [ne][4]
@@ -79,7 +79,7 @@ struct SweepLaunch {
   int *abort_flag;       // persistent: set when a wait expires (zeroed by each run)
   int n_cu;              // persistent and streaming level launches: compute units of the device
   bool single;           // the handle holds one problem (streaming level kernels)
-  bool shared;           // row-set LU level launches solve with the class inverses (KProb::cls_inv; one
+  bool shared;           // row-set LU level launches solve with the class matrices (KProb::cls_inv; one
                          // problem, streaming form; the fourth descriptor field is the class)
   const KProb *probs;
   const KIO *io;
@@ -118,13 +118,16 @@ hipError_t launch_zero_nonpos(const KMomIO *io, int n_probs, hipStream_t s);
 hipError_t launch_elem_mat(int p, int nq, bool fp32, int ne, const double *tab_d, const double *geo_vd,
                            const double *geo_fd, void *out, hipStream_t s);
 
-// Inverses of shared local matrices (row-set LU kernels, affine elements,
-// p >= 3): for each class c, the local matrix of its representative
-// (element, direction, inflow faces) rep[c] = (e, d, inflow, 0) of problem 0,
-// assembled and inverted in double (Gauss-Jordan, partial pivoting) and
-// written as T out[c][n][16][RS], entry [j][r][s] = (A^-1)[r + s H][j] (zero
-// where r + s H is not a row), the slot layout of the row-set LU.  A zero
-// pivot sets bit 0 of *status.
+// Matrices of classes of solves that share their local matrix (row-set LU
+// kernels, affine elements, p >= 3): for each class c, with the local matrix
+// A of its representative (element, direction, inflow faces) rep[c] = (e, d,
+// inflow, 0) of problem 0, K = A^-1 R, where R maps a solve's inputs (nodal
+// source [n], interior-face traces [4][tw], boundary data [4][tw], q_dir [Q];
+// tw = max(p + 1, nq)) to its right-hand side; formed in double
+// (Gauss-Jordan, partial pivoting on [A | R]) and written as T
+// out[c][ncol][16][RS], ncol = n + 8 tw + Q, entry [j][r][s] = K[r + s H][j]
+// (zero where r + s H is not a row), the slot layout of the row-set LU.  A
+// zero pivot sets bit 0 of *status.
 struct ClassInvLaunch {
   int p, nq;
   bool fp32;

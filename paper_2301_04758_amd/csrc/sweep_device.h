@@ -1732,7 +1732,7 @@ struct LuShape {
   static constexpr int H = (N + RS - 1) / RS;       // lanes holding rows
 };
 
-template <int P, int NQ>
+template <int P, int NQ, bool CLS = false>
 struct LuLds {
   static constexpr int P1 = P + 1, N = P1 * P1, Q = NQ * NQ;
   // tables: 1D mass m [P1][P1], 1D derivative table gd [P1][P1], boundary
@@ -1742,7 +1742,25 @@ struct LuLds {
   // upwind traces or boundary data of the four faces [4][TW] (streaming kernel)
   static constexpr int TW = P1 > NQ ? P1 : NQ;
   static constexpr int A_G = 0, A_S = 16, A_QD = 16 + N, A_TR = 16 + N + Q, A_SC = A_TR + 4 * TW;
-  static constexpr int AREA = ((A_SC + 3 + 1) / 2) * 2;  // A_SC: sigma_t, Omega_x, Omega_y
+  // class matrices (CLS): traces of interior faces in A_TR, boundary data in
+  // A_TB [4][TW], each zero where the face has the other kind or is outflow
+  static constexpr int A_TB = A_SC + 4;
+  static constexpr int AREA = CLS ? ((A_TB + 4 * TW + 1) / 2) * 2
+                                  : ((A_SC + 3 + 1) / 2) * 2;  // A_SC: sigma_t, Omega_x, Omega_y
+};
+
+// Columns of a class matrix K = A^-1 R (shared local matrices, p >= 3): the
+// solution of every solve of the class is K times its staged inputs, in the
+// order of the slot's area: nodal source [N] (R = J M), interior traces
+// [4][TW] (R = the inflow face terms with m), boundary data [4][TW] (with
+// w l), q_dir [Q] (R = J (w V)^T).  Stored T [NCOL][16][RS] per class, entry
+// [j][r][s] = K[r + s H][j].
+template <int P, int NQ>
+struct ClsCols {
+  static constexpr int P1 = P + 1, N = P1 * P1, Q = NQ * NQ, TW = P1 > NQ ? P1 : NQ;
+  static constexpr int C_S = 0, C_FI = N, C_FB = N + 4 * TW, C_QD = N + 8 * TW, NCOL = N + 8 * TW + Q;
+  static constexpr int RS = (N + 15) / 16;
+  static constexpr int BLOCK = NCOL * 16 * RS;
 };
 
 // Per-lane inputs of one solve (loaded ahead of it).
@@ -1781,6 +1799,108 @@ __device__ __forceinline__ void load_one(SolveInL<P, NQ, T> &in, int d, const KP
   for (int k = 0; k < SolveInL<P, NQ, T>::QD; ++k) {
     const int q = r + 16 * k;
     in.qd[k] = (pio.q_dir && q < Q) ? static_cast<T>(pio.q_dir[((size_t)d * pb.ne + e) * Q + q]) : T(0);
+  }
+}
+
+// One block of class-matrix columns [cb, cb + L) against the slot's own
+// area entries [ab, ab + L).
+template <int L, int RS, typename T>
+__device__ __forceinline__ void cls_block_own(T (&x)[RS], const T *K, const T *area, int cb, int ab) {
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    const T in = area[ab + l];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) x[s] += gload(K + (size_t)(cb + l) * 16 * RS + s) * in;
+  }
+}
+
+// One block of class-matrix columns [cb, cb + L) against area entries
+// [ab, ab + L) of the wave's four slots: slot q takes the columns q, q + 4,
+// ... and adds its share to the sums acc[t] of every slot t.
+template <int L, int RS, int AREA, typename T>
+__device__ __forceinline__ void cls_block_split(T (&acc)[4][RS], const T *K, const T *area, int cb, int ab, int q) {
+#pragma unroll
+  for (int ll = 0; ll < (L + 3) / 4; ++ll) {
+    const int l = q + 4 * ll;
+    const int lc = l < L ? l : L - 1;
+    T kv[RS];
+    if constexpr (RS == 2) {
+      typedef T V2 __attribute__((ext_vector_type(2)));
+      const V2 v = gload(reinterpret_cast<const V2 *>(K + (size_t)(cb + lc) * 16 * RS));
+      kv[0] = v.x;
+      kv[1] = v.y;
+    } else {
+#pragma unroll
+      for (int s = 0; s < RS; ++s) kv[s] = gload(K + (size_t)(cb + lc) * 16 * RS + s);
+    }
+#pragma unroll
+    for (int s = 0; s < RS; ++s) kv[s] = l < L ? kv[s] : T(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const T in = area[(t - q) * AREA + ab + lc];
+#pragma unroll
+      for (int s = 0; s < RS; ++s) acc[t][s] += kv[s] * in;
+    }
+  }
+}
+
+// x = K in for the solve's class matrix K (ClsCols) and its inputs staged in
+// the slot's area (LuLds<P, NQ, true>); rows r + s H of lane r.  When the
+// wave's four slots solve systems of one class (the usual case: a level's
+// solves are listed direction by direction) the columns are shared out over
+// the slots and a reduction across them completes each slot's sums; else
+// each slot multiplies by its own class's matrix.  Blocks of boundary data
+// and q_dir are skipped when the run has none.
+template <int P, int NQ, typename T>
+__device__ __forceinline__ void cls_product(T (&x)[LuShape<P>::RS], const KProb &pb, const KIO &pio, const T *area,
+                                            bool valid, int cls, int r) {
+  using C = ClsCols<P, NQ>;
+  using LD = LuLds<P, NQ, true>;
+  constexpr int RS = LuShape<P>::RS, TW = C::TW;
+  const int q = (threadIdx.x & 63) >> 4;
+  const bool bc = pio.psi_bc != nullptr, qd = pio.q_dir != nullptr;
+  const int cl = valid ? cls : -1;
+  int c0 = __builtin_amdgcn_readfirstlane(cl);
+  c0 = c0 < 0 ? 0 : c0;
+  const bool same = __builtin_amdgcn_ballot_w64(cl >= 0 && cl != c0) == 0;
+  const T *K = static_cast<const T *>(pb.cls_inv) + r * RS;
+  if (same) {
+    K += (size_t)c0 * C::BLOCK;
+    T acc[4][RS];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int s = 0; s < RS; ++s) acc[t][s] = T(0);
+    cls_block_split<C::N, RS, LD::AREA>(acc, K, area, C::C_S, LD::A_S, q);
+    cls_block_split<4 * TW, RS, LD::AREA>(acc, K, area, C::C_FI, LD::A_TR, q);
+    if (bc) cls_block_split<4 * TW, RS, LD::AREA>(acc, K, area, C::C_FB, LD::A_TB, q);
+    if (qd) cls_block_split<C::Q, RS, LD::AREA>(acc, K, area, C::C_QD, LD::A_QD, q);
+    // reduce-scatter over the slots: slot q keeps the sums of its own
+    // inputs, exchanging with slot q ^ 1 (lanes 16 apart), then q ^ 2 (32)
+    const bool o1 = (q & 1) != 0, o2 = (q & 2) != 0;
+    T h[2][RS];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int s = 0; s < RS; ++s) {
+        const T keep = o1 ? acc[2 * tt + 1][s] : acc[2 * tt][s];
+        const T give = o1 ? acc[2 * tt][s] : acc[2 * tt + 1][s];
+        h[tt][s] = keep + __shfl_xor(give, 16);
+      }
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const T keep = o2 ? h[1][s] : h[0][s];
+      const T give = o2 ? h[0][s] : h[1][s];
+      x[s] = keep + __shfl_xor(give, 32);
+    }
+  } else {
+    K += (size_t)(cls < 0 ? 0 : cls) * C::BLOCK;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) x[s] = T(0);
+    cls_block_own<C::N, RS>(x, K, area, C::C_S, LD::A_S);
+    cls_block_own<4 * TW, RS>(x, K, area, C::C_FI, LD::A_TR);
+    if (bc) cls_block_own<4 * TW, RS>(x, K, area, C::C_FB, LD::A_TB);
+    if (qd) cls_block_own<C::Q, RS>(x, K, area, C::C_QD, LD::A_QD);
   }
 }
 
@@ -1870,10 +1990,11 @@ __device__ __forceinline__ void lu_core(int e, int d, bool valid, int flags, con
   // before the matrix is live): b = J (m (x) m) s + J (w V)^T q_dir - the
   // inflow face terms; A[(a,b)][(c,d)] = m_bd (stJ m_ac - gx gd_ac)
   // - gd_bd (gy m_ac) (test index first), plus (Omega . N_f) m on the
-  // outflow faces
+  // outflow faces.  With class matrices (CLS) none of this: the solution is
+  // the class matrix times the staged inputs.
   T A[RS][N + 1];
 #pragma unroll
-  for (int s = 0; s < RS; ++s) {
+  for (int s = 0; s < RS && !CLS; ++s) {
     const int row = r + s * H;
     const bool row_ok = valid && r < H && row < N;
     const int rr = (r < H && row < N) ? row : N - 1;
@@ -1923,32 +2044,7 @@ __device__ __forceinline__ void lu_core(int e, int d, bool valid, int flags, con
   }
   T x[RS];
   if constexpr (CLS) {
-    // a shared local matrix: x = A^-1 b with the inverse of the solve's
-    // class (block [n][16][RS]: entry [j][r][s] = (A^-1)[r + s H][j]), b
-    // broadcast from the slot's area once every lane has read the sources
-    wave_sync_lds();
-#pragma unroll
-    for (int s = 0; s < RS; ++s) {
-      const int row = r + s * H;
-      if (r < H && row < N) area[LD::A_S + row] = A[s][N];
-    }
-    wave_sync_lds();
-    const T *iv = static_cast<const T *>(pb.cls_inv) + (size_t)cls * (N * 16 * RS) + r * RS;
-#pragma unroll
-    for (int s = 0; s < RS; ++s) x[s] = T(0);
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const T bj = area[LD::A_S + j];
-      if constexpr (RS == 2) {
-        typedef T V2 __attribute__((ext_vector_type(2)));
-        const V2 v = gload(reinterpret_cast<const V2 *>(iv + j * 16 * RS));
-        x[0] += v.x * bj;
-        x[1] += v.y * bj;
-      } else {
-#pragma unroll
-        for (int s = 0; s < RS; ++s) x[s] += gload(iv + j * 16 * RS + s) * bj;
-      }
-    }
+    cls_product<P, NQ, T>(x, pb, pio, area, valid, cls, r);
   } else {
 #pragma unroll
     for (int s = 0; s < RS; ++s) {
@@ -2184,13 +2280,14 @@ __device__ __forceinline__ void lu_prefetch(LuPre<P, NQ, T> &x, int e, int d, in
 }
 
 // Stage a prefetched solve in the slot's area; the direction-dependent
-// source q_dir (not prefetched) is read here.
-template <int P, int NQ, typename T>
+// source q_dir (not prefetched) is read here.  CLS: the area of the class
+// matrices, boundary data apart from the traces.
+template <int P, int NQ, typename T, bool CLS = false>
 __device__ __forceinline__ void lu_stage(const LuPre<P, NQ, T> &x, T *area, const KProb &pb, const KIO &pio, int e,
                                          int d, bool valid, int r) {
 #pragma clang fp contract(off)
   using X = LuPre<P, NQ, T>;
-  using LD = LuLds<P, NQ>;
+  using LD = LuLds<P, NQ, CLS>;
   constexpr int N = (P + 1) * (P + 1), Q = NQ * NQ;
   constexpr bool kWide = sizeof(T) == sizeof(double);
   area[LD::A_G + r] = x.g;
@@ -2219,7 +2316,13 @@ __device__ __forceinline__ void lu_stage(const LuPre<P, NQ, T> &x, T *area, cons
       if constexpr (!kWide) {
         if ((x.use >> (8 + k)) & 1) v = static_cast<T>(x.bc[k]);
       }
-      area[LD::A_TR + r + 16 * k] = v;
+      if constexpr (CLS) {
+        const bool bnd = (x.use >> (8 + k)) & 1;
+        area[LD::A_TR + r + 16 * k] = bnd ? T(0) : v;
+        area[LD::A_TB + r + 16 * k] = bnd ? v : T(0);
+      } else {
+        area[LD::A_TR + r + 16 * k] = v;
+      }
     }
   if (r < 3) area[LD::A_SC + r] = x.sc;
 }
@@ -2227,12 +2330,12 @@ __device__ __forceinline__ void lu_stage(const LuPre<P, NQ, T> &x, T *area, cons
 constexpr int kLuStreamMax = 16;  // solves per slot and launch (one per lane of the slot)
 
 template <int P, int NQ, typename T, bool FIX, bool CLS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CLS ? (sizeof(T) == 4 ? 4 : 3) : sizeof(T) == 4 ? 3 : 2)))
 k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__restrict__ probs,
                   const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
                   int *__restrict__ status) {
   using S = LuShape<P>;
-  using LD = LuLds<P, NQ>;
+  using LD = LuLds<P, NQ, CLS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
   const int lane = threadIdx.x & 63;
@@ -2286,7 +2389,7 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
     const int e = a.x, d = a.y, fl = a.z;
     const bool valid = (long long)sid0 + (long long)k * n_slots < n_solves;
     wave_sync_lds();  // the previous solve is done with the area
-    lu_stage<P, NQ, T>(nx, area, pb, pio, e, d, valid, r);
+    lu_stage<P, NQ, T, CLS>(nx, area, pb, pio, e, d, valid, r);
     wave_sync_lds();
     if (k + 1 < n_it) prefetch(k + 1);
     // only the sign of a neighbour index is used by the solve
@@ -2297,18 +2400,24 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
   }
 }
 
-// Inverse of the local matrix of one class of solves that share it (one
-// work-group of 64 threads per class, see ClassInvLaunch): thread i < n
-// assembles row i in double from the element's geometry, sigma_t and the
-// direction, as the row-set LU does; then Gauss-Jordan elimination with
-// partial pivoting on [A | I] in LDS.
+// Class matrix K = A^-1 R (ClsCols) of one class of solves that share their
+// local matrix A (one work-group of 64 threads per class, see
+// ClassInvLaunch): thread i < n assembles row i of A and of R in double from
+// the representative element's geometry, sigma_t and the direction, as the
+// row-set LU assembles A and b; then Gauss-Jordan elimination with partial
+// pivoting on [A | R] in LDS.  R maps the staged inputs to b: J M for the
+// nodal source, -(Omega . N_f) m (interior traces) or -(Omega . N_f) w l
+// (boundary data) on the rows of each inflow face f, J (w V)^T for q_dir.
 template <int P, int NQ, typename T>
 __global__ void __launch_bounds__(64)
 k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const T *__restrict__ tables,
             T *__restrict__ out, int *__restrict__ status) {
   using S = LuShape<P>;
-  constexpr int P1 = S::P1, N = S::N, RS = S::RS, H = S::H, W = 2 * N;
-  __shared__ double m1[P1 * P1], gd[P1 * P1];
+  using C = ClsCols<P, NQ>;
+  using SH = Shape<P, NQ>;
+  constexpr int P1 = S::P1, N = S::N, RS = S::RS, H = S::H, Q = C::Q, TW = C::TW;
+  constexpr int W = N + C::NCOL;
+  __shared__ double m1[P1 * P1], gd[P1 * P1], wl[NQ * P1];
   __shared__ double M[N][W + 1];
   __shared__ double fac[N];
   __shared__ int piv;
@@ -2316,26 +2425,39 @@ k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const
   const int4 rp = rep[blockIdx.x];
   const KProb &pb = probs[0];
   for (int i = t; i < P1 * P1; i += 64) {
-    m1[i] = static_cast<double>(tables[Shape<P, NQ>::A_M1 + i]);
-    gd[i] = static_cast<double>(tables[Shape<P, NQ>::A_GD1 + i]);
+    m1[i] = static_cast<double>(tables[SH::A_M1 + i]);
+    gd[i] = static_cast<double>(tables[SH::A_GD1 + i]);
   }
+  for (int i = t; i < NQ * P1; i += 64) wl[i] = static_cast<double>(tables[SH::A_WL + i]);
+  for (int x = t; x < N * W; x += 64) M[x / W][x % W] = 0.0;
   __syncthreads();
   if (t < N) {
     const T *g = static_cast<const T *>(pb.geo_a) + (size_t)rp.x * 16;
     const double ox = pb.omega[2 * rp.y], oy = pb.omega[2 * rp.y + 1];
-    const double stJ = pb.sig[2 * rp.x] * static_cast<double>(g[0]);
+    const double J = static_cast<double>(g[0]);
+    const double stJ = pb.sig[2 * rp.x] * J;
     const double gx = static_cast<double>(g[1]) * ox + static_cast<double>(g[2]) * oy;
     const double gy = static_cast<double>(g[3]) * ox + static_cast<double>(g[4]) * oy;
+    const unsigned inflow = (unsigned)rp.z & 15u;
     double on[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) on[f] = ox * static_cast<double>(g[5 + 2 * f]) + oy * static_cast<double>(g[6 + 2 * f]);
     double row[N];
-    affine_lu_row<P, double>(row, t, m1, gd, stJ, gx, gy, on, (unsigned)rp.z & 15u);
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      M[t][j] = row[j];
-      M[t][N + j] = j == t ? 1.0 : 0.0;
+    affine_lu_row<P, double>(row, t, m1, gd, stJ, gx, gy, on, inflow);
+    for (int j = 0; j < N; ++j) M[t][j] = row[j];
+    const int a = t % P1, b = t / P1;
+    double *R = &M[t][N];
+    for (int dd = 0; dd < P1; ++dd)
+      for (int c = 0; c < P1; ++c) R[C::C_S + c + P1 * dd] = J * m1[a * P1 + c] * m1[b * P1 + dd];
+    for (int f = 0; f < 4; ++f) {
+      const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+      if (!((inflow >> f) & 1u) || !on_face) continue;
+      const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+      for (int c = 0; c < P1; ++c) R[C::C_FI + f * TW + c] = -on[f] * m1[pos * P1 + c];
+      for (int qq = 0; qq < NQ; ++qq) R[C::C_FB + f * TW + qq] = -on[f] * wl[qq * P1 + pos];
     }
+    const T *wv = tables + SH::A_WV;
+    for (int qq = 0; qq < Q; ++qq) R[C::C_QD + qq] = J * static_cast<double>(wv[qq * N + t]);
   }
   __syncthreads();
   for (int k = 0; k < N; ++k) {
@@ -2370,8 +2492,8 @@ k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const
     for (int j = t; j < W; j += 64) M[k][j] /= pk;
     __syncthreads();
   }
-  T *o = out + (size_t)blockIdx.x * (N * 16 * RS);
-  for (int x = t; x < N * 16 * RS; x += 64) {
+  T *o = out + (size_t)blockIdx.x * C::BLOCK;
+  for (int x = t; x < C::BLOCK; x += 64) {
     const int j = x / (16 * RS), r = (x / RS) % 16, s = x % RS;
     const int row = r + s * H;
     o[x] = (r < H && row < N) ? static_cast<T>(M[row][N + j]) : T(0);
@@ -2469,7 +2591,10 @@ hipError_t launch_level_lu_t(const SweepLaunch &L) {
     int grid = (L.count + per_block - 1) / per_block;
     if (grid == 0) return hipSuccess;
     if (!L.desc) return hipErrorInvalidValue;
-    const size_t bytes_s = bytes + sizeof(int) * 8 * kLuStreamMax * per_block;  // + the descriptor tables
+    // + the descriptor tables (the class-matrix form has larger areas)
+    const size_t area_s = L.shared ? LuLds<P, NQ, true>::AREA : LD::AREA;
+    const size_t bytes_s =
+        sizeof(T) * ((size_t)LD::TAB + area_s * per_block) + sizeof(int) * 8 * kLuStreamMax * per_block;
     if (L.single && L.n_cu > 0 && bytes_s <= L.lds_max) {
       // streaming form: the resident work-groups, and enough of them that a
       // slot has at most kLuStreamMax solves

@@ -123,16 +123,17 @@ def _shared_class_count(pr, s=8):
     (the corners' offsets from the first corner, compared exactly) and the
     same direction, which then fixes the inflow faces.  0 where the
     library's rule declines them (more than 4096 element classes, fewer than
-    8 solves per class, or more than 8 MiB of inverses)."""
+    8 solves per class, or more than 16 MiB of class matrices)."""
     xy = pr.cp_xy[pr.elem_cp]  # [ne][(m+1)^2][2]
     shape = xy - xy[:, :1, :]
     keys = {}
     for e in range(pr.n_elem):
         keys.setdefault((pr.sigma_t[e],) + tuple(shape[e].ravel()), len(keys))
     n_cls = len(keys) * pr.n_dir
-    n = (pr.p + 1) ** 2
-    inv_bytes = n * 16 * ((n + 15) // 16) * s
-    if len(keys) > 4096 or n_cls * 8 > pr.n_elem * pr.n_dir or n_cls * inv_bytes > (8 << 20):
+    n, nq = (pr.p + 1) ** 2, pr.nq or pr.p + pr.m
+    tw = max(pr.p + 1, nq)
+    inv_bytes = (n + 8 * tw + nq * nq) * 16 * ((n + 15) // 16) * s
+    if len(keys) > 4096 or n_cls * 8 > pr.n_elem * pr.n_dir or n_cls * inv_bytes > (16 << 20):
         return 0
     return n_cls
 
