@@ -58,6 +58,17 @@ def flops_per_solve(p):
     return (2.0 / 3.0) * n ** 3 + 2 * n * n + 6 * n * n + 2 * n * n + 12 * (p + 1) ** 2 + 12 * n
 
 
+def flops_per_solve_shared(p):
+    """Algorithmic flops of one solve by the matrix K = A^-1 R of its class of
+    shared local matrices: the product with the nodal source (n columns) and
+    with the traces of the two inflow faces (2 (p+1) columns),
+    2 n (n + 2 (p+1)), and the six angular moments (12 n).  Forming K once
+    per class and run (O(n^3)) is amortised over the class's solves and left
+    out (under one flop per solve at 512x512, S16)."""
+    n = (p + 1) ** 2
+    return 2 * n * (n + 2 * (p + 1)) + 12 * n
+
+
 def bytes_per_solve(p, m, n_dir, s):
     """Algorithmic HBM bytes of one solve: the angular flux written (n s), the
     upwind trace read (2 (p+1) s), and per element the control points, cross
@@ -68,11 +79,13 @@ def bytes_per_solve(p, m, n_dir, s):
     return n * s + 2 * (p + 1) * s + ((m + 1) ** 2 * 16 + 16 + 8 * n + 48 * n) / (n_dir / 4.0)
 
 
-def roofline(probs, s, sweep_s, launches_per_sweep, kernel, alu_peak, traffic=None):
+def roofline(probs, s, sweep_s, launches_per_sweep, kernel, alu_peak, traffic=None, shared=False):
     """Roofline of the sweep kernel over one sweep of probs: algorithmic flops
     and bytes per launch against the average launch duration; the bound is
-    the ALU when F/B exceeds the machine balance, else HBM."""
-    F = sum(pr.n_elem * pr.n_dir * flops_per_solve(pr.p) for pr in probs)
+    the ALU when F/B exceeds the machine balance, else HBM.  shared: the
+    solves go through their class matrices (flops_per_solve_shared)."""
+    fps = flops_per_solve_shared if shared else flops_per_solve
+    F = sum(pr.n_elem * pr.n_dir * fps(pr.p) for pr in probs)
     B = sum(pr.n_elem * pr.n_dir * bytes_per_solve(pr.p, pr.m, pr.n_dir, s) for pr in probs)
     solves = sum(pr.n_elem * pr.n_dir for pr in probs)
     L = max(launches_per_sweep, 1)
@@ -225,7 +238,7 @@ def workload_leg(name, steps, warmup, schedule):
         out[prec] = {"ms_per_step": ms, "solves_per_s": solves / (ms * 1e-3), "schedule": g["schedule"],
                      "tuning": g["tuned"], "sweep_ms": g["sweep_ms"],
                      "roofline": roofline(probs, s, g["sweep_ms"] * 1e-3, g["launches"], kname, peak,
-                                          measured_traffic(kname)),
+                                          measured_traffic(kname), shared=g["kernel"] == 7),
                      "rel_inf_vs_oracle": fixture_error(cfg["fixture"], g["mom"])}
     out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
     return out
@@ -642,7 +655,7 @@ def main():
     value = solves_per_step * args.steps / g64["seconds"]
     kname = kernel_name(g64, pr)
     roof = roofline(probs, 8, g64["sweep_ms"] * 1e-3, g64["launches"], kname, FP64_PEAK_TFLOPS,
-                    measured_traffic(kname))
+                    measured_traffic(kname), shared=g64["kernel"] == 7)
     roof.update(levels_per_sweep=g64["n_levels"], measured_peak=machine["fp64_fma_tflops"],
                 frac_of_measured_peak=roof["alu_tflops"] / machine["fp64_fma_tflops"],
                 # lower bounds of one sweep: HBM traffic, FP64 ALU work, and the chain of dependent
@@ -659,6 +672,7 @@ def main():
         "config": {"workload": cfg["text"], "name": args.workload, "n_elem": pr.n_elem, "p": pr.p,
                    "n_dir": pr.n_dir, "sweeps_per_step": n_iter,
                    "schedule": ("autotuned: " if g64["tuned"] else "") + g64["schedule"],
+                   "kernel": vef.KERNEL_NAMES[g64["kernel"]],
                    "tuning": g64["tuned"], "precision": "fp64"},
         "rel_inf_vs_oracle": fixture_error(cfg["fixture"], g64["mom"]),
         "roofline": roof,
@@ -676,7 +690,8 @@ def main():
                                 "within_1e-5_of_oracle": (ora["phi"] <= 1e-5) if ora else None,
                                 "rel_inf_phi_vs_fp64_path": err,
                                 "roofline": roofline(probs, 4, g32["sweep_ms"] * 1e-3, g32["launches"], k32,
-                                                     FP32_PEAK_TFLOPS, measured_traffic(k32))}
+                                                     FP32_PEAK_TFLOPS, measured_traffic(k32),
+                                                     shared=g32["kernel"] == 7)}
     for leg in ("c3", "c2"):
         if leg in legs and leg != args.workload:
             result["workload_" + leg] = workload_leg(leg, args.steps, args.warmup, args.schedule)

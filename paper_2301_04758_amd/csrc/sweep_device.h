@@ -2343,12 +2343,31 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
   const int slot = (threadIdx.x >> 6) * S::SPW + (lane >> 4);
   const int per_block = (blockDim.x >> 6) * S::SPW;
   const int n_slots = gridDim.x * per_block;
+  // Slot s of work-group b takes the solves b per_block + s + k n_slots
   // (plain block order: the XCD-aware order halves the HBM reads of the
-  // element data here but measured slower on the 512x512 p = 4 sweep)
-  const int sid0 = blockIdx.x * per_block + slot;
-  const int sidw = blockIdx.x * per_block + (threadIdx.x >> 6) * S::SPW;  // first slot of the wave
-  // the host sizes the grid so that no slot has more than kLuStreamMax solves
-  const int n_it = sidw < n_solves ? (n_solves - sidw + n_slots - 1) / n_slots : 0;
+  // element data of the row-set LU but measured slower on the 512x512 p = 4
+  // sweep).  With class matrices (CLS) the solves are cut into kXcds
+  // contiguous ranges, one per XCD (work-groups go to the XCDs round robin;
+  // the host makes the grid a multiple of kXcds), taken in the same strided
+  // order within the range: a level's solves are listed direction by
+  // direction, so each XCD's L2 holds the matrices of about an eighth of the
+  // classes.  The host sizes the grid so that no slot has more than
+  // kLuStreamMax solves.
+  int sid0, stride, lim;
+  if constexpr (CLS) {
+    const int nxb = gridDim.x / kXcds, x = blockIdx.x % kXcds;
+    const int chunk = (n_solves + kXcds - 1) / kXcds;
+    const int lo = x * chunk;
+    lim = lo + chunk < n_solves ? lo + chunk : n_solves;
+    sid0 = lo + (blockIdx.x / kXcds) * per_block + slot;
+    stride = nxb * per_block;
+  } else {
+    sid0 = blockIdx.x * per_block + slot;
+    stride = n_slots;
+    lim = n_solves;
+  }
+  const int sidw = sid0 - (lane >> 4);  // first slot of the wave
+  const int n_it = sidw < lim ? (lim - sidw + stride - 1) / stride : 0;
   const KProb &pb = probs[0];
   const KIO &pio = io[0];
 
@@ -2359,8 +2378,8 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
   int *dtab = reinterpret_cast<int *>(lds + LD::TAB + (size_t)per_block * LD::AREA) + slot * (kLuStreamMax * 8);
   int4 da = make_int4(0, 0, 0, 0), db = make_int4(-1, -1, -1, -1);
   {
-    const long long sid = (long long)sid0 + (long long)r * n_slots;
-    if (sid < n_solves) {
+    const long long sid = (long long)sid0 + (long long)r * stride;
+    if (sid < lim) {
       da = desc[2 * sid];
       db = desc[2 * sid + 1];
     }
@@ -2380,14 +2399,13 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
     const int4 a = reinterpret_cast<const int4 *>(dtab + k * 8)[0];
     const int4 b = reinterpret_cast<const int4 *>(dtab + k * 8)[1];
     const int nb[4] = {b.x, b.y, b.z, b.w};
-    lu_prefetch<P, NQ, T>(nx, a.x, a.y, a.z, nb, (long long)sid0 + (long long)k * n_slots < n_solves, pb, pio, it,
-                          r);
+    lu_prefetch<P, NQ, T>(nx, a.x, a.y, a.z, nb, (long long)sid0 + (long long)k * stride < lim, pb, pio, it, r);
   };
   prefetch(0);
   for (int k = 0; k < n_it; ++k) {
     const int4 a = reinterpret_cast<const int4 *>(dtab + k * 8)[0];
     const int e = a.x, d = a.y, fl = a.z;
-    const bool valid = (long long)sid0 + (long long)k * n_slots < n_solves;
+    const bool valid = (long long)sid0 + (long long)k * stride < lim;
     wave_sync_lds();  // the previous solve is done with the area
     lu_stage<P, NQ, T, CLS>(nx, area, pb, pio, e, d, valid, r);
     wave_sync_lds();
@@ -2618,9 +2636,20 @@ hipError_t launch_level_lu_t(const SweepLaunch &L) {
         if (cacheable) cache[dev][block / 64 - 1][cv].store(per_cu, std::memory_order_relaxed);
       }
       const int cap = per_block * kLuStreamMax;
-      const int lo = (L.count + cap - 1) / cap;
       const int res = per_cu * L.n_cu;
-      if (grid > res) grid = res > lo ? res : lo;
+      if (L.shared) {
+        // a multiple of kXcds work-groups, each XCD's covering an eighth of
+        // the solves (see k_sweep_level_lus)
+        const int per_x = (L.count + kXcds - 1) / kXcds;
+        const int need = (per_x + per_block - 1) / per_block, lo_x = (per_x + cap - 1) / cap;
+        int gx = res / kXcds;
+        if (gx > need) gx = need;
+        if (gx < lo_x) gx = lo_x;
+        grid = gx * kXcds;
+      } else {
+        const int lo = (L.count + cap - 1) / cap;
+        if (grid > res) grid = res > lo ? res : lo;
+      }
       if (L.shared)
         hipLaunchKernelGGL((k_sweep_level_lus<P, NQ, T, FIX, true>), dim3(grid), dim3(block), bytes_s, L.stream,
                            L.desc, L.count, L.probs, L.io, static_cast<const T *>(L.tables), L.it, L.stop, L.status);
