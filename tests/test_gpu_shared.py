@@ -1,7 +1,9 @@
 """Affine elements of degree 3 and 4 whose local matrices repeat (uniform
-grids with a few materials): each run inverts one matrix per class of
-(direction, element) pairs that share it, and the level-synchronous sweep
-solves each local system as a product with its class's inverse.  Checked
+grids with a few materials): each run forms one matrix per class of
+(direction, element) pairs that share their local matrix A, K = A^-1 R with R
+the map from a solve's inputs to its right-hand side, and the
+level-synchronous sweep computes each local solution as K times the solve's
+inputs.  Checked
 against the oracle and against the row-set LU (shared_matrices=False) on the
 same inputs, with the paths that feed the right-hand side: a scalar flux and
 isotropic source, the direction-dependent source and boundary inflow data,
@@ -75,14 +77,14 @@ def test_shared_matrices_match_oracle_and_lu(torch, precision, p):
     assert rel_inf(b["psi"], ref["psi"]) <= tol
     for k in range(6):
         assert rel_inf(a["mom"][k], ref["mom"][k], np.abs(ref["mom"][0]).max()) <= tol
-    # the same systems solved by elimination and by the inverse
+    # the same systems solved by elimination and by the class matrices
     assert rel_inf(a["psi"], b["psi"]) <= (1e-13 if precision == "fp64" else tol)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_shared_matrices_source_iteration(torch, precision):
-    """Four source iterations: the inverses formed before the first sweep
-    serve every sweep of the run."""
+    """Four source iterations: the class matrices formed before the first
+    sweep serve every sweep of the run."""
     pr, _ = _uniform_case(4, seed=6, with_mms=False)
     pr.sigma_s = 0.95 * pr.sigma_t
     ref = O.source_iteration(pr, 4)
@@ -94,7 +96,7 @@ def test_shared_matrices_source_iteration(torch, precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_shared_matrices_fixup(torch, precision):
     """Thick cells with a source in one corner: negative values are zeroed
-    and the rest scaled, after the product with the inverse."""
+    and the rest scaled, after the product with the class matrix."""
     pr = _small(8, 8, 4, 1, 4, st=200.0, q=0.0)
     pr.q_iso[0] = 50.0
     ref = O.sweep(pr, fixup=True)
@@ -121,7 +123,7 @@ def test_shared_matrices_only_where_they_repeat(torch):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_autotune_weighs_shared_matrices_against_lu(torch, precision):
     """The autotuner times the level-synchronous kernels with the class
-    inverses and with the row-set LU; the handle then runs what it reports."""
+    matrices and with the row-set LU; the handle then runs what it reports."""
     from paper_2301_04758_amd import vef
     pr, phi = _uniform_case(4, seed=2)
     ref = O.sweep(pr, phi_in=phi)
@@ -143,8 +145,8 @@ def test_autotune_weighs_shared_matrices_against_lu(torch, precision):
 
 
 def test_shared_matrices_runs_are_deterministic(torch):
-    """Two runs of one handle give the same bits (the inverses are formed
-    again by the second run)."""
+    """Two runs of one handle give the same bits (the class matrices are
+    formed again by the second run)."""
     from paper_2301_04758_amd import vef
     pr, phi = _uniform_case(4, seed=9)
     sw = vef.Sweep([pr], precision="fp64", schedule="level")
@@ -157,3 +159,37 @@ def test_shared_matrices_runs_are_deterministic(torch):
         outs.append(io[0]["psi_out"].cpu().numpy().copy())
     sw.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_shared_matrices_graph_replays(torch, precision):
+    """A run with class matrices (their formation included) captured in a HIP
+    graph: every replay, with eager work on the same buffers in between,
+    gives the bits of the eager run."""
+    from paper_2301_04758_amd import vef
+    pr, phi = _uniform_case(4, seed=4, with_mms=False)
+    pr.sigma_s = 0.9 * pr.sigma_t
+    print("shared graph capture", precision, flush=True)
+    sw = vef.Sweep([pr], precision=precision, schedule="level")
+    assert vef.KERNEL_NAMES[sw.info[0]["kernel"]] == "affine_shared"
+    io = sw.buffers(n_iter=3, phi_in=phi)
+    sw.run(io, n_iter=3)
+    torch.cuda.synchronize()
+    sw.check()
+    ref = {k: io[0][k].clone() for k in ("mom", "psi_out", "resid")}
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sw.run(io, n_iter=3)
+    for rep in range(3):
+        io[0]["mom"].fill_(-1.0)  # eager work between replays
+        io[0]["psi_out"].zero_()
+        io[0]["resid"].zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        sw.check()
+        for key in ("mom", "psi_out", "resid"):
+            assert torch.equal(io[0][key], ref[key]), (rep, key)
+    del g
+    sw.close()
+    assert rel_inf(ref["mom"][0].cpu().numpy(), O.source_iteration(pr, 3, phi0=phi)["mom"][0]) <= TOL[precision]
