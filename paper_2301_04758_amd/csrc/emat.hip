@@ -15,6 +15,11 @@
 // chunks of 4 points (zero padded), the B operand (V) shared by all three.
 // The face matrices F^c_f[pos][k] = sum_s (w n_c ds)_s L_s,pos L_s,k (L the
 // 1D basis at the face points) take one lane each.
+//
+// Layout per element: M, G^x, G^y, each with entry (i, j) at
+// ((j / W) 16 + i) W + j % W, W = 16 bytes / sizeof(T) (so that the 16 lanes
+// of a solve, lane i reading row i, read 16 W consecutive values per 16-byte
+// load), then the face matrices [f][component][pos][k].
 
 #include <hip/hip_runtime.h>
 
@@ -58,13 +63,15 @@ __global__ void __launch_bounds__(256) k_elem_mat(int ne, const double *__restri
     cy = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, bv, cy, 0, 0, 0);
   }
   T *o = out + (size_t)e * SIZE;
+  constexpr int W = 16 / sizeof(T);
   const int j = lane & 15;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = (lane >> 4) + 4 * v;
-    o[row * N + j] = static_cast<T>(m[v]);
-    o[N * N + row * N + j] = static_cast<T>(cx[v]);
-    o[2 * N * N + row * N + j] = static_cast<T>(cy[v]);
+    const int at = ((j / W) * 16 + row) * W + j % W;
+    o[at] = static_cast<T>(m[v]);
+    o[N * N + at] = static_cast<T>(cx[v]);
+    o[2 * N * N + at] = static_cast<T>(cy[v]);
   }
   // face matrices: lane = 16 f + 4 pos + k
   {

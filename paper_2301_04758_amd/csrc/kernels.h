@@ -13,7 +13,8 @@ struct KProb {
   const void *geo_v;       // T [ne][Q][5]: w J, w adj(F) (row major)
   const void *geo_f;       // T [ne][4][nq][2]: w_s n ds
   const void *geo_a;       // T [ne][16]: J, adj(F) (row major), face chords N_0..N_3 (affine meshes)
-  const void *emat;        // T [ne][3 n n + 8 (p+1)^2]: element matrices (general elements, p = 3), or NULL
+  const void *emat;        // T [ne][3 n n + 8 (p+1)^2]: element matrices (general elements, p = 3; layout in
+                           // emat.hip), or NULL
   const void *cls_inv;     // T [n_cls][ncol][16][RS]: class matrices of shared local matrices (affine, p >= 3), or NULL
   const double *geo_fd;    // double copy of geo_f
   const int32_t *nbr;      // [ne][4] neighbour or -(bf+1)

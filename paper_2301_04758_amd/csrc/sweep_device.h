@@ -785,14 +785,26 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
   const int a = rr % P1, b = rr / P1;
   const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
 
-  // the lane's rows of M, G^x, G^y and of the face matrices of its faces
+  // the lane's rows of M, G^x, G^y (entry (i, j) at ((j / W) 16 + i) W + j %
+  // W: the slot's 16 lanes read 16 W consecutive values per 16-byte load)
   const T *em = static_cast<const T *>(pb.emat) + (size_t)(valid ? e : 0) * EM::SIZE;
   T mr[N], gx[N], gy[N];
+  {
+    constexpr int W = 16 / sizeof(T);
+    typedef T VW __attribute__((ext_vector_type(W)));
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    mr[j] = gload(em + rr * N + j);
-    gx[j] = gload(em + EM::OFF_GX + rr * N + j);
-    gy[j] = gload(em + EM::OFF_GY + rr * N + j);
+    for (int jj = 0; jj < N / W; ++jj) {
+      const int at = (jj * 16 + rr) * W;
+      const VW vm = gload(reinterpret_cast<const VW *>(em + at));
+      const VW vx = gload(reinterpret_cast<const VW *>(em + EM::OFF_GX + at));
+      const VW vy = gload(reinterpret_cast<const VW *>(em + EM::OFF_GY + at));
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        mr[W * jj + w] = vm[w];
+        gx[W * jj + w] = vx[w];
+        gy[W * jj + w] = vy[w];
+      }
+    }
   }
   // the face matrices [4][2][P1][P1] and the upwind traces [4][P1] go
   // through the slot's LDS area, each lane loading a share, so that they hold
