@@ -157,12 +157,36 @@ __global__ void k_finalize(const KIO *__restrict__ io, int n_probs, int it, doub
 }
 
 // Closures at volume points (E, Q0, Q1) and boundary points (E_b, J_in).
+// The direction weights and cosines are staged in LDS as (w, w ox, w oy);
+// without a direction-dependent source, Q0 and Q1 at a point are q_iso times
+// the sums of those over the directions, formed once per work-group in
+// direction order (so every work-group has the same values).
 __global__ void __launch_bounds__(256)
 k_closures(const KProb *__restrict__ probs, const KMomIO *__restrict__ mio, int prob, int ne, int Q,
            int nbf, int nq) {
+  __shared__ double3 dirs[kMaxMomDirs];
+  __shared__ double wsum[3];
   const KProb &pb = probs[prob];
   const KMomIO &io = mio[prob];
   const int n = pb.n;
+  const int nd = pb.nd;
+  for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+    const double w = pb.weight[d];
+    dirs[d] = make_double3(w, w * pb.omega[2 * d], w * pb.omega[2 * d + 1]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int d = 0; d < nd; ++d) {
+      s0 += dirs[d].x;
+      s1 += dirs[d].y;
+      s2 += dirs[d].z;
+    }
+    wsum[0] = s0;
+    wsum[1] = s1;
+    wsum[2] = s2;
+  }
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nvol = ne * Q;
   int bad = 0;
@@ -193,12 +217,17 @@ k_closures(const KProb *__restrict__ probs, const KMomIO *__restrict__ mio, int 
       if (io.q_iso)
         for (int j = 0; j < n; ++j) qi += io.q_iso[(size_t)e * n + j] * V[j];
       double s0 = 0, s1 = 0, s2 = 0;
-      for (int d = 0; d < pb.nd; ++d) {
-        const double qq = qi + (io.q_dir ? io.q_dir[((size_t)d * ne + e) * Q + q] : 0.0);
-        const double w = pb.weight[d];
-        s0 += w * qq;
-        s1 += w * pb.omega[2 * d] * qq;
-        s2 += w * pb.omega[2 * d + 1] * qq;
+      if (io.q_dir) {
+        for (int d = 0; d < nd; ++d) {
+          const double qq = qi + io.q_dir[((size_t)d * ne + e) * Q + q];
+          s0 += dirs[d].x * qq;
+          s1 += dirs[d].y * qq;
+          s2 += dirs[d].z * qq;
+        }
+      } else {
+        s0 = qi * wsum[0];
+        s1 = qi * wsum[1];
+        s2 = qi * wsum[2];
       }
       if (io.Q0) io.Q0[i] = s0;
       if (io.Q1) {
