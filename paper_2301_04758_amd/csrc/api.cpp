@@ -1059,7 +1059,7 @@ int vef_moments(vef_sweep_t *h, const vef_moment_io *io, void *stream) {
   if (he != hipSuccess) return hip_fail(h, he, "upload closure pointers");
   for (int k = 0; k < np; ++k) {
     const auto &pl = h->plans[k];
-    he = vefk::launch_closures(h->d_probs, h->d_mio, k, pl.ne, pl.Q, pl.nbf, pl.nq, s);
+    he = vefk::launch_closures(h->d_probs, h->d_mio, k, pl.ne, pl.Q, pl.n, pl.nbf, pl.nq, s);
     if (he != hipSuccess) return hip_fail(h, he, "launch closures");
   }
   h->last_stream = s;

@@ -107,7 +107,7 @@ hipError_t launch_run_init(const KIO *io, int n_probs, int n_iter, int *stop, in
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 hipError_t launch_finalize(const KIO *io, int n_probs, int it, double tol, int *stop, int *iters,
                            int *iters_user, hipStream_t s);
-hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int nbf,
+hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int n, int nbf,
                            int nq, hipStream_t s);
 hipError_t launch_zero_nonpos(const KMomIO *io, int n_probs, hipStream_t s);
 

@@ -160,12 +160,22 @@ __global__ void k_finalize(const KIO *__restrict__ io, int n_probs, int it, doub
 // The direction weights and cosines are staged in LDS as (w, w ox, w oy);
 // without a direction-dependent source, Q0 and Q1 at a point are q_iso times
 // the sums of those over the directions, formed once per work-group in
-// direction order (so every work-group has the same values).
-__global__ void __launch_bounds__(256)
+// direction order (so every work-group has the same values).  STAGE: the
+// basis table V [Q][n] and the work-group's elements' phi, Pxx, Pxy, Pyy and
+// q_iso coefficients go through LDS first, read with consecutive addresses
+// (the host checks that they fit: kClStageEl elements' worth, kClStageV
+// table entries).
+constexpr int kClThreads = 256;
+constexpr int kClStageEl = 320;   // element-node entries per staged array
+constexpr int kClStageV = 49 * 25;
+template <bool STAGE>
+__global__ void __launch_bounds__(kClThreads)
 k_closures(const KProb *__restrict__ probs, const KMomIO *__restrict__ mio, int prob, int ne, int Q,
            int nbf, int nq) {
   __shared__ double3 dirs[kMaxMomDirs];
   __shared__ double wsum[3];
+  __shared__ double sV[STAGE ? kClStageV : 1];
+  __shared__ double sM[STAGE ? 5 : 1][STAGE ? kClStageEl : 1];  // phi, Pxx, Pxy, Pyy, q_iso
   const KProb &pb = probs[prob];
   const KMomIO &io = mio[prob];
   const int n = pb.n;
@@ -186,22 +196,48 @@ k_closures(const KProb *__restrict__ probs, const KMomIO *__restrict__ mio, int 
     wsum[1] = s1;
     wsum[2] = s2;
   }
-  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nvol = ne * Q;
+  // the work-group's elements (volume points i0 .. i0 + 255)
+  const int i0 = blockIdx.x * blockDim.x;
+  const int e0 = i0 < nvol ? i0 / Q : 0;
+  const int e1 = i0 < nvol ? ((i0 + (int)blockDim.x < nvol ? i0 + (int)blockDim.x : nvol) - 1) / Q + 1 : 0;
+  const size_t N = (size_t)ne * n;
+  if constexpr (STAGE) {
+    for (int x = threadIdx.x; x < Q * n; x += blockDim.x) sV[x] = pb.tab_d[x];
+    const int cnt = (e1 - e0) * n;
+    const size_t b0 = (size_t)e0 * n;
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+      if (io.mom) {
+        sM[0][x] = io.mom[b0 + x];
+        sM[1][x] = io.mom[3 * N + b0 + x];
+        sM[2][x] = io.mom[4 * N + b0 + x];
+        sM[3][x] = io.mom[5 * N + b0 + x];
+      }
+      sM[4][x] = io.q_iso ? io.q_iso[b0 + x] : 0.0;
+    }
+  }
+  __syncthreads();
   int bad = 0;
   if (i < nvol) {
     const int e = i / Q, q = i % Q;
-    const double *V = pb.tab_d + (size_t)q * n;
+    const double *V = STAGE ? sV + q * n : pb.tab_d + (size_t)q * n;
+    const int el = (e - e0) * n;  // the element's staged entries
     if (io.E && io.mom) {
-      const size_t N = (size_t)ne * n;
       double ph = 0, pxx = 0, pxy = 0, pyy = 0;
       for (int j = 0; j < n; ++j) {
         const double v = V[j];
-        ph += io.mom[(size_t)e * n + j] * v;
-        pxx += io.mom[3 * N + (size_t)e * n + j] * v;
-        pxy += io.mom[4 * N + (size_t)e * n + j] * v;
-        pyy += io.mom[5 * N + (size_t)e * n + j] * v;
+        if constexpr (STAGE) {
+          ph += sM[0][el + j] * v;
+          pxx += sM[1][el + j] * v;
+          pxy += sM[2][el + j] * v;
+          pyy += sM[3][el + j] * v;
+        } else {
+          ph += io.mom[(size_t)e * n + j] * v;
+          pxx += io.mom[3 * N + (size_t)e * n + j] * v;
+          pxy += io.mom[4 * N + (size_t)e * n + j] * v;
+          pyy += io.mom[5 * N + (size_t)e * n + j] * v;
+        }
       }
       if (ph > 0.0) {
         io.E[i] = pxx / ph;
@@ -215,7 +251,7 @@ k_closures(const KProb *__restrict__ probs, const KMomIO *__restrict__ mio, int 
     if (io.Q0 || io.Q1) {
       double qi = 0.0;
       if (io.q_iso)
-        for (int j = 0; j < n; ++j) qi += io.q_iso[(size_t)e * n + j] * V[j];
+        for (int j = 0; j < n; ++j) qi += (STAGE ? sM[4][el + j] : io.q_iso[(size_t)e * n + j]) * V[j];
       double s0 = 0, s1 = 0, s2 = 0;
       if (io.q_dir) {
         for (int d = 0; d < nd; ++d) {
@@ -346,11 +382,16 @@ hipError_t launch_finalize(const KIO *io, int n_probs, int it, double tol, int *
   return hipGetLastError();
 }
 
-hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int nbf,
+hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int n, int nbf,
                            int nq, hipStream_t s) {
   const int tot = ne * Q + nbf * nq;
-  const int grid = (tot + 255) / 256;
-  hipLaunchKernelGGL(k_closures, dim3(grid), dim3(256), 0, s, probs, io, prob, ne, Q, nbf, nq);
+  const int grid = (tot + kClThreads - 1) / kClThreads;
+  // LDS staging when a work-group's elements and the basis table fit
+  const bool stage = Q > 0 && (kClThreads / Q + 2) * n <= kClStageEl && Q * n <= kClStageV;
+  if (stage)
+    hipLaunchKernelGGL(k_closures<true>, dim3(grid), dim3(kClThreads), 0, s, probs, io, prob, ne, Q, nbf, nq);
+  else
+    hipLaunchKernelGGL(k_closures<false>, dim3(grid), dim3(kClThreads), 0, s, probs, io, prob, ne, Q, nbf, nq);
   return hipGetLastError();
 }
 
