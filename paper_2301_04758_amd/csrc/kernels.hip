@@ -83,7 +83,11 @@ k_moments(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob,
 }
 
 // Boundary sums sum_d w |Omega.n| psi_d and sum_d w psi_d at boundary face
-// points (interior trace), one thread per (boundary face, point).
+// points (interior trace).  One wave per boundary face: lane l takes the
+// directions l, l + 64, ..., reads the face's nodal values of psi once per
+// direction and evaluates the trace at every point of the face; a butterfly
+// over the lanes in a fixed order then completes each point's sums.
+constexpr int kBndMaxNq = 8;
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_boundary(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob, int nbf, int nq,
@@ -91,15 +95,12 @@ k_boundary(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob
   if (stop && *stop) return;
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbf * nq) return;
-  const int bf = i / nq, q = i % nq;
+  const int bf = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (bf >= nbf) return;  // whole waves
   const int e = pb.bf_ef[bf] >> 2, f = pb.bf_ef[bf] & 3;
   const int P1 = p + 1, n = P1 * P1;
-  const double *g = pb.geo_fd + (((size_t)e * 4 + f) * nq + q) * 2;
-  const double len = sqrt(g[0] * g[0] + g[1] * g[1]);
-  const double nx = g[0] / len, ny = g[1] / len;
-  const double *F = pb.tab_d + 3 * (size_t)pb.Q * n + (size_t)q * P1;
+  const double *F = pb.tab_d + 3 * (size_t)pb.Q * n;  // 1D basis at the face points [nq][p+1]
   int nodes[5];
   for (int c = 0; c < P1; ++c) {
     switch (f) {
@@ -109,18 +110,45 @@ k_boundary(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob
       default: nodes[c] = P1 * (p - c); break;
     }
   }
-  const T *psi = static_cast<const T *>(pio.psi);
-  double num = 0.0, den = 0.0;
-  for (int d = 0; d < pb.nd; ++d) {
-    const T *u = psi + ((size_t)d * pb.ne + e) * n;
-    double tr = 0.0;
-    for (int c = 0; c < P1; ++c) tr += static_cast<double>(u[nodes[c]]) * F[c];
-    const double w = pb.weight[d];
-    num += w * fabs(pb.omega[2 * d] * nx + pb.omega[2 * d + 1] * ny) * tr;
-    den += w * tr;
+  double nx[kBndMaxNq], ny[kBndMaxNq], num[kBndMaxNq], den[kBndMaxNq];
+#pragma unroll
+  for (int q = 0; q < kBndMaxNq; ++q) {
+    nx[q] = ny[q] = num[q] = den[q] = 0.0;
+    if (q < nq) {
+      const double *g = pb.geo_fd + (((size_t)e * 4 + f) * nq + q) * 2;
+      const double len = sqrt(g[0] * g[0] + g[1] * g[1]);
+      nx[q] = g[0] / len;
+      ny[q] = g[1] / len;
+    }
   }
-  pb.bnd[2 * (size_t)i] = num;
-  pb.bnd[2 * (size_t)i + 1] = den;
+  const T *psi = static_cast<const T *>(pio.psi);
+  for (int d = lane; d < pb.nd; d += 64) {
+    const T *u = psi + ((size_t)d * pb.ne + e) * n;
+    double uc[5];
+    for (int c = 0; c < P1; ++c) uc[c] = static_cast<double>(u[nodes[c]]);
+    const double w = pb.weight[d], ox = pb.omega[2 * d], oy = pb.omega[2 * d + 1];
+#pragma unroll
+    for (int q = 0; q < kBndMaxNq; ++q) {
+      if (q >= nq) continue;
+      double tr = 0.0;
+      for (int c = 0; c < P1; ++c) tr += uc[c] * F[q * P1 + c];
+      num[q] += w * fabs(ox * nx[q] + oy * ny[q]) * tr;
+      den[q] += w * tr;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kBndMaxNq; ++q) {
+    if (q >= nq) continue;
+    double a = num[q], b = den[q];
+    for (int off = 32; off >= 1; off >>= 1) {
+      a += __shfl_xor(a, off, 64);
+      b += __shfl_xor(b, off, 64);
+    }
+    if (lane == q) {
+      pb.bnd[2 * ((size_t)bf * nq + q)] = a;
+      pb.bnd[2 * ((size_t)bf * nq + q) + 1] = b;
+    }
+  }
 }
 
 __global__ void k_run_init(const KIO *__restrict__ io, int n_probs, int n_iter, int *stop,
@@ -352,9 +380,9 @@ hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob
 
 hipError_t launch_boundary(bool fp32, const KProb *probs, const KIO *io, int prob, int nbf, int nq,
                            int p, const int *stop, hipStream_t s) {
-  const int tot = nbf * nq;
-  if (tot == 0) return hipSuccess;
-  const int grid = (tot + 255) / 256;
+  if (nbf == 0) return hipSuccess;
+  if (nq > kBndMaxNq || p > 4) return hipErrorInvalidValue;
+  const int grid = (nbf + 3) / 4;  // one wave per boundary face
   if (fp32)
     hipLaunchKernelGGL(k_boundary<float>, dim3(grid), dim3(256), 0, s, probs, io, prob, nbf, nq, p, stop);
   else
