@@ -2431,15 +2431,16 @@ k_sweep_level_lus(const int4 *__restrict__ desc, int n_solves, const KProb *__re
 }
 
 // Class matrix K = A^-1 R (ClsCols) of one class of solves that share their
-// local matrix A (one work-group of 64 threads per class, see
+// local matrix A (one work-group of kClsThreads threads per class, see
 // ClassInvLaunch): thread i < n assembles row i of A and of R in double from
 // the representative element's geometry, sigma_t and the direction, as the
 // row-set LU assembles A and b; then Gauss-Jordan elimination with partial
 // pivoting on [A | R] in LDS.  R maps the staged inputs to b: J M for the
 // nodal source, -(Omega . N_f) m (interior traces) or -(Omega . N_f) w l
 // (boundary data) on the rows of each inflow face f, J (w V)^T for q_dir.
+constexpr int kClsThreads = 256;
 template <int P, int NQ, typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kClsThreads)
 k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const T *__restrict__ tables,
             T *__restrict__ out, int *__restrict__ status) {
   using S = LuShape<P>;
@@ -2454,12 +2455,12 @@ k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const
   const int t = threadIdx.x;
   const int4 rp = rep[blockIdx.x];
   const KProb &pb = probs[0];
-  for (int i = t; i < P1 * P1; i += 64) {
+  for (int i = t; i < P1 * P1; i += kClsThreads) {
     m1[i] = static_cast<double>(tables[SH::A_M1 + i]);
     gd[i] = static_cast<double>(tables[SH::A_GD1 + i]);
   }
-  for (int i = t; i < NQ * P1; i += 64) wl[i] = static_cast<double>(tables[SH::A_WL + i]);
-  for (int x = t; x < N * W; x += 64) M[x / W][x % W] = 0.0;
+  for (int i = t; i < NQ * P1; i += kClsThreads) wl[i] = static_cast<double>(tables[SH::A_WL + i]);
+  for (int x = t; x < N * W; x += kClsThreads) M[x / W][x % W] = 0.0;
   __syncthreads();
   if (t < N) {
     const T *g = static_cast<const T *>(pb.geo_a) + (size_t)rp.x * 16;
@@ -2505,7 +2506,7 @@ k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const
     __syncthreads();
     const int pr = piv;
     if (pr != k)
-      for (int j = t; j < W; j += 64) {
+      for (int j = t; j < W; j += kClsThreads) {
         const double v = M[k][j];
         M[k][j] = M[pr][j];
         M[pr][j] = v;
@@ -2514,16 +2515,16 @@ k_class_inv(const int4 *__restrict__ rep, const KProb *__restrict__ probs, const
     const double pk = M[k][k];
     if (t < N) fac[t] = t == k ? 0.0 : M[t][k] / pk;
     __syncthreads();
-    for (int x = t; x < N * W; x += 64) {
+    for (int x = t; x < N * W; x += kClsThreads) {
       const int i = x / W, j = x - i * W;
       if (i != k) M[i][j] -= fac[i] * M[k][j];
     }
     __syncthreads();
-    for (int j = t; j < W; j += 64) M[k][j] /= pk;
+    for (int j = t; j < W; j += kClsThreads) M[k][j] /= pk;
     __syncthreads();
   }
   T *o = out + (size_t)blockIdx.x * C::BLOCK;
-  for (int x = t; x < C::BLOCK; x += 64) {
+  for (int x = t; x < C::BLOCK; x += kClsThreads) {
     const int j = x / (16 * RS), r = (x / RS) % 16, s = x % RS;
     const int row = r + s * H;
     o[x] = (r < H && row < N) ? static_cast<T>(M[row][N + j]) : T(0);
@@ -2536,7 +2537,7 @@ hipError_t launch_class_inv_t(const ClassInvLaunch &C) {
     return hipErrorInvalidValue;
   } else {
     if (C.n_cls <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_class_inv<P, NQ, T>), dim3(C.n_cls), dim3(64), 0, C.stream, C.rep, C.probs,
+    hipLaunchKernelGGL((k_class_inv<P, NQ, T>), dim3(C.n_cls), dim3(kClsThreads), 0, C.stream, C.rep, C.probs,
                        static_cast<const T *>(C.tables), static_cast<T *>(C.out), C.status);
     return hipGetLastError();
   }
