@@ -193,3 +193,27 @@ def test_shared_matrices_graph_replays(torch, precision):
     del g
     sw.close()
     assert rel_inf(ref["mom"][0].cpu().numpy(), O.source_iteration(pr, 3, phi0=phi)["mom"][0]) <= TOL[precision]
+
+
+@pytest.mark.parametrize("p,nq", [(3, 5), (3, 6), (4, 7)])
+def test_shared_matrices_more_face_points(torch, p, nq):
+    """More quadrature points than face nodes: the class matrix's trace
+    block carries padding columns and its boundary-data block more entries
+    than a face has nodes; direction-dependent source and inflow data at
+    those points (FP64 against the oracle and the row-set LU, FP32 against
+    the oracle)."""
+    st = _blocks(8, [0.7, 4.0, 25.0])
+    pr = _small(8, 8, p, 1, 6, st=st, ss=0.5 * st, seed=11)
+    pr.nq = nq
+    pr.q_iso = None
+    vxy, bxy, _ = O.qp_coords(pr)
+    mms.attach(pr, vxy, bxy)
+    phi = np.random.default_rng(11).uniform(0.0, 2.0, (pr.n_elem, (p + 1) ** 2))
+    ref = O.sweep(pr, phi_in=phi)
+    a = _run(torch, pr, "fp64", True, phi)
+    b = _run(torch, pr, "fp64", False, phi)
+    c = _run(torch, pr, "fp32", True, phi)
+    assert a["kernel"] == "affine_shared" and c["kernel"] == "affine_shared"
+    assert rel_inf(a["psi"], ref["psi"]) <= TOL["fp64"]
+    assert rel_inf(a["psi"], b["psi"]) <= 1e-13
+    assert rel_inf(c["psi"], ref["psi"]) <= TOL["fp32"]
