@@ -11,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -118,7 +119,8 @@ struct vef_sweep {
   std::vector<vefk::KMomIO> mio_last;
   bool mio_valid = false;
   int2 *d_solves = nullptr;
-  int4 *d_solve_desc = nullptr;  // per entry of d_solves: (element, direction | problem << 16, flags, 0), neighbours
+  int4 *d_solve_desc = nullptr;  // per entry of d_solves: (element, direction | problem << 16, flags, class or
+                                 // pivot-order entry), neighbours
   std::vector<std::vector<LevelLaunch>> levels;
   int2 *d_dir_tasks = nullptr;
   std::vector<FlowLaunch> flow;   // persistent schedule
@@ -142,6 +144,7 @@ struct vef_sweep {
   int n_cls = 0;                     // classes of shared local matrices of problem 0 (0: none)
   int4 *d_cls_rep = nullptr;         // [n_cls] representative (element, direction, inflow faces, 0)
   void *d_cls_inv = nullptr;         // T [n_cls][ncol][16][RS] class matrices (written by every run)
+  std::vector<std::unordered_map<long long, int>> piv_index;  // per problem: d ne + e -> its entry of piv_perm
   double *static_resid = nullptr;    // this device's copy of `scratch` (vef_sweep_run_static)
   hipStream_t last_stream = nullptr;
   bool timing = false;
@@ -412,6 +415,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
 
   // per-problem constant data
   h->h_probs.resize(n_probs);
+  h->piv_index.assign(n_probs, {});
+  std::vector<std::vector<int2>> piv_lists(n_probs);  // (element, direction) of the uncertified solves
   for (int k = 0; k < n_probs; ++k) {
     const auto &pl = h->plans[k];
     vefk::KProb kp{};
@@ -502,11 +507,47 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       }
       if (he != hipSuccess) return hip_fail(h, he, "element matrices");
       kp.emat = em;
+      if (!pl.nopivot && pl.n_pivoting > 0) {
+        // solves not certified for elimination in natural order: their row
+        // order of partial pivoting, formed on the device below (by
+        // direction, then element; the level lists carry the entry)
+        auto &ix = h->piv_index[k];
+        auto &ls = piv_lists[k];
+        for (int d = 0; d < pl.nd; ++d)
+          for (int e = 0; e < pl.ne; ++e)
+            if (pl.mask[(size_t)d * pl.ne + e] & 0x80) {
+              ix[(long long)d * pl.ne + e] = (int)ls.size();
+              ls.push_back(make_int2(e, d));
+            }
+        uint8_t *pp = nullptr;
+        he = dev_alloc(h, &pp, ls.size() * 16);
+        if (he != hipSuccess) return hip_fail(h, he, "pivot orders");
+        kp.piv_perm = pp;
+      }
     }
     kp.cls_inv = h->n_cls > 0 ? h->d_cls_inv : nullptr;
     h->h_probs[k] = kp;
   }
   he = upload(h, &h->d_probs, h->h_probs.data(), h->h_probs.size());
+  for (int k = 0; k < n_probs && he == hipSuccess; ++k) {
+    if (piv_lists[k].empty()) continue;
+    int2 *tmp = nullptr;
+    vefk::PivotOrderLaunch PL{};
+    PL.p = h->plans[k].p;
+    PL.fp32 = fp32;
+    PL.n = (int)piv_lists[k].size();
+    PL.probs = h->d_probs;
+    PL.prob = k;
+    PL.out = const_cast<uint8_t *>(h->h_probs[k].piv_perm);
+    he = hipMalloc((void **)&tmp, sizeof(int2) * piv_lists[k].size());
+    if (he != hipSuccess) break;
+    he = hipMemcpy(tmp, piv_lists[k].data(), sizeof(int2) * piv_lists[k].size(), hipMemcpyHostToDevice);
+    PL.list = tmp;
+    if (he == hipSuccess) he = vefk::launch_pivot_order(PL);
+    if (he == hipSuccess) he = hipDeviceSynchronize();
+    const hipError_t fe = hipFree(tmp);
+    if (he == hipSuccess) he = fe;
+  }
   if (he == hipSuccess) he = dev_alloc(h, &h->d_io, n_probs);
   if (he == hipSuccess) he = dev_alloc(h, &h->d_mio, n_probs);
   if (he == hipSuccess) he = dev_alloc(h, &h->d_flags, 4);
@@ -654,7 +695,15 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         fl |= ((int)pl.nbr_face[4 * (size_t)e + f] & 3) << (4 + 2 * f);
         fl |= (nb[f] < 0 ? 1 : 0) << (16 + f);
       }
-      desc[2 * i] = make_int4(e, solves[i].y, fl, h->n_cls > 0 ? shared.of(pl, e, d) : 0);
+      // fourth field: the solve's class of shared local matrices, or the
+      // entry of its pivot order (element matrices, uncertified solves)
+      int w = h->n_cls > 0 ? shared.of(pl, e, d) : 0;
+      if (mk & 0x80u) {
+        const auto &ix = h->piv_index[k];
+        const auto it = ix.find((long long)d * pl.ne + e);
+        if (it != ix.end()) w = it->second;
+      }
+      desc[2 * i] = make_int4(e, solves[i].y, fl, w);
       desc[2 * i + 1] = make_int4(nb[0], nb[1], nb[2], nb[3]);
     }
     he = upload(h, &h->d_solve_desc, desc.data(), desc.size());
@@ -946,6 +995,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
         SL.mode = launch_mode(h->mat_quadrature, F.v.mode);
         SL.flow = true;
         SL.list = h->d_solves;
+        SL.desc = h->d_solve_desc;  // the pivot-order entries of uncertified solves
         SL.tasks = h->d_flow_tasks + F.off;
         SL.count = F.cnt;
         SL.pred_ptr = h->d_pred_ptr + F.off;

@@ -16,6 +16,8 @@ struct KProb {
   const void *emat;        // T [ne][3 n n + 8 (p+1)^2]: element matrices (general elements, p = 3; layout in
                            // emat.hip), or NULL
   const void *cls_inv;     // T [n_cls][ncol][16][RS]: class matrices of shared local matrices (affine, p >= 3), or NULL
+  const uint8_t *piv_perm; // [n_pivoting][16]: partial-pivoting row order of each solve not certified for natural-order
+                           // elimination (element matrices), or NULL
   const double *geo_fd;    // double copy of geo_f
   const int32_t *nbr;      // [ne][4] neighbour or -(bf+1)
   const int8_t *nbr_face;  // [ne][4]
@@ -60,7 +62,9 @@ struct SweepLaunch {
   bool fp32;
   int mode;          // 0: general elements, pivoting; 1: general, pivot-free; 2: affine, pivot-free
   const int4 *desc;  // level schedule: two records per entry of list (element, direction | problem << 16,
-                     // flags, 0), (neighbours); flags as the kernels' SolveIn flags, boundary faces << 16
+                     // flags, w), (neighbours); flags as the kernels' SolveIn flags, boundary faces << 16;
+                     // w: class of shared local matrices, or entry of KProb::piv_perm; persistent
+                     // schedule: the records of the whole solve list (the pivot-order entries)
   const int2 *list;  // level schedule: (element, direction | problem << 16) pairs of one level;
                      // direction-resident schedule: (problem, direction) tasks
   int count;       // level: solves; direction-resident: tasks; persistent: tasks
@@ -141,6 +145,23 @@ struct ClassInvLaunch {
   hipStream_t stream;
 };
 hipError_t launch_class_inv(const ClassInvLaunch &L);
+
+// Row orders of partial pivoting for the local matrices of general elements
+// (p = 3, element matrices) not certified for elimination in natural order:
+// list[i] = (element, direction) of problem `prob`; out[16 i + k] = the row
+// that is the pivot of elimination step k.  Reads probs[prob].emat, mask,
+// omega and sig.
+struct PivotOrderLaunch {
+  int p;
+  bool fp32;
+  int n;
+  const int2 *list;
+  const KProb *probs;
+  int prob;
+  uint8_t *out;
+  hipStream_t stream;
+};
+hipError_t launch_pivot_order(const PivotOrderLaunch &L);
 
 // Element-local HRT VEF blocks and their inverse (hrt.hip), affine elements.
 struct HrtLaunch {

@@ -365,6 +365,12 @@ hipError_t launch_class_inv(const ClassInvLaunch &C) {
   }
 }
 
+hipError_t launch_pivot_order_p3(const PivotOrderLaunch &L);
+
+hipError_t launch_pivot_order(const PivotOrderLaunch &L) {
+  return L.p == 3 ? launch_pivot_order_p3(L) : hipErrorInvalidValue;
+}
+
 hipError_t launch_sweep_level(const SweepLaunch &L) { return launch_sweep(L, false); }
 hipError_t launch_sweep_dir(const SweepLaunch &L) { return launch_sweep(L, true); }
 

@@ -744,20 +744,30 @@ struct EMat {
   static constexpr int SIZE = 3 * N * N + 8 * P1 * P1;  // values per element
 };
 
-template <int P, int NQ, typename T>
+// ORD: a solve not certified for elimination in natural order assembles its
+// rows in the partial-pivoting order formed for it before the sweep (row
+// piv_perm[16 pix + r] on lane r) and eliminates in natural order; without
+// ORD such a solve runs Gauss-Jordan with partial pivoting.
+template <int P, int NQ, typename T, bool ORD = false>
 struct SolveInM {
   int e, flags;  // flags as SolveIn
   int nb[4];
   bool valid;
-  T s;  // nodal source at node r
+  int pix;  // ORD: the solve's entry of piv_perm
+  int rr;   // the row of the local matrix this lane assembles
+  T s;      // nodal source at node r
 };
 
-template <int P, int NQ, typename T>
-__device__ __forceinline__ void load_one(SolveInM<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio, int it,
-                                         int r) {
+template <int P, int NQ, typename T, bool ORD>
+__device__ __forceinline__ void load_one(SolveInM<P, NQ, T, ORD> &in, int d, const KProb &pb, const KIO &pio,
+                                         int it, int r) {
   constexpr int N = (P + 1) * (P + 1);
   (void)d;
+  in.rr = r;
   if (!in.valid) return;
+  if constexpr (ORD) {
+    if ((in.flags >> 12) & 1) in.rr = pb.piv_perm[(size_t)in.pix * 16 + r] & 15;
+  }
   const int e = in.e;
   const double *phi = it == 0 ? pio.phi_in : pio.mom;
   T sv = T(0);
@@ -768,9 +778,9 @@ __device__ __forceinline__ void load_one(SolveInM<P, NQ, T> &in, int d, const KP
   in.s = sv;
 }
 
-template <int P, int NQ, typename T, bool PIVOT, bool FIX, bool COH = false>
-__device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, const KProb &pb, const KIO &pio,
-                                          T *lds, int r, int slot, int *status) {
+template <int P, int NQ, typename T, bool PIVOT, bool FIX, bool COH = false, bool ORD>
+__device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T, ORD> &in, int d, const KProb &pb,
+                                          const KIO &pio, T *lds, int r, int slot, int *status) {
   using S = Shape<P, NQ>;
   using EM = EMat<P>;
   constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
@@ -781,7 +791,7 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
   const int e = in.e;
   const bool valid = in.valid;
   const bool row_ok = valid && r < N;
-  const int rr = r < N ? r : N - 1;
+  const int rr = in.rr;  // r, or the pivot order's row (N == SLOT)
   const int a = rr % P1, b = rr / P1;
   const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
 
@@ -879,17 +889,19 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
     }
   }
 
-  // elimination: the certified LU with fused broadcasts, or Gauss-Jordan
-  // with partial pivoting (see the general solve)
+  // elimination: the LU with fused broadcasts in natural order (certified
+  // solves; with ORD every solve, its rows already in pivoting order), or
+  // Gauss-Jordan with partial pivoting (see the general solve); lane r ends
+  // with unknown my_k
   int my_k = r;
-  if (!PIVOT || !((in.flags >> 12) & 1)) {
+  if (!PIVOT || ORD || !((in.flags >> 12) & 1)) {
     T A1[1][N + 1], idg[1];
 #pragma unroll
     for (int j = 0; j < N; ++j) A1[0][j] = A[j];
     A1[0][N] = rhs;
     lu_rows<N, 1, 16, T>(A1, idg, r);
     rhs = A1[0][N] * idg[0];
-  } else if constexpr (PIVOT) {
+  } else if constexpr (PIVOT && !ORD) {
     bool active = row_ok;
     gj_pivot<SLOT, N, 0, T>(A, rhs, r, active, my_k, area + S::OFF_PIV_M);
   }
@@ -903,9 +915,9 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T> &in, int d, c
       for (int j = 0; j < N; ++j) sm += mr[j];
       cr = st * sm + cw;
     }
-    if constexpr (PIVOT) {  // lane r holds unknown my_k: fetch its weight
+    if constexpr (PIVOT) {  // the weight of row rr, wanted for unknown my_k
       T *cwl = area + S::OFF_PIV_M;
-      if (row_ok) cwl[r] = cr;
+      if (row_ok) cwl[rr] = cr;
       wave_sync_lds();
       cr = cwl[my_k];
       __builtin_amdgcn_wave_barrier();
@@ -1103,10 +1115,10 @@ __device__ __forceinline__ void solve_one(const SolveInA<P, NQ, T> &in, int d, c
   }
 }
 
-template <int P, int NQ, typename T, int MODE>
+template <int P, int NQ, typename T, int MODE, bool ORD = false>
 using InputsOf = std::conditional_t<
     (MODE & MODE_KIND) == MODE_AFFINE_NOPIVOT, SolveInA<P, NQ, T>,
-    std::conditional_t<(MODE & MODE_KIND) == MODE_GENERAL_MAT, SolveInM<P, NQ, T>, SolveIn<P, NQ, T>>>;
+    std::conditional_t<(MODE & MODE_KIND) == MODE_GENERAL_MAT, SolveInM<P, NQ, T, ORD>, SolveIn<P, NQ, T>>>;
 
 // Modes whose solves may pivot (per solve: see the plan's certification bit).
 constexpr bool mode_pivots(int mode) {
@@ -1136,7 +1148,7 @@ k_sweep_level(const int4 *__restrict__ desc, int n_solves, const KProb *__restri
   const int r = lane & (S::SLOT - 1);
   const int slot = (threadIdx.x >> 6) * S::SPW + lane / S::SLOT;
   const int sid = xcd_block(blockIdx.x, gridDim.x) * ((blockDim.x >> 6) * S::SPW) + slot;
-  InputsOf<P, NQ, T, MODE> in;
+  InputsOf<P, NQ, T, MODE, true> in;
   in.valid = sid < n_solves;
   // the solve's descriptor, read before the stop flag so the two loads overlap
   int4 da = make_int4(0, 0, 0, 0), db = make_int4(-1, -1, -1, -1);
@@ -1154,6 +1166,7 @@ k_sweep_level(const int4 *__restrict__ desc, int n_solves, const KProb *__restri
   in.nb[1] = db.y;
   in.nb[2] = db.z;
   in.nb[3] = db.w;
+  if constexpr ((MODE & MODE_KIND) == MODE_GENERAL_MAT) in.pix = da.w;
   const KProb &pb = probs[prob];
   const KIO &pio = io[prob];
   load_one<P, NQ, T>(in, d, pb, pio, it, r);
@@ -2543,6 +2556,67 @@ hipError_t launch_class_inv_t(const ClassInvLaunch &C) {
   }
 }
 
+// Row order of partial pivoting for each local matrix of a general element
+// (element matrices, p = 3) that is not certified for elimination in natural
+// order.  A 16-lane slot per listed (element, direction): lane r forms row r
+// of A from the element matrices with the sums of the sweep's assembly, then
+// the slot runs Gauss-Jordan elimination with partial pivoting; the lane
+// whose row is the pivot of step k writes out[16 i + k] = r.  Elimination in
+// natural order of the rows taken in that order meets the pivots of partial
+// pivoting, so the sweep needs no pivot search (nor its divergent path).
+// Every step picks a lane not yet used (a zero pivot too), so each out row is
+// a permutation of 0..15.
+template <int P, typename T>
+__global__ void __launch_bounds__(256)
+k_pivot_order(const int2 *__restrict__ list, int n, const KProb *__restrict__ probs, int prob,
+              uint8_t *__restrict__ out) {
+  using EM = EMat<P>;
+  constexpr int P1 = P + 1, N = P1 * P1, W = 16 / sizeof(T);
+  static_assert(N == 16, "element matrices: degree 3");
+  __shared__ T pv[16][N + 1];
+  const int r = threadIdx.x & 15, slot = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + slot;
+  const KProb &pb = probs[prob];
+  T A[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) A[j] = j == r ? T(1) : T(0);  // past the list: identity
+  if (i < n) {
+    const int e = list[i].x, d = list[i].y;
+    const T *em = static_cast<const T *>(pb.emat) + (size_t)e * EM::SIZE;
+    const unsigned mask = pb.mask[(size_t)d * pb.ne + e] & 15u;
+    const T ox = static_cast<T>(pb.omega[2 * d]), oy = static_cast<T>(pb.omega[2 * d + 1]);
+    const T st = static_cast<T>(pb.sig[2 * e]);
+    const int a = r % P1, b = r / P1;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int at = ((j / W) * 16 + r) * W + j % W;
+      A[j] = st * em[at] - (ox * em[EM::OFF_GX + at] + oy * em[EM::OFF_GY + at]);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const bool on_face = (f == 0) ? (b == 0) : (f == 1) ? (a == P) : (f == 2) ? (b == P) : (a == 0);
+      const int pos = (f == 0) ? a : (f == 1) ? b : (f == 2) ? (P - a) : (P - b);
+      if (!on_face || ((mask >> f) & 1u)) continue;
+      const T *fx = em + EM::OFF_F + (2 * f) * P1 * P1 + pos * P1, *fy = fx + P1 * P1;
+#pragma unroll
+      for (int c = 0; c < P1; ++c) A[face_node<P>(f, c)] += ox * fx[c] + oy * fy[c];
+    }
+  }
+  T rhs = T(0);
+  bool active = true;
+  int my_k = r;
+  gj_pivot<16, N, 0, T>(A, rhs, r, active, my_k, &pv[slot][0]);
+  if (i < n) out[(size_t)i * 16 + my_k] = (uint8_t)r;
+}
+
+template <int P, typename T>
+hipError_t launch_pivot_order_t(const PivotOrderLaunch &L) {
+  if (L.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_pivot_order<P, T>), dim3((L.n + 15) / 16), dim3(256), 0, L.stream, L.list, L.n, L.probs,
+                     L.prob, L.out);
+  return hipGetLastError();
+}
+
 // Direction-resident schedule with the row-set LU (as k_sweep_dir).
 template <int P, int NQ, typename T, bool FIX>
 __global__ void __launch_bounds__(256)
@@ -2747,7 +2821,7 @@ struct FlowPolicy<P, NQ, T, MODE, false> {
   static constexpr int SLOT = Shape<P, NQ>::SLOT, SPW = Shape<P, NQ>::SPW;
   static constexpr bool kPrefetch = true;
   static constexpr int TAB = Lds<P, NQ, MODE>::TAB, AREA = Lds<P, NQ, MODE>::AREA;
-  using In = InputsOf<P, NQ, T, MODE>;
+  using In = InputsOf<P, NQ, T, MODE, true>;  // the level-synchronous kernel's inputs and arithmetic
   static __device__ __forceinline__ void stage(const T *tables, T *lds) { stage_tables<P, NQ, T, MODE>(tables, lds); }
   static __device__ __forceinline__ void solve(const In &in, int d, const KProb &pb, const KIO &pio,
                                                const T *tables, T *lds, int r, int slot, int *status) {
@@ -2765,7 +2839,8 @@ struct FlowItem {
 
 template <int P, int NQ, typename T, int MODE>
 __global__ void __launch_bounds__(256, 2)
-k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, int n_tasks,
+k_sweep_flow(const int2 *__restrict__ solves, const int4 *__restrict__ desc, const int2 *__restrict__ tasks,
+             int n_tasks,
              const int *__restrict__ pred_ptr, const int *__restrict__ pred_idx, int *__restrict__ flags,
              int own_base, int *__restrict__ abort_flag, const KProb *__restrict__ probs,
              const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
@@ -2806,6 +2881,10 @@ k_sweep_flow(const int2 *__restrict__ solves, const int2 *__restrict__ tasks, in
       {
         const unsigned mk = pb.mask[(size_t)x.d * pb.ne + x.in.e];
         x.in.flags = (int)((mk & 15u) | ((mk >> 7) << 12));  // inflow faces, pivoting needed
+        if constexpr ((MODE & MODE_KIND) == MODE_GENERAL_MAT) {
+          x.in.pix = 0;
+          if (mk & 0x80u) x.in.pix = desc[2 * (size_t)(tk.x + k)].w;  // its pivot order
+        }
       }
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
@@ -2882,8 +2961,8 @@ hipError_t launch_flow_t(const SweepLaunch &L) {
   int grid = per_cu * L.n_cu;
   const int need = (L.count + (block / 64) - 1) / (block / 64);
   if (grid > need) grid = need;
-  hipLaunchKernelGGL((k_sweep_flow<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.list, L.tasks,
-                     L.count, L.pred_ptr, L.pred_idx, L.flags, L.own_base, L.abort_flag, L.probs, L.io,
+  hipLaunchKernelGGL((k_sweep_flow<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.list, L.desc,
+                     L.tasks, L.count, L.pred_ptr, L.pred_idx, L.flags, L.own_base, L.abort_flag, L.probs, L.io,
                      static_cast<const T *>(L.tables), L.it, L.stop, L.status, L.wait_spins);
   return hipGetLastError();
 }

@@ -258,7 +258,10 @@ def test_schedules_agree(torch, precision, cfg, scale):
     and must agree bit for bit (any race or stale read would show), except
     for affine elements of degree <= 2, where the direction-resident schedule
     factors each local matrix once (LU, then substitution) instead of
-    Gauss-Jordan: there they agree to rounding."""
+    Gauss-Jordan, and for the solves of curved degree-3 elements that are not
+    certified for elimination in natural order, which the direction-resident
+    schedule pivots as it eliminates while the others take the rows in the
+    pivoting order formed beforehand: there they agree to rounding."""
     from paper_2301_04758_amd import vef
     (pr,), _ = P.make_config(cfg, scale=scale)
     (a,), _ = gpu_run(torch, [pr], precision, n_iter=2, schedule="level")
@@ -271,6 +274,11 @@ def test_schedules_agree(torch, precision, cfg, scale):
     if info["affine"] and pr.p <= 2:
         assert rel_inf(b["psi_out"], a["psi_out"]) <= TOL[precision]
         assert rel_inf(b["mom"][0], a["mom"][0]) <= TOL[precision]
+        return
+    if not info["affine"] and pr.p == 3 and info["n_pivoting"] > 0:
+        tol = 1e-13 if precision == "fp64" else 2e-6
+        assert rel_inf(b["psi_out"], a["psi_out"]) <= tol
+        assert rel_inf(b["mom"][0], a["mom"][0]) <= tol
         return
     assert np.array_equal(a["psi_out"], b["psi_out"])
     assert np.array_equal(a["mom"], b["mom"])
