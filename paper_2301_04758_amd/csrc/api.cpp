@@ -631,6 +631,20 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
   // on a handle with shared local matrices, direction by direction
   // (consecutive slots then read the same class matrix).
   const bool dir_major = h->n_cls > 0;
+  // The row-per-lane level kernel reads the problem of a wave from its first
+  // slot.  With several problems in one launch, each problem's solves start
+  // on a whole wave, the gap filled with entries that solve nothing (element
+  // -1).  A wave holds 64 / slot solves, the slot being (p+1)^2 lanes rounded
+  // up to 4, 8, 16 or 32.
+  const bool pad_waves = n_probs > 1;
+  auto row_level_kernel = [](int mode) {
+    return mode == 0 || mode == 1 || mode == 2 || mode == 6;  // k_sweep_level, not the row-set LU
+  };
+  auto solves_per_wave = [](int p) {
+    const int n = (p + 1) * (p + 1);
+    return 64 / (n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32);
+  };
+  size_t n_pad = 0;
   // per level and variant, two level-synchronous launches: the problems the
   // persistent schedule covers, then the others
   for (int L = 0; L < max_levels; ++L)
@@ -642,6 +656,11 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         const auto &pl = h->plans[k];
         if (!in_level_variant(pl, var) || L >= pl.n_levels) continue;
         if (flow_ok(pl, var) != pass_flow) continue;
+        if (pad_waves && row_level_kernel(var.mode))
+          while ((solves.size() - off) % solves_per_wave(var.p) != 0) {
+            solves.push_back(make_int2(-1, k << 16));
+            ++n_pad;
+          }
         for (int g = 0; g < pl.n_groups; ++g) {
           const int *lo = &pl.level_off[(size_t)g * (pl.n_levels + 1)];
           const int32_t *ord = &pl.order[(size_t)g * pl.ne];
@@ -673,7 +692,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         h->levels[L].push_back({var, off, cnt, affine_tables(var.mode) ? ts.dev_A : ts.dev_T, pass_flow});
       }
       }
-  if (solves.size() != total) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
+  if (solves.size() != total + n_pad) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
   if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
   he = upload(h, &h->d_solves, solves.data(), solves.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload solve lists");
@@ -686,6 +705,11 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     std::vector<int4> desc(2 * solves.size());
     for (size_t i = 0; i < solves.size(); ++i) {
       const int e = solves[i].x, d = solves[i].y & 0xffff, k = solves[i].y >> 16;
+      if (e < 0) {  // padding: solves nothing
+        desc[2 * i] = make_int4(-1, solves[i].y, 0, 0);
+        desc[2 * i + 1] = make_int4(-1, -1, -1, -1);
+        continue;
+      }
       const auto &pl = h->plans[k];
       const unsigned mk = pl.mask[(size_t)d * pl.ne + e];
       int fl = (int)((mk & 15u) | ((mk >> 7) << 12));
@@ -1392,6 +1416,7 @@ int vef_sweep_check(vef_sweep_t *h) {
   he = hipMemcpy(flags, h->d_flags, sizeof(flags), hipMemcpyDeviceToHost);
   if (he != hipSuccess) return hip_fail(h, he, "read status");
   if (flags[2] & 2) return set_err(h, VEF_ERR_TIMEOUT, "a pipelined sweep wait exceeded its bound");
+  if (flags[2] & 4) return set_err(h, VEF_ERR_INVALID, "internal: a level-synchronous wave held two problems");
   if (flags[2]) return set_err(h, VEF_ERR_INVALID, "non-finite unknown (singular local system)");
   return VEF_OK;
 }

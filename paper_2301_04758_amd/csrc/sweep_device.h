@@ -785,7 +785,9 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T, ORD> &in, int
   using EM = EMat<P>;
   constexpr int P1 = S::P1, N = S::N, Q = S::Q, SLOT = S::SLOT;
   static_assert(N == 16 && SLOT == 16, "element matrices: degree 3");
-  const T *sF = lds + 3 * Q * N;
+  // the face table F [nq][P1], read from the double tables (boundary data
+  // only), so that the level kernel stages no tables
+  const double *sF = pb.tab_d + 3 * Q * N;
   T *area = lds + S::TAB + (size_t)slot * S::SLOT_AREA_M;
   const int ne = pb.ne;
   const int e = in.e;
@@ -884,7 +886,7 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T, ORD> &in, int
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const T on = ox * gf[2 * q] + oy * gf[2 * q + 1];
-        rhs -= on * sF[q * P1 + pos] * static_cast<T>(bc[q]);
+        rhs -= on * static_cast<T>(sF[q * P1 + pos]) * static_cast<T>(bc[q]);
       }
     }
   }
@@ -1157,10 +1159,16 @@ k_sweep_level(const int4 *__restrict__ desc, int n_solves, const KProb *__restri
     db = desc[2 * (size_t)sid + 1];
   }
   if (*stop) return;
-  stage_tables<P, NQ, T, MODE>(tables, lds);
-  __syncthreads();
-  in.e = da.x;
-  const int d = da.y & 0xffff, prob = da.y >> 16;
+  if constexpr ((MODE & MODE_KIND) != MODE_GENERAL_MAT) {  // the element-matrix solve reads no staged table
+    stage_tables<P, NQ, T, MODE>(tables, lds);
+    __syncthreads();
+  }
+  in.valid = in.valid && da.x >= 0;  // element -1: an entry that pads a problem's solves to whole waves
+  in.e = in.valid ? da.x : 0;
+  // one problem per wave (the lists start each problem's solves on a whole
+  // wave): its records come through the scalar cache
+  const int d = da.y & 0xffff, prob = __builtin_amdgcn_readfirstlane(da.y >> 16);
+  if (in.valid && (da.y >> 16) != prob) atomicOr(status, 4);  // a list that breaks that layout
   in.flags = da.z & 0xffff;  // inflow faces, neighbour faces, pivoting needed
   in.nb[0] = db.x;
   in.nb[1] = db.y;

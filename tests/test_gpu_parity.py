@@ -251,6 +251,28 @@ def test_invalid_problem_rejected_before_launch(torch):
         vef.Sweep([pr])
 
 
+@pytest.mark.parametrize("p,m,warp,kernel", [(3, 2, 0.05, "general_mat"), (2, 2, 0.05, None),
+                                             (1, 1, 0.0, None)])
+def test_level_lists_start_problems_on_whole_waves(torch, p, m, warp, kernel):
+    """Three problems of one kernel variant in one handle, with level widths
+    that leave partial waves: the level kernel takes each wave's problem from
+    its first slot, so every problem's solves start on a whole wave (padding
+    entries between them).  Each problem gives the bits it gives alone."""
+    from paper_2301_04758_amd import vef
+    probs = [_small(5, 3, p, m, 4, st=2.0, ss=0.3, warp=warp, seed=1),
+             _small(3, 7, p, m, 4, st=0.5, ss=0.3, warp=warp, seed=2),
+             _small(7, 5, p, m, 4, st=lambda r, n: r.uniform(0.5, 5.0, n), ss=0.3, warp=warp, seed=3)]
+    batch, out = gpu_run(torch, probs, "fp64", n_iter=2, schedule="level")
+    kinds = {vef.KERNEL_NAMES[i["kernel"]] for i in out["info"]}
+    assert len(kinds) == 1 and (kernel is None or kinds == {kernel}), kinds
+    for k, pr in enumerate(probs):
+        (alone,), _ = gpu_run(torch, [pr], "fp64", n_iter=2, schedule="level")
+        for key in ("psi_out", "mom", "resid"):
+            assert np.array_equal(batch[k][key], alone[key]), (k, key)
+        ref = O.source_iteration(pr, 2)
+        assert rel_inf(batch[k]["mom"][0], ref["mom"][0]) <= TOL["fp64"]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("cfg,scale", [("c2", 24), ("c3", 10), ("c5", 12)])
 def test_schedules_agree(torch, precision, cfg, scale):
