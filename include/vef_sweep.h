@@ -536,7 +536,9 @@ int vef_sweep_autotune(vef_sweep_t *h, const vef_run_args *a, void *stream, int 
 /* Synchronise the handle's last stream and return the device status word of
  * the last run (each run clears it when it starts): VEF_OK; VEF_ERR_INVALID
  * when a local solve produced a non-finite unknown (singular or overflowing
- * local system); VEF_ERR_TIMEOUT when a bounded device-side wait of a sweep
+ * local system), or, as an internal error, when a level-synchronous kernel met
+ * a solve list that breaks its layout (a wave with solves of two problems);
+ * VEF_ERR_TIMEOUT when a bounded device-side wait of a sweep
  * kernel expired (vef_options.wait_polls; the kernel then exits without
  * finishing the sweep). */
 int vef_sweep_check(vef_sweep_t *h);
