@@ -1019,7 +1019,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
         SL.mode = launch_mode(h->mat_quadrature, F.v.mode);
         SL.flow = true;
         SL.list = h->d_solves;
-        SL.desc = h->d_solve_desc;  // the pivot-order entries of uncertified solves
+        SL.desc = h->d_solve_desc;  // the records of the whole solve list, indexed as the tasks index it
         SL.tasks = h->d_flow_tasks + F.off;
         SL.count = F.cnt;
         SL.pred_ptr = h->d_pred_ptr + F.off;

@@ -64,7 +64,7 @@ struct SweepLaunch {
   const int4 *desc;  // level schedule: two records per entry of list (element, direction | problem << 16,
                      // flags, w), (neighbours); flags as the kernels' SolveIn flags, boundary faces << 16;
                      // w: class of shared local matrices, or entry of KProb::piv_perm; persistent
-                     // schedule: the records of the whole solve list (the pivot-order entries)
+                     // schedule: the records of the whole solve list, which the tasks index
   const int2 *list;  // level schedule: (element, direction | problem << 16) pairs of one level;
                      // direction-resident schedule: (problem, direction) tasks
   int count;       // level: solves; direction-resident: tasks; persistent: tasks

@@ -2161,10 +2161,8 @@ __device__ __forceinline__ void solve_one_lu(const SolveInL<P, NQ, T> &in, int d
                                              const T *tab, const T *wv, T *area, int r, int *status) {
   using LD = LuLds<P, NQ>;
   constexpr int P1 = P + 1, N = P1 * P1, Q = NQ * NQ;
-  const int ne = pb.ne;
   const int e = in.e;
   const bool valid = in.valid;
-  const unsigned mask = valid ? (unsigned)in.flags & 15u : 0u;
 
   // staging (wave-local)
   area[LD::A_G + r] = in.g;
@@ -2847,8 +2845,7 @@ struct FlowItem {
 
 template <int P, int NQ, typename T, int MODE>
 __global__ void __launch_bounds__(256, 2)
-k_sweep_flow(const int2 *__restrict__ solves, const int4 *__restrict__ desc, const int2 *__restrict__ tasks,
-             int n_tasks,
+k_sweep_flow(const int4 *__restrict__ desc, const int2 *__restrict__ tasks, int n_tasks,
              const int *__restrict__ pred_ptr, const int *__restrict__ pred_idx, int *__restrict__ flags,
              int own_base, int *__restrict__ abort_flag, const KProb *__restrict__ probs,
              const KIO *__restrict__ io, const T *__restrict__ tables, int it, const int *__restrict__ stop,
@@ -2870,37 +2867,27 @@ k_sweep_flow(const int2 *__restrict__ solves, const int4 *__restrict__ desc, con
   if (w >= n_tasks) return;
 
   auto fetch = [&](Item &x, const int2 &tk, int rd) {
+    // the solve's packed descriptor (element, direction | problem << 16,
+    // flags, pivot-order entry; neighbours), as the level kernels read it
     const int k = rd * Pol::SPW + sw;
     x.in.valid = k < tk.y;
-    x.in.e = 0;
-    x.in.flags = 0;
-    x.d = 0;
-    x.prob = 0;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) x.in.nb[f] = -1;
+    int4 da = make_int4(0, 0, 0, 0), db = make_int4(-1, -1, -1, -1);
     if (x.in.valid) {
-      const int2 sv = solves[tk.x + k];
-      x.in.e = sv.x;
-      x.d = sv.y & 0xffff;
-      x.prob = sv.y >> 16;
+      da = desc[2 * ((size_t)tk.x + k)];
+      db = desc[2 * ((size_t)tk.x + k) + 1];
     }
-    const KProb &pb = probs[x.prob];
-    if (x.in.valid) {
-      {
-        const unsigned mk = pb.mask[(size_t)x.d * pb.ne + x.in.e];
-        x.in.flags = (int)((mk & 15u) | ((mk >> 7) << 12));  // inflow faces, pivoting needed
-        if constexpr ((MODE & MODE_KIND) == MODE_GENERAL_MAT) {
-          x.in.pix = 0;
-          if (mk & 0x80u) x.in.pix = desc[2 * (size_t)(tk.x + k)].w;  // its pivot order
-        }
-      }
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        x.in.nb[f] = pb.nbr[4 * x.in.e + f];
-        x.in.flags |= ((int)pb.nbr_face[4 * x.in.e + f] & 3) << (4 + 2 * f);
-      }
-    }
-    load_one<P, NQ, T>(x.in, x.d, pb, io[x.prob], it, r);
+    x.in.e = da.x;
+    x.d = da.y & 0xffff;
+    // a task holds solves of one problem and a wave's slots one task: the
+    // problem's records come through the scalar cache
+    x.prob = __builtin_amdgcn_readfirstlane(da.y >> 16);
+    x.in.flags = da.z & 0xffff;  // inflow faces, neighbour faces, pivoting needed
+    x.in.nb[0] = db.x;
+    x.in.nb[1] = db.y;
+    x.in.nb[2] = db.z;
+    x.in.nb[3] = db.w;
+    if constexpr ((MODE & MODE_KIND) == MODE_GENERAL_MAT) x.in.pix = da.w;
+    load_one<P, NQ, T>(x.in, x.d, probs[x.prob], io[x.prob], it, r);
   };
 
   int t = w, rd = 0;
@@ -2969,7 +2956,8 @@ hipError_t launch_flow_t(const SweepLaunch &L) {
   int grid = per_cu * L.n_cu;
   const int need = (L.count + (block / 64) - 1) / (block / 64);
   if (grid > need) grid = need;
-  hipLaunchKernelGGL((k_sweep_flow<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.list, L.desc,
+  if (!L.desc) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep_flow<P, NQ, T, MODE>), dim3(grid), dim3(block), bytes, L.stream, L.desc,
                      L.tasks, L.count, L.pred_ptr, L.pred_idx, L.flags, L.own_base, L.abort_flag, L.probs, L.io,
                      static_cast<const T *>(L.tables), L.it, L.stop, L.status, L.wait_spins);
   return hipGetLastError();
