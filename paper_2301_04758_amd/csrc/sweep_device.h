@@ -766,14 +766,14 @@ __device__ __forceinline__ void load_one(SolveInM<P, NQ, T, ORD> &in, int d, con
   in.rr = r;
   if (!in.valid) return;
   if constexpr (ORD) {
-    if ((in.flags >> 12) & 1) in.rr = pb.piv_perm[(size_t)in.pix * 16 + r] & 15;
+    if ((in.flags >> 12) & 1) in.rr = gload(pb.piv_perm + (size_t)in.pix * 16 + r) & 15;
   }
   const int e = in.e;
   const double *phi = it == 0 ? pio.phi_in : pio.mom;
   T sv = T(0);
   if (r < N) {
-    if (phi) sv = static_cast<T>(pb.sig[2 * e + 1] * kInv4Pi) * static_cast<T>(phi[(size_t)e * N + r]);
-    if (pio.q_iso) sv += static_cast<T>(pio.q_iso[(size_t)e * N + r]);
+    if (phi) sv = static_cast<T>(gload(pb.sig + 2 * e + 1) * kInv4Pi) * static_cast<T>(gload(phi + (size_t)e * N + r));
+    if (pio.q_iso) sv += static_cast<T>(gload(pio.q_iso + (size_t)e * N + r));
   }
   in.s = sv;
 }
@@ -843,9 +843,9 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T, ORD> &in, int
   if (r < N) area[S::OFF_S_M + r] = in.s;
   wave_sync_lds();
 
-  const T ox = static_cast<T>(pb.omega[2 * d]);
-  const T oy = static_cast<T>(pb.omega[2 * d + 1]);
-  const T st = static_cast<T>(pb.sig[2 * (valid ? e : 0)]);
+  const T ox = static_cast<T>(gload(pb.omega + 2 * d));
+  const T oy = static_cast<T>(gload(pb.omega + 2 * d + 1));
+  const T st = static_cast<T>(gload(pb.sig + 2 * (valid ? e : 0)));
   T A[N];
   T rhs = T(0);
 #pragma unroll
@@ -859,7 +859,8 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T, ORD> &in, int
     const T *g5 = static_cast<const T *>(pb.geo_v) + (size_t)e * Q * 5;
     const double *qd = pio.q_dir + ((size_t)d * ne + e) * Q;
     T acc = T(0);
-    for (int q = 0; q < Q; ++q) acc += g5[5 * q] * static_cast<T>(pb.tab_d[q * N + rr]) * static_cast<T>(qd[q]);
+    for (int q = 0; q < Q; ++q)
+      acc += gload(g5 + 5 * q) * static_cast<T>(gload(pb.tab_d + q * N + rr)) * static_cast<T>(gload(qd + q));
     rhs += acc;
   }
   T cw = T(0);  // outflow part of the balance weight (fixup)
@@ -885,8 +886,8 @@ __device__ __forceinline__ void solve_one(const SolveInM<P, NQ, T, ORD> &in, int
       const double *bc = pio.psi_bc + ((size_t)d * pb.nbf + (-in.nb[f] - 1)) * NQ;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const T on = ox * gf[2 * q] + oy * gf[2 * q + 1];
-        rhs -= on * static_cast<T>(sF[q * P1 + pos]) * static_cast<T>(bc[q]);
+        const T on = ox * gload(gf + 2 * q) + oy * gload(gf + 2 * q + 1);
+        rhs -= on * static_cast<T>(gload(sF + q * P1 + pos)) * static_cast<T>(gload(bc + q));
       }
     }
   }
