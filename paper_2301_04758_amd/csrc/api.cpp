@@ -529,7 +529,8 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     h->h_probs[k] = kp;
   }
   he = upload(h, &h->d_probs, h->h_probs.data(), h->h_probs.size());
-  for (int k = 0; k < n_probs && he == hipSuccess; ++k) {
+  if (he != hipSuccess) return hip_fail(h, he, "upload problem records");
+  for (int k = 0; k < n_probs; ++k) {
     if (piv_lists[k].empty()) continue;
     int2 *tmp = nullptr;
     vefk::PivotOrderLaunch PL{};
@@ -540,13 +541,14 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
     PL.prob = k;
     PL.out = const_cast<uint8_t *>(h->h_probs[k].piv_perm);
     he = hipMalloc((void **)&tmp, sizeof(int2) * piv_lists[k].size());
-    if (he != hipSuccess) break;
+    if (he != hipSuccess) return hip_fail(h, he, "pivot orders");
     he = hipMemcpy(tmp, piv_lists[k].data(), sizeof(int2) * piv_lists[k].size(), hipMemcpyHostToDevice);
     PL.list = tmp;
     if (he == hipSuccess) he = vefk::launch_pivot_order(PL);
     if (he == hipSuccess) he = hipDeviceSynchronize();
     const hipError_t fe = hipFree(tmp);
     if (he == hipSuccess) he = fe;
+    if (he != hipSuccess) return hip_fail(h, he, "pivot orders");
   }
   if (he == hipSuccess) he = dev_alloc(h, &h->d_io, n_probs);
   if (he == hipSuccess) he = dev_alloc(h, &h->d_mio, n_probs);
@@ -693,7 +695,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       }
       }
   if (solves.size() != total + n_pad) return set_err(h, VEF_ERR_INVALID, "internal: solve list size mismatch");
-  if (total > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
+  if (solves.size() > (size_t)0x7fffffff) return set_err(h, VEF_ERR_INVALID, "too many element-direction pairs");
   he = upload(h, &h->d_solves, solves.data(), solves.size());
   if (he != hipSuccess) return hip_fail(h, he, "upload solve lists");
   {
