@@ -188,14 +188,16 @@ __global__ void k_finalize(const KIO *__restrict__ io, int n_probs, int it, doub
 // The direction weights and cosines are staged in LDS as (w, w ox, w oy);
 // without a direction-dependent source, Q0 and Q1 at a point are q_iso times
 // the sums of those over the directions, formed once per work-group in
-// direction order (so every work-group has the same values).  STAGE: the
-// basis table V [Q][n] and the work-group's elements' phi, Pxx, Pxy, Pyy and
-// q_iso coefficients go through LDS first, read with consecutive addresses
-// (the host checks that they fit: kClStageEl elements' worth, kClStageV
-// table entries).
+// direction order (so every work-group has the same values).  A work-group
+// takes chunks of 256 points in turn, so this setup is paid once per
+// work-group.  STAGE: the basis table V [Q][n] and, per chunk, its elements'
+// phi, Pxx, Pxy, Pyy and q_iso coefficients go through LDS first, read with
+// consecutive addresses (the host checks that they fit: kClStageEl elements'
+// worth, kClStageV table entries).
 constexpr int kClThreads = 256;
 constexpr int kClStageEl = 320;   // element-node entries per staged array
 constexpr int kClStageV = 49 * 25;
+constexpr int kClMaxGroups = 2048;
 template <bool STAGE>
 __global__ void __launch_bounds__(kClThreads)
 k_closures(const KProb *__restrict__ probs, const KMomIO *__restrict__ mio, int prob, int ne, int Q,
@@ -224,111 +226,117 @@ k_closures(const KProb *__restrict__ probs, const KMomIO *__restrict__ mio, int 
     wsum[1] = s1;
     wsum[2] = s2;
   }
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nvol = ne * Q;
-  // the work-group's elements (volume points i0 .. i0 + 255)
-  const int i0 = blockIdx.x * blockDim.x;
-  const int e0 = i0 < nvol ? i0 / Q : 0;
-  const int e1 = i0 < nvol ? ((i0 + (int)blockDim.x < nvol ? i0 + (int)blockDim.x : nvol) - 1) / Q + 1 : 0;
+  const int total = nvol + nbf * nq;
   const size_t N = (size_t)ne * n;
-  if constexpr (STAGE) {
+  if constexpr (STAGE)
     for (int x = threadIdx.x; x < Q * n; x += blockDim.x) sV[x] = pb.tab_d[x];
-    const int cnt = (e1 - e0) * n;
-    const size_t b0 = (size_t)e0 * n;
-    for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
-      if (io.mom) {
-        sM[0][x] = io.mom[b0 + x];
-        sM[1][x] = io.mom[3 * N + b0 + x];
-        sM[2][x] = io.mom[4 * N + b0 + x];
-        sM[3][x] = io.mom[5 * N + b0 + x];
+  // chunks of blockDim points, the work-group's every gridDim-th: the
+  // direction sums and the basis table above are staged once per work-group
+  for (int i0 = blockIdx.x * blockDim.x; i0 < total; i0 += gridDim.x * blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    // the chunk's elements (volume points i0 .. i0 + 255)
+    const int e0 = i0 < nvol ? i0 / Q : 0;
+    const int e1 = i0 < nvol ? ((i0 + (int)blockDim.x < nvol ? i0 + (int)blockDim.x : nvol) - 1) / Q + 1 : 0;
+    if constexpr (STAGE) {
+      __syncthreads();  // the previous chunk's reads of sM are done
+      const int cnt = (e1 - e0) * n;
+      const size_t b0 = (size_t)e0 * n;
+      for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+        if (io.mom) {
+          sM[0][x] = io.mom[b0 + x];
+          sM[1][x] = io.mom[3 * N + b0 + x];
+          sM[2][x] = io.mom[4 * N + b0 + x];
+          sM[3][x] = io.mom[5 * N + b0 + x];
+        }
+        sM[4][x] = io.q_iso ? io.q_iso[b0 + x] : 0.0;
       }
-      sM[4][x] = io.q_iso ? io.q_iso[b0 + x] : 0.0;
     }
-  }
-  __syncthreads();
-  int bad = 0;
-  if (i < nvol) {
-    const int e = i / Q, q = i % Q;
-    const double *V = STAGE ? sV + q * n : pb.tab_d + (size_t)q * n;
-    const int el = (e - e0) * n;  // the element's staged entries
-    if (io.E && io.mom) {
-      double ph = 0, pxx = 0, pxy = 0, pyy = 0;
-      for (int j = 0; j < n; ++j) {
-        const double v = V[j];
-        if constexpr (STAGE) {
-          ph += sM[0][el + j] * v;
-          pxx += sM[1][el + j] * v;
-          pxy += sM[2][el + j] * v;
-          pyy += sM[3][el + j] * v;
+    __syncthreads();
+    int bad = 0;
+    if (i < nvol) {
+      const int e = i / Q, q = i % Q;
+      const double *V = STAGE ? sV + q * n : pb.tab_d + (size_t)q * n;
+      const int el = (e - e0) * n;  // the element's staged entries
+      if (io.E && io.mom) {
+        double ph = 0, pxx = 0, pxy = 0, pyy = 0;
+        for (int j = 0; j < n; ++j) {
+          const double v = V[j];
+          if constexpr (STAGE) {
+            ph += sM[0][el + j] * v;
+            pxx += sM[1][el + j] * v;
+            pxy += sM[2][el + j] * v;
+            pyy += sM[3][el + j] * v;
+          } else {
+            ph += io.mom[(size_t)e * n + j] * v;
+            pxx += io.mom[3 * N + (size_t)e * n + j] * v;
+            pxy += io.mom[4 * N + (size_t)e * n + j] * v;
+            pyy += io.mom[5 * N + (size_t)e * n + j] * v;
+          }
+        }
+        if (ph > 0.0) {
+          io.E[i] = pxx / ph;
+          io.E[(size_t)nvol + i] = pxy / ph;
+          io.E[2 * (size_t)nvol + i] = pyy / ph;
         } else {
-          ph += io.mom[(size_t)e * n + j] * v;
-          pxx += io.mom[3 * N + (size_t)e * n + j] * v;
-          pxy += io.mom[4 * N + (size_t)e * n + j] * v;
-          pyy += io.mom[5 * N + (size_t)e * n + j] * v;
+          io.E[i] = io.E[(size_t)nvol + i] = io.E[2 * (size_t)nvol + i] = 0.0;
+          bad = 1;
         }
       }
-      if (ph > 0.0) {
-        io.E[i] = pxx / ph;
-        io.E[(size_t)nvol + i] = pxy / ph;
-        io.E[2 * (size_t)nvol + i] = pyy / ph;
-      } else {
-        io.E[i] = io.E[(size_t)nvol + i] = io.E[2 * (size_t)nvol + i] = 0.0;
-        bad = 1;
-      }
-    }
-    if (io.Q0 || io.Q1) {
-      double qi = 0.0;
-      if (io.q_iso)
-        for (int j = 0; j < n; ++j) qi += (STAGE ? sM[4][el + j] : io.q_iso[(size_t)e * n + j]) * V[j];
-      double s0 = 0, s1 = 0, s2 = 0;
-      if (io.q_dir) {
-        for (int d = 0; d < nd; ++d) {
-          const double qq = qi + io.q_dir[((size_t)d * ne + e) * Q + q];
-          s0 += dirs[d].x * qq;
-          s1 += dirs[d].y * qq;
-          s2 += dirs[d].z * qq;
+      if (io.Q0 || io.Q1) {
+        double qi = 0.0;
+        if (io.q_iso)
+          for (int j = 0; j < n; ++j) qi += (STAGE ? sM[4][el + j] : io.q_iso[(size_t)e * n + j]) * V[j];
+        double s0 = 0, s1 = 0, s2 = 0;
+        if (io.q_dir) {
+          for (int d = 0; d < nd; ++d) {
+            const double qq = qi + io.q_dir[((size_t)d * ne + e) * Q + q];
+            s0 += dirs[d].x * qq;
+            s1 += dirs[d].y * qq;
+            s2 += dirs[d].z * qq;
+          }
+        } else {
+          s0 = qi * wsum[0];
+          s1 = qi * wsum[1];
+          s2 = qi * wsum[2];
         }
-      } else {
-        s0 = qi * wsum[0];
-        s1 = qi * wsum[1];
-        s2 = qi * wsum[2];
-      }
-      if (io.Q0) io.Q0[i] = s0;
-      if (io.Q1) {
-        io.Q1[i] = s1;
-        io.Q1[(size_t)nvol + i] = s2;
-      }
-    }
-  } else if (i < nvol + nbf * nq) {
-    const int j = i - nvol;
-    const int bf = j / nq, q = j % nq;
-    if (io.Eb) {
-      const double num = pb.bnd[2 * (size_t)j], den = pb.bnd[2 * (size_t)j + 1];
-      if (den > 0.0) {
-        io.Eb[j] = num / den;
-      } else {
-        io.Eb[j] = 0.0;
-        bad = 1;
-      }
-    }
-    if (io.Jin) {
-      const int e = pb.bf_ef[bf] >> 2, f = pb.bf_ef[bf] & 3;
-      const double *g = pb.geo_fd + (((size_t)e * 4 + f) * nq + q) * 2;
-      const double len = sqrt(g[0] * g[0] + g[1] * g[1]);
-      const double nx = g[0] / len, ny = g[1] / len;
-      double s = 0.0;
-      if (io.psi_bc)
-        for (int d = 0; d < pb.nd; ++d) {
-          const double on = pb.omega[2 * d] * nx + pb.omega[2 * d + 1] * ny;
-          if (on < 0.0) s += pb.weight[d] * on * io.psi_bc[((size_t)d * nbf + bf) * nq + q];
+        if (io.Q0) io.Q0[i] = s0;
+        if (io.Q1) {
+          io.Q1[i] = s1;
+          io.Q1[(size_t)nvol + i] = s2;
         }
-      io.Jin[j] = s;
+      }
+    } else if (i < nvol + nbf * nq) {
+      const int j = i - nvol;
+      const int bf = j / nq, q = j % nq;
+      if (io.Eb) {
+        const double num = pb.bnd[2 * (size_t)j], den = pb.bnd[2 * (size_t)j + 1];
+        if (den > 0.0) {
+          io.Eb[j] = num / den;
+        } else {
+          io.Eb[j] = 0.0;
+          bad = 1;
+        }
+      }
+      if (io.Jin) {
+        const int e = pb.bf_ef[bf] >> 2, f = pb.bf_ef[bf] & 3;
+        const double *g = pb.geo_fd + (((size_t)e * 4 + f) * nq + q) * 2;
+        const double len = sqrt(g[0] * g[0] + g[1] * g[1]);
+        const double nx = g[0] / len, ny = g[1] / len;
+        double s = 0.0;
+        if (io.psi_bc)
+          for (int d = 0; d < pb.nd; ++d) {
+            const double on = pb.omega[2 * d] * nx + pb.omega[2 * d + 1] * ny;
+            if (on < 0.0) s += pb.weight[d] * on * io.psi_bc[((size_t)d * nbf + bf) * nq + q];
+          }
+        io.Jin[j] = s;
+      }
     }
-  }
-  if (io.n_nonpos) {
-    // count per wavefront, one atomic per wave
-    const unsigned long long ballot = __ballot(bad);
-    if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(io.n_nonpos, (int)__popcll(ballot));
+    if (io.n_nonpos) {
+      // count per wavefront, one atomic per wave
+      const unsigned long long ballot = __ballot(bad);
+      if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(io.n_nonpos, (int)__popcll(ballot));
+    }
   }
 }
 
@@ -419,7 +427,10 @@ hipError_t launch_finalize(const KIO *io, int n_probs, int it, double tol, int *
 hipError_t launch_closures(const KProb *probs, const KMomIO *io, int prob, int ne, int Q, int n, int nbf,
                            int nq, hipStream_t s) {
   const int tot = ne * Q + nbf * nq;
-  const int grid = (tot + kClThreads - 1) / kClThreads;
+  // enough work-groups to fill the device a few times over; each loops over
+  // its chunks
+  const int need = (tot + kClThreads - 1) / kClThreads;
+  const int grid = need < kClMaxGroups ? need : kClMaxGroups;
   // LDS staging when a work-group's elements and the basis table fit
   const bool stage = Q > 0 && (kClThreads / Q + 2) * n <= kClStageEl && Q * n <= kClStageV;
   if (stage)
