@@ -1074,7 +1074,7 @@ int run_impl(vef_sweep_t *h, const vef_run_args *a, void *stream, bool no_alloc)
       return hip_fail(h, he, "record timing event");
     for (int k = 0; k < np; ++k) {
       const auto &pl = h->plans[k];
-      he = vefk::launch_moments(fp32, h->d_probs, h->d_io, k, pl.ne * pl.n, it, stop, s);
+      he = vefk::launch_moments(fp32, h->d_probs, h->d_io, k, pl.ne * pl.n, pl.nd, it, stop, s);
       if (he != hipSuccess) return hip_fail(h, he, "launch moments");
     }
     // the stop test needs a tolerance; without one only the count of sweeps

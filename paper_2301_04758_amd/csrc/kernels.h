@@ -100,7 +100,9 @@ struct SweepLaunch {
 
 hipError_t launch_sweep_level(const SweepLaunch &L);
 hipError_t launch_sweep_dir(const SweepLaunch &L);
-hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob, int ne_n, int it,
+// nd: the problem's directions (1..1024), the size of the staged direction
+// table.
+hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob, int ne_n, int nd, int it,
                           const int *stop, hipStream_t s);
 hipError_t launch_boundary(bool fp32, const KProb *probs, const KIO *io, int prob, int nbf, int nq,
                            int p, const int *stop, hipStream_t s);

@@ -32,7 +32,10 @@ k_moments(const KProb *__restrict__ probs, const KIO *__restrict__ io, int prob,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   const int nd = pb.nd;
-  __shared__ double3 dirs[kMaxMomDirs];  // (w, w ox, w oy)
+  // (w, ox, oy) of the directions, nd entries (the launch sizes the
+  // work-group's dynamic LDS to them, which leaves room for more resident
+  // work-groups than a table for the most directions would)
+  extern __shared__ double3 dirs[];
   for (int d = threadIdx.x; d < nd; d += blockDim.x) {
     const double wt = pb.weight[d];
     dirs[d] = make_double3(wt, pb.omega[2 * d], pb.omega[2 * d + 1]);
@@ -382,13 +385,17 @@ hipError_t launch_pivot_order(const PivotOrderLaunch &L) {
 hipError_t launch_sweep_level(const SweepLaunch &L) { return launch_sweep(L, false); }
 hipError_t launch_sweep_dir(const SweepLaunch &L) { return launch_sweep(L, true); }
 
-hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob, int ne_n, int it,
+hipError_t launch_moments(bool fp32, const KProb *probs, const KIO *io, int prob, int ne_n, int nd, int it,
                           const int *stop, hipStream_t s) {
+  if (nd < 1 || nd > kMaxMomDirs) return hipErrorInvalidValue;
   const int grid = (ne_n + 63) / 64;
+  const size_t bytes = sizeof(double3) * (size_t)nd;
   if (fp32)
-    hipLaunchKernelGGL(k_moments<float>, dim3(grid), dim3(64 * kMomWaves), 0, s, probs, io, prob, ne_n, it, stop);
+    hipLaunchKernelGGL(k_moments<float>, dim3(grid), dim3(64 * kMomWaves), bytes, s, probs, io, prob, ne_n, it,
+                       stop);
   else
-    hipLaunchKernelGGL(k_moments<double>, dim3(grid), dim3(64 * kMomWaves), 0, s, probs, io, prob, ne_n, it, stop);
+    hipLaunchKernelGGL(k_moments<double>, dim3(grid), dim3(64 * kMomWaves), bytes, s, probs, io, prob, ne_n, it,
+                       stop);
   return hipGetLastError();
 }
 
