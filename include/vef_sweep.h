@@ -275,7 +275,8 @@ typedef struct {
   long long n_lagged; /* lagged (direction, element, face) couplings; 0 for
                     acyclic upwind graphs */
   long long n_pivoting; /* (direction, element) pairs whose local system is
-                    solved with partial pivoting: those the plan cannot
+                    solved with partial pivoting (or, with element matrices,
+                    in the pivot order formed at create): those the plan cannot
                     certify for elimination in natural order (sigma_t = 0,
                     or a curved face along which Omega . n changes sign or
                     takes the other role's sign); 0 when every face is
@@ -303,7 +304,11 @@ typedef struct {
 #define VEF_KERNEL_GENERAL_MAT 6     /* general elements, p = 3: row per lane
                                        from precomputed element matrices;
                                        LU in natural order where the plan
-                                       certifies it, else partial pivoting */
+                                       certifies it, else partial pivoting
+                                       (level-synchronous and persistent:
+                                       the rows taken in the pivot order
+                                       formed at create, then LU in natural
+                                       order; 16 bytes per such pair) */
 #define VEF_KERNEL_AFFINE_SHARED 7   /* affine, p >= 3, level-synchronous: a
                                        16-lane slot per solve; the solution
                                        is the matrix of the solve's class
