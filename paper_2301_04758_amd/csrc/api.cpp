@@ -144,7 +144,6 @@ struct vef_sweep {
   int n_cls = 0;                     // classes of shared local matrices of problem 0 (0: none)
   int4 *d_cls_rep = nullptr;         // [n_cls] representative (element, direction, inflow faces, 0)
   void *d_cls_inv = nullptr;         // T [n_cls][ncol][16][RS] class matrices (written by every run)
-  std::vector<std::unordered_map<long long, int>> piv_index;  // per problem: d ne + e -> its entry of piv_perm
   double *static_resid = nullptr;    // this device's copy of `scratch` (vef_sweep_run_static)
   hipStream_t last_stream = nullptr;
   bool timing = false;
@@ -415,7 +414,9 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
 
   // per-problem constant data
   h->h_probs.resize(n_probs);
-  h->piv_index.assign(n_probs, {});
+  // per problem: d ne + e -> its entry of piv_perm (needed only while the
+  // descriptors below are built)
+  std::vector<std::unordered_map<long long, int>> piv_index(n_probs);
   std::vector<std::vector<int2>> piv_lists(n_probs);  // (element, direction) of the uncertified solves
   for (int k = 0; k < n_probs; ++k) {
     const auto &pl = h->plans[k];
@@ -511,7 +512,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
         // solves not certified for elimination in natural order: their row
         // order of partial pivoting, formed on the device below (by
         // direction, then element; the level lists carry the entry)
-        auto &ix = h->piv_index[k];
+        auto &ix = piv_index[k];
         auto &ls = piv_lists[k];
         for (int d = 0; d < pl.nd; ++d)
           for (int e = 0; e < pl.ne; ++e)
@@ -725,7 +726,7 @@ int create_impl(const vef_problem_desc *probs, int n_probs, const vef_options *o
       // entry of its pivot order (element matrices, uncertified solves)
       int w = h->n_cls > 0 ? shared.of(pl, e, d) : 0;
       if (mk & 0x80u) {
-        const auto &ix = h->piv_index[k];
+        const auto &ix = piv_index[k];
         const auto it = ix.find((long long)d * pl.ne + e);
         if (it != ix.end()) w = it->second;
       }
